@@ -1,0 +1,379 @@
+"""Pins for the CPU oracle against what the paper and the mathematics fix.
+
+None of these compares the oracle with itself: each check is a worked example
+printed in the paper, a closed form, an identity, a brute-force enumeration
+computed a different way, or a dense Kronecker-product construction.
+"""
+import itertools
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from tests import dense_ref as D
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _rand_state(n, seed):
+    rng = np.random.default_rng(seed)
+    v = rng.standard_normal(1 << n) + 1j * rng.standard_normal(1 << n)
+    return v / np.linalg.norm(v)
+
+
+def _rand_unitary(seed):
+    return oracle.gate_matrix("U", matrix=W.haar_unitary_2x2(seed))
+
+
+# ---------------------------------------------------------------- index sets
+
+def _ith_cleared(i, t):
+    """Insert a 0 at bit t of i (the pair-index helper the paper borrows)."""
+    return ((i >> t) << (t + 1)) | (i & ((1 << t) - 1))
+
+
+def _skip_map(i_r, t, controls):
+    """The paper's iterative skip-interval map (Sec. III-B), ascending
+    controls, each adjusted relative to the target, then ithCleared."""
+    i = i_r
+    for c in sorted(controls):
+        c_adj = c - 1 if c > t else c
+        s = 1 << c_adj
+        i = i + (i // s + 1) * s
+    return i
+
+
+def test_worked_example_golden():
+    g = json.load(open(os.path.join(GOLDEN, "worked_example_n3_t1.json")))
+    n, t = g["n"], g["target"]
+    for case in g["cases"]:
+        ctrls = case["controls"]
+        adj = [c - 1 if c > t else c for c in ctrls]
+        assert adj == case["adjusted_controls"]
+        assert [1 << a for a in adj] == case["skip_intervals"]
+        got = [_skip_map(i, t, ctrls) for i in case["reduced_set"]]
+        assert got == case["global_iterations"]
+        # the oracle's brute-force pair list, mapped back to iteration indices
+        pl = oracle.pair_list(n, t, ctrls)
+        it = [((int(k) >> (t + 1)) << t) | (int(k) & ((1 << t) - 1)) for k in pl]
+        assert it == case["global_iterations"]
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 5, 6, 7])
+def test_pair_list_matches_skip_map_exhaustive(n):
+    """Every target and every control subset (values 1): brute force equals
+    the paper's iterative map followed by ithCleared, order included."""
+    for t in range(n):
+        others = [q for q in range(n) if q != t]
+        for c in range(len(others) + 1):
+            for ctrls in itertools.combinations(others, c):
+                bf = oracle.pair_list(n, t, ctrls)
+                sm = [_ith_cleared(_skip_map(i, t, ctrls), t) for i in range(1 << (n - 1 - c))]
+                assert bf.tolist() == sm, (n, t, ctrls)
+
+
+def test_pair_list_descending_controls_fails():
+    """The map needs ascending controls (Sec. III-B); applying it in
+    descending order gives a different set for some two-control case."""
+    n, t, ctrls = 4, 0, (1, 2)
+    i = 0
+    for c in sorted(ctrls, reverse=True):
+        c_adj = c - 1 if c > t else c
+        s = 1 << c_adj
+        i = i + (i // s + 1) * s
+    assert _ith_cleared(i, t) != int(oracle.pair_list(n, t, ctrls)[0])
+
+
+@pytest.mark.parametrize("n", [3, 5, 7])
+def test_pair_list_any_control_values(n):
+    """Values 0/1: the list equals all k with bit t clear and control bits equal
+    to the values, enumerated by itertools over the free bits."""
+    rng = np.random.default_rng(n)
+    for _ in range(30):
+        t = int(rng.integers(0, n))
+        others = [q for q in range(n) if q != t]
+        c = int(rng.integers(0, len(others) + 1))
+        ctrls = tuple(sorted(rng.choice(others, size=c, replace=False).tolist())) if c else ()
+        vals = tuple(int(v) for v in rng.integers(0, 2, size=c))
+        free = [q for q in range(n) if q != t and q not in ctrls]
+        fixed = sum(v << q for q, v in zip(ctrls, vals))
+        expect = sorted(fixed + sum(b << q for b, q in zip(bits, free))
+                        for bits in itertools.product((0, 1), repeat=len(free)))
+        assert oracle.pair_list(n, t, ctrls, vals).tolist() == expect
+
+
+# ---------------------------------------------------------------- gate update
+
+@pytest.mark.parametrize("t", [0, 1, 4])
+def test_x_swaps_bit_exact(t):
+    n = 5
+    psi = _rand_state(n, 1)
+    out = oracle.apply_gate(psi.copy(), n, t, (), (), oracle.gate_matrix("X"))
+    idx = np.arange(1 << n) ^ (1 << t)
+    assert np.array_equal(out, psi[idx])
+
+
+def test_h_all_qubits_uniform():
+    n = 8
+    psi = oracle.zero_state(n)
+    for q in range(n):
+        oracle.apply_gate(psi, n, q, (), (), oracle.gate_matrix("H"))
+    assert np.max(np.abs(psi - 2.0 ** (-n / 2))) < 1e-15
+
+
+def test_h_basis_states():
+    n = 1
+    for b, sgn in ((0, 1), (1, -1)):
+        psi = np.zeros(2, dtype=np.complex128); psi[b] = 1
+        oracle.apply_gate(psi, n, 0, (), (), oracle.gate_matrix("H"))
+        assert np.allclose(psi, np.array([1, sgn]) / math.sqrt(2), atol=1e-16)
+
+
+def test_norm_preserved():
+    n = 10
+    psi = _rand_state(n, 2)
+    rng = np.random.default_rng(3)
+    for i in range(50):
+        t = int(rng.integers(0, n))
+        others = [q for q in range(n) if q != t]
+        c = int(rng.integers(0, 4))
+        ctrls = tuple(rng.choice(others, size=c, replace=False).tolist())
+        oracle.apply_gate(psi, n, t, ctrls, (), _rand_unitary(100 + i))
+    assert abs(oracle.norm2(psi, n) - 1.0) < 1e-13
+
+
+def test_ghz():
+    n = 9
+    psi = oracle.run_circuit(W.ghz(n))
+    ref = np.zeros(1 << n, dtype=np.complex128)
+    ref[0] = ref[-1] = 1 / math.sqrt(2)
+    assert np.max(np.abs(psi - ref)) < 1e-15
+
+
+def _bitrev(x, n):
+    return int(format(x, "0%db" % n)[::-1], 2)
+
+
+@pytest.mark.parametrize("n", [3, 4, 5, 7])
+def test_qft_closed_form(n):
+    """The staircase as drawn (no swaps) equals the Fourier matrix with
+    e^{+2 pi i x y / N} / sqrt(N) after bit-reversing the input index."""
+    N = 1 << n
+    psi0 = _rand_state(n, 10 + n)
+    out = oracle.run_circuit(W.qft(n), psi0=psi0)
+    rev = np.array([_bitrev(x, n) for x in range(N)])
+    ref = np.fft.ifft(psi0[rev]) * math.sqrt(N)
+    assert np.max(np.abs(out - ref)) < 1e-13
+
+
+@pytest.mark.parametrize("n", [2, 4, 6])
+def test_stream_decrements(n):
+    """The streaming circuit maps |x> to |x - 1 mod 2^n> (Sec. IV-C figure)."""
+    psi0 = _rand_state(n, 20 + n)
+    out = oracle.run_circuit(W.stream(n), psi0=psi0)
+    # amplitude of |x> moves to |x-1>
+    assert np.array_equal(out, np.roll(psi0, -1))
+
+
+def test_negative_control_identity():
+    """X on the control, controlled G, X on the control equals G controlled
+    on value 0 (Sec. I, two-qubit circuit figure)."""
+    n = 4
+    G = _rand_unitary(7)
+    for t, c in ((0, 1), (1, 0), (3, 1), (0, 3)):
+        psi = _rand_state(n, 30 + t)
+        a = psi.copy()
+        oracle.apply_gate(a, n, c, (), (), oracle.gate_matrix("X"))
+        oracle.apply_gate(a, n, t, (c,), (), G)
+        oracle.apply_gate(a, n, c, (), (), oracle.gate_matrix("X"))
+        b = oracle.apply_gate(psi.copy(), n, t, (c,), (0,), G)
+        assert np.max(np.abs(a - b)) < 1e-15
+
+
+@pytest.mark.parametrize("n", [1, 2, 4, 7])
+def test_dense_kron_random_gates(n):
+    rng = np.random.default_rng(40 + n)
+    for i in range(25):
+        t = int(rng.integers(0, n))
+        others = [q for q in range(n) if q != t]
+        c = int(rng.integers(0, min(3, n - 1) + 1))
+        ctrls = tuple(rng.choice(others, size=c, replace=False).tolist()) if c else ()
+        vals = tuple(int(v) for v in rng.integers(0, 2, size=c))
+        G = _rand_unitary(500 + i)
+        psi = _rand_state(n, 600 + i)
+        got = oracle.apply_gate(psi.copy(), n, t, ctrls, vals, G)
+        ref = D.controlled_unitary(n, t, ctrls, vals, G) @ psi
+        assert np.max(np.abs(got - ref)) < 1e-14
+
+
+def test_dense_kron_config0_small():
+    """A config-0 style circuit at n=8 against the product of dense gates."""
+    c = W.config0(seed=11, n=8, ngates=60)
+    got = oracle.run_circuit(c)
+    psi = np.zeros(1 << c.n, dtype=np.complex128); psi[0] = 1
+    for g in c.gates:
+        G = oracle.gate_matrix(g.kind, g.theta, g.matrix)
+        psi = D.controlled_unitary(c.n, g.target, g.controls, g.values, G) @ psi
+    assert np.max(np.abs(got - psi)) < 1e-13
+
+
+def test_gate_matrices_closed_forms():
+    th = 0.7
+    for kind, P in (("RX", D.PX), ("RY", D.PY), ("RZ", D.PZ)):
+        ref = math.cos(th / 2) * np.eye(2) - 1j * math.sin(th / 2) * P
+        assert np.allclose(oracle.gate_matrix(kind, th), ref, atol=1e-15)
+    for m in range(1, 6):
+        Rm = oracle.gate_matrix("P", 2 * math.pi / (1 << m))
+        assert np.allclose(Rm, np.diag([1, np.exp(2j * math.pi / (1 << m))]), atol=1e-15)
+    for kind in ("X", "Y", "Z", "H"):
+        U = oracle.gate_matrix(kind)
+        assert np.allclose(U @ U.conj().T, np.eye(2), atol=1e-15)
+    U = _rand_unitary(3)
+    assert np.allclose(oracle.gate_matrix("~U", matrix=W.haar_unitary_2x2(3)), U.conj().T)
+
+
+def test_gate_amplitudes_match_full_gate():
+    n = 9
+    psi = _rand_state(n, 50)
+    G = _rand_unitary(51)
+    for t, ctrls, vals in ((0, (), ()), (4, (1, 7), (1, 0)), (8, (0, 2, 5), ())):
+        full = oracle.apply_gate(psi.copy(), n, t, ctrls, vals, G)
+        idx = np.arange(1 << n)
+        amp = oracle.gate_amplitudes(psi, n, t, ctrls, vals, G, idx)
+        assert np.array_equal(amp, full)
+
+
+# ---------------------------------------------------------------- expectation
+
+def test_pauli_expectation_dense_all_strings():
+    n = 3
+    psi = _rand_state(n, 60)
+    for x in range(1 << n):
+        for z in range(1 << n):
+            ref = np.vdot(psi, D.pauli_matrix(n, x, z) @ psi)
+            got = oracle.expect_pauli(psi, n, x, z)
+            assert abs(got - ref) < 1e-14
+            assert abs(got.imag) < 1e-14
+
+
+def test_expectation_product_states():
+    n = 6
+    zero = oracle.zero_state(n)
+    plus = zero.copy()
+    for q in range(n):
+        oracle.apply_gate(plus, n, q, (), (), oracle.gate_matrix("H"))
+    for i in range(n - 1):
+        assert abs(oracle.expect_pauli(zero, n, 0, 3 << i).real - 1.0) < 1e-15
+    for i in range(n):
+        assert abs(oracle.expect_pauli(plus, n, 1 << i, 0).real - 1.0) < 1e-14
+        assert abs(oracle.expect_pauli(zero, n, 1 << i, 0).real) < 1e-15
+
+
+def test_hamiltonian_apply_dense():
+    n = 5
+    terms = W.zz_x_hamiltonian(n, 3) + [W.PauliTerm(0.3, 0b00101, 0b00111)]
+    psi = _rand_state(n, 61)
+    ref = D.hamiltonian_matrix(n, terms) @ psi
+    assert np.max(np.abs(oracle.apply_hamiltonian(psi, n, terms) - ref)) < 1e-14
+    assert abs(oracle.expect(psi, n, terms) - np.vdot(psi, ref).real) < 1e-14
+
+
+# ---------------------------------------------------------------- gradients
+
+def test_gradient_one_qubit_analytic():
+    """<Z> after RY(theta)|0> is cos(theta): gradient -sin(theta)."""
+    c = W.Circuit(1, [W.Gate("RY", 0, param=0)], np.array([0.9]))
+    terms = [W.PauliTerm(1.0, 0, 1)]
+    assert abs(oracle.loss(c, c.params, terms) - math.cos(0.9)) < 1e-15
+    g = oracle.grad_param_shift(c, c.params, terms)
+    assert abs(g[0] + math.sin(0.9)) < 1e-14
+
+
+def _dense_grad(c, params, terms):
+    """Exact gradient from dense matrices: d/dtheta of a (controlled)
+    rotation is P_sat (x) dR/dtheta with dR/dtheta = -i/2 P R."""
+    n = c.n
+    H = D.hamiltonian_matrix(n, terms)
+    mats = []
+    for g in c.gates:
+        th = params[g.param] if g.param >= 0 else g.theta
+        mats.append(D.controlled_unitary(n, g.target, g.controls, g.values,
+                                         oracle.gate_matrix(g.kind, th, g.matrix)))
+    grad = np.zeros(len(params))
+    psi0 = np.zeros(1 << n, dtype=np.complex128); psi0[0] = 1
+    for gi, g in enumerate(c.gates):
+        if g.param < 0:
+            continue
+        th = params[g.param]
+        Pm = {"RX": D.PX, "RY": D.PY, "RZ": D.PZ}[g.kind]
+        dR = -0.5j * Pm @ oracle.gate_matrix(g.kind, th)
+        vals = g.values if len(g.values) else [1] * len(g.controls)
+        proj = {q: (D.P1 if v else D.P0) for q, v in zip(g.controls, vals)}
+        dM = D.kron_ops({**proj, g.target: dR}, n)
+        psi = psi0.copy(); dpsi = None
+        for k, M in enumerate(mats):
+            if k == gi:
+                dpsi = dM @ psi
+                psi = M @ psi
+            else:
+                psi = M @ psi
+                if dpsi is not None:
+                    dpsi = M @ dpsi
+        grad[g.param] += 2.0 * np.vdot(psi, H @ dpsi).real
+    return grad
+
+
+def test_param_shift_vs_dense_with_controlled_rotations():
+    n = 4
+    rng = np.random.default_rng(70)
+    gates, p = [], 0
+    for layer in range(2):
+        for q in range(n):
+            gates.append(W.Gate("RY", q, param=p)); p += 1
+        gates.append(W.Gate("RZ", 2, (0,), param=p)); p += 1
+        gates.append(W.Gate("RY", 1, (3, 0), (1, 0), param=p)); p += 1
+        gates.append(W.Gate("RX", 3, param=p)); p += 1
+        for q in range(n - 1):
+            gates.append(W.Gate("X", q + 1, (q,)))
+    params = rng.uniform(0, 2 * math.pi, size=p)
+    c = W.Circuit(n, gates, params)
+    terms = W.zz_x_hamiltonian(n, 9)
+    ref = _dense_grad(c, params, terms)
+    ps = oracle.grad_param_shift(c, params, terms)
+    fd = oracle.grad_finite_diff(c, params, terms)
+    assert np.max(np.abs(ps - ref)) < 1e-12
+    assert np.max(np.abs(fd - ref)) < 1e-8
+
+
+def test_param_shift_shared_parameter():
+    """One parameter used by two gates: contributions add (product rule)."""
+    n = 2
+    gates = [W.Gate("RY", 0, param=0), W.Gate("RZ", 1, (0,), param=0), W.Gate("RY", 1, param=0)]
+    c = W.Circuit(n, gates, np.array([0.4]))
+    terms = [W.PauliTerm(0.7, 0, 3), W.PauliTerm(-0.2, 1, 0), W.PauliTerm(0.5, 2, 0)]
+    ref = _dense_grad(c, c.params, terms)
+    assert abs(oracle.grad_param_shift(c, c.params, terms)[0] - ref[0]) < 1e-12
+
+
+# ---------------------------------------------------------------- generators
+
+def test_generators_deterministic_and_shaped():
+    a, b = W.config0(), W.config0()
+    assert a.gates == b.gates and len(a.gates) == 200 and a.n == 12
+    kinds = {g.kind for g in a.gates}
+    assert kinds <= {"X", "H", "RY", "RZ"}
+    assert all(len(g.controls) <= 3 and g.target not in g.controls for g in a.gates)
+    cases = W.config1_cases()
+    assert len(cases) == 27
+    for t, ctrls in cases:
+        assert t not in ctrls and len(set(ctrls)) == len(ctrls)
+    c3, H = W.config3()
+    assert c3.nparams == 768 and len(c3.gates) == 16 * (48 + 23) and len(H) == 23 + 24
+    c2 = W.config2()
+    assert len(c2.gates) == 20 * (32 + 31 + 8)
+    U = oracle.gate_matrix("U", matrix=W.haar_unitary_2x2(2))
+    assert np.allclose(U @ U.conj().T, np.eye(2), atol=1e-15)
