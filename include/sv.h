@@ -1,0 +1,154 @@
+/*
+ * sv.h — C ABI of the MI355X state-vector library (libsv.so).
+ *
+ * The library applies single-qubit gates with any number of controls to a
+ * 2^n complex state vector held in device memory, enumerating only the
+ * amplitude pairs whose control bits hold (control-aware iteration
+ * scheduling, arXiv:2411.18354 Sec. III-B), and builds circuits, Pauli-sum
+ * expectation values, adjoint gradients and batched runs on top of it.
+ *
+ * Conventions shared by every entry point
+ *  - Amplitude k of an n-qubit state is complex; qubit q is bit q of k, qubit
+ *    0 the least significant (paper Sec. III).  Storage is interleaved
+ *    (re, im): complex128 = two doubles (16 B), complex64 = two floats (8 B).
+ *  - A 2x2 gate G = [[a, b], [c, d]] on target t updates each pair
+ *    (C_k, C_{k+2^t}) with bit t of k clear to (a C_k + b C_{k+2^t},
+ *    c C_k + d C_{k+2^t}) (pair-update equation, Sec. III).  Matrices are
+ *    passed as 8 doubles: a.re a.im b.re b.im c.re c.im d.re d.im.
+ *  - Controls are qubit-indexed: bit q of ctrl_mask marks qubit q as a
+ *    control and bit q of ctrl_vals is its required value (the paper uses
+ *    value 1; value 0 is the negative control of its Sec. I figure).
+ *  - Every function returns SV_OK (0) or a negative sv_status; the reason is
+ *    available from sv_last_error() (thread-local, valid until the next call
+ *    on the same thread).  Arguments are validated before anything is
+ *    enqueued, so an argument error leaves device memory untouched.
+ *  - sv_stream_t is a hipStream_t (NULL selects the null stream).  Work is
+ *    enqueued on it and calls return without synchronising; host arrays
+ *    passed in are copied before the call returns, device outputs are valid
+ *    once the stream reaches them.
+ *  - The library never frees memory it did not allocate.  sv_state_t is a
+ *    non-owning view; data may be any device allocation of the right size
+ *    and 16-byte (complex128) or 8-byte (complex64) alignment.
+ */
+#ifndef SV_H
+#define SV_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef void *sv_stream_t;
+
+typedef enum sv_status {
+    SV_OK = 0,
+    SV_EINVAL = -1,  /* invalid argument (range, duplicate, null, mismatch) */
+    SV_ENOMEM = -2,  /* device allocation failed */
+    SV_EHIP = -3,    /* a HIP runtime call failed */
+    SV_ENOTSUP = -4  /* valid request the library does not handle */
+} sv_status;
+
+typedef enum sv_dtype { SV_C128 = 0, SV_C64 = 1 } sv_dtype;
+
+/* Largest supported register: 2^34 complex128 amplitudes is 256 GiB. */
+#define SV_MAX_QUBITS_C128 34
+#define SV_MAX_QUBITS_C64 35
+
+typedef struct sv_state {
+    void *data;    /* device pointer to 2^n amplitudes, caller-owned */
+    int32_t n;     /* number of qubits, 1 <= n <= SV_MAX_QUBITS_* */
+    int32_t dtype; /* sv_dtype */
+} sv_state_t;
+
+/* Message for the last failing call on this thread ("" if none). */
+const char *sv_last_error(void);
+
+/* Library ABI version (major * 10000 + minor * 100 + patch). */
+int sv_version(void);
+
+/* Allocate 2^n amplitudes of the given dtype on the current device and fill
+ * s; the caller releases it with sv_free.  SV_ENOMEM if hipMalloc fails. */
+int sv_alloc(sv_state_t *s, int n, int dtype);
+
+/* Release memory obtained from sv_alloc and clear s->data.  Passing a state
+ * whose data came from elsewhere is undefined. */
+int sv_free(sv_state_t *s);
+
+/* Set the state to the basis state |basis_index> (all amplitudes zero except
+ * amplitude basis_index = 1).  basis_index < 2^n. */
+int sv_init(const sv_state_t *s, uint64_t basis_index, sv_stream_t st);
+
+/* Kernel selection for sv_apply_gate. */
+typedef enum sv_mode {
+    SV_MODE_AUTO = 0,   /* scheduled enumeration, kernel chosen from the target */
+    SV_MODE_MASKED = 1, /* baseline: all 2^(n-1) pairs, control test per pair
+                           (the paper's baseline kernel figure, Sec. III-A) */
+    SV_MODE_PAIR = 2,   /* scheduled, one pair per iteration (Sec. III-B) */
+    SV_MODE_WAVE = 3,   /* scheduled at 64-amplitude granularity, partner
+                           exchanged inside the wavefront; target < 6 */
+    SV_MODE_TILE = 4    /* scheduled, LDS-staged tile of 2^m amplitudes;
+                           target < m (m chosen by the library) */
+} sv_mode;
+
+/* Apply one single-qubit gate with controls (paper Sec. III and III-B).
+ *   target      0 <= target < n
+ *   controls    ncontrols distinct qubits in [0, n), none equal to target,
+ *               in any order (the library sorts them; the skip-interval map
+ *               of Sec. III-B needs them ascending); may be NULL when
+ *               ncontrols == 0
+ *   ctrl_vals   qubit-indexed required values; bits outside the control set
+ *               must be 0
+ *   U           8 doubles, host memory (converted to float for complex64)
+ *   mode        sv_mode; every mode gives the same result
+ * Scheduled modes launch 2^(n-1-ncontrols) pair updates; SV_MODE_MASKED
+ * launches 2^(n-1) and skips the pairs whose controls fail. */
+int sv_apply_gate(const sv_state_t *s, int target, const int32_t *controls,
+                  int ncontrols, uint64_t ctrl_vals, const double *U, int mode,
+                  sv_stream_t st);
+
+/* Same gate with controls given as (ctrl_mask, ctrl_vals) bit masks. */
+int sv_apply_gate_masks(const sv_state_t *s, int target, uint64_t ctrl_mask,
+                        uint64_t ctrl_vals, const double *U, int mode,
+                        sv_stream_t st);
+
+/* Describe, without launching anything, the kernel sv_apply_gate would run
+ * for this gate: its demangled name (written to kernel, at most kernel_len
+ * bytes including the terminator; may be NULL) and its number of work items
+ * (pairs for the pair kernels, 64-amplitude chunks for SV_MODE_WAVE, tiles
+ * for SV_MODE_TILE; iterations may be NULL).  Host-only; needs no device. */
+int sv_gate_plan(int n, int dtype, int target, uint64_t ctrl_mask,
+                 uint64_t ctrl_vals, int mode, char *kernel, int kernel_len,
+                 uint64_t *iterations);
+
+/* Launch-choice knobs shared by every call of the process (not per device).
+ * Keys and ranges:
+ *   "granule_bits_c128", "granule_bits_c64"  [0, 6]  controls on index bits
+ *       below this value are tested per pair/lane instead of scheduled (a
+ *       skipped pair there shares cache lines with updated ones)
+ *   "low_policy"      [0, 1]  0: such failing pairs are skipped; 1: they are
+ *       read and rewritten unchanged so writes cover whole cache lines
+ *   "wave_auto"       [0, 1]  SV_MODE_AUTO may choose the wavefront kernel
+ *   "tile_log2_c128" [6, 13], "tile_log2_c64" [6, 14]  LDS tile width m of
+ *       the fused pass and of SV_MODE_TILE (2^m amplitudes per tile)
+ *   "fuse_min_gates"  [1, 2^20]  shortest gate run fused into one LDS pass
+ * None of them changes results.  SV_EINVAL for an unknown key or a value out
+ * of range.  Not thread-safe against concurrent launches. */
+int sv_tune_set(const char *key, int64_t value);
+int sv_tune_get(const char *key, int64_t *value);
+
+/* Write, for each reduced iteration index i_r in [0, 2^(n-1-ncontrols)), the
+ * index of the first pair element (bit target clear) that the scheduled
+ * kernels update for it, computed with the same device function they use
+ * (Sec. III-B: the reduced set mapped back to the global set, then to the
+ * pair index).  out_dev is a device array of out_len >= 2^(n-1-ncontrols)
+ * uint64 values; n <= 34. */
+int sv_debug_pair_indices(int n, int target, const int32_t *controls,
+                          int ncontrols, uint64_t ctrl_vals, uint64_t *out_dev,
+                          int64_t out_len, sv_stream_t st);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SV_H */

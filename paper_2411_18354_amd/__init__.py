@@ -1,0 +1,228 @@
+"""Python binding of libsv.so, the MI355X state-vector library.
+
+Argument marshalling only: every function here converts Python/torch
+arguments into the C ABI declared in include/sv.h and calls the function of
+the same name.  All arithmetic runs in the library's HIP kernels; torch only
+provides device memory (tensors) and streams.  If libsv.so is missing the
+import fails: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsv.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError("libsv.so not built at %s; run `python paper_2411_18354_amd/build.py`" % LIB_PATH)
+
+_L = ctypes.CDLL(LIB_PATH)
+
+SV_OK, SV_EINVAL, SV_ENOMEM, SV_EHIP, SV_ENOTSUP = 0, -1, -2, -3, -4
+SV_C128, SV_C64 = 0, 1
+SV_MODE_AUTO, SV_MODE_MASKED, SV_MODE_PAIR, SV_MODE_WAVE, SV_MODE_TILE = 0, 1, 2, 3, 4
+MODES = {"auto": SV_MODE_AUTO, "masked": SV_MODE_MASKED, "pair": SV_MODE_PAIR,
+         "wave": SV_MODE_WAVE, "tile": SV_MODE_TILE}
+
+
+class SvError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__("sv error %d: %s" % (code, msg))
+        self.code = code
+
+
+class sv_state_t(ctypes.Structure):
+    _fields_ = [("data", ctypes.c_void_p), ("n", ctypes.c_int32), ("dtype", ctypes.c_int32)]
+
+
+_vp, _i32, _u64, _i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_uint64, ctypes.c_int64
+_dp = ctypes.POINTER(ctypes.c_double)
+_sp = ctypes.POINTER(sv_state_t)
+
+
+def _sig(name, args, res=ctypes.c_int):
+    f = getattr(_L, name)
+    f.argtypes = args
+    f.restype = res
+    return f
+
+
+_L_last_error = _sig("sv_last_error", [], ctypes.c_char_p)
+_sig("sv_version", [])
+_sig("sv_alloc", [_sp, ctypes.c_int, ctypes.c_int])
+_sig("sv_free", [_sp])
+_sig("sv_init", [_sp, _u64, _vp])
+_sig("sv_apply_gate", [_sp, ctypes.c_int, ctypes.POINTER(_i32), ctypes.c_int, _u64, _dp, ctypes.c_int, _vp])
+_sig("sv_apply_gate_masks", [_sp, ctypes.c_int, _u64, _u64, _dp, ctypes.c_int, _vp])
+_sig("sv_debug_pair_indices", [ctypes.c_int, ctypes.c_int, ctypes.POINTER(_i32), ctypes.c_int, _u64, _vp,
+                               _i64, _vp])
+
+
+def lib():
+    return _L
+
+
+def sv_last_error() -> str:
+    return _L_last_error().decode()
+
+
+def sv_version() -> int:
+    return int(_L.sv_version())
+
+
+def _check(rc: int):
+    if rc != SV_OK:
+        raise SvError(rc, sv_last_error())
+
+
+# ---------------------------------------------------------------- marshalling
+
+def _torch():
+    import torch
+    return torch
+
+
+def stream_ptr(stream=None):
+    """hipStream_t of a torch stream (default: the current stream)."""
+    if isinstance(stream, (int, ctypes.c_void_p)):
+        return ctypes.c_void_p(stream if isinstance(stream, int) else stream.value)
+    torch = _torch()
+    if stream is None:
+        if not torch.cuda.is_available():
+            return ctypes.c_void_p(0)  # host-only use: argument checks, no launch
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _dtype_code(t) -> int:
+    torch = _torch()
+    if t.dtype == torch.complex128:
+        return SV_C128
+    if t.dtype == torch.complex64:
+        return SV_C64
+    raise TypeError("state tensor must be complex128 or complex64, got %s" % t.dtype)
+
+
+def state_view(t, n: Optional[int] = None) -> sv_state_t:
+    """sv_state_t view of a contiguous complex CUDA tensor of 2^n elements."""
+    if isinstance(t, sv_state_t):
+        return t
+    if not t.is_cuda or not t.is_contiguous():
+        raise ValueError("state must be a contiguous CUDA tensor")
+    numel = t.numel()
+    if n is None:
+        n = numel.bit_length() - 1
+    if numel != (1 << n):
+        raise ValueError("state has %d elements, expected 2^%d" % (numel, n))
+    return sv_state_t(t.data_ptr(), n, _dtype_code(t))
+
+
+def _u8(U) -> ctypes.Array:
+    """8 doubles (a, b, c, d as re, im) from a 2x2 complex array or 8 floats."""
+    import numpy as np
+    a = np.asarray(U)
+    if np.iscomplexobj(a) or a.shape == (2, 2):
+        a = np.asarray(a, dtype=np.complex128).reshape(4)
+        vals = [v for c in a for v in (float(c.real), float(c.imag))]
+    else:
+        vals = [float(v) for v in a.reshape(-1)]
+    if len(vals) != 8:
+        raise ValueError("U must be 2x2 complex or 8 doubles")
+    return (ctypes.c_double * 8)(*vals)
+
+
+def _ctrl_array(controls: Sequence[int]):
+    arr = (_i32 * max(1, len(controls)))(*[int(c) for c in controls])
+    return arr
+
+
+def ctrl_vals_mask(controls: Sequence[int], values: Sequence[int] = ()) -> int:
+    vals = list(values) if len(values) else [1] * len(controls)
+    if len(vals) != len(controls):
+        raise ValueError("values must align with controls")
+    m = 0
+    for q, v in zip(controls, vals):
+        if v:
+            m |= 1 << int(q)
+    return m
+
+
+# ---------------------------------------------------------------- C ABI
+
+def sv_alloc(n: int, dtype: int = SV_C128) -> sv_state_t:
+    s = sv_state_t()
+    _check(_L.sv_alloc(ctypes.byref(s), int(n), int(dtype)))
+    return s
+
+
+def sv_free(s: sv_state_t) -> None:
+    _check(_L.sv_free(ctypes.byref(s)))
+
+
+def sv_init(state, basis_index: int = 0, stream=None) -> None:
+    s = state_view(state)
+    _check(_L.sv_init(ctypes.byref(s), int(basis_index), stream_ptr(stream)))
+
+
+def sv_apply_gate(state, target: int, controls: Sequence[int] = (), ctrl_vals: Optional[int] = None,
+                  U=None, mode="auto", stream=None) -> None:
+    """Apply U (2x2) on target with controls; ctrl_vals is the qubit-indexed
+    mask of required control values (default: all controls require 1)."""
+    s = state_view(state)
+    if ctrl_vals is None:
+        ctrl_vals = ctrl_vals_mask(controls)
+    m = MODES[mode] if isinstance(mode, str) else int(mode)
+    _check(_L.sv_apply_gate(ctypes.byref(s), int(target), _ctrl_array(controls), len(controls),
+                            int(ctrl_vals), _u8(U), m, stream_ptr(stream)))
+
+
+def sv_apply_gate_masks(state, target: int, ctrl_mask: int, ctrl_vals: int, U, mode="auto", stream=None) -> None:
+    s = state_view(state)
+    m = MODES[mode] if isinstance(mode, str) else int(mode)
+    _check(_L.sv_apply_gate_masks(ctypes.byref(s), int(target), int(ctrl_mask), int(ctrl_vals), _u8(U), m,
+                                  stream_ptr(stream)))
+
+
+def sv_debug_pair_indices(n: int, target: int, controls: Sequence[int] = (), ctrl_vals: Optional[int] = None,
+                          out=None, stream=None):
+    """Device uint64 tensor of the first pair element for every reduced
+    iteration index, from the kernels' own index function."""
+    torch = _torch()
+    if ctrl_vals is None:
+        ctrl_vals = ctrl_vals_mask(controls)
+    count = 1 << (n - 1 - len(controls))
+    if out is None:
+        out = torch.empty(count, dtype=torch.uint64 if hasattr(torch, "uint64") else torch.int64, device="cuda")
+    _check(_L.sv_debug_pair_indices(int(n), int(target), _ctrl_array(controls), len(controls), int(ctrl_vals),
+                                    ctypes.c_void_p(out.data_ptr()), out.numel(), stream_ptr(stream)))
+    return out
+
+
+_sig("sv_gate_plan", [ctypes.c_int, ctypes.c_int, ctypes.c_int, _u64, _u64, ctypes.c_int, ctypes.c_char_p,
+                      ctypes.c_int, ctypes.POINTER(_u64)])
+
+
+def sv_gate_plan(n: int, dtype: int, target: int, ctrl_mask: int = 0, ctrl_vals: int = 0, mode="auto"):
+    """(kernel name, work items) that sv_apply_gate would launch."""
+    buf = ctypes.create_string_buffer(256)
+    it = _u64(0)
+    m = MODES[mode] if isinstance(mode, str) else int(mode)
+    _check(_L.sv_gate_plan(int(n), int(dtype), int(target), int(ctrl_mask), int(ctrl_vals), m, buf, 256,
+                           ctypes.byref(it)))
+    return buf.value.decode(), int(it.value)
+
+
+_sig("sv_tune_set", [ctypes.c_char_p, _i64])
+_sig("sv_tune_get", [ctypes.c_char_p, ctypes.POINTER(_i64)])
+
+
+def sv_tune_set(key: str, value: int) -> None:
+    _check(_L.sv_tune_set(key.encode(), int(value)))
+
+
+def sv_tune_get(key: str) -> int:
+    v = _i64(0)
+    _check(_L.sv_tune_get(key.encode(), ctypes.byref(v)))
+    return int(v.value)

@@ -1,0 +1,392 @@
+// Single-gate kernels: the control-scheduled pair kernel, the masked
+// baseline, the low-target wavefront kernel and the single-gate LDS tile
+// pass, plus sv_apply_gate.
+//
+// All kernels are in-place read-modify-write streams over the touched
+// amplitudes and are HBM-bound (0.44 flop/B in complex128), so the design
+// goal is full 16-byte (complex128) coalesced accesses and enough loads in
+// flight per lane; the index arithmetic is a handful of integer ops per pair.
+#include <algorithm>
+#include <cstring>
+
+#include "tile.hpp"
+
+namespace sv {
+
+constexpr int kThreads = 256;
+
+// What a pair or lane does when its lane-tested controls fail.
+constexpr int kSkip = 0;     // no load, no store (the baseline kernel figure)
+constexpr int kRewrite = 1;  // load and store the unchanged values, so that
+                             // writes cover whole cache lines
+
+// ---------------------------------------------------------------------------
+// Pair kernel.  Iteration i of the launch is one amplitude pair; its first
+// element is p1 = expand(i), the second p1 | 2^t.
+//   Scheduled (Sec. III-B): i runs over the reduced iteration set and the
+//     expansion inserts the target bit (0) and every scheduled control bit
+//     (its required value), so every iteration updates memory.  Controls
+//     below the granule bit (tmask) are tested per pair instead, because a
+//     pair skipped there shares its cache lines with pairs that are updated.
+//   Masked baseline (Sec. III-A, baseline kernel figure): i runs over all
+//     2^(n-1) pairs, the expansion inserts only the target bit, and the pair
+//     is skipped unless all its control bits (tmask) match.
+// Each lane handles K iterations spaced kThreads apart so a wavefront's loads
+// are contiguous and 2K loads per lane are in flight.
+// ---------------------------------------------------------------------------
+template <typename R, typename I, int K, int POLICY, typename MS>
+__global__ __launch_bounds__(kThreads) void k_pair(cplx_t<R> *__restrict__ psi, uint64_t niter, Expand e,
+                                                   uint64_t tmask, uint64_t tvals, uint32_t t, MS ms) {
+    const Mat2<R> m = ms.get();
+    const uint64_t base = (uint64_t)blockIdx.x * (kThreads * K) + threadIdx.x;
+    const I st = (I)1 << t;
+    cplx_t<R> x[K], y[K];
+    I p1[K];
+    bool in[K], pass[K];
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        const uint64_t i = base + (uint64_t)j * kThreads;
+        p1[j] = expand_index<I>(e, (I)i);
+        in[j] = i < niter;
+        pass[j] = in[j] && (((uint64_t)p1[j] & tmask) == tvals);
+        if (POLICY == kRewrite ? in[j] : pass[j]) {
+            x[j] = ld_stream<R>(psi + p1[j]);
+            y[j] = ld_stream<R>(psi + (p1[j] | st));
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        if (pass[j])
+            apply_pair<R>(m, x[j], y[j]);
+        if (POLICY == kRewrite ? in[j] : pass[j]) {
+            st_stream<R>(psi + p1[j], x[j]);
+            st_stream<R>(psi + (p1[j] | st), y[j]);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Wavefront kernel for targets whose partner lies in the same wavefront.
+// Iteration a of the launch is one amplitude, at index expand(a): the
+// expansion inserts the scheduled control bits only, so the target bit stays
+// a free bit of a.  A wavefront covers 64 consecutive iterations with one
+// contiguous load per lane (lane l holds iteration 64w + l); when the target
+// is free bit tl < 6 of a, the partner amplitude sits in lane l ^ 2^tl and is
+// exchanged across lanes.  Controls below the granule bit are tested per
+// lane.  This schedules at amplitude granularity: only amplitudes whose
+// scheduled controls hold are visited, every lane of a visited wavefront is
+// busy, and the loads stay fully contiguous.
+// ---------------------------------------------------------------------------
+template <typename R, int K, int POLICY, typename MS>
+__global__ __launch_bounds__(kThreads) void k_wave(cplx_t<R> *__restrict__ psi, uint64_t nwaves, Expand ae,
+                                                   uint32_t tmask, uint32_t tvals, uint32_t tl, MS ms) {
+    const Mat2<R> m = ms.get();
+    const uint32_t lane = threadIdx.x & 63;
+    const uint32_t wave = threadIdx.x >> 6;
+    constexpr int W = kThreads / 64;
+    const bool upper = (lane >> tl) & 1;
+    const int xm = 1 << tl;
+    cplx_t<R> v[K];
+    uint64_t addr[K];
+    bool in[K], pass[K];
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        const uint64_t w = ((uint64_t)blockIdx.x * K + j) * W + wave;
+        in[j] = w < nwaves;
+        addr[j] = expand_index<uint64_t>(ae, (w << 6) | lane);
+        pass[j] = in[j] && (((uint32_t)addr[j] & tmask) == tvals);
+        if (POLICY == kRewrite ? in[j] : pass[j])
+            v[j] = ld_stream<R>(psi + addr[j]);
+    }
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        if (!in[j])
+            continue;  // uniform across the wavefront
+        const cplx_t<R> p = lane_xor<R>(v[j], xm);
+        // component-wise selects keep everything in registers
+        cplx_t<R> lo, hi, o;
+        lo.x = upper ? p.x : v[j].x;
+        lo.y = upper ? p.y : v[j].y;
+        hi.x = upper ? v[j].x : p.x;
+        hi.y = upper ? v[j].y : p.y;
+        apply_pair<R>(m, lo, hi);
+        o.x = pass[j] ? (upper ? hi.x : lo.x) : v[j].x;
+        o.y = pass[j] ? (upper ? hi.y : lo.y) : v[j].y;
+        if (POLICY == kRewrite || pass[j])
+            st_stream<R>(psi + addr[j], o);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+
+TileGate make_tile_gate(int m, int target, uint64_t cmask, uint64_t cvals, const double *U) {
+    TileGate g;
+    memset(&g, 0, sizeof(g));
+    for (int i = 0; i < 8; ++i)
+        g.m[i] = U[i];
+    g.target = (uint32_t)target;
+    const uint64_t lowm = (m >= 64) ? ~0ull : ((1ull << m) - 1);
+    const uint64_t lo_c = cmask & lowm;
+    g.hi_mask = cmask & ~lowm;
+    g.hi_vals = cvals & ~lowm;
+    std::vector<int> pos, bits;
+    const uint64_t all = lo_c | (1ull << target);
+    for (int q = 0; q < m; ++q)
+        if (all & (1ull << q)) {
+            pos.push_back(q);
+            bits.push_back(q == target ? 0 : (int)((cvals >> q) & 1));
+        }
+    const Expand e = make_expand(m, pos, bits);
+    g.nseg = e.nseg;
+    for (uint32_t s = 0; s < e.nseg; ++s) {
+        g.shift[s] = e.shift[s];
+        g.mask[s] = (uint32_t)e.mask[s];
+    }
+    g.fixed = (uint32_t)e.fixed;
+    g.npairs = 1u << (m - 1 - popcount64(lo_c));
+    return g;
+}
+
+int tile_log2(int dtype) { return tuning().tile_log2[dtype == SV_C128 ? 0 : 1]; }
+
+template <typename R> static int set_lds_limit(const void *fn, size_t bytes) {
+    static bool done[2] = {false, false};
+    (void)done;
+    if (bytes > 65536)
+        SV_HIP_TRY(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+    return SV_OK;
+}
+
+// Pairs (or wavefronts) per lane: 4 once the launch has enough work to fill
+// the chip several times over, 1 below that so small launches still spread
+// over every CU.
+constexpr uint64_t kBigLaunch = (uint64_t)kThreads * 4 * 2048;
+
+int make_gate_plan(const GateSpec &g, int dtype, int mode, GatePlan *p) {
+    const Tuning &tn = tuning();
+    const int gb = std::min(tn.granule_bits[dtype == SV_C128 ? 0 : 1], 6);
+    const uint64_t low = (1ull << gb) - 1;
+    const uint64_t sched = g.cmask & ~low;  // controls scheduled by index expansion
+    p->tmask = g.cmask & low;               // controls tested per pair or lane
+    p->tvals = g.cvals & low;
+    p->policy = tn.low_policy;
+    p->target = g.target;
+    const int below_t = popcount64(sched & ((1ull << g.target) - 1));
+    const int tl = g.target - below_t;  // target's bit in the wave iteration index
+    const bool wave_ok = tl < 6 && g.n - popcount64(sched) >= 6;
+    int k = mode;
+    if (mode == SV_MODE_AUTO)
+        k = (wave_ok && tn.wave_auto) ? SV_MODE_WAVE : SV_MODE_PAIR;
+    std::vector<int> pos, bits;
+    switch (k) {
+    case SV_MODE_MASKED:
+        p->kind = GateKernel::Masked;
+        pos.push_back(g.target);
+        bits.push_back(0);
+        p->e = make_expand(g.n, pos, bits);
+        p->tmask = g.cmask;
+        p->tvals = g.cvals;
+        p->policy = kSkip;
+        p->niter = 1ull << (g.n - 1);
+        break;
+    case SV_MODE_PAIR: {
+        p->kind = GateKernel::Pair;
+        GateSpec gs{g.n, g.target, sched, g.cvals & sched};
+        gate_positions(gs, pos, bits);
+        p->e = make_expand(g.n, pos, bits);
+        p->niter = 1ull << (g.n - 1 - popcount64(sched));
+        break;
+    }
+    case SV_MODE_WAVE:
+        if (!wave_ok)
+            return fail(SV_EINVAL, "SV_MODE_WAVE needs the target among the 6 lowest free index bits and "
+                                   "n - scheduled controls >= 6 (target %d, n %d)", g.target, g.n);
+        p->kind = GateKernel::Wave;
+        for (int q = 0; q < g.n; ++q)
+            if (sched & (1ull << q)) {
+                pos.push_back(q);
+                bits.push_back((int)((g.cvals >> q) & 1));
+            }
+        p->e = make_expand(g.n, pos, bits);
+        p->target = tl;
+        p->niter = 1ull << (g.n - popcount64(sched) - 6);  // wavefronts of 64 amplitudes
+        break;
+    case SV_MODE_TILE: {
+        const int m = std::min(tile_log2(dtype), g.n);
+        if (g.target >= m)
+            return fail(SV_EINVAL, "SV_MODE_TILE needs target < %d (target %d)", m, g.target);
+        p->kind = GateKernel::Tile;
+        p->niter = 1ull << (g.n - m);
+        break;
+    }
+    default:
+        return fail(SV_EINVAL, "unknown mode %d", mode);
+    }
+    const uint64_t work = p->kind == GateKernel::Wave ? p->niter * 64 : p->niter;
+    p->unroll = work >= kBigLaunch ? 4 : 1;
+    if (p->kind == GateKernel::Masked || p->kind == GateKernel::Pair)
+        p->index64 = g.n > 32;
+    else
+        p->index64 = true;
+    return SV_OK;
+}
+
+std::string gate_plan_name(const GatePlan &p, int dtype, const char *matsrc) {
+    const char *R = dtype == SV_C128 ? "double" : "float";
+    char buf[256];
+    switch (p.kind) {
+    case GateKernel::Masked:
+    case GateKernel::Pair:
+        snprintf(buf, sizeof(buf), "sv::k_pair<%s, %s, %d, %d, sv::%s<%s> >", R,
+                 p.index64 ? "unsigned long" : "unsigned int", p.unroll, p.policy, matsrc, R);
+        break;
+    case GateKernel::Wave:
+        snprintf(buf, sizeof(buf), "sv::k_wave<%s, %d, %d, sv::%s<%s> >", R, p.unroll, p.policy, matsrc, R);
+        break;
+    default:
+        snprintf(buf, sizeof(buf), "sv::k_tile<%s, 512, sv::InlineGates<1> >", R);
+        break;
+    }
+    return buf;
+}
+
+template <typename R, typename I, int K, typename MS>
+static void go_pair(cplx_t<R> *psi, const GatePlan &p, const MS &ms, hipStream_t st) {
+    const uint64_t blocks = (p.niter + kThreads * K - 1) / (kThreads * K);
+    if (p.policy == kRewrite)
+        hipLaunchKernelGGL((k_pair<R, I, K, kRewrite, MS>), dim3((unsigned)blocks), dim3(kThreads), 0, st, psi,
+                           p.niter, p.e, p.tmask, p.tvals, (uint32_t)p.target, ms);
+    else
+        hipLaunchKernelGGL((k_pair<R, I, K, kSkip, MS>), dim3((unsigned)blocks), dim3(kThreads), 0, st, psi,
+                           p.niter, p.e, p.tmask, p.tvals, (uint32_t)p.target, ms);
+}
+
+template <typename R, int K, typename MS>
+static void go_wave(cplx_t<R> *psi, const GatePlan &p, const MS &ms, hipStream_t st) {
+    constexpr uint64_t W = kThreads / 64;
+    const uint64_t blocks = (p.niter + W * K - 1) / (W * K);
+    if (p.policy == kRewrite)
+        hipLaunchKernelGGL((k_wave<R, K, kRewrite, MS>), dim3((unsigned)blocks), dim3(kThreads), 0, st, psi,
+                           p.niter, p.e, (uint32_t)p.tmask, (uint32_t)p.tvals, (uint32_t)p.target, ms);
+    else
+        hipLaunchKernelGGL((k_wave<R, K, kSkip, MS>), dim3((unsigned)blocks), dim3(kThreads), 0, st, psi,
+                           p.niter, p.e, (uint32_t)p.tmask, (uint32_t)p.tvals, (uint32_t)p.target, ms);
+}
+
+template <typename R, typename MS>
+int launch_plan(cplx_t<R> *psi, const GatePlan &p, const MS &ms, hipStream_t st) {
+    switch (p.kind) {
+    case GateKernel::Masked:
+    case GateKernel::Pair:
+        if (p.index64) {
+            if (p.unroll == 4)
+                go_pair<R, uint64_t, 4>(psi, p, ms, st);
+            else
+                go_pair<R, uint64_t, 1>(psi, p, ms, st);
+        } else {
+            if (p.unroll == 4)
+                go_pair<R, uint32_t, 4>(psi, p, ms, st);
+            else
+                go_pair<R, uint32_t, 1>(psi, p, ms, st);
+        }
+        break;
+    case GateKernel::Wave:
+        if (p.unroll == 4)
+            go_wave<R, 4>(psi, p, ms, st);
+        else
+            go_wave<R, 1>(psi, p, ms, st);
+        break;
+    default:
+        return fail(SV_EINVAL, "launch_plan: tile plans go through the tile launcher");
+    }
+    SV_LAUNCH_CHECK();
+    return SV_OK;
+}
+
+template int launch_plan<double, MatVal<double>>(double2 *, const GatePlan &, const MatVal<double> &, hipStream_t);
+template int launch_plan<float, MatVal<float>>(float2 *, const GatePlan &, const MatVal<float> &, hipStream_t);
+template int launch_plan<double, MatPtr<double>>(double2 *, const GatePlan &, const MatPtr<double> &, hipStream_t);
+template int launch_plan<float, MatPtr<float>>(float2 *, const GatePlan &, const MatPtr<float> &, hipStream_t);
+
+template <typename R>
+static int launch_tile1(const sv_state_t *s, const GateSpec &g, const double *U, hipStream_t st) {
+    const int m = std::min(tile_log2(s->dtype), g.n);
+    InlineGates<1> gs;
+    gs.g[0] = make_tile_gate(m, g.target, g.cmask, g.cvals, U);
+    gs.count = 1;
+    const size_t lds = ((size_t)1 << m) * sizeof(cplx_t<R>);
+    auto fn = k_tile<R, 512, InlineGates<1>>;
+    SV_TRY(set_lds_limit<R>((const void *)fn, lds));
+    const uint64_t tiles = 1ull << (g.n - m);
+    hipLaunchKernelGGL(fn, dim3((unsigned)tiles), dim3(512), lds, st, reinterpret_cast<cplx_t<R> *>(s->data), m,
+                       gs);
+    SV_LAUNCH_CHECK();
+    return SV_OK;
+}
+
+int launch_gate(const sv_state_t *s, const GateSpec &g, const double *U, int mode, hipStream_t st) {
+    GatePlan p;
+    SV_TRY(make_gate_plan(g, s->dtype, mode, &p));
+    if (p.kind == GateKernel::Tile)
+        return s->dtype == SV_C128 ? launch_tile1<double>(s, g, U, st) : launch_tile1<float>(s, g, U, st);
+    if (s->dtype == SV_C128)
+        return launch_plan<double>(reinterpret_cast<double2 *>(s->data), p, MatVal<double>{to_mat<double>(U)}, st);
+    return launch_plan<float>(reinterpret_cast<float2 *>(s->data), p, MatVal<float>{to_mat<float>(U)}, st);
+}
+
+} // namespace sv
+
+using namespace sv;
+
+extern "C" {
+
+int sv_apply_gate_masks(const sv_state_t *s, int target, uint64_t ctrl_mask, uint64_t ctrl_vals, const double *U,
+                        int mode, sv_stream_t st) {
+    clear_error();
+    SV_TRY(validate_state(s));
+    if (!U)
+        return fail(SV_EINVAL, "U is NULL");
+    GateSpec g{s->n, target, ctrl_mask, ctrl_vals};
+    SV_TRY(validate_gate(g));
+    return launch_gate(s, g, U, mode, (hipStream_t)st);
+}
+
+int sv_apply_gate(const sv_state_t *s, int target, const int32_t *controls, int ncontrols, uint64_t ctrl_vals,
+                  const double *U, int mode, sv_stream_t st) {
+    clear_error();
+    SV_TRY(validate_state(s));
+    if (!U)
+        return fail(SV_EINVAL, "U is NULL");
+    if (target < 0 || target >= s->n)
+        return fail(SV_EINVAL, "target %d outside [0, %d)", target, s->n);
+    uint64_t mask = 0;
+    SV_TRY(controls_to_mask(s->n, target, controls, ncontrols, &mask));
+    GateSpec g{s->n, target, mask, ctrl_vals};
+    SV_TRY(validate_gate(g));
+    return launch_gate(s, g, U, mode, (hipStream_t)st);
+}
+
+int sv_gate_plan(int n, int dtype, int target, uint64_t ctrl_mask, uint64_t ctrl_vals, int mode, char *kernel,
+                 int kernel_len, uint64_t *iterations) {
+    clear_error();
+    if (dtype != SV_C128 && dtype != SV_C64)
+        return fail(SV_EINVAL, "unknown dtype %d", dtype);
+    if (n < 1 || n > max_qubits(dtype))
+        return fail(SV_EINVAL, "n=%d outside [1, %d]", n, max_qubits(dtype));
+    GateSpec g{n, target, ctrl_mask, ctrl_vals};
+    SV_TRY(validate_gate(g));
+    GatePlan p;
+    SV_TRY(make_gate_plan(g, dtype, mode, &p));
+    const std::string name = gate_plan_name(p, dtype, "MatVal");
+    if (iterations)
+        *iterations = p.niter;
+    if (kernel && kernel_len > 0) {
+        strncpy(kernel, name.c_str(), (size_t)kernel_len - 1);
+        kernel[kernel_len - 1] = '\0';
+    }
+    return SV_OK;
+}
+
+} // extern "C"

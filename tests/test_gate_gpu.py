@@ -1,0 +1,204 @@
+"""GPU parity of the single-gate path against the CPU oracle, through the
+C ABI: index sets bit-exact, amplitudes within 1e-12 (complex128) and 1e-5
+(complex64) relative to the largest oracle amplitude, all kernel modes
+bit-identical to each other."""
+import itertools
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"c128": 1e-12, "c64": 1e-5}
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _to_dev(psi, dtype):
+    import torch
+    t = torch.from_numpy(psi)
+    if dtype == "c64":
+        t = t.to(torch.complex64)
+    return t.cuda()
+
+
+def _rel_err(got, ref):
+    return float(np.max(np.abs(got.astype(np.complex128) - ref)) / max(1e-300, np.max(np.abs(ref))))
+
+
+def _rand_state(n, seed):
+    rng = np.random.default_rng(seed)
+    v = rng.standard_normal(1 << n) + 1j * rng.standard_normal(1 << n)
+    return v / np.linalg.norm(v)
+
+
+# ------------------------------------------------------------ index function
+
+def test_pair_indices_exhaustive_small(gpu):
+    import torch
+    _say("pair indices exhaustive n<=10, c<=4")
+    cases = 0
+    for n in range(1, 11):
+        for t in range(n):
+            others = [q for q in range(n) if q != t]
+            for c in range(0, min(4, n - 1) + 1):
+                for ctrls in itertools.combinations(others, c):
+                    got = gpu.sv_debug_pair_indices(n, t, ctrls)
+                    ref = oracle.pair_list(n, t, ctrls)
+                    assert np.array_equal(got.cpu().numpy().astype(np.uint64), ref), (n, t, ctrls)
+                    cases += 1
+    torch.cuda.synchronize()
+    _say("cases", cases)
+
+
+def test_pair_indices_random_values_and_large(gpu):
+    rng = np.random.default_rng(5)
+    for it in range(200):
+        n = int(rng.integers(2, 21))
+        t = int(rng.integers(0, n))
+        others = [q for q in range(n) if q != t]
+        c = int(rng.integers(0, min(8, n - 1) + 1))
+        ctrls = tuple(rng.choice(others, size=c, replace=False).tolist()) if c else ()
+        vals = tuple(int(v) for v in rng.integers(0, 2, size=c))
+        cv = gpu.ctrl_vals_mask(ctrls, vals)
+        got = gpu.sv_debug_pair_indices(n, t, ctrls, cv).cpu().numpy().astype(np.uint64)
+        ref = oracle.pair_list(n, t, ctrls, vals)
+        assert np.array_equal(got, ref), (n, t, ctrls, vals)
+
+
+def test_pair_indices_properties_n34(gpu):
+    """At n=34 (beyond 32-bit indices) check a slice of the device map by
+    properties that pin it: strictly increasing, right bits fixed, and the
+    free bits of the i-th index equal i (so the count and order are forced)."""
+    import torch
+    n, t, ctrls = 34, 33, (0, 5, 32)
+    vals = (1, 0, 1)
+    cv = gpu.ctrl_vals_mask(ctrls, vals)
+    count = 1 << (n - 1 - len(ctrls))
+    out = torch.empty(count, dtype=torch.int64, device="cuda")
+    gpu.sv_debug_pair_indices(n, t, ctrls, cv, out=out)
+    sl = np.concatenate([out[:1 << 16].cpu().numpy(), out[-(1 << 16):].cpu().numpy()]).astype(np.uint64)
+    ids = np.concatenate([np.arange(1 << 16), np.arange(count - (1 << 16), count)]).astype(np.uint64)
+    free = [q for q in range(n) if q != t and q not in ctrls]
+    rebuilt = np.zeros_like(ids)
+    for j, q in enumerate(free):
+        rebuilt |= ((ids >> np.uint64(j)) & np.uint64(1)) << np.uint64(q)
+    rebuilt |= np.uint64(cv)
+    assert np.array_equal(sl, rebuilt)
+    del out
+    torch.cuda.empty_cache()
+
+
+# ------------------------------------------------------------ amplitudes
+
+MODES_ALL = ("masked", "pair", "auto", "wave", "tile")
+# (granule bits, low-control policy) settings every kernel must agree under
+TUNINGS = ((0, 1), (3, 1), (3, 0), (6, 1), (2, 0))
+
+
+def _modes_for(gpu, n, t, dtype, cm=0, cv=0):
+    """Modes whose kernel accepts this gate under the current tuning."""
+    code = gpu.SV_C128 if dtype == "c128" else gpu.SV_C64
+    out = []
+    for m in MODES_ALL:
+        try:
+            gpu.sv_gate_plan(n, code, t, cm, cv, m)
+            out.append(m)
+        except gpu.SvError:
+            pass
+    assert "masked" in out and "pair" in out
+    return out
+
+
+def _set_tuning(gpu, gran, pol):
+    for k in ("granule_bits_c128", "granule_bits_c64"):
+        gpu.sv_tune_set(k, gran)
+    gpu.sv_tune_set("low_policy", pol)
+
+
+@pytest.mark.parametrize("tuning", TUNINGS)
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_single_gate_random(gpu, dtype, tuning):
+    _say("single gate random", dtype, "granule/policy", tuning)
+    _set_tuning(gpu, *tuning)
+    rng = np.random.default_rng(11)
+    worst = 0.0
+    for it in range(150):
+        n = int(rng.integers(1, 16))
+        t = int(rng.integers(0, n))
+        others = [q for q in range(n) if q != t]
+        c = int(rng.integers(0, min(5, n - 1) + 1))
+        ctrls = tuple(rng.choice(others, size=c, replace=False).tolist()) if c else ()
+        vals = tuple(int(v) for v in rng.integers(0, 2, size=c))
+        U = oracle.gate_matrix("U", matrix=W.haar_unitary_2x2(1000 + it))
+        psi = _rand_state(n, 2000 + it)
+        ref = oracle.apply_gate(psi.copy(), n, t, ctrls, vals, U)
+        outs = {}
+        cm, cv = sum(1 << q for q in ctrls), gpu.ctrl_vals_mask(ctrls, vals)
+        for mode in _modes_for(gpu, n, t, dtype, cm, cv):
+            d = _to_dev(psi, dtype)
+            gpu.sv_apply_gate(d, t, ctrls, cv, U, mode=mode)
+            outs[mode] = d.cpu().numpy()
+        for mode, got in outs.items():
+            err = _rel_err(got, ref)
+            worst = max(worst, err)
+            assert err <= TOL[dtype], (dtype, mode, n, t, ctrls, vals, err)
+            assert np.array_equal(got.view(np.uint8), outs["masked"].view(np.uint8)), (mode, n, t, ctrls)
+    _set_tuning(gpu, 0, 1)
+    _say("worst rel err", dtype, worst)
+
+
+def test_edge_cases(gpu):
+    import torch
+    # n=1: one pair; all-other-qubits controls: one pair; wave boundary n=6
+    for n, t, ctrls in ((1, 0, ()), (5, 2, (0, 1, 3, 4)), (6, 5, (0, 1, 2, 3, 4)), (6, 0, ()), (7, 6, (0,)),
+                        (13, 12, tuple(range(12))), (13, 0, tuple(range(1, 13)))):
+        U = oracle.gate_matrix("U", matrix=W.haar_unitary_2x2(n * 100 + t))
+        psi = _rand_state(n, n)
+        ref = oracle.apply_gate(psi.copy(), n, t, ctrls, (), U)
+        cm = sum(1 << q for q in ctrls)
+        for mode in _modes_for(gpu, n, t, "c128", cm, cm):
+            d = _to_dev(psi, "c128")
+            gpu.sv_apply_gate(d, t, ctrls, None, U, mode=mode)
+            assert _rel_err(d.cpu().numpy(), ref) <= 1e-12, (n, t, ctrls, mode)
+    # basis init
+    d = torch.empty(1 << 9, dtype=torch.complex128, device="cuda")
+    gpu.sv_init(d, 300)
+    h = d.cpu().numpy()
+    assert h[300] == 1 and np.count_nonzero(h) == 1
+    d = torch.empty(1 << 9, dtype=torch.complex64, device="cuda")
+    gpu.sv_init(d, 0)
+    assert d.cpu().numpy()[0] == 1
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("mode", ["auto", "masked"])
+def test_config0_circuit_gate_by_gate(gpu, dtype, mode):
+    """config0: n=12, 200 gates, |0..0>, applied gate by gate."""
+    import torch
+    c = W.config0()
+    ref = oracle.run_circuit(c)
+    d = torch.zeros(1 << c.n, dtype=torch.complex128 if dtype == "c128" else torch.complex64, device="cuda")
+    gpu.sv_init(d, 0)
+    for g in c.gates:
+        U = _matrix_via_library_conventions(g)
+        gpu.sv_apply_gate(d, g.target, g.controls, None, U, mode=mode)
+    err = _rel_err(d.cpu().numpy(), ref)
+    _say("config0", dtype, mode, "rel err", err)
+    assert err <= TOL[dtype]
+
+
+def _matrix_via_library_conventions(g):
+    """Named-gate matrices for the gate-by-gate test, written out here (not
+    taken from the oracle) from the textbook definitions."""
+    c, s = np.cos(g.theta / 2), np.sin(g.theta / 2)
+    return {"X": np.array([[0, 1], [1, 0]]), "H": np.array([[1, 1], [1, -1]]) / np.sqrt(2),
+            "RY": np.array([[c, -s], [s, c]]),
+            "RZ": np.diag([np.exp(-0.5j * g.theta), np.exp(0.5j * g.theta)])}[g.kind]

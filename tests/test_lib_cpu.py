@@ -1,0 +1,109 @@
+"""Host-only checks of libsv.so: it loads, exports every function sv.h
+declares, and rejects invalid arguments before touching a device."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "sv.h")
+LIB = os.path.join(ROOT, "paper_2411_18354_amd", "libsv.so")
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(sv_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_header_declares_entry_points():
+    names = _declared()
+    for required in ("sv_alloc", "sv_free", "sv_init", "sv_apply_gate", "sv_debug_pair_indices",
+                     "sv_last_error"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol():
+    assert os.path.exists(LIB), "build the library first"
+    out = subprocess.run(["nm", "-D", "--defined-only", LIB], capture_output=True, text=True, check=True).stdout
+    exported = set(re.findall(r"\bT (sv_[a-z0-9_]+)", out))
+    missing = [n for n in _declared() if n not in exported]
+    assert not missing, missing
+    L = ctypes.CDLL(LIB)
+    for n in _declared():
+        assert hasattr(L, n)
+
+
+@pytest.fixture(scope="module")
+def sv():
+    import paper_2411_18354_amd as sv
+    return sv
+
+
+def _state(sv, n=8, dtype=0, ptr=0x10000):
+    return sv.sv_state_t(ptr, n, dtype)
+
+
+def _rc(fn):
+    try:
+        fn()
+    except Exception as e:  # SvError
+        return getattr(e, "code", None), str(e)
+    return 0, ""
+
+
+U = [0, 0, 1, 0, 1, 0, 0, 0]
+
+
+@pytest.mark.parametrize("case,needle", [
+    (dict(target=8), "target"),
+    (dict(target=-1), "target"),
+    (dict(target=2, controls=(2,)), "equals the target"),
+    (dict(target=2, controls=(3, 3)), "duplicate"),
+    (dict(target=2, controls=(9,)), "outside"),
+    (dict(target=2, controls=(3,), ctrl_vals=1 << 4), "outside the control mask"),
+    (dict(target=2, mode=9), "mode"),
+    (dict(target=7, mode="wave"), "SV_MODE_WAVE"),
+    (dict(target=5, controls=(3, 4, 6, 7), n=8, mode="wave"), "SV_MODE_WAVE"),
+    (dict(target=12, mode="tile", n=14), "SV_MODE_TILE"),
+])
+def test_gate_argument_errors(sv, case, needle):
+    n = case.pop("n", 8)
+    s = _state(sv, n)
+    code, msg = _rc(lambda: sv.sv_apply_gate(s, U=U, **case))
+    assert code == sv.SV_EINVAL and needle in msg, msg
+
+
+def test_state_errors(sv):
+    for st, needle in ((_state(sv, 0), "n=0"), (_state(sv, 35), "n=35"), (_state(sv, 8, 2), "dtype"),
+                       (_state(sv, 8, 0, 0), "NULL"), (_state(sv, 8, 0, 0x10008), "aligned")):
+        code, msg = _rc(lambda: sv.sv_apply_gate(st, 0, U=U))
+        assert code == sv.SV_EINVAL and needle in msg, msg
+    code, msg = _rc(lambda: sv.sv_init(_state(sv, 4), 16))
+    assert code == sv.SV_EINVAL and "basis" in msg
+    code, msg = _rc(lambda: sv.sv_alloc(40))
+    assert code == sv.SV_EINVAL
+    # c64 allows one more qubit than c128
+    code, msg = _rc(lambda: sv.sv_apply_gate(_state(sv, 35, 1), 40, U=U))
+    assert code == sv.SV_EINVAL and "target" in msg
+
+
+def test_null_matrix_and_masks(sv):
+    L = sv.lib()
+    s = _state(sv)
+    rc = L.sv_apply_gate(ctypes.byref(s), 0, None, 0, 0, None, 0, None)
+    assert rc == sv.SV_EINVAL and "U is NULL" in sv.sv_last_error()
+    rc = L.sv_apply_gate(ctypes.byref(s), 0, None, 2, 0, (ctypes.c_double * 8)(*U), 0, None)
+    assert rc == sv.SV_EINVAL and "controls is NULL" in sv.sv_last_error()
+    code, msg = _rc(lambda: sv.sv_apply_gate_masks(s, 1, 0b10, 0, U))
+    assert code == sv.SV_EINVAL and "both target and control" in msg
+
+
+def test_debug_indices_errors(sv):
+    L = sv.lib()
+    rc = L.sv_debug_pair_indices(8, 0, None, 0, 0, ctypes.c_void_p(0x1000), 10, None)
+    assert rc == sv.SV_EINVAL and "out_len" in sv.sv_last_error()
+    rc = L.sv_debug_pair_indices(8, 0, None, 0, 0, None, 1 << 10, None)
+    assert rc == sv.SV_EINVAL
