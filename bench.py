@@ -60,6 +60,113 @@ def load_traffic(kernel, src_hash):
         return None
 
 
+COPY_KERNEL = "sv::k_copy"
+COPY_BYTES = 1 << 30  # read and written per calibration launch
+
+
+def _read_csv_rows(d, suffix):
+    import csv
+    import glob
+    rows = []
+    for f in glob.glob(os.path.join(d, "**", "*" + suffix), recursive=True):
+        with open(f) as fh:
+            rows += list(csv.DictReader(fh))
+    return rows
+
+
+def _counter_per_kernel(d, counter):
+    """{kernel name: [counter value per dispatch]} from counter_collection.csv."""
+    out = {}
+    for r in _read_csv_rows(d, "counter_collection.csv"):
+        if r.get("Counter_Name") != counter:
+            continue
+        out.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
+    return out
+
+
+def summarize_profile(trace_dir, fetch_dir, write_dir):
+    """Write the kernel-trace summary and the HBM-traffic record of the
+    dominant kernel under profiles/ from rocprofv3 CSV output."""
+    import subprocess
+    import workloads as W
+    import paper_2411_18354_amd as sv
+    n = N_QUBITS
+    cases = W.config1_cases(n, seed=3)
+    plan = {}
+    for t, ctrls in cases:
+        cm = sum(1 << q for q in ctrls)
+        name, pairs = sv.sv_gate_plan(n, sv.SV_C128, t, cm, cm, "auto")
+        plan.setdefault(name, []).append(2 * (1 << (n - 1 - len(ctrls))) * 2 * AMP_BYTES)
+    stats = _read_csv_rows(trace_dir, "kernel_stats.csv")
+    stats.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    dom = None
+    for r in stats:
+        for k in plan:
+            if r["Name"].startswith("void " + k) or r["Name"].startswith(k):
+                dom = (k, r)
+                break
+        if dom:
+            break
+    assert dom, "dominant kernel not found in the trace"
+    kname, krow = dom
+    alg = sum(plan[kname]) / len(plan[kname])
+    src_hash = kernel_source_hash()
+    os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
+    lines = ["# Kernel trace: controlled-gate sweep, n=28 complex128", "",
+             "Command (from the repository root; rocprofv3 1.x, ROCm 7.2):", "",
+             "    rocprofv3 --kernel-trace --stats -f csv -d <dir> -o bench -- "
+             "python3 bench.py --steps 5 --warmup 1 --cpu-seconds 0 --no-masked --pmc-copy", "",
+             "kernel_source_hash: %s" % src_hash, "",
+             "| kernel | calls | avg us | min us | max us | share |", "|---|---|---|---|---|---|"]
+    for r in stats[:12]:
+        nm = r["Name"].split("(")[0].replace("void ", "")
+        lines.append("| `%s` | %s | %.2f | %.2f | %.2f | %.1f%% |" % (
+            nm, r["Calls"], float(r["AverageNs"]) / 1e3, float(r["MinNs"]) / 1e3, float(r["MaxNs"]) / 1e3,
+            float(r["Percentage"])))
+    lines += ["", "Dominant scheduled kernel: `%s`, average %.2f us over %s launches; "
+              "average algorithmic bytes per launch %.4g (read + write of every touched "
+              "amplitude), i.e. %.1f GB/s." % (kname, float(krow["AverageNs"]) / 1e3, krow["Calls"], alg,
+                                                alg / float(krow["AverageNs"]))]
+    with open(os.path.join(ROOT, "profiles", "kernel_trace_config1_n28.md"), "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    # traffic: FETCH_SIZE and WRITE_SIZE (KiB per dispatch), scaled by the copy kernel
+    fetch = _counter_per_kernel(fetch_dir, "FETCH_SIZE")
+    write = _counter_per_kernel(write_dir, "WRITE_SIZE")
+
+    def pick(dct, key):
+        for k, v in dct.items():
+            if k.replace("void ", "").startswith(key):
+                return v
+        return None
+    fk, wk = pick(fetch, kname), pick(write, kname)
+    fc, wc = pick(fetch, COPY_KERNEL), pick(write, COPY_KERNEL)
+    assert fk and wk and fc and wc, "counters missing for the kernel or the copy calibration"
+    f_scale = COPY_BYTES / (sum(fc) / len(fc) * 1024.0)
+    w_scale = COPY_BYTES / (sum(wc) / len(wc) * 1024.0)
+    f_b = sum(fk) / len(fk) * 1024.0 * f_scale
+    w_b = sum(wk) / len(wk) * 1024.0 * w_scale
+    tl = ["# HBM traffic of the dominant kernel: controlled-gate sweep, n=28 complex128", "",
+          "Commands (each its own run, from the repository root):", "",
+          "    rocprofv3 --pmc FETCH_SIZE -f csv -d <fetch_dir> -o bench -- python3 bench.py --steps 2 "
+          "--warmup 0 --cpu-seconds 0 --no-masked --pmc-copy",
+          "    rocprofv3 --pmc WRITE_SIZE -f csv -d <write_dir> -o bench -- python3 bench.py --steps 2 "
+          "--warmup 0 --cpu-seconds 0 --no-masked --pmc-copy", "",
+          "Counters are KiB per dispatch.  Each is scaled by what it reads for the library's plain copy "
+          "kernel `sv::k_copy` moving a known 1 GiB (read 1 GiB, write 1 GiB): FETCH scale %.4f, "
+          "WRITE scale %.4f." % (f_scale, w_scale), "",
+          "- kernel: %s" % kname.replace(" ", "_"),
+          "- kernel_source_hash: %s" % src_hash,
+          "- dispatches: %d" % len(fk),
+          "- fetch_bytes_per_launch: %.6g" % f_b,
+          "- write_bytes_per_launch: %.6g" % w_b,
+          "- hbm_bytes_per_launch: %.6g" % (f_b + w_b),
+          "- alg_bytes_per_launch: %.6g" % alg,
+          "- traffic_over_alg: %.4f" % ((f_b + w_b) / alg), ""]
+    with open(os.path.join(ROOT, "profiles", "traffic_k_pair_config1_n28.md"), "w") as fh:
+        fh.write("\n".join(tl) + "\n")
+    print("\n".join(lines + [""] + tl))
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -68,7 +175,15 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="time budget of the CPU-oracle baseline sample (0 disables it)")
     ap.add_argument("--no-masked", action="store_true", help="skip the masked-baseline sweep")
+    ap.add_argument("--pmc-copy", action="store_true",
+                    help="first copy a 1 GiB state three times with the library's plain copy kernel "
+                         "(calibration of the rocprofv3 byte counters)")
+    ap.add_argument("--summarize-profile", nargs=3, metavar=("TRACE_DIR", "FETCH_DIR", "WRITE_DIR"),
+                    help="write profiles/ summaries from rocprofv3 CSV output of this script and exit")
     args = ap.parse_args()
+    if args.summarize_profile:
+        summarize_profile(*args.summarize_profile)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
               "(the sharding design is described in DESIGN.md); rerun with --gpus 1", file=sys.stderr)
@@ -93,6 +208,13 @@ def main():
     cases = [cases[i] for i in order]
     d = torch.from_numpy(psi_host).to(dev)
     stream = torch.cuda.Stream(device=dev)  # default priority
+    if args.pmc_copy:
+        a = torch.zeros(1 << 26, dtype=torch.complex128, device=dev)  # 1 GiB
+        b = torch.empty_like(a)
+        for _ in range(3):
+            sv.sv_copy_state(b, a, stream=stream)
+        torch.cuda.synchronize()
+        del a, b
 
     plans = {}
     for mode in ("auto", "masked"):

@@ -79,6 +79,10 @@ int sv_free(sv_state_t *s);
  * amplitude basis_index = 1).  basis_index < 2^n. */
 int sv_init(const sv_state_t *s, uint64_t basis_index, sv_stream_t st);
 
+/* Copy one state into another of the same n and dtype (non-overlapping
+ * device buffers; a state copied onto itself is a no-op). */
+int sv_copy_state(const sv_state_t *dst, const sv_state_t *src, sv_stream_t st);
+
 /* Kernel selection for sv_apply_gate. */
 typedef enum sv_mode {
     SV_MODE_AUTO = 0,   /* scheduled enumeration, kernel chosen from the target */

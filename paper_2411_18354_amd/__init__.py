@@ -226,3 +226,11 @@ def sv_tune_get(key: str) -> int:
     v = _i64(0)
     _check(_L.sv_tune_get(key.encode(), ctypes.byref(v)))
     return int(v.value)
+
+
+_sig("sv_copy_state", [_sp, _sp, _vp])
+
+
+def sv_copy_state(dst, src, stream=None) -> None:
+    a, b = state_view(dst), state_view(src)
+    _check(_L.sv_copy_state(ctypes.byref(a), ctypes.byref(b), stream_ptr(stream)))
