@@ -141,6 +141,93 @@ int sv_gate_plan(int n, int dtype, int target, uint64_t ctrl_mask,
 int sv_tune_set(const char *key, int64_t value);
 int sv_tune_get(const char *key, int64_t *value);
 
+/* ------------------------------------------------------------------ circuits
+ *
+ * A circuit is a sequence of gates applied in order (the paper schedules one
+ * launch per gate, serially, Sec. III-A).  Gate kinds (named gates follow
+ * Nielsen & Chuang; X and H as in Sec. I; R_m of the QFT is SV_G_P with angle
+ * 2 pi / 2^m):
+ *   SV_G_MATRIX  the 8 doubles in U
+ *   SV_G_X, SV_G_Y, SV_G_Z, SV_G_H
+ *   SV_G_RX, SV_G_RY, SV_G_RZ   exp(-i theta P / 2)
+ *   SV_G_P       diag(1, e^{i theta})
+ * OR-ing SV_G_ADJOINT into kind applies the conjugate transpose. */
+typedef enum sv_gate_kind {
+    SV_G_MATRIX = 0,
+    SV_G_X = 1,
+    SV_G_Y = 2,
+    SV_G_Z = 3,
+    SV_G_H = 4,
+    SV_G_RX = 5,
+    SV_G_RY = 6,
+    SV_G_RZ = 7,
+    SV_G_P = 8
+} sv_gate_kind;
+#define SV_G_ADJOINT 0x100
+
+typedef struct sv_gate {
+    int32_t kind;       /* sv_gate_kind, optionally | SV_G_ADJOINT */
+    int32_t target;     /* 0 <= target < n */
+    uint64_t ctrl_mask; /* qubit-indexed controls (target bit clear) */
+    uint64_t ctrl_vals; /* required control values (subset of ctrl_mask) */
+    int32_t param;      /* RX/RY/RZ/P: >= 0 takes the angle from
+                           params[param] on the device at run time; -1 uses
+                           theta.  Must be -1 for the other kinds. */
+    int32_t reserved;   /* 0 */
+    double theta;       /* angle when param < 0 */
+    double U[8];        /* SV_G_MATRIX only */
+} sv_gate_t;
+
+/* Circuit flags. */
+#define SV_FUSE 1    /* fuse runs of gates with target below the LDS tile
+                        width into one LDS-resident pass per tile */
+#define SV_GRAPH 2   /* capture the launch sequence once as a HIP graph and
+                        replay it (per state and parameter pointer pair) */
+#define SV_MASKED 4  /* every gate on the masked baseline kernel, no fusion */
+
+/* Write the 2x2 matrix of a gate kind (8 doubles, layout as above) for angle
+ * theta; U is read for SV_G_MATRIX only (may be NULL otherwise).  Host-only. */
+int sv_gate_matrix(int kind, double theta, const double *U, double *out);
+
+typedef struct sv_circuit sv_circuit_t;
+
+/* Validate a gate list for an n-qubit state of the given dtype, plan it
+ * (fusion, kernel choice per pass) and copy it to the current device.
+ * nparams is the length of the parameter array later passed to
+ * sv_circuit_run (every gate's param must be < nparams).  Validation covers
+ * every gate before anything is allocated, so an error names the first bad
+ * gate (its index is in the message) and creates nothing.  The returned
+ * handle is released with sv_circuit_destroy. */
+int sv_circuit_create(int n, int dtype, const sv_gate_t *gates, int ngates, int nparams, int flags,
+                      sv_circuit_t **out);
+
+/* Apply the circuit to s (same n and dtype as at creation).  params_dev is a
+ * device array of nparams doubles (may be NULL when nparams == 0), read by
+ * the kernels when the stream reaches them.  Calls on one handle must not
+ * run concurrently with each other. */
+int sv_circuit_run(sv_circuit_t *c, const sv_state_t *s, const double *params_dev, sv_stream_t st);
+
+/* Plan statistics: number of HBM passes (fused runs + single-gate launches),
+ * number of gates inside fused runs, and number of fused runs.  Any output
+ * pointer may be NULL. */
+int sv_circuit_info(const sv_circuit_t *c, int64_t *passes, int64_t *fused_gates, int64_t *fused_runs);
+
+/* Host-only dry run of sv_circuit_create's planner (no device needed):
+ * validates the gates and writes the execution order the plan uses
+ * (order[k] = index of the k-th gate applied; gates moved ahead only past
+ * gates they commute with) and the pass each belongs to (pass_of[k]; gates of
+ * one fused run share a pass).  order and pass_of hold ngates entries each
+ * (either may be NULL); npasses (may be NULL) receives the pass count. */
+int sv_circuit_plan(int n, int dtype, const sv_gate_t *gates, int ngates, int nparams, int flags, int32_t *order,
+                    int32_t *pass_of, int64_t *npasses);
+
+/* Release the plan (waits for the device work of earlier runs to finish). */
+int sv_circuit_destroy(sv_circuit_t *c);
+
+/* One-shot: create, run on st, destroy.  SV_GRAPH is ignored here. */
+int sv_apply_circuit(const sv_state_t *s, const sv_gate_t *gates, int ngates, const double *params_dev,
+                     int nparams, int flags, sv_stream_t st);
+
 /* Write, for each reduced iteration index i_r in [0, 2^(n-1-ncontrols)), the
  * index of the first pair element (bit target clear) that the scheduled
  * kernels update for it, computed with the same device function they use

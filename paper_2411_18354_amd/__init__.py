@@ -234,3 +234,128 @@ _sig("sv_copy_state", [_sp, _sp, _vp])
 def sv_copy_state(dst, src, stream=None) -> None:
     a, b = state_view(dst), state_view(src)
     _check(_L.sv_copy_state(ctypes.byref(a), ctypes.byref(b), stream_ptr(stream)))
+
+
+# ---------------------------------------------------------------- circuits
+
+SV_G_MATRIX, SV_G_X, SV_G_Y, SV_G_Z, SV_G_H, SV_G_RX, SV_G_RY, SV_G_RZ, SV_G_P = range(9)
+SV_G_ADJOINT = 0x100
+SV_FUSE, SV_GRAPH, SV_MASKED = 1, 2, 4
+KIND_CODES = {"U": SV_G_MATRIX, "X": SV_G_X, "Y": SV_G_Y, "Z": SV_G_Z, "H": SV_G_H,
+              "RX": SV_G_RX, "RY": SV_G_RY, "RZ": SV_G_RZ, "P": SV_G_P}
+
+
+class sv_gate_t(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("target", ctypes.c_int32), ("ctrl_mask", ctypes.c_uint64),
+                ("ctrl_vals", ctypes.c_uint64), ("param", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("theta", ctypes.c_double), ("U", ctypes.c_double * 8)]
+
+
+def kind_code(kind: str) -> int:
+    adj = kind.startswith("~")
+    return KIND_CODES[kind[1:] if adj else kind] | (SV_G_ADJOINT if adj else 0)
+
+
+def circuit_gates(circ_or_gates):
+    """ctypes array of sv_gate_t from a workloads.Circuit (or a gate list)."""
+    gates = getattr(circ_or_gates, "gates", circ_or_gates)
+    arr = (sv_gate_t * max(1, len(gates)))()
+    for i, g in enumerate(gates):
+        e = arr[i]
+        e.kind = kind_code(g.kind)
+        e.target = int(g.target)
+        vals = g.values if len(g.values) else (1,) * len(g.controls)
+        e.ctrl_mask = sum(1 << int(q) for q in g.controls)
+        e.ctrl_vals = sum(1 << int(q) for q, v in zip(g.controls, vals) if v)
+        e.param = int(g.param) if g.param is not None and g.param >= 0 else -1
+        e.reserved = 0
+        e.theta = float(g.theta)
+        if g.matrix is not None:
+            for k in range(8):
+                e.U[k] = float(g.matrix[k])
+    arr._sv_count = len(gates)
+    return arr
+
+
+_sig("sv_gate_matrix", [ctypes.c_int, ctypes.c_double, _dp, _dp])
+_sig("sv_circuit_create", [ctypes.c_int, ctypes.c_int, ctypes.POINTER(sv_gate_t), ctypes.c_int, ctypes.c_int,
+                           ctypes.c_int, ctypes.POINTER(_vp)])
+_sig("sv_circuit_run", [_vp, _sp, _vp, _vp])
+_sig("sv_circuit_info", [_vp, ctypes.POINTER(_i64), ctypes.POINTER(_i64), ctypes.POINTER(_i64)])
+_sig("sv_circuit_destroy", [_vp])
+_sig("sv_apply_circuit", [_sp, ctypes.POINTER(sv_gate_t), ctypes.c_int, _vp, ctypes.c_int, ctypes.c_int, _vp])
+
+
+def sv_gate_matrix(kind, theta: float = 0.0, U=None):
+    """The library's 2x2 matrix for a gate kind (code or name), as 8 doubles."""
+    k = kind_code(kind) if isinstance(kind, str) else int(kind)
+    out = (ctypes.c_double * 8)()
+    u = _u8(U) if U is not None else None
+    _check(_L.sv_gate_matrix(k, float(theta), u, out))
+    return list(out)
+
+
+def _params_ptr(params):
+    if params is None:
+        return ctypes.c_void_p(0), 0
+    return ctypes.c_void_p(params.data_ptr()), int(params.numel())
+
+
+class Circuit:
+    """Owns an sv_circuit_t plan (sv_circuit_create / run / destroy)."""
+
+    def __init__(self, n: int, gates, dtype: int = SV_C128, nparams: int = 0, flags: int = SV_FUSE):
+        arr = gates if isinstance(gates, ctypes.Array) else circuit_gates(gates)
+        count = getattr(arr, "_sv_count", len(arr))
+        h = _vp()
+        _check(_L.sv_circuit_create(int(n), int(dtype), arr, count, int(nparams), int(flags), ctypes.byref(h)))
+        self._h = h
+        self.n, self.dtype, self.nparams, self.flags = n, dtype, nparams, flags
+
+    def run(self, state, params=None, stream=None) -> None:
+        s = state_view(state)
+        p, _ = _params_ptr(params)
+        _check(_L.sv_circuit_run(self._h, ctypes.byref(s), p, stream_ptr(stream)))
+
+    def info(self):
+        a, b, c = _i64(0), _i64(0), _i64(0)
+        _check(_L.sv_circuit_info(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+        return {"passes": a.value, "fused_gates": b.value, "fused_runs": c.value}
+
+    def close(self) -> None:
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _L.sv_circuit_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def sv_apply_circuit(state, gates, params=None, nparams: Optional[int] = None, flags: int = SV_FUSE,
+                     stream=None) -> None:
+    s = state_view(state)
+    arr = gates if isinstance(gates, ctypes.Array) else circuit_gates(gates)
+    count = getattr(arr, "_sv_count", len(arr))
+    p, np_ = _params_ptr(params)
+    if nparams is None:
+        nparams = np_
+    _check(_L.sv_apply_circuit(ctypes.byref(s), arr, count, p, int(nparams), int(flags), stream_ptr(stream)))
+
+
+_sig("sv_circuit_plan", [ctypes.c_int, ctypes.c_int, ctypes.POINTER(sv_gate_t), ctypes.c_int, ctypes.c_int,
+                         ctypes.c_int, ctypes.POINTER(_i32), ctypes.POINTER(_i32), ctypes.POINTER(_i64)])
+
+
+def sv_circuit_plan(n: int, gates, dtype: int = SV_C128, nparams: int = 0, flags: int = SV_FUSE):
+    """Host-only planner dry run: (order, pass_of, npasses)."""
+    arr = gates if isinstance(gates, ctypes.Array) else circuit_gates(gates)
+    count = getattr(arr, "_sv_count", len(arr))
+    order = (_i32 * max(1, count))()
+    pas = (_i32 * max(1, count))()
+    npas = _i64(0)
+    _check(_L.sv_circuit_plan(int(n), int(dtype), arr, count, int(nparams), int(flags), order, pas,
+                              ctypes.byref(npas)))
+    return list(order)[:count], list(pas)[:count], int(npas.value)

@@ -1,0 +1,490 @@
+// Circuit driver: validation of a whole gate list, the fusion planner, the
+// per-pass launch sequence and its HIP-graph capture.
+//
+// The paper applies a circuit as one kernel launch per gate, in order, since
+// consecutive gates depend on each other (Sec. III-A).  Here every gate is
+// still one pass unless it can join an LDS-fused run: gates whose target lies
+// below the tile width m touch only amplitudes inside aligned 2^m-amplitude
+// tiles, so a run of them is applied tile by tile with one HBM read and one
+// HBM write per touched tile (gate fusion, future work in Sec. V).  A gate
+// whose target is at or above m may be deferred past later fusable gates when
+// the two commute (see commute() below), so runs are not cut by every
+// unrelated high-target gate.
+#include <algorithm>
+#include <cstring>
+#include <memory>
+
+#include "gates.hpp"
+#include "tile.hpp"
+
+namespace sv {
+
+struct ParamJob {
+    int32_t kind;
+    int32_t param;
+    int32_t mat_slot;   // gate index: matrix at mats + 8 * mat_slot
+    int32_t tile_slot;  // fused-run descriptor index or -1
+};
+
+struct Pass {
+    bool fused;
+    int gate;        // single: gate index
+    int first, count;  // fused: descriptors [first, first + count)
+    GatePlan plan;   // single
+};
+
+__global__ void k_param_mats(const ParamJob *__restrict__ jobs, int njobs, const double *__restrict__ params,
+                             double *__restrict__ mats, TileGate *__restrict__ tiles) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= njobs)
+        return;
+    const ParamJob j = jobs[i];
+    double m[8];
+    gate_matrix(j.kind, params[j.param], nullptr, m);
+    for (int k = 0; k < 8; ++k)
+        mats[8 * j.mat_slot + k] = m[k];
+    if (j.tile_slot >= 0)
+        for (int k = 0; k < 8; ++k)
+            tiles[j.tile_slot].m[k] = m[k];
+}
+
+// Gates a and b commute when every qubit they share is, in each of them,
+// either a control or the target of a diagonal gate: both are then block
+// diagonal over the shared qubits and act on disjoint qubits inside each
+// block.
+static bool commute(const sv_gate_t &a, const sv_gate_t &b) {
+    const uint64_t qa = a.ctrl_mask | (1ull << a.target);
+    const uint64_t qb = b.ctrl_mask | (1ull << b.target);
+    const uint64_t shared = qa & qb;
+    if (!shared)
+        return true;
+    const bool da = gate_kind_diagonal(a.kind), db = gate_kind_diagonal(b.kind);
+    if ((shared & (1ull << a.target)) && !da)
+        return false;
+    if ((shared & (1ull << b.target)) && !db)
+        return false;
+    return true;
+}
+
+int validate_circuit_gate(int n, int nparams, const sv_gate_t &g, int index) {
+    if (!gate_kind_valid(g.kind))
+        return fail(SV_EINVAL, "gate %d: unknown kind %d", index, g.kind);
+    GateSpec gs{n, g.target, g.ctrl_mask, g.ctrl_vals};
+    const int r = validate_gate(gs);
+    if (r != SV_OK) {
+        char msg[400];
+        snprintf(msg, sizeof(msg), "%s", sv_last_error());
+        return fail(r, "gate %d: %s", index, msg);
+    }
+    if (g.param >= 0) {
+        if (!gate_kind_param(g.kind))
+            return fail(SV_EINVAL, "gate %d: kind %d takes no parameter (param %d)", index, g.kind, g.param);
+        if (g.param >= nparams)
+            return fail(SV_EINVAL, "gate %d: param %d >= nparams %d", index, g.param, nparams);
+    } else if (g.param != -1) {
+        return fail(SV_EINVAL, "gate %d: param %d (use -1 for none)", index, g.param);
+    }
+    return SV_OK;
+}
+
+} // namespace sv
+
+using namespace sv;
+
+struct sv_circuit {
+    int n = 0, dtype = 0, flags = 0, nparams = 0, device = 0, m = 0;
+    std::vector<sv_gate_t> gates;
+    std::vector<Pass> passes;
+    int njobs = 0;
+    int64_t fused_gates = 0, fused_runs = 0;
+    double *d_mats = nullptr;
+    TileGate *d_tiles = nullptr;
+    ParamJob *d_jobs = nullptr;
+    bool async_buffers = false;  // allocated stream-ordered (one-shot use)
+    hipStream_t cap = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    void *g_data = nullptr;
+    const double *g_params = nullptr;
+    hipEvent_t done = nullptr;
+};
+
+namespace sv {
+
+static int plan_circuit(sv_circuit *c, std::vector<TileGate> &tiles, std::vector<ParamJob> &jobs,
+                        std::vector<double> &mats) {
+    const int G = (int)c->gates.size();
+    mats.assign((size_t)G * 8, 0.0);
+    for (int i = 0; i < G; ++i) {
+        const sv_gate_t &g = c->gates[i];
+        if (g.param < 0)
+            gate_matrix(g.kind, g.theta, g.U, &mats[(size_t)8 * i]);
+    }
+    const bool masked = c->flags & SV_MASKED;
+    const bool fuse = (c->flags & SV_FUSE) && !masked;
+    c->m = std::min(tuning().tile_log2[c->dtype == SV_C128 ? 0 : 1], c->n);
+    const int min_run = std::max(1, tuning().fuse_min_gates);
+    std::vector<int> tile_slot(G, -1);
+
+    auto single = [&](int i) -> int {
+        Pass p;
+        p.fused = false;
+        p.gate = i;
+        p.first = p.count = 0;
+        const sv_gate_t &g = c->gates[i];
+        GateSpec gs{c->n, g.target, g.ctrl_mask, g.ctrl_vals};
+        SV_TRY(make_gate_plan(gs, c->dtype, masked ? SV_MODE_MASKED : SV_MODE_AUTO, &p.plan));
+        c->passes.push_back(p);
+        return SV_OK;
+    };
+    std::vector<int> run, deferred;
+    auto flush = [&]() -> int {
+        if ((int)run.size() >= min_run) {
+            Pass p;
+            p.fused = true;
+            p.gate = -1;
+            p.first = (int)tiles.size();
+            p.count = (int)run.size();
+            for (int i : run) {
+                const sv_gate_t &g = c->gates[i];
+                tile_slot[i] = (int)tiles.size();
+                tiles.push_back(make_tile_gate(c->m, g.target, g.ctrl_mask, g.ctrl_vals, &mats[(size_t)8 * i]));
+                tiles.back().src_gate = i;
+            }
+            c->passes.push_back(p);
+            c->fused_gates += (int64_t)run.size();
+            c->fused_runs++;
+        } else {
+            for (int i : run)
+                SV_TRY(single(i));
+        }
+        for (int i : deferred)
+            SV_TRY(single(i));
+        run.clear();
+        deferred.clear();
+        return SV_OK;
+    };
+    for (int i = 0; i < G; ++i) {
+        const sv_gate_t &g = c->gates[i];
+        if (!fuse) {
+            SV_TRY(single(i));
+            continue;
+        }
+        if (g.target < c->m) {
+            bool ok = true;
+            for (int d : deferred)
+                if (!commute(g, c->gates[d])) {
+                    ok = false;
+                    break;
+                }
+            if (!ok)
+                SV_TRY(flush());
+            run.push_back(i);
+        } else if (run.empty()) {
+            SV_TRY(single(i));
+        } else {
+            deferred.push_back(i);
+            if (deferred.size() > 64)
+                SV_TRY(flush());
+        }
+    }
+    SV_TRY(flush());
+    for (int i = 0; i < G; ++i) {
+        const sv_gate_t &g = c->gates[i];
+        if (g.param >= 0)
+            jobs.push_back(ParamJob{g.kind, g.param, i, tile_slot[i]});
+    }
+    c->njobs = (int)jobs.size();
+    return SV_OK;
+}
+
+static void free_buffers(sv_circuit *c, hipStream_t st) {
+    void *bufs[3] = {c->d_mats, c->d_tiles, c->d_jobs};
+    for (void *b : bufs)
+        if (b) {
+            if (c->async_buffers)
+                (void)hipFreeAsync(b, st);
+            else
+                (void)hipFree(b);
+        }
+    c->d_mats = nullptr;
+    c->d_tiles = nullptr;
+    c->d_jobs = nullptr;
+}
+
+template <typename T> static int upload(T **dst, const std::vector<T> &src, bool async, hipStream_t st) {
+    *dst = nullptr;
+    if (src.empty())
+        return SV_OK;
+    const size_t bytes = src.size() * sizeof(T);
+    hipError_t e = async ? hipMallocAsync((void **)dst, bytes, st) : hipMalloc((void **)dst, bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        *dst = nullptr;
+        return fail(SV_ENOMEM, "device allocation of %zu bytes failed: %s", bytes, hipGetErrorString(e));
+    }
+    if (async)
+        SV_HIP_TRY(hipMemcpyAsync(*dst, src.data(), bytes, hipMemcpyHostToDevice, st));
+    else
+        SV_HIP_TRY(hipMemcpy(*dst, src.data(), bytes, hipMemcpyHostToDevice));
+    return SV_OK;
+}
+
+static int create_impl(int n, int dtype, const sv_gate_t *gates, int ngates, int nparams, int flags, bool async,
+                       hipStream_t st, sv_circuit **out) {
+    *out = nullptr;
+    if (dtype != SV_C128 && dtype != SV_C64)
+        return fail(SV_EINVAL, "unknown dtype %d", dtype);
+    if (n < 1 || n > max_qubits(dtype))
+        return fail(SV_EINVAL, "n=%d outside [1, %d]", n, max_qubits(dtype));
+    if (ngates < 0 || (ngates > 0 && !gates))
+        return fail(SV_EINVAL, "bad gate list (ngates %d, gates %p)", ngates, (const void *)gates);
+    if (nparams < 0)
+        return fail(SV_EINVAL, "nparams %d < 0", nparams);
+    if (flags & ~(SV_FUSE | SV_GRAPH | SV_MASKED))
+        return fail(SV_EINVAL, "unknown flags 0x%x", flags);
+    for (int i = 0; i < ngates; ++i)
+        SV_TRY(validate_circuit_gate(n, nparams, gates[i], i));
+    std::unique_ptr<sv_circuit> c(new sv_circuit());
+    c->n = n;
+    c->dtype = dtype;
+    c->flags = flags;
+    c->nparams = nparams;
+    c->async_buffers = async;
+    SV_HIP_TRY(hipGetDevice(&c->device));
+    c->gates.assign(gates, gates + ngates);
+    std::vector<TileGate> tiles;
+    std::vector<ParamJob> jobs;
+    std::vector<double> mats;
+    SV_TRY(plan_circuit(c.get(), tiles, jobs, mats));
+    int r = upload(&c->d_mats, mats, async, st);
+    if (r == SV_OK)
+        r = upload(&c->d_tiles, tiles, async, st);
+    if (r == SV_OK)
+        r = upload(&c->d_jobs, jobs, async, st);
+    if (r != SV_OK) {
+        free_buffers(c.get(), st);
+        return r;
+    }
+    // large LDS tiles need the per-kernel limit raised before any launch
+    const size_t lds = ((size_t)1 << c->m) * amp_bytes(dtype);
+    if (lds > 65536) {
+        if (dtype == SV_C128)
+            SV_HIP_TRY(hipFuncSetAttribute((const void *)k_tile<double, 512, DeviceGates>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        else
+            SV_HIP_TRY(hipFuncSetAttribute((const void *)k_tile<float, 512, DeviceGates>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    }
+    *out = c.release();
+    return SV_OK;
+}
+
+template <typename R> static int enqueue(sv_circuit *c, cplx_t<R> *psi, const double *params, hipStream_t st) {
+    if (c->njobs > 0) {
+        hipLaunchKernelGGL(k_param_mats, dim3((c->njobs + 127) / 128), dim3(128), 0, st, c->d_jobs, c->njobs,
+                           params, c->d_mats, c->d_tiles);
+        SV_LAUNCH_CHECK();
+    }
+    const size_t lds = ((size_t)1 << c->m) * sizeof(cplx_t<R>);
+    const uint64_t ntiles = 1ull << (c->n - c->m);
+    for (const Pass &p : c->passes) {
+        if (p.fused) {
+            DeviceGates dg{c->d_tiles + p.first, p.count};
+            hipLaunchKernelGGL((k_tile<R, 512, DeviceGates>), dim3((unsigned)ntiles), dim3(512), lds, st, psi, c->m,
+                               dg);
+            SV_LAUNCH_CHECK();
+        } else {
+            SV_TRY(launch_plan<R>(psi, p.plan, MatPtr<R>{c->d_mats + (size_t)8 * p.gate}, st));
+        }
+    }
+    return SV_OK;
+}
+
+static int enqueue_any(sv_circuit *c, const sv_state_t *s, const double *params, hipStream_t st) {
+    if (c->dtype == SV_C128)
+        return enqueue<double>(c, reinterpret_cast<double2 *>(s->data), params, st);
+    return enqueue<float>(c, reinterpret_cast<float2 *>(s->data), params, st);
+}
+
+static int check_run_args(sv_circuit *c, const sv_state_t *s, const double *params) {
+    if (!c)
+        return fail(SV_EINVAL, "circuit is NULL");
+    SV_TRY(validate_state(s));
+    if (s->n != c->n || s->dtype != c->dtype)
+        return fail(SV_EINVAL, "state (n=%d, dtype=%d) does not match the circuit (n=%d, dtype=%d)", s->n, s->dtype,
+                    c->n, c->dtype);
+    if (c->njobs > 0 && !params)
+        return fail(SV_EINVAL, "circuit has parameterised gates but params_dev is NULL");
+    return SV_OK;
+}
+
+static void drop_graph(sv_circuit *c) {
+    if (c->exec)
+        (void)hipGraphExecDestroy(c->exec);
+    if (c->graph)
+        (void)hipGraphDestroy(c->graph);
+    c->exec = nullptr;
+    c->graph = nullptr;
+}
+
+static int run_graph(sv_circuit *c, const sv_state_t *s, const double *params, hipStream_t st) {
+    if (!c->exec || c->g_data != s->data || c->g_params != params) {
+        drop_graph(c);
+        if (!c->cap)
+            SV_HIP_TRY(hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking));
+        SV_HIP_TRY(hipStreamBeginCapture(c->cap, hipStreamCaptureModeRelaxed));
+        const int r = enqueue_any(c, s, params, c->cap);
+        hipGraph_t g = nullptr;
+        const hipError_t e = hipStreamEndCapture(c->cap, &g);
+        if (r != SV_OK) {
+            if (g)
+                (void)hipGraphDestroy(g);
+            return r;
+        }
+        if (e != hipSuccess)
+            return fail(SV_EHIP, "graph capture failed: %s", hipGetErrorString(e));
+        c->graph = g;
+        SV_HIP_TRY(hipGraphInstantiate(&c->exec, c->graph, nullptr, nullptr, 0));
+        c->g_data = s->data;
+        c->g_params = params;
+    }
+    SV_HIP_TRY(hipGraphLaunch(c->exec, st));
+    return SV_OK;
+}
+
+} // namespace sv
+
+extern "C" {
+
+int sv_gate_matrix(int kind, double theta, const double *U, double *out) {
+    clear_error();
+    if (!gate_kind_valid(kind))
+        return fail(SV_EINVAL, "unknown kind %d", kind);
+    if (!out)
+        return fail(SV_EINVAL, "out is NULL");
+    if ((kind & ~SV_G_ADJOINT) == SV_G_MATRIX && !U)
+        return fail(SV_EINVAL, "SV_G_MATRIX needs U");
+    gate_matrix(kind, theta, U, out);
+    return SV_OK;
+}
+
+int sv_circuit_plan(int n, int dtype, const sv_gate_t *gates, int ngates, int nparams, int flags, int32_t *order,
+                    int32_t *pass_of, int64_t *npasses) {
+    clear_error();
+    if (dtype != SV_C128 && dtype != SV_C64)
+        return fail(SV_EINVAL, "unknown dtype %d", dtype);
+    if (n < 1 || n > max_qubits(dtype))
+        return fail(SV_EINVAL, "n=%d outside [1, %d]", n, max_qubits(dtype));
+    if (ngates < 0 || (ngates > 0 && !gates))
+        return fail(SV_EINVAL, "bad gate list (ngates %d, gates %p)", ngates, (const void *)gates);
+    if (flags & ~(SV_FUSE | SV_GRAPH | SV_MASKED))
+        return fail(SV_EINVAL, "unknown flags 0x%x", flags);
+    for (int i = 0; i < ngates; ++i)
+        SV_TRY(validate_circuit_gate(n, nparams, gates[i], i));
+    sv_circuit c;
+    c.n = n;
+    c.dtype = dtype;
+    c.flags = flags;
+    c.nparams = nparams;
+    c.gates.assign(gates, gates + ngates);
+    std::vector<TileGate> tiles;
+    std::vector<ParamJob> jobs;
+    std::vector<double> mats;
+    SV_TRY(plan_circuit(&c, tiles, jobs, mats));
+    int k = 0;
+    for (size_t pi = 0; pi < c.passes.size(); ++pi) {
+        const Pass &p = c.passes[pi];
+        if (!p.fused) {
+            if (order)
+                order[k] = p.gate;
+            if (pass_of)
+                pass_of[k] = (int32_t)pi;
+            ++k;
+        } else {
+            for (int j = 0; j < p.count; ++j) {
+                if (order)
+                    order[k] = tiles[p.first + j].src_gate;
+                if (pass_of)
+                    pass_of[k] = (int32_t)pi;
+                ++k;
+            }
+        }
+    }
+    if (npasses)
+        *npasses = (int64_t)c.passes.size();
+    return SV_OK;
+}
+
+int sv_circuit_create(int n, int dtype, const sv_gate_t *gates, int ngates, int nparams, int flags,
+                      sv_circuit_t **out) {
+    clear_error();
+    if (!out)
+        return fail(SV_EINVAL, "out is NULL");
+    return create_impl(n, dtype, gates, ngates, nparams, flags, false, nullptr, out);
+}
+
+int sv_circuit_run(sv_circuit_t *c, const sv_state_t *s, const double *params_dev, sv_stream_t st) {
+    clear_error();
+    SV_TRY(check_run_args(c, s, params_dev));
+    int dev = 0;
+    SV_HIP_TRY(hipGetDevice(&dev));
+    if (dev != c->device)
+        return fail(SV_EINVAL, "circuit was created on device %d, current device is %d", c->device, dev);
+    int r;
+    if (c->flags & SV_GRAPH)
+        r = run_graph(c, s, params_dev, (hipStream_t)st);
+    else
+        r = enqueue_any(c, s, params_dev, (hipStream_t)st);
+    if (r != SV_OK)
+        return r;
+    if (!c->done)
+        SV_HIP_TRY(hipEventCreateWithFlags(&c->done, hipEventDisableTiming));
+    SV_HIP_TRY(hipEventRecord(c->done, (hipStream_t)st));
+    return SV_OK;
+}
+
+int sv_circuit_info(const sv_circuit_t *c, int64_t *passes, int64_t *fused_gates, int64_t *fused_runs) {
+    clear_error();
+    if (!c)
+        return fail(SV_EINVAL, "circuit is NULL");
+    if (passes)
+        *passes = (int64_t)c->passes.size();
+    if (fused_gates)
+        *fused_gates = c->fused_gates;
+    if (fused_runs)
+        *fused_runs = c->fused_runs;
+    return SV_OK;
+}
+
+int sv_circuit_destroy(sv_circuit_t *c) {
+    clear_error();
+    if (!c)
+        return SV_OK;
+    if (c->done)
+        (void)hipEventSynchronize(c->done);
+    drop_graph(c);
+    free_buffers(c, nullptr);
+    if (c->cap)
+        (void)hipStreamDestroy(c->cap);
+    if (c->done)
+        (void)hipEventDestroy(c->done);
+    delete c;
+    return SV_OK;
+}
+
+int sv_apply_circuit(const sv_state_t *s, const sv_gate_t *gates, int ngates, const double *params_dev, int nparams,
+                     int flags, sv_stream_t st) {
+    clear_error();
+    SV_TRY(validate_state(s));
+    sv_circuit *c = nullptr;
+    SV_TRY(create_impl(s->n, s->dtype, gates, ngates, nparams, flags & ~SV_GRAPH, true, (hipStream_t)st, &c));
+    int r = check_run_args(c, s, params_dev);
+    if (r == SV_OK)
+        r = enqueue_any(c, s, params_dev, (hipStream_t)st);
+    free_buffers(c, (hipStream_t)st);  // stream-ordered: after the kernels above
+    delete c;
+    return r;
+}
+
+} // extern "C"

@@ -27,6 +27,8 @@ struct TileGate {
     uint32_t npairs;      // 2^(m - 1 - low controls)
     uint64_t hi_mask;     // controls >= m, as amplitude-index bits
     uint64_t hi_vals;
+    int32_t src_gate;     // index of the gate in its circuit (host bookkeeping)
+    int32_t pad2;
 };
 
 // Build the tile descriptor of one gate for tile width m (host).

@@ -1,0 +1,129 @@
+"""Host-only checks of the circuit planner: the gate order it executes is
+equivalent to the circuit's own order (checked with the oracle), runs are
+made only of gates whose target lies below the tile width, and validation
+names the offending gate."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+
+@pytest.fixture(scope="module")
+def sv():
+    import paper_2411_18354_amd as sv
+    return sv
+
+
+def _rand_circuit(n, ngates, seed, kinds=("X", "Y", "Z", "H", "RX", "RY", "RZ", "P")):
+    rng = np.random.default_rng(seed)
+    gates = []
+    for _ in range(ngates):
+        k = kinds[int(rng.integers(0, len(kinds)))]
+        t = int(rng.integers(0, n))
+        others = [q for q in range(n) if q != t]
+        c = int(rng.integers(0, 4))
+        ctrls = tuple(int(q) for q in rng.choice(others, size=c, replace=False)) if c else ()
+        vals = tuple(int(v) for v in rng.integers(0, 2, size=c))
+        gates.append(W.Gate(k, t, ctrls, vals, float(rng.uniform(0, 2 * np.pi))))
+    return W.Circuit(n, gates)
+
+
+def _apply_in_order(c, order, psi0):
+    psi = psi0.copy()
+    for i in order:
+        g = c.gates[i]
+        oracle.apply_gate(psi, c.n, g.target, g.controls, g.values, oracle.gate_matrix(g.kind, g.theta, g.matrix))
+    return psi
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_planned_order_equivalent(sv, seed):
+    n = 10
+    sv.sv_tune_set("tile_log2_c128", 6)
+    try:
+        c = _rand_circuit(n, 300, seed)
+        order, pass_of, npasses = sv.sv_circuit_plan(n, c, flags=sv.SV_FUSE)
+        assert sorted(order) == list(range(len(c.gates)))
+        rng = np.random.default_rng(100 + seed)
+        psi0 = rng.standard_normal(1 << n) + 1j * rng.standard_normal(1 << n)
+        psi0 /= np.linalg.norm(psi0)
+        ref = _apply_in_order(c, range(len(c.gates)), psi0)
+        got = _apply_in_order(c, order, psi0)
+        assert np.max(np.abs(got - ref)) < 1e-12
+        # fused passes hold only gates with target < m and keep their relative order
+        passes = {}
+        for k, (g, p) in enumerate(zip(order, pass_of)):
+            passes.setdefault(p, []).append(g)
+        fused = [v for v in passes.values() if len(v) > 1]
+        assert fused, "expected some fused runs"
+        for v in fused:
+            assert all(c.gates[g].target < 6 for g in v)
+            assert v == sorted(v)
+        assert npasses == len(passes) < len(c.gates)
+    finally:
+        sv.sv_tune_set("tile_log2_c128", 12)
+
+
+def test_reordering_happens_and_respects_dependencies(sv):
+    """A high-target gate between two low runs is moved after the second run
+    only when it commutes with it."""
+    sv.sv_tune_set("tile_log2_c128", 6)
+    try:
+        n = 8
+        g = [W.Gate("H", 0), W.Gate("X", 7, (1,)), W.Gate("H", 2), W.Gate("H", 1)]
+        order, pass_of, _ = sv.sv_circuit_plan(n, g, flags=sv.SV_FUSE)
+        # H(2) commutes with CX(1->7) and joins the first run; H(1) does not
+        assert order[:2] == [0, 2] and pass_of[0] == pass_of[1]
+        assert order.index(1) < order.index(3)
+        # diagonal gates commute with controls on their target
+        g = [W.Gate("H", 0), W.Gate("X", 7, (1,)), W.Gate("RZ", 1, theta=0.3), W.Gate("Z", 0)]
+        order, pass_of, _ = sv.sv_circuit_plan(n, g, flags=sv.SV_FUSE)
+        assert pass_of[0] == pass_of[1] == pass_of[2]
+    finally:
+        sv.sv_tune_set("tile_log2_c128", 12)
+
+
+def test_unfused_and_masked_keep_order(sv):
+    c = _rand_circuit(9, 50, 3)
+    for flags in (0, sv.SV_MASKED, sv.SV_MASKED | sv.SV_FUSE):
+        order, pass_of, npasses = sv.sv_circuit_plan(9, c, flags=flags)
+        assert order == list(range(50)) and npasses == 50
+
+
+def test_workload_plan_stats(sv):
+    for c, npar, max_passes in ((W.config0(), 0, 1), (W.config2(), 0, 1000), (W.config3()[0], 768, 650)):
+        _, _, npasses = sv.sv_circuit_plan(c.n, c, nparams=npar, flags=sv.SV_FUSE)
+        assert npasses <= max_passes, (c.meta, npasses)
+
+
+def test_circuit_validation_names_gate(sv):
+    bad = [W.Gate("H", 0), W.Gate("X", 3, (3,))]
+    with pytest.raises(sv.SvError) as e:
+        sv.sv_circuit_plan(4, bad)
+    assert "gate 1" in str(e.value)
+    with pytest.raises(sv.SvError) as e:
+        sv.sv_circuit_plan(4, [W.Gate("H", 0, param=0)], nparams=1)
+    assert "takes no parameter" in str(e.value)
+    with pytest.raises(sv.SvError) as e:
+        sv.sv_circuit_plan(4, [W.Gate("RY", 0, param=3)], nparams=2)
+    assert "nparams" in str(e.value)
+    with pytest.raises(sv.SvError):
+        sv.sv_circuit_plan(4, [W.Gate("RY", 4)])
+    # the C entry point rejects an unknown kind and unknown flags
+    arr = sv.circuit_gates([W.Gate("H", 0)])
+    arr[0].kind = 99
+    with pytest.raises(sv.SvError):
+        sv.sv_circuit_plan(4, arr)
+    with pytest.raises(sv.SvError):
+        sv.sv_circuit_plan(4, [W.Gate("H", 0)], flags=64)
+
+
+def test_library_gate_matrices_match_definitions(sv):
+    for k in ("X", "Y", "Z", "H", "RX", "RY", "RZ", "P", "~RX", "~RY", "~RZ", "~P", "~H"):
+        for th in (0.0, 0.7, 2.5):
+            a = np.array(sv.sv_gate_matrix(k, th))
+            m = oracle.gate_matrix(k, th)
+            assert np.max(np.abs(a - np.stack([m.real, m.imag], -1).reshape(8))) < 1e-15, (k, th)
+    U = W.haar_unitary_2x2(5)
+    assert np.allclose(sv.sv_gate_matrix("U", 0.0, U), U)

@@ -1,0 +1,161 @@
+"""GPU parity of the circuit path (sv_apply_circuit / sv_circuit_*) against
+the oracle: fused, unfused, masked and graph-replayed runs, device-resident
+angles, the paper's QFT and streaming circuits, and config2's layers."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"c128": 1e-12, "c64": 1e-5}
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+def _err(got, ref):
+    return float(np.max(np.abs(got.astype(np.complex128) - ref)) / np.max(np.abs(ref)))
+
+
+def _dev_state(n, dtype, psi=None):
+    import torch
+    td = torch.complex128 if dtype == "c128" else torch.complex64
+    if psi is None:
+        return torch.empty(1 << n, dtype=td, device="cuda")
+    return torch.from_numpy(psi).to(td).cuda()
+
+
+def _rand_circuit(n, ngates, seed, nparams=0):
+    rng = np.random.default_rng(seed)
+    kinds = ("X", "Y", "Z", "H", "RX", "RY", "RZ", "P", "U", "~RY", "~U")
+    gates = []
+    for i in range(ngates):
+        k = kinds[int(rng.integers(0, len(kinds)))]
+        t = int(rng.integers(0, n))
+        others = [q for q in range(n) if q != t]
+        c = int(rng.integers(0, 4))
+        ctrls = tuple(int(q) for q in rng.choice(others, size=c, replace=False)) if c else ()
+        vals = tuple(int(v) for v in rng.integers(0, 2, size=c))
+        th = float(rng.uniform(0, 2 * np.pi))
+        mat = W.haar_unitary_2x2(seed * 1000 + i) if k.endswith("U") else None
+        p = int(rng.integers(0, nparams)) if (nparams and k in ("RX", "RY", "RZ", "P") and rng.random() < 0.7) else -1
+        gates.append(W.Gate(k, t, ctrls, vals, th, p, mat))
+    params = rng.uniform(0, 2 * np.pi, size=nparams) if nparams else None
+    return W.Circuit(n, gates, params)
+
+
+FLAGS = {"fuse": 1, "plain": 0, "masked": 4, "fuse+graph": 3}
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("flags", list(FLAGS))
+def test_config0(gpu, dtype, flags):
+    c = W.config0()
+    ref = oracle.run_circuit(c)
+    d = _dev_state(c.n, dtype)
+    gpu.sv_init(d, 0)
+    if "graph" in flags:
+        circ = gpu.Circuit(c.n, c, dtype=0 if dtype == "c128" else 1, flags=FLAGS[flags])
+        for _ in range(3):
+            gpu.sv_init(d, 0)
+            circ.run(d)
+        circ.close()
+    else:
+        gpu.sv_apply_circuit(d, c, flags=FLAGS[flags])
+    e = _err(d.cpu().numpy(), ref)
+    _say("config0", dtype, flags, e)
+    assert e <= TOL[dtype]
+
+
+@pytest.mark.parametrize("tile", [6, 9, 12])
+@pytest.mark.parametrize("seed", [1, 2])
+def test_random_circuits_device_params(gpu, tile, seed):
+    import torch
+    gpu.sv_tune_set("tile_log2_c128", tile)
+    try:
+        for n in (7, 11, 14):
+            c = _rand_circuit(n, 250, seed * 10 + n, nparams=12)
+            psi0 = W.random_state(n, seed)
+            ref = oracle.run_circuit(c, c.params, psi0)
+            params = torch.from_numpy(c.params).cuda()
+            outs = {}
+            for name, fl in FLAGS.items():
+                d = _dev_state(n, "c128", psi0)
+                gpu.sv_apply_circuit(d, c, params=params, flags=fl)
+                outs[name] = d.cpu().numpy()
+                assert _err(outs[name], ref) <= 1e-12, (n, name, tile)
+            # unfused and masked apply identical arithmetic in the same order
+            assert np.array_equal(outs["plain"].view(np.uint8), outs["masked"].view(np.uint8))
+    finally:
+        gpu.sv_tune_set("tile_log2_c128", 12)
+
+
+def test_graph_replay_new_params(gpu):
+    """One captured graph replayed with new angle values written into the same
+    device array; eager work and synchronisation between replays; every
+    replay checked against the oracle and against an eager run."""
+    import torch
+    n = 13
+    c = _rand_circuit(n, 200, 77, nparams=8)
+    params = torch.zeros(8, dtype=torch.float64, device="cuda")
+    circ = gpu.Circuit(n, c, nparams=8, flags=gpu.SV_FUSE | gpu.SV_GRAPH)
+    eager = gpu.Circuit(n, c, nparams=8, flags=gpu.SV_FUSE)
+    d = _dev_state(n, "c128")
+    e = _dev_state(n, "c128")
+    rng = np.random.default_rng(5)
+    for rep in range(4):
+        p = rng.uniform(0, 2 * np.pi, size=8)
+        params.copy_(torch.from_numpy(p))
+        gpu.sv_init(d, rep)
+        gpu.sv_init(e, rep)
+        circ.run(d, params)
+        torch.cuda.synchronize()
+        eager.run(e, params)
+        psi0 = np.zeros(1 << n, dtype=np.complex128); psi0[rep] = 1
+        ref = oracle.run_circuit(c, p, psi0)
+        assert _err(d.cpu().numpy(), ref) <= 1e-12, rep
+        assert torch.equal(d.view(torch.float64), e.view(torch.float64)), rep
+    circ.close(); eager.close()
+
+
+@pytest.mark.parametrize("n", [5, 12, 16])
+def test_qft_and_stream_closed_forms(gpu, n):
+    N = 1 << n
+    psi0 = W.random_state(n, 3)
+    for name, circ in (("qft", W.qft(n)), ("stream", W.stream(n))):
+        for fl in (1, 4):
+            d = _dev_state(n, "c128", psi0)
+            gpu.sv_apply_circuit(d, circ, flags=fl)
+            got = d.cpu().numpy()
+            if name == "qft":
+                rev = np.array([int(format(x, "0%db" % n)[::-1], 2) for x in range(N)])
+                ref = np.fft.ifft(psi0[rev]) * np.sqrt(N)
+            else:
+                ref = np.roll(psi0, -1)
+            assert _err(got, ref) <= 1e-12, (name, n, fl)
+
+
+def test_config2_layers_small(gpu):
+    """config2's construction at n=20 (all 20 layers) against the oracle."""
+    c = W.config2(n=20)
+    ref = oracle.run_circuit(c)
+    for fl in (1, 0):
+        d = _dev_state(c.n, "c128")
+        gpu.sv_init(d, 0)
+        gpu.sv_apply_circuit(d, c, flags=fl)
+        assert _err(d.cpu().numpy(), ref) <= 1e-12, fl
+
+
+def test_invalid_circuit_leaves_state(gpu):
+    import torch
+    n = 8
+    d = _dev_state(n, "c128", W.random_state(n, 1))
+    before = d.clone()
+    bad = [W.Gate("H", 0), W.Gate("X", 2), W.Gate("X", 3, (3,))]
+    with pytest.raises(gpu.SvError):
+        gpu.sv_apply_circuit(d, bad)
+    torch.cuda.synchronize()
+    assert torch.equal(d, before)
