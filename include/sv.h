@@ -228,6 +228,48 @@ int sv_circuit_destroy(sv_circuit_t *c);
 int sv_apply_circuit(const sv_state_t *s, const sv_gate_t *gates, int ngates, const double *params_dev,
                      int nparams, int flags, sv_stream_t st);
 
+/* ------------------------------------------------------------ observables
+ *
+ * A Hamiltonian is a list of Pauli strings with real coefficients,
+ * H = sum_j coef_j P_j, P_j = i^{|x&z|} X^x Z^z: bit q of x_mask (z_mask)
+ * puts an X (Z) on qubit q, both bits a Y = iXZ.  Reductions are
+ * deterministic (fixed grid, fixed summation order, no atomics). */
+typedef struct sv_pauli {
+    double coef;
+    uint64_t x_mask;
+    uint64_t z_mask;
+} sv_pauli_t;
+
+/* out_dev[0] = <psi|H|psi> (real), written when the stream reaches it.
+ * nterms >= 1; masks must lie within the n qubits. */
+int sv_expect(const sv_state_t *s, const sv_pauli_t *terms, int nterms, double *out_dev, sv_stream_t st);
+
+/* out_dev[j] = <psi|P_j|psi> for every term j (coefficients not applied). */
+int sv_expect_terms(const sv_state_t *s, const sv_pauli_t *terms, int nterms, double *out_dev, sv_stream_t st);
+
+/* out = H in (out and in distinct, same n and dtype). */
+int sv_apply_pauli_sum(const sv_state_t *in, const sv_state_t *out, const sv_pauli_t *terms, int nterms,
+                       sv_stream_t st);
+
+/* Adjoint gradient of L(theta) = <psi(theta)|H|psi(theta)> for the circuit
+ * psi(theta) = U_G ... U_1 psi_0 (Jones & Gacon, arXiv:2009.02823, extended to
+ * controlled gates: a controlled gate's derivative is summed over exactly the
+ * control-satisfying amplitude pairs, the set scheduled in Sec. III-B).
+ *   psi       in: the final forward state psi(theta); out: psi_0 recovered by
+ *             un-applying every gate (the forward state is consumed)
+ *   lam       workspace state of the same n and dtype (overwritten)
+ *   gates     the circuit as given to sv_circuit_create; only RX/RY/RZ/P
+ *             gates with param >= 0 are differentiated
+ *   params_dev device array of nparams angles
+ *   grad_dev  device array of nparams doubles, overwritten with dL/dtheta_j
+ *             (summed over every gate using parameter j; 0 for unused ones),
+ *             times scale_dev[0] when scale_dev is not NULL
+ *   loss_dev  device double receiving L (may be NULL)
+ * Uses two state vectors; stream-ordered, no host synchronisation. */
+int sv_adjoint_grad(const sv_state_t *psi, const sv_state_t *lam, const sv_gate_t *gates, int ngates,
+                    const double *params_dev, int nparams, const sv_pauli_t *terms, int nterms, double *grad_dev,
+                    double *loss_dev, const double *scale_dev, sv_stream_t st);
+
 /* Write, for each reduced iteration index i_r in [0, 2^(n-1-ncontrols)), the
  * index of the first pair element (bit target clear) that the scheduled
  * kernels update for it, computed with the same device function they use

@@ -359,3 +359,7 @@ def sv_circuit_plan(n: int, gates, dtype: int = SV_C128, nparams: int = 0, flags
     _check(_L.sv_circuit_plan(int(n), int(dtype), arr, count, int(nparams), int(flags), order, pas,
                               ctypes.byref(npas)))
     return list(order)[:count], list(pas)[:count], int(npas.value)
+
+
+from .observables import (sv_pauli_t, pauli_terms, sv_expect, sv_expect_terms, sv_apply_pauli_sum,  # noqa: E402
+                          sv_adjoint_grad, SvExpectation, ExpectationModel)

@@ -1,0 +1,308 @@
+// Pauli-sum expectation values <psi|H|psi> and the product H psi.
+//
+// For one x mask X != 0 the amplitudes pair up as (k, k ^ X); with b the
+// lowest set bit of X and k running over indices with bit b clear, the two
+// contributions of a pair to <psi|P|psi> are complex conjugates (P is
+// Hermitian), so the term is 2 Re( conj(psi_k) i^{ny} (-1)^{z.(k^X)}
+// psi_{k^X} ) summed over half the indices: one read of every amplitude per
+// x-mask group, enumerated with the same index expansion as the gate
+// kernels.  Diagonal terms (X = 0) sum |psi_k|^2 (-1)^{z.k}.  Terms of a
+// group are evaluated together in one pass.  Reductions are deterministic
+// (reduce.hpp).
+#include <algorithm>
+#include <cstring>
+#include <numeric>
+
+#include "pauli.hpp"
+
+namespace sv {
+
+constexpr int kMaxT = 16;  // terms evaluated per pass
+
+int make_pauli_plan(int n, const sv_pauli_t *terms, int nterms, PauliPlan *p) {
+    if (nterms < 1 || !terms)
+        return fail(SV_EINVAL, "need at least one term (nterms %d, terms %p)", nterms, (const void *)terms);
+    const uint64_t full = (n >= 64) ? ~0ull : ((1ull << n) - 1);
+    std::vector<int> idx(nterms);
+    std::iota(idx.begin(), idx.end(), 0);
+    for (int j = 0; j < nterms; ++j)
+        if ((terms[j].x_mask | terms[j].z_mask) & ~full)
+            return fail(SV_EINVAL, "term %d acts on qubits >= n=%d", j, n);
+    std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return terms[a].x_mask < terms[b].x_mask; });
+    p->groups.clear();
+    p->terms.clear();
+    for (int k = 0; k < nterms; ++k) {
+        const sv_pauli_t &t = terms[idx[k]];
+        const bool start = p->groups.empty() || p->groups.back().x != t.x_mask || p->groups.back().count == kMaxT;
+        if (start)
+            p->groups.push_back(DGroup{t.x_mask, (int32_t)p->terms.size(), 0});
+        DTerm d;
+        d.coef = t.coef;
+        d.z = t.z_mask;
+        d.ny = popcount64(t.x_mask & t.z_mask) & 3;
+        d.idx = idx[k];
+        p->terms.push_back(d);
+        p->groups.back().count++;
+    }
+    return SV_OK;
+}
+
+int pauli_upload(const PauliPlan &p, size_t partial_doubles, hipStream_t st, PauliDevice *d) {
+    *d = PauliDevice();
+    d->nterms = (int)p.terms.size();
+    d->ngroups = (int)p.groups.size();
+    auto alloc = [&](void **ptr, size_t bytes) -> int {
+        hipError_t e = hipMallocAsync(ptr, bytes, st);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            *ptr = nullptr;
+            return fail(SV_ENOMEM, "device allocation of %zu bytes failed: %s", bytes, hipGetErrorString(e));
+        }
+        return SV_OK;
+    };
+    int r = alloc((void **)&d->terms, p.terms.size() * sizeof(DTerm));
+    if (r == SV_OK)
+        r = alloc((void **)&d->groups, p.groups.size() * sizeof(DGroup));
+    if (r == SV_OK && partial_doubles)
+        r = alloc((void **)&d->partials, partial_doubles * sizeof(double));
+    if (r != SV_OK) {
+        pauli_release(d, st);
+        return r;
+    }
+    SV_HIP_TRY(hipMemcpyAsync(d->terms, p.terms.data(), p.terms.size() * sizeof(DTerm), hipMemcpyHostToDevice, st));
+    SV_HIP_TRY(
+        hipMemcpyAsync(d->groups, p.groups.data(), p.groups.size() * sizeof(DGroup), hipMemcpyHostToDevice, st));
+    return SV_OK;
+}
+
+void pauli_release(PauliDevice *d, hipStream_t st) {
+    if (d->terms)
+        (void)hipFreeAsync(d->terms, st);
+    if (d->groups)
+        (void)hipFreeAsync(d->groups, st);
+    if (d->partials)
+        (void)hipFreeAsync(d->partials, st);
+    *d = PauliDevice();
+}
+
+// One pass for one group (<= kMaxT terms sharing the x mask X).
+// partials[(first + j) * kMaxPartials + block] receives the workgroup's sum
+// of <P_j> contributions.
+template <typename R>
+__global__ __launch_bounds__(kRedThreads) void k_expect_group(const cplx_t<R> *__restrict__ psi, uint64_t count,
+                                                              uint64_t X, uint32_t b, const DTerm *__restrict__ terms,
+                                                              int first, int nt, double *__restrict__ partials) {
+    __shared__ double scratch[kRedThreads / 64];
+    uint64_t z[kMaxT];
+    int ny[kMaxT];
+    double acc[kMaxT];
+#pragma unroll
+    for (int j = 0; j < kMaxT; ++j) {
+        acc[j] = 0.0;
+        z[j] = j < nt ? terms[first + j].z : 0;
+        ny[j] = j < nt ? terms[first + j].ny : 0;
+    }
+    const uint64_t stride = (uint64_t)gridDim.x * kRedThreads;
+    const uint64_t lowb = (1ull << b) - 1;
+    for (uint64_t i = (uint64_t)blockIdx.x * kRedThreads + threadIdx.x; i < count; i += stride) {
+        if (X == 0) {
+            const cplx_t<R> v = psi[i];
+            const double pr = (double)v.x * (double)v.x + (double)v.y * (double)v.y;
+#pragma unroll
+            for (int j = 0; j < kMaxT; ++j)
+                if (j < nt)
+                    acc[j] += odd_parity(z[j] & i) ? -pr : pr;
+        } else {
+            const uint64_t k = ((i >> b) << (b + 1)) | (i & lowb);  // bit b cleared
+            const uint64_t k2 = k ^ X;
+            const cplx_t<R> u = psi[k], v = psi[k2];
+            // w = conj(u) * v
+            const double wr = (double)u.x * (double)v.x + (double)u.y * (double)v.y;
+            const double wi = (double)u.x * (double)v.y - (double)u.y * (double)v.x;
+#pragma unroll
+            for (int j = 0; j < kMaxT; ++j)
+                if (j < nt) {
+                    const double r = re_ipow(ny[j], wr, wi);
+                    acc[j] += odd_parity(z[j] & k2) ? -r : r;
+                }
+        }
+    }
+    const double scale = X == 0 ? 1.0 : 2.0;
+#pragma unroll
+    for (int j = 0; j < kMaxT; ++j) {
+        if (j < nt) {  // uniform
+            const double s = block_sum(acc[j], scratch);
+            if (threadIdx.x == 0)
+                partials[(size_t)(first + j) * kMaxPartials + blockIdx.x] = scale * s;
+        }
+    }
+}
+
+// Sum every term's partials in a fixed order; write per-term values (in the
+// caller's order) and the coefficient-weighted total.
+__global__ __launch_bounds__(kRedThreads) void k_expect_final(const DTerm *__restrict__ terms, int nterms,
+                                                              const int32_t *__restrict__ nblk,
+                                                              const double *__restrict__ partials,
+                                                              double *__restrict__ out_total,
+                                                              double *__restrict__ out_terms) {
+    __shared__ double scratch[kRedThreads / 64];
+    double total = 0.0;
+    for (int j = 0; j < nterms; ++j) {
+        const double s = block_sum_array(partials + (size_t)j * kMaxPartials, nblk[j], scratch);
+        total += terms[j].coef * s;
+        if (threadIdx.x == 0 && out_terms)
+            out_terms[terms[j].idx] = s;
+    }
+    if (threadIdx.x == 0 && out_total)
+        out_total[0] = total;
+}
+
+// out_k = sum_groups sum_terms coef i^ny (-1)^{z.(k^X)} psi_{k^X}; partials
+// of Re conj(psi_k) out_k per workgroup.
+template <typename R>
+__global__ __launch_bounds__(kRedThreads) void k_apply_paulis(const cplx_t<R> *__restrict__ psi,
+                                                              cplx_t<R> *__restrict__ out, uint64_t N,
+                                                              const DGroup *__restrict__ groups, int ngroups,
+                                                              const DTerm *__restrict__ terms,
+                                                              double *__restrict__ partials) {
+    __shared__ double scratch[kRedThreads / 64];
+    double lp = 0.0;
+    const uint64_t stride = (uint64_t)gridDim.x * kRedThreads;
+    for (uint64_t k = (uint64_t)blockIdx.x * kRedThreads + threadIdx.x; k < N; k += stride) {
+        double ar = 0.0, ai = 0.0;
+        for (int g = 0; g < ngroups; ++g) {
+            const DGroup G = groups[g];
+            const uint64_t kx = k ^ G.x;
+            const cplx_t<R> v = psi[kx];
+            double cr = 0.0, ci = 0.0;  // sum over the group's terms of coef i^ny (-1)^{z.kx}
+            for (int j = G.first; j < G.first + G.count; ++j) {
+                const DTerm T = terms[j];
+                const double s = odd_parity(T.z & kx) ? -T.coef : T.coef;
+                cr += re_ipow(T.ny, s, 0.0);
+                ci += im_ipow(T.ny, s, 0.0);
+            }
+            ar += cr * (double)v.x - ci * (double)v.y;
+            ai += cr * (double)v.y + ci * (double)v.x;
+        }
+        cplx_t<R> o;
+        o.x = (R)ar;
+        o.y = (R)ai;
+        out[k] = o;
+        const cplx_t<R> p = psi[k];
+        lp += (double)p.x * ar + (double)p.y * ai;
+    }
+    const double s = block_sum(lp, scratch);
+    if (threadIdx.x == 0 && partials)
+        partials[blockIdx.x] = s;
+}
+
+int launch_apply_paulis(int dtype, const void *psi, void *out, int n, const PauliDevice &d, hipStream_t st,
+                        unsigned *grid) {
+    const uint64_t N = 1ull << n;
+    const unsigned g = reduce_grid(N);
+    if (dtype == SV_C128)
+        hipLaunchKernelGGL(k_apply_paulis<double>, dim3(g), dim3(kRedThreads), 0, st, (const double2 *)psi,
+                           (double2 *)out, N, d.groups, d.ngroups, d.terms, d.partials);
+    else
+        hipLaunchKernelGGL(k_apply_paulis<float>, dim3(g), dim3(kRedThreads), 0, st, (const float2 *)psi,
+                           (float2 *)out, N, d.groups, d.ngroups, d.terms, d.partials);
+    SV_LAUNCH_CHECK();
+    if (grid)
+        *grid = g;
+    return SV_OK;
+}
+
+
+static int expect_impl(const sv_state_t *s, const sv_pauli_t *terms, int nterms, double *out_total,
+                       double *out_terms, hipStream_t st) {
+    SV_TRY(validate_state(s));
+    PauliPlan plan;
+    SV_TRY(make_pauli_plan(s->n, terms, nterms, &plan));
+    PauliDevice d;
+    SV_TRY(pauli_upload(plan, (size_t)plan.terms.size() * kMaxPartials, st, &d));
+    // per-term partial counts
+    std::vector<int32_t> nblk(plan.terms.size());
+    int32_t *d_nblk = nullptr;
+    int r = SV_OK;
+    const int n = s->n;
+    for (const DGroup &g : plan.groups) {
+        const uint64_t count = g.x == 0 ? (1ull << n) : (1ull << (n - 1));
+        const unsigned grid = reduce_grid(count);
+        for (int j = g.first; j < g.first + g.count; ++j)
+            nblk[j] = (int32_t)grid;
+        const uint32_t b = g.x ? (uint32_t)__builtin_ctzll(g.x) : 0;
+        if (s->dtype == SV_C128)
+            hipLaunchKernelGGL(k_expect_group<double>, dim3(grid), dim3(kRedThreads), 0, st,
+                               (const double2 *)s->data, count, g.x, b, d.terms, g.first, g.count, d.partials);
+        else
+            hipLaunchKernelGGL(k_expect_group<float>, dim3(grid), dim3(kRedThreads), 0, st, (const float2 *)s->data,
+                               count, g.x, b, d.terms, g.first, g.count, d.partials);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) {
+            r = fail(SV_EHIP, "expectation launch failed: %s", hipGetErrorString(e));
+            break;
+        }
+    }
+    if (r == SV_OK) {
+        hipError_t e = hipMallocAsync((void **)&d_nblk, nblk.size() * sizeof(int32_t), st);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            r = fail(SV_ENOMEM, "device allocation failed: %s", hipGetErrorString(e));
+        } else {
+            e = hipMemcpyAsync(d_nblk, nblk.data(), nblk.size() * sizeof(int32_t), hipMemcpyHostToDevice, st);
+            if (e != hipSuccess)
+                r = fail(SV_EHIP, "copy failed: %s", hipGetErrorString(e));
+        }
+    }
+    if (r == SV_OK) {
+        hipLaunchKernelGGL(k_expect_final, dim3(1), dim3(kRedThreads), 0, st, d.terms, d.nterms, d_nblk, d.partials,
+                           out_total, out_terms);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess)
+            r = fail(SV_EHIP, "expectation launch failed: %s", hipGetErrorString(e));
+    }
+    if (d_nblk)
+        (void)hipFreeAsync(d_nblk, st);
+    pauli_release(&d, st);
+    return r;
+}
+
+} // namespace sv
+
+using namespace sv;
+
+extern "C" {
+
+int sv_expect(const sv_state_t *s, const sv_pauli_t *terms, int nterms, double *out_dev, sv_stream_t st) {
+    clear_error();
+    if (!out_dev)
+        return fail(SV_EINVAL, "out_dev is NULL");
+    return expect_impl(s, terms, nterms, out_dev, nullptr, (hipStream_t)st);
+}
+
+int sv_expect_terms(const sv_state_t *s, const sv_pauli_t *terms, int nterms, double *out_dev, sv_stream_t st) {
+    clear_error();
+    if (!out_dev)
+        return fail(SV_EINVAL, "out_dev is NULL");
+    return expect_impl(s, terms, nterms, nullptr, out_dev, (hipStream_t)st);
+}
+
+int sv_apply_pauli_sum(const sv_state_t *in, const sv_state_t *out, const sv_pauli_t *terms, int nterms,
+                       sv_stream_t st) {
+    clear_error();
+    SV_TRY(validate_state(in));
+    SV_TRY(validate_state(out));
+    if (in->n != out->n || in->dtype != out->dtype)
+        return fail(SV_EINVAL, "states differ in size or dtype");
+    if (in->data == out->data)
+        return fail(SV_EINVAL, "in and out must not alias");
+    PauliPlan plan;
+    SV_TRY(make_pauli_plan(in->n, terms, nterms, &plan));
+    PauliDevice d;
+    SV_TRY(pauli_upload(plan, 0, (hipStream_t)st, &d));
+    const int r = launch_apply_paulis(in->dtype, in->data, out->data, in->n, d, (hipStream_t)st, nullptr);
+    pauli_release(&d, (hipStream_t)st);
+    return r;
+}
+
+} // extern "C"

@@ -1,0 +1,179 @@
+"""GPU parity of expectation values and adjoint gradients against the
+oracle: <psi|H|psi> and H psi to 1e-12, gradients to 1e-8 against the
+oracle's parameter-shift rule (and central finite differences where no shift
+rule applies), through the C ABI and through torch.autograd."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+def _rand_terms(n, nterms, seed):
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(nterms):
+        x = int(rng.integers(0, 1 << n))
+        z = int(rng.integers(0, 1 << n))
+        if rng.random() < 0.3:
+            x = 0
+        out.append(W.PauliTerm(float(rng.standard_normal()), x, z))
+    return out
+
+
+def _dev(psi, dtype="c128"):
+    import torch
+    t = torch.from_numpy(psi)
+    return (t if dtype == "c128" else t.to(torch.complex64)).cuda()
+
+
+@pytest.mark.parametrize("n", [1, 3, 8, 14])
+def test_expect_random_paulis(gpu, n):
+    psi = W.random_state(n, 40 + n)
+    terms = _rand_terms(n, 40, n)
+    d = _dev(psi)
+    tot = gpu.sv_expect(d, terms).item()
+    per = gpu.sv_expect_terms(d, terms).cpu().numpy()
+    ref_per = np.array([oracle.expect_pauli(psi, n, t.x_mask, t.z_mask).real for t in terms])
+    ref = oracle.expect(psi, n, terms)
+    assert np.max(np.abs(per - ref_per)) <= 1e-12
+    assert abs(tot - ref) <= 1e-12 * max(1.0, np.sum(np.abs([t.coef for t in terms])))
+    # deterministic: same bits on a second evaluation
+    assert gpu.sv_expect(d, terms).item() == tot
+    # complex64 against the fp64 oracle
+    tot64 = gpu.sv_expect(_dev(psi, "c64"), terms).item()
+    assert abs(tot64 - ref) <= 1e-5 * max(1.0, np.sum(np.abs([t.coef for t in terms])))
+
+
+@pytest.mark.parametrize("n", [2, 9, 13])
+def test_apply_pauli_sum(gpu, n):
+    import torch
+    psi = W.random_state(n, 7)
+    terms = _rand_terms(n, 25, 100 + n)
+    d = _dev(psi)
+    out = torch.empty_like(d)
+    gpu.sv_apply_pauli_sum(d, out, terms)
+    ref = oracle.apply_hamiltonian(psi, n, terms)
+    assert np.max(np.abs(out.cpu().numpy() - ref)) <= 1e-12 * np.max(np.abs(ref))
+
+
+def _grad_check(gpu, circ, terms, ref, tol=1e-8):
+    import torch
+    params = torch.from_numpy(circ.params).cuda()
+    psi = torch.empty(1 << circ.n, dtype=torch.complex128, device="cuda")
+    gpu.sv_init(psi, 0)
+    gpu.sv_apply_circuit(psi, circ, params=params)
+    lam = torch.empty_like(psi)
+    grad, loss = gpu.sv_adjoint_grad(psi, lam, circ, params, terms)
+    g = grad.cpu().numpy()
+    err = np.max(np.abs(g - ref)) / max(1.0, np.max(np.abs(ref)))
+    assert err <= tol, err
+    # the sweep un-applies every gate: psi is back to |0...0>
+    back = psi.cpu().numpy()
+    e0 = np.zeros_like(back); e0[0] = 1
+    assert np.max(np.abs(back - e0)) <= 1e-12
+    assert abs(loss.item() - oracle.loss(circ, circ.params, terms)) <= 1e-12 * max(1, sum(abs(t.coef) for t in terms))
+    return err
+
+
+@pytest.mark.parametrize("n,layers", [(4, 2), (8, 3), (12, 2)])
+def test_adjoint_hea_vs_param_shift(gpu, n, layers):
+    c = W.hea(n, layers, seed=n)
+    terms = W.zz_x_hamiltonian(n, n)
+    ref = oracle.grad_param_shift(c, c.params, terms)
+    err = _grad_check(gpu, c, terms, ref)
+    _say("hea n=%d err %.2e" % (n, err))
+
+
+def test_adjoint_controlled_rotations_vs_param_shift(gpu):
+    """Controlled RY/RZ with positive and negative controls, parameters
+    shared between gates, fixed gates in between (including adjoints)."""
+    n = 7
+    rng = np.random.default_rng(3)
+    gates, P = [], 6
+    for i in range(40):
+        t = int(rng.integers(0, n))
+        others = [q for q in range(n) if q != t]
+        c = int(rng.integers(0, 3))
+        ctrls = tuple(int(q) for q in rng.choice(others, size=c, replace=False)) if c else ()
+        vals = tuple(int(v) for v in rng.integers(0, 2, size=c))
+        r = rng.random()
+        if r < 0.5:
+            gates.append(W.Gate(("RY", "RZ")[i % 2], t, ctrls, vals, param=int(rng.integers(0, P))))
+        elif r < 0.7:
+            gates.append(W.Gate("H", t, ctrls, vals))
+        else:
+            gates.append(W.Gate("~U", t, ctrls, vals, matrix=W.haar_unitary_2x2(i)))
+    circ = W.Circuit(n, gates, rng.uniform(0, 2 * np.pi, size=P))
+    terms = _rand_terms(n, 12, 9)
+    ref = oracle.grad_param_shift(circ, circ.params, terms)
+    _grad_check(gpu, circ, terms, ref)
+
+
+def test_adjoint_rx_phase_and_adjoint_flags_vs_finite_differences(gpu):
+    """Kinds without a shift rule in the oracle here (controlled RX and P,
+    adjoint-flagged rotations): central differences, h = 1e-5."""
+    n = 6
+    rng = np.random.default_rng(4)
+    gates = []
+    kinds = ("RX", "P", "~RY", "~RZ", "RZ", "~P")
+    for i in range(30):
+        t = int(rng.integers(0, n))
+        others = [q for q in range(n) if q != t]
+        c = int(rng.integers(0, 3))
+        ctrls = tuple(int(q) for q in rng.choice(others, size=c, replace=False)) if c else ()
+        vals = tuple(int(v) for v in rng.integers(0, 2, size=c))
+        gates.append(W.Gate(kinds[i % len(kinds)], t, ctrls, vals, param=i % 5))
+        gates.append(W.Gate("H", int(rng.integers(0, n))))
+    circ = W.Circuit(n, gates, rng.uniform(0, 2 * np.pi, size=5))
+    terms = _rand_terms(n, 10, 5)
+    ref = oracle.grad_finite_diff(circ, circ.params, terms)
+    _grad_check(gpu, circ, terms, ref, tol=1e-7)
+
+
+def test_autograd_function(gpu):
+    import torch
+    n = 9
+    c = W.hea(n, 2, seed=21)
+    terms = W.zz_x_hamiltonian(n, 21)
+    model = gpu.ExpectationModel(c, terms)
+    p = torch.tensor(c.params, dtype=torch.float64, device="cuda", requires_grad=True)
+    loss = model(p)
+    (3.0 * loss).backward()
+    ref = oracle.grad_param_shift(c, c.params, terms)
+    assert abs(loss.item() - oracle.loss(c, c.params, terms)) <= 1e-12 * 20
+    assert np.max(np.abs(p.grad.cpu().numpy() - 3.0 * ref)) <= 3e-8
+    # a second backward through a fresh forward agrees bit for bit
+    p2 = p.detach().clone().requires_grad_(True)
+    model(p2).mul(3.0).backward()
+    assert torch.equal(p.grad, p2.grad)
+
+
+def test_adjoint_config3_sampled(gpu):
+    """config3 at full size (n=24, 16 layers, 768 parameters): adjoint
+    gradient against the oracle's parameter shift on a seeded sample of
+    parameters, and loss against the oracle."""
+    import torch
+    c, terms = W.config3()
+    rng = np.random.default_rng(55)
+    sample = sorted(rng.choice(c.nparams, size=4, replace=False).tolist())
+    params = torch.from_numpy(c.params).cuda()
+    psi = torch.empty(1 << c.n, dtype=torch.complex128, device="cuda")
+    gpu.sv_init(psi, 0)
+    gpu.sv_apply_circuit(psi, c, params=params)
+    lam = torch.empty_like(psi)
+    grad, loss = gpu.sv_adjoint_grad(psi, lam, c, params, terms)
+    g = grad.cpu().numpy()
+    _say("config3 loss %.12f" % loss.item())
+    ref_loss = oracle.loss(c, c.params, terms)
+    assert abs(loss.item() - ref_loss) <= 1e-10
+    ref = oracle.grad_param_shift(c, c.params, terms, which=sample)
+    err = np.max(np.abs(g[sample] - ref)) / max(1.0, np.max(np.abs(ref)))
+    _say("config3 sampled grad err %.2e" % err)
+    assert err <= 1e-8
