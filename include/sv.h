@@ -270,6 +270,37 @@ int sv_adjoint_grad(const sv_state_t *psi, const sv_state_t *lam, const sv_gate_
                     const double *params_dev, int nparams, const sv_pauli_t *terms, int nterms, double *grad_dev,
                     double *loss_dev, const double *scale_dev, sv_stream_t st);
 
+/* ------------------------------------------------------------------ batches
+ *
+ * Many independent circuits, each on its own state (n may differ; one dtype
+ * per batch), run by one persistent launch: each workgroup takes the next
+ * circuit from a device work queue (longest first) and applies all its
+ * gates; a state of at most 64 KiB stays in LDS for the whole circuit.
+ *   states        ncirc state views (device buffers must not overlap)
+ *   gates         all circuits' gates concatenated; circuit c owns
+ *                 gates[gate_offsets[c] .. gate_offsets[c+1])
+ *   params_dev    concatenated angles (device); circuit c's gate with
+ *                 param p reads params_dev[param_offsets[c] + p];
+ *                 param_offsets may be NULL when no gate has a parameter
+ *   nparams_total length of params_dev
+ * Every circuit is validated before anything is enqueued; errors name the
+ * circuit. */
+int sv_apply_circuits_batched(const sv_state_t *states, int ncirc, const sv_gate_t *gates,
+                              const int64_t *gate_offsets, const double *params_dev, const int64_t *param_offsets,
+                              int64_t nparams_total, sv_stream_t st);
+
+/* Batched adjoint gradients: for each circuit c, psi_states[c] holds its
+ * final forward state (consumed, as in sv_adjoint_grad), lam_states[c] is a
+ * distinct workspace state of the same shape, its Hamiltonian is
+ * terms[term_offsets[c] .. term_offsets[c+1]) (at least one term),
+ * grad_dev[param_offsets[c] + j] receives dL_c/dtheta_j and loss_dev[c] the
+ * loss.  One workgroup per circuit; sums are reduced in a fixed order.
+ * n <= 31 per circuit. */
+int sv_adjoint_grad_batched(const sv_state_t *psi_states, const sv_state_t *lam_states, int ncirc,
+                            const sv_gate_t *gates, const int64_t *gate_offsets, const double *params_dev,
+                            const int64_t *param_offsets, int64_t nparams_total, const sv_pauli_t *terms,
+                            const int64_t *term_offsets, double *grad_dev, double *loss_dev, sv_stream_t st);
+
 /* Write, for each reduced iteration index i_r in [0, 2^(n-1-ncontrols)), the
  * index of the first pair element (bit target clear) that the scheduled
  * kernels update for it, computed with the same device function they use

@@ -363,3 +363,4 @@ def sv_circuit_plan(n: int, gates, dtype: int = SV_C128, nparams: int = 0, flags
 
 from .observables import (sv_pauli_t, pauli_terms, sv_expect, sv_expect_terms, sv_apply_pauli_sum,  # noqa: E402
                           sv_adjoint_grad, SvExpectation, ExpectationModel)
+from .batched import sv_apply_circuits_batched, sv_adjoint_grad_batched  # noqa: E402

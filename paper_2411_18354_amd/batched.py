@@ -1,0 +1,76 @@
+"""Binding of the batched entry points (sv_apply_circuits_batched,
+sv_adjoint_grad_batched).  Argument marshalling only."""
+from __future__ import annotations
+
+import ctypes
+from typing import Optional, Sequence
+
+from . import _L, _check, _sig, _vp, circuit_gates, state_view, stream_ptr, sv_gate_t, sv_state_t
+from .observables import pauli_terms, sv_pauli_t
+
+_i64p = ctypes.POINTER(ctypes.c_int64)
+_sig("sv_apply_circuits_batched", [ctypes.POINTER(sv_state_t), ctypes.c_int, ctypes.POINTER(sv_gate_t), _i64p, _vp,
+                                   _i64p, ctypes.c_int64, _vp])
+_sig("sv_adjoint_grad_batched", [ctypes.POINTER(sv_state_t), ctypes.POINTER(sv_state_t), ctypes.c_int,
+                                 ctypes.POINTER(sv_gate_t), _i64p, _vp, _i64p, ctypes.c_int64,
+                                 ctypes.POINTER(sv_pauli_t), _i64p, _vp, _vp, _vp])
+
+
+def _states(tensors):
+    arr = (sv_state_t * len(tensors))()
+    for i, t in enumerate(tensors):
+        arr[i] = state_view(t)
+    return arr
+
+
+def _offsets(counts):
+    arr = (ctypes.c_int64 * (len(counts) + 1))()
+    acc = 0
+    for i, c in enumerate(counts):
+        arr[i] = acc
+        acc += int(c)
+    arr[len(counts)] = acc
+    return arr
+
+
+def _concat_gates(circuits):
+    gates = [g for c in circuits for g in c.gates]
+    return circuit_gates(gates), _offsets([len(c.gates) for c in circuits])
+
+
+def sv_apply_circuits_batched(states: Sequence, circuits: Sequence, params=None, param_counts=None,
+                              stream=None) -> None:
+    """Run circuits[c] on states[c] in one persistent launch.  params: device
+    float64 tensor of all circuits' angles concatenated; param_counts: number
+    of parameters of each circuit (defaults to circuit.nparams)."""
+    st = _states(states)
+    garr, goff = _concat_gates(circuits)
+    if param_counts is None:
+        param_counts = [getattr(c, "nparams", 0) or 0 for c in circuits]
+    poff = _offsets(param_counts)
+    p = ctypes.c_void_p(0 if params is None else params.data_ptr())
+    total = 0 if params is None else int(params.numel())
+    _check(_L.sv_apply_circuits_batched(st, len(states), garr, goff, p, poff, total, stream_ptr(stream)))
+
+
+def sv_adjoint_grad_batched(psi_states: Sequence, lam_states: Sequence, circuits: Sequence, params, hamiltonians,
+                            param_counts=None, grad=None, loss=None, stream=None):
+    """Batched adjoint gradients; returns (grad, loss) device tensors."""
+    import torch
+    ps, ls = _states(psi_states), _states(lam_states)
+    garr, goff = _concat_gates(circuits)
+    if param_counts is None:
+        param_counts = [c.nparams for c in circuits]
+    poff = _offsets(param_counts)
+    terms = [t for h in hamiltonians for t in h]
+    tarr = pauli_terms(terms)
+    toff = _offsets([len(h) for h in hamiltonians])
+    dev = psi_states[0].device
+    if grad is None:
+        grad = torch.empty(max(1, int(params.numel())), dtype=torch.float64, device=dev)
+    if loss is None:
+        loss = torch.empty(len(circuits), dtype=torch.float64, device=dev)
+    _check(_L.sv_adjoint_grad_batched(ps, ls, len(circuits), garr, goff, ctypes.c_void_p(params.data_ptr()), poff,
+                                      int(params.numel()), tarr, toff, ctypes.c_void_p(grad.data_ptr()),
+                                      ctypes.c_void_p(loss.data_ptr()), stream_ptr(stream)))
+    return grad[:int(params.numel())], loss

@@ -93,6 +93,7 @@ using namespace sv;
 
 struct sv_circuit {
     int n = 0, dtype = 0, flags = 0, nparams = 0, device = 0, m = 0;
+    int m_cap = 64;  // upper bound on the tile width (callers with a fixed LDS budget)
     std::vector<sv_gate_t> gates;
     std::vector<Pass> passes;
     int njobs = 0;
@@ -122,7 +123,7 @@ static int plan_circuit(sv_circuit *c, std::vector<TileGate> &tiles, std::vector
     }
     const bool masked = c->flags & SV_MASKED;
     const bool fuse = (c->flags & SV_FUSE) && !masked;
-    c->m = std::min(tuning().tile_log2[c->dtype == SV_C128 ? 0 : 1], c->n);
+    c->m = std::min(std::min(tuning().tile_log2[c->dtype == SV_C128 ? 0 : 1], c->n), c->m_cap);
     const int min_run = std::max(1, tuning().fuse_min_gates);
     std::vector<int> tile_slot(G, -1);
 
@@ -353,6 +354,9 @@ static int run_graph(sv_circuit *c, const sv_state_t *s, const double *params, h
     return SV_OK;
 }
 
+int circuit_plan_capped(int n, int dtype, const sv_gate_t *gates, int ngates, int nparams, int flags, int m_cap,
+                        int32_t *order, int32_t *pass_of, int64_t *npasses, int *m_used);
+
 } // namespace sv
 
 extern "C" {
@@ -372,6 +376,15 @@ int sv_gate_matrix(int kind, double theta, const double *U, double *out) {
 int sv_circuit_plan(int n, int dtype, const sv_gate_t *gates, int ngates, int nparams, int flags, int32_t *order,
                     int32_t *pass_of, int64_t *npasses) {
     clear_error();
+    return circuit_plan_capped(n, dtype, gates, ngates, nparams, flags, 64, order, pass_of, npasses, nullptr);
+}
+
+} // extern "C"
+
+namespace sv {
+
+int circuit_plan_capped(int n, int dtype, const sv_gate_t *gates, int ngates, int nparams, int flags, int m_cap,
+                        int32_t *order, int32_t *pass_of, int64_t *npasses, int *m_used) {
     if (dtype != SV_C128 && dtype != SV_C64)
         return fail(SV_EINVAL, "unknown dtype %d", dtype);
     if (n < 1 || n > max_qubits(dtype))
@@ -387,6 +400,7 @@ int sv_circuit_plan(int n, int dtype, const sv_gate_t *gates, int ngates, int np
     c.dtype = dtype;
     c.flags = flags;
     c.nparams = nparams;
+    c.m_cap = m_cap;
     c.gates.assign(gates, gates + ngates);
     std::vector<TileGate> tiles;
     std::vector<ParamJob> jobs;
@@ -413,8 +427,14 @@ int sv_circuit_plan(int n, int dtype, const sv_gate_t *gates, int ngates, int np
     }
     if (npasses)
         *npasses = (int64_t)c.passes.size();
+    if (m_used)
+        *m_used = c.m;
     return SV_OK;
 }
+
+} // namespace sv
+
+extern "C" {
 
 int sv_circuit_create(int n, int dtype, const sv_gate_t *gates, int ngates, int nparams, int flags,
                       sv_circuit_t **out) {

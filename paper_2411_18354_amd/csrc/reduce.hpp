@@ -18,18 +18,18 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
-// Sum of v over the workgroup (kRedThreads lanes); valid in every lane.
-// scratch: kRedThreads / 64 doubles of LDS.
+// Sum of v over the whole workgroup (blockDim.x lanes, a multiple of 64);
+// valid in every lane.  scratch: blockDim.x / 64 doubles of LDS.
 __device__ __forceinline__ double block_sum(double v, double *scratch) {
     v = wave_sum(v);
     const int w = threadIdx.x >> 6;
+    const int nw = blockDim.x >> 6;
     __syncthreads();
     if ((threadIdx.x & 63) == 0)
         scratch[w] = v;
     __syncthreads();
     double s = 0.0;
-#pragma unroll
-    for (int i = 0; i < kRedThreads / 64; ++i)
+    for (int i = 0; i < nw; ++i)
         s += scratch[i];
     return s;
 }
@@ -42,7 +42,7 @@ inline unsigned reduce_grid(uint64_t work_items) {
 // Sum partials[0 .. count) in a fixed order with one workgroup.
 __device__ __forceinline__ double block_sum_array(const double *partials, int count, double *scratch) {
     double v = 0.0;
-    for (int i = threadIdx.x; i < count; i += kRedThreads)
+    for (int i = threadIdx.x; i < count; i += blockDim.x)
         v += partials[i];
     return block_sum(v, scratch);
 }

@@ -1,0 +1,164 @@
+"""GPU parity of the batched entry points against the oracle: mixed-width
+batches (LDS-resident and global-memory circuits), config4 at full size on
+a seeded sample of circuits, and batched adjoint gradients."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+def _packed_states(ns, dtype):
+    """One device buffer holding every state (|0..0> each) and views into it."""
+    import torch
+    td = torch.complex128 if dtype == "c128" else torch.complex64
+    sizes = [1 << n for n in ns]
+    offs = np.concatenate([[0], np.cumsum(sizes)])
+    buf = torch.zeros(int(offs[-1]), dtype=td, device="cuda")
+    idx = torch.from_numpy(offs[:-1].astype(np.int64)).cuda()
+    buf[idx] = 1
+    views = [buf[int(offs[i]):int(offs[i + 1])] for i in range(len(ns))]
+    return buf, views
+
+
+def _err(got, ref):
+    return float(np.max(np.abs(got.astype(np.complex128) - ref)) / np.max(np.abs(ref)))
+
+
+def _mixed(seed, ncirc=40):
+    rng = np.random.default_rng(seed)
+    circs = []
+    for i in range(ncirc):
+        n = int(rng.integers(2, 17))
+        c = W.config0(seed=seed * 1000 + i, n=n, ngates=int(rng.integers(20, 120)))
+        # turn some rotations into parameterised gates
+        gates, p = [], 0
+        for g in c.gates:
+            if g.kind in ("RY", "RZ") and rng.random() < 0.5:
+                gates.append(W.Gate(g.kind, g.target, g.controls, g.values, param=p)); p += 1
+            else:
+                gates.append(g)
+        circs.append(W.Circuit(n, gates, rng.uniform(0, 2 * np.pi, size=p)))
+    return circs
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("tile", [12, 7])
+def test_batched_mixed_widths(gpu, dtype, tile):
+    import torch
+    gpu.sv_tune_set("tile_log2_c128", tile)
+    gpu.sv_tune_set("tile_log2_c64", tile + 1)
+    try:
+        circs = _mixed(3)
+        buf, views = _packed_states([c.n for c in circs], dtype)
+        params = torch.from_numpy(np.concatenate([c.params for c in circs])).cuda()
+        gpu.sv_apply_circuits_batched(views, circs, params)
+        worst = 0.0
+        for c, v in zip(circs, views):
+            ref = oracle.run_circuit(c, c.params)
+            e = _err(v.cpu().numpy(), ref)
+            worst = max(worst, e)
+            assert e <= (1e-12 if dtype == "c128" else 1e-5), (c.n, e)
+        _say("batched", dtype, "tile", tile, "worst", worst)
+    finally:
+        gpu.sv_tune_set("tile_log2_c128", 12)
+        gpu.sv_tune_set("tile_log2_c64", 13)
+
+
+def test_batched_errors_name_circuit(gpu):
+    import torch
+    circs = [W.config0(n=5, ngates=10), W.Circuit(5, [W.Gate("X", 7)])]
+    buf, views = _packed_states([5, 5], "c128")
+    before = buf.clone()
+    with pytest.raises(gpu.SvError) as e:
+        gpu.sv_apply_circuits_batched(views, circs)
+    assert "circuit 1" in str(e.value)
+    torch.cuda.synchronize()
+    assert torch.equal(buf, before)
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_config4_full_sampled(gpu, dtype):
+    """config4: 4096 circuits, n uniform in 10..20, 100-400 gates each
+    (12.5 GB of complex128 states); a seeded sample checked against the
+    oracle, every state's norm checked on the device."""
+    import torch
+    circs = W.config4()
+    _say("config4", dtype, "states", sum(1 << c.n for c in circs) * (16 if dtype == "c128" else 8) / 2 ** 30, "GiB")
+    buf, views = _packed_states([c.n for c in circs], dtype)
+    torch.cuda.synchronize()
+    gpu.sv_apply_circuits_batched(views, circs)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(17)
+    sample = sorted(rng.choice(len(circs), size=5, replace=False).tolist())
+    big = [i for i, c in enumerate(circs) if c.n == 20][:1]
+    tol = 1e-12 if dtype == "c128" else 1e-5
+    for i in sample + big:
+        ref = oracle.run_circuit(circs[i])
+        e = _err(views[i].cpu().numpy(), ref)
+        _say("config4 circuit", i, "n", circs[i].n, "err", e)
+        assert e <= tol
+    norms = torch.stack([v.abs().pow(2).sum() for v in views]).double()
+    assert float((norms - 1).abs().max()) <= (1e-12 if dtype == "c128" else 1e-4)
+
+
+def test_batched_adjoint_small(gpu):
+    import torch
+    circs, hams = [], []
+    for i in range(10):
+        n = 3 + i % 7
+        c = W.hea(n, 2, seed=200 + i)
+        circs.append(c)
+        hams.append(W.zz_x_hamiltonian(n, 300 + i))
+    buf, views = _packed_states([c.n for c in circs], "c128")
+    params = torch.from_numpy(np.concatenate([c.params for c in circs])).cuda()
+    gpu.sv_apply_circuits_batched(views, circs, params)
+    lbuf = torch.empty_like(buf)
+    lviews = []
+    off = 0
+    for c in circs:
+        lviews.append(lbuf[off:off + (1 << c.n)]); off += 1 << c.n
+    grad, loss = gpu.sv_adjoint_grad_batched(views, lviews, circs, params, hams)
+    g = grad.cpu().numpy()
+    L = loss.cpu().numpy()
+    off = 0
+    for i, (c, h) in enumerate(zip(circs, hams)):
+        ref = oracle.grad_param_shift(c, c.params, h)
+        got = g[off:off + c.nparams]
+        off += c.nparams
+        assert np.max(np.abs(got - ref)) <= 1e-8 * max(1, np.max(np.abs(ref))), i
+        assert abs(L[i] - oracle.loss(c, c.params, h)) <= 1e-12 * 20
+        back = views[i].cpu().numpy()
+        assert abs(back[0] - 1) <= 1e-12 and np.max(np.abs(back[1:])) <= 1e-12
+
+
+def test_config4_adjoint_full_sampled(gpu):
+    """256 ansatz circuits at n=16, 4 layers (128 parameters each): batched
+    forward and batched adjoint; gradients of a seeded sample against the
+    oracle's parameter shift."""
+    import torch
+    pairs = W.config4_adjoint()
+    circs = [c for c, _ in pairs]
+    hams = [h for _, h in pairs]
+    buf, views = _packed_states([c.n for c in circs], "c128")
+    lbuf = torch.empty_like(buf)
+    lviews = [lbuf[i << 16:(i + 1) << 16] for i in range(len(circs))]
+    params = torch.from_numpy(np.concatenate([c.params for c in circs])).cuda()
+    gpu.sv_apply_circuits_batched(views, circs, params)
+    grad, loss = gpu.sv_adjoint_grad_batched(views, lviews, circs, params, hams)
+    g = grad.cpu().numpy()
+    rng = np.random.default_rng(23)
+    for ci in rng.choice(len(circs), size=2, replace=False).tolist():
+        c, h = circs[ci], hams[ci]
+        which = sorted(rng.choice(c.nparams, size=3, replace=False).tolist())
+        ref = oracle.grad_param_shift(c, c.params, h, which=which)
+        got = g[ci * 128 + np.array(which)]
+        _say("config4 adjoint circuit", ci, "err", np.max(np.abs(got - ref)))
+        assert np.max(np.abs(got - ref)) <= 1e-8 * max(1, np.max(np.abs(ref)))
+        assert abs(loss[ci].item() - oracle.loss(c, c.params, h)) <= 1e-10
