@@ -45,7 +45,7 @@ def kernel_source_hash():
 def load_traffic(kernel, src_hash):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 --pmc
     summary, or None when absent or taken on other kernel sources."""
-    path = os.path.join(ROOT, "profiles", "traffic_k_pair_config1_n28.md")
+    path = os.path.join(ROOT, "profiles", "traffic_k_pair_gate_sweep_n28.md")
     if not os.path.exists(path):
         return None
     txt = open(path).read()
@@ -91,7 +91,7 @@ def summarize_profile(trace_dir, fetch_dir, write_dir):
     import workloads as W
     import paper_2411_18354_amd as sv
     n = N_QUBITS
-    cases = W.config1_cases(n, seed=3)
+    cases = W.gate_sweep_cases(n, seed=3)
     plan = {}
     for t, ctrls in cases:
         cm = sum(1 << q for q in ctrls)
@@ -127,7 +127,7 @@ def summarize_profile(trace_dir, fetch_dir, write_dir):
               "average algorithmic bytes per launch %.4g (read + write of every touched "
               "amplitude), i.e. %.1f GB/s." % (kname, float(krow["AverageNs"]) / 1e3, krow["Calls"], alg,
                                                 alg / float(krow["AverageNs"]))]
-    with open(os.path.join(ROOT, "profiles", "kernel_trace_config1_n28.md"), "w") as fh:
+    with open(os.path.join(ROOT, "profiles", "kernel_trace_gate_sweep_n28.md"), "w") as fh:
         fh.write("\n".join(lines) + "\n")
     # traffic: FETCH_SIZE and WRITE_SIZE (KiB per dispatch), scaled by the copy kernel
     fetch = _counter_per_kernel(fetch_dir, "FETCH_SIZE")
@@ -162,9 +162,147 @@ def summarize_profile(trace_dir, fetch_dir, write_dir):
           "- hbm_bytes_per_launch: %.6g" % (f_b + w_b),
           "- alg_bytes_per_launch: %.6g" % alg,
           "- traffic_over_alg: %.4f" % ((f_b + w_b) / alg), ""]
-    with open(os.path.join(ROOT, "profiles", "traffic_k_pair_config1_n28.md"), "w") as fh:
+    with open(os.path.join(ROOT, "profiles", "traffic_k_pair_gate_sweep_n28.md"), "w") as fh:
         fh.write("\n".join(tl) + "\n")
     print("\n".join(lines + [""] + tl))
+
+
+def _time_ms(torch, stream, fn, reps):
+    """Median of reps HIP-event timings of fn() on stream (after one warmup)."""
+    with torch.cuda.stream(stream):
+        fn()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            fn()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1))
+    ts.sort()
+    return ts[len(ts) // 2]
+
+
+def measure_extras(sv, W, torch, np, stream, with_layered):
+    """Adjoint gradients (n=24 ansatz), batched circuits (4096 uneven circuits), the paper's
+    QFT and streaming circuits at 29 qubits, and optionally the layered n=32 circuit."""
+    out = {}
+    dev = torch.device("cuda:0")
+    # ---- adjoint gradients: n=24 HEA, 768 parameters
+    log("adjoint: n=24 ansatz")
+    c3, H = W.hea_problem_n24()
+    params = torch.from_numpy(c3.params).to(dev)
+    psi = torch.empty(1 << c3.n, dtype=torch.complex128, device=dev)
+    work = torch.empty_like(psi)
+    lam = torch.empty_like(psi)
+    plan = sv.Circuit(c3.n, c3, nparams=c3.nparams, flags=sv.SV_FUSE)
+    gates = sv.circuit_gates(c3)
+    terms = sv.pauli_terms(H)
+    loss = torch.empty(1, dtype=torch.float64, device=dev)
+    grad = torch.empty(c3.nparams, dtype=torch.float64, device=dev)
+
+    def fwd():
+        sv.sv_init(psi, 0, stream=stream)
+        plan.run(psi, params, stream=stream)
+        sv.sv_expect(psi, terms, out=loss, stream=stream)
+
+    def bwd():
+        sv.sv_copy_state(work, psi, stream=stream)
+        sv.sv_adjoint_grad(work, lam, gates, params, terms, grad=grad, stream=stream)
+
+    t_f = _time_ms(torch, stream, fwd, 5)
+    t_b = _time_ms(torch, stream, bwd, 5)
+    out["adjoint_hea_n24"] = {
+        "n": c3.n, "params": c3.nparams, "gates": len(c3.gates), "forward_ms": round(t_f, 3),
+        "backward_ms": round(t_b, 3), "backward_over_forward": round(t_b / t_f, 2),
+        "gradients_per_s": round(1e3 / t_b, 3), "param_derivatives_per_s": round(c3.nparams * 1e3 / t_b, 1),
+        "forward_passes": plan.info()["passes"]}
+    plan.close()
+    del psi, work, lam
+    torch.cuda.empty_cache()
+    # ---- batched: 4096 uneven circuits forward (complex128 and complex64) and batched adjoint
+    for dt, td in (("c128", torch.complex128), ("c64", torch.complex64)):
+        log("batched: 4096 uneven circuits", dt)
+        circs = W.uneven_batch()
+        ns = [c.n for c in circs]
+        offs = np.concatenate([[0], np.cumsum([1 << n for n in ns])])
+        buf = torch.zeros(int(offs[-1]), dtype=td, device=dev)
+        views = [buf[int(offs[i]):int(offs[i + 1])] for i in range(len(circs))]
+        t_b4 = _time_ms(torch, stream, lambda: sv.sv_apply_circuits_batched(views, circs, stream=stream), 3)
+        ngates = sum(len(c.gates) for c in circs)
+        alg = sum(len(c.gates) * (1 << c.n) * 2 * (16 if dt == "c128" else 8) for c in circs)
+        out["batched_uneven4096_" + dt] = {"circuits": len(circs), "gates": ngates, "ms": round(t_b4, 2),
+                                        "circuits_per_s": round(len(circs) * 1e3 / t_b4, 1),
+                                        "gate_updates_per_s": round(ngates * 1e3 / t_b4, 1),
+                                        "unfused_equivalent_GBps": round(alg / t_b4 / 1e6, 1)}
+        del buf, views
+        torch.cuda.empty_cache()
+    log("batched adjoint: 256 x n=16")
+    pairs = W.hea_batch_n16()
+    circs = [c for c, _ in pairs]
+    hams = [h for _, h in pairs]
+    buf = torch.zeros(len(circs) << 16, dtype=torch.complex128, device=dev)
+    lbuf = torch.empty_like(buf)
+    views = [buf[i << 16:(i + 1) << 16] for i in range(len(circs))]
+    lviews = [lbuf[i << 16:(i + 1) << 16] for i in range(len(circs))]
+    bparams = torch.from_numpy(np.concatenate([c.params for c in circs])).to(dev)
+    bgrad = torch.empty(bparams.numel(), dtype=torch.float64, device=dev)
+    bloss = torch.empty(len(circs), dtype=torch.float64, device=dev)
+
+    def bfwd():
+        buf.zero_()
+        buf[::1 << 16] = 1
+        sv.sv_apply_circuits_batched(views, circs, bparams, stream=stream)
+
+    def bboth():
+        bfwd()
+        sv.sv_adjoint_grad_batched(views, lviews, circs, bparams, hams, grad=bgrad, loss=bloss, stream=stream)
+
+    t_bf = _time_ms(torch, stream, bfwd, 3)
+    t_bb = _time_ms(torch, stream, bboth, 3) - t_bf
+    out["batched_adjoint_hea256_n16"] = {"circuits": len(circs), "n": 16, "params_each": circs[0].nparams,
+                                      "forward_ms": round(t_bf, 2), "backward_ms": round(t_bb, 2),
+                                      "gradients_per_s": round(len(circs) * 1e3 / t_bb, 1)}
+    del buf, lbuf, views, lviews
+    torch.cuda.empty_cache()
+    # ---- the paper's 29-qubit circuits, masked vs scheduled (vs fused)
+    for name, circ in (("qft29", W.qft(29)), ("stream29", W.stream(29))):
+        for dt, td in (("c64", torch.complex64), ("c128", torch.complex128)):
+            log("paper circuit", name, dt)
+            st = torch.empty(1 << 29, dtype=td, device=dev)
+            row = {"gates": len(circ.gates)}
+            for label, fl in (("masked", sv.SV_MASKED), ("scheduled", 0), ("scheduled_fused", sv.SV_FUSE)):
+                p = sv.Circuit(29, circ, dtype=sv.SV_C128 if dt == "c128" else sv.SV_C64, flags=fl)
+
+                def run():
+                    sv.sv_init(st, 1, stream=stream)
+                    p.run(st, stream=stream)
+                row[label + "_ms"] = round(_time_ms(torch, stream, run, 3), 3)
+                p.close()
+            row["masked_over_scheduled"] = round(row["masked_ms"] / row["scheduled_ms"], 2)
+            out["%s_%s" % (name, dt)] = row
+            del st
+            torch.cuda.empty_cache()
+    if with_layered:
+        log("layered circuit: n=32 complex128")
+        c2 = W.layered_circuit_n32()
+        st = torch.empty(1 << 32, dtype=torch.complex128, device=dev)
+        row = {"gates": len(c2.gates)}
+        for label, fl in (("unfused", 0), ("fused", sv.SV_FUSE)):
+            p = sv.Circuit(32, c2, flags=fl)
+            row[label + "_passes"] = p.info()["passes"]
+
+            def run():
+                sv.sv_init(st, 0, stream=stream)
+                p.run(st, stream=stream)
+            row[label + "_ms"] = round(_time_ms(torch, stream, run, 1), 1)
+            p.close()
+        out["layered_n32"] = row
+        del st
+        torch.cuda.empty_cache()
+    return out
 
 
 def main():
@@ -178,6 +316,10 @@ def main():
     ap.add_argument("--pmc-copy", action="store_true",
                     help="first copy a 1 GiB state three times with the library's plain copy kernel "
                          "(calibration of the rocprofv3 byte counters)")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the adjoint, batched and paper-circuit measurements")
+    ap.add_argument("--layered-n32", action="store_true",
+                    help="also time the layered n=32 circuit (64 GiB) with and without LDS fusion (about a minute)")
     ap.add_argument("--summarize-profile", nargs=3, metavar=("TRACE_DIR", "FETCH_DIR", "WRITE_DIR"),
                     help="write profiles/ summaries from rocprofv3 CSV output of this script and exit")
     args = ap.parse_args()
@@ -200,8 +342,8 @@ def main():
     n = N_QUBITS
     log("generating n=%d input state" % n)
     psi_host = W.random_state(n, seed=1)
-    U = np.asarray(W.config1_gate(seed=2), dtype=np.float64)
-    cases = W.config1_cases(n, seed=3)
+    U = np.asarray(W.sweep_unitary(seed=2), dtype=np.float64)
+    cases = W.gate_sweep_cases(n, seed=3)
     # interleave targets and control counts so consecutive gates touch
     # unrelated amplitudes
     order = sorted(range(len(cases)), key=lambda i: (len(cases[i][1]), cases[i][0]))
@@ -295,6 +437,12 @@ def main():
                 "alg_bytes_per_launch": avg_bytes, "launches": ks["launches"],
                 "kernel_source_hash": src_hash}
 
+    extras = None
+    if not args.no_extras:
+        del d
+        torch.cuda.empty_cache()
+        extras = measure_extras(sv, W, torch, np, stream, args.layered_n32)
+
     cpu = None
     if args.cpu_seconds > 0:
         import oracle
@@ -334,6 +482,7 @@ def main():
         "cpu_baseline": cpu,
         "masked_value": None if masked_total is None else round(ngates / (masked_total / 1e3), 2),
         "sweep": rows,
+        "extras": extras,
     }
     print(json.dumps(out), flush=True)
 

@@ -155,12 +155,12 @@ def test_autograd_function(gpu):
     assert torch.equal(p.grad, p2.grad)
 
 
-def test_adjoint_config3_sampled(gpu):
-    """config3 at full size (n=24, 16 layers, 768 parameters): adjoint
+def test_adjoint_hea_n24_sampled(gpu):
+    """The n=24 ansatz problem at full size (n=24, 16 layers, 768 parameters): adjoint
     gradient against the oracle's parameter shift on a seeded sample of
     parameters, and loss against the oracle."""
     import torch
-    c, terms = W.config3()
+    c, terms = W.hea_problem_n24()
     rng = np.random.default_rng(55)
     sample = sorted(rng.choice(c.nparams, size=4, replace=False).tolist())
     params = torch.from_numpy(c.params).cuda()
@@ -170,10 +170,10 @@ def test_adjoint_config3_sampled(gpu):
     lam = torch.empty_like(psi)
     grad, loss = gpu.sv_adjoint_grad(psi, lam, c, params, terms)
     g = grad.cpu().numpy()
-    _say("config3 loss %.12f" % loss.item())
+    _say("hea n24 loss %.12f" % loss.item())
     ref_loss = oracle.loss(c, c.params, terms)
     assert abs(loss.item() - ref_loss) <= 1e-10
     ref = oracle.grad_param_shift(c, c.params, terms, which=sample)
     err = np.max(np.abs(g[sample] - ref)) / max(1.0, np.max(np.abs(ref)))
-    _say("config3 sampled grad err %.2e" % err)
+    _say("hea n24 sampled grad err %.2e" % err)
     assert err <= 1e-8

@@ -1,5 +1,5 @@
 """GPU parity of the batched entry points against the oracle: mixed-width
-batches (LDS-resident and global-memory circuits), config4 at full size on
+batches (LDS-resident and global-memory circuits), the 4096-circuit batch at full size on
 a seeded sample of circuits, and batched adjoint gradients."""
 import numpy as np
 import pytest
@@ -36,7 +36,7 @@ def _mixed(seed, ncirc=40):
     circs = []
     for i in range(ncirc):
         n = int(rng.integers(2, 17))
-        c = W.config0(seed=seed * 1000 + i, n=n, ngates=int(rng.integers(20, 120)))
+        c = W.random_gates_n12(seed=seed * 1000 + i, n=n, ngates=int(rng.integers(20, 120)))
         # turn some rotations into parameterised gates
         gates, p = [], 0
         for g in c.gates:
@@ -73,7 +73,7 @@ def test_batched_mixed_widths(gpu, dtype, tile):
 
 def test_batched_errors_name_circuit(gpu):
     import torch
-    circs = [W.config0(n=5, ngates=10), W.Circuit(5, [W.Gate("X", 7)])]
+    circs = [W.random_gates_n12(n=5, ngates=10), W.Circuit(5, [W.Gate("X", 7)])]
     buf, views = _packed_states([5, 5], "c128")
     before = buf.clone()
     with pytest.raises(gpu.SvError) as e:
@@ -84,13 +84,13 @@ def test_batched_errors_name_circuit(gpu):
 
 
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
-def test_config4_full_sampled(gpu, dtype):
-    """config4: 4096 circuits, n uniform in 10..20, 100-400 gates each
+def test_uneven_batch_full_sampled(gpu, dtype):
+    """4096 circuits, n uniform in 10..20, 100-400 gates each
     (12.5 GB of complex128 states); a seeded sample checked against the
     oracle, every state's norm checked on the device."""
     import torch
-    circs = W.config4()
-    _say("config4", dtype, "states", sum(1 << c.n for c in circs) * (16 if dtype == "c128" else 8) / 2 ** 30, "GiB")
+    circs = W.uneven_batch()
+    _say("uneven batch", dtype, "states", sum(1 << c.n for c in circs) * (16 if dtype == "c128" else 8) / 2 ** 30, "GiB")
     buf, views = _packed_states([c.n for c in circs], dtype)
     torch.cuda.synchronize()
     gpu.sv_apply_circuits_batched(views, circs)
@@ -102,7 +102,7 @@ def test_config4_full_sampled(gpu, dtype):
     for i in sample + big:
         ref = oracle.run_circuit(circs[i])
         e = _err(views[i].cpu().numpy(), ref)
-        _say("config4 circuit", i, "n", circs[i].n, "err", e)
+        _say("uneven batch circuit", i, "n", circs[i].n, "err", e)
         assert e <= tol
     norms = torch.stack([v.abs().pow(2).sum() for v in views]).double()
     assert float((norms - 1).abs().max()) <= (1e-12 if dtype == "c128" else 1e-4)
@@ -138,12 +138,12 @@ def test_batched_adjoint_small(gpu):
         assert abs(back[0] - 1) <= 1e-12 and np.max(np.abs(back[1:])) <= 1e-12
 
 
-def test_config4_adjoint_full_sampled(gpu):
+def test_hea_batch_n16_full_sampled(gpu):
     """256 ansatz circuits at n=16, 4 layers (128 parameters each): batched
     forward and batched adjoint; gradients of a seeded sample against the
     oracle's parameter shift."""
     import torch
-    pairs = W.config4_adjoint()
+    pairs = W.hea_batch_n16()
     circs = [c for c, _ in pairs]
     hams = [h for _, h in pairs]
     buf, views = _packed_states([c.n for c in circs], "c128")
@@ -159,6 +159,6 @@ def test_config4_adjoint_full_sampled(gpu):
         which = sorted(rng.choice(c.nparams, size=3, replace=False).tolist())
         ref = oracle.grad_param_shift(c, c.params, h, which=which)
         got = g[ci * 128 + np.array(which)]
-        _say("config4 adjoint circuit", ci, "err", np.max(np.abs(got - ref)))
+        _say("hea batch circuit", ci, "err", np.max(np.abs(got - ref)))
         assert np.max(np.abs(got - ref)) <= 1e-8 * max(1, np.max(np.abs(ref)))
         assert abs(loss[ci].item() - oracle.loss(c, c.params, h)) <= 1e-10

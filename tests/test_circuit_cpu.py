@@ -92,7 +92,7 @@ def test_unfused_and_masked_keep_order(sv):
 
 
 def test_workload_plan_stats(sv):
-    for c, npar, max_passes in ((W.config0(), 0, 1), (W.config2(), 0, 1000), (W.config3()[0], 768, 650)):
+    for c, npar, max_passes in ((W.random_gates_n12(), 0, 1), (W.layered_circuit_n32(), 0, 1000), (W.hea_problem_n24()[0], 768, 650)):
         _, _, npasses = sv.sv_circuit_plan(c.n, c, nparams=npar, flags=sv.SV_FUSE)
         assert npasses <= max_passes, (c.meta, npasses)
 

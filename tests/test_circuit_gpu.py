@@ -1,6 +1,6 @@
 """GPU parity of the circuit path (sv_apply_circuit / sv_circuit_*) against
 the oracle: fused, unfused, masked and graph-replayed runs, device-resident
-angles, the paper's QFT and streaming circuits, and config2's layers."""
+angles, the paper's QFT and streaming circuits, and the layered circuit."""
 import numpy as np
 import pytest
 
@@ -52,8 +52,8 @@ FLAGS = {"fuse": 1, "plain": 0, "masked": 4, "fuse+graph": 3}
 
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
 @pytest.mark.parametrize("flags", list(FLAGS))
-def test_config0(gpu, dtype, flags):
-    c = W.config0()
+def test_random_gates_n12(gpu, dtype, flags):
+    c = W.random_gates_n12()
     ref = oracle.run_circuit(c)
     d = _dev_state(c.n, dtype)
     gpu.sv_init(d, 0)
@@ -66,7 +66,7 @@ def test_config0(gpu, dtype, flags):
     else:
         gpu.sv_apply_circuit(d, c, flags=FLAGS[flags])
     e = _err(d.cpu().numpy(), ref)
-    _say("config0", dtype, flags, e)
+    _say("random_gates_n12", dtype, flags, e)
     assert e <= TOL[dtype]
 
 
@@ -138,9 +138,9 @@ def test_qft_and_stream_closed_forms(gpu, n):
             assert _err(got, ref) <= 1e-12, (name, n, fl)
 
 
-def test_config2_layers_small(gpu):
-    """config2's construction at n=20 (all 20 layers) against the oracle."""
-    c = W.config2(n=20)
+def test_layered_circuit_small(gpu):
+    """The layered circuit's construction at n=20 (all 20 layers) against the oracle."""
+    c = W.layered_circuit_n32(n=20)
     ref = oracle.run_circuit(c)
     for fl in (1, 0):
         d = _dev_state(c.n, "c128")

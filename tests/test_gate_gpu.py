@@ -180,10 +180,10 @@ def test_edge_cases(gpu):
 
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
 @pytest.mark.parametrize("mode", ["auto", "masked"])
-def test_config0_circuit_gate_by_gate(gpu, dtype, mode):
-    """config0: n=12, 200 gates, |0..0>, applied gate by gate."""
+def test_random_gates_n12_gate_by_gate(gpu, dtype, mode):
+    """n=12 random controlled gates:, 200 gates, |0..0>, applied gate by gate."""
     import torch
-    c = W.config0()
+    c = W.random_gates_n12()
     ref = oracle.run_circuit(c)
     d = torch.zeros(1 << c.n, dtype=torch.complex128 if dtype == "c128" else torch.complex64, device="cuda")
     gpu.sv_init(d, 0)
@@ -191,7 +191,7 @@ def test_config0_circuit_gate_by_gate(gpu, dtype, mode):
         U = _matrix_via_library_conventions(g)
         gpu.sv_apply_gate(d, g.target, g.controls, None, U, mode=mode)
     err = _rel_err(d.cpu().numpy(), ref)
-    _say("config0", dtype, mode, "rel err", err)
+    _say("random_gates_n12", dtype, mode, "rel err", err)
     assert err <= TOL[dtype]
 
 

@@ -41,16 +41,16 @@ def _samples(n, t, ctrls, rng):
     return np.unique(np.concatenate(idx))
 
 
-def test_config1_sweep_sampled(gpu, big):
+def test_gate_sweep_sampled(gpu, big):
     import torch
     n, psi, d_in = big
-    U = oracle.gate_matrix("U", matrix=W.config1_gate())
-    Ulib = np.asarray(W.config1_gate(), dtype=np.float64)
+    U = oracle.gate_matrix("U", matrix=W.sweep_unitary())
+    Ulib = np.asarray(W.sweep_unitary(), dtype=np.float64)
     rng = np.random.default_rng(99)
     work = torch.empty_like(d_in)
     ref_full = torch.empty_like(d_in)
     worst = 0.0
-    for t, ctrls in W.config1_cases(n):
+    for t, ctrls in W.gate_sweep_cases(n):
         idx = _samples(n, t, ctrls, rng)
         exp = oracle.gate_amplitudes(psi, n, t, ctrls, (), U, idx)
         tidx = torch.from_numpy(idx.astype(np.int64)).cuda()
@@ -63,7 +63,7 @@ def test_config1_sweep_sampled(gpu, big):
             except gpu.SvError:
                 pass
         for mode in modes:
-            _say("config1 n=28 t=%d c=%d mode=%s" % (t, len(ctrls), mode))
+            _say("sweep n=28 t=%d c=%d mode=%s" % (t, len(ctrls), mode))
             work.copy_(d_in)
             gpu.sv_apply_gate(work, t, ctrls, None, Ulib, mode=mode)
             got = work.index_select(0, tidx).cpu().numpy()
@@ -78,21 +78,21 @@ def test_config1_sweep_sampled(gpu, big):
                 ref_full.copy_(work)
             else:
                 assert torch.equal(work.view(torch.float64), ref_full.view(torch.float64)), (t, ctrls, mode)
-    _say("config1 worst rel err", worst)
+    _say("sweep worst rel err", worst)
 
 
-def test_config1_c64_sampled(gpu, big):
+def test_gate_sweep_c64_sampled(gpu, big):
     """complex64 variant of the sweep at n=28, error against the fp64 oracle."""
     import torch
     n, psi, d_in = big
-    U = oracle.gate_matrix("U", matrix=W.config1_gate())
-    Ulib = np.asarray(W.config1_gate(), dtype=np.float64)
+    U = oracle.gate_matrix("U", matrix=W.sweep_unitary())
+    Ulib = np.asarray(W.sweep_unitary(), dtype=np.float64)
     rng = np.random.default_rng(98)
     d64 = d_in.to(torch.complex64)
     work = torch.empty_like(d64)
     psi32 = psi.astype(np.complex64).astype(np.complex128)  # the input the c64 path actually sees
     worst = 0.0
-    for t, ctrls in W.config1_cases(n)[::4]:
+    for t, ctrls in W.gate_sweep_cases(n)[::4]:
         idx = _samples(n, t, ctrls, rng)
         exp = oracle.gate_amplitudes(psi32, n, t, ctrls, (), U, idx)
         tidx = torch.from_numpy(idx.astype(np.int64)).cuda()
@@ -103,5 +103,5 @@ def test_config1_c64_sampled(gpu, big):
             err = float(np.max(np.abs(got - exp)) / np.max(np.abs(exp)))
             worst = max(worst, err)
             assert err <= 1e-5, (t, ctrls, mode, err)
-    _say("config1 c64 worst rel err vs fp64 oracle", worst)
+    _say("sweep c64 worst rel err vs fp64 oracle", worst)
     del d64, work

@@ -210,9 +210,9 @@ def test_dense_kron_random_gates(n):
         assert np.max(np.abs(got - ref)) < 1e-14
 
 
-def test_dense_kron_config0_small():
-    """A config-0 style circuit at n=8 against the product of dense gates."""
-    c = W.config0(seed=11, n=8, ngates=60)
+def test_dense_kron_random_gates_small():
+    """A random controlled-gate circuit at n=8 against the product of dense gates."""
+    c = W.random_gates_n12(seed=11, n=8, ngates=60)
     got = oracle.run_circuit(c)
     psi = np.zeros(1 << c.n, dtype=np.complex128); psi[0] = 1
     for g in c.gates:
@@ -362,18 +362,18 @@ def test_param_shift_shared_parameter():
 # ---------------------------------------------------------------- generators
 
 def test_generators_deterministic_and_shaped():
-    a, b = W.config0(), W.config0()
+    a, b = W.random_gates_n12(), W.random_gates_n12()
     assert a.gates == b.gates and len(a.gates) == 200 and a.n == 12
     kinds = {g.kind for g in a.gates}
     assert kinds <= {"X", "H", "RY", "RZ"}
     assert all(len(g.controls) <= 3 and g.target not in g.controls for g in a.gates)
-    cases = W.config1_cases()
+    cases = W.gate_sweep_cases()
     assert len(cases) == 27
     for t, ctrls in cases:
         assert t not in ctrls and len(set(ctrls)) == len(ctrls)
-    c3, H = W.config3()
+    c3, H = W.hea_problem_n24()
     assert c3.nparams == 768 and len(c3.gates) == 16 * (48 + 23) and len(H) == 23 + 24
-    c2 = W.config2()
+    c2 = W.layered_circuit_n32()
     assert len(c2.gates) == 20 * (32 + 31 + 8)
     U = oracle.gate_matrix("U", matrix=W.haar_unitary_2x2(2))
     assert np.allclose(U @ U.conj().T, np.eye(2), atol=1e-15)

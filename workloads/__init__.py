@@ -13,15 +13,15 @@ two-qubit circuit figure in Sec. I motivates value 0).
 
 Workloads (all seeded, all synthetic):
 
-* ``config0``   n=12, 200 gates from {X, H, RY, RZ}, 0-3 controls.
-* ``config1``   n=28 random normalised state, one Haar 2x2, target in
+* ``random_gates_n12``  n=12, 200 gates from {X, H, RY, RZ}, 0-3 controls.
+* ``gate_sweep_*``     n=28 random normalised state, one Haar 2x2, target in
   {0, 13, 27}, c = 0..8 controls on random distinct qubits.
-* ``config2``   n=32, 20 layers of (H or RY on every qubit, CNOT ladder,
+* ``layered_circuit_n32`` n=32, 20 layers of (H or RY on every qubit, CNOT ladder,
   8 multi-controlled X with 1-6 controls).
-* ``config3``   n=24 hardware-efficient ansatz, 16 layers of RY, RZ on every
+* ``hea_problem_n24``  n=24 hardware-efficient ansatz, 16 layers of RY, RZ on every
   qubit plus a CNOT chain (768 parameters); H = sum a_i Z_i Z_{i+1} + b_i X_i.
-* ``config4``   4096 circuits with n uniform in 10..20 and 100-400 gates as in
-  config0; plus 256 ansatz circuits at n=16 with 4 layers for batched
+* ``uneven_batch``     4096 circuits with n uniform in 10..20 and 100-400 gates as in
+  random_gates_n12; plus 256 ansatz circuits at n=16 with 4 layers for batched
   gradients.
 * the paper's own evaluation circuits: the QFT staircase (Sec. IV-A figure)
   and the streaming circuit (Sec. IV-C figure).
@@ -112,7 +112,7 @@ def haar_unitary_2x2(seed: int) -> Tuple[float, ...]:
 
 def _random_controlled_gates(rng: np.random.Generator, n: int, ngates: int,
                              max_controls: int = 3) -> List[Gate]:
-    """Config-0 style gates.  Per gate the draw order is fixed: kind, then the
+    """Random controlled gates.  Per gate the draw order is fixed: kind, then the
     angle (RY/RZ only), target, number of controls, controls."""
     kinds = ("X", "H", "RY", "RZ")
     out = []
@@ -131,19 +131,19 @@ def _random_controlled_gates(rng: np.random.Generator, n: int, ngates: int,
 # the five workloads
 # --------------------------------------------------------------------------
 
-def config0(seed: int = 0, n: int = 12, ngates: int = 200) -> Circuit:
+def random_gates_n12(seed: int = 0, n: int = 12, ngates: int = 200) -> Circuit:
     rng = np.random.default_rng(seed)
     return Circuit(n, _random_controlled_gates(rng, n, ngates),
-                   meta={"name": "config0", "seed": seed})
+                   meta={"name": "random_gates_n12", "seed": seed})
 
 
-CONFIG1_TARGETS = (0, 13, 27)
-CONFIG1_CONTROLS = tuple(range(0, 9))
+SWEEP_TARGETS = (0, 13, 27)
+SWEEP_CONTROLS = tuple(range(0, 9))
 
 
-def config1_cases(n: int = 28, seed: int = 3,
-                  targets: Sequence[int] = CONFIG1_TARGETS,
-                  counts: Sequence[int] = CONFIG1_CONTROLS):
+def gate_sweep_cases(n: int = 28, seed: int = 3,
+                  targets: Sequence[int] = SWEEP_TARGETS,
+                  counts: Sequence[int] = SWEEP_CONTROLS):
     """(target, controls) for every target and control count, controls drawn
     as random distinct qubits other than the target.  Draw order: for each
     target in order, for each count in order, the controls."""
@@ -157,11 +157,11 @@ def config1_cases(n: int = 28, seed: int = 3,
     return cases
 
 
-def config1_gate(seed: int = 2) -> Tuple[float, ...]:
+def sweep_unitary(seed: int = 2) -> Tuple[float, ...]:
     return haar_unitary_2x2(seed)
 
 
-def config2(seed: int = 4, n: int = 32, layers: int = 20, mcx_per_layer: int = 8,
+def layered_circuit_n32(seed: int = 4, n: int = 32, layers: int = 20, mcx_per_layer: int = 8,
             mcx_controls: Tuple[int, int] = (1, 6)) -> Circuit:
     """Per layer: H or RY(theta) (fair coin per qubit) on every qubit, a CNOT
     ladder (control i, target i+1), then multi-controlled X gates with a
@@ -182,7 +182,7 @@ def config2(seed: int = 4, n: int = 32, layers: int = 20, mcx_per_layer: int = 8
             others = [q for q in range(n) if q != t]
             ctrls = tuple(int(q) for q in rng.choice(others, size=nc, replace=False))
             gates.append(Gate("X", t, ctrls))
-    return Circuit(n, gates, meta={"name": "config2", "seed": seed})
+    return Circuit(n, gates, meta={"name": "layered_n32", "seed": seed})
 
 
 def hea(n: int, layers: int, seed: int) -> Circuit:
@@ -213,15 +213,15 @@ def zz_x_hamiltonian(n: int, seed: int) -> List[PauliTerm]:
     return terms
 
 
-def config3(seed: int = 5, n: int = 24, layers: int = 16):
+def hea_problem_n24(seed: int = 5, n: int = 24, layers: int = 16):
     c = hea(n, layers, seed)
-    c.meta["name"] = "config3"
+    c.meta["name"] = "hea_n24"
     return c, zz_x_hamiltonian(n, seed)
 
 
-def config4(seed: int = 6, ncirc: int = 4096, nrange=(10, 20), grange=(100, 400)) -> List[Circuit]:
+def uneven_batch(seed: int = 6, ncirc: int = 4096, nrange=(10, 20), grange=(100, 400)) -> List[Circuit]:
     """Independent circuits of uneven width; per circuit draw n, then the gate
-    count, then the gates as in config0."""
+    count, then the gates as in random_gates_n12."""
     rng = np.random.default_rng(seed)
     out = []
     for i in range(ncirc):
@@ -231,8 +231,8 @@ def config4(seed: int = 6, ncirc: int = 4096, nrange=(10, 20), grange=(100, 400)
     return out
 
 
-def config4_adjoint(seed: int = 7, ncirc: int = 256, n: int = 16, layers: int = 4):
-    """Batched-gradient workload: the config-3 ansatz at n=16 with 4 layers
+def hea_batch_n16(seed: int = 7, ncirc: int = 256, n: int = 16, layers: int = 4):
+    """Batched-gradient workload: the n=24 problem's ansatz at n=16 with 4 layers
     (128 parameters) per circuit, each circuit with its own angles and its own
     ZZ+X Hamiltonian."""
     out = []
