@@ -25,7 +25,7 @@ namespace sv {
 
 int validate_circuit_gate(int n, int nparams, const sv_gate_t &g, int index);
 int circuit_plan_capped(int n, int dtype, const sv_gate_t *gates, int ngates, int nparams, int flags, int m_cap,
-                        int32_t *order, int32_t *pass_of, int64_t *npasses, int *m_used);
+                        int32_t *order, int32_t *pass_of, int64_t *npasses, int *m_used, bool general);
 
 constexpr int kBatchThreads = 512;
 constexpr size_t kBatchLds = 65536;
@@ -361,7 +361,7 @@ static int build_batch(const sv_state_t *states, const sv_state_t *lams, int nci
                 int64_t np = 0;
                 int m_used = 0;
                 r = circuit_plan_capped(s.n, *dtype, gates + g0, bc.ngates, (int)(p1 - p0), SV_FUSE, m_cap,
-                                        ord.data(), pas.data(), &np, &m_used);
+                                        ord.data(), pas.data(), &np, &m_used, false);
                 if (r != SV_OK)
                     return fail(r, "circuit %d: %s", c, sv_last_error());
                 if (m_used != bc.m)

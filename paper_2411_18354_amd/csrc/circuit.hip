@@ -31,6 +31,7 @@ struct Pass {
     int gate;        // single: gate index
     int first, count;  // fused: descriptors [first, first + count)
     GatePlan plan;   // single
+    TileMap tm;      // fused: which qubits a tile spans
 };
 
 __global__ void k_param_mats(const ParamJob *__restrict__ jobs, int njobs, const double *__restrict__ params,
@@ -94,6 +95,7 @@ using namespace sv;
 struct sv_circuit {
     int n = 0, dtype = 0, flags = 0, nparams = 0, device = 0, m = 0;
     int m_cap = 64;  // upper bound on the tile width (callers with a fixed LDS budget)
+    bool general_tiles = true;  // tiles over any qubit set; false: contiguous tiles only
     std::vector<sv_gate_t> gates;
     std::vector<Pass> passes;
     int njobs = 0;
@@ -112,6 +114,24 @@ struct sv_circuit {
 
 namespace sv {
 
+// Diagonal for this gate's actual matrix (named diagonal kinds, or a
+// fixed matrix with both off-diagonal entries exactly zero).
+static bool gate_is_diagonal(const sv_gate_t &g, const double *mat) {
+    if (gate_kind_diagonal(g.kind))
+        return true;
+    if (g.param >= 0)
+        return false;
+    return mat[2] == 0.0 && mat[3] == 0.0 && mat[4] == 0.0 && mat[5] == 0.0;
+}
+
+// Greedy fusion planner.
+//  general: a run's tile spans the `a` lowest qubits plus up to m - a other
+//    qubits picked as targets appear, and diagonal gates join any run;
+//  otherwise (contiguous tiles) a gate joins when its target is below m.
+// A gate that cannot join the open run is deferred; later gates may still
+// join the run ahead of the deferred ones only if they commute with all of
+// them.  When the run closes, the deferred gates start the next run, so the
+// relative order of non-commuting gates is never changed.
 static int plan_circuit(sv_circuit *c, std::vector<TileGate> &tiles, std::vector<ParamJob> &jobs,
                         std::vector<double> &mats) {
     const int G = (int)c->gates.size();
@@ -121,11 +141,18 @@ static int plan_circuit(sv_circuit *c, std::vector<TileGate> &tiles, std::vector
         if (g.param < 0)
             gate_matrix(g.kind, g.theta, g.U, &mats[(size_t)8 * i]);
     }
+    const int di = c->dtype == SV_C128 ? 0 : 1;
     const bool masked = c->flags & SV_MASKED;
     const bool fuse = (c->flags & SV_FUSE) && !masked;
-    c->m = std::min(std::min(tuning().tile_log2[c->dtype == SV_C128 ? 0 : 1], c->n), c->m_cap);
+    c->m = std::min(std::min(tuning().tile_log2[di], c->n), c->m_cap);
+    const int m = c->m;
+    // the tile holds the a lowest qubits plus at most kTileMaxHigh others
+    const int a = c->general_tiles ? std::max(std::min(tuning().tile_low_bits[di], m), m - kTileMaxHigh) : m;
     const int min_run = std::max(1, tuning().fuse_min_gates);
     std::vector<int> tile_slot(G, -1);
+    std::vector<char> diag(G, 0);
+    for (int i = 0; i < G; ++i)
+        diag[i] = c->general_tiles && gate_is_diagonal(c->gates[i], &mats[(size_t)8 * i]);
 
     auto single = [&](int i) -> int {
         Pass p;
@@ -138,58 +165,82 @@ static int plan_circuit(sv_circuit *c, std::vector<TileGate> &tiles, std::vector
         c->passes.push_back(p);
         return SV_OK;
     };
-    std::vector<int> run, deferred;
-    auto flush = [&]() -> int {
-        if ((int)run.size() >= min_run) {
-            Pass p;
-            p.fused = true;
-            p.gate = -1;
-            p.first = (int)tiles.size();
-            p.count = (int)run.size();
-            for (int i : run) {
-                const sv_gate_t &g = c->gates[i];
-                tile_slot[i] = (int)tiles.size();
-                tiles.push_back(make_tile_gate(c->m, g.target, g.ctrl_mask, g.ctrl_vals, &mats[(size_t)8 * i]));
-                tiles.back().src_gate = i;
-            }
-            c->passes.push_back(p);
-            c->fused_gates += (int64_t)run.size();
-            c->fused_runs++;
-        } else {
-            for (int i : run)
-                SV_TRY(single(i));
-        }
-        for (int i : deferred)
+    if (!fuse) {
+        for (int i = 0; i < G; ++i)
             SV_TRY(single(i));
-        run.clear();
-        deferred.clear();
-        return SV_OK;
-    };
-    for (int i = 0; i < G; ++i) {
-        const sv_gate_t &g = c->gates[i];
-        if (!fuse) {
-            SV_TRY(single(i));
-            continue;
-        }
-        if (g.target < c->m) {
-            bool ok = true;
-            for (int d : deferred)
-                if (!commute(g, c->gates[d])) {
-                    ok = false;
-                    break;
+    } else {
+        std::vector<int> stream(G);
+        for (int i = 0; i < G; ++i)
+            stream[i] = i;
+        std::vector<int> run, deferred, high;
+        size_t pos = 0;
+        while (pos < stream.size()) {
+            run.clear();
+            deferred.clear();
+            high.clear();
+            size_t i = pos;
+            for (; i < stream.size(); ++i) {
+                const int gi = stream[i];
+                const sv_gate_t &g = c->gates[gi];
+                bool fits = diag[gi] || g.target < a ||
+                            std::find(high.begin(), high.end(), g.target) != high.end();
+                const bool can_add_high = !fits && (int)high.size() < m - a;
+                bool free = true;
+                for (int d : deferred)
+                    if (!commute(g, c->gates[d])) {
+                        free = false;
+                        break;
+                    }
+                if ((fits || can_add_high) && free) {
+                    if (!fits)
+                        high.push_back(g.target);
+                    run.push_back(gi);
+                } else if (run.empty()) {
+                    // nothing is open (so nothing is deferred): a gate that
+                    // cannot start a run is a pass of its own
+                    SV_TRY(single(gi));
+                } else {
+                    deferred.push_back(gi);
+                    if (deferred.size() > 64) {
+                        ++i;
+                        break;
+                    }
                 }
-            if (!ok)
-                SV_TRY(flush());
-            run.push_back(i);
-        } else if (run.empty()) {
-            SV_TRY(single(i));
-        } else {
-            deferred.push_back(i);
-            if (deferred.size() > 64)
-                SV_TRY(flush());
+            }
+            if ((int)run.size() >= min_run) {
+                // fill the tile's qubit set up to m, preferring the lowest free qubits
+                std::sort(high.begin(), high.end());
+                for (int q = a; (int)high.size() < m - a && q < c->n; ++q)
+                    if (std::find(high.begin(), high.end(), q) == high.end())
+                        high.push_back(q);
+                std::sort(high.begin(), high.end());
+                Pass p;
+                p.fused = true;
+                p.gate = -1;
+                p.first = (int)tiles.size();
+                p.count = (int)run.size();
+                p.tm = make_tile_map(c->n, m, a, high);
+                for (int gi : run) {
+                    const sv_gate_t &g = c->gates[gi];
+                    tile_slot[gi] = (int)tiles.size();
+                    tiles.push_back(
+                        make_tile_gate(p.tm, g.target, g.ctrl_mask, g.ctrl_vals, &mats[(size_t)8 * gi], diag[gi]));
+                    tiles.back().src_gate = gi;
+                }
+                c->passes.push_back(p);
+                c->fused_gates += (int64_t)run.size();
+                c->fused_runs++;
+            } else {
+                for (int gi : run)
+                    SV_TRY(single(gi));
+            }
+            // the deferred gates, then the unscanned rest, form the next stream
+            std::vector<int> next(deferred);
+            next.insert(next.end(), stream.begin() + (long)i, stream.end());
+            stream.swap(next);
+            pos = 0;
         }
     }
-    SV_TRY(flush());
     for (int i = 0; i < G; ++i) {
         const sv_gate_t &g = c->gates[i];
         if (g.param >= 0)
@@ -292,7 +343,7 @@ template <typename R> static int enqueue(sv_circuit *c, cplx_t<R> *psi, const do
     for (const Pass &p : c->passes) {
         if (p.fused) {
             DeviceGates dg{c->d_tiles + p.first, p.count};
-            hipLaunchKernelGGL((k_tile<R, 512, DeviceGates>), dim3((unsigned)ntiles), dim3(512), lds, st, psi, c->m,
+            hipLaunchKernelGGL((k_tile<R, 512, DeviceGates>), dim3((unsigned)ntiles), dim3(512), lds, st, psi, p.tm,
                                dg);
             SV_LAUNCH_CHECK();
         } else {
@@ -355,7 +406,7 @@ static int run_graph(sv_circuit *c, const sv_state_t *s, const double *params, h
 }
 
 int circuit_plan_capped(int n, int dtype, const sv_gate_t *gates, int ngates, int nparams, int flags, int m_cap,
-                        int32_t *order, int32_t *pass_of, int64_t *npasses, int *m_used);
+                        int32_t *order, int32_t *pass_of, int64_t *npasses, int *m_used, bool general);
 
 } // namespace sv
 
@@ -376,7 +427,7 @@ int sv_gate_matrix(int kind, double theta, const double *U, double *out) {
 int sv_circuit_plan(int n, int dtype, const sv_gate_t *gates, int ngates, int nparams, int flags, int32_t *order,
                     int32_t *pass_of, int64_t *npasses) {
     clear_error();
-    return circuit_plan_capped(n, dtype, gates, ngates, nparams, flags, 64, order, pass_of, npasses, nullptr);
+    return circuit_plan_capped(n, dtype, gates, ngates, nparams, flags, 64, order, pass_of, npasses, nullptr, true);
 }
 
 } // extern "C"
@@ -384,7 +435,7 @@ int sv_circuit_plan(int n, int dtype, const sv_gate_t *gates, int ngates, int np
 namespace sv {
 
 int circuit_plan_capped(int n, int dtype, const sv_gate_t *gates, int ngates, int nparams, int flags, int m_cap,
-                        int32_t *order, int32_t *pass_of, int64_t *npasses, int *m_used) {
+                        int32_t *order, int32_t *pass_of, int64_t *npasses, int *m_used, bool general) {
     if (dtype != SV_C128 && dtype != SV_C64)
         return fail(SV_EINVAL, "unknown dtype %d", dtype);
     if (n < 1 || n > max_qubits(dtype))
@@ -401,6 +452,7 @@ int circuit_plan_capped(int n, int dtype, const sv_gate_t *gates, int ngates, in
     c.flags = flags;
     c.nparams = nparams;
     c.m_cap = m_cap;
+    c.general_tiles = general;
     c.gates.assign(gates, gates + ngates);
     std::vector<TileGate> tiles;
     std::vector<ParamJob> jobs;

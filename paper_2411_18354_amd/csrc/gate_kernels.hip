@@ -121,31 +121,80 @@ __global__ __launch_bounds__(kThreads) void k_wave(cplx_t<R> *__restrict__ psi, 
 // host side
 // ---------------------------------------------------------------------------
 
-TileGate make_tile_gate(int m, int target, uint64_t cmask, uint64_t cvals, const double *U) {
+TileMap make_tile_map(int n, int m, int a, const std::vector<int> &high) {
+    TileMap tm;
+    memset(&tm, 0, sizeof(tm));
+    tm.m = (uint32_t)m;
+    tm.a = (uint32_t)a;
+    tm.nh = (uint32_t)high.size();
+    std::vector<int> S, zeros;
+    for (int q = 0; q < a; ++q)
+        S.push_back(q);
+    for (size_t i = 0; i < high.size(); ++i) {
+        tm.hpos[i] = (uint32_t)high[i];
+        S.push_back(high[i]);
+    }
+    zeros.assign(S.size(), 0);
+    tm.outer = make_expand(n, S, zeros);  // tile index deposited outside S
+    return tm;
+}
+
+TileMap contiguous_tile_map(int n, int m) { return make_tile_map(n, m, m, {}); }
+
+// Tile-local bit of global qubit q, or -1 when q is outside S.
+static int local_bit(const TileMap &tm, int q) {
+    if (q < (int)tm.a)
+        return q;
+    for (uint32_t i = 0; i < tm.nh; ++i)
+        if ((int)tm.hpos[i] == q)
+            return (int)tm.a + (int)i;
+    return -1;
+}
+
+TileGate make_tile_gate(const TileMap &tm, int target, uint64_t cmask, uint64_t cvals, const double *U,
+                        bool diagonal) {
     TileGate g;
     memset(&g, 0, sizeof(g));
     for (int i = 0; i < 8; ++i)
         g.m[i] = U[i];
-    g.target = (uint32_t)target;
-    const uint64_t lowm = (m >= 64) ? ~0ull : ((1ull << m) - 1);
-    const uint64_t lo_c = cmask & lowm;
-    g.hi_mask = cmask & ~lowm;
-    g.hi_vals = cvals & ~lowm;
-    std::vector<int> pos, bits;
-    const uint64_t all = lo_c | (1ull << target);
-    for (int q = 0; q < m; ++q)
-        if (all & (1ull << q)) {
-            pos.push_back(q);
-            bits.push_back(q == target ? 0 : (int)((cvals >> q) & 1));
+    if (diagonal) {
+        g.diag = 1;
+        g.target = (uint32_t)target;
+        g.hi_mask = cmask;
+        g.hi_vals = cvals;
+        return g;
+    }
+    const int tl = local_bit(tm, target);
+    g.target = (uint32_t)tl;
+    std::vector<std::pair<int, int>> loc;  // (local position, required bit)
+    loc.push_back({tl, 0});
+    int in_tile = 0;
+    for (int q = 0; q < 64; ++q) {
+        if (!(cmask & (1ull << q)))
+            continue;
+        const int lq = local_bit(tm, q);
+        if (lq >= 0) {
+            loc.push_back({lq, (int)((cvals >> q) & 1)});
+            ++in_tile;
+        } else {
+            g.hi_mask |= 1ull << q;
+            g.hi_vals |= cvals & (1ull << q);
         }
-    const Expand e = make_expand(m, pos, bits);
+    }
+    std::sort(loc.begin(), loc.end());
+    std::vector<int> pos, bits;
+    for (auto &pb : loc) {
+        pos.push_back(pb.first);
+        bits.push_back(pb.second);
+    }
+    const Expand e = make_expand((int)tm.m, pos, bits);
     g.nseg = e.nseg;
     for (uint32_t s = 0; s < e.nseg; ++s) {
         g.shift[s] = e.shift[s];
         g.mask[s] = (uint32_t)e.mask[s];
     }
     g.fixed = (uint32_t)e.fixed;
-    g.npairs = 1u << (m - 1 - popcount64(lo_c));
+    g.npairs = 1u << ((int)tm.m - 1 - in_tile);
     return g;
 }
 
@@ -313,14 +362,15 @@ template int launch_plan<float, MatPtr<float>>(float2 *, const GatePlan &, const
 template <typename R>
 static int launch_tile1(const sv_state_t *s, const GateSpec &g, const double *U, hipStream_t st) {
     const int m = std::min(tile_log2(s->dtype), g.n);
+    const TileMap tm = contiguous_tile_map(g.n, m);
     InlineGates<1> gs;
-    gs.g[0] = make_tile_gate(m, g.target, g.cmask, g.cvals, U);
+    gs.g[0] = make_tile_gate(tm, g.target, g.cmask, g.cvals, U, false);
     gs.count = 1;
     const size_t lds = ((size_t)1 << m) * sizeof(cplx_t<R>);
     auto fn = k_tile<R, 512, InlineGates<1>>;
     SV_TRY(set_lds_limit<R>((const void *)fn, lds));
     const uint64_t tiles = 1ull << (g.n - m);
-    hipLaunchKernelGGL(fn, dim3((unsigned)tiles), dim3(512), lds, st, reinterpret_cast<cplx_t<R> *>(s->data), m,
+    hipLaunchKernelGGL(fn, dim3((unsigned)tiles), dim3(512), lds, st, reinterpret_cast<cplx_t<R> *>(s->data), tm,
                        gs);
     SV_LAUNCH_CHECK();
     return SV_OK;

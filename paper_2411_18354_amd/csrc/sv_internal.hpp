@@ -135,6 +135,7 @@ struct Tuning {
     int low_policy;       // 0: failing pairs skipped, 1: rewritten unchanged
     int wave_auto;        // SV_MODE_AUTO may pick the wavefront kernel
     int tile_log2[2];     // fused-pass tile width (amplitudes = 2^m)
+    int tile_low_bits[2]; // lowest qubits always inside a fused tile (contiguous runs)
     int fuse_min_gates;   // shortest run worth an LDS pass
 };
 Tuning &tuning();

@@ -16,7 +16,9 @@ Tuning &tuning() {
     //  - the wavefront kernel is the faster scheduled kernel whenever the
     //    target is among the 6 lowest free index bits;
     //  - 64 KiB LDS tiles for the fused pass.
-    static Tuning t = {{3, 4}, 1, 1, {12, 13}, 2};
+    //  - fused tiles always hold the 6 (complex128) / 7 (complex64) lowest
+    //    qubits, i.e. 1 KiB contiguous runs, plus qubits picked per run.
+    static Tuning t = {{3, 4}, 1, 1, {12, 13}, {6, 7}, 2};
     return t;
 }
 
@@ -35,6 +37,8 @@ static int find_key(const char *name, Key *out) {
         {"wave_auto", &t.wave_auto, 0, 1},
         {"tile_log2_c128", &t.tile_log2[0], 6, 13},
         {"tile_log2_c64", &t.tile_log2[1], 6, 14},
+        {"tile_low_bits_c128", &t.tile_low_bits[0], 1, 13},
+        {"tile_low_bits_c64", &t.tile_low_bits[1], 1, 14},
         {"fuse_min_gates", &t.fuse_min_gates, 1, 1 << 20},
     };
     for (const Key &k : keys)

@@ -159,3 +159,45 @@ def test_invalid_circuit_leaves_state(gpu):
         gpu.sv_apply_circuit(d, bad)
     torch.cuda.synchronize()
     assert torch.equal(d, before)
+
+
+@pytest.mark.parametrize("low", [2, 4, 6])
+def test_qubit_set_tiles(gpu, low):
+    """Fused tiles over the `low` lowest qubits plus planner-chosen ones (small
+    tiles force many high qubits per run); random gates of every kind, device
+    angles, against the oracle."""
+    import torch
+    gpu.sv_tune_set("tile_log2_c128", 8)
+    gpu.sv_tune_set("tile_low_bits_c128", low)
+    try:
+        for n, seed in ((9, 1), (14, 2), (16, 3)):
+            c = _rand_circuit(n, 300, 400 + seed, nparams=6)
+            psi0 = W.random_state(n, seed)
+            ref = oracle.run_circuit(c, c.params, psi0)
+            params = torch.from_numpy(c.params).cuda()
+            circ = gpu.Circuit(n, c, nparams=6, flags=gpu.SV_FUSE)
+            info = circ.info()
+            d = _dev_state(n, "c128", psi0)
+            circ.run(d, params)
+            circ.close()
+            assert _err(d.cpu().numpy(), ref) <= 1e-12, (n, low, info)
+            assert info["passes"] < len(c.gates) // 3, info
+    finally:
+        gpu.sv_tune_set("tile_log2_c128", 12)
+        gpu.sv_tune_set("tile_low_bits_c128", 6)
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_qft_fused_large(gpu, dtype):
+    """QFT at n=20 (a handful of fused passes over qubit-set tiles) against
+    its closed form."""
+    n, N = 20, 1 << 20
+    psi0 = W.random_state(n, 9)
+    d = _dev_state(n, dtype, psi0)
+    circ = gpu.Circuit(n, W.qft(n), dtype=0 if dtype == "c128" else 1, flags=gpu.SV_FUSE)
+    assert circ.info()["passes"] <= 4
+    circ.run(d)
+    rev = np.array([int(format(x, "020b")[::-1], 2) for x in range(N)])
+    ref = np.fft.ifft(psi0[rev]) * np.sqrt(N)
+    assert _err(d.cpu().numpy(), ref) <= TOL[dtype]
+    circ.close()
