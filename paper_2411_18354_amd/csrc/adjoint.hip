@@ -17,27 +17,13 @@
 #include <algorithm>
 #include <cstring>
 
+#include "circuit.hpp"
 #include "gates.hpp"
 #include "pauli.hpp"
 
 namespace sv {
 
 int validate_circuit_gate(int n, int nparams, const sv_gate_t &g, int index);
-
-struct AdjJob {
-    int32_t kind;   // kind of the inverse gate
-    int32_t param;
-    int32_t gate;
-};
-
-__global__ void k_adj_mats(const AdjJob *__restrict__ jobs, int njobs, const double *__restrict__ params,
-                           double *__restrict__ udag) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= njobs)
-        return;
-    const AdjJob j = jobs[i];
-    gate_matrix(j.kind, params[j.param], nullptr, udag + (size_t)8 * j.gate);
-}
 
 // One gate of the reverse sweep on the pairs of a scheduled plan (pair index
 // p1 = expand(i), partner p1 | 2^t; tmask/tvals as in the pair kernel).
@@ -84,6 +70,114 @@ __global__ __launch_bounds__(kRedThreads) void k_adj(cplx_t<R> *__restrict__ psi
         const double s = block_sum(acc, scratch);
         if (threadIdx.x == 0)
             partial[blockIdx.x] = s;
+    }
+}
+
+// A fused run of the reverse sweep on one tile of psi and one of lambda held
+// together in LDS (tile layout and operation kinds as in the forward tile
+// pass).  Operation i un-applies its gate (the descriptor holds U^dag); when
+// gslot[i] >= 0 its gradient term 2 Re <lambda|Pi_c A|psi> is taken first
+// and added, in tile order, to this workgroup's partial of that slot.
+constexpr int kAdjTileThreads = 512;
+
+template <typename R>
+__global__ __launch_bounds__(kAdjTileThreads) void k_adj_tile(cplx_t<R> *__restrict__ psi, cplx_t<R> *__restrict__ lam,
+                                                              TileMap tm, DeviceGates gates,
+                                                              const int32_t *__restrict__ gslot,
+                                                              const double *__restrict__ gens,
+                                                              double *__restrict__ partials) {
+    extern __shared__ unsigned char lds_raw[];
+    const uint32_t T = 1u << tm.m;
+    cplx_t<R> *tp = reinterpret_cast<cplx_t<R> *>(lds_raw);
+    cplx_t<R> *tl = tp + T;
+    __shared__ double scratch[kAdjTileThreads / 64];
+    if (threadIdx.x == 0)
+        for (int i = 0; i < gates.size(); ++i)
+            if (gslot[i] >= 0)
+                partials[(size_t)gslot[i] * kMaxPartials + blockIdx.x] = 0.0;
+    for (uint64_t t = blockIdx.x; t < tm.ntiles; t += gridDim.x) {
+        const uint64_t base = expand_index<uint64_t>(tm.outer, t);
+        bool any = false;
+        for (int i = 0; i < gates.size(); ++i) {
+            const TileGate &g = gates.get(i);
+            any |= g.diag ? true : ((base & g.hi_mask) == g.hi_vals);
+        }
+        if (!any)
+            continue;  // uniform
+        for (uint32_t j = threadIdx.x; j < T; j += kAdjTileThreads) {
+            const uint64_t k = base | tile_offset(tm, j);
+            tp[j] = ld_stream<R>(psi + k);
+            tl[j] = ld_stream<R>(lam + k);
+        }
+        __syncthreads();
+        for (int i = 0; i < gates.size(); ++i) {
+            const TileGate &g = gates.get(i);
+            const int sl = gslot[i];
+            double a[8];
+            for (int q = 0; q < 8; ++q)
+                a[q] = sl >= 0 ? gens[8 * sl + q] : 0.0;
+            double acc = 0.0;
+            bool did = false;
+            if (g.diag) {
+                did = true;
+                for (uint32_t j = threadIdx.x; j < T; j += kAdjTileThreads) {
+                    const uint64_t k = base | tile_offset(tm, j);
+                    if ((k & g.hi_mask) != g.hi_vals)
+                        continue;
+                    const int o = ((k >> g.target) & 1ull) ? 6 : 0;
+                    const cplx_t<R> x = tp[j], lx = tl[j];
+                    if (sl >= 0) {
+                        const double axr = a[o] * x.x - a[o + 1] * x.y, axi = a[o] * x.y + a[o + 1] * x.x;
+                        acc += 2.0 * ((double)lx.x * axr + (double)lx.y * axi);
+                    }
+                    const R ur = (R)g.m[o], ui = (R)g.m[o + 1];
+                    cplx_t<R> nx, nl;
+                    nx.x = x.x * ur - x.y * ui;
+                    nx.y = x.x * ui + x.y * ur;
+                    nl.x = lx.x * ur - lx.y * ui;
+                    nl.y = lx.x * ui + lx.y * ur;
+                    tp[j] = nx;
+                    tl[j] = nl;
+                }
+            } else if ((base & g.hi_mask) == g.hi_vals) {  // uniform
+                did = true;
+                const Mat2<R> u = tile_mat<R>(g);
+                const uint32_t st = 1u << g.target;
+                for (uint32_t r = threadIdx.x; r < g.npairs; r += kAdjTileThreads) {
+                    const uint32_t p1 = tile_expand(g, r);
+                    cplx_t<R> x = tp[p1], y = tp[p1 | st], lx = tl[p1], ly = tl[p1 | st];
+                    if (sl >= 0) {
+                        const double xr = x.x, xi = x.y, yr = y.x, yi = y.y;
+                        const double axr = a[0] * xr - a[1] * xi + a[2] * yr - a[3] * yi;
+                        const double axi = a[0] * xi + a[1] * xr + a[2] * yi + a[3] * yr;
+                        const double ayr = a[4] * xr - a[5] * xi + a[6] * yr - a[7] * yi;
+                        const double ayi = a[4] * xi + a[5] * xr + a[6] * yi + a[7] * yr;
+                        acc += 2.0 * ((double)lx.x * axr + (double)lx.y * axi + (double)ly.x * ayr +
+                                      (double)ly.y * ayi);
+                    }
+                    apply_pair<R>(u, x, y);
+                    apply_pair<R>(u, lx, ly);
+                    tp[p1] = x;
+                    tp[p1 | st] = y;
+                    tl[p1] = lx;
+                    tl[p1 | st] = ly;
+                }
+            }
+            if (did) {
+                if (sl >= 0) {  // uniform; block_sum synchronises
+                    const double s = block_sum(acc, scratch);
+                    if (threadIdx.x == 0)
+                        partials[(size_t)sl * kMaxPartials + blockIdx.x] += s;
+                }
+                __syncthreads();
+            }
+        }
+        for (uint32_t j = threadIdx.x; j < T; j += kAdjTileThreads) {
+            const uint64_t k = base | tile_offset(tm, j);
+            st_stream<R>(psi + k, tp[j]);
+            st_stream<R>(lam + k, tl[j]);
+        }
+        __syncthreads();
     }
 }
 
@@ -143,20 +237,6 @@ static void launch_adj(void *psi, void *lam, const GatePlan &p, const double *ud
     }
 }
 
-struct AdjBuffers {
-    double *udag = nullptr, *gen = nullptr, *partials = nullptr;
-    AdjJob *jobs = nullptr;
-    int32_t *ints = nullptr;
-};
-
-static void adj_release(AdjBuffers *b, hipStream_t st) {
-    void *ps[] = {b->udag, b->gen, b->partials, b->jobs, b->ints};
-    for (void *p : ps)
-        if (p)
-            (void)hipFreeAsync(p, st);
-    *b = AdjBuffers();
-}
-
 int adjoint_impl(const sv_state_t *psi, const sv_state_t *lam, const sv_gate_t *gates, int ngates,
                  const double *params, int nparams, const sv_pauli_t *terms, int nterms, double *grad, double *loss,
                  const double *scale, hipStream_t st) {
@@ -170,47 +250,69 @@ int adjoint_impl(const sv_state_t *psi, const sv_state_t *lam, const sv_gate_t *
         return fail(SV_EINVAL, "bad gate list");
     if (nparams < 0 || (nparams > 0 && (!params || !grad)))
         return fail(SV_EINVAL, "nparams %d needs params_dev and grad_dev", nparams);
-    const int n = psi->n;
+    const int n = psi->n, dtype = psi->dtype;
     for (int i = 0; i < ngates; ++i)
         SV_TRY(validate_circuit_gate(n, nparams, gates[i], i));
     PauliPlan pplan;
     SV_TRY(make_pauli_plan(n, terms, nterms, &pplan));
 
-    // host tables
-    std::vector<GatePlan> plans(ngates);
-    std::vector<double> udag((size_t)8 * std::max(1, ngates), 0.0);
-    std::vector<double> gen;
+    // The reverse sweep is the circuit of inverses in reverse order, planned
+    // like a forward circuit (fused runs of two LDS tiles, so one size down).
+    std::vector<sv_gate_t> rev(ngates);
+    for (int r = 0; r < ngates; ++r) {
+        rev[r] = gates[ngates - 1 - r];
+        rev[r].kind ^= SV_G_ADJOINT;
+    }
+    // generator of every differentiated gate (A with dU/dtheta = A U; A^dag
+    // for a gate given with the adjoint flag, as A commutes with U)
     std::vector<int> gen_slot(ngates, -1);
-    std::vector<AdjJob> jobs;
+    std::vector<double> gen;
     std::vector<std::vector<int>> param_slots(nparams);
-    for (int i = 0; i < ngates; ++i) {
-        const sv_gate_t &g = gates[i];
-        GateSpec gs{n, g.target, g.ctrl_mask, g.ctrl_vals};
-        SV_TRY(make_gate_plan(gs, psi->dtype, SV_MODE_PAIR, &plans[i]));
-        const int inv = g.kind ^ SV_G_ADJOINT;
-        if (g.param < 0) {
-            gate_matrix(inv, g.theta, g.U, &udag[(size_t)8 * i]);
-        } else {
-            jobs.push_back(AdjJob{inv, g.param, i});
-            double a[8];
-            gate_generator(g.kind, a);
-            if (g.kind & SV_G_ADJOINT) {
-                // d/dtheta U^dag = (A U)^dag = U^dag A^dag = A^dag U^dag, as A
-                // commutes with U for every parameterised kind: use A^dag
-                for (int k = 1; k < 8; k += 2)
-                    a[k] = -a[k];
-                std::swap(a[2], a[4]);
-                std::swap(a[3], a[5]);
-            }
-            gen_slot[i] = (int)(gen.size() / 8);
-            gen.insert(gen.end(), a, a + 8);
-            param_slots[g.param].push_back(gen_slot[i]);
+    for (int r = 0; r < ngates; ++r) {
+        const sv_gate_t &g = gates[ngates - 1 - r];
+        if (g.param < 0)
+            continue;
+        double A[8];
+        gate_generator(g.kind, A);
+        if (g.kind & SV_G_ADJOINT) {
+            for (int k = 1; k < 8; k += 2)
+                A[k] = -A[k];
+            std::swap(A[2], A[4]);
+            std::swap(A[3], A[5]);
         }
+        gen_slot[r] = (int)(gen.size() / 8);
+        gen.insert(gen.end(), A, A + 8);
+        param_slots[g.param].push_back(gen_slot[r]);
     }
     const int nslots = (int)(gen.size() / 8);
-    // CSR of slots per parameter + blocks per slot
-    std::vector<int32_t> ints;
-    ints.reserve((size_t)nparams + 1 + 2 * (size_t)nslots);
+    const int m_cap = std::max(1, tuning().tile_log2[dtype == SV_C128 ? 0 : 1] - 1);
+    sv_circuit *rc = nullptr;
+    SV_TRY(circuit_create(n, dtype, rev.data(), ngates, nparams, SV_FUSE, true, st, m_cap, &rc));
+
+    // per pass: single passes need pair plans, fused ones per-descriptor slots
+    std::vector<GatePlan> single_plan(rc->passes.size());
+    std::vector<int32_t> dslot(rc->tile_src.size(), -1);
+    std::vector<int32_t> slot_blocks(std::max(1, nslots), 1);
+    int r = SV_OK;
+    for (size_t pi = 0; pi < rc->passes.size() && r == SV_OK; ++pi) {
+        const Pass &p = rc->passes[pi];
+        if (p.fused) {
+            const unsigned grid = (unsigned)std::min<uint64_t>(p.tm.ntiles, kMaxPartials);
+            for (int j = 0; j < p.count; ++j) {
+                const int gi = rc->tile_src[p.first + j];
+                dslot[p.first + j] = gen_slot[gi];
+                if (gen_slot[gi] >= 0)
+                    slot_blocks[gen_slot[gi]] = (int32_t)grid;
+            }
+        } else {
+            const sv_gate_t &g = rev[p.gate];
+            GateSpec gs{n, g.target, g.ctrl_mask, g.ctrl_vals};
+            r = make_gate_plan(gs, dtype, SV_MODE_PAIR, &single_plan[pi]);
+            if (r == SV_OK && gen_slot[p.gate] >= 0)
+                slot_blocks[gen_slot[p.gate]] = (int32_t)reduce_grid(single_plan[pi].niter);
+        }
+    }
+    std::vector<int32_t> ints;  // CSR of slots per parameter, then blocks per slot
     {
         int32_t acc = 0;
         for (int j = 0; j < nparams; ++j) {
@@ -219,26 +321,22 @@ int adjoint_impl(const sv_state_t *psi, const sv_state_t *lam, const sv_gate_t *
         }
         ints.push_back(acc);
         for (int j = 0; j < nparams; ++j)
-            for (int s : param_slots[j])
-                ints.push_back(s);
-        std::vector<int32_t> blocks(nslots, 1);
-        for (int i = 0; i < ngates; ++i)
-            if (gen_slot[i] >= 0)
-                blocks[gen_slot[i]] = (int32_t)reduce_grid(plans[i].niter);
-        ints.insert(ints.end(), blocks.begin(), blocks.end());
+            for (int sidx : param_slots[j])
+                ints.push_back(sidx);
+        ints.insert(ints.end(), slot_blocks.begin(), slot_blocks.begin() + nslots);
     }
     const size_t off_slots = (size_t)nparams + 1, off_blocks = off_slots + (size_t)nslots;
 
-    // device buffers (stream-ordered)
-    AdjBuffers B;
+    double *d_gen = nullptr, *d_partials = nullptr;
+    int32_t *d_ints = nullptr, *d_dslot = nullptr;
     PauliDevice pd;
-    auto alloc = [&](void **p, size_t bytes) -> int {
+    auto alloc = [&](void **ptr, size_t bytes) -> int {
         if (bytes == 0)
             return SV_OK;
-        hipError_t e = hipMallocAsync(p, bytes, st);
+        hipError_t e = hipMallocAsync(ptr, bytes, st);
         if (e != hipSuccess) {
             (void)hipGetLastError();
-            *p = nullptr;
+            *ptr = nullptr;
             return fail(SV_ENOMEM, "device allocation of %zu bytes failed: %s", bytes, hipGetErrorString(e));
         }
         return SV_OK;
@@ -249,55 +347,70 @@ int adjoint_impl(const sv_state_t *psi, const sv_state_t *lam, const sv_gate_t *
         hipError_t e = hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st);
         return e == hipSuccess ? SV_OK : fail(SV_EHIP, "copy failed: %s", hipGetErrorString(e));
     };
-    int r = alloc((void **)&B.udag, udag.size() * sizeof(double));
     if (r == SV_OK)
-        r = alloc((void **)&B.gen, gen.size() * sizeof(double));
+        r = alloc((void **)&d_gen, gen.size() * sizeof(double));
     if (r == SV_OK)
-        r = alloc((void **)&B.partials, ((size_t)nslots + 1) * kMaxPartials * sizeof(double));
+        r = alloc((void **)&d_partials, ((size_t)nslots + 1) * kMaxPartials * sizeof(double));
     if (r == SV_OK)
-        r = alloc((void **)&B.jobs, jobs.size() * sizeof(AdjJob));
+        r = alloc((void **)&d_ints, ints.size() * sizeof(int32_t));
     if (r == SV_OK)
-        r = alloc((void **)&B.ints, ints.size() * sizeof(int32_t));
+        r = alloc((void **)&d_dslot, dslot.size() * sizeof(int32_t));
     if (r == SV_OK)
-        r = put(B.udag, udag.data(), udag.size() * sizeof(double));
+        r = put(d_gen, gen.data(), gen.size() * sizeof(double));
     if (r == SV_OK)
-        r = put(B.gen, gen.data(), gen.size() * sizeof(double));
+        r = put(d_ints, ints.data(), ints.size() * sizeof(int32_t));
     if (r == SV_OK)
-        r = put(B.jobs, jobs.data(), jobs.size() * sizeof(AdjJob));
-    if (r == SV_OK)
-        r = put(B.ints, ints.data(), ints.size() * sizeof(int32_t));
+        r = put(d_dslot, dslot.data(), dslot.size() * sizeof(int32_t));
     if (r == SV_OK)
         r = pauli_upload(pplan, 0, st, &pd);
-    if (r != SV_OK) {
-        adj_release(&B, st);
-        return r;
-    }
-    double *loss_partials = B.partials + (size_t)nslots * kMaxPartials;
-    pd.partials = loss_partials;  // borrowed; released with B
+    double *loss_partials = d_partials ? d_partials + (size_t)nslots * kMaxPartials : nullptr;
+    pd.partials = loss_partials;  // borrowed
     unsigned loss_blocks = 1;
-    if (!jobs.empty()) {
-        hipLaunchKernelGGL(k_adj_mats, dim3((unsigned)((jobs.size() + 127) / 128)), dim3(128), 0, st, B.jobs,
-                           (int)jobs.size(), params, B.udag);
-        r = hipGetLastError() == hipSuccess ? SV_OK : fail(SV_EHIP, "launch failed");
-    }
     if (r == SV_OK)
-        r = launch_apply_paulis(psi->dtype, psi->data, lam->data, n, pd, st, &loss_blocks);
-    for (int i = ngates - 1; i >= 0 && r == SV_OK; --i) {
-        const GatePlan &p = plans[i];
-        const unsigned grid = reduce_grid(p.niter);
-        const double *gptr = gen_slot[i] >= 0 ? B.gen + (size_t)8 * gen_slot[i] : nullptr;
-        double *part = gen_slot[i] >= 0 ? B.partials + (size_t)gen_slot[i] * kMaxPartials : nullptr;
-        if (psi->dtype == SV_C128)
-            launch_adj<double>(psi->data, lam->data, p, B.udag + (size_t)8 * i, gptr, part, grid, st);
-        else
-            launch_adj<float>(psi->data, lam->data, p, B.udag + (size_t)8 * i, gptr, part, grid, st);
+        r = circuit_param_mats(rc, params, st);
+    if (r == SV_OK)
+        r = launch_apply_paulis(dtype, psi->data, lam->data, n, pd, st, &loss_blocks);
+    const size_t lds = ((size_t)2 << rc->m) * amp_bytes(dtype);
+    if (r == SV_OK && lds > 65536) {
+        const hipError_t e = dtype == SV_C128 ? hipFuncSetAttribute((const void *)k_adj_tile<double>,
+                                                                    hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                                    (int)lds)
+                                              : hipFuncSetAttribute((const void *)k_adj_tile<float>,
+                                                                    hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                                    (int)lds);
+        if (e != hipSuccess)
+            r = fail(SV_EHIP, "LDS limit for %zu bytes: %s", lds, hipGetErrorString(e));
+    }
+    for (size_t pi = 0; pi < rc->passes.size() && r == SV_OK; ++pi) {
+        const Pass &p = rc->passes[pi];
+        if (p.fused) {
+            const unsigned grid = (unsigned)std::min<uint64_t>(p.tm.ntiles, kMaxPartials);
+            const DeviceGates dg{rc->d_tiles + p.first, p.count};
+            if (dtype == SV_C128)
+                hipLaunchKernelGGL(k_adj_tile<double>, dim3(grid), dim3(kAdjTileThreads), lds, st,
+                                   (double2 *)psi->data, (double2 *)lam->data, p.tm, dg, d_dslot + p.first, d_gen,
+                                   d_partials);
+            else
+                hipLaunchKernelGGL(k_adj_tile<float>, dim3(grid), dim3(kAdjTileThreads), lds, st, (float2 *)psi->data,
+                                   (float2 *)lam->data, p.tm, dg, d_dslot + p.first, d_gen, d_partials);
+        } else {
+            const GatePlan &gp = single_plan[pi];
+            const int gi = p.gate;
+            const unsigned grid = reduce_grid(gp.niter);
+            const double *gptr = gen_slot[gi] >= 0 ? d_gen + (size_t)8 * gen_slot[gi] : nullptr;
+            double *part = gen_slot[gi] >= 0 ? d_partials + (size_t)gen_slot[gi] * kMaxPartials : nullptr;
+            if (dtype == SV_C128)
+                launch_adj<double>(psi->data, lam->data, gp, rc->d_mats + (size_t)8 * gi, gptr, part, grid, st);
+            else
+                launch_adj<float>(psi->data, lam->data, gp, rc->d_mats + (size_t)8 * gi, gptr, part, grid, st);
+        }
         hipError_t e = hipGetLastError();
         if (e != hipSuccess)
             r = fail(SV_EHIP, "adjoint launch failed: %s", hipGetErrorString(e));
     }
     if (r == SV_OK && (nparams > 0 || loss)) {
-        hipLaunchKernelGGL(k_grad_final, dim3((unsigned)nparams + 1), dim3(kRedThreads), 0, st, nparams, B.ints,
-                           B.ints + off_slots, B.ints + off_blocks, B.partials, loss_partials, (int)loss_blocks, scale,
+        hipLaunchKernelGGL(k_grad_final, dim3((unsigned)nparams + 1), dim3(kRedThreads), 0, st, nparams, d_ints,
+                           d_ints + off_slots, d_ints + off_blocks, d_partials, loss_partials, (int)loss_blocks, scale,
                            grad, loss);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess)
@@ -305,7 +418,11 @@ int adjoint_impl(const sv_state_t *psi, const sv_state_t *lam, const sv_gate_t *
     }
     pd.partials = nullptr;
     pauli_release(&pd, st);
-    adj_release(&B, st);
+    void *bufs[] = {d_gen, d_partials, d_ints, d_dslot};
+    for (void *b : bufs)
+        if (b)
+            (void)hipFreeAsync(b, st);
+    circuit_free(rc, st);
     return r;
 }
 

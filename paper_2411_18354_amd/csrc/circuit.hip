@@ -14,25 +14,10 @@
 #include <cstring>
 #include <memory>
 
+#include "circuit.hpp"
 #include "gates.hpp"
-#include "tile.hpp"
 
 namespace sv {
-
-struct ParamJob {
-    int32_t kind;
-    int32_t param;
-    int32_t mat_slot;   // gate index: matrix at mats + 8 * mat_slot
-    int32_t tile_slot;  // fused-run descriptor index or -1
-};
-
-struct Pass {
-    bool fused;
-    int gate;        // single: gate index
-    int first, count;  // fused: descriptors [first, first + count)
-    GatePlan plan;   // single
-    TileMap tm;      // fused: which qubits a tile spans
-};
 
 __global__ void k_param_mats(const ParamJob *__restrict__ jobs, int njobs, const double *__restrict__ params,
                              double *__restrict__ mats, TileGate *__restrict__ tiles) {
@@ -91,26 +76,6 @@ int validate_circuit_gate(int n, int nparams, const sv_gate_t &g, int index) {
 } // namespace sv
 
 using namespace sv;
-
-struct sv_circuit {
-    int n = 0, dtype = 0, flags = 0, nparams = 0, device = 0, m = 0;
-    int m_cap = 64;  // upper bound on the tile width (callers with a fixed LDS budget)
-    bool general_tiles = true;  // tiles over any qubit set; false: contiguous tiles only
-    std::vector<sv_gate_t> gates;
-    std::vector<Pass> passes;
-    int njobs = 0;
-    int64_t fused_gates = 0, fused_runs = 0;
-    double *d_mats = nullptr;
-    TileGate *d_tiles = nullptr;
-    ParamJob *d_jobs = nullptr;
-    bool async_buffers = false;  // allocated stream-ordered (one-shot use)
-    hipStream_t cap = nullptr;
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
-    void *g_data = nullptr;
-    const double *g_params = nullptr;
-    hipEvent_t done = nullptr;
-};
 
 namespace sv {
 
@@ -219,13 +184,32 @@ static int plan_circuit(sv_circuit *c, std::vector<TileGate> &tiles, std::vector
                 p.gate = -1;
                 p.first = (int)tiles.size();
                 p.count = (int)run.size();
-                p.tm = make_tile_map(c->n, m, a, high);
+                // outer control bits shared (same value) by every gate of the run
+                uint64_t S = (a >= 64) ? ~0ull : ((1ull << a) - 1);
+                for (int q : high)
+                    S |= 1ull << q;
+                uint64_t fmask = ~0ull, fvals = 0;
+                bool first = true;
+                for (int gi : run) {
+                    const sv_gate_t &g = c->gates[gi];
+                    const uint64_t om = g.ctrl_mask & ~S, ov = g.ctrl_vals & ~S;
+                    if (first) {
+                        fmask = om;
+                        fvals = ov;
+                        first = false;
+                    } else {
+                        fmask &= om & ~(fvals ^ ov);
+                    }
+                }
+                fvals &= fmask;
+                p.tm = make_tile_map(c->n, m, a, high, fmask, fvals);
                 for (int gi : run) {
                     const sv_gate_t &g = c->gates[gi];
                     tile_slot[gi] = (int)tiles.size();
                     tiles.push_back(
                         make_tile_gate(p.tm, g.target, g.ctrl_mask, g.ctrl_vals, &mats[(size_t)8 * gi], diag[gi]));
                     tiles.back().src_gate = gi;
+                    c->tile_src.push_back(gi);
                 }
                 c->passes.push_back(p);
                 c->fused_gates += (int64_t)run.size();
@@ -282,8 +266,8 @@ template <typename T> static int upload(T **dst, const std::vector<T> &src, bool
     return SV_OK;
 }
 
-static int create_impl(int n, int dtype, const sv_gate_t *gates, int ngates, int nparams, int flags, bool async,
-                       hipStream_t st, sv_circuit **out) {
+int circuit_create(int n, int dtype, const sv_gate_t *gates, int ngates, int nparams, int flags, bool async,
+                   hipStream_t st, int m_cap, sv_circuit **out) {
     *out = nullptr;
     if (dtype != SV_C128 && dtype != SV_C64)
         return fail(SV_EINVAL, "unknown dtype %d", dtype);
@@ -303,6 +287,7 @@ static int create_impl(int n, int dtype, const sv_gate_t *gates, int ngates, int
     c->flags = flags;
     c->nparams = nparams;
     c->async_buffers = async;
+    c->m_cap = m_cap;
     SV_HIP_TRY(hipGetDevice(&c->device));
     c->gates.assign(gates, gates + ngates);
     std::vector<TileGate> tiles;
@@ -332,18 +317,29 @@ static int create_impl(int n, int dtype, const sv_gate_t *gates, int ngates, int
     return SV_OK;
 }
 
-template <typename R> static int enqueue(sv_circuit *c, cplx_t<R> *psi, const double *params, hipStream_t st) {
+int circuit_param_mats(sv_circuit *c, const double *params, hipStream_t st) {
     if (c->njobs > 0) {
         hipLaunchKernelGGL(k_param_mats, dim3((c->njobs + 127) / 128), dim3(128), 0, st, c->d_jobs, c->njobs,
                            params, c->d_mats, c->d_tiles);
         SV_LAUNCH_CHECK();
     }
+    return SV_OK;
+}
+
+void circuit_free(sv_circuit *c, hipStream_t st) {
+    if (!c)
+        return;
+    free_buffers(c, st);
+    delete c;
+}
+
+template <typename R> static int enqueue(sv_circuit *c, cplx_t<R> *psi, const double *params, hipStream_t st) {
+    SV_TRY(circuit_param_mats(c, params, st));
     const size_t lds = ((size_t)1 << c->m) * sizeof(cplx_t<R>);
-    const uint64_t ntiles = 1ull << (c->n - c->m);
     for (const Pass &p : c->passes) {
         if (p.fused) {
             DeviceGates dg{c->d_tiles + p.first, p.count};
-            hipLaunchKernelGGL((k_tile<R, 512, DeviceGates>), dim3((unsigned)ntiles), dim3(512), lds, st, psi, p.tm,
+            hipLaunchKernelGGL((k_tile<R, 512, DeviceGates>), dim3((unsigned)p.tm.ntiles), dim3(512), lds, st, psi, p.tm,
                                dg);
             SV_LAUNCH_CHECK();
         } else {
@@ -493,7 +489,7 @@ int sv_circuit_create(int n, int dtype, const sv_gate_t *gates, int ngates, int 
     clear_error();
     if (!out)
         return fail(SV_EINVAL, "out is NULL");
-    return create_impl(n, dtype, gates, ngates, nparams, flags, false, nullptr, out);
+    return circuit_create(n, dtype, gates, ngates, nparams, flags, false, nullptr, 64, out);
 }
 
 int sv_circuit_run(sv_circuit_t *c, const sv_state_t *s, const double *params_dev, sv_stream_t st) {
@@ -550,7 +546,7 @@ int sv_apply_circuit(const sv_state_t *s, const sv_gate_t *gates, int ngates, co
     clear_error();
     SV_TRY(validate_state(s));
     sv_circuit *c = nullptr;
-    SV_TRY(create_impl(s->n, s->dtype, gates, ngates, nparams, flags & ~SV_GRAPH, true, (hipStream_t)st, &c));
+    SV_TRY(circuit_create(s->n, s->dtype, gates, ngates, nparams, flags & ~SV_GRAPH, true, (hipStream_t)st, 64, &c));
     int r = check_run_args(c, s, params_dev);
     if (r == SV_OK)
         r = enqueue_any(c, s, params_dev, (hipStream_t)st);

@@ -1,0 +1,61 @@
+// Internal circuit plan shared by the circuit driver and the adjoint sweep.
+#pragma once
+
+#include "tile.hpp"
+
+namespace sv {
+
+struct ParamJob {
+    int32_t kind;
+    int32_t param;
+    int32_t mat_slot;   // gate index: matrix at mats + 8 * mat_slot
+    int32_t tile_slot;  // fused-run descriptor index or -1
+};
+
+struct Pass {
+    bool fused;
+    int gate;        // single: gate index
+    int first, count;  // fused: descriptors [first, first + count)
+    GatePlan plan;   // single
+    TileMap tm;      // fused: which qubits a tile spans
+};
+
+} // namespace sv
+
+struct sv_circuit {
+    // (the C ABI's opaque sv_circuit_t)
+    int n = 0, dtype = 0, flags = 0, nparams = 0, device = 0, m = 0;
+    int m_cap = 64;  // upper bound on the tile width (callers with a fixed LDS budget)
+    bool general_tiles = true;  // tiles over any qubit set; false: contiguous tiles only
+    std::vector<sv_gate_t> gates;
+    std::vector<sv::Pass> passes;
+    std::vector<int32_t> tile_src;  // gate index of every fused-run descriptor
+    int njobs = 0;
+    int64_t fused_gates = 0, fused_runs = 0;
+    double *d_mats = nullptr;
+    sv::TileGate *d_tiles = nullptr;
+    sv::ParamJob *d_jobs = nullptr;
+    bool async_buffers = false;  // allocated stream-ordered (one-shot use)
+    hipStream_t cap = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    void *g_data = nullptr;
+    const double *g_params = nullptr;
+    hipEvent_t done = nullptr;
+};
+
+
+namespace sv {
+
+// Validate, plan and upload a circuit (the body of sv_circuit_create).
+// async: device buffers are allocated and released stream-ordered on st.
+// m_cap bounds the tile width (callers with a fixed LDS budget).
+int circuit_create(int n, int dtype, const sv_gate_t *gates, int ngates, int nparams, int flags, bool async,
+                   hipStream_t st, int m_cap, sv_circuit **out);
+// Release device buffers (stream-ordered on st for async plans) and the plan.
+void circuit_free(sv_circuit *c, hipStream_t st);
+// Compute the matrices of parameterised gates from params (device) into the
+// plan's tables.
+int circuit_param_mats(sv_circuit *c, const double *params, hipStream_t st);
+
+} // namespace sv

@@ -121,21 +121,49 @@ __global__ __launch_bounds__(kThreads) void k_wave(cplx_t<R> *__restrict__ psi, 
 // host side
 // ---------------------------------------------------------------------------
 
-TileMap make_tile_map(int n, int m, int a, const std::vector<int> &high) {
+TileMap make_tile_map(int n, int m, int a, const std::vector<int> &high, uint64_t fixed_mask, uint64_t fixed_vals) {
     TileMap tm;
     memset(&tm, 0, sizeof(tm));
+    // high qubits that continue the low block extend it
+    size_t h0 = 0;
+    while (h0 < high.size() && high[h0] == a) {
+        ++a;
+        ++h0;
+    }
     tm.m = (uint32_t)m;
     tm.a = (uint32_t)a;
-    tm.nh = (uint32_t)high.size();
-    std::vector<int> S, zeros;
+    tm.nh = (uint32_t)(high.size() - h0);
+    uint64_t S = 0;
     for (int q = 0; q < a; ++q)
-        S.push_back(q);
-    for (size_t i = 0; i < high.size(); ++i) {
-        tm.hpos[i] = (uint32_t)high[i];
-        S.push_back(high[i]);
+        S |= 1ull << q;
+    for (size_t i = h0; i < high.size(); ++i) {
+        tm.hpos[i - h0] = (uint32_t)high[i];
+        S |= 1ull << high[i];
     }
-    zeros.assign(S.size(), 0);
-    tm.outer = make_expand(n, S, zeros);  // tile index deposited outside S
+    // local bit a+i goes to hpos[i]; consecutive hpos form one shifted segment
+    for (uint32_t i = 0; i < tm.nh;) {
+        uint32_t e = i + 1;
+        while (e < tm.nh && tm.hpos[e] == tm.hpos[e - 1] + 1)
+            ++e;
+        const uint32_t lo = (uint32_t)a + i, len = e - i;
+        tm.seg_in[tm.nseg] = ((1u << len) - 1) << lo;
+        tm.seg_shift[tm.nseg] = tm.hpos[i] - lo;
+        tm.nseg++;
+        i = e;
+    }
+    fixed_mask &= ~S;
+    std::vector<int> pos, bits;  // S bits (0) and the fixed outer bits (their values)
+    for (int q = 0; q < n; ++q) {
+        if (S & (1ull << q)) {
+            pos.push_back(q);
+            bits.push_back(0);
+        } else if (fixed_mask & (1ull << q)) {
+            pos.push_back(q);
+            bits.push_back((int)((fixed_vals >> q) & 1));
+        }
+    }
+    tm.outer = make_expand(n, pos, bits);
+    tm.ntiles = 1ull << (n - (int)pos.size());
     return tm;
 }
 
@@ -369,8 +397,7 @@ static int launch_tile1(const sv_state_t *s, const GateSpec &g, const double *U,
     const size_t lds = ((size_t)1 << m) * sizeof(cplx_t<R>);
     auto fn = k_tile<R, 512, InlineGates<1>>;
     SV_TRY(set_lds_limit<R>((const void *)fn, lds));
-    const uint64_t tiles = 1ull << (g.n - m);
-    hipLaunchKernelGGL(fn, dim3((unsigned)tiles), dim3(512), lds, st, reinterpret_cast<cplx_t<R> *>(s->data), tm,
+    hipLaunchKernelGGL(fn, dim3((unsigned)tm.ntiles), dim3(512), lds, st, reinterpret_cast<cplx_t<R> *>(s->data), tm,
                        gs);
     SV_LAUNCH_CHECK();
     return SV_OK;

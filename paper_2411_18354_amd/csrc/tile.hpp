@@ -46,16 +46,26 @@ struct TileGate {
 // Where a tile's amplitudes live: base = deposit(tile index) over the qubits
 // outside S; local index j maps to base | (j & (2^a - 1)) | scatter(j >> a)
 // over the high qubits of S.
+// Control bits outside S that every operation of a run requires (with the
+// same value) are inserted into the tile index too, so only tiles that can
+// be touched are launched: the control-aware scheduling of Sec. III-B
+// applied at tile granularity.
 struct TileMap {
     uint32_t m;
-    uint32_t a;
-    uint32_t nh;
+    uint32_t a;        // S holds qubits 0 .. a-1 (contiguous runs of 2^a)
+    uint32_t nh;       // and these further qubits, ascending
     uint32_t hpos[kTileMaxHigh];
+    uint32_t nseg;     // local bits >= a scattered as (j & in_mask) << shift
+    uint32_t seg_in[kTileMaxHigh];
+    uint32_t seg_shift[kTileMaxHigh];
     Expand outer;
+    uint64_t ntiles;  // launched tiles: 2^(n - m - fixed outer bits)
 };
 
-// Tile map for S = {0 .. a-1} u high (host).  high: ascending qubits >= a.
-TileMap make_tile_map(int n, int m, int a, const std::vector<int> &high);
+// Tile map for S = {0 .. a-1} u high (host).  high: ascending qubits >= a;
+// fixed_mask/fixed_vals: outer index bits every launched tile has.
+TileMap make_tile_map(int n, int m, int a, const std::vector<int> &high, uint64_t fixed_mask = 0,
+                      uint64_t fixed_vals = 0);
 // Descriptor of one gate for a tile map (host).  A pair gate's target must be
 // in S.
 TileGate make_tile_gate(const TileMap &tm, int target, uint64_t cmask, uint64_t cvals, const double *U,
@@ -92,9 +102,8 @@ __device__ __forceinline__ uint32_t tile_expand(const TileGate &g, uint32_t x) {
 
 __device__ __forceinline__ uint64_t tile_offset(const TileMap &tm, uint32_t j) {
     uint64_t o = j & ((1u << tm.a) - 1);
-    const uint32_t h = j >> tm.a;
-    for (uint32_t i = 0; i < tm.nh; ++i)
-        o |= (uint64_t)((h >> i) & 1u) << tm.hpos[i];
+    for (uint32_t s = 0; s < tm.nseg; ++s)
+        o |= (uint64_t)(j & tm.seg_in[s]) << tm.seg_shift[s];
     return o;
 }
 

@@ -177,3 +177,32 @@ def test_adjoint_hea_n24_sampled(gpu):
     err = np.max(np.abs(g[sample] - ref)) / max(1.0, np.max(np.abs(ref)))
     _say("hea n24 sampled grad err %.2e" % err)
     assert err <= 1e-8
+
+
+@pytest.mark.parametrize("tile,low", [(8, 3), (10, 5), (13, 6)])
+def test_adjoint_fused_tiles(gpu, tile, low):
+    """The fused reverse sweep under several tile shapes (small tiles force
+    scattered qubit sets and many runs; 13 gives 128 KiB of LDS): gradients
+    against the oracle's parameter shift, psi restored to |0>."""
+    gpu.sv_tune_set("tile_log2_c128", tile)
+    gpu.sv_tune_set("tile_low_bits_c128", low)
+    try:
+        n = 11
+        rng = np.random.default_rng(tile)
+        gates, P = [], 7
+        for i in range(60):
+            t = int(rng.integers(0, n))
+            others = [q for q in range(n) if q != t]
+            c = int(rng.integers(0, 3))
+            ctrls = tuple(int(q) for q in rng.choice(others, size=c, replace=False)) if c else ()
+            vals = tuple(int(v) for v in rng.integers(0, 2, size=c))
+            kind = ("RY", "RZ", "H", "X", "RZ")[i % 5]
+            p = int(rng.integers(0, P)) if kind in ("RY", "RZ") else -1
+            gates.append(W.Gate(kind, t, ctrls, vals, 0.3, p))
+        circ = W.Circuit(n, gates, rng.uniform(0, 2 * np.pi, size=P))
+        terms = _rand_terms(n, 9, tile)
+        ref = oracle.grad_param_shift(circ, circ.params, terms)
+        _grad_check(gpu, circ, terms, ref)
+    finally:
+        gpu.sv_tune_set("tile_log2_c128", 12)
+        gpu.sv_tune_set("tile_low_bits_c128", 6)

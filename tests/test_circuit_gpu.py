@@ -201,3 +201,30 @@ def test_qft_fused_large(gpu, dtype):
     ref = np.fft.ifft(psi0[rev]) * np.sqrt(N)
     assert _err(d.cpu().numpy(), ref) <= TOL[dtype]
     circ.close()
+
+
+@pytest.mark.parametrize("tile,low", [(6, 3), (8, 4), (12, 6)])
+def test_stream_fused_tile_scheduling(gpu, tile, low):
+    """Streaming circuits (gate j controlled by all lower qubits): fused runs
+    launch only the tiles whose shared outer control bits hold.  Closed form
+    |x> -> |x-1>, plus controlled streams with negative controls against the
+    oracle."""
+    gpu.sv_tune_set("tile_log2_c128", tile)
+    gpu.sv_tune_set("tile_low_bits_c128", low)
+    try:
+        for n in (10, 17):
+            psi0 = W.random_state(n, n)
+            d = _dev_state(n, "c128", psi0)
+            gpu.sv_apply_circuit(d, W.stream(n), flags=gpu.SV_FUSE)
+            assert _err(d.cpu().numpy(), np.roll(psi0, -1)) <= 1e-12, (n, tile)
+            g = [W.Gate("H", q) for q in range(n)] + [
+                W.Gate("RY" if j % 2 else "X", j, tuple(range(j)), tuple((j + k) % 2 for k in range(j)), 0.4 + j)
+                for j in range(1, n)]
+            c = W.Circuit(n, g)
+            ref = oracle.run_circuit(c, psi0=psi0)
+            d = _dev_state(n, "c128", psi0)
+            gpu.sv_apply_circuit(d, c, flags=gpu.SV_FUSE)
+            assert _err(d.cpu().numpy(), ref) <= 1e-12, (n, tile, "controlled")
+    finally:
+        gpu.sv_tune_set("tile_log2_c128", 12)
+        gpu.sv_tune_set("tile_low_bits_c128", 6)
