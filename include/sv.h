@@ -184,6 +184,10 @@ typedef struct sv_gate {
 #define SV_GRAPH 2   /* capture the launch sequence once as a HIP graph and
                         replay it (per state and parameter pointer pair) */
 #define SV_MASKED 4  /* every gate on the masked baseline kernel, no fusion */
+#define SV_DENSE 8   /* with SV_FUSE: stretches of at least "dense_min_gates"
+                        gates acting only on the "dense_qubits" lowest qubits
+                        become one dense block applied with matrix cores
+                        (complex128: 4 qubits; complex64: 4 or 5; n >= k+6) */
 
 /* Write the 2x2 matrix of a gate kind (8 doubles, layout as above) for angle
  * theta; U is read for SV_G_MATRIX only (may be NULL otherwise).  Host-only. */
@@ -223,6 +227,13 @@ int sv_circuit_plan(int n, int dtype, const sv_gate_t *gates, int ngates, int np
 
 /* Release the plan (waits for the device work of earlier runs to finish). */
 int sv_circuit_destroy(sv_circuit_t *c);
+
+/* Apply a dense 2^k x 2^k matrix M (host, row-major, 8 bytes per real:
+ * M[a][b] at M[2(a 2^k + b)] (re) and M[2(a 2^k + b) + 1] (im)) to the k
+ * lowest qubits: every row of 2^k consecutive amplitudes becomes M row.
+ * Runs as a real-embedded GEMM on MFMA.  k = 4 for complex128, 4 or 5 for
+ * complex64, n >= k + 6; SV_ENOTSUP otherwise. */
+int sv_apply_dense_low(const sv_state_t *s, int k, const double *M, sv_stream_t st);
 
 /* One-shot: create, run on st, destroy.  SV_GRAPH is ignored here. */
 int sv_apply_circuit(const sv_state_t *s, const sv_gate_t *gates, int ngates, const double *params_dev,

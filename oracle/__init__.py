@@ -61,6 +61,8 @@ def lib():
         L.or_norm2.restype = ctypes.c_double
         L.or_basis.argtypes = [dp, ctypes.c_int, u64]
         L.or_basis.restype = None
+        L.or_apply_block_low.argtypes = [dp, ctypes.c_int, ctypes.c_int, dp]
+        L.or_apply_block_low.restype = None
         L.or_num_threads.argtypes = []
         L.or_num_threads.restype = ctypes.c_int
         _lib = L
@@ -189,6 +191,16 @@ def run_circuit(circ, params: Optional[np.ndarray] = None, psi0: Optional[np.nda
     for g in circ.gates:
         U = gate_matrix(g.kind, gate_angle(g, params), g.matrix)
         apply_gate(psi, n, g.target, g.controls, g.values, U)
+    return psi
+
+
+def apply_block_low(psi: np.ndarray, n: int, k: int, M: np.ndarray) -> np.ndarray:
+    """In place: every row of 2^k consecutive amplitudes becomes M . row (a
+    k-qubit operator on the k lowest qubits; k <= 6)."""
+    assert k <= 6 and psi.size == (1 << n)
+    m = np.ascontiguousarray(np.asarray(M, dtype=np.complex128).reshape(1 << k, 1 << k))
+    buf = np.ascontiguousarray(np.stack([m.real, m.imag], axis=-1).reshape(-1))
+    lib().or_apply_block_low(_dptr(psi.view(np.float64)), n, k, _dptr(buf))
     return psi
 
 

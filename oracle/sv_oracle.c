@@ -218,3 +218,29 @@ int or_num_threads(void)
     return 1;
 #endif
 }
+
+/* A 2^k x 2^k complex matrix M (row-major, interleaved re/im) applied to the
+ * k lowest qubits: each row of 2^k consecutive amplitudes becomes M . row.
+ * Plain triple loop through a temporary row. */
+void or_apply_block_low(double *psi, int n, int k, const double *M)
+{
+    const int64_t dim = (int64_t)1 << k;
+    const int64_t rows = (int64_t)1 << (n - k);
+#pragma omp parallel for schedule(static)
+    for (int64_t r = 0; r < rows; ++r) {
+        double tmp[2 * 64];
+        double *row = psi + 2 * r * dim;
+        for (int64_t a = 0; a < dim; ++a) {
+            double sr = 0.0, si = 0.0;
+            for (int64_t b = 0; b < dim; ++b) {
+                const double mr = M[2 * (a * dim + b)], mi = M[2 * (a * dim + b) + 1];
+                sr += mul_re(mr, mi, row[2 * b], row[2 * b + 1]);
+                si += mul_im(mr, mi, row[2 * b], row[2 * b + 1]);
+            }
+            tmp[2 * a] = sr;
+            tmp[2 * a + 1] = si;
+        }
+        for (int64_t a = 0; a < 2 * dim; ++a)
+            row[a] = tmp[a];
+    }
+}

@@ -240,7 +240,7 @@ def sv_copy_state(dst, src, stream=None) -> None:
 
 SV_G_MATRIX, SV_G_X, SV_G_Y, SV_G_Z, SV_G_H, SV_G_RX, SV_G_RY, SV_G_RZ, SV_G_P = range(9)
 SV_G_ADJOINT = 0x100
-SV_FUSE, SV_GRAPH, SV_MASKED = 1, 2, 4
+SV_FUSE, SV_GRAPH, SV_MASKED, SV_DENSE = 1, 2, 4, 8
 KIND_CODES = {"U": SV_G_MATRIX, "X": SV_G_X, "Y": SV_G_Y, "Z": SV_G_Z, "H": SV_G_H,
               "RX": SV_G_RX, "RY": SV_G_RY, "RZ": SV_G_RZ, "P": SV_G_P}
 
@@ -359,6 +359,18 @@ def sv_circuit_plan(n: int, gates, dtype: int = SV_C128, nparams: int = 0, flags
     _check(_L.sv_circuit_plan(int(n), int(dtype), arr, count, int(nparams), int(flags), order, pas,
                               ctypes.byref(npas)))
     return list(order)[:count], list(pas)[:count], int(npas.value)
+
+
+_sig("sv_apply_dense_low", [_sp, ctypes.c_int, _dp, _vp])
+
+
+def sv_apply_dense_low(state, k: int, M, stream=None) -> None:
+    """Apply the 2^k x 2^k complex matrix M to the k lowest qubits (MFMA)."""
+    import numpy as np
+    s = state_view(state)
+    m = np.ascontiguousarray(np.asarray(M, dtype=np.complex128).reshape(1 << k, 1 << k))
+    buf = np.ascontiguousarray(np.stack([m.real, m.imag], axis=-1).reshape(-1))
+    _check(_L.sv_apply_dense_low(ctypes.byref(s), int(k), buf.ctypes.data_as(_dp), stream_ptr(stream)))
 
 
 from .observables import (sv_pauli_t, pauli_terms, sv_expect, sv_expect_terms, sv_apply_pauli_sum,  # noqa: E402

@@ -98,7 +98,7 @@ static bool gate_is_diagonal(const sv_gate_t &g, const double *mat) {
 // them.  When the run closes, the deferred gates start the next run, so the
 // relative order of non-commuting gates is never changed.
 static int plan_circuit(sv_circuit *c, std::vector<TileGate> &tiles, std::vector<ParamJob> &jobs,
-                        std::vector<double> &mats) {
+                        std::vector<double> &mats, std::vector<DenseGate> &dense_list, int &dense_runs) {
     const int G = (int)c->gates.size();
     mats.assign((size_t)G * 8, 0.0);
     for (int i = 0; i < G; ++i) {
@@ -130,13 +130,8 @@ static int plan_circuit(sv_circuit *c, std::vector<TileGate> &tiles, std::vector
         c->passes.push_back(p);
         return SV_OK;
     };
-    if (!fuse) {
-        for (int i = 0; i < G; ++i)
-            SV_TRY(single(i));
-    } else {
-        std::vector<int> stream(G);
-        for (int i = 0; i < G; ++i)
-            stream[i] = i;
+    // fusion planner over one stream of gate indices
+    auto fuse_stream = [&](std::vector<int> stream) -> int {
         std::vector<int> run, deferred, high;
         size_t pos = 0;
         while (pos < stream.size()) {
@@ -224,6 +219,51 @@ static int plan_circuit(sv_circuit *c, std::vector<TileGate> &tiles, std::vector
             stream.swap(next);
             pos = 0;
         }
+        return SV_OK;
+    };
+    const int dk = tuning().dense_qubits;
+    const bool dense = fuse && (c->flags & SV_DENSE) && dense_supported(c->dtype, dk, c->n);
+    if (!fuse) {
+        for (int i = 0; i < G; ++i)
+            SV_TRY(single(i));
+    } else if (!dense) {
+        std::vector<int> all(G);
+        for (int i = 0; i < G; ++i)
+            all[i] = i;
+        SV_TRY(fuse_stream(all));
+    } else {
+        // maximal stretches of gates acting only on qubits 0 .. dk-1 become
+        // dense passes when long enough; the rest is fused as usual
+        c->dense_k = dk;
+        const uint64_t low = (1ull << dk) - 1;
+        std::vector<int> pending;
+        int i = 0;
+        while (i < G) {
+            int j = i;
+            while (j < G && (((c->gates[j].ctrl_mask | (1ull << c->gates[j].target)) & ~low) == 0))
+                ++j;
+            if (j - i >= std::max(1, tuning().dense_min_gates)) {
+                SV_TRY(fuse_stream(pending));
+                pending.clear();
+                Pass p;
+                p.fused = false;
+                p.dense = true;
+                p.first = (int)dense_list.size();
+                p.count = j - i;
+                for (int q = i; q < j; ++q) {
+                    const sv_gate_t &g = c->gates[q];
+                    dense_list.push_back(DenseGate{g.target, q, g.ctrl_mask, g.ctrl_vals});
+                }
+                p.gate = dense_runs++;
+                c->passes.push_back(p);
+                i = j;
+            } else {
+                for (int q = i; q < std::max(j, i + 1); ++q)
+                    pending.push_back(q);
+                i = std::max(j, i + 1);
+            }
+        }
+        SV_TRY(fuse_stream(pending));
     }
     for (int i = 0; i < G; ++i) {
         const sv_gate_t &g = c->gates[i];
@@ -235,7 +275,7 @@ static int plan_circuit(sv_circuit *c, std::vector<TileGate> &tiles, std::vector
 }
 
 static void free_buffers(sv_circuit *c, hipStream_t st) {
-    void *bufs[3] = {c->d_mats, c->d_tiles, c->d_jobs};
+    void *bufs[5] = {c->d_mats, c->d_tiles, c->d_jobs, c->d_dense, c->d_rmat};
     for (void *b : bufs)
         if (b) {
             if (c->async_buffers)
@@ -246,6 +286,8 @@ static void free_buffers(sv_circuit *c, hipStream_t st) {
     c->d_mats = nullptr;
     c->d_tiles = nullptr;
     c->d_jobs = nullptr;
+    c->d_dense = nullptr;
+    c->d_rmat = nullptr;
 }
 
 template <typename T> static int upload(T **dst, const std::vector<T> &src, bool async, hipStream_t st) {
@@ -277,7 +319,7 @@ int circuit_create(int n, int dtype, const sv_gate_t *gates, int ngates, int npa
         return fail(SV_EINVAL, "bad gate list (ngates %d, gates %p)", ngates, (const void *)gates);
     if (nparams < 0)
         return fail(SV_EINVAL, "nparams %d < 0", nparams);
-    if (flags & ~(SV_FUSE | SV_GRAPH | SV_MASKED))
+    if (flags & ~(SV_FUSE | SV_GRAPH | SV_MASKED | SV_DENSE))
         return fail(SV_EINVAL, "unknown flags 0x%x", flags);
     for (int i = 0; i < ngates; ++i)
         SV_TRY(validate_circuit_gate(n, nparams, gates[i], i));
@@ -293,12 +335,21 @@ int circuit_create(int n, int dtype, const sv_gate_t *gates, int ngates, int npa
     std::vector<TileGate> tiles;
     std::vector<ParamJob> jobs;
     std::vector<double> mats;
-    SV_TRY(plan_circuit(c.get(), tiles, jobs, mats));
+    std::vector<DenseGate> dense_list;
+    int dense_runs = 0;
+    SV_TRY(plan_circuit(c.get(), tiles, jobs, mats, dense_list, dense_runs));
     int r = upload(&c->d_mats, mats, async, st);
     if (r == SV_OK)
         r = upload(&c->d_tiles, tiles, async, st);
     if (r == SV_OK)
         r = upload(&c->d_jobs, jobs, async, st);
+    if (r == SV_OK)
+        r = upload((DenseGate **)&c->d_dense, dense_list, async, st);
+    if (r == SV_OK && dense_runs > 0) {
+        const size_t D = (size_t)2 << c->dense_k;
+        std::vector<double> zeros(D * D * (size_t)dense_runs, 0.0);  // room for either precision
+        r = upload((double **)&c->d_rmat, zeros, async, st);
+    }
     if (r != SV_OK) {
         free_buffers(c.get(), st);
         return r;
@@ -337,7 +388,13 @@ template <typename R> static int enqueue(sv_circuit *c, cplx_t<R> *psi, const do
     SV_TRY(circuit_param_mats(c, params, st));
     const size_t lds = ((size_t)1 << c->m) * sizeof(cplx_t<R>);
     for (const Pass &p : c->passes) {
-        if (p.fused) {
+        if (p.dense) {
+            const size_t D = (size_t)2 << c->dense_k;
+            void *rm = (char *)c->d_rmat + D * D * sizeof(R) * (size_t)p.gate;
+            SV_TRY(launch_dense_compose(c->dtype, (const DenseGate *)c->d_dense + p.first, p.count, c->d_mats,
+                                        c->dense_k, rm, st));
+            SV_TRY(launch_dense(c->dtype, psi, c->n, c->dense_k, rm, st));
+        } else if (p.fused) {
             DeviceGates dg{c->d_tiles + p.first, p.count};
             hipLaunchKernelGGL((k_tile<R, 512, DeviceGates>), dim3((unsigned)p.tm.ntiles), dim3(512), lds, st, psi, p.tm,
                                dg);
@@ -438,7 +495,7 @@ int circuit_plan_capped(int n, int dtype, const sv_gate_t *gates, int ngates, in
         return fail(SV_EINVAL, "n=%d outside [1, %d]", n, max_qubits(dtype));
     if (ngates < 0 || (ngates > 0 && !gates))
         return fail(SV_EINVAL, "bad gate list (ngates %d, gates %p)", ngates, (const void *)gates);
-    if (flags & ~(SV_FUSE | SV_GRAPH | SV_MASKED))
+    if (flags & ~(SV_FUSE | SV_GRAPH | SV_MASKED | SV_DENSE))
         return fail(SV_EINVAL, "unknown flags 0x%x", flags);
     for (int i = 0; i < ngates; ++i)
         SV_TRY(validate_circuit_gate(n, nparams, gates[i], i));
@@ -453,7 +510,9 @@ int circuit_plan_capped(int n, int dtype, const sv_gate_t *gates, int ngates, in
     std::vector<TileGate> tiles;
     std::vector<ParamJob> jobs;
     std::vector<double> mats;
-    SV_TRY(plan_circuit(&c, tiles, jobs, mats));
+    std::vector<DenseGate> dense_list;
+    int dense_runs = 0;
+    SV_TRY(plan_circuit(&c, tiles, jobs, mats, dense_list, dense_runs));
     int k = 0;
     for (size_t pi = 0; pi < c.passes.size(); ++pi) {
         const Pass &p = c.passes[pi];

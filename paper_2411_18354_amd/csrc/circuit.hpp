@@ -14,6 +14,7 @@ struct ParamJob {
 
 struct Pass {
     bool fused;
+    bool dense = false;  // dense k-qubit block: gates [first, first+count) of the dense list
     int gate;        // single: gate index
     int first, count;  // fused: descriptors [first, first + count)
     GatePlan plan;   // single
@@ -30,6 +31,9 @@ struct sv_circuit {
     std::vector<sv_gate_t> gates;
     std::vector<sv::Pass> passes;
     std::vector<int32_t> tile_src;  // gate index of every fused-run descriptor
+    int dense_k = 0;                // qubits of dense blocks
+    void *d_dense = nullptr;        // DenseGate list of all dense passes
+    void *d_rmat = nullptr;         // one real embedding per dense pass
     int njobs = 0;
     int64_t fused_gates = 0, fused_runs = 0;
     double *d_mats = nullptr;
@@ -57,5 +61,15 @@ void circuit_free(sv_circuit *c, hipStream_t st);
 // Compute the matrices of parameterised gates from params (device) into the
 // plan's tables.
 int circuit_param_mats(sv_circuit *c, const double *params, hipStream_t st);
+
+// Dense k-qubit blocks (dense.hip).
+struct DenseGate {
+    int32_t target, mat;  // mat: gate index into the circuit's matrix table
+    uint64_t cmask, cvals;
+};
+bool dense_supported(int dtype, int kq, int n);
+int launch_dense(int dtype, void *psi, int n, int kq, const void *rmat, hipStream_t st);
+int launch_dense_compose(int dtype, const void *gates, int count, const double *mats, int kq, void *rmat,
+                         hipStream_t st);
 
 } // namespace sv

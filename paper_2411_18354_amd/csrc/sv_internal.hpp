@@ -137,6 +137,8 @@ struct Tuning {
     int tile_log2[2];     // fused-pass tile width (amplitudes = 2^m)
     int tile_low_bits[2]; // lowest qubits always inside a fused tile (contiguous runs)
     int fuse_min_gates;   // shortest run worth an LDS pass
+    int dense_qubits;     // k of dense k-qubit blocks (SV_DENSE)
+    int dense_min_gates;  // shortest stretch on qubits < k made a dense block
 };
 Tuning &tuning();
 

@@ -18,7 +18,9 @@ Tuning &tuning() {
     //  - 64 KiB LDS tiles for the fused pass.
     //  - fused tiles always hold the 6 (complex128) / 7 (complex64) lowest
     //    qubits, i.e. 1 KiB contiguous runs, plus qubits picked per run.
-    static Tuning t = {{3, 4}, 1, 1, {12, 13}, {6, 7}, 2};
+    //  - dense blocks (SV_DENSE) on the 4 lowest qubits for stretches of at
+    //    least 16 gates.
+    static Tuning t = {{3, 4}, 1, 1, {12, 13}, {6, 7}, 2, 4, 16};
     return t;
 }
 
@@ -40,6 +42,8 @@ static int find_key(const char *name, Key *out) {
         {"tile_low_bits_c128", &t.tile_low_bits[0], 1, 13},
         {"tile_low_bits_c64", &t.tile_low_bits[1], 1, 14},
         {"fuse_min_gates", &t.fuse_min_gates, 1, 1 << 20},
+        {"dense_qubits", &t.dense_qubits, 4, 5},
+        {"dense_min_gates", &t.dense_min_gates, 1, 1 << 20},
     };
     for (const Key &k : keys)
         if (name && strcmp(k.name, name) == 0) {

@@ -377,3 +377,26 @@ def test_generators_deterministic_and_shaped():
     assert len(c2.gates) == 20 * (32 + 31 + 8)
     U = oracle.gate_matrix("U", matrix=W.haar_unitary_2x2(2))
     assert np.allclose(U @ U.conj().T, np.eye(2), atol=1e-15)
+
+
+def test_block_low_matches_kron_and_gate_sequence():
+    """A k-qubit matrix on the lowest qubits equals kron(I, M) (dense), and the
+    matrix composed from a gate sequence on those qubits (by dense products)
+    acts like the sequence applied gate by gate."""
+    rng = np.random.default_rng(91)
+    for n, k in ((5, 2), (7, 4), (8, 5)):
+        z = rng.standard_normal((1 << k, 1 << k)) + 1j * rng.standard_normal((1 << k, 1 << k))
+        M, _ = np.linalg.qr(z)
+        psi = _rand_state(n, 92 + n)
+        got = oracle.apply_block_low(psi.copy(), n, k, M)
+        ref = np.kron(np.eye(1 << (n - k)), M) @ psi
+        assert np.max(np.abs(got - ref)) < 1e-14
+        gates = W.random_gates_n12(seed=n, n=k, ngates=30).gates
+        Mg = np.eye(1 << k, dtype=np.complex128)
+        for g in gates:
+            Mg = D.controlled_unitary(k, g.target, g.controls, g.values, oracle.gate_matrix(g.kind, g.theta)) @ Mg
+        a = oracle.apply_block_low(psi.copy(), n, k, Mg)
+        b = psi.copy()
+        for g in gates:
+            oracle.apply_gate(b, n, g.target, g.controls, g.values, oracle.gate_matrix(g.kind, g.theta))
+        assert np.max(np.abs(a - b)) < 1e-13
