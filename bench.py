@@ -267,6 +267,22 @@ def measure_extras(sv, W, torch, np, stream, with_layered):
                                       "gradients_per_s": round(len(circs) * 1e3 / t_bb, 1)}
     del buf, lbuf, views, lviews
     torch.cuda.empty_cache()
+    # ---- dense k-qubit block on matrix cores (4 GiB states)
+    for dt, td, n_d, k in (("c128", torch.complex128, 28, 4), ("c64", torch.complex64, 29, 5)):
+        log("dense block", dt, "k=%d n=%d" % (k, n_d))
+        st = torch.zeros(1 << n_d, dtype=td, device=dev)
+        rng = np.random.default_rng(k)
+        z = rng.standard_normal((1 << k, 1 << k)) + 1j * rng.standard_normal((1 << k, 1 << k))
+        M, _ = np.linalg.qr(z)
+        ms = _time_ms(torch, stream, lambda: sv.sv_apply_dense_low(st, k, M, stream=stream), 5)
+        amps = 1 << n_d
+        byts = 2 * amps * (16 if dt == "c128" else 8)
+        flops = amps * (8 << k)  # 2^(k+1) reals per row times 2^(k+1) multiply-adds
+        out["dense_k%d_n%d_%s" % (k, n_d, dt)] = {"ms": round(ms, 3), "GBps": round(byts / ms / 1e6, 1),
+                                                  "TFLOPs": round(flops / ms / 1e9, 2),
+                                                  "hbm_frac": round(byts / ms / 1e6 / HBM_PEAK_GBPS, 3)}
+        del st
+        torch.cuda.empty_cache()
     # ---- the paper's 29-qubit circuits, masked vs scheduled (vs fused)
     for name, circ in (("qft29", W.qft(29)), ("stream29", W.stream(29))):
         for dt, td in (("c64", torch.complex64), ("c128", torch.complex128)):

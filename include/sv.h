@@ -89,8 +89,10 @@ typedef enum sv_mode {
     SV_MODE_MASKED = 1, /* baseline: all 2^(n-1) pairs, control test per pair
                            (the paper's baseline kernel figure, Sec. III-A) */
     SV_MODE_PAIR = 2,   /* scheduled, one pair per iteration (Sec. III-B) */
-    SV_MODE_WAVE = 3,   /* scheduled at 64-amplitude granularity, partner
-                           exchanged inside the wavefront; target < 6 */
+    SV_MODE_WAVE = 3,   /* scheduled at amplitude granularity, 64 per
+                           wavefront, partner exchanged across lanes; the
+                           target must be among the 6 lowest index bits that
+                           are not scheduled controls */
     SV_MODE_TILE = 4    /* scheduled, LDS-staged tile of 2^m amplitudes;
                            target < m (m chosen by the library) */
 } sv_mode;
@@ -135,11 +137,32 @@ int sv_gate_plan(int n, int dtype, int target, uint64_t ctrl_mask,
  *   "wave_auto"       [0, 1]  SV_MODE_AUTO may choose the wavefront kernel
  *   "tile_log2_c128" [6, 13], "tile_log2_c64" [6, 14]  LDS tile width m of
  *       the fused pass and of SV_MODE_TILE (2^m amplitudes per tile)
+ *   "tile_low_bits_c128" [1, 13], "tile_low_bits_c64" [1, 14]  lowest
+ *       qubits every fused tile holds (runs of 2^bits contiguous amplitudes);
+ *       the other tile qubits are chosen per run
  *   "fuse_min_gates"  [1, 2^20]  shortest gate run fused into one LDS pass
+ *   "dense_qubits"    [4, 5]  k of dense blocks (SV_DENSE)
+ *   "dense_min_gates" [1, 2^20]  shortest stretch made a dense block
  * None of them changes results.  SV_EINVAL for an unknown key or a value out
  * of range.  Not thread-safe against concurrent launches. */
 int sv_tune_set(const char *key, int64_t value);
 int sv_tune_get(const char *key, int64_t *value);
+
+/* Autotuner: time candidate values of the knobs above on the current device
+ * (HIP events on st, a scratch state of 2^n amplitudes of the given dtype,
+ * 16 <= n <= 30) and keep the fastest: the low-control granule and policy,
+ * "wave_auto", and the fused tile width and contiguous low block.  Blocking
+ * (synchronises st).  When cache_path is not NULL the choice is stored there
+ * as one JSON object per line, keyed by device architecture and dtype (other
+ * lines are kept).  report (may be NULL) receives the timings, truncated to
+ * report_len bytes including the terminator.  Results never change. */
+int sv_autotune(int n, int dtype, const char *cache_path, char *report, int report_len, sv_stream_t st);
+
+/* Apply the records of a cache written by sv_autotune that match the current
+ * device's architecture (the environment variable SV_TUNE_ARCH, when set,
+ * names the architecture instead; then no device is needed).  SV_EINVAL for
+ * a missing file, a file without records or a malformed record. */
+int sv_tune_load(const char *path);
 
 /* ------------------------------------------------------------------ circuits
  *

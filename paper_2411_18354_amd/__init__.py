@@ -222,6 +222,22 @@ def sv_tune_set(key: str, value: int) -> None:
     _check(_L.sv_tune_set(key.encode(), int(value)))
 
 
+_sig("sv_autotune", [ctypes.c_int, ctypes.c_int, ctypes.c_char_p, ctypes.c_char_p, ctypes.c_int, _vp])
+_sig("sv_tune_load", [ctypes.c_char_p])
+
+
+def sv_autotune(n: int = 24, dtype: int = SV_C128, cache_path: Optional[str] = None, stream=None) -> str:
+    """Measure and apply the fastest launch choices; returns the timing report."""
+    buf = ctypes.create_string_buffer(8192)
+    _check(_L.sv_autotune(int(n), int(dtype), cache_path.encode() if cache_path else None, buf, 8192,
+                          stream_ptr(stream)))
+    return buf.value.decode()
+
+
+def sv_tune_load(path: str) -> None:
+    _check(_L.sv_tune_load(path.encode()))
+
+
 def sv_tune_get(key: str) -> int:
     v = _i64(0)
     _check(_L.sv_tune_get(key.encode(), ctypes.byref(v)))

@@ -107,3 +107,31 @@ def test_debug_indices_errors(sv):
     assert rc == sv.SV_EINVAL and "out_len" in sv.sv_last_error()
     rc = L.sv_debug_pair_indices(8, 0, None, 0, 0, None, 1 << 10, None)
     assert rc == sv.SV_EINVAL
+
+
+def test_tune_cache_load(sv, tmp_path, monkeypatch):
+    """A cache record for the named architecture is applied; records for other
+    architectures are ignored; malformed files are rejected."""
+    keys = ("granule_bits_c128", "low_policy", "wave_auto", "tile_log2_c128", "tile_low_bits_c128")
+    before = {k: sv.sv_tune_get(k) for k in keys}
+    p = tmp_path / "tune.json"
+    p.write_text('{"arch": "gfx000", "dtype": "c128", "granule_bits": 1, "low_policy": 0, "wave_auto": 0, '
+                 '"tile_log2": 9, "tile_low_bits": 4}\n'
+                 '{"arch": "gfx950:sramecc+:xnack-", "dtype": "c128", "granule_bits": 2, "low_policy": 0, '
+                 '"wave_auto": 0, "tile_log2": 11, "tile_low_bits": 5}\n')
+    monkeypatch.setenv("SV_TUNE_ARCH", "gfx950:sramecc+:xnack-")
+    try:
+        sv.sv_tune_load(str(p))
+        assert sv.sv_tune_get("granule_bits_c128") == 2
+        assert sv.sv_tune_get("tile_log2_c128") == 11 and sv.sv_tune_get("tile_low_bits_c128") == 5
+        assert sv.sv_tune_get("wave_auto") == 0 and sv.sv_tune_get("low_policy") == 0
+        bad = tmp_path / "bad.json"
+        bad.write_text('{"arch": "gfx950:sramecc+:xnack-", "dtype": "c128", "granule_bits": 99, '
+                       '"low_policy": 0, "wave_auto": 0, "tile_log2": 11, "tile_low_bits": 5}\n')
+        with pytest.raises(sv.SvError):
+            sv.sv_tune_load(str(bad))
+        with pytest.raises(sv.SvError):
+            sv.sv_tune_load(str(tmp_path / "missing.json"))
+    finally:
+        for k, v in before.items():
+            sv.sv_tune_set(k, v)
