@@ -115,7 +115,7 @@ def summarize_profile(trace_dir, fetch_dir, write_dir):
     lines = ["# Kernel trace: controlled-gate sweep, n=28 complex128", "",
              "Command (from the repository root; rocprofv3 1.x, ROCm 7.2):", "",
              "    rocprofv3 --kernel-trace --stats -f csv -d <dir> -o bench -- "
-             "python3 bench.py --steps 5 --warmup 1 --cpu-seconds 0 --no-masked --pmc-copy", "",
+             "python3 bench.py --steps 5 --warmup 1 --cpu-seconds 0 --no-masked --no-extras --pmc-copy", "",
              "kernel_source_hash: %s" % src_hash, "",
              "| kernel | calls | avg us | min us | max us | share |", "|---|---|---|---|---|---|"]
     for r in stats[:12]:
@@ -148,9 +148,9 @@ def summarize_profile(trace_dir, fetch_dir, write_dir):
     tl = ["# HBM traffic of the dominant kernel: controlled-gate sweep, n=28 complex128", "",
           "Commands (each its own run, from the repository root):", "",
           "    rocprofv3 --pmc FETCH_SIZE -f csv -d <fetch_dir> -o bench -- python3 bench.py --steps 2 "
-          "--warmup 0 --cpu-seconds 0 --no-masked --pmc-copy",
+          "--warmup 0 --cpu-seconds 0 --no-masked --no-extras --pmc-copy",
           "    rocprofv3 --pmc WRITE_SIZE -f csv -d <write_dir> -o bench -- python3 bench.py --steps 2 "
-          "--warmup 0 --cpu-seconds 0 --no-masked --pmc-copy", "",
+          "--warmup 0 --cpu-seconds 0 --no-masked --no-extras --pmc-copy", "",
           "Counters are KiB per dispatch.  Each is scaled by what it reads for the library's plain copy "
           "kernel `sv::k_copy` moving a known 1 GiB (read 1 GiB, write 1 GiB): FETCH scale %.4f, "
           "WRITE scale %.4f." % (f_scale, w_scale), "",
@@ -230,13 +230,22 @@ def measure_extras(sv, W, torch, np, stream, with_layered):
         offs = np.concatenate([[0], np.cumsum([1 << n for n in ns])])
         buf = torch.zeros(int(offs[-1]), dtype=td, device=dev)
         views = [buf[int(offs[i]):int(offs[i + 1])] for i in range(len(circs))]
-        t_b4 = _time_ms(torch, stream, lambda: sv.sv_apply_circuits_batched(views, circs, stream=stream), 3)
+        t0 = time.perf_counter()
+        batch = sv.Batch(views, circs)
+        t_create = (time.perf_counter() - t0) * 1e3
+        t_b4 = _time_ms(torch, stream, lambda: batch.run(stream=stream), 3)
+        t0 = time.perf_counter()
+        sv.sv_apply_circuits_batched(views, circs, stream=stream)
+        torch.cuda.synchronize()
+        t_once = (time.perf_counter() - t0) * 1e3
         ngates = sum(len(c.gates) for c in circs)
         alg = sum(len(c.gates) * (1 << c.n) * 2 * (16 if dt == "c128" else 8) for c in circs)
         out["batched_uneven4096_" + dt] = {"circuits": len(circs), "gates": ngates, "ms": round(t_b4, 2),
                                         "circuits_per_s": round(len(circs) * 1e3 / t_b4, 1),
                                         "gate_updates_per_s": round(ngates * 1e3 / t_b4, 1),
-                                        "unfused_equivalent_GBps": round(alg / t_b4 / 1e6, 1)}
+                                        "unfused_equivalent_GBps": round(alg / t_b4 / 1e6, 1),
+                                        "plan_ms": round(t_create, 1), "one_shot_ms": round(t_once, 1)}
+        batch.close()
         del buf, views
         torch.cuda.empty_cache()
     log("batched adjoint: 256 x n=16")
@@ -251,20 +260,23 @@ def measure_extras(sv, W, torch, np, stream, with_layered):
     bgrad = torch.empty(bparams.numel(), dtype=torch.float64, device=dev)
     bloss = torch.empty(len(circs), dtype=torch.float64, device=dev)
 
+    hbatch = sv.Batch(views, circs, lam_states=lviews, hamiltonians=hams)
+
     def bfwd():
         buf.zero_()
         buf[::1 << 16] = 1
-        sv.sv_apply_circuits_batched(views, circs, bparams, stream=stream)
+        hbatch.run(bparams, stream=stream)
 
     def bboth():
         bfwd()
-        sv.sv_adjoint_grad_batched(views, lviews, circs, bparams, hams, grad=bgrad, loss=bloss, stream=stream)
+        hbatch.adjoint(bparams, grad=bgrad, loss=bloss, stream=stream)
 
     t_bf = _time_ms(torch, stream, bfwd, 3)
     t_bb = _time_ms(torch, stream, bboth, 3) - t_bf
     out["batched_adjoint_hea256_n16"] = {"circuits": len(circs), "n": 16, "params_each": circs[0].nparams,
                                       "forward_ms": round(t_bf, 2), "backward_ms": round(t_bb, 2),
                                       "gradients_per_s": round(len(circs) * 1e3 / t_bb, 1)}
+    hbatch.close()
     del buf, lbuf, views, lviews
     torch.cuda.empty_cache()
     # ---- dense k-qubit block on matrix cores (4 GiB states)

@@ -309,7 +309,9 @@ int sv_adjoint_grad(const sv_state_t *psi, const sv_state_t *lam, const sv_gate_
  * Many independent circuits, each on its own state (n may differ; one dtype
  * per batch), run by one persistent launch: each workgroup takes the next
  * circuit from a device work queue (longest first) and applies all its
- * gates; a state of at most 64 KiB stays in LDS for the whole circuit.
+ * gates; a state of at most 64 KiB stays in LDS for the whole circuit, a
+ * larger one runs its fused plan pass by pass (a fused run through LDS tiles
+ * over the run's qubit set, other gates as pair loops over the state).
  *   states        ncirc state views (device buffers must not overlap)
  *   gates         all circuits' gates concatenated; circuit c owns
  *                 gates[gate_offsets[c] .. gate_offsets[c+1])
@@ -334,6 +336,29 @@ int sv_adjoint_grad_batched(const sv_state_t *psi_states, const sv_state_t *lam_
                             const sv_gate_t *gates, const int64_t *gate_offsets, const double *params_dev,
                             const int64_t *param_offsets, int64_t nparams_total, const sv_pauli_t *terms,
                             const int64_t *term_offsets, double *grad_dev, double *loss_dev, sv_stream_t st);
+
+/* A planned batch kept on the device, for running the same circuits many
+ * times (new angles, new states in the same buffers).  sv_batch_create
+ * validates and plans every circuit (host threads for large batches) and
+ * uploads the tables; the batch keeps the state pointers given here, so those
+ * buffers must outlive it and keep their shapes.  Arguments are those of
+ * sv_apply_circuits_batched / sv_adjoint_grad_batched; with lam_states NULL
+ * (terms and term_offsets ignored) the batch only runs forward.
+ *   sv_batch_run      the forward circuits (fused plan), angles from
+ *                     params_dev as in sv_apply_circuits_batched
+ *   sv_batch_adjoint  the batched adjoint gradients, as in
+ *                     sv_adjoint_grad_batched (psi_states hold the final
+ *                     forward states and are consumed)
+ * Runs of one batch use one device counter: enqueue them on one stream (or
+ * order them).  sv_batch_destroy waits for the last run, then frees the
+ * device tables; NULL is a no-op. */
+typedef struct sv_batch sv_batch_t;
+int sv_batch_create(const sv_state_t *states, const sv_state_t *lam_states, int ncirc, const sv_gate_t *gates,
+                    const int64_t *gate_offsets, const int64_t *param_offsets, int64_t nparams_total,
+                    const sv_pauli_t *terms, const int64_t *term_offsets, sv_batch_t **out);
+int sv_batch_run(sv_batch_t *b, const double *params_dev, sv_stream_t st);
+int sv_batch_adjoint(sv_batch_t *b, const double *params_dev, double *grad_dev, double *loss_dev, sv_stream_t st);
+int sv_batch_destroy(sv_batch_t *b);
 
 /* Write, for each reduced iteration index i_r in [0, 2^(n-1-ncontrols)), the
  * index of the first pair element (bit target clear) that the scheduled

@@ -267,6 +267,17 @@ class sv_gate_t(ctypes.Structure):
                 ("theta", ctypes.c_double), ("U", ctypes.c_double * 8)]
 
 
+def _gate_dtype():
+    import numpy as np
+    dt = np.dtype([("kind", "<i4"), ("target", "<i4"), ("ctrl_mask", "<u8"), ("ctrl_vals", "<u8"),
+                   ("param", "<i4"), ("reserved", "<i4"), ("theta", "<f8"), ("U", "<f8", (8,))])
+    assert dt.itemsize == ctypes.sizeof(sv_gate_t)
+    return dt
+
+
+_GATE_DTYPE = _gate_dtype()
+
+
 def kind_code(kind: str) -> int:
     adj = kind.startswith("~")
     return KIND_CODES[kind[1:] if adj else kind] | (SV_G_ADJOINT if adj else 0)
@@ -274,21 +285,43 @@ def kind_code(kind: str) -> int:
 
 def circuit_gates(circ_or_gates):
     """ctypes array of sv_gate_t from a workloads.Circuit (or a gate list)."""
+    import numpy as np
     gates = getattr(circ_or_gates, "gates", circ_or_gates)
-    arr = (sv_gate_t * max(1, len(gates)))()
+    n = len(gates)
+    K, T, CM, CV, P, TH, mats = [], [], [], [], [], [], []
+    codes = {}
     for i, g in enumerate(gates):
-        e = arr[i]
-        e.kind = kind_code(g.kind)
-        e.target = int(g.target)
-        vals = g.values if len(g.values) else (1,) * len(g.controls)
-        e.ctrl_mask = sum(1 << int(q) for q in g.controls)
-        e.ctrl_vals = sum(1 << int(q) for q, v in zip(g.controls, vals) if v)
-        e.param = int(g.param) if g.param is not None and g.param >= 0 else -1
-        e.reserved = 0
-        e.theta = float(g.theta)
+        code = codes.get(g.kind)
+        if code is None:
+            code = codes[g.kind] = kind_code(g.kind)
+        cm = cv = 0
+        if g.controls:
+            vals = g.values
+            for j, q in enumerate(g.controls):
+                b = 1 << int(q)
+                cm |= b
+                if not len(vals) or vals[j]:
+                    cv |= b
+        p = g.param
+        K.append(code)
+        T.append(int(g.target))
+        CM.append(cm)
+        CV.append(cv)
+        P.append(-1 if p is None or p < 0 else int(p))
+        TH.append(float(g.theta))
         if g.matrix is not None:
-            for k in range(8):
-                e.U[k] = float(g.matrix[k])
+            mats.append((i, g.matrix))
+    rec = np.zeros(max(1, n), dtype=_GATE_DTYPE)
+    if n:
+        rec["kind"][:n] = K
+        rec["target"][:n] = T
+        rec["ctrl_mask"][:n] = np.array(CM, dtype=np.uint64)
+        rec["ctrl_vals"][:n] = np.array(CV, dtype=np.uint64)
+        rec["param"][:n] = P
+        rec["theta"][:n] = TH
+        for i, m in mats:
+            rec["U"][i] = [float(x) for x in m]
+    arr = (sv_gate_t * max(1, n)).from_buffer_copy(rec.tobytes())
     arr._sv_count = len(gates)
     return arr
 
@@ -391,4 +424,4 @@ def sv_apply_dense_low(state, k: int, M, stream=None) -> None:
 
 from .observables import (sv_pauli_t, pauli_terms, sv_expect, sv_expect_terms, sv_apply_pauli_sum,  # noqa: E402
                           sv_adjoint_grad, SvExpectation, ExpectationModel)
-from .batched import sv_apply_circuits_batched, sv_adjoint_grad_batched  # noqa: E402
+from .batched import sv_apply_circuits_batched, sv_adjoint_grad_batched, Batch  # noqa: E402

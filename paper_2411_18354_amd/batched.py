@@ -1,5 +1,6 @@
 """Binding of the batched entry points (sv_apply_circuits_batched,
-sv_adjoint_grad_batched).  Argument marshalling only."""
+sv_adjoint_grad_batched, and the planned batch sv_batch_create / sv_batch_run /
+sv_batch_adjoint / sv_batch_destroy).  Argument marshalling only."""
 from __future__ import annotations
 
 import ctypes
@@ -14,6 +15,12 @@ _sig("sv_apply_circuits_batched", [ctypes.POINTER(sv_state_t), ctypes.c_int, cty
 _sig("sv_adjoint_grad_batched", [ctypes.POINTER(sv_state_t), ctypes.POINTER(sv_state_t), ctypes.c_int,
                                  ctypes.POINTER(sv_gate_t), _i64p, _vp, _i64p, ctypes.c_int64,
                                  ctypes.POINTER(sv_pauli_t), _i64p, _vp, _vp, _vp])
+_sig("sv_batch_create", [ctypes.POINTER(sv_state_t), ctypes.POINTER(sv_state_t), ctypes.c_int,
+                         ctypes.POINTER(sv_gate_t), _i64p, _i64p, ctypes.c_int64, ctypes.POINTER(sv_pauli_t), _i64p,
+                         ctypes.POINTER(_vp)])
+_sig("sv_batch_run", [_vp, _vp, _vp])
+_sig("sv_batch_adjoint", [_vp, _vp, _vp, _vp, _vp])
+_sig("sv_batch_destroy", [_vp])
 
 
 def _states(tensors):
@@ -74,3 +81,57 @@ def sv_adjoint_grad_batched(psi_states: Sequence, lam_states: Sequence, circuits
                                       int(params.numel()), tarr, toff, ctypes.c_void_p(grad.data_ptr()),
                                       ctypes.c_void_p(loss.data_ptr()), stream_ptr(stream)))
     return grad[:int(params.numel())], loss
+
+
+class Batch:
+    """A planned batch on the device (sv_batch_create).  states (and, for
+    gradients, lam_states and hamiltonians) are bound at creation: run()
+    applies the circuits to whatever those buffers hold, adjoint() computes
+    the batched gradients from the final states they hold."""
+
+    def __init__(self, states: Sequence, circuits: Sequence, param_counts=None, lam_states=None,
+                 hamiltonians=None, nparams_total: Optional[int] = None):
+        self._keep = (list(states), list(lam_states) if lam_states is not None else None)
+        st = _states(states)
+        ls = _states(lam_states) if lam_states is not None else None
+        garr, goff = _concat_gates(circuits)
+        if param_counts is None:
+            param_counts = [getattr(c, "nparams", 0) or 0 for c in circuits]
+        poff = _offsets(param_counts)
+        self.nparams_total = int(poff[len(circuits)]) if nparams_total is None else int(nparams_total)
+        self.ncirc = len(circuits)
+        tarr = toff = None
+        if lam_states is not None:
+            tarr = pauli_terms([t for h in hamiltonians for t in h])
+            toff = _offsets([len(h) for h in hamiltonians])
+        self.device = states[0].device
+        h = _vp()
+        _check(_L.sv_batch_create(st, ls, len(circuits), garr, goff, poff, self.nparams_total, tarr, toff,
+                                  ctypes.byref(h)))
+        self._h = h
+
+    def run(self, params=None, stream=None) -> None:
+        p = ctypes.c_void_p(0 if params is None else params.data_ptr())
+        _check(_L.sv_batch_run(self._h, p, stream_ptr(stream)))
+
+    def adjoint(self, params, grad=None, loss=None, stream=None):
+        """Returns (grad, loss) device float64 tensors."""
+        import torch
+        if grad is None:
+            grad = torch.empty(max(1, self.nparams_total), dtype=torch.float64, device=self.device)
+        if loss is None:
+            loss = torch.empty(self.ncirc, dtype=torch.float64, device=self.device)
+        _check(_L.sv_batch_adjoint(self._h, ctypes.c_void_p(params.data_ptr()), ctypes.c_void_p(grad.data_ptr()),
+                                   ctypes.c_void_p(loss.data_ptr()), stream_ptr(stream)))
+        return grad[:self.nparams_total], loss
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            _L.sv_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -9,14 +9,20 @@
 //    bytes) is read once, all gates are applied in LDS, and it is written
 //    back once.
 //  - A larger state is processed pass by pass from global memory with the
-//    circuit's fused plan: fused runs tile by tile through LDS, other gates as
-//    pair loops over the state; a workgroup barrier separates passes.
+//    circuit's fused plan: a fused run visits the state tile by tile, a tile
+//    being the 2^m amplitudes that share the index bits outside the run's
+//    qubit set S (the lowest qubits plus planner-chosen ones), held in LDS
+//    while the run's gates act on it; other gates are pair loops over the
+//    state.  A workgroup barrier separates passes.
 // Each gate visits only the amplitude pairs whose controls hold: the pair
 // index is built by inserting the target bit (0) and the control bits (their
 // values) into the iteration counter, lowest position first (Sec. III-B).
 #include <algorithm>
+#include <atomic>
 #include <cstring>
 #include <numeric>
+#include <string>
+#include <thread>
 
 #include "gates.hpp"
 #include "pauli.hpp"
@@ -25,7 +31,8 @@ namespace sv {
 
 int validate_circuit_gate(int n, int nparams, const sv_gate_t &g, int index);
 int circuit_plan_capped(int n, int dtype, const sv_gate_t *gates, int ngates, int nparams, int flags, int m_cap,
-                        int32_t *order, int32_t *pass_of, int64_t *npasses, int *m_used, bool general);
+                        int32_t *order, int32_t *pass_of, int64_t *npasses, int *m_used, bool general,
+                        bool diag_any, std::vector<uint64_t> *pass_S);
 
 constexpr int kBatchThreads = 512;
 constexpr size_t kBatchLds = 65536;
@@ -37,6 +44,12 @@ struct BGate {
     int32_t target;
     int32_t pass;     // pass number within its circuit (fused runs share one)
     uint64_t cmask, cvals;
+    // fused runs: the tile's qubit set, and target and controls inside S
+    // renumbered to tile-local bit positions
+    uint64_t S;
+    int32_t ltarget;
+    int32_t pad;
+    uint64_t lcmask, lcvals;
 };
 
 struct BCirc {
@@ -62,6 +75,20 @@ __device__ __forceinline__ uint64_t insert_bits(uint64_t x, uint64_t positions, 
     return x;
 }
 
+// Global offset of tile-local index k: its a low bits stay in place, its
+// higher bits go, in ascending order, to the positions of the bits of high.
+__device__ __forceinline__ uint64_t scatter_bits(uint64_t k, int a, uint64_t high) {
+    uint64_t off = k & ((1ull << a) - 1);
+    uint64_t h = k >> a;
+    while (h) {
+        const int p = __builtin_ctzll(high);
+        high &= high - 1;
+        off |= (h & 1ull) << p;
+        h >>= 1;
+    }
+    return off;
+}
+
 // The gate's matrix (angle from params when parameterised), or its conjugate
 // transpose for the reverse sweep.
 template <typename R>
@@ -77,17 +104,18 @@ __device__ __forceinline__ Mat2<R> bgate_mat(const BGate &g, const double *param
     return Mat2<R>{(R)m[0], (R)m[1], (R)m[2], (R)m[3], (R)m[4], (R)m[5], (R)m[6], (R)m[7]};
 }
 
-// Apply one gate to amplitudes held at base[0 .. 2^nbits) (LDS or global),
-// controls below nbits enumerated, controls at or above nbits already known
-// to hold.
+// Apply one gate (target, controls) to amplitudes held at base[0 .. 2^nbits)
+// (LDS or global), controls below nbits enumerated, controls at or above
+// nbits already known to hold.
 template <typename R>
-__device__ __forceinline__ void gate_on_block(cplx_t<R> *base, int nbits, const BGate &g, const Mat2<R> &mm) {
+__device__ __forceinline__ void gate_on_block(cplx_t<R> *base, int nbits, int target, uint64_t cmask, uint64_t cvals,
+                                              const Mat2<R> &mm) {
     const uint64_t lowm = (1ull << nbits) - 1;
-    const uint64_t cm = g.cmask & lowm;
-    const uint64_t pos = cm | (1ull << g.target);
+    const uint64_t cm = cmask & lowm;
+    const uint64_t pos = cm | (1ull << target);
     const uint64_t npairs = 1ull << (nbits - 1 - __popcll(cm));
-    const uint64_t st = 1ull << g.target;
-    const uint64_t cv = g.cvals & cm;
+    const uint64_t st = 1ull << target;
+    const uint64_t cv = cvals & cm;
     constexpr int U = 4;  // pairs per lane per step: 2U loads in flight
     for (uint64_t i0 = threadIdx.x; i0 < npairs; i0 += (uint64_t)U * kBatchThreads) {
         cplx_t<R> x[U], y[U];
@@ -123,48 +151,54 @@ __device__ void run_circuit_block(const BCirc &c, const BGate *__restrict__ gate
         __syncthreads();
         for (int i = 0; i < c.ngates; ++i) {
             const BGate &g = gates[c.first_gate + i];
-            gate_on_block<R>(lds, c.n, g, bgate_mat<R>(g, params, false));
+            gate_on_block<R>(lds, c.n, g.target, g.cmask, g.cvals, bgate_mat<R>(g, params, false));
             __syncthreads();
         }
         for (uint64_t k = threadIdx.x; k < N; k += kBatchThreads)
             psi[k] = lds[k];
         return;
     }
-    const uint64_t T = 1ull << c.m;
     int i = 0;
     while (i < c.ngates) {
         const int pass = gates[c.first_gate + i].pass;
         int j = i;
         while (j < c.ngates && gates[c.first_gate + j].pass == pass)
             ++j;
-        if (j - i > 1) {  // fused run: every target < m
-            for (uint64_t base = 0; base < N; base += T) {
+        if (j - i > 1) {  // fused run: every target in S
+            const uint64_t S = gates[c.first_gate + i].S;
+            const int m = __popcll(S);
+            const int a = __builtin_ctzll(~S);  // S holds qubits 0 .. a-1
+            const uint64_t lowm = (1ull << a) - 1, high = S & ~lowm;
+            const uint64_t T = 1ull << m, ntiles = N >> m;
+            for (uint64_t tt = 0; tt < ntiles; ++tt) {
+                // the tile's fixed bits: tt spread over the qubits outside S
+                const uint64_t base = insert_bits(tt << a, high, 0);
                 bool any = false;
                 for (int k = i; k < j; ++k) {
                     const BGate &g = gates[c.first_gate + k];
-                    const uint64_t hm = g.cmask & ~(T - 1);
-                    any |= (base & hm) == (g.cvals & hm);
+                    const uint64_t om = g.cmask & ~S;
+                    any |= (base & om) == (g.cvals & om);
                 }
                 if (!any)
                     continue;
                 for (uint64_t k = threadIdx.x; k < T; k += kBatchThreads)
-                    lds[k] = psi[base + k];
+                    lds[k] = psi[base | scatter_bits(k, a, high)];
                 __syncthreads();
                 for (int k = i; k < j; ++k) {
                     const BGate &g = gates[c.first_gate + k];
-                    const uint64_t hm = g.cmask & ~(T - 1);
-                    if ((base & hm) != (g.cvals & hm))
+                    const uint64_t om = g.cmask & ~S;
+                    if ((base & om) != (g.cvals & om))
                         continue;
-                    gate_on_block<R>(lds, c.m, g, bgate_mat<R>(g, params, false));
+                    gate_on_block<R>(lds, m, g.ltarget, g.lcmask, g.lcvals, bgate_mat<R>(g, params, false));
                     __syncthreads();
                 }
                 for (uint64_t k = threadIdx.x; k < T; k += kBatchThreads)
-                    psi[base + k] = lds[k];
+                    psi[base | scatter_bits(k, a, high)] = lds[k];
                 __syncthreads();
             }
         } else {
             const BGate &g = gates[c.first_gate + i];
-            gate_on_block<R>(psi, c.n, g, bgate_mat<R>(g, params, false));
+            gate_on_block<R>(psi, c.n, g.target, g.cmask, g.cvals, bgate_mat<R>(g, params, false));
             __syncthreads();
         }
         i = j;
@@ -297,6 +331,138 @@ __global__ __launch_bounds__(kBatchThreads) void k_batched_adjoint(
 
 // ----------------------------------------------------------------- host
 
+// One circuit's tables, built independently of the others (so circuits can
+// be planned in parallel) and concatenated afterwards.
+struct CircBuild {
+    BCirc bc;
+    std::vector<BGate> gates;
+    std::vector<double> gens;      // generators of the parameterised gates
+    std::vector<int32_t> gen_of;   // per gate: index into gens / 8, or -1
+    std::vector<DTerm> terms;
+    double cost = 0.0;
+    int err = SV_OK;
+    std::string msg;
+};
+
+struct BatchArgs {
+    const sv_state_t *states, *lams;
+    int ncirc;
+    const sv_gate_t *gates;
+    const int64_t *gate_off, *param_off;
+    int64_t nparams_total;
+    const sv_pauli_t *terms;
+    const int64_t *term_off;
+};
+
+// Tables of circuit c.  adjoint: gates in program order with generators and
+// the Hamiltonian; otherwise the fused plan's order with each fused gate's
+// tile set and tile-local masks.
+static int build_circuit(const BatchArgs &A, int c, int dtype, bool adjoint, CircBuild *out) {
+    const sv_state_t &s = A.states[c];
+    const int64_t g0 = A.gate_off[c], g1 = A.gate_off[c + 1];
+    const int64_t p0 = A.param_off ? A.param_off[c] : 0, p1 = A.param_off ? A.param_off[c + 1] : 0;
+    BCirc &bc = out->bc;
+    memset(&bc, 0, sizeof(bc));
+    bc.psi = s.data;
+    bc.lam = adjoint ? A.lams[c].data : nullptr;
+    bc.n = s.n;
+    // the fused tiles must fit the workgroup's LDS buffer
+    const int m_cap = dtype == SV_C128 ? 12 : 13;  // 2^m amplitudes <= kBatchLds bytes
+    const int tl = tuning().tile_log2[dtype == SV_C128 ? 0 : 1];
+    bc.m = std::min(std::min(tl, s.n), m_cap);
+    bc.ngates = (int32_t)(g1 - g0);
+    bc.first_param = (int32_t)p0;
+    bc.nparams = (int32_t)(p1 - p0);
+    std::vector<int32_t> ord(bc.ngates), pas(bc.ngates);
+    std::vector<uint64_t> pass_S;
+    if (bc.ngates > 0) {
+        for (int64_t i = g0; i < g1; ++i)
+            SV_TRY(validate_circuit_gate(s.n, (int)(p1 - p0), A.gates[i], (int)(i - g0)));
+        if (adjoint) {
+            std::iota(ord.begin(), ord.end(), 0);
+            std::iota(pas.begin(), pas.end(), 0);
+        } else {
+            int64_t np = 0;
+            int m_used = 0;
+            // qubit-set tiles; diagonal gates join a run only with their
+            // target in S (the batch kernel has no elementwise sweeps)
+            SV_TRY(circuit_plan_capped(s.n, dtype, A.gates + g0, bc.ngates, (int)(p1 - p0), SV_FUSE, m_cap,
+                                       ord.data(), pas.data(), &np, &m_used, true, false, &pass_S));
+            if (m_used != bc.m)
+                return fail(SV_EINVAL, "planner tile width %d != %d", m_used, bc.m);
+        }
+    }
+    double work = 0.0;
+    out->gates.reserve(bc.ngates);
+    for (int k = 0; k < bc.ngates; ++k) {
+        const sv_gate_t &g = A.gates[g0 + ord[k]];
+        BGate b;
+        memset(&b, 0, sizeof(b));
+        if (g.param < 0)
+            gate_matrix(g.kind, g.theta, g.U, b.m);
+        else
+            for (int q = 0; q < 8; ++q)
+                b.m[q] = g.U[q];
+        b.kind = g.kind;
+        b.param = g.param >= 0 ? (int32_t)(p0 + g.param) : -1;
+        b.target = g.target;
+        b.pass = pas[k];
+        b.cmask = g.ctrl_mask;
+        b.cvals = g.ctrl_vals;
+        b.S = pass_S.empty() ? 0 : pass_S[pas[k]];
+        b.ltarget = -1;
+        if (b.S) {
+            if (!((b.S >> g.target) & 1) || popcount64(b.S) > m_cap)
+                return fail(SV_EINVAL, "fused gate outside its tile or tile too wide");
+            b.ltarget = popcount64(b.S & ((1ull << g.target) - 1));
+            int q = 0;
+            for (int bit = 0; bit < 64; ++bit)
+                if ((b.S >> bit) & 1) {
+                    b.lcmask |= ((g.ctrl_mask >> bit) & 1ull) << q;
+                    b.lcvals |= ((g.ctrl_vals >> bit) & 1ull) << q;
+                    ++q;
+                }
+            b.lcvals &= b.lcmask;
+        }
+        int gs = -1;
+        if (adjoint && g.param >= 0) {
+            double a[8];
+            gate_generator(g.kind, a);
+            if (g.kind & SV_G_ADJOINT) {
+                for (int q = 1; q < 8; q += 2)
+                    a[q] = -a[q];
+                std::swap(a[2], a[4]);
+                std::swap(a[3], a[5]);
+            }
+            gs = (int)(out->gens.size() / 8);
+            out->gens.insert(out->gens.end(), a, a + 8);
+        }
+        out->gen_of.push_back(gs);
+        out->gates.push_back(b);
+        work += std::ldexp(1.0, s.n - popcount64(g.ctrl_mask));
+    }
+    if (adjoint) {
+        const int64_t t0 = A.term_off[c], t1 = A.term_off[c + 1];
+        if (t0 < 0 || t1 <= t0)
+            return fail(SV_EINVAL, "needs at least one term");
+        const uint64_t full = (1ull << s.n) - 1;
+        bc.nterms = (int32_t)(t1 - t0);
+        for (int64_t j = t0; j < t1; ++j) {
+            if ((A.terms[j].x_mask | A.terms[j].z_mask) & ~full)
+                return fail(SV_EINVAL, "term %lld acts on qubits >= n", (long long)(j - t0));
+            DTerm d;
+            d.coef = A.terms[j].coef;
+            d.z = A.terms[j].z_mask;
+            d.ny = popcount64(A.terms[j].x_mask & A.terms[j].z_mask) & 3;
+            d.idx = (int32_t)A.terms[j].x_mask;  // x mask (n <= 31 in batches)
+            out->terms.push_back(d);
+        }
+        work *= 2.0;
+    }
+    out->cost = work;
+    return SV_OK;
+}
+
 struct BatchHost {
     std::vector<BCirc> circs;
     std::vector<BGate> gates;
@@ -306,128 +472,96 @@ struct BatchHost {
     std::vector<DTerm> terms;
 };
 
-static int build_batch(const sv_state_t *states, const sv_state_t *lams, int ncirc, const sv_gate_t *gates,
-                       const int64_t *gate_off, const int64_t *param_off, int64_t nparams_total,
-                       const sv_pauli_t *terms, const int64_t *term_off, bool adjoint, BatchHost *h, int *dtype) {
-    if (ncirc < 1 || !states || !gate_off || (gate_off[ncirc] > 0 && !gates))
-        return fail(SV_EINVAL, "bad batch description (ncirc %d)", ncirc);
-    *dtype = states[0].dtype;
-    std::vector<double> cost(ncirc);
-    const int tl = tuning().tile_log2[*dtype == SV_C128 ? 0 : 1];
-    for (int c = 0; c < ncirc; ++c) {
-        const sv_state_t &s = states[c];
+// Checks the batch description, plans every circuit (in parallel over host
+// threads for large batches) and concatenates the tables; circuits are
+// ordered by decreasing cost for the work queue.
+static int build_batch(const BatchArgs &A, bool adjoint, BatchHost *h, int *dtype) {
+    if (A.ncirc < 1 || !A.states || !A.gate_off || (A.gate_off[A.ncirc] > 0 && !A.gates))
+        return fail(SV_EINVAL, "bad batch description (ncirc %d)", A.ncirc);
+    if (adjoint && (!A.term_off || !A.terms || !A.lams || !A.param_off))
+        return fail(SV_EINVAL, "batched adjoint needs lambda states, param offsets, terms and term offsets");
+    *dtype = A.states[0].dtype;
+    int64_t total_gates = 0;
+    for (int c = 0; c < A.ncirc; ++c) {
+        const sv_state_t &s = A.states[c];
         int r = validate_state(&s);
         if (r != SV_OK)
             return fail(r, "circuit %d: %s", c, sv_last_error());
         if (s.dtype != *dtype)
             return fail(SV_EINVAL, "circuit %d: all states of a batch need one dtype", c);
         if (adjoint) {
-            r = validate_state(&lams[c]);
+            r = validate_state(&A.lams[c]);
             if (r != SV_OK)
                 return fail(r, "circuit %d (lambda): %s", c, sv_last_error());
-            if (lams[c].n != s.n || lams[c].dtype != s.dtype || lams[c].data == s.data)
+            if (A.lams[c].n != s.n || A.lams[c].dtype != s.dtype || A.lams[c].data == s.data)
                 return fail(SV_EINVAL, "circuit %d: lambda must be a distinct state of the same shape", c);
-        }
-        const int64_t g0 = gate_off[c], g1 = gate_off[c + 1];
-        if (g0 < 0 || g1 < g0)
-            return fail(SV_EINVAL, "circuit %d: bad gate offsets", c);
-        const int64_t p0 = param_off ? param_off[c] : 0, p1 = param_off ? param_off[c + 1] : 0;
-        if (p0 < 0 || p1 < p0 || p1 > nparams_total)
-            return fail(SV_EINVAL, "circuit %d: bad parameter offsets", c);
-        BCirc bc;
-        memset(&bc, 0, sizeof(bc));
-        bc.psi = s.data;
-        bc.lam = adjoint ? lams[c].data : nullptr;
-        bc.n = s.n;
-        // the fused tiles must fit the workgroup's LDS buffer
-        const int m_cap = *dtype == SV_C128 ? 12 : 13;  // 2^m amplitudes <= kBatchLds bytes
-        bc.m = std::min(std::min(tl, s.n), m_cap);
-        bc.first_gate = (int32_t)h->gates.size();
-        bc.ngates = (int32_t)(g1 - g0);
-        bc.first_param = (int32_t)p0;
-        bc.nparams = (int32_t)(p1 - p0);
-        // fused plan of this circuit (host planner, shared with sv_circuit_plan)
-        std::vector<int32_t> ord(bc.ngates), pas(bc.ngates);
-        if (bc.ngates > 0) {
-            for (int64_t i = g0; i < g1; ++i) {
-                r = validate_circuit_gate(s.n, (int)(p1 - p0), gates[i], (int)(i - g0));
-                if (r != SV_OK)
-                    return fail(r, "circuit %d: %s", c, sv_last_error());
-            }
-            if (adjoint) {
-                std::iota(ord.begin(), ord.end(), 0);
-                std::iota(pas.begin(), pas.end(), 0);
-            } else {
-                int64_t np = 0;
-                int m_used = 0;
-                r = circuit_plan_capped(s.n, *dtype, gates + g0, bc.ngates, (int)(p1 - p0), SV_FUSE, m_cap,
-                                        ord.data(), pas.data(), &np, &m_used, false);
-                if (r != SV_OK)
-                    return fail(r, "circuit %d: %s", c, sv_last_error());
-                if (m_used != bc.m)
-                    return fail(SV_EINVAL, "circuit %d: planner tile width %d != %d", c, m_used, bc.m);
-            }
-        }
-        double work = 0.0;
-        for (int k = 0; k < bc.ngates; ++k) {
-            const sv_gate_t &g = gates[g0 + ord[k]];
-            BGate b;
-            memset(&b, 0, sizeof(b));
-            if (g.param < 0)
-                gate_matrix(g.kind, g.theta, g.U, b.m);
-            else
-                for (int q = 0; q < 8; ++q)
-                    b.m[q] = g.U[q];
-            b.kind = g.kind;
-            b.param = g.param >= 0 ? (int32_t)(p0 + g.param) : -1;
-            b.target = g.target;
-            b.pass = pas[k];
-            b.cmask = g.ctrl_mask;
-            b.cvals = g.ctrl_vals;
-            int gs = -1;
-            if (adjoint && g.param >= 0) {
-                double a[8];
-                gate_generator(g.kind, a);
-                if (g.kind & SV_G_ADJOINT) {
-                    for (int q = 1; q < 8; q += 2)
-                        a[q] = -a[q];
-                    std::swap(a[2], a[4]);
-                    std::swap(a[3], a[5]);
-                }
-                gs = (int)(h->gens.size() / 8);
-                h->gens.insert(h->gens.end(), a, a + 8);
-            }
-            h->gen_of.push_back(gs);
-            h->gates.push_back(b);
-            work += std::ldexp(1.0, s.n - popcount64(g.ctrl_mask));
-        }
-        if (adjoint) {
-            if (!term_off || !terms)
-                return fail(SV_EINVAL, "batched adjoint needs terms and term offsets");
-            const int64_t t0 = term_off[c], t1 = term_off[c + 1];
-            if (t0 < 0 || t1 <= t0)
-                return fail(SV_EINVAL, "circuit %d: needs at least one term", c);
-            const uint64_t full = (1ull << s.n) - 1;
-            bc.first_term = (int32_t)h->terms.size();
-            bc.nterms = (int32_t)(t1 - t0);
-            for (int64_t j = t0; j < t1; ++j) {
-                if ((terms[j].x_mask | terms[j].z_mask) & ~full)
-                    return fail(SV_EINVAL, "circuit %d: term %lld acts on qubits >= n", c, (long long)(j - t0));
-                DTerm d;
-                d.coef = terms[j].coef;
-                d.z = terms[j].z_mask;
-                d.ny = popcount64(terms[j].x_mask & terms[j].z_mask) & 3;
-                d.idx = (int32_t)terms[j].x_mask;  // x mask (n <= 31 in batches)
-                h->terms.push_back(d);
-            }
-            work *= 2.0;
             if (s.n > 31)
                 return fail(SV_EINVAL, "circuit %d: batched adjoint supports n <= 31", c);
         }
-        cost[c] = work;
-        h->circs.push_back(bc);
+        const int64_t g0 = A.gate_off[c], g1 = A.gate_off[c + 1];
+        if (g0 < 0 || g1 < g0 || g1 - g0 > INT32_MAX)
+            return fail(SV_EINVAL, "circuit %d: bad gate offsets", c);
+        const int64_t p0 = A.param_off ? A.param_off[c] : 0, p1 = A.param_off ? A.param_off[c + 1] : 0;
+        if (p0 < 0 || p1 < p0 || p1 > A.nparams_total)
+            return fail(SV_EINVAL, "circuit %d: bad parameter offsets", c);
+        total_gates += g1 - g0;
     }
-    h->order.resize(ncirc);
+    if (total_gates > INT32_MAX)
+        return fail(SV_EINVAL, "batch holds %lld gates (at most 2^31 - 1)", (long long)total_gates);
+    std::vector<CircBuild> cb(A.ncirc);
+    auto work = [&](int lo, int hi) {
+        for (int c = lo; c < hi; ++c) {
+            CircBuild &b = cb[c];
+            b.err = build_circuit(A, c, *dtype, adjoint, &b);
+            if (b.err != SV_OK) {
+                b.msg = sv_last_error();  // error text is per thread
+                return;
+            }
+        }
+    };
+    unsigned nth = std::min(16u, std::max(1u, std::thread::hardware_concurrency()));
+    if (total_gates < 20000)
+        nth = 1;
+    nth = std::min<unsigned>(nth, (unsigned)A.ncirc);
+    if (nth <= 1) {
+        work(0, A.ncirc);
+    } else {
+        int dev = 0;
+        const bool have_dev = hipGetDevice(&dev) == hipSuccess;
+        std::vector<std::thread> pool;
+        std::atomic<int> next{0};
+        constexpr int kChunk = 16;
+        for (unsigned t = 0; t < nth; ++t)
+            pool.emplace_back([&, have_dev, dev] {
+                if (have_dev)
+                    (void)hipSetDevice(dev);  // planner queries use the caller's device
+                for (;;) {
+                    const int lo = next.fetch_add(kChunk);
+                    if (lo >= A.ncirc)
+                        break;
+                    work(lo, std::min(A.ncirc, lo + kChunk));
+                }
+            });
+        for (auto &t : pool)
+            t.join();
+    }
+    std::vector<double> cost(A.ncirc);
+    for (int c = 0; c < A.ncirc; ++c) {
+        CircBuild &b = cb[c];
+        if (b.err != SV_OK)
+            return fail(b.err, "circuit %d: %s", c, b.msg.c_str());
+        b.bc.first_gate = (int32_t)h->gates.size();
+        b.bc.first_term = (int32_t)h->terms.size();
+        const int32_t gbase = (int32_t)(h->gens.size() / 8);
+        for (int32_t g : b.gen_of)
+            h->gen_of.push_back(g >= 0 ? g + gbase : -1);
+        h->gates.insert(h->gates.end(), b.gates.begin(), b.gates.end());
+        h->gens.insert(h->gens.end(), b.gens.begin(), b.gens.end());
+        h->terms.insert(h->terms.end(), b.terms.begin(), b.terms.end());
+        h->circs.push_back(b.bc);
+        cost[c] = b.cost;
+    }
+    h->order.resize(A.ncirc);
     std::iota(h->order.begin(), h->order.end(), 0);
     std::stable_sort(h->order.begin(), h->order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
     return SV_OK;
@@ -442,51 +576,60 @@ struct BatchDevice {
     unsigned int *queue = nullptr;
 };
 
-static void batch_release(BatchDevice *d, hipStream_t st) {
+// Stream-ordered release when async (after the kernels enqueued on st),
+// otherwise an immediate free.
+static void batch_release(BatchDevice *d, bool async, hipStream_t st) {
     void *ps[] = {d->circs, d->gates, d->order, d->gen_of, d->gens, d->terms, d->queue};
     for (void *p : ps)
         if (p)
-            (void)hipFreeAsync(p, st);
+            (void)(async ? hipFreeAsync(p, st) : hipFree(p));
     *d = BatchDevice();
 }
 
-template <typename T> static int dev_copy(T **dst, const std::vector<T> &src, hipStream_t st, size_t min_count = 0) {
+template <typename T>
+static int dev_copy(T **dst, const std::vector<T> &src, bool async, hipStream_t st, size_t min_count = 0) {
     const size_t cnt = std::max(src.size(), min_count);
     *dst = nullptr;
     if (cnt == 0)
         return SV_OK;
-    hipError_t e = hipMallocAsync((void **)dst, cnt * sizeof(T), st);
+    hipError_t e = async ? hipMallocAsync((void **)dst, cnt * sizeof(T), st) : hipMalloc((void **)dst, cnt * sizeof(T));
     if (e != hipSuccess) {
         (void)hipGetLastError();
         *dst = nullptr;
         return fail(SV_ENOMEM, "device allocation failed: %s", hipGetErrorString(e));
     }
-    if (!src.empty())
-        SV_HIP_TRY(hipMemcpyAsync(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice, st));
+    if (!src.empty()) {
+        if (async)
+            SV_HIP_TRY(hipMemcpyAsync(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice, st));
+        else
+            SV_HIP_TRY(hipMemcpy(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice));
+    }
     return SV_OK;
 }
 
-static int upload_batch(const BatchHost &h, hipStream_t st, BatchDevice *d) {
-    int r = dev_copy(&d->circs, h.circs, st);
+static int upload_batch(const BatchHost &h, bool async, hipStream_t st, BatchDevice *d) {
+    int r = dev_copy(&d->circs, h.circs, async, st);
     if (r == SV_OK)
-        r = dev_copy(&d->gates, h.gates, st, 1);
+        r = dev_copy(&d->gates, h.gates, async, st, 1);
     if (r == SV_OK)
-        r = dev_copy(&d->order, h.order, st);
+        r = dev_copy(&d->order, h.order, async, st);
     if (r == SV_OK)
-        r = dev_copy(&d->gen_of, h.gen_of, st, 1);
+        r = dev_copy(&d->gen_of, h.gen_of, async, st, 1);
     if (r == SV_OK)
-        r = dev_copy(&d->gens, h.gens, st, 8);
+        r = dev_copy(&d->gens, h.gens, async, st, 8);
     if (r == SV_OK)
-        r = dev_copy(&d->terms, h.terms, st, 1);
+        r = dev_copy(&d->terms, h.terms, async, st, 1);
     if (r == SV_OK) {
-        hipError_t e = hipMallocAsync((void **)&d->queue, sizeof(unsigned int), st);
+        hipError_t e = async ? hipMallocAsync((void **)&d->queue, sizeof(unsigned int), st)
+                             : hipMalloc((void **)&d->queue, sizeof(unsigned int));
         if (e != hipSuccess) {
             (void)hipGetLastError();
+            d->queue = nullptr;
             r = fail(SV_ENOMEM, "device allocation failed");
         }
     }
     if (r != SV_OK)
-        batch_release(d, st);
+        batch_release(d, async, st);
     return r;
 }
 
@@ -498,47 +641,163 @@ static unsigned persistent_grid(int ncirc) {
     return std::min<unsigned>(g, (unsigned)ncirc);
 }
 
+constexpr size_t kBatchDynLds = kBatchLds + 64;  // the tile, then the work-item slot
+
+static int launch_forward(int dtype, const BatchDevice &d, int ncirc, const double *params, hipStream_t s) {
+    hipError_t a = dtype == SV_C128 ? hipFuncSetAttribute((const void *)k_batched<double>,
+                                                          hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                          (int)kBatchDynLds)
+                                    : hipFuncSetAttribute((const void *)k_batched<float>,
+                                                          hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                          (int)kBatchDynLds);
+    if (a != hipSuccess)
+        return fail(SV_EHIP, "LDS limit: %s", hipGetErrorString(a));
+    const unsigned grid = persistent_grid(ncirc);
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, s, d.queue);
+    if (dtype == SV_C128)
+        hipLaunchKernelGGL(k_batched<double>, dim3(grid), dim3(kBatchThreads), kBatchDynLds, s, d.circs, d.order,
+                           ncirc, d.gates, params, d.queue);
+    else
+        hipLaunchKernelGGL(k_batched<float>, dim3(grid), dim3(kBatchThreads), kBatchDynLds, s, d.circs, d.order,
+                           ncirc, d.gates, params, d.queue);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return fail(SV_EHIP, "batched launch failed: %s", hipGetErrorString(e));
+    return SV_OK;
+}
+
+static int launch_adjoint(int dtype, const BatchDevice &d, int ncirc, const double *params, double *grad,
+                          double *loss, hipStream_t s) {
+    const unsigned grid = persistent_grid(ncirc);
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, s, d.queue);
+    if (dtype == SV_C128)
+        hipLaunchKernelGGL(k_batched_adjoint<double>, dim3(grid), dim3(kBatchThreads), 0, s, d.circs, d.order, ncirc,
+                           d.gates, params, d.terms, d.gens, d.gen_of, grad, loss, d.queue);
+    else
+        hipLaunchKernelGGL(k_batched_adjoint<float>, dim3(grid), dim3(kBatchThreads), 0, s, d.circs, d.order, ncirc,
+                           d.gates, params, d.terms, d.gens, d.gen_of, grad, loss, d.queue);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return fail(SV_EHIP, "batched adjoint launch failed: %s", hipGetErrorString(e));
+    return SV_OK;
+}
+
 } // namespace sv
+
+// A planned batch resident on one device (the C ABI's opaque sv_batch_t).
+struct sv_batch {
+    int dtype = 0, ncirc = 0, device = 0;
+    int64_t nparams_total = 0;
+    bool has_adjoint = false;
+    sv::BatchDevice fwd, adj;
+    hipEvent_t done = nullptr;  // end of the last run
+};
 
 using namespace sv;
 
 extern "C" {
 
+int sv_batch_create(const sv_state_t *states, const sv_state_t *lam_states, int ncirc, const sv_gate_t *gates,
+                    const int64_t *gate_offsets, const int64_t *param_offsets, int64_t nparams_total,
+                    const sv_pauli_t *terms, const int64_t *term_offsets, sv_batch_t **out) {
+    clear_error();
+    if (!out)
+        return fail(SV_EINVAL, "out is NULL");
+    *out = nullptr;
+    const bool adj = lam_states != nullptr;
+    BatchArgs A{states, lam_states, ncirc, gates, gate_offsets, param_offsets, nparams_total, terms, term_offsets};
+    BatchHost hf, ha;
+    int dtype = 0;
+    SV_TRY(build_batch(A, false, &hf, &dtype));
+    if (adj)
+        SV_TRY(build_batch(A, true, &ha, &dtype));
+    sv_batch *b = new sv_batch();
+    b->dtype = dtype;
+    b->ncirc = ncirc;
+    b->nparams_total = nparams_total;
+    b->has_adjoint = adj;
+    int r = hipGetDevice(&b->device) == hipSuccess ? SV_OK : fail(SV_EHIP, "no current device");
+    if (r == SV_OK)
+        r = upload_batch(hf, false, nullptr, &b->fwd);
+    if (r == SV_OK && adj)
+        r = upload_batch(ha, false, nullptr, &b->adj);
+    if (r != SV_OK) {
+        batch_release(&b->fwd, false, nullptr);
+        batch_release(&b->adj, false, nullptr);
+        delete b;
+        return r;
+    }
+    *out = b;
+    return SV_OK;
+}
+
+static int batch_check(sv_batch_t *b, const double *params_dev) {
+    if (!b)
+        return fail(SV_EINVAL, "batch is NULL");
+    if (b->nparams_total > 0 && !params_dev)
+        return fail(SV_EINVAL, "params_dev is NULL");
+    int dev = 0;
+    SV_HIP_TRY(hipGetDevice(&dev));
+    if (dev != b->device)
+        return fail(SV_EINVAL, "batch was created on device %d, current device is %d", b->device, dev);
+    return SV_OK;
+}
+
+static int batch_done(sv_batch_t *b, hipStream_t st) {
+    if (!b->done)
+        SV_HIP_TRY(hipEventCreateWithFlags(&b->done, hipEventDisableTiming));
+    SV_HIP_TRY(hipEventRecord(b->done, st));
+    return SV_OK;
+}
+
+int sv_batch_run(sv_batch_t *b, const double *params_dev, sv_stream_t st) {
+    clear_error();
+    SV_TRY(batch_check(b, params_dev));
+    SV_TRY(launch_forward(b->dtype, b->fwd, b->ncirc, params_dev, (hipStream_t)st));
+    return batch_done(b, (hipStream_t)st);
+}
+
+int sv_batch_adjoint(sv_batch_t *b, const double *params_dev, double *grad_dev, double *loss_dev, sv_stream_t st) {
+    clear_error();
+    SV_TRY(batch_check(b, params_dev));
+    if (!b->has_adjoint)
+        return fail(SV_EINVAL, "batch was created without lambda states and terms");
+    if (!grad_dev || !loss_dev)
+        return fail(SV_EINVAL, "grad_dev and loss_dev are required");
+    SV_TRY(launch_adjoint(b->dtype, b->adj, b->ncirc, params_dev, grad_dev, loss_dev, (hipStream_t)st));
+    return batch_done(b, (hipStream_t)st);
+}
+
+int sv_batch_destroy(sv_batch_t *b) {
+    clear_error();
+    if (!b)
+        return SV_OK;
+    if (b->done) {
+        (void)hipEventSynchronize(b->done);
+        (void)hipEventDestroy(b->done);
+    }
+    batch_release(&b->fwd, false, nullptr);
+    batch_release(&b->adj, false, nullptr);
+    delete b;
+    return SV_OK;
+}
+
 int sv_apply_circuits_batched(const sv_state_t *states, int ncirc, const sv_gate_t *gates, const int64_t *gate_offsets,
                               const double *params_dev, const int64_t *param_offsets, int64_t nparams_total,
                               sv_stream_t st) {
     clear_error();
+    BatchArgs A{states, nullptr, ncirc, gates, gate_offsets, param_offsets, nparams_total, nullptr, nullptr};
     BatchHost h;
     int dtype = 0;
-    SV_TRY(build_batch(states, nullptr, ncirc, gates, gate_offsets, param_offsets, nparams_total, nullptr, nullptr,
-                       false, &h, &dtype));
+    SV_TRY(build_batch(A, false, &h, &dtype));
     if (nparams_total > 0 && !params_dev)
         return fail(SV_EINVAL, "params_dev is NULL");
     BatchDevice d;
     hipStream_t s = (hipStream_t)st;
-    SV_TRY(upload_batch(h, s, &d));
-    const unsigned grid = persistent_grid(ncirc);
-    constexpr size_t lds = kBatchLds + 64;  // the tile, then the work-item slot
-    hipError_t a = dtype == SV_C128 ? hipFuncSetAttribute((const void *)k_batched<double>,
-                                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds)
-                                    : hipFuncSetAttribute((const void *)k_batched<float>,
-                                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (a != hipSuccess) {
-        batch_release(&d, s);
-        return fail(SV_EHIP, "LDS limit: %s", hipGetErrorString(a));
-    }
-    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, s, d.queue);
-    if (dtype == SV_C128)
-        hipLaunchKernelGGL(k_batched<double>, dim3(grid), dim3(kBatchThreads), lds, s, d.circs, d.order, ncirc,
-                           d.gates, params_dev, d.queue);
-    else
-        hipLaunchKernelGGL(k_batched<float>, dim3(grid), dim3(kBatchThreads), lds, s, d.circs, d.order, ncirc,
-                           d.gates, params_dev, d.queue);
-    hipError_t e = hipGetLastError();
-    batch_release(&d, s);
-    if (e != hipSuccess)
-        return fail(SV_EHIP, "batched launch failed: %s", hipGetErrorString(e));
-    return SV_OK;
+    SV_TRY(upload_batch(h, true, s, &d));
+    const int r = launch_forward(dtype, d, ncirc, params_dev, s);
+    batch_release(&d, true, s);
+    return r;
 }
 
 int sv_adjoint_grad_batched(const sv_state_t *psi_states, const sv_state_t *lam_states, int ncirc,
@@ -548,28 +807,19 @@ int sv_adjoint_grad_batched(const sv_state_t *psi_states, const sv_state_t *lam_
     clear_error();
     if (!lam_states || !grad_dev || !loss_dev || !param_offsets)
         return fail(SV_EINVAL, "batched adjoint needs lambda states, param offsets, grad_dev and loss_dev");
+    BatchArgs A{psi_states, lam_states, ncirc, gates, gate_offsets, param_offsets, nparams_total, terms,
+                term_offsets};
     BatchHost h;
     int dtype = 0;
-    SV_TRY(build_batch(psi_states, lam_states, ncirc, gates, gate_offsets, param_offsets, nparams_total, terms,
-                       term_offsets, true, &h, &dtype));
+    SV_TRY(build_batch(A, true, &h, &dtype));
     if (nparams_total > 0 && !params_dev)
         return fail(SV_EINVAL, "params_dev is NULL");
     BatchDevice d;
     hipStream_t s = (hipStream_t)st;
-    SV_TRY(upload_batch(h, s, &d));
-    const unsigned grid = persistent_grid(ncirc);
-    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, s, d.queue);
-    if (dtype == SV_C128)
-        hipLaunchKernelGGL(k_batched_adjoint<double>, dim3(grid), dim3(kBatchThreads), 0, s, d.circs, d.order, ncirc,
-                           d.gates, params_dev, d.terms, d.gens, d.gen_of, grad_dev, loss_dev, d.queue);
-    else
-        hipLaunchKernelGGL(k_batched_adjoint<float>, dim3(grid), dim3(kBatchThreads), 0, s, d.circs, d.order, ncirc,
-                           d.gates, params_dev, d.terms, d.gens, d.gen_of, grad_dev, loss_dev, d.queue);
-    hipError_t e = hipGetLastError();
-    batch_release(&d, s);
-    if (e != hipSuccess)
-        return fail(SV_EHIP, "batched adjoint launch failed: %s", hipGetErrorString(e));
-    return SV_OK;
+    SV_TRY(upload_batch(h, true, s, &d));
+    const int r = launch_adjoint(dtype, d, ncirc, params_dev, grad_dev, loss_dev, s);
+    batch_release(&d, true, s);
+    return r;
 }
 
 } // extern "C"

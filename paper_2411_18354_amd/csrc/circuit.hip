@@ -117,7 +117,7 @@ static int plan_circuit(sv_circuit *c, std::vector<TileGate> &tiles, std::vector
     std::vector<int> tile_slot(G, -1);
     std::vector<char> diag(G, 0);
     for (int i = 0; i < G; ++i)
-        diag[i] = c->general_tiles && gate_is_diagonal(c->gates[i], &mats[(size_t)8 * i]);
+        diag[i] = c->general_tiles && c->diag_any && gate_is_diagonal(c->gates[i], &mats[(size_t)8 * i]);
 
     auto single = [&](int i) -> int {
         Pass p;
@@ -459,7 +459,8 @@ static int run_graph(sv_circuit *c, const sv_state_t *s, const double *params, h
 }
 
 int circuit_plan_capped(int n, int dtype, const sv_gate_t *gates, int ngates, int nparams, int flags, int m_cap,
-                        int32_t *order, int32_t *pass_of, int64_t *npasses, int *m_used, bool general);
+                        int32_t *order, int32_t *pass_of, int64_t *npasses, int *m_used, bool general,
+                        bool diag_any, std::vector<uint64_t> *pass_S);
 
 } // namespace sv
 
@@ -480,7 +481,8 @@ int sv_gate_matrix(int kind, double theta, const double *U, double *out) {
 int sv_circuit_plan(int n, int dtype, const sv_gate_t *gates, int ngates, int nparams, int flags, int32_t *order,
                     int32_t *pass_of, int64_t *npasses) {
     clear_error();
-    return circuit_plan_capped(n, dtype, gates, ngates, nparams, flags, 64, order, pass_of, npasses, nullptr, true);
+    return circuit_plan_capped(n, dtype, gates, ngates, nparams, flags, 64, order, pass_of, npasses, nullptr, true,
+                               true, nullptr);
 }
 
 } // extern "C"
@@ -488,7 +490,8 @@ int sv_circuit_plan(int n, int dtype, const sv_gate_t *gates, int ngates, int np
 namespace sv {
 
 int circuit_plan_capped(int n, int dtype, const sv_gate_t *gates, int ngates, int nparams, int flags, int m_cap,
-                        int32_t *order, int32_t *pass_of, int64_t *npasses, int *m_used, bool general) {
+                        int32_t *order, int32_t *pass_of, int64_t *npasses, int *m_used, bool general,
+                        bool diag_any, std::vector<uint64_t> *pass_S) {
     if (dtype != SV_C128 && dtype != SV_C64)
         return fail(SV_EINVAL, "unknown dtype %d", dtype);
     if (n < 1 || n > max_qubits(dtype))
@@ -506,6 +509,7 @@ int circuit_plan_capped(int n, int dtype, const sv_gate_t *gates, int ngates, in
     c.nparams = nparams;
     c.m_cap = m_cap;
     c.general_tiles = general;
+    c.diag_any = diag_any;
     c.gates.assign(gates, gates + ngates);
     std::vector<TileGate> tiles;
     std::vector<ParamJob> jobs;
@@ -514,15 +518,31 @@ int circuit_plan_capped(int n, int dtype, const sv_gate_t *gates, int ngates, in
     int dense_runs = 0;
     SV_TRY(plan_circuit(&c, tiles, jobs, mats, dense_list, dense_runs));
     int k = 0;
+    if (pass_S)
+        pass_S->assign(c.passes.size(), 0);
     for (size_t pi = 0; pi < c.passes.size(); ++pi) {
         const Pass &p = c.passes[pi];
-        if (!p.fused) {
+        if (p.dense) {
+            for (int j = 0; j < p.count; ++j) {
+                if (order)
+                    order[k] = dense_list[p.first + j].mat;
+                if (pass_of)
+                    pass_of[k] = (int32_t)pi;
+                ++k;
+            }
+        } else if (!p.fused) {
             if (order)
                 order[k] = p.gate;
             if (pass_of)
                 pass_of[k] = (int32_t)pi;
             ++k;
         } else {
+            if (pass_S) {
+                uint64_t S = (p.tm.a >= 64) ? ~0ull : ((1ull << p.tm.a) - 1);
+                for (uint32_t h = 0; h < p.tm.nh; ++h)
+                    S |= 1ull << p.tm.hpos[h];
+                (*pass_S)[pi] = S;
+            }
             for (int j = 0; j < p.count; ++j) {
                 if (order)
                     order[k] = tiles[p.first + j].src_gate;

@@ -1,6 +1,7 @@
 """GPU parity of the batched entry points against the oracle: mixed-width
 batches (LDS-resident and global-memory circuits), the 4096-circuit batch at full size on
-a seeded sample of circuits, and batched adjoint gradients."""
+a seeded sample of circuits, batched adjoint gradients, and planned batches
+(sv_batch_*) run repeatedly."""
 import numpy as np
 import pytest
 
@@ -162,3 +163,75 @@ def test_hea_batch_n16_full_sampled(gpu):
         _say("hea batch circuit", ci, "err", np.max(np.abs(got - ref)))
         assert np.max(np.abs(got - ref)) <= 1e-8 * max(1, np.max(np.abs(ref)))
         assert abs(loss[ci].item() - oracle.loss(c, c.params, h)) <= 1e-10
+
+
+def test_batch_object_reuse(gpu):
+    """A planned batch (sv_batch_create) run twice with different angles on
+    re-initialised states, each run against the oracle; a forward-only batch
+    refuses gradients."""
+    import torch
+    circs = _mixed(5, ncirc=24)
+    buf, views = _packed_states([c.n for c in circs], "c128")
+    init = buf.clone()
+    b = gpu.Batch(views, circs)
+    try:
+        for rep in range(2):
+            angles = [c.params + 0.37 * rep for c in circs]
+            params = torch.from_numpy(np.concatenate(angles)).cuda()
+            buf.copy_(init)
+            b.run(params)
+            for c, a, v in zip(circs, angles, views):
+                e = _err(v.cpu().numpy(), oracle.run_circuit(c, a))
+                assert e <= 1e-12, (rep, c.n, e)
+    finally:
+        b.close()
+    with pytest.raises(gpu.SvError):
+        gpu.Batch(views, circs).adjoint(params)  # created without lambda states
+
+
+def test_batch_object_adjoint(gpu):
+    import torch
+    circs, hams = [], []
+    for i in range(8):
+        n = 4 + i % 5
+        circs.append(W.hea(n, 2, seed=400 + i))
+        hams.append(W.zz_x_hamiltonian(n, 500 + i))
+    buf, views = _packed_states([c.n for c in circs], "c128")
+    init = buf.clone()
+    lbuf = torch.empty_like(buf)
+    lviews, off = [], 0
+    for c in circs:
+        lviews.append(lbuf[off:off + (1 << c.n)]); off += 1 << c.n
+    params = torch.from_numpy(np.concatenate([c.params for c in circs])).cuda()
+    b = gpu.Batch(views, circs, lam_states=lviews, hamiltonians=hams)
+    try:
+        for rep in range(2):
+            buf.copy_(init)
+            b.run(params)
+            grad, loss = b.adjoint(params)
+            g = grad.cpu().numpy()
+            off = 0
+            for i, (c, h) in enumerate(zip(circs, hams)):
+                ref = oracle.grad_param_shift(c, c.params, h)
+                got = g[off:off + c.nparams]
+                off += c.nparams
+                assert np.max(np.abs(got - ref)) <= 1e-8 * max(1, np.max(np.abs(ref))), (rep, i)
+                assert abs(loss[i].item() - oracle.loss(c, c.params, h)) <= 1e-10
+    finally:
+        b.close()
+
+
+def test_batched_qubit_set_tiles(gpu):
+    """Circuits of 13-15 qubits whose gates target every qubit: the fused
+    plan's tiles span the low qubits plus planner-chosen high ones."""
+    import torch
+    circs = []
+    for i in range(6):
+        n = 13 + i % 3
+        circs.append(W.random_gates_n12(seed=900 + i, n=n, ngates=150))
+    for dtype, tol in (("c128", 1e-12), ("c64", 1e-5)):
+        buf, views = _packed_states([c.n for c in circs], dtype)
+        gpu.sv_apply_circuits_batched(views, circs)
+        for c, v in zip(circs, views):
+            e = _err(v.cpu().numpy(), oracle.run_circuit(c))
+            assert e <= tol, (dtype, c.n, e)
