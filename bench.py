@@ -185,6 +185,41 @@ def _time_ms(torch, stream, fn, reps):
     return ts[len(ts) // 2]
 
 
+def control_position_sweep(sv, torch, np, d, U, stream, n, t=13, reps=5):
+    """Target 13 with c = 1..8 controls placed on the lowest free qubits and
+    on the highest ones: exposes the cache-line granularity of skipped pairs
+    (controls below bit 3 of a complex128 index share 128-byte lines with
+    updated pairs).  Median HIP-event time per gate, scheduled and masked."""
+    out = []
+    for place in ("lowest", "highest"):
+        free = [q for q in range(n) if q != t]
+        if place == "highest":
+            free = free[::-1]
+        for c in range(1, 9):
+            ctrls = tuple(sorted(free[:c]))
+            row = {"placement": place, "t": t, "c": c, "controls": list(ctrls)}
+            alg = 2 * (1 << (n - c)) * AMP_BYTES
+            for mode in ("auto", "masked"):
+                ts = []
+                with torch.cuda.stream(stream):
+                    sv.sv_apply_gate(d, t, ctrls, None, U, mode=mode, stream=stream)
+                    for _ in range(reps):
+                        e0 = torch.cuda.Event(enable_timing=True)
+                        e1 = torch.cuda.Event(enable_timing=True)
+                        e0.record(stream)
+                        sv.sv_apply_gate(d, t, ctrls, None, U, mode=mode, stream=stream)
+                        e1.record(stream)
+                        ts.append((e0, e1))
+                torch.cuda.synchronize()
+                med = float(np.median([a.elapsed_time(b) for a, b in ts]))
+                key = "sched" if mode == "auto" else "masked"
+                row[key + "_us"] = round(med * 1e3, 2)
+                row[key + "_GBps"] = round(alg / med / 1e6, 1)
+            row["masked_over_sched"] = round(row["masked_us"] / row["sched_us"], 2)
+            out.append(row)
+    return out
+
+
 def measure_extras(sv, W, torch, np, stream, with_layered):
     """Adjoint gradients (n=24 ansatz), batched circuits (4096 uneven circuits), the paper's
     QFT and streaming circuits at 29 qubits, and optionally the layered n=32 circuit."""
@@ -465,6 +500,10 @@ def main():
                 "alg_bytes_per_launch": avg_bytes, "launches": ks["launches"],
                 "kernel_source_hash": src_hash}
 
+    positions = None
+    if not args.no_extras:
+        positions = control_position_sweep(sv, torch, np, d, U, stream, n)
+
     extras = None
     if not args.no_extras:
         del d
@@ -510,6 +549,7 @@ def main():
         "cpu_baseline": cpu,
         "masked_value": None if masked_total is None else round(ngates / (masked_total / 1e3), 2),
         "sweep": rows,
+        "control_positions": positions,
         "extras": extras,
     }
     print(json.dumps(out), flush=True)

@@ -29,9 +29,13 @@ __global__ void k_param_mats(const ParamJob *__restrict__ jobs, int njobs, const
     gate_matrix(j.kind, params[j.param], nullptr, m);
     for (int k = 0; k < 8; ++k)
         mats[8 * j.mat_slot + k] = m[k];
-    if (j.tile_slot >= 0)
+    if (j.tile_slot >= 0) {
+        TileGate &t = tiles[j.tile_slot];
         for (int k = 0; k < 8; ++k)
-            tiles[j.tile_slot].m[k] = m[k];
+            t.m[k] = m[k];
+        if (t.diag)
+            diag_phases(m, t.ph, &t.unit);
+    }
 }
 
 // Gates a and b commute when every qubit they share is, in each of them,
@@ -206,6 +210,8 @@ static int plan_circuit(sv_circuit *c, std::vector<TileGate> &tiles, std::vector
                     tiles.back().src_gate = gi;
                     c->tile_src.push_back(gi);
                 }
+                if (c->reg_groups && tuning().tile_groups)
+                    form_register_groups(p.tm, &tiles[p.first], p.count);
                 c->passes.push_back(p);
                 c->fused_gates += (int64_t)run.size();
                 c->fused_runs++;
@@ -308,6 +314,14 @@ template <typename T> static int upload(T **dst, const std::vector<T> &src, bool
     return SV_OK;
 }
 
+// One fused pass: one workgroup per launched tile.
+template <typename R>
+static int launch_tile_pass(cplx_t<R> *psi, const TileMap &tm, const DeviceGates &dg, size_t lds, hipStream_t st) {
+    hipLaunchKernelGGL((k_tile<R, 512, DeviceGates>), dim3((unsigned)tm.ntiles), dim3(512), lds, st, psi, tm, dg);
+    SV_LAUNCH_CHECK();
+    return SV_OK;
+}
+
 int circuit_create(int n, int dtype, const sv_gate_t *gates, int ngates, int nparams, int flags, bool async,
                    hipStream_t st, int m_cap, sv_circuit **out) {
     *out = nullptr;
@@ -396,9 +410,7 @@ template <typename R> static int enqueue(sv_circuit *c, cplx_t<R> *psi, const do
             SV_TRY(launch_dense(c->dtype, psi, c->n, c->dense_k, rm, st));
         } else if (p.fused) {
             DeviceGates dg{c->d_tiles + p.first, p.count};
-            hipLaunchKernelGGL((k_tile<R, 512, DeviceGates>), dim3((unsigned)p.tm.ntiles), dim3(512), lds, st, psi, p.tm,
-                               dg);
-            SV_LAUNCH_CHECK();
+            SV_TRY(launch_tile_pass<R>(psi, p.tm, dg, lds, st));
         } else {
             SV_TRY(launch_plan<R>(psi, p.plan, MatPtr<R>{c->d_mats + (size_t)8 * p.gate}, st));
         }

@@ -41,7 +41,38 @@ struct TileGate {
     uint64_t hi_vals;
     int32_t src_gate;     // index of the gate in its circuit (host bookkeeping)
     int32_t pad2;
+    // diagonal gate split over the tile's qubit set S: controls outside S
+    // (global bits; a tile predicate), controls inside S (tile-local bits)
+    // and the target's tile-local bit, or -1 when the target is outside S
+    // (pair gates use l_mask/l_vals for their tile-local controls too)
+    uint64_t o_mask, o_vals;
+    uint32_t l_mask, l_vals;
+    int32_t l_target;
+    // register group of consecutive pair gates whose targets lie in three
+    // tile-local qubits Q.  Each lane holds 8 amplitudes a[v]; bit i of the
+    // register index v stands for one qubit of Q, and the assignment is
+    // permuted as the group goes so that every gate's target sits on bit 0.
+    // At the group's first gate: grp = gates in the group, qpos / qout = the
+    // tile-local qubit of each register bit when loading / storing.  Per
+    // gate: swp = register bit swapped with bit 0 before the gate (0: none),
+    // qmask/qvals = its controls inside Q as register-index bits (after the
+    // swap), lcm/lcv = its tile-local controls outside Q.
+    uint32_t grp;
+    uint32_t qpos[3], qout[3];
+    uint32_t swp, qmask, qvals, lcm, lcv;
+    // diagonal gate: phases of its two entries, and whether both have unit
+    // modulus (then a sweep may add phases instead of multiplying factors)
+    uint32_t unit;
+    double ph[2];
 };
+
+// Phases of the diagonal entries m[0..1] and m[6..7] (host and device).
+__host__ __device__ inline void diag_phases(const double *m, double *ph, uint32_t *unit) {
+    ph[0] = atan2(m[1], m[0]);
+    ph[1] = atan2(m[7], m[6]);
+    const double a = m[0] * m[0] + m[1] * m[1], b = m[6] * m[6] + m[7] * m[7];
+    *unit = (fabs(a - 1.0) <= 1e-12 && fabs(b - 1.0) <= 1e-12) ? 1u : 0u;
+}
 
 // Where a tile's amplitudes live: base = deposit(tile index) over the qubits
 // outside S; local index j maps to base | (j & (2^a - 1)) | scatter(j >> a)
@@ -70,6 +101,10 @@ TileMap make_tile_map(int n, int m, int a, const std::vector<int> &high, uint64_
 // in S.
 TileGate make_tile_gate(const TileMap &tm, int target, uint64_t cmask, uint64_t cvals, const double *U,
                         bool diagonal);
+// Mark register groups among tiles[0 .. count) (one fused run; host): runs
+// of at least two consecutive pair gates whose targets span at most three
+// tile-local qubits.
+void form_register_groups(const TileMap &tm, TileGate *tiles, int count);
 // Contiguous tiles (S = {0 .. m-1}).
 TileMap contiguous_tile_map(int n, int m);
 
@@ -107,27 +142,187 @@ __device__ __forceinline__ uint64_t tile_offset(const TileMap &tm, uint32_t j) {
     return o;
 }
 
-// One workgroup per tile.  Dynamic LDS holds the 2^m amplitudes.
-template <typename R, int THREADS, typename Src>
-__global__ __launch_bounds__(THREADS) void k_tile(cplx_t<R> *__restrict__ psi, TileMap tm, Src gates) {
-    extern __shared__ unsigned char lds_raw[];
-    cplx_t<R> *tile = reinterpret_cast<cplx_t<R> *>(lds_raw);
-    const uint64_t base = expand_index<uint64_t>(tm.outer, (uint64_t)blockIdx.x);
-    const uint32_t T = 1u << tm.m;
+// Diagonal sweeps with at least this many gates reading tile-local bits add
+// phases instead of multiplying factors (measured break-even on MI355X is a
+// handful of gates).
+constexpr int kPhaseSweepMin = 8;
 
-    // a tile that no operation of the run touches is left alone
+// A wave-uniform double held in scalar registers.
+__device__ __forceinline__ double uniform_f64(double v) {
+    const uint64_t b = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)b);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(b >> 32));
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+// Conditional swap and select written component-wise on values: a ternary
+// over whole aggregates selects between their addresses, which keeps a
+// register array in scratch memory.
+template <typename R> __device__ __forceinline__ void cswap(cplx_t<R> &x, cplx_t<R> &y, bool c) {
+    const R xr = x.x, xi = x.y, yr = y.x, yi = y.y;
+    x.x = c ? yr : xr;
+    x.y = c ? yi : xi;
+    y.x = c ? xr : yr;
+    y.y = c ? xi : yi;
+}
+
+template <typename R> __device__ __forceinline__ void csel(cplx_t<R> &dst, const cplx_t<R> &v, bool c) {
+    const R dr = dst.x, di = dst.y;
+    dst.x = c ? v.x : dr;
+    dst.y = c ? v.y : di;
+}
+
+// One gate of a register group on the 8 amplitudes a[v] of a coset: first
+// the register-bit swap that brings its target to bit 0 (selects only, so
+// the array stays in registers), then the pairs (v, v|1) whose controls in
+// Q hold.  active: the gate's tile predicate; cc: its tile-local controls
+// outside Q hold for this coset.
+template <typename R>
+__device__ __forceinline__ void reg_gate(cplx_t<R> (&a)[8], const TileGate &g, bool active, bool cc) {
+    // selects rather than branches: branches on swp get merged into one
+    // path indexing the array by swp, which moves it to scratch memory
+    const bool s1 = g.swp == 1, s2 = g.swp == 2;
+    cswap<R>(a[1], a[2], s1);
+    cswap<R>(a[5], a[6], s1);
+    cswap<R>(a[1], a[4], s2);
+    cswap<R>(a[3], a[6], s2);
+    if (!active)
+        return;  // uniform
+    const Mat2<R> mm = tile_mat<R>(g);
+    if (g.qmask == 0 && g.lcm == 0) {  // uniform: no control inside the tile
+#pragma unroll
+        for (int v0 = 0; v0 < 8; v0 += 2) {
+            cplx_t<R> x = a[v0], y = a[v0 + 1];
+            apply_pair<R>(mm, x, y);
+            a[v0] = x;
+            a[v0 + 1] = y;
+        }
+        return;
+    }
+#pragma unroll
+    for (int v0 = 0; v0 < 8; v0 += 2) {
+        const bool on = cc && (((uint32_t)v0 & g.qmask) == g.qvals);
+        cplx_t<R> x = a[v0], y = a[v0 + 1];
+        apply_pair<R>(mm, x, y);
+        csel<R>(a[v0], x, on);
+        csel<R>(a[v0 + 1], y, on);
+    }
+}
+
+// sin and cos of a phase: quadrant reduction by pi/2 held as two doubles
+// (their sum is pi/2 to about 1e-33), then Taylor polynomials on
+// |r| <= pi/4 (the first omitted terms are below 1e-19).  The phases here are
+// sums of gate phases, |theta| well below 2^20.
+__device__ __forceinline__ void phase_sincos(double th, double *sn, double *cs) {
+    constexpr double kPio2Hi = 1.5707963267948966;     // nearest double to pi/2
+    constexpr double kPio2Lo = 6.123233995736766e-17;  // pi/2 - kPio2Hi
+    const double k = rint(th * 0.63661977236758134);  // th / (pi/2)
+    double r = fma(-k, kPio2Hi, th);
+    r = fma(-k, kPio2Lo, r);
+    const double r2 = r * r;
+    // sin r = r (1 - r^2/3! + r^4/5! - ...), cos r = 1 - r^2/2! + r^4/4! - ...
+    double ps = 1.0 / 355687428096000.0;  // 1/17!
+    ps = fma(ps, -r2, 1.0 / 1307674368000.0);
+    ps = fma(ps, -r2, 1.0 / 6227020800.0);
+    ps = fma(ps, -r2, 1.0 / 39916800.0);
+    ps = fma(ps, -r2, 1.0 / 362880.0);
+    ps = fma(ps, -r2, 1.0 / 5040.0);
+    ps = fma(ps, -r2, 1.0 / 120.0);
+    ps = fma(ps, -r2, 1.0 / 6.0);
+    ps = fma(ps, -r2, 1.0);
+    const double s = r * ps;  // signs alternate through the -r2 factors
+    double pc = 1.0 / 20922789888000.0;  // 1/16!
+    pc = fma(pc, -r2, 1.0 / 87178291200.0);
+    pc = fma(pc, -r2, 1.0 / 479001600.0);
+    pc = fma(pc, -r2, 1.0 / 3628800.0);
+    pc = fma(pc, -r2, 1.0 / 40320.0);
+    pc = fma(pc, -r2, 1.0 / 720.0);
+    pc = fma(pc, -r2, 1.0 / 24.0);
+    pc = fma(pc, -r2, 1.0 / 2.0);
+    pc = fma(pc, -r2, 1.0);
+    const double c = pc;
+    const int q = (int)((int64_t)k & 3);
+    // th = r + q pi/2: rotate (c, s) by q quarter turns
+    *sn = q == 0 ? s : q == 1 ? c : q == 2 ? -s : -c;
+    *cs = q == 0 ? c : q == 1 ? -s : q == 2 ? -c : s;
+}
+
+// A sweep of consecutive diagonal gates [i, e) whose entries all have unit
+// modulus: each amplitude is multiplied by exp(i theta), theta being the sum
+// of the phases its index selects (a tile-uniform part plus the gates that
+// read tile-local bits), accumulated in double precision.
+template <typename R, int THREADS, typename Src>
+__device__ __forceinline__ void diag_sweep_phases(cplx_t<R> *tile, uint64_t base, uint32_t T, const Src &gates,
+                                                  int i, int e) {
+    double th0 = 0.0;
+    bool any_local = false;
+    for (int q = i; q < e; ++q) {
+        const TileGate &d = gates.get(q);
+        if ((base & d.o_mask) != d.o_vals)
+            continue;
+        if (d.l_target >= 0 || d.l_mask) {
+            any_local = true;
+            continue;
+        }
+        th0 += ((base >> d.target) & 1ull) ? d.ph[1] : d.ph[0];
+    }
+    // four amplitudes per lane at a time (named scalars, not an array)
+    for (uint32_t j0 = threadIdx.x; j0 < T; j0 += 4 * THREADS) {
+        const uint32_t j1 = j0 + THREADS, j2 = j0 + 2 * THREADS, j3 = j0 + 3 * THREADS;
+        double t0 = th0, t1 = th0, t2 = th0, t3 = th0;
+        if (any_local) {  // uniform
+            for (int q = i; q < e; ++q) {
+                const TileGate &d = gates.get(q);
+                if ((base & d.o_mask) != d.o_vals || (d.l_target < 0 && !d.l_mask))
+                    continue;  // uniform
+                const double p0 = uniform_f64(d.ph[0]), p1 = uniform_f64(d.ph[1]);
+                const bool tin = d.l_target >= 0;
+                const double pt = ((base >> d.target) & 1ull) ? p1 : p0;
+                auto add = [&](double &t, uint32_t j) {
+                    const double p = tin ? (((j >> d.l_target) & 1u) ? p1 : p0) : pt;
+                    t += ((j & d.l_mask) == d.l_vals) ? p : 0.0;
+                };
+                add(t0, j0);
+                add(t1, j1);
+                add(t2, j2);
+                add(t3, j3);
+            }
+        }
+        auto put = [&](double t, uint32_t j) {
+            if (j < T) {
+                double sn, cs;
+                phase_sincos(t, &sn, &cs);
+                const R fr = (R)cs, fi = (R)sn;
+                const cplx_t<R> v = tile[j];
+                cplx_t<R> w;
+                w.x = v.x * fr - v.y * fi;
+                w.y = v.x * fi + v.y * fr;
+                tile[j] = w;
+            }
+        };
+        put(t0, j0);
+        put(t1, j1);
+        put(t2, j2);
+        put(t3, j3);
+    }
+    __syncthreads();
+}
+
+// Whether any operation of the run acts on the tile at base.
+template <typename Src> __device__ __forceinline__ bool tile_touched(uint64_t base, const Src &gates) {
     bool any = false;
     for (int i = 0; i < gates.size(); ++i) {
         const TileGate &g = gates.get(i);
-        any |= g.diag ? true : ((base & g.hi_mask) == g.hi_vals);
+        any |= g.diag ? ((base & g.o_mask) == g.o_vals) : ((base & g.hi_mask) == g.hi_vals);
     }
-    if (!any)
-        return;
+    return any;
+}
 
-    for (uint32_t j = threadIdx.x; j < T; j += THREADS)
-        tile[j] = ld_stream<R>(psi + (base | tile_offset(tm, j)));
-    __syncthreads();
-
+// The run's operations applied to the tile held in LDS (all threads of the
+// workgroup; the tile is complete in LDS on entry and on exit).
+template <typename R, int THREADS, typename Src>
+__device__ __forceinline__ void tile_run(cplx_t<R> *tile, uint64_t base, const TileMap &tm, const Src &gates) {
+    const uint32_t T = 1u << tm.m;
     int i = 0;
     while (i < gates.size()) {
         const TileGate &g = gates.get(i);
@@ -135,26 +330,117 @@ __global__ __launch_bounds__(THREADS) void k_tile(cplx_t<R> *__restrict__ psi, T
             int e = i + 1;
             while (e < gates.size() && gates.get(e).diag)
                 ++e;
-            for (uint32_t j = threadIdx.x; j < T; j += THREADS) {
-                const uint64_t k = base | tile_offset(tm, j);
-                R fr = (R)1, fi = (R)0;
+            // Diagonal gates commute, so the sweep multiplies each amplitude
+            // by the product of its factors.  Gates whose target and controls
+            // all lie outside S give the whole tile one factor (computed
+            // once); the others are evaluated per amplitude on tile-local bits.
+            // When every factor has unit modulus, phases are added instead and
+            // turned into one factor per amplitude at the end.
+            // Long sweeps whose factors all have unit modulus add phases
+            // (one sine and cosine per amplitude); short ones multiply.
+            bool unit = true;
+            int nlocal = 0;
+            for (int q = i; q < e; ++q) {
+                const TileGate &d = gates.get(q);
+                unit &= d.unit != 0;
+                nlocal += (d.l_target >= 0 || d.l_mask) ? 1 : 0;
+            }
+            if (unit && nlocal >= kPhaseSweepMin) {  // uniform
+                diag_sweep_phases<R, THREADS>(tile, base, T, gates, i, e);
+                i = e;
+                continue;
+            }
+            // multiply the factors: gates that read no tile-local bit give one
+            // factor for the whole tile, the others are applied per amplitude
+            R ur0 = (R)1, ui0 = (R)0;
+            for (int q = i; q < e; ++q) {
+                const TileGate &d = gates.get(q);
+                if ((base & d.o_mask) != d.o_vals || d.l_target >= 0 || d.l_mask)
+                    continue;
+                const bool one = (base >> d.target) & 1ull;
+                const R ur = (R)(one ? d.m[6] : d.m[0]), ui = (R)(one ? d.m[7] : d.m[1]);
+                const R nr = ur0 * ur - ui0 * ui;
+                ui0 = ur0 * ui + ui0 * ur;
+                ur0 = nr;
+            }
+            // four amplitudes per lane at a time (named scalars, not an array:
+            // the descriptor loads are shared and everything stays in registers)
+            for (uint32_t j0 = threadIdx.x; j0 < T; j0 += 4 * THREADS) {
+                const uint32_t j1 = j0 + THREADS, j2 = j0 + 2 * THREADS, j3 = j0 + 3 * THREADS;
+                R f0r = ur0, f0i = ui0, f1r = ur0, f1i = ui0, f2r = ur0, f2i = ui0, f3r = ur0, f3i = ui0;
                 for (int q = i; q < e; ++q) {
                     const TileGate &d = gates.get(q);
-                    if ((k & d.hi_mask) != d.hi_vals)
-                        continue;
-                    const int o = ((k >> d.target) & 1ull) ? 6 : 0;
-                    const R ur = (R)d.m[o], ui = (R)d.m[o + 1];
-                    const R nr = fr * ur - fi * ui;
-                    fi = fr * ui + fi * ur;
-                    fr = nr;
+                    if ((base & d.o_mask) != d.o_vals || (d.l_target < 0 && !d.l_mask))
+                        continue;  // uniform
+                    const bool tin = d.l_target >= 0;
+                    const bool tone = (base >> d.target) & 1ull;
+                    const R m0r = (R)uniform_f64(d.m[0]), m0i = (R)uniform_f64(d.m[1]);
+                    const R m1r = (R)uniform_f64(d.m[6]), m1i = (R)uniform_f64(d.m[7]);
+                    auto mul = [&](R &fr, R &fi, uint32_t j) {
+                        const bool on = (j & d.l_mask) == d.l_vals;
+                        const bool one = tin ? ((j >> d.l_target) & 1u) : tone;
+                        const R ur = on ? (one ? m1r : m0r) : (R)1, ui = on ? (one ? m1i : m0i) : (R)0;
+                        const R nr = fr * ur - fi * ui;
+                        fi = fr * ui + fi * ur;
+                        fr = nr;
+                    };
+                    mul(f0r, f0i, j0);
+                    mul(f1r, f1i, j1);
+                    mul(f2r, f2i, j2);
+                    mul(f3r, f3i, j3);
                 }
-                const cplx_t<R> v = tile[j];
-                cplx_t<R> w;
-                w.x = v.x * fr - v.y * fi;
-                w.y = v.x * fi + v.y * fr;
-                tile[j] = w;
+                auto put = [&](R fr, R fi, uint32_t j) {
+                    if (j < T) {
+                        const cplx_t<R> v = tile[j];
+                        cplx_t<R> w;
+                        w.x = v.x * fr - v.y * fi;
+                        w.y = v.x * fi + v.y * fr;
+                        tile[j] = w;
+                    }
+                };
+                put(f0r, f0i, j0);
+                put(f1r, f1i, j1);
+                put(f2r, f2i, j2);
+                put(f3r, f3i, j3);
             }
             __syncthreads();
+            i = e;
+            continue;
+        }
+        if (g.grp >= 2) {
+            // each lane holds the 8 amplitudes of one coset of Q in registers
+            // and applies the whole group to them: one LDS round trip for
+            // the group instead of one per gate
+            const int e = i + (int)g.grp;
+            bool act = false;
+            for (int q = i; q < e; ++q) {
+                const TileGate &d = gates.get(q);
+                act |= (base & d.hi_mask) == d.hi_vals;
+            }
+            if (act) {  // uniform
+                for (uint32_t x = threadIdx.x; x < (T >> 3); x += THREADS) {
+                    // the coset's base: the lane's index with zeros inserted
+                    // at the qubits of Q (qpos is ascending)
+                    uint32_t c = x;
+#pragma unroll
+                    for (int b = 0; b < 3; ++b)
+                        c = ((c >> g.qpos[b]) << (g.qpos[b] + 1)) | (c & ((1u << g.qpos[b]) - 1));
+                    cplx_t<R> a[8];
+#pragma unroll
+                    for (int v = 0; v < 8; ++v)
+                        a[v] = tile[c | ((v & 1u) << g.qpos[0]) | (((v >> 1) & 1u) << g.qpos[1]) |
+                                    (((v >> 2) & 1u) << g.qpos[2])];
+                    for (int q = i; q < e; ++q) {
+                        const TileGate &d = gates.get(q);
+                        reg_gate<R>(a, d, (base & d.hi_mask) == d.hi_vals, (c & d.lcm) == d.lcv);
+                    }
+#pragma unroll
+                    for (int v = 0; v < 8; ++v)
+                        tile[c | ((v & 1u) << g.qout[0]) | (((v >> 1) & 1u) << g.qout[1]) |
+                             (((v >> 2) & 1u) << g.qout[2])] = a[v];
+                }
+                __syncthreads();
+            }
             i = e;
             continue;
         }
@@ -172,7 +458,22 @@ __global__ __launch_bounds__(THREADS) void k_tile(cplx_t<R> *__restrict__ psi, T
         }
         ++i;
     }
+}
 
+// One workgroup per tile.  Dynamic LDS holds the 2^m amplitudes.
+template <typename R, int THREADS, typename Src>
+__global__ __launch_bounds__(THREADS) void k_tile(cplx_t<R> *__restrict__ psi, TileMap tm, Src gates) {
+    extern __shared__ unsigned char lds_raw[];
+    cplx_t<R> *tile = reinterpret_cast<cplx_t<R> *>(lds_raw);
+    const uint64_t base = expand_index<uint64_t>(tm.outer, (uint64_t)blockIdx.x);
+    const uint32_t T = 1u << tm.m;
+    // a tile that no operation of the run touches is left alone
+    if (!tile_touched(base, gates))
+        return;
+    for (uint32_t j = threadIdx.x; j < T; j += THREADS)
+        tile[j] = ld_stream<R>(psi + (base | tile_offset(tm, j)));
+    __syncthreads();
+    tile_run<R, THREADS>(tile, base, tm, gates);
     for (uint32_t j = threadIdx.x; j < T; j += THREADS)
         st_stream<R>(psi + (base | tile_offset(tm, j)), tile[j]);
 }

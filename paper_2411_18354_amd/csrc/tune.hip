@@ -21,7 +21,7 @@ Tuning &tuning() {
     //    qubits, i.e. 1 KiB contiguous runs, plus qubits picked per run.
     //  - dense blocks (SV_DENSE) on the 4 lowest qubits for stretches of at
     //    least 16 gates.
-    static Tuning t = {{3, 4}, 1, 1, {12, 13}, {6, 7}, 2, 4, 16};
+    static Tuning t = {{3, 4}, 1, 1, {12, 13}, {6, 7}, 2, 4, 16, 0};
     return t;
 }
 
@@ -45,6 +45,7 @@ static int find_key(const char *name, Key *out) {
         {"fuse_min_gates", &t.fuse_min_gates, 1, 1 << 20},
         {"dense_qubits", &t.dense_qubits, 4, 5},
         {"dense_min_gates", &t.dense_min_gates, 1, 1 << 20},
+        {"tile_groups", &t.tile_groups, 0, 1},
     };
     for (const Key &k : keys)
         if (name && strcmp(k.name, name) == 0) {
@@ -120,6 +121,8 @@ static int time_events(hipStream_t st, int reps, float *ms_out, const std::funct
     return r;
 }
 
+bool dense_supported(int dtype, int kq, int n);
+
 static std::string tune_json(const DeviceInfo &di, int dtype) {
     const Tuning &t = tuning();
     const int d = dtype == SV_C128 ? 0 : 1;
@@ -127,7 +130,8 @@ static std::string tune_json(const DeviceInfo &di, int dtype) {
     o << "{\"arch\": \"" << di.arch << "\", \"dtype\": \"" << (dtype == SV_C128 ? "c128" : "c64")
       << "\", \"granule_bits\": " << t.granule_bits[d] << ", \"low_policy\": " << t.low_policy
       << ", \"wave_auto\": " << t.wave_auto << ", \"tile_log2\": " << t.tile_log2[d]
-      << ", \"tile_low_bits\": " << t.tile_low_bits[d] << "}";
+      << ", \"tile_low_bits\": " << t.tile_low_bits[d] << ", \"tile_groups\": " << t.tile_groups
+      << ", \"dense_min_gates\": " << t.dense_min_gates << "}";
     return o.str();
 }
 
@@ -161,6 +165,13 @@ static int apply_tune_json(const std::string &line, const std::string &arch) {
         const bool per_dtype = strcmp(k, "low_policy") != 0 && strcmp(k, "wave_auto") != 0;
         const std::string name = std::string(k) + (per_dtype ? sfx : "");
         SV_TRY(sv_tune_set(name.c_str(), atoll(v.c_str())));
+    }
+    // optional fields (a record may omit them)
+    const char *opt[] = {"tile_groups", "dense_min_gates"};
+    for (const char *k : opt) {
+        std::string v;
+        if (field(k, &v))
+            SV_TRY(sv_tune_set(k, atoll(v.c_str())));
     }
     return SV_OK;
 }
@@ -303,6 +314,53 @@ int sv_autotune(int n, int dtype, const char *cache_path, char *report, int repo
             }
         t.tile_log2[d] = bw;
         t.tile_low_bits[d] = bl;
+        // 4. register groups in fused runs, on the same circuit
+        float msg[2] = {0, 0};
+        const int g0 = t.tile_groups;
+        for (int grp = 0; grp < 2 && r == SV_OK; ++grp) {
+            t.tile_groups = grp;
+            sv_circuit_t *c = nullptr;
+            r = sv_circuit_create(n, dtype, gates.data(), (int)gates.size(), 0, SV_FUSE, &c);
+            if (r != SV_OK)
+                break;
+            r = time_events(st, 3, &msg[grp], [&]() -> int { return sv_circuit_run(c, &s, nullptr, st); });
+            (void)sv_circuit_destroy(c);
+            rep << "tile_groups " << grp << ": " << msg[grp] << " ms\n";
+        }
+        t.tile_groups = r == SV_OK ? (msg[1] < msg[0] ? 1 : 0) : g0;
+    }
+    // 5. dense blocks against fused gates for a long stretch on the low qubits
+    if (r == SV_OK && dense_supported(dtype, t.dense_qubits, n)) {
+        std::vector<sv_gate_t> gates;
+        const int k = t.dense_qubits;
+        for (int i = 0; i < 48; ++i) {
+            sv_gate_t g;
+            memset(&g, 0, sizeof(g));
+            g.param = -1;
+            g.target = i % k;
+            if (i % 3 == 2) {
+                g.kind = SV_G_X;
+                g.ctrl_mask = g.ctrl_vals = 1ull << ((i + 1) % k);
+            } else {
+                g.kind = i % 3 ? SV_G_RY : SV_G_H;
+                g.theta = 0.1 * i;
+            }
+            gates.push_back(g);
+        }
+        float msd[2] = {0, 0};
+        for (int dn = 0; dn < 2 && r == SV_OK; ++dn) {
+            sv_circuit_t *c = nullptr;
+            r = sv_circuit_create(n, dtype, gates.data(), (int)gates.size(), 0, dn ? (SV_FUSE | SV_DENSE) : SV_FUSE,
+                                  &c);
+            if (r != SV_OK)
+                break;
+            r = time_events(st, 3, &msd[dn], [&]() -> int { return sv_circuit_run(c, &s, nullptr, st); });
+            (void)sv_circuit_destroy(c);
+            rep << (dn ? "dense block" : "fused gates") << " for a 48-gate stretch: " << msd[dn] << " ms\n";
+        }
+        // SV_DENSE only turns stretches into dense blocks when that is faster
+        if (r == SV_OK && msd[1] >= msd[0])
+            t.dense_min_gates = 1 << 20;
     }
     (void)hipStreamSynchronize(st);
     (void)sv_free(&s);

@@ -155,3 +155,23 @@ def test_library_gate_matrices_match_definitions(sv):
             assert np.max(np.abs(a - np.stack([m.real, m.imag], -1).reshape(8))) < 1e-15, (k, th)
     U = W.haar_unitary_2x2(5)
     assert np.allclose(sv.sv_gate_matrix("U", 0.0, U), U)
+
+
+def test_circuit_json_round_trip(tmp_path):
+    """The serialised circuit format reproduces every gate exactly (angles,
+    parameters, explicit matrices, negative controls)."""
+    circs = [W.qft(6), W.hea(5, 2, seed=3), W.random_gates_n12(seed=4, n=7, ngates=40),
+             W.Circuit(4, [W.Gate("U", 1, (0, 3), (1, 0), matrix=tuple(W.haar_unitary_2x2(5))),
+                           W.Gate("RY", 2, (), (), param=0)], np.array([0.123456789012345678]))]
+    path = str(tmp_path / "c.jsonl")
+    W.save_circuits(path, circs)
+    back = W.load_circuits(path)
+    assert len(back) == len(circs)
+    for a, b in zip(circs, back):
+        assert a.n == b.n and a.gates == b.gates
+        assert (a.params is None) == (b.params is None)
+        if a.params is not None:
+            assert np.array_equal(a.params, b.params)
+        psi_a = oracle.run_circuit(a, a.params)
+        psi_b = oracle.run_circuit(b, b.params)
+        assert np.array_equal(psi_a, psi_b)

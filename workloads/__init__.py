@@ -79,6 +79,45 @@ class Circuit:
 
 
 # --------------------------------------------------------------------------
+# serialised circuit format (JSON): one object per circuit
+#   {"n": n, "gates": [[kind, target, [controls], [values], theta, param,
+#                       matrix-or-null], ...], "params": [...] or null,
+#    "meta": {...}}
+# Floats are written with repr precision, so a round trip is exact.
+# --------------------------------------------------------------------------
+
+def circuit_to_json(c: Circuit) -> dict:
+    return {"n": int(c.n),
+            "gates": [[g.kind, int(g.target), [int(q) for q in g.controls], [int(v) for v in g.values],
+                       float(g.theta), int(g.param), None if g.matrix is None else [float(x) for x in g.matrix]]
+                      for g in c.gates],
+            "params": None if c.params is None else [float(x) for x in c.params],
+            "meta": dict(c.meta)}
+
+
+def circuit_from_json(d: dict) -> Circuit:
+    gates = [Gate(k, int(t), tuple(int(q) for q in cs), tuple(int(v) for v in vs), float(th), int(p),
+                  None if m is None else tuple(float(x) for x in m))
+             for k, t, cs, vs, th, p, m in d["gates"]]
+    params = None if d.get("params") is None else np.asarray(d["params"], dtype=np.float64)
+    return Circuit(int(d["n"]), gates, params, dict(d.get("meta") or {}))
+
+
+def save_circuits(path: str, circuits: Sequence[Circuit]) -> None:
+    """One JSON object per line."""
+    import json
+    with open(path, "w") as f:
+        for c in circuits:
+            f.write(json.dumps(circuit_to_json(c)) + "\n")
+
+
+def load_circuits(path: str) -> List[Circuit]:
+    import json
+    with open(path) as f:
+        return [circuit_from_json(json.loads(line)) for line in f if line.strip()]
+
+
+# --------------------------------------------------------------------------
 # random primitives
 # --------------------------------------------------------------------------
 
