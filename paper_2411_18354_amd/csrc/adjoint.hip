@@ -90,17 +90,24 @@ __global__ __launch_bounds__(kAdjTileThreads) void k_adj_tile(cplx_t<R> *__restr
     const uint32_t T = 1u << tm.m;
     cplx_t<R> *tp = reinterpret_cast<cplx_t<R> *>(lds_raw);
     cplx_t<R> *tl = tp + T;
-    __shared__ double scratch[kAdjTileThreads / 64];
-    if (threadIdx.x == 0)
-        for (int i = 0; i < gates.size(); ++i)
-            if (gslot[i] >= 0)
-                partials[(size_t)gslot[i] * kMaxPartials + blockIdx.x] = 0.0;
+    // after the two tiles: one gradient accumulator per wavefront for each
+    // parameterised gate of the run (k-th such gate: accl[k * kWaves + w]),
+    // so a gate's sum needs a wavefront reduction but no workgroup barrier
+    constexpr int kWaves = kAdjTileThreads / 64;
+    double *accl = reinterpret_cast<double *>(tl + T);
+    const int w = threadIdx.x >> 6;
+    int npg = 0;
+    for (int i = 0; i < gates.size(); ++i)
+        npg += gslot[i] >= 0 ? 1 : 0;
+    for (int k = threadIdx.x; k < npg * kWaves; k += kAdjTileThreads)
+        accl[k] = 0.0;
+    __syncthreads();
     for (uint64_t t = blockIdx.x; t < tm.ntiles; t += gridDim.x) {
         const uint64_t base = expand_index<uint64_t>(tm.outer, t);
         bool any = false;
         for (int i = 0; i < gates.size(); ++i) {
             const TileGate &g = gates.get(i);
-            any |= g.diag ? true : ((base & g.hi_mask) == g.hi_vals);
+            any |= g.diag ? ((base & g.o_mask) == g.o_vals) : ((base & g.hi_mask) == g.hi_vals);
         }
         if (!any)
             continue;  // uniform
@@ -110,6 +117,7 @@ __global__ __launch_bounds__(kAdjTileThreads) void k_adj_tile(cplx_t<R> *__restr
             tl[j] = ld_stream<R>(lam + k);
         }
         __syncthreads();
+        int kacc = 0;  // parameterised gates seen so far in this run
         for (int i = 0; i < gates.size(); ++i) {
             const TileGate &g = gates.get(i);
             const int sl = gslot[i];
@@ -119,32 +127,41 @@ __global__ __launch_bounds__(kAdjTileThreads) void k_adj_tile(cplx_t<R> *__restr
             double acc = 0.0;
             bool did = false;
             if (g.diag) {
-                did = true;
-                for (uint32_t j = threadIdx.x; j < T; j += kAdjTileThreads) {
-                    const uint64_t k = base | tile_offset(tm, j);
-                    if ((k & g.hi_mask) != g.hi_vals)
-                        continue;
-                    const int o = ((k >> g.target) & 1ull) ? 6 : 0;
-                    const cplx_t<R> x = tp[j], lx = tl[j];
-                    if (sl >= 0) {
-                        const double axr = a[o] * x.x - a[o + 1] * x.y, axi = a[o] * x.y + a[o + 1] * x.x;
-                        acc += 2.0 * ((double)lx.x * axr + (double)lx.y * axi);
+                if ((base & g.o_mask) == g.o_vals) {  // uniform
+                    did = true;
+                    const bool tin = g.l_target >= 0;
+                    const bool tone = (base >> g.target) & 1ull;
+                    // entries made wave-uniform before the per-lane select
+                    const R m0r = (R)uniform_f64(g.m[0]), m0i = (R)uniform_f64(g.m[1]);
+                    const R m1r = (R)uniform_f64(g.m[6]), m1i = (R)uniform_f64(g.m[7]);
+                    for (uint32_t j = threadIdx.x; j < T; j += kAdjTileThreads) {
+                        if ((j & g.l_mask) != g.l_vals)
+                            continue;
+                        const bool one = tin ? ((j >> g.l_target) & 1u) : tone;
+                        const cplx_t<R> x = tp[j], lx = tl[j];
+                        if (sl >= 0) {
+                            const double gr = one ? a[6] : a[0], gi = one ? a[7] : a[1];
+                            const double axr = gr * x.x - gi * x.y, axi = gr * x.y + gi * x.x;
+                            acc += 2.0 * ((double)lx.x * axr + (double)lx.y * axi);
+                        }
+                        const R ur = one ? m1r : m0r, ui = one ? m1i : m0i;
+                        cplx_t<R> nx, nl;
+                        nx.x = x.x * ur - x.y * ui;
+                        nx.y = x.x * ui + x.y * ur;
+                        nl.x = lx.x * ur - lx.y * ui;
+                        nl.y = lx.x * ui + lx.y * ur;
+                        tp[j] = nx;
+                        tl[j] = nl;
                     }
-                    const R ur = (R)g.m[o], ui = (R)g.m[o + 1];
-                    cplx_t<R> nx, nl;
-                    nx.x = x.x * ur - x.y * ui;
-                    nx.y = x.x * ui + x.y * ur;
-                    nl.x = lx.x * ur - lx.y * ui;
-                    nl.y = lx.x * ui + lx.y * ur;
-                    tp[j] = nx;
-                    tl[j] = nl;
                 }
             } else if ((base & g.hi_mask) == g.hi_vals) {  // uniform
                 did = true;
                 const Mat2<R> u = tile_mat<R>(g);
                 const uint32_t st = 1u << g.target;
+                const bool in_regs = g.nseg <= (uint32_t)kExpRegs;  // uniform
+                const TileExp ex = tile_exp_load(g);
                 for (uint32_t r = threadIdx.x; r < g.npairs; r += kAdjTileThreads) {
-                    const uint32_t p1 = tile_expand(g, r);
+                    const uint32_t p1 = in_regs ? tile_exp(ex, r) : tile_expand(g, r);
                     cplx_t<R> x = tp[p1], y = tp[p1 | st], lx = tl[p1], ly = tl[p1 | st];
                     if (sl >= 0) {
                         const double xr = x.x, xi = x.y, yr = y.x, yi = y.y;
@@ -163,14 +180,15 @@ __global__ __launch_bounds__(kAdjTileThreads) void k_adj_tile(cplx_t<R> *__restr
                     tl[p1 | st] = ly;
                 }
             }
-            if (did) {
-                if (sl >= 0) {  // uniform; block_sum synchronises
-                    const double s = block_sum(acc, scratch);
-                    if (threadIdx.x == 0)
-                        partials[(size_t)sl * kMaxPartials + blockIdx.x] += s;
+            if (did) {  // uniform
+                if (sl >= 0) {
+                    const double s = wave_sum(acc);
+                    if ((threadIdx.x & 63) == 0)
+                        accl[kacc * kWaves + w] += s;
                 }
                 __syncthreads();
             }
+            kacc += sl >= 0 ? 1 : 0;
         }
         for (uint32_t j = threadIdx.x; j < T; j += kAdjTileThreads) {
             const uint64_t k = base | tile_offset(tm, j);
@@ -178,6 +196,23 @@ __global__ __launch_bounds__(kAdjTileThreads) void k_adj_tile(cplx_t<R> *__restr
             st_stream<R>(lam + k, tl[j]);
         }
         __syncthreads();
+    }
+    // this workgroup's partial of every parameterised gate: its wavefronts'
+    // accumulators summed in index order
+    __syncthreads();
+    for (int k = threadIdx.x; k < npg; k += kAdjTileThreads) {
+        double s = 0.0;
+        for (int q = 0; q < kWaves; ++q)
+            s += accl[k * kWaves + q];
+        int c = 0;
+        for (int i = 0; i < gates.size(); ++i)
+            if (gslot[i] >= 0) {
+                if (c == k) {
+                    partials[(size_t)gslot[i] * kMaxPartials + blockIdx.x] = s;
+                    break;
+                }
+                ++c;
+            }
     }
 }
 
@@ -370,7 +405,23 @@ int adjoint_impl(const sv_state_t *psi, const sv_state_t *lam, const sv_gate_t *
         r = circuit_param_mats(rc, params, st);
     if (r == SV_OK)
         r = launch_apply_paulis(dtype, psi->data, lam->data, n, pd, st, &loss_blocks);
-    const size_t lds = ((size_t)2 << rc->m) * amp_bytes(dtype);
+    // dynamic LDS: the two tiles, then 8 accumulators per parameterised gate
+    // of the pass (sized for the largest pass)
+    std::vector<size_t> pass_lds(rc->passes.size(), 0);
+    size_t lds = 0;
+    for (size_t pi = 0; pi < rc->passes.size(); ++pi) {
+        const Pass &p = rc->passes[pi];
+        if (!p.fused)
+            continue;
+        size_t npg = 0;
+        for (int j = 0; j < p.count; ++j)
+            npg += dslot[p.first + j] >= 0 ? 1 : 0;
+        pass_lds[pi] = ((size_t)2 << rc->m) * amp_bytes(dtype) + npg * (kAdjTileThreads / 64) * sizeof(double);
+        lds = std::max(lds, pass_lds[pi]);
+    }
+    constexpr size_t kLdsPerWorkgroup = 160 * 1024;  // gfx950, with the opt-in limit raised
+    if (r == SV_OK && lds > kLdsPerWorkgroup)
+        r = fail(SV_ENOTSUP, "adjoint pass needs %zu bytes of LDS", lds);
     if (r == SV_OK && lds > 65536) {
         const hipError_t e = dtype == SV_C128 ? hipFuncSetAttribute((const void *)k_adj_tile<double>,
                                                                     hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -387,11 +438,12 @@ int adjoint_impl(const sv_state_t *psi, const sv_state_t *lam, const sv_gate_t *
             const unsigned grid = (unsigned)std::min<uint64_t>(p.tm.ntiles, kMaxPartials);
             const DeviceGates dg{rc->d_tiles + p.first, p.count};
             if (dtype == SV_C128)
-                hipLaunchKernelGGL(k_adj_tile<double>, dim3(grid), dim3(kAdjTileThreads), lds, st,
+                hipLaunchKernelGGL(k_adj_tile<double>, dim3(grid), dim3(kAdjTileThreads), pass_lds[pi], st,
                                    (double2 *)psi->data, (double2 *)lam->data, p.tm, dg, d_dslot + p.first, d_gen,
                                    d_partials);
             else
-                hipLaunchKernelGGL(k_adj_tile<float>, dim3(grid), dim3(kAdjTileThreads), lds, st, (float2 *)psi->data,
+                hipLaunchKernelGGL(k_adj_tile<float>, dim3(grid), dim3(kAdjTileThreads), pass_lds[pi], st,
+                                   (float2 *)psi->data,
                                    (float2 *)lam->data, p.tm, dg, d_dslot + p.first, d_gen, d_partials);
         } else {
             const GatePlan &gp = single_plan[pi];

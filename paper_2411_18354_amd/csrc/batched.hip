@@ -64,13 +64,13 @@ struct BCirc {
 };
 
 // Insert the target bit (0) and the control bits (their values) into x,
-// lowest position first.
-__device__ __forceinline__ uint64_t insert_bits(uint64_t x, uint64_t positions, uint64_t vals) {
+// lowest position first.  I: uint32_t when every index fits 32 bits.
+template <typename I> __device__ __forceinline__ I insert_bits(I x, I positions, I vals) {
     while (positions) {
-        const int p = __builtin_ctzll(positions);
+        const int p = sizeof(I) == 8 ? __builtin_ctzll((uint64_t)positions) : __builtin_ctz((uint32_t)positions);
         positions &= positions - 1;
-        const uint64_t lo = x & ((1ull << p) - 1);
-        x = ((x >> p) << (p + 1)) | (((vals >> p) & 1ull) << p) | lo;
+        const I lo = x & (((I)1 << p) - 1);
+        x = ((x >> p) << (p + 1)) | (((vals >> p) & (I)1) << p) | lo;
     }
     return x;
 }
@@ -107,23 +107,23 @@ __device__ __forceinline__ Mat2<R> bgate_mat(const BGate &g, const double *param
 // Apply one gate (target, controls) to amplitudes held at base[0 .. 2^nbits)
 // (LDS or global), controls below nbits enumerated, controls at or above
 // nbits already known to hold.
-template <typename R>
-__device__ __forceinline__ void gate_on_block(cplx_t<R> *base, int nbits, int target, uint64_t cmask, uint64_t cvals,
-                                              const Mat2<R> &mm) {
-    const uint64_t lowm = (1ull << nbits) - 1;
-    const uint64_t cm = cmask & lowm;
-    const uint64_t pos = cm | (1ull << target);
-    const uint64_t npairs = 1ull << (nbits - 1 - __popcll(cm));
-    const uint64_t st = 1ull << target;
-    const uint64_t cv = cvals & cm;
+template <typename R, typename I>
+__device__ __forceinline__ void gate_on_block_i(cplx_t<R> *base, int nbits, int target, uint64_t cmask,
+                                                uint64_t cvals, const Mat2<R> &mm) {
+    const uint64_t lowm = (nbits >= 64) ? ~0ull : ((1ull << nbits) - 1);
+    const I cm = (I)(cmask & lowm);
+    const I pos = cm | ((I)1 << target);
+    const I npairs = (I)1 << (nbits - 1 - __popcll((uint64_t)cm));
+    const I st = (I)1 << target;
+    const I cv = (I)(cvals & cm);
     constexpr int U = 4;  // pairs per lane per step: 2U loads in flight
-    for (uint64_t i0 = threadIdx.x; i0 < npairs; i0 += (uint64_t)U * kBatchThreads) {
+    for (I i0 = threadIdx.x; i0 < npairs; i0 += (I)U * kBatchThreads) {
         cplx_t<R> x[U], y[U];
-        uint64_t p1[U];
+        I p1[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const uint64_t i = i0 + (uint64_t)u * kBatchThreads;
-            p1[u] = insert_bits(i, pos, cv);
+            const I i = i0 + (I)u * kBatchThreads;
+            p1[u] = insert_bits<I>(i, pos, cv);
             if (i < npairs) {
                 x[u] = base[p1[u]];
                 y[u] = base[p1[u] | st];
@@ -131,13 +131,24 @@ __device__ __forceinline__ void gate_on_block(cplx_t<R> *base, int nbits, int ta
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            if (i0 + (uint64_t)u * kBatchThreads < npairs) {
+            if (i0 + (I)u * kBatchThreads < npairs) {
                 apply_pair<R>(mm, x[u], y[u]);
                 base[p1[u]] = x[u];
                 base[p1[u] | st] = y[u];
             }
         }
     }
+}
+
+// 32-bit index arithmetic whenever the block's indices fit (always for LDS
+// tiles; for global memory up to n = 32).
+template <typename R>
+__device__ __forceinline__ void gate_on_block(cplx_t<R> *base, int nbits, int target, uint64_t cmask, uint64_t cvals,
+                                              const Mat2<R> &mm) {
+    if (nbits <= 32)
+        gate_on_block_i<R, uint32_t>(base, nbits, target, cmask, cvals, mm);
+    else
+        gate_on_block_i<R, uint64_t>(base, nbits, target, cmask, cvals, mm);
 }
 
 template <typename R>
@@ -172,7 +183,7 @@ __device__ void run_circuit_block(const BCirc &c, const BGate *__restrict__ gate
             const uint64_t T = 1ull << m, ntiles = N >> m;
             for (uint64_t tt = 0; tt < ntiles; ++tt) {
                 // the tile's fixed bits: tt spread over the qubits outside S
-                const uint64_t base = insert_bits(tt << a, high, 0);
+                const uint64_t base = insert_bits<uint64_t>(tt << a, high, 0);
                 bool any = false;
                 for (int k = i; k < j; ++k) {
                     const BGate &g = gates[c.first_gate + k];
@@ -281,7 +292,7 @@ __device__ void adjoint_block(const BCirc &c, const BGate *__restrict__ gates, c
         const uint64_t st = 1ull << g.target;
         double acc = 0.0;
         for (uint64_t it = threadIdx.x; it < npairs; it += kBatchThreads) {
-            const uint64_t p1 = insert_bits(it, pos, g.cvals);
+            const uint64_t p1 = insert_bits<uint64_t>(it, pos, g.cvals);
             cplx_t<R> x = psi[p1], y = psi[p1 | st], lx = lam[p1], ly = lam[p1 | st];
             if (gs >= 0) {
                 const double xr = x.x, xi = x.y, yr = y.x, yi = y.y;

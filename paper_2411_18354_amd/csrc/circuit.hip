@@ -210,8 +210,6 @@ static int plan_circuit(sv_circuit *c, std::vector<TileGate> &tiles, std::vector
                     tiles.back().src_gate = gi;
                     c->tile_src.push_back(gi);
                 }
-                if (c->reg_groups && tuning().tile_groups)
-                    form_register_groups(p.tm, &tiles[p.first], p.count);
                 c->passes.push_back(p);
                 c->fused_gates += (int64_t)run.size();
                 c->fused_runs++;

@@ -29,7 +29,6 @@ struct sv_circuit {
     int m_cap = 64;  // upper bound on the tile width (callers with a fixed LDS budget)
     bool general_tiles = true;  // tiles over any qubit set; false: contiguous tiles only
     bool diag_any = true;       // diagonal gates join runs whatever their target
-    bool reg_groups = true;     // register groups in fused runs (forward tile kernels)
     std::vector<sv_gate_t> gates;
     std::vector<sv::Pass> passes;
     std::vector<int32_t> tile_src;  // gate index of every fused-run descriptor

@@ -169,61 +169,6 @@ TileMap make_tile_map(int n, int m, int a, const std::vector<int> &high, uint64_
 
 TileMap contiguous_tile_map(int n, int m) { return make_tile_map(n, m, m, {}); }
 
-void form_register_groups(const TileMap &tm, TileGate *t, int count) {
-    const int m = (int)tm.m;
-    if (m < 3)
-        return;
-    int k = 0;
-    while (k < count) {
-        if (t[k].diag) {
-            ++k;
-            continue;
-        }
-        uint32_t Q = 1u << t[k].target;
-        int j = k + 1;
-        while (j < count && !t[j].diag && __builtin_popcount(Q | (1u << t[j].target)) <= 3) {
-            Q |= 1u << t[j].target;
-            ++j;
-        }
-        if (j - k >= 2) {
-            // pad Q to three qubits with the highest free tile-local bits, so
-            // the lanes' cosets stay contiguous in LDS
-            for (int b = m - 1; b >= 0 && __builtin_popcount(Q) < 3; --b)
-                Q |= 1u << b;
-            uint32_t qp[3];
-            int nq = 0;
-            for (int b = 0; b < m; ++b)
-                if (Q & (1u << b))
-                    qp[nq++] = (uint32_t)b;
-            // f[i]: the qubit of Q (as an index into qp) held by register bit i
-            int f[3] = {0, 1, 2};
-            t[k].grp = (uint32_t)(j - k);
-            for (int i = 0; i < 3; ++i)
-                t[k].qpos[i] = qp[i];
-            for (int g = k; g < j; ++g) {
-                TileGate &d = t[g];
-                int r = 0;
-                while (qp[f[r]] != d.target)
-                    ++r;
-                d.swp = (uint32_t)r;
-                std::swap(f[0], f[r]);
-                for (int i = 0; i < 3; ++i) {
-                    const uint32_t q = qp[f[i]];
-                    if (d.l_mask & (1u << q)) {
-                        d.qmask |= 1u << i;
-                        d.qvals |= ((d.l_vals >> q) & 1u) << i;
-                    }
-                }
-                d.lcm = d.l_mask & ~Q;
-                d.lcv = d.l_vals & d.lcm;
-            }
-            for (int i = 0; i < 3; ++i)
-                t[k].qout[i] = qp[f[i]];
-        }
-        k = j;
-    }
-}
-
 // Tile-local bit of global qubit q, or -1 when q is outside S.
 static int local_bit(const TileMap &tm, int q) {
     if (q < (int)tm.a)

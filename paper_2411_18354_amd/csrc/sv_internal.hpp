@@ -139,7 +139,6 @@ struct Tuning {
     int fuse_min_gates;   // shortest run worth an LDS pass
     int dense_qubits;     // k of dense k-qubit blocks (SV_DENSE)
     int dense_min_gates;  // shortest stretch on qubits < k made a dense block
-    int tile_groups;      // fused runs apply register groups (3-qubit cosets)
 };
 Tuning &tuning();
 

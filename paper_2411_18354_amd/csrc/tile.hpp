@@ -48,18 +48,6 @@ struct TileGate {
     uint64_t o_mask, o_vals;
     uint32_t l_mask, l_vals;
     int32_t l_target;
-    // register group of consecutive pair gates whose targets lie in three
-    // tile-local qubits Q.  Each lane holds 8 amplitudes a[v]; bit i of the
-    // register index v stands for one qubit of Q, and the assignment is
-    // permuted as the group goes so that every gate's target sits on bit 0.
-    // At the group's first gate: grp = gates in the group, qpos / qout = the
-    // tile-local qubit of each register bit when loading / storing.  Per
-    // gate: swp = register bit swapped with bit 0 before the gate (0: none),
-    // qmask/qvals = its controls inside Q as register-index bits (after the
-    // swap), lcm/lcv = its tile-local controls outside Q.
-    uint32_t grp;
-    uint32_t qpos[3], qout[3];
-    uint32_t swp, qmask, qvals, lcm, lcv;
     // diagonal gate: phases of its two entries, and whether both have unit
     // modulus (then a sweep may add phases instead of multiplying factors)
     uint32_t unit;
@@ -101,10 +89,6 @@ TileMap make_tile_map(int n, int m, int a, const std::vector<int> &high, uint64_
 // in S.
 TileGate make_tile_gate(const TileMap &tm, int target, uint64_t cmask, uint64_t cvals, const double *U,
                         bool diagonal);
-// Mark register groups among tiles[0 .. count) (one fused run; host): runs
-// of at least two consecutive pair gates whose targets span at most three
-// tile-local qubits.
-void form_register_groups(const TileMap &tm, TileGate *tiles, int count);
 // Contiguous tiles (S = {0 .. m-1}).
 TileMap contiguous_tile_map(int n, int m);
 
@@ -135,6 +119,35 @@ __device__ __forceinline__ uint32_t tile_expand(const TileGate &g, uint32_t x) {
     return p;
 }
 
+// A gate's in-tile pair expansion held in registers: up to kExpRegs
+// segments (the target plus up to four tile-local controls), unused ones
+// with an empty mask.  Loading it once per gate keeps the descriptor loads
+// out of the pair loop.
+constexpr int kExpRegs = 6;
+struct TileExp {
+    uint32_t fixed;
+    uint32_t sh[kExpRegs], mk[kExpRegs];
+};
+
+__device__ __forceinline__ TileExp tile_exp_load(const TileGate &g) {
+    TileExp e;
+    e.fixed = g.fixed;
+#pragma unroll
+    for (int s = 0; s < kExpRegs; ++s) {
+        e.sh[s] = s < (int)g.nseg ? g.shift[s] : 0u;
+        e.mk[s] = s < (int)g.nseg ? g.mask[s] : 0u;
+    }
+    return e;
+}
+
+__device__ __forceinline__ uint32_t tile_exp(const TileExp &e, uint32_t x) {
+    uint32_t p = e.fixed;
+#pragma unroll
+    for (int s = 0; s < kExpRegs; ++s)
+        p |= (x << e.sh[s]) & e.mk[s];
+    return p;
+}
+
 __device__ __forceinline__ uint64_t tile_offset(const TileMap &tm, uint32_t j) {
     uint64_t o = j & ((1u << tm.a) - 1);
     for (uint32_t s = 0; s < tm.nseg; ++s)
@@ -153,60 +166,6 @@ __device__ __forceinline__ double uniform_f64(double v) {
     const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)b);
     const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(b >> 32));
     return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
-}
-
-// Conditional swap and select written component-wise on values: a ternary
-// over whole aggregates selects between their addresses, which keeps a
-// register array in scratch memory.
-template <typename R> __device__ __forceinline__ void cswap(cplx_t<R> &x, cplx_t<R> &y, bool c) {
-    const R xr = x.x, xi = x.y, yr = y.x, yi = y.y;
-    x.x = c ? yr : xr;
-    x.y = c ? yi : xi;
-    y.x = c ? xr : yr;
-    y.y = c ? xi : yi;
-}
-
-template <typename R> __device__ __forceinline__ void csel(cplx_t<R> &dst, const cplx_t<R> &v, bool c) {
-    const R dr = dst.x, di = dst.y;
-    dst.x = c ? v.x : dr;
-    dst.y = c ? v.y : di;
-}
-
-// One gate of a register group on the 8 amplitudes a[v] of a coset: first
-// the register-bit swap that brings its target to bit 0 (selects only, so
-// the array stays in registers), then the pairs (v, v|1) whose controls in
-// Q hold.  active: the gate's tile predicate; cc: its tile-local controls
-// outside Q hold for this coset.
-template <typename R>
-__device__ __forceinline__ void reg_gate(cplx_t<R> (&a)[8], const TileGate &g, bool active, bool cc) {
-    // selects rather than branches: branches on swp get merged into one
-    // path indexing the array by swp, which moves it to scratch memory
-    const bool s1 = g.swp == 1, s2 = g.swp == 2;
-    cswap<R>(a[1], a[2], s1);
-    cswap<R>(a[5], a[6], s1);
-    cswap<R>(a[1], a[4], s2);
-    cswap<R>(a[3], a[6], s2);
-    if (!active)
-        return;  // uniform
-    const Mat2<R> mm = tile_mat<R>(g);
-    if (g.qmask == 0 && g.lcm == 0) {  // uniform: no control inside the tile
-#pragma unroll
-        for (int v0 = 0; v0 < 8; v0 += 2) {
-            cplx_t<R> x = a[v0], y = a[v0 + 1];
-            apply_pair<R>(mm, x, y);
-            a[v0] = x;
-            a[v0 + 1] = y;
-        }
-        return;
-    }
-#pragma unroll
-    for (int v0 = 0; v0 < 8; v0 += 2) {
-        const bool on = cc && (((uint32_t)v0 & g.qmask) == g.qvals);
-        cplx_t<R> x = a[v0], y = a[v0 + 1];
-        apply_pair<R>(mm, x, y);
-        csel<R>(a[v0], x, on);
-        csel<R>(a[v0 + 1], y, on);
-    }
 }
 
 // sin and cos of a phase: quadrant reduction by pi/2 held as two doubles
@@ -407,48 +366,14 @@ __device__ __forceinline__ void tile_run(cplx_t<R> *tile, uint64_t base, const T
             i = e;
             continue;
         }
-        if (g.grp >= 2) {
-            // each lane holds the 8 amplitudes of one coset of Q in registers
-            // and applies the whole group to them: one LDS round trip for
-            // the group instead of one per gate
-            const int e = i + (int)g.grp;
-            bool act = false;
-            for (int q = i; q < e; ++q) {
-                const TileGate &d = gates.get(q);
-                act |= (base & d.hi_mask) == d.hi_vals;
-            }
-            if (act) {  // uniform
-                for (uint32_t x = threadIdx.x; x < (T >> 3); x += THREADS) {
-                    // the coset's base: the lane's index with zeros inserted
-                    // at the qubits of Q (qpos is ascending)
-                    uint32_t c = x;
-#pragma unroll
-                    for (int b = 0; b < 3; ++b)
-                        c = ((c >> g.qpos[b]) << (g.qpos[b] + 1)) | (c & ((1u << g.qpos[b]) - 1));
-                    cplx_t<R> a[8];
-#pragma unroll
-                    for (int v = 0; v < 8; ++v)
-                        a[v] = tile[c | ((v & 1u) << g.qpos[0]) | (((v >> 1) & 1u) << g.qpos[1]) |
-                                    (((v >> 2) & 1u) << g.qpos[2])];
-                    for (int q = i; q < e; ++q) {
-                        const TileGate &d = gates.get(q);
-                        reg_gate<R>(a, d, (base & d.hi_mask) == d.hi_vals, (c & d.lcm) == d.lcv);
-                    }
-#pragma unroll
-                    for (int v = 0; v < 8; ++v)
-                        tile[c | ((v & 1u) << g.qout[0]) | (((v >> 1) & 1u) << g.qout[1]) |
-                             (((v >> 2) & 1u) << g.qout[2])] = a[v];
-                }
-                __syncthreads();
-            }
-            i = e;
-            continue;
-        }
         if ((base & g.hi_mask) == g.hi_vals) {  // uniform across the workgroup
             const Mat2<R> mm = tile_mat<R>(g);
             const uint32_t st = 1u << g.target;
-            for (uint32_t r = threadIdx.x; r < g.npairs; r += THREADS) {
-                const uint32_t p1 = tile_expand(g, r);
+            const uint32_t np = g.npairs;
+            const bool in_regs = g.nseg <= (uint32_t)kExpRegs;  // uniform
+            const TileExp ex = tile_exp_load(g);
+            for (uint32_t r = threadIdx.x; r < np; r += THREADS) {
+                const uint32_t p1 = in_regs ? tile_exp(ex, r) : tile_expand(g, r);
                 cplx_t<R> x = tile[p1], y = tile[p1 | st];
                 apply_pair<R>(mm, x, y);
                 tile[p1] = x;
@@ -460,9 +385,10 @@ __device__ __forceinline__ void tile_run(cplx_t<R> *tile, uint64_t base, const T
     }
 }
 
-// One workgroup per tile.  Dynamic LDS holds the 2^m amplitudes.
+// One workgroup per tile.  Dynamic LDS holds the 2^m amplitudes.  Two
+// 64 KiB tiles share a CU, so registers are capped for 4 waves per SIMD.
 template <typename R, int THREADS, typename Src>
-__global__ __launch_bounds__(THREADS) void k_tile(cplx_t<R> *__restrict__ psi, TileMap tm, Src gates) {
+__global__ __launch_bounds__(THREADS, 4) void k_tile(cplx_t<R> *__restrict__ psi, TileMap tm, Src gates) {
     extern __shared__ unsigned char lds_raw[];
     cplx_t<R> *tile = reinterpret_cast<cplx_t<R> *>(lds_raw);
     const uint64_t base = expand_index<uint64_t>(tm.outer, (uint64_t)blockIdx.x);

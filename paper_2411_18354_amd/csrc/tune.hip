@@ -21,7 +21,7 @@ Tuning &tuning() {
     //    qubits, i.e. 1 KiB contiguous runs, plus qubits picked per run.
     //  - dense blocks (SV_DENSE) on the 4 lowest qubits for stretches of at
     //    least 16 gates.
-    static Tuning t = {{3, 4}, 1, 1, {12, 13}, {6, 7}, 2, 4, 16, 0};
+    static Tuning t = {{3, 4}, 1, 1, {12, 13}, {6, 7}, 2, 4, 16};
     return t;
 }
 
@@ -45,7 +45,6 @@ static int find_key(const char *name, Key *out) {
         {"fuse_min_gates", &t.fuse_min_gates, 1, 1 << 20},
         {"dense_qubits", &t.dense_qubits, 4, 5},
         {"dense_min_gates", &t.dense_min_gates, 1, 1 << 20},
-        {"tile_groups", &t.tile_groups, 0, 1},
     };
     for (const Key &k : keys)
         if (name && strcmp(k.name, name) == 0) {
@@ -130,8 +129,8 @@ static std::string tune_json(const DeviceInfo &di, int dtype) {
     o << "{\"arch\": \"" << di.arch << "\", \"dtype\": \"" << (dtype == SV_C128 ? "c128" : "c64")
       << "\", \"granule_bits\": " << t.granule_bits[d] << ", \"low_policy\": " << t.low_policy
       << ", \"wave_auto\": " << t.wave_auto << ", \"tile_log2\": " << t.tile_log2[d]
-      << ", \"tile_low_bits\": " << t.tile_low_bits[d] << ", \"tile_groups\": " << t.tile_groups
-      << ", \"dense_min_gates\": " << t.dense_min_gates << "}";
+      << ", \"tile_low_bits\": " << t.tile_low_bits[d] << ", \"dense_min_gates\": " << t.dense_min_gates
+      << "}";
     return o.str();
 }
 
@@ -167,7 +166,7 @@ static int apply_tune_json(const std::string &line, const std::string &arch) {
         SV_TRY(sv_tune_set(name.c_str(), atoll(v.c_str())));
     }
     // optional fields (a record may omit them)
-    const char *opt[] = {"tile_groups", "dense_min_gates"};
+    const char *opt[] = {"dense_min_gates"};
     for (const char *k : opt) {
         std::string v;
         if (field(k, &v))
@@ -314,22 +313,8 @@ int sv_autotune(int n, int dtype, const char *cache_path, char *report, int repo
             }
         t.tile_log2[d] = bw;
         t.tile_low_bits[d] = bl;
-        // 4. register groups in fused runs, on the same circuit
-        float msg[2] = {0, 0};
-        const int g0 = t.tile_groups;
-        for (int grp = 0; grp < 2 && r == SV_OK; ++grp) {
-            t.tile_groups = grp;
-            sv_circuit_t *c = nullptr;
-            r = sv_circuit_create(n, dtype, gates.data(), (int)gates.size(), 0, SV_FUSE, &c);
-            if (r != SV_OK)
-                break;
-            r = time_events(st, 3, &msg[grp], [&]() -> int { return sv_circuit_run(c, &s, nullptr, st); });
-            (void)sv_circuit_destroy(c);
-            rep << "tile_groups " << grp << ": " << msg[grp] << " ms\n";
-        }
-        t.tile_groups = r == SV_OK ? (msg[1] < msg[0] ? 1 : 0) : g0;
     }
-    // 5. dense blocks against fused gates for a long stretch on the low qubits
+    // 4. dense blocks against fused gates for a long stretch on the low qubits
     if (r == SV_OK && dense_supported(dtype, t.dense_qubits, n)) {
         std::vector<sv_gate_t> gates;
         const int k = t.dense_qubits;

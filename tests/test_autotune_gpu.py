@@ -8,8 +8,7 @@ import workloads as W
 
 pytestmark = pytest.mark.gpu
 
-KEYS = ("granule_bits_c128", "low_policy", "wave_auto", "tile_log2_c128", "tile_low_bits_c128", "tile_groups",
-        "dense_min_gates")
+KEYS = ("granule_bits_c128", "low_policy", "wave_auto", "tile_log2_c128", "tile_low_bits_c128", "dense_min_gates")
 
 
 def test_autotune_roundtrip_and_results(gpu, tmp_path):

@@ -231,26 +231,20 @@ def test_stream_fused_tile_scheduling(gpu, tile, low):
 
 
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
-@pytest.mark.parametrize("groups", [0, 1])
-def test_fused_register_groups_and_diag_sweeps(gpu, dtype, groups):
-    """Fused runs with register groups on or off, and long diagonal sweeps
-    (the QFT's controlled phases: phases added, one sine and cosine per
-    amplitude) against short ones (factors multiplied), at n=16."""
+def test_fused_diag_sweeps(gpu, dtype):
+    """Long diagonal sweeps (the QFT's controlled phases: phases added, one
+    sine and cosine per amplitude), short ones (factors multiplied), and
+    fused runs of controlled pair gates, at n=16."""
     import torch
-    old = gpu.sv_tune_get("tile_groups")
-    gpu.sv_tune_set("tile_groups", groups)
-    try:
-        n = 16
-        circs = [W.qft(n), W.random_gates_n12(seed=21, n=n, ngates=400), W.hea(n, 3, seed=8)]
-        for c in circs:
-            params = None if c.params is None else torch.from_numpy(c.params).cuda()
-            ref = oracle.run_circuit(c, c.params)
-            d = torch.zeros(1 << n, dtype=torch.complex128 if dtype == "c128" else torch.complex64, device="cuda")
-            d[0] = 1
-            plan = gpu.Circuit(n, c, dtype=0 if dtype == "c128" else 1, nparams=c.nparams, flags=gpu.SV_FUSE)
-            plan.run(d, params)
-            plan.close()
-            e = float(np.max(np.abs(d.cpu().numpy().astype(np.complex128) - ref)))
-            assert e <= (1e-12 if dtype == "c128" else 1e-5), (c.meta, e)
-    finally:
-        gpu.sv_tune_set("tile_groups", old)
+    n = 16
+    circs = [W.qft(n), W.random_gates_n12(seed=21, n=n, ngates=400), W.hea(n, 3, seed=8)]
+    for c in circs:
+        params = None if c.params is None else torch.from_numpy(c.params).cuda()
+        ref = oracle.run_circuit(c, c.params)
+        d = torch.zeros(1 << n, dtype=torch.complex128 if dtype == "c128" else torch.complex64, device="cuda")
+        d[0] = 1
+        plan = gpu.Circuit(n, c, dtype=0 if dtype == "c128" else 1, nparams=c.nparams, flags=gpu.SV_FUSE)
+        plan.run(d, params)
+        plan.close()
+        e = float(np.max(np.abs(d.cpu().numpy().astype(np.complex128) - ref)))
+        assert e <= (1e-12 if dtype == "c128" else 1e-5), (c.meta, e)
