@@ -248,3 +248,38 @@ def test_fused_diag_sweeps(gpu, dtype):
         plan.close()
         e = float(np.max(np.abs(d.cpu().numpy().astype(np.complex128) - ref)))
         assert e <= (1e-12 if dtype == "c128" else 1e-5), (c.meta, e)
+
+
+def test_layered_circuit_n32_full(gpu):
+    """The layered circuit at its full size (n=32, complex128, 64 GiB per
+    state), where the oracle cannot run: the fused plan agrees with the
+    unfused one everywhere, the norm stays 1, and the fused inverse circuit
+    brings the state back to |0...0>."""
+    import torch
+    free, _ = torch.cuda.mem_get_info()
+    if free < (140 << 30):
+        pytest.skip("needs about 130 GiB of free device memory")
+    n = 32
+    c = W.layered_circuit_n32()
+    a = torch.empty(1 << n, dtype=torch.complex128, device="cuda")
+    b = torch.empty_like(a)
+    gpu.sv_init(a, 0)
+    gpu.sv_apply_circuit(a, c, flags=gpu.SV_FUSE)
+    gpu.sv_init(b, 0)
+    gpu.sv_apply_circuit(b, c, flags=0)
+    chunk = 1 << 27
+    diff, norm = 0.0, 0.0
+    for o in range(0, 1 << n, chunk):
+        x, y = a[o:o + chunk], b[o:o + chunk]
+        diff = max(diff, float((x - y).abs().max()))
+        norm += float(x.abs().pow(2).sum())
+    assert diff <= 1e-12, diff
+    assert abs(norm - 1.0) <= 1e-10, norm
+    del b
+    gpu.sv_apply_circuit(a, W.inverse(c), flags=gpu.SV_FUSE)
+    assert abs(complex(a[0].item()) - 1.0) <= 1e-10
+    rest = 0.0
+    for o in range(0, 1 << n, chunk):
+        x = a[o:o + chunk]
+        rest = max(rest, float(x.abs().max()) if o else float(x[1:].abs().max()))
+    assert rest <= 1e-10, rest
