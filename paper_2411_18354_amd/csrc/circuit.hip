@@ -202,6 +202,7 @@ static int plan_circuit(sv_circuit *c, std::vector<TileGate> &tiles, std::vector
                 }
                 fvals &= fmask;
                 p.tm = make_tile_map(c->n, m, a, high, fmask, fvals);
+                std::vector<char> from_param;
                 for (int gi : run) {
                     const sv_gate_t &g = c->gates[gi];
                     tile_slot[gi] = (int)tiles.size();
@@ -209,7 +210,9 @@ static int plan_circuit(sv_circuit *c, std::vector<TileGate> &tiles, std::vector
                         make_tile_gate(p.tm, g.target, g.ctrl_mask, g.ctrl_vals, &mats[(size_t)8 * gi], diag[gi]));
                     tiles.back().src_gate = gi;
                     c->tile_src.push_back(gi);
+                    from_param.push_back(g.param >= 0);
                 }
+                mark_diag_sweeps(&tiles[p.first], p.count, from_param.data());
                 c->passes.push_back(p);
                 c->fused_gates += (int64_t)run.size();
                 c->fused_runs++;
@@ -312,9 +315,17 @@ template <typename T> static int upload(T **dst, const std::vector<T> &src, bool
     return SV_OK;
 }
 
+// Dynamic LDS of a fused pass: the tile, then the diagonal-sweep tables.
+static size_t fused_lds(int m, int dtype) {
+    return ((size_t)1 << m) * amp_bytes(dtype) + (size_t)diag_table_doubles((uint32_t)m) * sizeof(double);
+}
+
 // One fused pass: one workgroup per launched tile.
 template <typename R>
-static int launch_tile_pass(cplx_t<R> *psi, const TileMap &tm, const DeviceGates &dg, size_t lds, hipStream_t st) {
+static int launch_tile_pass(cplx_t<R> *psi, const TileMap &tm_in, const DeviceGates &dg, size_t lds,
+                            hipStream_t st) {
+    TileMap tm = tm_in;
+    tm.tab = 1;  // lds includes the tables
     hipLaunchKernelGGL((k_tile<R, 512, DeviceGates>), dim3((unsigned)tm.ntiles), dim3(512), lds, st, psi, tm, dg);
     SV_LAUNCH_CHECK();
     return SV_OK;
@@ -367,7 +378,7 @@ int circuit_create(int n, int dtype, const sv_gate_t *gates, int ngates, int npa
         return r;
     }
     // large LDS tiles need the per-kernel limit raised before any launch
-    const size_t lds = ((size_t)1 << c->m) * amp_bytes(dtype);
+    const size_t lds = fused_lds(c->m, dtype);
     if (lds > 65536) {
         if (dtype == SV_C128)
             SV_HIP_TRY(hipFuncSetAttribute((const void *)k_tile<double, 512, DeviceGates>,
@@ -398,7 +409,7 @@ void circuit_free(sv_circuit *c, hipStream_t st) {
 
 template <typename R> static int enqueue(sv_circuit *c, cplx_t<R> *psi, const double *params, hipStream_t st) {
     SV_TRY(circuit_param_mats(c, params, st));
-    const size_t lds = ((size_t)1 << c->m) * sizeof(cplx_t<R>);
+    const size_t lds = fused_lds(c->m, c->dtype);
     for (const Pass &p : c->passes) {
         if (p.dense) {
             const size_t D = (size_t)2 << c->dense_k;

@@ -169,6 +169,27 @@ TileMap make_tile_map(int n, int m, int a, const std::vector<int> &high, uint64_
 
 TileMap contiguous_tile_map(int n, int m) { return make_tile_map(n, m, m, {}); }
 
+void mark_diag_sweeps(TileGate *t, int count, const char *param_gate) {
+    int k = 0;
+    while (k < count) {
+        if (!t[k].diag) {
+            ++k;
+            continue;
+        }
+        int e = k;
+        bool unit = true;
+        int nlocal = 0;
+        while (e < count && t[e].diag && e - k < 0xffff) {
+            unit &= param_gate[e] != 0 || t[e].unit != 0;
+            nlocal += (t[e].l_target >= 0 || t[e].l_mask) ? 1 : 0;
+            ++e;
+        }
+        t[k].sweep_len = (uint16_t)(e - k);
+        t[k].sweep_phase = (unit && nlocal >= kPhaseSweepMin) ? 1 : 0;
+        k = e;
+    }
+}
+
 // Tile-local bit of global qubit q, or -1 when q is outside S.
 static int local_bit(const TileMap &tm, int q) {
     if (q < (int)tm.a)
@@ -187,6 +208,7 @@ TileGate make_tile_gate(const TileMap &tm, int target, uint64_t cmask, uint64_t 
         g.m[i] = U[i];
     if (diagonal) {
         g.diag = 1;
+        g.sweep_len = 1;  // a block of one unless a run marks a longer one
         diag_phases(g.m, g.ph, &g.unit);
         g.target = (uint32_t)target;  // global qubit
         g.hi_mask = cmask;            // every control, global bits

@@ -29,30 +29,43 @@ constexpr int kTileMaxLog = 14;
 constexpr int kTileMaxHigh = 8;  // qubits of S above the contiguous low block
 
 struct TileGate {
-    double m[8];          // matrix (a, b, c, d as re, im), double precision
-    uint32_t diag;        // 1: diagonal gate applied elementwise
-    uint32_t target;      // pair gate: tile-local bit; diagonal: global qubit
-    uint32_t nseg;        // pair gate: in-tile expansion of the reduced index
-    uint32_t shift[kTileSeg];
-    uint32_t mask[kTileSeg];
-    uint32_t fixed;       // in-tile control bits that must be 1
-    uint32_t npairs;      // 2^(m - 1 - in-tile controls)
+    // The first 64 bytes hold what the loops over a run read for every gate,
+    // so a gate costs one scalar load there (the descriptors of a long run
+    // must also fit the scalar cache).
     uint64_t hi_mask;     // controls outside S (global bits; diagonal: all controls)
     uint64_t hi_vals;
-    int32_t src_gate;     // index of the gate in its circuit (host bookkeeping)
-    int32_t pad2;
     // diagonal gate split over the tile's qubit set S: controls outside S
     // (global bits; a tile predicate), controls inside S (tile-local bits)
     // and the target's tile-local bit, or -1 when the target is outside S
     // (pair gates use l_mask/l_vals for their tile-local controls too)
     uint64_t o_mask, o_vals;
+    uint32_t diag;        // 1: diagonal gate applied elementwise
+    uint32_t target;      // pair gate: tile-local bit; diagonal: global qubit
+    uint32_t npairs;      // 2^(m - 1 - in-tile controls)
+    uint32_t fixed;       // in-tile control bits that must be 1
     uint32_t l_mask, l_vals;
     int32_t l_target;
+    // first gate of a block of consecutive diagonal gates: the block's
+    // length, and whether it is long enough and of unit modulus throughout
+    // to add phases (bit 0); set on the host
+    uint16_t sweep_len, sweep_phase;
     // diagonal gate: phases of its two entries, and whether both have unit
     // modulus (then a sweep may add phases instead of multiplying factors)
-    uint32_t unit;
     double ph[2];
+    uint32_t unit;
+    uint32_t nseg;        // pair gate: in-tile expansion of the reduced index
+    double m[8];          // matrix (a, b, c, d as re, im), double precision
+    uint32_t shift[kTileSeg];
+    uint32_t mask[kTileSeg];
+    int32_t src_gate;     // index of the gate in its circuit (host bookkeeping)
+    int32_t pad2;
 };
+
+// Mark the blocks of consecutive diagonal gates among tiles[0 .. count) (one
+// fused run; host): length and phase-sum eligibility at each block's first
+// gate.  param_gate[i] != 0: the entries of gate i come from parameters at
+// run time (their kinds are unitary), so it counts as unit modulus.
+void mark_diag_sweeps(TileGate *tiles, int count, const char *param_gate);
 
 // Phases of the diagonal entries m[0..1] and m[6..7] (host and device).
 __host__ __device__ inline void diag_phases(const double *m, double *ph, uint32_t *unit) {
@@ -79,7 +92,16 @@ struct TileMap {
     uint32_t seg_shift[kTileMaxHigh];
     Expand outer;
     uint64_t ntiles;  // launched tiles: 2^(n - m - fixed outer bits)
+    uint32_t tab;     // the launch reserves the diagonal-sweep tables after the tile
+    uint32_t pad;
 };
+
+// Doubles of the diagonal-sweep tables for tile width m (0 below m = 7):
+// A[64] over tile-local bits 0..5, B[2^(m-6)] over bits 6..m-1, and for each
+// bit q >= 6 and value b a row R[q][b][64] over bits 0..5.
+__host__ __device__ inline uint32_t diag_table_doubles(uint32_t m) {
+    return m < 7 ? 0u : 64u + (1u << (m - 6)) + (m - 6) * 128u;
+}
 
 // Tile map for S = {0 .. a-1} u high (host).  high: ascending qubits >= a;
 // fixed_mask/fixed_vals: outer index bits every launched tile has.
@@ -206,6 +228,42 @@ __device__ __forceinline__ void phase_sincos(double th, double *sn, double *cs) 
     *cs = q == 0 ? c : q == 1 ? -s : q == 2 ? -c : s;
 }
 
+// Single-precision factor for complex64 states: the quadrant reduction stays
+// in double precision, the polynomials (to r^9 / r^8, truncation below 3e-8
+// on |r| <= pi/4) run in single precision.
+__device__ __forceinline__ void phase_sincos_f(double th, float *sn, float *cs) {
+    constexpr double kPio2Hi = 1.5707963267948966;
+    constexpr double kPio2Lo = 6.123233995736766e-17;
+    const double k = rint(th * 0.63661977236758134);
+    double rd = fma(-k, kPio2Hi, th);
+    rd = fma(-k, kPio2Lo, rd);
+    const float r = (float)rd, r2 = r * r;
+    float ps = 1.0f / 362880.0f;
+    ps = fmaf(ps, -r2, 1.0f / 5040.0f);
+    ps = fmaf(ps, -r2, 1.0f / 120.0f);
+    ps = fmaf(ps, -r2, 1.0f / 6.0f);
+    ps = fmaf(ps, -r2, 1.0f);
+    const float s = r * ps;
+    float pc = 1.0f / 40320.0f;
+    pc = fmaf(pc, -r2, 1.0f / 720.0f);
+    pc = fmaf(pc, -r2, 1.0f / 24.0f);
+    pc = fmaf(pc, -r2, 1.0f / 2.0f);
+    pc = fmaf(pc, -r2, 1.0f);
+    const float c = pc;
+    const int q = (int)((int64_t)k & 3);
+    *sn = q == 0 ? s : q == 1 ? c : q == 2 ? -s : -c;
+    *cs = q == 0 ? c : q == 1 ? -s : q == 2 ? -c : s;
+}
+
+// exp(i th) in the state's precision.
+template <typename R> __device__ __forceinline__ void phase_factor(double th, R *fr, R *fi);
+template <> __device__ __forceinline__ void phase_factor<double>(double th, double *fr, double *fi) {
+    phase_sincos(th, fi, fr);
+}
+template <> __device__ __forceinline__ void phase_factor<float>(double th, float *fr, float *fi) {
+    phase_sincos_f(th, fi, fr);
+}
+
 // A sweep of consecutive diagonal gates [i, e) whose entries all have unit
 // modulus: each amplitude is multiplied by exp(i theta), theta being the sum
 // of the phases its index selects (a tile-uniform part plus the gates that
@@ -225,10 +283,10 @@ __device__ __forceinline__ void diag_sweep_phases(cplx_t<R> *tile, uint64_t base
         }
         th0 += ((base >> d.target) & 1ull) ? d.ph[1] : d.ph[0];
     }
-    // four amplitudes per lane at a time (named scalars, not an array)
-    for (uint32_t j0 = threadIdx.x; j0 < T; j0 += 4 * THREADS) {
-        const uint32_t j1 = j0 + THREADS, j2 = j0 + 2 * THREADS, j3 = j0 + 3 * THREADS;
-        double t0 = th0, t1 = th0, t2 = th0, t3 = th0;
+    // eight amplitudes per lane at a time (named scalars, not an array), so
+    // each gate's uniform checks and loads are shared by eight updates
+    for (uint32_t j0 = threadIdx.x; j0 < T; j0 += 8 * THREADS) {
+        double t0 = th0, t1 = th0, t2 = th0, t3 = th0, t4 = th0, t5 = th0, t6 = th0, t7 = th0;
         if (any_local) {  // uniform
             for (int q = i; q < e; ++q) {
                 const TileGate &d = gates.get(q);
@@ -242,16 +300,19 @@ __device__ __forceinline__ void diag_sweep_phases(cplx_t<R> *tile, uint64_t base
                     t += ((j & d.l_mask) == d.l_vals) ? p : 0.0;
                 };
                 add(t0, j0);
-                add(t1, j1);
-                add(t2, j2);
-                add(t3, j3);
+                add(t1, j0 + THREADS);
+                add(t2, j0 + 2 * THREADS);
+                add(t3, j0 + 3 * THREADS);
+                add(t4, j0 + 4 * THREADS);
+                add(t5, j0 + 5 * THREADS);
+                add(t6, j0 + 6 * THREADS);
+                add(t7, j0 + 7 * THREADS);
             }
         }
         auto put = [&](double t, uint32_t j) {
             if (j < T) {
-                double sn, cs;
-                phase_sincos(t, &sn, &cs);
-                const R fr = (R)cs, fi = (R)sn;
+                R fr, fi;
+                phase_factor<R>(t, &fr, &fi);
                 const cplx_t<R> v = tile[j];
                 cplx_t<R> w;
                 w.x = v.x * fr - v.y * fi;
@@ -260,9 +321,115 @@ __device__ __forceinline__ void diag_sweep_phases(cplx_t<R> *tile, uint64_t base
             }
         };
         put(t0, j0);
-        put(t1, j1);
-        put(t2, j2);
-        put(t3, j3);
+        put(t1, j0 + THREADS);
+        put(t2, j0 + 2 * THREADS);
+        put(t3, j0 + 3 * THREADS);
+        put(t4, j0 + 4 * THREADS);
+        put(t5, j0 + 5 * THREADS);
+        put(t6, j0 + 6 * THREADS);
+        put(t7, j0 + 7 * THREADS);
+    }
+    __syncthreads();
+}
+
+// Phase of one diagonal gate at tile-local index j (0 unless its tile-local
+// controls hold there); tone: its target bit when the target is outside S.
+__device__ __forceinline__ double diag_phase_at(const TileGate &d, uint32_t j, bool tone, double p0, double p1) {
+    const bool one = d.l_target >= 0 ? ((j >> d.l_target) & 1u) : tone;
+    return ((j & d.l_mask) == d.l_vals) ? (one ? p1 : p0) : 0.0;
+}
+
+// Long unit-modulus sweep with tables.  The phase of amplitude j is a sum of
+// gate terms, each depending on the few tile-local bits the gate reads.  With
+// u = bits 0..5 of j and v = bits 6..m-1:
+//   theta(j) = th0 + A[u] + B[v] + sum over q of R[q][bit q of v][u] + rest,
+// where A collects the gates reading only bits of u, B those reading only
+// bits of v, R[q] those reading bits of u and the single bit 6+q, and rest
+// (evaluated per amplitude) those reading bits of u and two or more bits of
+// v.  Each wavefront builds whole tables (one lane per entry, skipping the
+// gates of other tables), so the per-amplitude cost is a handful of LDS reads
+// whatever the sweep's length.
+template <typename R, int THREADS, typename Src>
+__device__ __forceinline__ void diag_sweep_tables(cplx_t<R> *tile, double *tab, uint64_t base, uint32_t m,
+                                                  const Src &gates, int i, int e) {
+    const uint32_t T = 1u << m;
+    const int Hb = (int)m - 6;
+    double *A = tab, *B = tab + 64, *Rt = tab + 64 + (1 << Hb);
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    double th0 = 0.0;
+    bool any_rest = false;
+    for (int q = i; q < e; ++q) {
+        const TileGate &d = gates.get(q);
+        if ((base & d.o_mask) != d.o_vals)
+            continue;
+        const uint32_t lm = d.l_mask | (d.l_target >= 0 ? 1u << d.l_target : 0u);
+        if (lm == 0)
+            th0 += ((base >> d.target) & 1ull) ? d.ph[1] : d.ph[0];
+        else if ((lm & 63u) && __popc(lm >> 6) > 1)
+            any_rest = true;
+    }
+    // table tb: 0 = A, 1 = B, 2 + q = R[q]; entries per lane: A 1, B
+    // ceil(2^Hb / 64) (lanes beyond 2^Hb idle when Hb < 6), R 2
+    const uint32_t nb = 1u << Hb;
+    for (int tb = w; tb < 2 + Hb; tb += THREADS / 64) {  // uniform per wavefront
+        const int ne = tb == 0 ? 1 : (tb == 1 ? (int)((nb + 63) / 64) : 2);
+        double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
+        for (int q = i; q < e; ++q) {
+            const TileGate &d = gates.get(q);
+            if ((base & d.o_mask) != d.o_vals)
+                continue;  // uniform
+            const uint32_t lm = d.l_mask | (d.l_target >= 0 ? 1u << d.l_target : 0u);
+            const uint32_t lo = lm & 63u, hi = lm >> 6;
+            const bool mine = tb == 0 ? (lo && !hi) : tb == 1 ? (hi && !lo) : (lo && hi == (1u << (tb - 2)));
+            if (!mine)
+                continue;  // uniform
+            const bool tone = (base >> d.target) & 1ull;
+            const double p0 = uniform_f64(d.ph[0]), p1 = uniform_f64(d.ph[1]);
+            // the tile-local index an entry stands for
+            auto at = [&](int k) -> uint32_t {
+                return tb == 0 ? (uint32_t)lane
+                               : tb == 1 ? (uint32_t)(lane + 64 * k) << 6 : (uint32_t)lane | ((uint32_t)k << (4 + tb));
+            };
+            acc0 += diag_phase_at(d, at(0), tone, p0, p1);
+            if (ne > 1)
+                acc1 += diag_phase_at(d, at(1), tone, p0, p1);
+            if (ne > 2) {
+                acc2 += diag_phase_at(d, at(2), tone, p0, p1);
+                acc3 += diag_phase_at(d, at(3), tone, p0, p1);
+            }
+        }
+        double *dst = tb == 0 ? A : tb == 1 ? B : Rt + (tb - 2) * 128;
+        if (tb != 1 || (uint32_t)lane < nb)
+            dst[lane] = acc0;
+        if (ne > 1)
+            dst[lane + 64] = acc1;
+        if (ne > 2) {
+            dst[lane + 128] = acc2;
+            dst[lane + 192] = acc3;
+        }
+    }
+    __syncthreads();
+    for (uint32_t j = threadIdx.x; j < T; j += THREADS) {
+        const uint32_t u = j & 63u, v = j >> 6;
+        double t = th0 + A[u] + B[v];
+        for (int q = 0; q < Hb; ++q)
+            t += Rt[q * 128 + ((v >> q) & 1u) * 64 + u];
+        if (any_rest) {  // uniform
+            for (int q = i; q < e; ++q) {
+                const TileGate &d = gates.get(q);
+                const uint32_t lm = d.l_mask | (d.l_target >= 0 ? 1u << d.l_target : 0u);
+                if ((base & d.o_mask) != d.o_vals || !(lm & 63u) || __popc(lm >> 6) < 2)
+                    continue;  // uniform
+                t += diag_phase_at(d, j, (base >> d.target) & 1ull, uniform_f64(d.ph[0]), uniform_f64(d.ph[1]));
+            }
+        }
+        R fr, fi;
+        phase_factor<R>(t, &fr, &fi);
+        const cplx_t<R> x = tile[j];
+        cplx_t<R> y;
+        y.x = x.x * fr - x.y * fi;
+        y.y = x.x * fi + x.y * fr;
+        tile[j] = y;
     }
     __syncthreads();
 }
@@ -273,6 +440,8 @@ template <typename Src> __device__ __forceinline__ bool tile_touched(uint64_t ba
     for (int i = 0; i < gates.size(); ++i) {
         const TileGate &g = gates.get(i);
         any |= g.diag ? ((base & g.o_mask) == g.o_vals) : ((base & g.hi_mask) == g.hi_vals);
+        if (any)
+            break;  // uniform
     }
     return any;
 }
@@ -286,9 +455,8 @@ __device__ __forceinline__ void tile_run(cplx_t<R> *tile, uint64_t base, const T
     while (i < gates.size()) {
         const TileGate &g = gates.get(i);
         if (g.diag) {
-            int e = i + 1;
-            while (e < gates.size() && gates.get(e).diag)
-                ++e;
+            // the block marked on the host, kept inside the run
+            const int e = min(gates.size(), i + max(1, (int)g.sweep_len));
             // Diagonal gates commute, so the sweep multiplies each amplitude
             // by the product of its factors.  Gates whose target and controls
             // all lie outside S give the whole tile one factor (computed
@@ -297,15 +465,11 @@ __device__ __forceinline__ void tile_run(cplx_t<R> *tile, uint64_t base, const T
             // turned into one factor per amplitude at the end.
             // Long sweeps whose factors all have unit modulus add phases
             // (one sine and cosine per amplitude); short ones multiply.
-            bool unit = true;
-            int nlocal = 0;
-            for (int q = i; q < e; ++q) {
-                const TileGate &d = gates.get(q);
-                unit &= d.unit != 0;
-                nlocal += (d.l_target >= 0 || d.l_mask) ? 1 : 0;
-            }
-            if (unit && nlocal >= kPhaseSweepMin) {  // uniform
-                diag_sweep_phases<R, THREADS>(tile, base, T, gates, i, e);
+            if (g.sweep_phase) {  // uniform
+                if (tm.tab && tm.m >= 7)
+                    diag_sweep_tables<R, THREADS>(tile, reinterpret_cast<double *>(tile + T), base, tm.m, gates, i, e);
+                else
+                    diag_sweep_phases<R, THREADS>(tile, base, T, gates, i, e);
                 i = e;
                 continue;
             }

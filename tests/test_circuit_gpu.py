@@ -230,19 +230,54 @@ def test_stream_fused_tile_scheduling(gpu, tile, low):
         gpu.sv_tune_set("tile_low_bits_c128", 6)
 
 
+def _diag_heavy(n, seed, blocks=6, per_block=14):
+    """Blocks of controlled phase / RZ gates on random qubits (0-3 controls,
+    some negative) separated by H layers: long diagonal sweeps whose gates
+    read every mix of tile-local and outer bits."""
+    rng = np.random.default_rng(seed)
+    gates = []
+    for b in range(blocks):
+        for q in rng.choice(n, size=3, replace=False):
+            gates.append(W.Gate("H", int(q)))
+        for i in range(per_block):
+            t = int(rng.integers(0, n))
+            others = [q for q in range(n) if q != t]
+            k = int(rng.integers(0, 4))
+            ctrls = tuple(int(q) for q in rng.choice(others, size=k, replace=False)) if k else ()
+            vals = tuple(int(v) for v in rng.integers(0, 2, size=k)) if k else ()
+            gates.append(W.Gate("P" if i % 2 else "RZ", t, ctrls, vals, float(rng.uniform(0, 2 * np.pi))))
+    return W.Circuit(n, gates, meta={"name": "diag_heavy", "seed": seed})
+
+
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
-def test_fused_diag_sweeps(gpu, dtype):
-    """Long diagonal sweeps (the QFT's controlled phases: phases added, one
-    sine and cosine per amplitude), short ones (factors multiplied), and
-    fused runs of controlled pair gates, at n=16."""
+@pytest.mark.parametrize("width", [0, 8, 10])
+def test_fused_diag_sweeps(gpu, dtype, width):
+    """Long diagonal sweeps (the QFT's controlled phases and random
+    controlled phases: phases added through tables, one sine and cosine per
+    amplitude), short ones (factors multiplied), and fused runs of controlled
+    pair gates, at n=16, for the default tile width and narrower ones."""
     import torch
     n = 16
-    circs = [W.qft(n), W.random_gates_n12(seed=21, n=n, ngates=400), W.hea(n, 3, seed=8)]
+    key = "tile_log2_" + dtype
+    old = gpu.sv_tune_get(key)
+    if width:
+        gpu.sv_tune_set(key, width)
+    try:
+        _check_diag_circuits(gpu, dtype, n)
+    finally:
+        gpu.sv_tune_set(key, old)
+
+
+def _check_diag_circuits(gpu, dtype, n):
+    import torch
+    circs = [W.qft(n), _diag_heavy(n, 5), W.random_gates_n12(seed=21, n=n, ngates=400), W.hea(n, 3, seed=8)]
+    psi0 = W.random_state(n, 3)  # every amplitude nonzero, so every phase counts
     for c in circs:
         params = None if c.params is None else torch.from_numpy(c.params).cuda()
-        ref = oracle.run_circuit(c, c.params)
-        d = torch.zeros(1 << n, dtype=torch.complex128 if dtype == "c128" else torch.complex64, device="cuda")
-        d[0] = 1
+        ref = oracle.run_circuit(c, c.params, psi0)
+        d = torch.from_numpy(psi0).cuda()
+        if dtype == "c64":
+            d = d.to(torch.complex64)
         plan = gpu.Circuit(n, c, dtype=0 if dtype == "c128" else 1, nparams=c.nparams, flags=gpu.SV_FUSE)
         plan.run(d, params)
         plan.close()
