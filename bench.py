@@ -220,6 +220,49 @@ def control_position_sweep(sv, torch, np, d, U, stream, n, t=13, reps=5):
     return out
 
 
+RATED_POWER_W = 1400.0  # MI355X total board power
+
+
+def _energy_reader():
+    """The board energy counter of the (single) GPU through amdsmi, as
+    (joules, counter timestamp in seconds), or None where it cannot be read."""
+    try:
+        import amdsmi
+        amdsmi.amdsmi_init()
+        h = amdsmi.amdsmi_get_processor_handles()[0]
+
+        def read():
+            e = amdsmi.amdsmi_get_energy_count(h)
+            joules = float(e["energy_accumulator"]) * float(e["counter_resolution"]) * 1e-6  # uJ -> J
+            return joules, float(e["timestamp"]) * 1e-9
+        read()
+        return read
+    except Exception:
+        return None
+
+
+def _energy_per_run(torch, stream, fn, read, min_s=1.0):
+    """Joules per call of fn and the board's average watts, over at least
+    min_s seconds of back-to-back calls.  The counter advances in steps, so
+    the power is taken between its own timestamps and multiplied by the
+    measured time per call."""
+    with torch.cuda.stream(stream):
+        fn()
+        torch.cuda.synchronize()
+        (e0, s0), t0, reps = read(), time.perf_counter(), 0
+        while True:
+            fn()
+            reps += 1
+            torch.cuda.synchronize()
+            if time.perf_counter() - t0 >= min_s:
+                break
+        (e1, s1), t1 = read(), time.perf_counter()
+    if s1 <= s0:
+        return None, None
+    watts = (e1 - e0) / (s1 - s0)
+    return watts * (t1 - t0) / reps, watts
+
+
 def measure_extras(sv, W, torch, np, stream, with_layered):
     """Adjoint gradients (n=24 ansatz), batched circuits (4096 uneven circuits), the paper's
     QFT and streaming circuits at 29 qubits, and optionally the layered n=32 circuit."""
@@ -330,7 +373,9 @@ def measure_extras(sv, W, torch, np, stream, with_layered):
                                                   "hbm_frac": round(byts / ms / 1e6 / HBM_PEAK_GBPS, 3)}
         del st
         torch.cuda.empty_cache()
-    # ---- the paper's 29-qubit circuits, masked vs scheduled (vs fused)
+    # ---- the paper's 29-qubit circuits, masked vs scheduled (vs fused), with
+    # energy per circuit from the board's energy counter where readable
+    energy = _energy_reader()
     for name, circ in (("qft29", W.qft(29)), ("stream29", W.stream(29))):
         for dt, td in (("c64", torch.complex64), ("c128", torch.complex128)):
             log("paper circuit", name, dt)
@@ -343,6 +388,13 @@ def measure_extras(sv, W, torch, np, stream, with_layered):
                     sv.sv_init(st, 1, stream=stream)
                     p.run(st, stream=stream)
                 row[label + "_ms"] = round(_time_ms(torch, stream, run, 3), 3)
+                # the paper's method: time x rated board power
+                row[label + "_J_rated"] = round(row[label + "_ms"] * 1e-3 * RATED_POWER_W, 2)
+                if energy is not None:
+                    j, w = _energy_per_run(torch, stream, run, energy)
+                    if j is not None:
+                        row[label + "_J_measured"] = round(j, 3)
+                        row[label + "_W_avg"] = round(w, 1)
                 p.close()
             row["masked_over_scheduled"] = round(row["masked_ms"] / row["scheduled_ms"], 2)
             out["%s_%s" % (name, dt)] = row

@@ -9,11 +9,12 @@
 //    bytes) is read once, all gates are applied in LDS, and it is written
 //    back once.
 //  - A larger state is processed pass by pass from global memory with the
-//    circuit's fused plan: a fused run visits the state tile by tile, a tile
-//    being the 2^m amplitudes that share the index bits outside the run's
-//    qubit set S (the lowest qubits plus planner-chosen ones), held in LDS
-//    while the run's gates act on it; other gates are pair loops over the
-//    state.  A workgroup barrier separates passes.
+//    circuit's fused plan (the same planner and tile code as single
+//    circuits): a fused run visits the state tile by tile, a tile being the
+//    2^m amplitudes that share the index bits outside the run's qubit set S,
+//    held in LDS while the run's operations act on it (pair gates, and
+//    diagonal sweeps through the phase tables); other gates are pair loops
+//    over the state.  A workgroup barrier separates passes.
 // Each gate visits only the amplitude pairs whose controls hold: the pair
 // index is built by inserting the target bit (0) and the control bits (their
 // values) into the iteration counter, lowest position first (Sec. III-B).
@@ -24,32 +25,41 @@
 #include <string>
 #include <thread>
 
+#include "circuit.hpp"
 #include "gates.hpp"
 #include "pauli.hpp"
 
 namespace sv {
 
 int validate_circuit_gate(int n, int nparams, const sv_gate_t &g, int index);
-int circuit_plan_capped(int n, int dtype, const sv_gate_t *gates, int ngates, int nparams, int flags, int m_cap,
-                        int32_t *order, int32_t *pass_of, int64_t *npasses, int *m_used, bool general,
-                        bool diag_any, std::vector<uint64_t> *pass_S);
 
 constexpr int kBatchThreads = 512;
-constexpr size_t kBatchLds = 65536;
+constexpr size_t kBatchLds = 65536;  // the tile (or a whole resident state)
+// dynamic LDS: the work-item slot, the tile, then the diagonal-sweep tables
+constexpr size_t kBatchSlot = 64;
+constexpr size_t kBatchDynLds = kBatchSlot + kBatchLds + 8 * 1088;  // tables for tile widths up to 13
 
 struct BGate {
     double m[8];      // matrix of a fixed gate
     int32_t kind;     // matrix recomputed from params[param] when param >= 0
     int32_t param;    // index into the concatenated parameter array, or -1
     int32_t target;
-    int32_t pass;     // pass number within its circuit (fused runs share one)
-    uint64_t cmask, cvals;
-    // fused runs: the tile's qubit set, and target and controls inside S
-    // renumbered to tile-local bit positions
-    uint64_t S;
-    int32_t ltarget;
     int32_t pad;
-    uint64_t lcmask, lcvals;
+    uint64_t cmask, cvals;
+};
+
+// One pass of a circuit's fused plan.
+struct BPass {
+    TileMap tm;       // fused: the tiles' qubit set (tm.tab set: tables reserved)
+    int32_t fused;    // 1: tile descriptors [first, first + count); 0: gate `gate`
+    int32_t gate;     // single: index among the circuit's gates
+    int32_t first, count;
+};
+
+// A parameterised gate inside a fused run: its descriptor's matrix (and
+// phases) is recomputed from the angle before each batched run.
+struct BTileJob {
+    int32_t kind, param, tile, pad;
 };
 
 struct BCirc {
@@ -57,7 +67,8 @@ struct BCirc {
     void *lam;           // adjoint only
     int32_t n;
     int32_t m;           // tile width of the fused plan
-    int32_t first_gate;  // gates [first_gate, first_gate + ngates), in execution order
+    int32_t first_pass, npasses;  // forward: the fused plan
+    int32_t first_gate;  // gates [first_gate, first_gate + ngates), in program order
     int32_t ngates;
     int32_t first_param, nparams;  // adjoint: gradient slots
     int32_t first_term, nterms;    // adjoint: Hamiltonian terms
@@ -73,20 +84,6 @@ template <typename I> __device__ __forceinline__ I insert_bits(I x, I positions,
         x = ((x >> p) << (p + 1)) | (((vals >> p) & (I)1) << p) | lo;
     }
     return x;
-}
-
-// Global offset of tile-local index k: its a low bits stay in place, its
-// higher bits go, in ascending order, to the positions of the bits of high.
-__device__ __forceinline__ uint64_t scatter_bits(uint64_t k, int a, uint64_t high) {
-    uint64_t off = k & ((1ull << a) - 1);
-    uint64_t h = k >> a;
-    while (h) {
-        const int p = __builtin_ctzll(high);
-        high &= high - 1;
-        off |= (h & 1ull) << p;
-        h >>= 1;
-    }
-    return off;
 }
 
 // The gate's matrix (angle from params when parameterised), or its conjugate
@@ -152,7 +149,8 @@ __device__ __forceinline__ void gate_on_block(cplx_t<R> *base, int nbits, int ta
 }
 
 template <typename R>
-__device__ void run_circuit_block(const BCirc &c, const BGate *__restrict__ gates, const double *__restrict__ params,
+__device__ void run_circuit_block(const BCirc &c, const BGate *__restrict__ gates, const BPass *__restrict__ passes,
+                                  const TileGate *__restrict__ tiles, const double *__restrict__ params,
                                   cplx_t<R> *lds) {
     cplx_t<R> *psi = reinterpret_cast<cplx_t<R> *>(c.psi);
     const uint64_t N = 1ull << c.n;
@@ -169,62 +167,59 @@ __device__ void run_circuit_block(const BCirc &c, const BGate *__restrict__ gate
             psi[k] = lds[k];
         return;
     }
-    int i = 0;
-    while (i < c.ngates) {
-        const int pass = gates[c.first_gate + i].pass;
-        int j = i;
-        while (j < c.ngates && gates[c.first_gate + j].pass == pass)
-            ++j;
-        if (j - i > 1) {  // fused run: every target in S
-            const uint64_t S = gates[c.first_gate + i].S;
-            const int m = __popcll(S);
-            const int a = __builtin_ctzll(~S);  // S holds qubits 0 .. a-1
-            const uint64_t lowm = (1ull << a) - 1, high = S & ~lowm;
-            const uint64_t T = 1ull << m, ntiles = N >> m;
-            for (uint64_t tt = 0; tt < ntiles; ++tt) {
-                // the tile's fixed bits: tt spread over the qubits outside S
-                const uint64_t base = insert_bits<uint64_t>(tt << a, high, 0);
-                bool any = false;
-                for (int k = i; k < j; ++k) {
-                    const BGate &g = gates[c.first_gate + k];
-                    const uint64_t om = g.cmask & ~S;
-                    any |= (base & om) == (g.cvals & om);
-                }
-                if (!any)
-                    continue;
-                for (uint64_t k = threadIdx.x; k < T; k += kBatchThreads)
-                    lds[k] = psi[base | scatter_bits(k, a, high)];
+    for (int pi = 0; pi < c.npasses; ++pi) {
+        const BPass &p = passes[c.first_pass + pi];
+        if (p.fused) {  // uniform
+            const DeviceGates dg{tiles + p.first, p.count};
+            const uint32_t T = 1u << p.tm.m;
+            for (uint64_t tt = 0; tt < p.tm.ntiles; ++tt) {
+                const uint64_t base = expand_index<uint64_t>(p.tm.outer, tt);
+                if (!tile_touched(base, dg))
+                    continue;  // uniform
+                for (uint32_t k = threadIdx.x; k < T; k += kBatchThreads)
+                    lds[k] = psi[base | tile_offset(p.tm, k)];
                 __syncthreads();
-                for (int k = i; k < j; ++k) {
-                    const BGate &g = gates[c.first_gate + k];
-                    const uint64_t om = g.cmask & ~S;
-                    if ((base & om) != (g.cvals & om))
-                        continue;
-                    gate_on_block<R>(lds, m, g.ltarget, g.lcmask, g.lcvals, bgate_mat<R>(g, params, false));
-                    __syncthreads();
-                }
-                for (uint64_t k = threadIdx.x; k < T; k += kBatchThreads)
-                    psi[base | scatter_bits(k, a, high)] = lds[k];
+                tile_run<R, kBatchThreads>(lds, base, p.tm, dg);
+                for (uint32_t k = threadIdx.x; k < T; k += kBatchThreads)
+                    psi[base | tile_offset(p.tm, k)] = lds[k];
                 __syncthreads();
             }
         } else {
-            const BGate &g = gates[c.first_gate + i];
+            const BGate &g = gates[c.first_gate + p.gate];
             gate_on_block<R>(psi, c.n, g.target, g.cmask, g.cvals, bgate_mat<R>(g, params, false));
             __syncthreads();
         }
-        i = j;
     }
+}
+
+// Angles of the parameterised gates inside fused runs, into their tile
+// descriptors (matrix, and phases of diagonal ones).
+__global__ void k_batch_tile_params(const BTileJob *__restrict__ jobs, int njobs, const double *__restrict__ params,
+                                    TileGate *__restrict__ tiles) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= njobs)
+        return;
+    const BTileJob j = jobs[i];
+    double m[8];
+    gate_matrix(j.kind, params[j.param], nullptr, m);
+    TileGate &t = tiles[j.tile];
+    for (int k = 0; k < 8; ++k)
+        t.m[k] = m[k];
+    if (t.diag)
+        diag_phases(m, t.ph, &t.unit);
 }
 
 template <typename R>
 __global__ __launch_bounds__(kBatchThreads) void k_batched(const BCirc *__restrict__ circs,
                                                            const int32_t *__restrict__ order, int ncirc,
                                                            const BGate *__restrict__ gates,
+                                                           const BPass *__restrict__ passes,
+                                                           const TileGate *__restrict__ tiles,
                                                            const double *__restrict__ params,
                                                            unsigned int *__restrict__ queue) {
     extern __shared__ unsigned char lds_raw[];
-    cplx_t<R> *lds = reinterpret_cast<cplx_t<R> *>(lds_raw);
-    int *item = reinterpret_cast<int *>(lds_raw + kBatchLds);
+    int *item = reinterpret_cast<int *>(lds_raw);
+    cplx_t<R> *lds = reinterpret_cast<cplx_t<R> *>(lds_raw + kBatchSlot);
     for (;;) {
         if (threadIdx.x == 0)
             *item = (int)atomicAdd(queue, 1u);
@@ -233,7 +228,7 @@ __global__ __launch_bounds__(kBatchThreads) void k_batched(const BCirc *__restri
         __syncthreads();
         if (it >= ncirc)
             break;
-        run_circuit_block<R>(circs[order[it]], gates, params, lds);
+        run_circuit_block<R>(circs[order[it]], gates, passes, tiles, params, lds);
         __syncthreads();
     }
 }
@@ -347,6 +342,9 @@ __global__ __launch_bounds__(kBatchThreads) void k_batched_adjoint(
 struct CircBuild {
     BCirc bc;
     std::vector<BGate> gates;
+    std::vector<BPass> passes;     // forward plan (circuit-local indices)
+    std::vector<TileGate> tiles;
+    std::vector<BTileJob> jobs;    // tile indices circuit-local
     std::vector<double> gens;      // generators of the parameterised gates
     std::vector<int32_t> gen_of;   // per gate: index into gens / 8, or -1
     std::vector<DTerm> terms;
@@ -365,9 +363,9 @@ struct BatchArgs {
     const int64_t *term_off;
 };
 
-// Tables of circuit c.  adjoint: gates in program order with generators and
-// the Hamiltonian; otherwise the fused plan's order with each fused gate's
-// tile set and tile-local masks.
+// Tables of circuit c: its gates in program order, and either the forward
+// fused plan (passes, tile descriptors, parameter jobs; none when the state
+// is LDS-resident) or, for the adjoint, generators and the Hamiltonian.
 static int build_circuit(const BatchArgs &A, int c, int dtype, bool adjoint, CircBuild *out) {
     const sv_state_t &s = A.states[c];
     const int64_t g0 = A.gate_off[c], g1 = A.gate_off[c + 1];
@@ -384,29 +382,44 @@ static int build_circuit(const BatchArgs &A, int c, int dtype, bool adjoint, Cir
     bc.ngates = (int32_t)(g1 - g0);
     bc.first_param = (int32_t)p0;
     bc.nparams = (int32_t)(p1 - p0);
-    std::vector<int32_t> ord(bc.ngates), pas(bc.ngates);
-    std::vector<uint64_t> pass_S;
     if (bc.ngates > 0) {
         for (int64_t i = g0; i < g1; ++i)
             SV_TRY(validate_circuit_gate(s.n, (int)(p1 - p0), A.gates[i], (int)(i - g0)));
-        if (adjoint) {
-            std::iota(ord.begin(), ord.end(), 0);
-            std::iota(pas.begin(), pas.end(), 0);
-        } else {
-            int64_t np = 0;
+        const bool resident = ((size_t)1 << s.n) * amp_bytes(dtype) <= kBatchLds;
+        if (!adjoint && !resident) {
+            std::vector<PlanPass> pp;
             int m_used = 0;
-            // qubit-set tiles; diagonal gates join a run only with their
-            // target in S (the batch kernel has no elementwise sweeps)
-            SV_TRY(circuit_plan_capped(s.n, dtype, A.gates + g0, bc.ngates, (int)(p1 - p0), SV_FUSE, m_cap,
-                                       ord.data(), pas.data(), &np, &m_used, true, false, &pass_S));
+            SV_TRY(circuit_plan_tiles(s.n, dtype, A.gates + g0, bc.ngates, (int)(p1 - p0), m_cap, &pp, &out->tiles,
+                                      &m_used));
             if (m_used != bc.m)
                 return fail(SV_EINVAL, "planner tile width %d != %d", m_used, bc.m);
+            for (const PlanPass &q : pp) {
+                BPass b;
+                memset(&b, 0, sizeof(b));
+                b.fused = q.fused;
+                b.gate = q.gate;
+                b.first = q.first;
+                b.count = q.count;
+                if (q.fused) {
+                    if (q.tm.m > (uint32_t)m_cap)
+                        return fail(SV_EINVAL, "tile width %u beyond the batch limit", q.tm.m);
+                    b.tm = q.tm;
+                    b.tm.tab = 1;  // the launch reserves the tables
+                }
+                out->passes.push_back(b);
+            }
+            for (size_t t = 0; t < out->tiles.size(); ++t) {
+                const sv_gate_t &g = A.gates[g0 + out->tiles[t].src_gate];
+                if (g.param >= 0)
+                    out->jobs.push_back(BTileJob{g.kind, (int32_t)(p0 + g.param), (int32_t)t, 0});
+            }
         }
     }
+    bc.npasses = (int32_t)out->passes.size();
     double work = 0.0;
     out->gates.reserve(bc.ngates);
     for (int k = 0; k < bc.ngates; ++k) {
-        const sv_gate_t &g = A.gates[g0 + ord[k]];
+        const sv_gate_t &g = A.gates[g0 + k];
         BGate b;
         memset(&b, 0, sizeof(b));
         if (g.param < 0)
@@ -417,24 +430,8 @@ static int build_circuit(const BatchArgs &A, int c, int dtype, bool adjoint, Cir
         b.kind = g.kind;
         b.param = g.param >= 0 ? (int32_t)(p0 + g.param) : -1;
         b.target = g.target;
-        b.pass = pas[k];
         b.cmask = g.ctrl_mask;
         b.cvals = g.ctrl_vals;
-        b.S = pass_S.empty() ? 0 : pass_S[pas[k]];
-        b.ltarget = -1;
-        if (b.S) {
-            if (!((b.S >> g.target) & 1) || popcount64(b.S) > m_cap)
-                return fail(SV_EINVAL, "fused gate outside its tile or tile too wide");
-            b.ltarget = popcount64(b.S & ((1ull << g.target) - 1));
-            int q = 0;
-            for (int bit = 0; bit < 64; ++bit)
-                if ((b.S >> bit) & 1) {
-                    b.lcmask |= ((g.ctrl_mask >> bit) & 1ull) << q;
-                    b.lcvals |= ((g.ctrl_vals >> bit) & 1ull) << q;
-                    ++q;
-                }
-            b.lcvals &= b.lcmask;
-        }
         int gs = -1;
         if (adjoint && g.param >= 0) {
             double a[8];
@@ -477,6 +474,9 @@ static int build_circuit(const BatchArgs &A, int c, int dtype, bool adjoint, Cir
 struct BatchHost {
     std::vector<BCirc> circs;
     std::vector<BGate> gates;
+    std::vector<BPass> passes;
+    std::vector<TileGate> tiles;
+    std::vector<BTileJob> jobs;
     std::vector<int32_t> order;
     std::vector<double> gens;
     std::vector<int32_t> gen_of;
@@ -563,6 +563,18 @@ static int build_batch(const BatchArgs &A, bool adjoint, BatchHost *h, int *dtyp
             return fail(b.err, "circuit %d: %s", c, b.msg.c_str());
         b.bc.first_gate = (int32_t)h->gates.size();
         b.bc.first_term = (int32_t)h->terms.size();
+        b.bc.first_pass = (int32_t)h->passes.size();
+        const int32_t tbase = (int32_t)h->tiles.size();
+        for (BPass p : b.passes) {
+            if (p.fused)
+                p.first += tbase;
+            h->passes.push_back(p);
+        }
+        for (BTileJob j : b.jobs) {
+            j.tile += tbase;
+            h->jobs.push_back(j);
+        }
+        h->tiles.insert(h->tiles.end(), b.tiles.begin(), b.tiles.end());
         const int32_t gbase = (int32_t)(h->gens.size() / 8);
         for (int32_t g : b.gen_of)
             h->gen_of.push_back(g >= 0 ? g + gbase : -1);
@@ -581,6 +593,10 @@ static int build_batch(const BatchArgs &A, bool adjoint, BatchHost *h, int *dtyp
 struct BatchDevice {
     BCirc *circs = nullptr;
     BGate *gates = nullptr;
+    BPass *passes = nullptr;
+    TileGate *tiles = nullptr;
+    BTileJob *jobs = nullptr;
+    int njobs = 0;
     int32_t *order = nullptr, *gen_of = nullptr;
     double *gens = nullptr;
     DTerm *terms = nullptr;
@@ -590,7 +606,7 @@ struct BatchDevice {
 // Stream-ordered release when async (after the kernels enqueued on st),
 // otherwise an immediate free.
 static void batch_release(BatchDevice *d, bool async, hipStream_t st) {
-    void *ps[] = {d->circs, d->gates, d->order, d->gen_of, d->gens, d->terms, d->queue};
+    void *ps[] = {d->circs, d->gates, d->passes, d->tiles, d->jobs, d->order, d->gen_of, d->gens, d->terms, d->queue};
     for (void *p : ps)
         if (p)
             (void)(async ? hipFreeAsync(p, st) : hipFree(p));
@@ -623,6 +639,13 @@ static int upload_batch(const BatchHost &h, bool async, hipStream_t st, BatchDev
     if (r == SV_OK)
         r = dev_copy(&d->gates, h.gates, async, st, 1);
     if (r == SV_OK)
+        r = dev_copy(&d->passes, h.passes, async, st, 1);
+    if (r == SV_OK)
+        r = dev_copy(&d->tiles, h.tiles, async, st, 1);
+    if (r == SV_OK)
+        r = dev_copy(&d->jobs, h.jobs, async, st, 1);
+    d->njobs = (int)h.jobs.size();
+    if (r == SV_OK)
         r = dev_copy(&d->order, h.order, async, st);
     if (r == SV_OK)
         r = dev_copy(&d->gen_of, h.gen_of, async, st, 1);
@@ -652,8 +675,6 @@ static unsigned persistent_grid(int ncirc) {
     return std::min<unsigned>(g, (unsigned)ncirc);
 }
 
-constexpr size_t kBatchDynLds = kBatchLds + 64;  // the tile, then the work-item slot
-
 static int launch_forward(int dtype, const BatchDevice &d, int ncirc, const double *params, hipStream_t s) {
     hipError_t a = dtype == SV_C128 ? hipFuncSetAttribute((const void *)k_batched<double>,
                                                           hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -664,13 +685,16 @@ static int launch_forward(int dtype, const BatchDevice &d, int ncirc, const doub
     if (a != hipSuccess)
         return fail(SV_EHIP, "LDS limit: %s", hipGetErrorString(a));
     const unsigned grid = persistent_grid(ncirc);
+    if (d.njobs > 0)
+        hipLaunchKernelGGL(k_batch_tile_params, dim3((d.njobs + 255) / 256), dim3(256), 0, s, d.jobs, d.njobs, params,
+                           d.tiles);
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, s, d.queue);
     if (dtype == SV_C128)
         hipLaunchKernelGGL(k_batched<double>, dim3(grid), dim3(kBatchThreads), kBatchDynLds, s, d.circs, d.order,
-                           ncirc, d.gates, params, d.queue);
+                           ncirc, d.gates, d.passes, d.tiles, params, d.queue);
     else
         hipLaunchKernelGGL(k_batched<float>, dim3(grid), dim3(kBatchThreads), kBatchDynLds, s, d.circs, d.order,
-                           ncirc, d.gates, params, d.queue);
+                           ncirc, d.gates, d.passes, d.tiles, params, d.queue);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess)
         return fail(SV_EHIP, "batched launch failed: %s", hipGetErrorString(e));

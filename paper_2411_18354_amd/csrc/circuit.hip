@@ -212,6 +212,28 @@ static int plan_circuit(sv_circuit *c, std::vector<TileGate> &tiles, std::vector
                     c->tile_src.push_back(gi);
                     from_param.push_back(g.param >= 0);
                 }
+                // Short diagonal blocks are not worth a sweep over the whole
+                // tile: their gates with the target in S run as pair gates,
+                // whose tile-local controls are then scheduled, not tested.
+                for (int k = p.first, end = p.first + p.count; k < end;) {
+                    if (!tiles[k].diag) {
+                        ++k;
+                        continue;
+                    }
+                    int e = k, nlocal = 0;
+                    for (; e < end && tiles[e].diag; ++e)
+                        nlocal += (tiles[e].l_target >= 0 || tiles[e].l_mask) ? 1 : 0;
+                    if (nlocal < kPhaseSweepMin)
+                        for (int q = k; q < e; ++q)
+                            if (tiles[q].l_target >= 0) {
+                                const int gi = tiles[q].src_gate;
+                                const sv_gate_t &g = c->gates[gi];
+                                tiles[q] = make_tile_gate(p.tm, g.target, g.ctrl_mask, g.ctrl_vals,
+                                                          &mats[(size_t)8 * gi], false);
+                                tiles[q].src_gate = gi;
+                            }
+                    k = e;
+                }
                 mark_diag_sweeps(&tiles[p.first], p.count, from_param.data());
                 c->passes.push_back(p);
                 c->fused_gates += (int64_t)run.size();
@@ -509,6 +531,46 @@ int sv_circuit_plan(int n, int dtype, const sv_gate_t *gates, int ngates, int np
 } // extern "C"
 
 namespace sv {
+
+int circuit_plan_tiles(int n, int dtype, const sv_gate_t *gates, int ngates, int nparams, int m_cap,
+                       std::vector<PlanPass> *passes, std::vector<TileGate> *tiles, int *m_used) {
+    if (dtype != SV_C128 && dtype != SV_C64)
+        return fail(SV_EINVAL, "unknown dtype %d", dtype);
+    if (n < 1 || n > max_qubits(dtype))
+        return fail(SV_EINVAL, "n=%d outside [1, %d]", n, max_qubits(dtype));
+    if (ngates < 0 || (ngates > 0 && !gates))
+        return fail(SV_EINVAL, "bad gate list (ngates %d, gates %p)", ngates, (const void *)gates);
+    for (int i = 0; i < ngates; ++i)
+        SV_TRY(validate_circuit_gate(n, nparams, gates[i], i));
+    sv_circuit c;
+    c.n = n;
+    c.dtype = dtype;
+    c.flags = SV_FUSE;
+    c.nparams = nparams;
+    c.m_cap = m_cap;
+    c.gates.assign(gates, gates + ngates);
+    std::vector<ParamJob> jobs;
+    std::vector<double> mats;
+    std::vector<DenseGate> dense_list;
+    int dense_runs = 0;
+    tiles->clear();
+    SV_TRY(plan_circuit(&c, *tiles, jobs, mats, dense_list, dense_runs));
+    passes->clear();
+    for (const Pass &p : c.passes) {
+        PlanPass q;
+        memset(&q, 0, sizeof(q));
+        q.fused = p.fused ? 1 : 0;
+        q.gate = p.fused ? -1 : p.gate;
+        q.first = p.fused ? p.first : 0;
+        q.count = p.fused ? p.count : 1;
+        if (p.fused)
+            q.tm = p.tm;
+        passes->push_back(q);
+    }
+    if (m_used)
+        *m_used = c.m;
+    return SV_OK;
+}
 
 int circuit_plan_capped(int n, int dtype, const sv_gate_t *gates, int ngates, int nparams, int flags, int m_cap,
                         int32_t *order, int32_t *pass_of, int64_t *npasses, int *m_used, bool general,

@@ -55,6 +55,18 @@ namespace sv {
 // Validate, plan and upload a circuit (the body of sv_circuit_create).
 // async: device buffers are allocated and released stream-ordered on st.
 // m_cap bounds the tile width (callers with a fixed LDS budget).
+// The fused plan of a circuit as data for other executors (the batched
+// kernel): each pass is either one gate (fused == 0, gate = its index in the
+// circuit) or the run of tile descriptors tiles[first .. first + count) over
+// the tile map tm.  Tiles over any qubit set, diagonal gates fused whatever
+// their target, tile width at most m_cap.
+struct PlanPass {
+    TileMap tm;
+    int32_t fused, gate, first, count;
+};
+int circuit_plan_tiles(int n, int dtype, const sv_gate_t *gates, int ngates, int nparams, int m_cap,
+                       std::vector<PlanPass> *passes, std::vector<TileGate> *tiles, int *m_used);
+
 int circuit_create(int n, int dtype, const sv_gate_t *gates, int ngates, int nparams, int flags, bool async,
                    hipStream_t st, int m_cap, sv_circuit **out);
 // Release device buffers (stream-ordered on st for async plans) and the plan.
