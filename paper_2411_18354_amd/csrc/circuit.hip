@@ -477,6 +477,8 @@ static void drop_graph(sv_circuit *c) {
 }
 
 static int run_graph(sv_circuit *c, const sv_state_t *s, const double *params, hipStream_t st) {
+    if (c->passes.empty())
+        return SV_OK;  // nothing to capture
     if (!c->exec || c->g_data != s->data || c->g_params != params) {
         drop_graph(c);
         if (!c->cap)

@@ -235,3 +235,17 @@ def test_batched_qubit_set_tiles(gpu):
         for c, v in zip(circs, views):
             e = _err(v.cpu().numpy(), oracle.run_circuit(c))
             assert e <= tol, (dtype, c.n, e)
+
+
+def test_batch_with_empty_circuits(gpu):
+    """Circuits without gates (LDS-resident and global-memory sizes) leave
+    their states untouched while the others in the same batch run."""
+    import torch
+    circs = [W.Circuit(9, []), W.random_gates_n12(seed=31, n=9, ngates=50), W.Circuit(14, []),
+             W.random_gates_n12(seed=32, n=14, ngates=120)]
+    psis = [W.random_state(c.n, 40 + i) for i, c in enumerate(circs)]
+    views = [torch.from_numpy(p).cuda() for p in psis]
+    gpu.sv_apply_circuits_batched(views, circs)
+    for c, p, v in zip(circs, psis, views):
+        ref = oracle.run_circuit(c, None, p) if c.gates else p
+        assert _err(v.cpu().numpy(), ref) <= 1e-12, (c.n, len(c.gates))

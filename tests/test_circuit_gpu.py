@@ -318,3 +318,17 @@ def test_layered_circuit_n32_full(gpu):
         x = a[o:o + chunk]
         rest = max(rest, float(x.abs().max()) if o else float(x[1:].abs().max()))
     assert rest <= 1e-10, rest
+
+
+def test_empty_circuit(gpu):
+    """A circuit without gates is a valid plan that leaves the state as it is."""
+    import torch
+    n = 12
+    psi = W.random_state(n, 9)
+    for flags in (0, gpu.SV_FUSE, gpu.SV_FUSE | gpu.SV_GRAPH):
+        d = torch.from_numpy(psi).cuda()
+        gpu.sv_apply_circuit(d, W.Circuit(n, []), flags=flags & ~gpu.SV_GRAPH)
+        plan = gpu.Circuit(n, W.Circuit(n, []), flags=flags)
+        plan.run(d)
+        plan.close()
+        assert torch.equal(d.cpu(), torch.from_numpy(psi)), flags
