@@ -20,6 +20,7 @@
 #include "circuit.hpp"
 #include "gates.hpp"
 #include "pauli.hpp"
+#include "tile_adj.hpp"
 
 namespace sv {
 
@@ -73,13 +74,10 @@ __global__ __launch_bounds__(kRedThreads) void k_adj(cplx_t<R> *__restrict__ psi
     }
 }
 
-// A fused run of the reverse sweep on one tile of psi and one of lambda held
-// together in LDS (tile layout and operation kinds as in the forward tile
-// pass).  Operation i un-applies its gate (the descriptor holds U^dag); when
-// gslot[i] >= 0 its gradient term 2 Re <lambda|Pi_c A|psi> is taken first
-// and added, in tile order, to this workgroup's partial of that slot.
-constexpr int kAdjTileThreads = 512;
-
+// A fused run of the reverse sweep, one workgroup per group of tiles: psi
+// and lambda tiles together in LDS, the run's operations un-applied by
+// adj_tile_run (tile_adj.hpp), each workgroup's gradient partials written
+// once at the end.
 template <typename R>
 __global__ __launch_bounds__(kAdjTileThreads) void k_adj_tile(cplx_t<R> *__restrict__ psi, cplx_t<R> *__restrict__ lam,
                                                               TileMap tm, DeviceGates gates,
@@ -90,26 +88,11 @@ __global__ __launch_bounds__(kAdjTileThreads) void k_adj_tile(cplx_t<R> *__restr
     const uint32_t T = 1u << tm.m;
     cplx_t<R> *tp = reinterpret_cast<cplx_t<R> *>(lds_raw);
     cplx_t<R> *tl = tp + T;
-    // after the two tiles: one gradient accumulator per wavefront for each
-    // parameterised gate of the run (k-th such gate: accl[k * kWaves + w]),
-    // so a gate's sum needs a wavefront reduction but no workgroup barrier
-    constexpr int kWaves = kAdjTileThreads / 64;
     double *accl = reinterpret_cast<double *>(tl + T);
-    const int w = threadIdx.x >> 6;
-    int npg = 0;
-    for (int i = 0; i < gates.size(); ++i)
-        npg += gslot[i] >= 0 ? 1 : 0;
-    for (int k = threadIdx.x; k < npg * kWaves; k += kAdjTileThreads)
-        accl[k] = 0.0;
-    __syncthreads();
+    const int npg = adj_acc_zero(gates, gslot, accl);
     for (uint64_t t = blockIdx.x; t < tm.ntiles; t += gridDim.x) {
         const uint64_t base = expand_index<uint64_t>(tm.outer, t);
-        bool any = false;
-        for (int i = 0; i < gates.size(); ++i) {
-            const TileGate &g = gates.get(i);
-            any |= g.diag ? ((base & g.o_mask) == g.o_vals) : ((base & g.hi_mask) == g.hi_vals);
-        }
-        if (!any)
+        if (!adj_tile_touched(base, gates))
             continue;  // uniform
         for (uint32_t j = threadIdx.x; j < T; j += kAdjTileThreads) {
             const uint64_t k = base | tile_offset(tm, j);
@@ -117,79 +100,7 @@ __global__ __launch_bounds__(kAdjTileThreads) void k_adj_tile(cplx_t<R> *__restr
             tl[j] = ld_stream<R>(lam + k);
         }
         __syncthreads();
-        int kacc = 0;  // parameterised gates seen so far in this run
-        for (int i = 0; i < gates.size(); ++i) {
-            const TileGate &g = gates.get(i);
-            const int sl = gslot[i];
-            double a[8];
-            for (int q = 0; q < 8; ++q)
-                a[q] = sl >= 0 ? gens[8 * sl + q] : 0.0;
-            double acc = 0.0;
-            bool did = false;
-            if (g.diag) {
-                if ((base & g.o_mask) == g.o_vals) {  // uniform
-                    did = true;
-                    const bool tin = g.l_target >= 0;
-                    const bool tone = (base >> g.target) & 1ull;
-                    // entries made wave-uniform before the per-lane select
-                    const R m0r = (R)uniform_f64(g.m[0]), m0i = (R)uniform_f64(g.m[1]);
-                    const R m1r = (R)uniform_f64(g.m[6]), m1i = (R)uniform_f64(g.m[7]);
-                    for (uint32_t j = threadIdx.x; j < T; j += kAdjTileThreads) {
-                        if ((j & g.l_mask) != g.l_vals)
-                            continue;
-                        const bool one = tin ? ((j >> g.l_target) & 1u) : tone;
-                        const cplx_t<R> x = tp[j], lx = tl[j];
-                        if (sl >= 0) {
-                            const double gr = one ? a[6] : a[0], gi = one ? a[7] : a[1];
-                            const double axr = gr * x.x - gi * x.y, axi = gr * x.y + gi * x.x;
-                            acc += 2.0 * ((double)lx.x * axr + (double)lx.y * axi);
-                        }
-                        const R ur = one ? m1r : m0r, ui = one ? m1i : m0i;
-                        cplx_t<R> nx, nl;
-                        nx.x = x.x * ur - x.y * ui;
-                        nx.y = x.x * ui + x.y * ur;
-                        nl.x = lx.x * ur - lx.y * ui;
-                        nl.y = lx.x * ui + lx.y * ur;
-                        tp[j] = nx;
-                        tl[j] = nl;
-                    }
-                }
-            } else if ((base & g.hi_mask) == g.hi_vals) {  // uniform
-                did = true;
-                const Mat2<R> u = tile_mat<R>(g);
-                const uint32_t st = 1u << g.target;
-                const bool in_regs = g.nseg <= (uint32_t)kExpRegs;  // uniform
-                const TileExp ex = tile_exp_load(g);
-                for (uint32_t r = threadIdx.x; r < g.npairs; r += kAdjTileThreads) {
-                    const uint32_t p1 = in_regs ? tile_exp(ex, r) : tile_expand(g, r);
-                    cplx_t<R> x = tp[p1], y = tp[p1 | st], lx = tl[p1], ly = tl[p1 | st];
-                    if (sl >= 0) {
-                        const double xr = x.x, xi = x.y, yr = y.x, yi = y.y;
-                        const double axr = a[0] * xr - a[1] * xi + a[2] * yr - a[3] * yi;
-                        const double axi = a[0] * xi + a[1] * xr + a[2] * yi + a[3] * yr;
-                        const double ayr = a[4] * xr - a[5] * xi + a[6] * yr - a[7] * yi;
-                        const double ayi = a[4] * xi + a[5] * xr + a[6] * yi + a[7] * yr;
-                        acc += 2.0 * ((double)lx.x * axr + (double)lx.y * axi + (double)ly.x * ayr +
-                                      (double)ly.y * ayi);
-                    }
-                    apply_pair<R>(u, x, y);
-                    apply_pair<R>(u, lx, ly);
-                    tp[p1] = x;
-                    tp[p1 | st] = y;
-                    tl[p1] = lx;
-                    tl[p1 | st] = ly;
-                }
-            }
-            if (did) {  // uniform
-                if (sl >= 0) {
-                    const double s = wave_sum(acc);
-                    if ((threadIdx.x & 63) == 0)
-                        accl[kacc * kWaves + w] += s;
-                }
-                __syncthreads();
-            }
-            kacc += sl >= 0 ? 1 : 0;
-        }
+        adj_tile_run<R, kAdjTileThreads>(tp, tl, base, T, gates, gslot, gens, accl);
         for (uint32_t j = threadIdx.x; j < T; j += kAdjTileThreads) {
             const uint64_t k = base | tile_offset(tm, j);
             st_stream<R>(psi + k, tp[j]);
@@ -201,18 +112,8 @@ __global__ __launch_bounds__(kAdjTileThreads) void k_adj_tile(cplx_t<R> *__restr
     // accumulators summed in index order
     __syncthreads();
     for (int k = threadIdx.x; k < npg; k += kAdjTileThreads) {
-        double s = 0.0;
-        for (int q = 0; q < kWaves; ++q)
-            s += accl[k * kWaves + q];
-        int c = 0;
-        for (int i = 0; i < gates.size(); ++i)
-            if (gslot[i] >= 0) {
-                if (c == k) {
-                    partials[(size_t)gslot[i] * kMaxPartials + blockIdx.x] = s;
-                    break;
-                }
-                ++c;
-            }
+        const int sl = adj_acc_slot(gates, gslot, k);
+        partials[(size_t)sl * kMaxPartials + blockIdx.x] = adj_acc_sum(accl, k);
     }
 }
 

@@ -28,6 +28,7 @@
 #include "circuit.hpp"
 #include "gates.hpp"
 #include "pauli.hpp"
+#include "tile_adj.hpp"
 
 namespace sv {
 
@@ -68,6 +69,7 @@ struct BCirc {
     int32_t n;
     int32_t m;           // tile width of the fused plan
     int32_t first_pass, npasses;  // forward: the fused plan
+    int32_t first_apass, napasses;  // adjoint: the fused plan of the reverse sweep
     int32_t first_gate;  // gates [first_gate, first_gate + ngates), in program order
     int32_t ngates;
     int32_t first_param, nparams;  // adjoint: gradient slots
@@ -237,14 +239,59 @@ __global__ void k_zero_u32(unsigned int *p) { *p = 0u; }
 
 // ----------------------------------------------------------------- adjoint
 
-// One circuit's adjoint inside one workgroup: lambda = H psi (and the loss),
-// then the reverse sweep with per-gate gradient sums reduced in the
-// workgroup (a fixed order, so results are reproducible).
+// One gate of the reverse sweep over the whole state in global memory:
+// gradient term (when parameterised) and un-apply on psi and lambda.
 template <typename R>
-__device__ void adjoint_block(const BCirc &c, const BGate *__restrict__ gates, const double *__restrict__ params,
+__device__ void adj_gate_global(const BCirc &c, const BGate &g, int gs, const double *__restrict__ params,
+                                const double *__restrict__ gens, cplx_t<R> *psi, cplx_t<R> *lam,
+                                double *__restrict__ grad, double *scratch) {
+    const Mat2<R> ud = bgate_mat<R>(g, params, true);
+    double a[8];
+    for (int k = 0; k < 8; ++k)
+        a[k] = gs >= 0 ? gens[8 * gs + k] : 0.0;
+    const uint64_t pos = g.cmask | (1ull << g.target);
+    const uint64_t npairs = 1ull << (c.n - 1 - __popcll(g.cmask));
+    const uint64_t st = 1ull << g.target;
+    double acc = 0.0;
+    for (uint64_t it = threadIdx.x; it < npairs; it += kBatchThreads) {
+        const uint64_t p1 = insert_bits<uint64_t>(it, pos, g.cvals);
+        cplx_t<R> x = psi[p1], y = psi[p1 | st], lx = lam[p1], ly = lam[p1 | st];
+        if (gs >= 0) {
+            const double xr = x.x, xi = x.y, yr = y.x, yi = y.y;
+            const double axr = a[0] * xr - a[1] * xi + a[2] * yr - a[3] * yi;
+            const double axi = a[0] * xi + a[1] * xr + a[2] * yi + a[3] * yr;
+            const double ayr = a[4] * xr - a[5] * xi + a[6] * yr - a[7] * yi;
+            const double ayi = a[4] * xi + a[5] * xr + a[6] * yi + a[7] * yr;
+            acc += 2.0 * ((double)lx.x * axr + (double)lx.y * axi + (double)ly.x * ayr + (double)ly.y * ayi);
+        }
+        apply_pair<R>(ud, x, y);
+        apply_pair<R>(ud, lx, ly);
+        psi[p1] = x;
+        psi[p1 | st] = y;
+        lam[p1] = lx;
+        lam[p1 | st] = ly;
+    }
+    if (gs >= 0) {  // uniform
+        const double s = block_sum(acc, scratch);
+        if (threadIdx.x == 0)
+            grad[g.param] += s;
+    }
+    __syncthreads();
+}
+
+// One circuit's adjoint inside one workgroup: lambda = H psi (and the loss),
+// then the reverse sweep: the fused plan of the inverse circuit, tiles of psi
+// and lambda together in LDS (adj_tile_run, shared with the single-circuit
+// adjoint), and single gates over global memory.  Gradient sums are reduced
+// in a fixed order (per wavefront, then wavefronts in index order, then
+// passes in order), so results are reproducible.
+template <typename R>
+__device__ void adjoint_block(const BCirc &c, const BGate *__restrict__ gates, const BPass *__restrict__ apasses,
+                              const TileGate *__restrict__ atiles, const int32_t *__restrict__ atslot,
+                              const int32_t *__restrict__ slot_param, const double *__restrict__ params,
                               const DTerm *__restrict__ terms, const double *__restrict__ gens,
                               const int32_t *__restrict__ gen_of, double *__restrict__ grad,
-                              double *__restrict__ loss, double *scratch) {
+                              double *__restrict__ loss, double *scratch, unsigned char *dyn) {
     cplx_t<R> *psi = reinterpret_cast<cplx_t<R> *>(c.psi);
     cplx_t<R> *lam = reinterpret_cast<cplx_t<R> *>(c.lam);
     const uint64_t N = 1ull << c.n;
@@ -275,50 +322,54 @@ __device__ void adjoint_block(const BCirc &c, const BGate *__restrict__ gates, c
     if (threadIdx.x == 0)
         loss[0] = L;
     __syncthreads();
-    for (int i = c.ngates - 1; i >= 0; --i) {
-        const BGate &g = gates[c.first_gate + i];
-        const Mat2<R> ud = bgate_mat<R>(g, params, true);
-        const int gs = gen_of[c.first_gate + i];
-        double a[8];
-        for (int k = 0; k < 8; ++k)
-            a[k] = gs >= 0 ? gens[8 * gs + k] : 0.0;
-        const uint64_t pos = g.cmask | (1ull << g.target);
-        const uint64_t npairs = 1ull << (c.n - 1 - __popcll(g.cmask));
-        const uint64_t st = 1ull << g.target;
-        double acc = 0.0;
-        for (uint64_t it = threadIdx.x; it < npairs; it += kBatchThreads) {
-            const uint64_t p1 = insert_bits<uint64_t>(it, pos, g.cvals);
-            cplx_t<R> x = psi[p1], y = psi[p1 | st], lx = lam[p1], ly = lam[p1 | st];
-            if (gs >= 0) {
-                const double xr = x.x, xi = x.y, yr = y.x, yi = y.y;
-                const double axr = a[0] * xr - a[1] * xi + a[2] * yr - a[3] * yi;
-                const double axi = a[0] * xi + a[1] * xr + a[2] * yi + a[3] * yr;
-                const double ayr = a[4] * xr - a[5] * xi + a[6] * yr - a[7] * yi;
-                const double ayi = a[4] * xi + a[5] * xr + a[6] * yi + a[7] * yr;
-                acc += 2.0 * ((double)lx.x * axr + (double)lx.y * axi + (double)ly.x * ayr + (double)ly.y * ayi);
+    cplx_t<R> *tp = reinterpret_cast<cplx_t<R> *>(dyn);
+    for (int pi = 0; pi < c.napasses; ++pi) {
+        const BPass &p = apasses[c.first_apass + pi];
+        if (p.fused) {  // uniform
+            const DeviceGates dg{atiles + p.first, p.count};
+            const int32_t *gs = atslot + p.first;
+            const uint32_t T = 1u << p.tm.m;
+            cplx_t<R> *tl = tp + T;
+            double *accl = reinterpret_cast<double *>(tl + T);
+            const int npg = adj_acc_zero(dg, gs, accl);
+            for (uint64_t tt = 0; tt < p.tm.ntiles; ++tt) {
+                const uint64_t base = expand_index<uint64_t>(p.tm.outer, tt);
+                if (!adj_tile_touched(base, dg))
+                    continue;  // uniform
+                for (uint32_t k = threadIdx.x; k < T; k += kBatchThreads) {
+                    const uint64_t o = base | tile_offset(p.tm, k);
+                    tp[k] = psi[o];
+                    tl[k] = lam[o];
+                }
+                __syncthreads();
+                adj_tile_run<R, kBatchThreads>(tp, tl, base, T, dg, gs, gens, accl);
+                for (uint32_t k = threadIdx.x; k < T; k += kBatchThreads) {
+                    const uint64_t o = base | tile_offset(p.tm, k);
+                    psi[o] = tp[k];
+                    lam[o] = tl[k];
+                }
+                __syncthreads();
             }
-            apply_pair<R>(ud, x, y);
-            apply_pair<R>(ud, lx, ly);
-            psi[p1] = x;
-            psi[p1 | st] = y;
-            lam[p1] = lx;
-            lam[p1 | st] = ly;
+            if (threadIdx.x == 0)  // in order: gates may share a parameter
+                for (int k = 0; k < npg; ++k)
+                    grad[slot_param[adj_acc_slot(dg, gs, k)]] += adj_acc_sum(accl, k);
+            __syncthreads();
+        } else {
+            const int f = p.gate;  // forward index of the gate un-applied here
+            adj_gate_global<R>(c, gates[c.first_gate + f], gen_of[c.first_gate + f], params, gens, psi, lam, grad,
+                               scratch);
         }
-        if (gs >= 0) {  // uniform
-            const double s = block_sum(acc, scratch);
-            if (threadIdx.x == 0)
-                grad[g.param] += s;
-        }
-        __syncthreads();
     }
 }
 
 template <typename R>
 __global__ __launch_bounds__(kBatchThreads) void k_batched_adjoint(
     const BCirc *__restrict__ circs, const int32_t *__restrict__ order, int ncirc, const BGate *__restrict__ gates,
-    const double *__restrict__ params, const DTerm *__restrict__ terms, const double *__restrict__ gens,
-    const int32_t *__restrict__ gen_of, double *__restrict__ grad, double *__restrict__ loss,
-    unsigned int *__restrict__ queue) {
+    const BPass *__restrict__ apasses, const TileGate *__restrict__ atiles, const int32_t *__restrict__ atslot,
+    const int32_t *__restrict__ slot_param, const double *__restrict__ params, const DTerm *__restrict__ terms,
+    const double *__restrict__ gens, const int32_t *__restrict__ gen_of, double *__restrict__ grad,
+    double *__restrict__ loss, unsigned int *__restrict__ queue) {
+    extern __shared__ unsigned char lds_raw[];  // psi and lambda tiles, then gradient accumulators
     __shared__ double scratch[kBatchThreads / 64];
     __shared__ int item;
     for (;;) {
@@ -330,7 +381,8 @@ __global__ __launch_bounds__(kBatchThreads) void k_batched_adjoint(
         if (it >= ncirc)
             break;
         const int ci = order[it];
-        adjoint_block<R>(circs[ci], gates, params, terms, gens, gen_of, grad, loss + ci, scratch);
+        adjoint_block<R>(circs[ci], gates, apasses, atiles, atslot, slot_param, params, terms, gens, gen_of, grad,
+                         loss + ci, scratch, lds_raw);
         __syncthreads();
     }
 }
@@ -345,6 +397,13 @@ struct CircBuild {
     std::vector<BPass> passes;     // forward plan (circuit-local indices)
     std::vector<TileGate> tiles;
     std::vector<BTileJob> jobs;    // tile indices circuit-local
+    // adjoint: the reverse sweep's fused plan, each descriptor's generator
+    // slot (circuit-local, -1 none), each slot's parameter (batch-global)
+    std::vector<BPass> apasses;
+    std::vector<TileGate> atiles;
+    std::vector<BTileJob> ajobs;
+    std::vector<int32_t> atslot, slot_param;
+    size_t adj_lds = 0;            // dynamic LDS its fused passes need
     std::vector<double> gens;      // generators of the parameterised gates
     std::vector<int32_t> gen_of;   // per gate: index into gens / 8, or -1
     std::vector<DTerm> terms;
@@ -444,10 +503,53 @@ static int build_circuit(const BatchArgs &A, int c, int dtype, bool adjoint, Cir
             }
             gs = (int)(out->gens.size() / 8);
             out->gens.insert(out->gens.end(), a, a + 8);
+            out->slot_param.push_back((int32_t)(p0 + g.param));
         }
         out->gen_of.push_back(gs);
         out->gates.push_back(b);
         work += std::ldexp(1.0, s.n - popcount64(g.ctrl_mask));
+    }
+    if (adjoint && bc.ngates > 0) {
+        // the reverse sweep: inverses in reverse order, planned like a forward
+        // circuit with two tiles (psi and lambda) in the LDS of one
+        const int m_cap_adj = m_cap - 1;
+        std::vector<sv_gate_t> rev(bc.ngates);
+        for (int r = 0; r < bc.ngates; ++r) {
+            rev[r] = A.gates[g0 + bc.ngates - 1 - r];
+            rev[r].kind ^= SV_G_ADJOINT;
+        }
+        std::vector<PlanPass> pp;
+        int m_used = 0;
+        SV_TRY(circuit_plan_tiles(s.n, dtype, rev.data(), bc.ngates, (int)(p1 - p0), m_cap_adj, &pp, &out->atiles,
+                                  &m_used));
+        for (const PlanPass &q : pp) {
+            BPass b;
+            memset(&b, 0, sizeof(b));
+            b.fused = q.fused;
+            b.first = q.first;
+            b.count = q.count;
+            if (q.fused) {
+                if (q.tm.m > (uint32_t)m_cap_adj)
+                    return fail(SV_EINVAL, "tile width %u beyond the batch limit", q.tm.m);
+                b.tm = q.tm;
+                size_t npg = 0;
+                for (int j = 0; j < q.count; ++j)
+                    npg += out->gen_of[bc.ngates - 1 - out->atiles[q.first + j].src_gate] >= 0 ? 1 : 0;
+                out->adj_lds = std::max(out->adj_lds, ((size_t)2 << q.tm.m) * amp_bytes(dtype) +
+                                                          npg * kAdjWaves * sizeof(double));
+            } else {
+                b.gate = bc.ngates - 1 - q.gate;  // forward index
+            }
+            out->apasses.push_back(b);
+        }
+        for (size_t t = 0; t < out->atiles.size(); ++t) {
+            const int f = bc.ngates - 1 - out->atiles[t].src_gate;
+            out->atslot.push_back(out->gen_of[f]);
+            const sv_gate_t &g = A.gates[g0 + f];
+            if (g.param >= 0)
+                out->ajobs.push_back(BTileJob{g.kind ^ SV_G_ADJOINT, (int32_t)(p0 + g.param), (int32_t)t, 0});
+        }
+        bc.napasses = (int32_t)out->apasses.size();
     }
     if (adjoint) {
         const int64_t t0 = A.term_off[c], t1 = A.term_off[c + 1];
@@ -477,6 +579,11 @@ struct BatchHost {
     std::vector<BPass> passes;
     std::vector<TileGate> tiles;
     std::vector<BTileJob> jobs;
+    std::vector<BPass> apasses;
+    std::vector<TileGate> atiles;
+    std::vector<BTileJob> ajobs;
+    std::vector<int32_t> atslot, slot_param;
+    size_t adj_lds = 0;
     std::vector<int32_t> order;
     std::vector<double> gens;
     std::vector<int32_t> gen_of;
@@ -575,7 +682,23 @@ static int build_batch(const BatchArgs &A, bool adjoint, BatchHost *h, int *dtyp
             h->jobs.push_back(j);
         }
         h->tiles.insert(h->tiles.end(), b.tiles.begin(), b.tiles.end());
-        const int32_t gbase = (int32_t)(h->gens.size() / 8);
+        const int32_t gbase = (int32_t)(h->gens.size() / 8);  // generator slots before this circuit's
+        b.bc.first_apass = (int32_t)h->apasses.size();
+        const int32_t abase = (int32_t)h->atiles.size();
+        for (BPass p : b.apasses) {
+            if (p.fused)
+                p.first += abase;
+            h->apasses.push_back(p);
+        }
+        for (BTileJob j : b.ajobs) {
+            j.tile += abase;
+            h->ajobs.push_back(j);
+        }
+        h->atiles.insert(h->atiles.end(), b.atiles.begin(), b.atiles.end());
+        for (int32_t sl : b.atslot)
+            h->atslot.push_back(sl >= 0 ? sl + gbase : -1);
+        h->slot_param.insert(h->slot_param.end(), b.slot_param.begin(), b.slot_param.end());
+        h->adj_lds = std::max(h->adj_lds, b.adj_lds);
         for (int32_t g : b.gen_of)
             h->gen_of.push_back(g >= 0 ? g + gbase : -1);
         h->gates.insert(h->gates.end(), b.gates.begin(), b.gates.end());
@@ -597,6 +720,12 @@ struct BatchDevice {
     TileGate *tiles = nullptr;
     BTileJob *jobs = nullptr;
     int njobs = 0;
+    BPass *apasses = nullptr;
+    TileGate *atiles = nullptr;
+    BTileJob *ajobs = nullptr;
+    int najobs = 0;
+    int32_t *atslot = nullptr, *slot_param = nullptr;
+    size_t adj_lds = 0;
     int32_t *order = nullptr, *gen_of = nullptr;
     double *gens = nullptr;
     DTerm *terms = nullptr;
@@ -606,7 +735,9 @@ struct BatchDevice {
 // Stream-ordered release when async (after the kernels enqueued on st),
 // otherwise an immediate free.
 static void batch_release(BatchDevice *d, bool async, hipStream_t st) {
-    void *ps[] = {d->circs, d->gates, d->passes, d->tiles, d->jobs, d->order, d->gen_of, d->gens, d->terms, d->queue};
+    void *ps[] = {d->circs,  d->gates,  d->passes, d->tiles,  d->jobs,  d->apasses, d->atiles,
+                  d->ajobs,  d->atslot, d->slot_param, d->order, d->gen_of, d->gens,    d->terms,
+                  d->queue};
     for (void *p : ps)
         if (p)
             (void)(async ? hipFreeAsync(p, st) : hipFree(p));
@@ -645,6 +776,18 @@ static int upload_batch(const BatchHost &h, bool async, hipStream_t st, BatchDev
     if (r == SV_OK)
         r = dev_copy(&d->jobs, h.jobs, async, st, 1);
     d->njobs = (int)h.jobs.size();
+    if (r == SV_OK)
+        r = dev_copy(&d->apasses, h.apasses, async, st, 1);
+    if (r == SV_OK)
+        r = dev_copy(&d->atiles, h.atiles, async, st, 1);
+    if (r == SV_OK)
+        r = dev_copy(&d->ajobs, h.ajobs, async, st, 1);
+    d->najobs = (int)h.ajobs.size();
+    if (r == SV_OK)
+        r = dev_copy(&d->atslot, h.atslot, async, st, 1);
+    if (r == SV_OK)
+        r = dev_copy(&d->slot_param, h.slot_param, async, st, 1);
+    d->adj_lds = h.adj_lds;
     if (r == SV_OK)
         r = dev_copy(&d->order, h.order, async, st);
     if (r == SV_OK)
@@ -703,14 +846,29 @@ static int launch_forward(int dtype, const BatchDevice &d, int ncirc, const doub
 
 static int launch_adjoint(int dtype, const BatchDevice &d, int ncirc, const double *params, double *grad,
                           double *loss, hipStream_t s) {
+    constexpr size_t kLdsPerWorkgroup = 160 * 1024;  // gfx950, with the opt-in limit raised
+    const size_t lds = std::max<size_t>(d.adj_lds, 8);
+    if (lds + 1024 > kLdsPerWorkgroup)
+        return fail(SV_ENOTSUP, "a fused reverse pass needs %zu bytes of LDS", lds);
+    hipError_t a = dtype == SV_C128 ? hipFuncSetAttribute((const void *)k_batched_adjoint<double>,
+                                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds)
+                                    : hipFuncSetAttribute((const void *)k_batched_adjoint<float>,
+                                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (a != hipSuccess)
+        return fail(SV_EHIP, "LDS limit: %s", hipGetErrorString(a));
     const unsigned grid = persistent_grid(ncirc);
+    if (d.najobs > 0)
+        hipLaunchKernelGGL(k_batch_tile_params, dim3((d.najobs + 255) / 256), dim3(256), 0, s, d.ajobs, d.najobs,
+                           params, d.atiles);
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, s, d.queue);
     if (dtype == SV_C128)
-        hipLaunchKernelGGL(k_batched_adjoint<double>, dim3(grid), dim3(kBatchThreads), 0, s, d.circs, d.order, ncirc,
-                           d.gates, params, d.terms, d.gens, d.gen_of, grad, loss, d.queue);
+        hipLaunchKernelGGL(k_batched_adjoint<double>, dim3(grid), dim3(kBatchThreads), lds, s, d.circs, d.order, ncirc,
+                           d.gates, d.apasses, d.atiles, d.atslot, d.slot_param, params, d.terms, d.gens, d.gen_of,
+                           grad, loss, d.queue);
     else
-        hipLaunchKernelGGL(k_batched_adjoint<float>, dim3(grid), dim3(kBatchThreads), 0, s, d.circs, d.order, ncirc,
-                           d.gates, params, d.terms, d.gens, d.gen_of, grad, loss, d.queue);
+        hipLaunchKernelGGL(k_batched_adjoint<float>, dim3(grid), dim3(kBatchThreads), lds, s, d.circs, d.order, ncirc,
+                           d.gates, d.apasses, d.atiles, d.atslot, d.slot_param, params, d.terms, d.gens, d.gen_of,
+                           grad, loss, d.queue);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess)
         return fail(SV_EHIP, "batched adjoint launch failed: %s", hipGetErrorString(e));
