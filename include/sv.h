@@ -202,8 +202,12 @@ typedef struct sv_gate {
 } sv_gate_t;
 
 /* Circuit flags. */
-#define SV_FUSE 1    /* fuse runs of gates with target below the LDS tile
-                        width into one LDS-resident pass per tile */
+#define SV_FUSE 1    /* fuse runs of gates into one pass over LDS tiles: a
+                        tile spans the lowest qubits plus qubits the planner
+                        picks per run (gate fusion, the future work of
+                        Sec. V); diagonal gates join a run whatever their
+                        target; gates are moved only past gates they commute
+                        with */
 #define SV_GRAPH 2   /* capture the launch sequence once as a HIP graph and
                         replay it (per state and parameter pointer pair) */
 #define SV_MASKED 4  /* every gate on the masked baseline kernel, no fusion */

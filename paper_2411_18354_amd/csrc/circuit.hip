@@ -116,12 +116,12 @@ static int plan_circuit(sv_circuit *c, std::vector<TileGate> &tiles, std::vector
     c->m = std::min(std::min(tuning().tile_log2[di], c->n), c->m_cap);
     const int m = c->m;
     // the tile holds the a lowest qubits plus at most kTileMaxHigh others
-    const int a = c->general_tiles ? std::max(std::min(tuning().tile_low_bits[di], m), m - kTileMaxHigh) : m;
+    const int a = std::max(std::min(tuning().tile_low_bits[di], m), m - kTileMaxHigh);
     const int min_run = std::max(1, tuning().fuse_min_gates);
     std::vector<int> tile_slot(G, -1);
     std::vector<char> diag(G, 0);
     for (int i = 0; i < G; ++i)
-        diag[i] = c->general_tiles && c->diag_any && gate_is_diagonal(c->gates[i], &mats[(size_t)8 * i]);
+        diag[i] = gate_is_diagonal(c->gates[i], &mats[(size_t)8 * i]);
 
     auto single = [&](int i) -> int {
         Pass p;
@@ -503,9 +503,8 @@ static int run_graph(sv_circuit *c, const sv_state_t *s, const double *params, h
     return SV_OK;
 }
 
-int circuit_plan_capped(int n, int dtype, const sv_gate_t *gates, int ngates, int nparams, int flags, int m_cap,
-                        int32_t *order, int32_t *pass_of, int64_t *npasses, int *m_used, bool general,
-                        bool diag_any, std::vector<uint64_t> *pass_S);
+static int circuit_plan_order(int n, int dtype, const sv_gate_t *gates, int ngates, int nparams, int flags,
+                              int32_t *order, int32_t *pass_of, int64_t *npasses);
 
 } // namespace sv
 
@@ -526,8 +525,7 @@ int sv_gate_matrix(int kind, double theta, const double *U, double *out) {
 int sv_circuit_plan(int n, int dtype, const sv_gate_t *gates, int ngates, int nparams, int flags, int32_t *order,
                     int32_t *pass_of, int64_t *npasses) {
     clear_error();
-    return circuit_plan_capped(n, dtype, gates, ngates, nparams, flags, 64, order, pass_of, npasses, nullptr, true,
-                               true, nullptr);
+    return circuit_plan_order(n, dtype, gates, ngates, nparams, flags, order, pass_of, npasses);
 }
 
 } // extern "C"
@@ -574,9 +572,9 @@ int circuit_plan_tiles(int n, int dtype, const sv_gate_t *gates, int ngates, int
     return SV_OK;
 }
 
-int circuit_plan_capped(int n, int dtype, const sv_gate_t *gates, int ngates, int nparams, int flags, int m_cap,
-                        int32_t *order, int32_t *pass_of, int64_t *npasses, int *m_used, bool general,
-                        bool diag_any, std::vector<uint64_t> *pass_S) {
+// The planned order of a circuit's gates and the pass of each (host dry run).
+static int circuit_plan_order(int n, int dtype, const sv_gate_t *gates, int ngates, int nparams, int flags,
+                              int32_t *order, int32_t *pass_of, int64_t *npasses) {
     if (dtype != SV_C128 && dtype != SV_C64)
         return fail(SV_EINVAL, "unknown dtype %d", dtype);
     if (n < 1 || n > max_qubits(dtype))
@@ -592,9 +590,6 @@ int circuit_plan_capped(int n, int dtype, const sv_gate_t *gates, int ngates, in
     c.dtype = dtype;
     c.flags = flags;
     c.nparams = nparams;
-    c.m_cap = m_cap;
-    c.general_tiles = general;
-    c.diag_any = diag_any;
     c.gates.assign(gates, gates + ngates);
     std::vector<TileGate> tiles;
     std::vector<ParamJob> jobs;
@@ -603,8 +598,6 @@ int circuit_plan_capped(int n, int dtype, const sv_gate_t *gates, int ngates, in
     int dense_runs = 0;
     SV_TRY(plan_circuit(&c, tiles, jobs, mats, dense_list, dense_runs));
     int k = 0;
-    if (pass_S)
-        pass_S->assign(c.passes.size(), 0);
     for (size_t pi = 0; pi < c.passes.size(); ++pi) {
         const Pass &p = c.passes[pi];
         if (p.dense) {
@@ -622,12 +615,6 @@ int circuit_plan_capped(int n, int dtype, const sv_gate_t *gates, int ngates, in
                 pass_of[k] = (int32_t)pi;
             ++k;
         } else {
-            if (pass_S) {
-                uint64_t S = (p.tm.a >= 64) ? ~0ull : ((1ull << p.tm.a) - 1);
-                for (uint32_t h = 0; h < p.tm.nh; ++h)
-                    S |= 1ull << p.tm.hpos[h];
-                (*pass_S)[pi] = S;
-            }
             for (int j = 0; j < p.count; ++j) {
                 if (order)
                     order[k] = tiles[p.first + j].src_gate;
@@ -639,8 +626,6 @@ int circuit_plan_capped(int n, int dtype, const sv_gate_t *gates, int ngates, in
     }
     if (npasses)
         *npasses = (int64_t)c.passes.size();
-    if (m_used)
-        *m_used = c.m;
     return SV_OK;
 }
 

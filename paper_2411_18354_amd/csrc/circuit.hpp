@@ -27,8 +27,6 @@ struct sv_circuit {
     // (the C ABI's opaque sv_circuit_t)
     int n = 0, dtype = 0, flags = 0, nparams = 0, device = 0, m = 0;
     int m_cap = 64;  // upper bound on the tile width (callers with a fixed LDS budget)
-    bool general_tiles = true;  // tiles over any qubit set; false: contiguous tiles only
-    bool diag_any = true;       // diagonal gates join runs whatever their target
     std::vector<sv_gate_t> gates;
     std::vector<sv::Pass> passes;
     std::vector<int32_t> tile_src;  // gate index of every fused-run descriptor
