@@ -249,3 +249,41 @@ def test_batch_with_empty_circuits(gpu):
     for c, p, v in zip(circs, psis, views):
         ref = oracle.run_circuit(c, None, p) if c.gates else p
         assert _err(v.cpu().numpy(), ref) <= 1e-12, (c.n, len(c.gates))
+
+
+def test_batch_mixed_operations_forward_and_gradients(gpu):
+    """A batch of circuits mixing controlled gates, diagonal-heavy blocks and
+    parameterised rotations (n = 8..15): forward states and, through a
+    planned batch, gradients against the oracle."""
+    import torch
+    from tests.test_circuit_gpu import _mixed_circuit
+    circs, hams = [], []
+    for i in range(8):
+        n = 8 + i
+        circs.append(_mixed_circuit(n, 70 + i))
+        hams.append(W.zz_x_hamiltonian(n, 80 + i))
+    buf, views = _packed_states([c.n for c in circs], "c128")
+    init = buf.clone()
+    lbuf = torch.empty_like(buf)
+    lviews, off = [], 0
+    for c in circs:
+        lviews.append(lbuf[off:off + (1 << c.n)]); off += 1 << c.n
+    params = torch.from_numpy(np.concatenate([c.params for c in circs])).cuda()
+    b = gpu.Batch(views, circs, lam_states=lviews, hamiltonians=hams)
+    try:
+        b.run(params)
+        for c, v in zip(circs, views):
+            assert _err(v.cpu().numpy(), oracle.run_circuit(c, c.params)) <= 1e-12, c.n
+        grad, loss = b.adjoint(params)
+        g = grad.cpu().numpy()
+        off = 0
+        rng = np.random.default_rng(5)
+        for i, (c, h) in enumerate(zip(circs, hams)):
+            which = sorted(rng.choice(c.nparams, size=4, replace=False).tolist())
+            ref = oracle.grad_param_shift(c, c.params, h, which=which)
+            got = g[off + np.array(which)]
+            off += c.nparams
+            assert np.max(np.abs(got - ref)) <= 1e-8 * max(1, np.max(np.abs(ref))), (i, got, ref)
+            assert abs(loss[i].item() - oracle.loss(c, c.params, h)) <= 1e-10
+    finally:
+        b.close()

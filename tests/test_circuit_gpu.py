@@ -332,3 +332,57 @@ def test_empty_circuit(gpu):
         plan.run(d)
         plan.close()
         assert torch.equal(d.cpu(), torch.from_numpy(psi)), flags
+
+
+def _mixed_circuit(n, seed):
+    """Random controlled gates, diagonal-heavy blocks and parameterised
+    rotations interleaved (draw order fixed by the seed)."""
+    rng = np.random.default_rng(seed)
+    gates, p = [], 0
+    for block in range(4):
+        gates += W.random_gates_n12(seed=seed * 10 + block, n=n, ngates=40).gates
+        gates += _diag_heavy(n, seed * 10 + block, blocks=1, per_block=int(rng.integers(4, 16))).gates
+        for _ in range(6):
+            t = int(rng.integers(0, n))
+            c = [q for q in range(n) if q != t]
+            kind = ("RY", "RZ", "RX", "P")[int(rng.integers(0, 4))]
+            # controls on RY/RZ only: the oracle's shift rule covers those
+            ctrls = (int(rng.choice(c)),) if kind in ("RY", "RZ") and rng.random() < 0.5 else ()
+            gates.append(W.Gate(kind, t, ctrls, (), param=p))
+            p += 1
+    return W.Circuit(n, gates, rng.uniform(0, 2 * np.pi, size=p), meta={"seed": seed})
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_fused_random_configurations(gpu, seed):
+    """Random tile widths and low-block sizes on circuits mixing every
+    operation kind, fused (with device angles) against the oracle, complex128
+    and complex64."""
+    import torch
+    rng = np.random.default_rng(1000 + seed)
+    n = int(rng.integers(10, 17))
+    c = _mixed_circuit(n, seed)
+    keys = ("tile_log2_c128", "tile_log2_c64", "tile_low_bits_c128", "tile_low_bits_c64")
+    old = {k: gpu.sv_tune_get(k) for k in keys}
+    try:
+        w = int(rng.integers(7, 13))
+        low = int(rng.integers(1, 7))
+        gpu.sv_tune_set("tile_log2_c128", w)
+        gpu.sv_tune_set("tile_log2_c64", w + 1)
+        gpu.sv_tune_set("tile_low_bits_c128", low)
+        gpu.sv_tune_set("tile_low_bits_c64", low)
+        psi0 = W.random_state(n, seed)
+        ref = oracle.run_circuit(c, c.params, psi0)
+        params = torch.from_numpy(c.params).cuda()
+        for dtype, tol in ((0, 1e-12), (1, 1e-5)):
+            d = torch.from_numpy(psi0).cuda()
+            if dtype == 1:
+                d = d.to(torch.complex64)
+            plan = gpu.Circuit(n, c, dtype=dtype, nparams=c.nparams, flags=gpu.SV_FUSE)
+            plan.run(d, params)
+            plan.close()
+            e = float(np.max(np.abs(d.cpu().numpy().astype(np.complex128) - ref)))
+            assert e <= tol, (seed, n, w, low, dtype, e)
+    finally:
+        for k, v in old.items():
+            gpu.sv_tune_set(k, v)
