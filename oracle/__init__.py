@@ -63,6 +63,8 @@ def lib():
         L.or_basis.restype = None
         L.or_apply_block_low.argtypes = [dp, ctypes.c_int, ctypes.c_int, dp]
         L.or_apply_block_low.restype = None
+        L.or_swap_qubits.argtypes = [dp, ctypes.c_int, ctypes.c_int, ctypes.c_int]
+        L.or_swap_qubits.restype = None
         L.or_num_threads.argtypes = []
         L.or_num_threads.restype = ctypes.c_int
         _lib = L
@@ -201,6 +203,15 @@ def apply_block_low(psi: np.ndarray, n: int, k: int, M: np.ndarray) -> np.ndarra
     m = np.ascontiguousarray(np.asarray(M, dtype=np.complex128).reshape(1 << k, 1 << k))
     buf = np.ascontiguousarray(np.stack([m.real, m.imag], axis=-1).reshape(-1))
     lib().or_apply_block_low(_dptr(psi.view(np.float64)), n, k, _dptr(buf))
+    return psi
+
+
+def swap_qubits(psi: np.ndarray, n: int, pairs) -> np.ndarray:
+    """In place: exchange the qubits of every pair (a, b), one pair after
+    the other (a relabelling of index bits; no arithmetic)."""
+    assert psi.size == (1 << n)
+    for a, b in pairs:
+        lib().or_swap_qubits(_dptr(psi.view(np.float64)), n, int(a), int(b))
     return psi
 
 

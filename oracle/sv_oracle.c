@@ -244,3 +244,24 @@ void or_apply_block_low(double *psi, int n, int k, const double *M)
             row[a] = tmp[a];
     }
 }
+
+/* Exchange qubits a and b: the amplitude at index k moves to the index with
+ * bits a and b of k exchanged.  Plain loop over every k, swapping each pair
+ * {k, k'} once from its smaller index. */
+void or_swap_qubits(double *psi, int n, int a, int b)
+{
+    const uint64_t N = (uint64_t)1 << n;
+    for (uint64_t k = 0; k < N; ++k) {
+        const uint64_t ba = (k >> a) & 1u, bb = (k >> b) & 1u;
+        if (ba == bb)
+            continue;
+        const uint64_t k2 = k ^ (((uint64_t)1 << a) | ((uint64_t)1 << b));
+        if (k2 < k)
+            continue;
+        const double r = psi[2 * k], i = psi[2 * k + 1];
+        psi[2 * k] = psi[2 * k2];
+        psi[2 * k + 1] = psi[2 * k2 + 1];
+        psi[2 * k2] = r;
+        psi[2 * k2 + 1] = i;
+    }
+}

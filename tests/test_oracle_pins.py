@@ -400,3 +400,28 @@ def test_block_low_matches_kron_and_gate_sequence():
         for g in gates:
             oracle.apply_gate(b, n, g.target, g.controls, g.values, oracle.gate_matrix(g.kind, g.theta))
         assert np.max(np.abs(a - b)) < 1e-13
+
+
+def test_swap_qubits_matches_axis_transpose_and_three_cnots():
+    """Exchanging qubits a and b equals swapping those two axes of the state
+    seen as an n-axis tensor (numpy, no index loops), and equals three CNOTs
+    (a->b, b->a, a->b) applied through the oracle's gate loop."""
+    n = 6
+    for a, b in ((0, 1), (0, 5), (2, 4), (5, 3)):
+        psi = W.random_state(n, 10 + a * 7 + b)
+        got = oracle.swap_qubits(psi.copy(), n, [(a, b)])
+        # axis q of the C-order tensor is qubit n-1-q
+        t = psi.reshape((2,) * n)
+        ref = np.swapaxes(t, n - 1 - a, n - 1 - b).reshape(-1)
+        assert np.array_equal(got, ref), (a, b)
+        X = oracle.gate_matrix("X")
+        cn = psi.copy()
+        for c, t_ in ((a, b), (b, a), (a, b)):
+            oracle.apply_gate(cn, n, t_, (c,), (), X)
+        assert np.array_equal(cn, ref), (a, b)
+    # several disjoint pairs in one call compose
+    psi = W.random_state(n, 3)
+    got = oracle.swap_qubits(psi.copy(), n, [(0, 4), (1, 5)])
+    t = psi.reshape((2,) * n)
+    ref = np.swapaxes(np.swapaxes(t, n - 1, n - 5), n - 2, n - 6).reshape(-1)
+    assert np.array_equal(got, ref)
