@@ -400,6 +400,23 @@ def measure_extras(sv, W, torch, np, stream, with_layered):
             out["%s_%s" % (name, dt)] = row
             del st
             torch.cuda.empty_cache()
+    # ---- qubit remapping: controls on the lowest qubits moved to high bits
+    log("low-control circuit n=28 c128, with and without SV_REMAP")
+    lc = W.low_control_circuit(n=28, ngates=24)
+    st = torch.empty(1 << 28, dtype=torch.complex128, device=dev)
+    row = {"gates": len(lc.gates)}
+    for label, fl in (("scheduled", 0), ("scheduled_remap", sv.SV_REMAP)):
+        p = sv.Circuit(28, lc, flags=fl)
+        row[label + "_passes"] = p.info()["passes"]
+
+        def run():
+            sv.sv_init(st, 0, stream=stream)
+            p.run(st, stream=stream)
+        row[label + "_ms"] = round(_time_ms(torch, stream, run, 3), 3)
+        p.close()
+    out["low_control_n28"] = row
+    del st
+    torch.cuda.empty_cache()
     if with_layered:
         log("layered circuit: n=32 complex128")
         c2 = W.layered_circuit_n32()

@@ -211,6 +211,12 @@ typedef struct sv_gate {
 #define SV_GRAPH 2   /* capture the launch sequence once as a HIP graph and
                         replay it (per state and parameter pointer pair) */
 #define SV_MASKED 4  /* every gate on the masked baseline kernel, no fusion */
+#define SV_REMAP 16  /* move low qubits that control many gates (below the
+                        cache-line granule, where their skips save no DRAM
+                        traffic) to high bit positions: one qubit-exchange
+                        pass before the circuit and one after (Sec. V names
+                        layout remapping as future work); results are the
+                        same, the state is back in the caller's layout */
 #define SV_DENSE 8   /* with SV_FUSE: stretches of at least "dense_min_gates"
                         gates acting only on the "dense_qubits" lowest qubits
                         become one dense block applied with matrix cores
@@ -261,6 +267,14 @@ int sv_circuit_destroy(sv_circuit_t *c);
  * Runs as a real-embedded GEMM on MFMA.  k = 4 for complex128, 4 or 5 for
  * complex64, n >= k + 6; SV_ENOTSUP otherwise. */
 int sv_apply_dense_low(const sv_state_t *s, int k, const double *M, sv_stream_t st);
+
+/* Exchange qubits: for each of the npairs disjoint pairs (pairs[2i],
+ * pairs[2i+1]) the amplitude at index k moves to the index with those two
+ * bits of k exchanged, all pairs at once (a relabelling of index bits, no
+ * arithmetic; the basis for moving qubits between bit positions, the layout
+ * remapping named as future work in Sec. V).  Every qubit in [0, n) at most
+ * once, npairs <= 32.  One read and one write of every moved amplitude. */
+int sv_swap_qubits(const sv_state_t *s, const int32_t *pairs, int npairs, sv_stream_t st);
 
 /* One-shot: create, run on st, destroy.  SV_GRAPH is ignored here. */
 int sv_apply_circuit(const sv_state_t *s, const sv_gate_t *gates, int ngates, const double *params_dev,

@@ -256,7 +256,7 @@ def sv_copy_state(dst, src, stream=None) -> None:
 
 SV_G_MATRIX, SV_G_X, SV_G_Y, SV_G_Z, SV_G_H, SV_G_RX, SV_G_RY, SV_G_RZ, SV_G_P = range(9)
 SV_G_ADJOINT = 0x100
-SV_FUSE, SV_GRAPH, SV_MASKED, SV_DENSE = 1, 2, 4, 8
+SV_FUSE, SV_GRAPH, SV_MASKED, SV_DENSE, SV_REMAP = 1, 2, 4, 8, 16
 KIND_CODES = {"U": SV_G_MATRIX, "X": SV_G_X, "Y": SV_G_Y, "Z": SV_G_Z, "H": SV_G_H,
               "RX": SV_G_RX, "RY": SV_G_RY, "RZ": SV_G_RZ, "P": SV_G_P}
 
@@ -408,6 +408,17 @@ def sv_circuit_plan(n: int, gates, dtype: int = SV_C128, nparams: int = 0, flags
     _check(_L.sv_circuit_plan(int(n), int(dtype), arr, count, int(nparams), int(flags), order, pas,
                               ctypes.byref(npas)))
     return list(order)[:count], list(pas)[:count], int(npas.value)
+
+
+_sig("sv_swap_qubits", [_sp, ctypes.POINTER(ctypes.c_int32), ctypes.c_int, _vp])
+
+
+def sv_swap_qubits(state, pairs, stream=None) -> None:
+    """Exchange the qubits of each (a, b) in pairs (disjoint pairs)."""
+    s = state_view(state)
+    flat = [int(q) for p in pairs for q in p]
+    arr = (ctypes.c_int32 * max(1, len(flat)))(*flat)
+    _check(_L.sv_swap_qubits(ctypes.byref(s), arr, len(pairs), stream_ptr(stream)))
 
 
 _sig("sv_apply_dense_low", [_sp, ctypes.c_int, _dp, _vp])

@@ -101,6 +101,54 @@ static bool gate_is_diagonal(const sv_gate_t &g, const double *mat) {
 // join the run ahead of the deferred ones only if they commute with all of
 // them.  When the run closes, the deferred gates start the next run, so the
 // relative order of non-commuting gates is never changed.
+// SV_REMAP: choose disjoint swaps (q, h) of a low qubit q, below the
+// cache-line granule (where a scheduled skip saves no DRAM traffic, so its
+// controls are tested instead), with a high qubit h, and relabel the gates.
+// A control on q then sits on a high bit, where each control halves the
+// traffic of an unfused gate.  The swaps cost two passes over the state
+// (into the new layout and back), so a pair is taken when q controls at
+// least four more gates than h.
+static void apply_remap(sv_circuit *c) {
+    const int n = c->n;
+    const int gran = tuning().granule_bits[c->dtype == SV_C128 ? 0 : 1];
+    std::vector<int> ctrl(n, 0);
+    for (const sv_gate_t &g : c->gates)
+        for (int q = 0; q < n; ++q)
+            ctrl[q] += (int)((g.ctrl_mask >> q) & 1ull);
+    std::vector<int> low, high;
+    for (int q = 0; q < std::min(gran, n); ++q)
+        low.push_back(q);
+    for (int q = n - 1; q >= gran; --q)
+        high.push_back(q);
+    std::stable_sort(low.begin(), low.end(), [&](int a, int b) { return ctrl[a] > ctrl[b]; });
+    std::stable_sort(high.begin(), high.end(), [&](int a, int b) { return ctrl[a] < ctrl[b]; });
+    std::vector<int> perm(n);
+    for (int q = 0; q < n; ++q)
+        perm[q] = q;
+    c->remap.clear();
+    for (size_t i = 0; i < low.size() && i < high.size() && (int)c->remap.size() / 2 < kMaxSwapPairs; ++i) {
+        const int q = low[i], h = high[i];
+        if (ctrl[q] - ctrl[h] < 4)
+            break;
+        c->remap.push_back(q);
+        c->remap.push_back(h);
+        std::swap(perm[q], perm[h]);
+    }
+    if (c->remap.empty())
+        return;
+    for (sv_gate_t &g : c->gates) {
+        g.target = perm[g.target];
+        uint64_t m = 0, v = 0;
+        for (int q = 0; q < n; ++q)
+            if ((g.ctrl_mask >> q) & 1ull) {
+                m |= 1ull << perm[q];
+                v |= ((g.ctrl_vals >> q) & 1ull) << perm[q];
+            }
+        g.ctrl_mask = m;
+        g.ctrl_vals = v;
+    }
+}
+
 static int plan_circuit(sv_circuit *c, std::vector<TileGate> &tiles, std::vector<ParamJob> &jobs,
                         std::vector<double> &mats, std::vector<DenseGate> &dense_list, int &dense_runs) {
     const int G = (int)c->gates.size();
@@ -364,7 +412,7 @@ int circuit_create(int n, int dtype, const sv_gate_t *gates, int ngates, int npa
         return fail(SV_EINVAL, "bad gate list (ngates %d, gates %p)", ngates, (const void *)gates);
     if (nparams < 0)
         return fail(SV_EINVAL, "nparams %d < 0", nparams);
-    if (flags & ~(SV_FUSE | SV_GRAPH | SV_MASKED | SV_DENSE))
+    if (flags & ~(SV_FUSE | SV_GRAPH | SV_MASKED | SV_DENSE | SV_REMAP))
         return fail(SV_EINVAL, "unknown flags 0x%x", flags);
     for (int i = 0; i < ngates; ++i)
         SV_TRY(validate_circuit_gate(n, nparams, gates[i], i));
@@ -377,6 +425,8 @@ int circuit_create(int n, int dtype, const sv_gate_t *gates, int ngates, int npa
     c->m_cap = m_cap;
     SV_HIP_TRY(hipGetDevice(&c->device));
     c->gates.assign(gates, gates + ngates);
+    if ((flags & SV_REMAP) && !(flags & SV_MASKED))
+        apply_remap(c.get());
     std::vector<TileGate> tiles;
     std::vector<ParamJob> jobs;
     std::vector<double> mats;
@@ -431,6 +481,8 @@ void circuit_free(sv_circuit *c, hipStream_t st) {
 
 template <typename R> static int enqueue(sv_circuit *c, cplx_t<R> *psi, const double *params, hipStream_t st) {
     SV_TRY(circuit_param_mats(c, params, st));
+    const int nsw = (int)(c->remap.size() / 2);
+    SV_TRY(launch_swap_qubits(c->dtype, psi, c->n, c->remap.data(), nsw, st));  // into the remapped layout
     const size_t lds = fused_lds(c->m, c->dtype);
     for (const Pass &p : c->passes) {
         if (p.dense) {
@@ -446,6 +498,8 @@ template <typename R> static int enqueue(sv_circuit *c, cplx_t<R> *psi, const do
             SV_TRY(launch_plan<R>(psi, p.plan, MatPtr<R>{c->d_mats + (size_t)8 * p.gate}, st));
         }
     }
+    // back to the caller's layout (the swaps are an involution)
+    SV_TRY(launch_swap_qubits(c->dtype, psi, c->n, c->remap.data(), nsw, st));
     return SV_OK;
 }
 
@@ -581,7 +635,7 @@ static int circuit_plan_order(int n, int dtype, const sv_gate_t *gates, int ngat
         return fail(SV_EINVAL, "n=%d outside [1, %d]", n, max_qubits(dtype));
     if (ngates < 0 || (ngates > 0 && !gates))
         return fail(SV_EINVAL, "bad gate list (ngates %d, gates %p)", ngates, (const void *)gates);
-    if (flags & ~(SV_FUSE | SV_GRAPH | SV_MASKED | SV_DENSE))
+    if (flags & ~(SV_FUSE | SV_GRAPH | SV_MASKED | SV_DENSE | SV_REMAP))
         return fail(SV_EINVAL, "unknown flags 0x%x", flags);
     for (int i = 0; i < ngates; ++i)
         SV_TRY(validate_circuit_gate(n, nparams, gates[i], i));
@@ -591,6 +645,8 @@ static int circuit_plan_order(int n, int dtype, const sv_gate_t *gates, int ngat
     c.flags = flags;
     c.nparams = nparams;
     c.gates.assign(gates, gates + ngates);
+    if ((flags & SV_REMAP) && !(flags & SV_MASKED))
+        apply_remap(&c);
     std::vector<TileGate> tiles;
     std::vector<ParamJob> jobs;
     std::vector<double> mats;
@@ -625,7 +681,7 @@ static int circuit_plan_order(int n, int dtype, const sv_gate_t *gates, int ngat
         }
     }
     if (npasses)
-        *npasses = (int64_t)c.passes.size();
+        *npasses = (int64_t)c.passes.size() + (c.remap.empty() ? 0 : 2);
     return SV_OK;
 }
 
@@ -666,7 +722,7 @@ int sv_circuit_info(const sv_circuit_t *c, int64_t *passes, int64_t *fused_gates
     if (!c)
         return fail(SV_EINVAL, "circuit is NULL");
     if (passes)
-        *passes = (int64_t)c->passes.size();
+        *passes = (int64_t)c->passes.size() + (c->remap.empty() ? 0 : 2);
     if (fused_gates)
         *fused_gates = c->fused_gates;
     if (fused_runs)

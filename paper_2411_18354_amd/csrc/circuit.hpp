@@ -27,7 +27,8 @@ struct sv_circuit {
     // (the C ABI's opaque sv_circuit_t)
     int n = 0, dtype = 0, flags = 0, nparams = 0, device = 0, m = 0;
     int m_cap = 64;  // upper bound on the tile width (callers with a fixed LDS budget)
-    std::vector<sv_gate_t> gates;
+    std::vector<sv_gate_t> gates;   // after the SV_REMAP relabelling, if any
+    std::vector<int32_t> remap;      // SV_REMAP: qubit swaps a0 b0 a1 b1 ... (empty: none)
     std::vector<sv::Pass> passes;
     std::vector<int32_t> tile_src;  // gate index of every fused-run descriptor
     int dense_k = 0;                // qubits of dense blocks
@@ -78,6 +79,11 @@ struct DenseGate {
     int32_t target, mat;  // mat: gate index into the circuit's matrix table
     uint64_t cmask, cvals;
 };
+// Disjoint qubit exchanges (permute.hip): pairs = a0 b0 a1 b1 ...
+constexpr int kMaxSwapPairs = 32;
+int check_swap_pairs(int n, const int32_t *pairs, int npairs);
+int launch_swap_qubits(int dtype, void *psi, int n, const int32_t *pairs, int npairs, hipStream_t st);
+
 bool dense_supported(int dtype, int kq, int n);
 int launch_dense(int dtype, void *psi, int n, int kq, const void *rmat, hipStream_t st);
 int launch_dense_compose(int dtype, const void *gates, int count, const double *mats, int kq, void *rmat,

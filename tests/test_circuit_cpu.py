@@ -175,3 +175,19 @@ def test_circuit_json_round_trip(tmp_path):
         psi_a = oracle.run_circuit(a, a.params)
         psi_b = oracle.run_circuit(b, b.params)
         assert np.array_equal(psi_a, psi_b)
+
+
+def test_remap_plan_host():
+    """SV_REMAP (host dry run): a circuit whose controls sit on the lowest
+    qubits gets the two qubit-exchange passes; one without such controls
+    does not; the execution order is that of the plan without remapping."""
+    import paper_2411_18354_amd as sv
+    c = W.low_control_circuit(n=20, ngates=30, seed=2)
+    o0, p0, n0 = sv.sv_circuit_plan(20, c, flags=0)
+    o1, p1, n1 = sv.sv_circuit_plan(20, c, flags=sv.SV_REMAP)
+    assert n1 == n0 + 2 and o0 == o1
+    plain = W.random_gates_n12(seed=3, n=20, ngates=30)
+    plain.gates = [g for g in plain.gates if not any(q < 3 for q in g.controls)]
+    _, _, a = sv.sv_circuit_plan(20, plain, flags=0)
+    _, _, b = sv.sv_circuit_plan(20, plain, flags=sv.SV_REMAP)
+    assert a == b

@@ -270,6 +270,27 @@ def uneven_batch(seed: int = 6, ncirc: int = 4096, nrange=(10, 20), grange=(100,
     return out
 
 
+def low_control_circuit(n: int = 28, ngates: int = 24, seed: int = 9) -> Circuit:
+    """Gates whose controls sit mostly on the lowest qubits (below the
+    128-byte granule of a complex128 state): per gate, kind uniform in
+    {X, H, RY}, target uniform in 3..n-1, one or two controls from {0, 1, 2}
+    and, with probability 1/2, one more control uniform among the other
+    qubits (value 1 throughout)."""
+    rng = np.random.default_rng(seed)
+    gates = []
+    for _ in range(ngates):
+        kind = ("X", "H", "RY")[int(rng.integers(0, 3))]
+        t = int(rng.integers(3, n))
+        k = int(rng.integers(1, 3))
+        ctrls = [int(q) for q in rng.choice(3, size=k, replace=False)]
+        if rng.random() < 0.5:
+            others = [q for q in range(3, n) if q != t]
+            ctrls.append(int(rng.choice(others)))
+        theta = float(rng.uniform(0, TWO_PI)) if kind == "RY" else 0.0
+        gates.append(Gate(kind, t, tuple(sorted(ctrls)), (), theta))
+    return Circuit(n, gates, meta={"name": "low_control", "seed": seed})
+
+
 def hea_batch_n16(seed: int = 7, ncirc: int = 256, n: int = 16, layers: int = 4):
     """Batched-gradient workload: the n=24 problem's ansatz at n=16 with 4 layers
     (128 parameters) per circuit, each circuit with its own angles and its own
