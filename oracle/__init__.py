@@ -31,7 +31,7 @@ def build(force: bool = True) -> str:
     """Compile sv_oracle.c with gcc into liboracle.so next to it."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", *CFLAGS, _SRC, "-o", tmp])
+        subprocess.check_call(["gcc", *CFLAGS, _SRC, "-o", tmp, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -65,6 +65,18 @@ def lib():
         L.or_apply_block_low.restype = None
         L.or_swap_qubits.argtypes = [dp, ctypes.c_int, ctypes.c_int, ctypes.c_int]
         L.or_swap_qubits.restype = None
+        i16p = ctypes.POINTER(ctypes.c_int16)
+        i8p = ctypes.POINTER(ctypes.c_int8)
+        L.or_q16_scale.argtypes = [ctypes.c_float]
+        L.or_q16_scale.restype = ctypes.c_int
+        L.or_q16_code.argtypes = [ctypes.c_float, ctypes.c_int]
+        L.or_q16_code.restype = ctypes.c_int16
+        L.or_q16_encode.argtypes = [dp, ctypes.c_int, i16p, i8p]
+        L.or_q16_encode.restype = None
+        L.or_q16_decode.argtypes = [i16p, i8p, ctypes.c_int, dp]
+        L.or_q16_decode.restype = None
+        L.or_q16_apply_gate.argtypes = [i16p, i8p, ctypes.c_int, ctypes.c_int, u64, u64, dp]
+        L.or_q16_apply_gate.restype = None
         L.or_num_threads.argtypes = []
         L.or_num_threads.restype = ctypes.c_int
         _lib = L
@@ -194,6 +206,92 @@ def run_circuit(circ, params: Optional[np.ndarray] = None, psi0: Optional[np.nda
         U = gate_matrix(g.kind, gate_angle(g, params), g.matrix)
         apply_gate(psi, n, g.target, g.controls, g.values, U)
     return psi
+
+
+# --------------------------------------------------------------------------
+# block-scaled 16-bit fixed-point states (format and arithmetic: the comment
+# above or_q16_scale in sv_oracle.c; the paper names fixed-point precision
+# as future work in its Conclusion)
+# --------------------------------------------------------------------------
+
+Q16_BLOCK = 64
+
+
+def q16_blocks(n: int) -> int:
+    """Number of scale blocks of an n-qubit fixed-point state."""
+    return max(1, (1 << n) // Q16_BLOCK)
+
+
+def q16_nbytes(n: int) -> int:
+    """Bytes of an n-qubit fixed-point state: 4 per amplitude, 1 per block."""
+    return (4 << n) + q16_blocks(n)
+
+
+def q16_views(buf: np.ndarray, n: int):
+    """(codes int16 [2^n, 2], scales int8 [blocks]) views of a state buffer."""
+    assert buf.dtype == np.uint8 and buf.size == q16_nbytes(n)
+    N = 1 << n
+    return buf[:4 * N].view(np.int16).reshape(N, 2), buf[4 * N:].view(np.int8)
+
+
+def _i16p(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int16))
+
+
+def _i8p(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int8))
+
+
+def q16_scale(m: float) -> int:
+    """Scale exponent of a block whose largest |component| is m (a float)."""
+    return int(lib().or_q16_scale(float(m)))
+
+
+def q16_code(v: float, s: int) -> int:
+    """Code of the float v under scale exponent s."""
+    return int(lib().or_q16_code(float(v), int(s)))
+
+
+def q16_encode(psi: np.ndarray, n: int) -> np.ndarray:
+    """Fixed-point state buffer (uint8) of a complex128 state."""
+    psi = np.ascontiguousarray(psi, dtype=np.complex128)
+    assert psi.size == (1 << n)
+    buf = np.zeros(q16_nbytes(n), dtype=np.uint8)
+    codes, scales = q16_views(buf, n)
+    lib().or_q16_encode(_dptr(psi.view(np.float64)), n, _i16p(codes), _i8p(scales))
+    return buf
+
+
+def q16_decode(buf: np.ndarray, n: int) -> np.ndarray:
+    """complex128 values of a fixed-point state buffer (exact)."""
+    codes, scales = q16_views(buf, n)
+    psi = np.empty(1 << n, dtype=np.complex128)
+    lib().or_q16_decode(_i16p(codes), _i8p(scales), n, _dptr(psi.view(np.float64)))
+    return psi
+
+
+def q16_apply_gate(buf: np.ndarray, n: int, target: int, controls: Sequence[int],
+                   values: Sequence[int], U: np.ndarray) -> np.ndarray:
+    """In place on a fixed-point state buffer: decode, pair update in float
+    on every pair whose controls hold, re-encode the blocks it touched."""
+    codes, scales = q16_views(buf, n)
+    cm, cv = masks(controls, values)
+    u = _u8(U)
+    lib().or_q16_apply_gate(_i16p(codes), _i8p(scales), n, int(target), cm, cv, _dptr(u))
+    return buf
+
+
+def q16_run_circuit(circ, params: Optional[np.ndarray] = None, buf0: Optional[np.ndarray] = None) -> np.ndarray:
+    """Every gate of the circuit in order on a fixed-point state (from |0>
+    encoded, or a copy of buf0)."""
+    n = circ.n
+    if params is None:
+        params = circ.params
+    buf = q16_encode(zero_state(n), n) if buf0 is None else np.array(buf0, dtype=np.uint8, copy=True)
+    for g in circ.gates:
+        U = gate_matrix(g.kind, gate_angle(g, params), g.matrix)
+        q16_apply_gate(buf, n, g.target, g.controls, g.values, U)
+    return buf
 
 
 def apply_block_low(psi: np.ndarray, n: int, k: int, M: np.ndarray) -> np.ndarray:

@@ -22,8 +22,10 @@
  *
  * U is passed as 8 doubles: a.re a.im b.re b.im c.re c.im d.re d.im.
  */
+#include <math.h>
 #include <stdint.h>
 #include <stddef.h>
+#include <stdlib.h>
 
 /* Complex product helpers with a fixed operation order. */
 static inline double mul_re(double ar, double ai, double xr, double xi)
@@ -264,4 +266,145 @@ void or_swap_qubits(double *psi, int n, int a, int b)
         psi[2 * k2] = r;
         psi[2 * k2 + 1] = i;
     }
+}
+
+/* ------------------------------------------------------------------------
+ * Block-scaled 16-bit fixed-point states.
+ *
+ * The paper names fixed-point arithmetic as future work (Conclusion) without
+ * a format.  The reading taken here: each component (re, im) of an amplitude
+ * is a signed 16-bit code q, and the 64 consecutive amplitudes of a block
+ * (all 2^n of them when n < 6) share one power-of-two scale s, so that a
+ * component's value is q * 2^s.  A single scale for the whole state could
+ * not hold both the largest and the typical amplitude of an n-qubit state
+ * (2^(-n/2) when spread evenly) in 16 bits.
+ *
+ * Storage: 2^n (re, im) int16 pairs, then one int8 scale per block.
+ *
+ * Encoding a block of floats: m = largest |component|; with
+ * m = f 2^e, f in [0.5, 1) (frexp), the scale is s = e - 15, clamped to
+ * [-126, 112] (s = -126 for m = 0); each code is the value times 2^-s
+ * rounded to nearest, ties to even, saturated to [-32767, 32767].  Codes of
+ * an encoded block therefore have their largest magnitude in
+ * [16384, 32767].
+ *
+ * A gate on a fixed-point state: decode every amplitude to float (exact),
+ * apply the pair update of Sec. III to each pair whose controls hold, in
+ * float with the fixed fused multiply-add order below, then re-encode every
+ * block that holds an amplitude of an updated pair.  Other blocks keep
+ * their codes and scale.
+ * ------------------------------------------------------------------------ */
+
+#define OR_Q16_BLOCK 64
+
+int or_q16_scale(float m)
+{
+    int e = 0;
+    if (m == 0.0f)
+        return -126;
+    (void)frexpf(m, &e);
+    int s = e - 15;
+    if (s < -126)
+        s = -126;
+    if (s > 112)
+        s = 112;
+    return s;
+}
+
+int16_t or_q16_code(float v, int s)
+{
+    float r = rintf(ldexpf(v, -s));
+    if (r > 32767.0f)
+        r = 32767.0f;
+    if (r < -32767.0f)
+        r = -32767.0f;
+    return (int16_t)r;
+}
+
+static void q16_encode_block(const float *v, int64_t len, int16_t *q, int8_t *s)
+{
+    float m = 0.0f;
+    for (int64_t i = 0; i < 2 * len; ++i) {
+        const float a = fabsf(v[i]);
+        if (a > m)
+            m = a;
+    }
+    const int sc = or_q16_scale(m);
+    for (int64_t i = 0; i < 2 * len; ++i)
+        q[i] = or_q16_code(v[i], sc);
+    *s = (int8_t)sc;
+}
+
+static int64_t q16_block_len(int n)
+{
+    const int64_t N = (int64_t)1 << n;
+    return N < OR_Q16_BLOCK ? N : OR_Q16_BLOCK;
+}
+
+/* Encode a complex128 state: each double is first rounded to float. */
+void or_q16_encode(const double *psi, int n, int16_t *q, int8_t *s)
+{
+    const int64_t N = (int64_t)1 << n, B = q16_block_len(n), nb = N / B;
+#pragma omp parallel for schedule(static)
+    for (int64_t b = 0; b < nb; ++b) {
+        float v[2 * OR_Q16_BLOCK];
+        for (int64_t i = 0; i < 2 * B; ++i)
+            v[i] = (float)psi[2 * b * B + i];
+        q16_encode_block(v, B, q + 2 * b * B, s + b);
+    }
+}
+
+void or_q16_decode(const int16_t *q, const int8_t *s, int n, double *psi)
+{
+    const int64_t N = (int64_t)1 << n, B = q16_block_len(n);
+    for (int64_t k = 0; k < N; ++k) {
+        const int sc = s[k / B];
+        psi[2 * k] = (double)ldexpf((float)q[2 * k], sc);
+        psi[2 * k + 1] = (double)ldexpf((float)q[2 * k + 1], sc);
+    }
+}
+
+/* u * x + v * y in float: one rounding chain per component, in this order:
+ *   re = u.re x.re - u.im x.im + v.re y.re - v.im y.im
+ *      evaluated as fma(u.re, x.re, fma(-u.im, x.im, fma(v.re, y.re, -(v.im y.im))))
+ *   im = fma(u.re, x.im, fma(u.im, x.re, fma(v.re, y.im, v.im y.re))) */
+static void q16_mac(const float *u, const float *v, float xr, float xi, float yr, float yi,
+                    float *outr, float *outi)
+{
+    *outr = fmaf(u[0], xr, fmaf(-u[1], xi, fmaf(v[0], yr, -(v[1] * yi))));
+    *outi = fmaf(u[0], xi, fmaf(u[1], xr, fmaf(v[0], yi, v[1] * yr)));
+}
+
+void or_q16_apply_gate(int16_t *q, int8_t *s, int n, int t, uint64_t cmask, uint64_t cvals,
+                       const double *U)
+{
+    const int64_t N = (int64_t)1 << n, B = q16_block_len(n), nb = N / B;
+    const int64_t st = (int64_t)1 << t;
+    float u[8];
+    for (int i = 0; i < 8; ++i)
+        u[i] = (float)U[i];
+    float *v = (float *)malloc(sizeof(float) * 2 * (size_t)N);
+    char *touched = (char *)calloc((size_t)nb, 1);
+    for (int64_t k = 0; k < N; ++k) {
+        const int sc = s[k / B];
+        v[2 * k] = ldexpf((float)q[2 * k], sc);
+        v[2 * k + 1] = ldexpf((float)q[2 * k + 1], sc);
+    }
+    for (int64_t k = 0; k < N; ++k) {
+        if (k & st)
+            continue;
+        if (((uint64_t)k & cmask) != cvals)
+            continue;
+        const int64_t k2 = k + st;
+        const float xr = v[2 * k], xi = v[2 * k + 1], yr = v[2 * k2], yi = v[2 * k2 + 1];
+        q16_mac(u, u + 2, xr, xi, yr, yi, &v[2 * k], &v[2 * k + 1]);
+        q16_mac(u + 4, u + 6, xr, xi, yr, yi, &v[2 * k2], &v[2 * k2 + 1]);
+        touched[k / B] = 1;
+        touched[k2 / B] = 1;
+    }
+    for (int64_t b = 0; b < nb; ++b)
+        if (touched[b])
+            q16_encode_block(v + 2 * b * B, B, q + 2 * b * B, s + b);
+    free(touched);
+    free(v);
 }

@@ -425,3 +425,172 @@ def test_swap_qubits_matches_axis_transpose_and_three_cnots():
     t = psi.reshape((2,) * n)
     ref = np.swapaxes(np.swapaxes(t, n - 1, n - 5), n - 2, n - 6).reshape(-1)
     assert np.array_equal(got, ref)
+
+
+# ---------------------------------------------------------------- fixed-point states
+#
+# Block-scaled 16-bit states: value = code * 2^scale, one scale per 64
+# amplitudes.  The pins below use only integers, closed forms and bounds that
+# any correct encoding must meet; none restates the scale formula.
+
+def _q16_random_buf(n, seed):
+    return oracle.q16_encode(_rand_state(n, seed), n)
+
+
+def test_q16_basis_and_hadamard_closed_forms():
+    n = 8
+    buf = oracle.q16_encode(oracle.zero_state(n), n)
+    codes, scales = oracle.q16_views(buf, n)
+    # 1.0 must be a code in [2^14, 2^15) times a power of two: 2^14 * 2^-14
+    assert tuple(codes[0]) == (16384, 0) and scales[0] == -14
+    assert not codes[1:].any()
+    # zero blocks take the smallest scale
+    assert (scales[1:] == -126).all()
+    # H on |0>: both amplitudes 1/sqrt(2) = 23170.47... * 2^-15
+    oracle.q16_apply_gate(buf, n, 0, [], [], np.array([[1, 1], [1, -1]]) / math.sqrt(2))
+    assert tuple(codes[0]) == (23170, 0) and tuple(codes[1]) == (23170, 0)
+    assert scales[0] == -15 and not codes[2:].any()
+    # a single block below 64 amplitudes (n < 6) has one scale
+    b3 = oracle.q16_encode(oracle.zero_state(3), 3)
+    assert b3.size == 4 * 8 + 1 and oracle.q16_views(b3, 3)[1][0] == -14
+
+
+def test_q16_exactly_representable_blocks_round_trip():
+    rng = np.random.default_rng(40)
+    n = 9
+    N, B = 1 << n, 64
+    codes = rng.integers(-32767, 32768, size=(N, 2)).astype(np.int64)
+    scales = rng.integers(-60, 0, size=N // B)
+    for b in range(N // B):  # put the block's largest magnitude in [2^14, 2^15)
+        blk = codes[b * B:(b + 1) * B]
+        big = int(rng.integers(16384, 32768))
+        blk[int(rng.integers(0, B)), int(rng.integers(0, 2))] = big * (1 if rng.random() < 0.5 else -1)
+        np.clip(blk, -big, big, out=blk)
+    vals = codes.astype(np.float64) * np.ldexp(1.0, np.repeat(scales, B))[:, None]
+    psi = vals[:, 0] + 1j * vals[:, 1]
+    buf = oracle.q16_encode(psi, n)
+    c2, s2 = oracle.q16_views(buf, n)
+    assert np.array_equal(c2, codes) and np.array_equal(s2, scales)
+    assert np.array_equal(oracle.q16_decode(buf, n), psi)
+    # encoding a decoded state reproduces it (random state)
+    b2 = _q16_random_buf(n, 41)
+    assert np.array_equal(oracle.q16_encode(oracle.q16_decode(b2, n), n), b2)
+
+
+def test_q16_encode_error_and_normalisation():
+    rng = np.random.default_rng(42)
+    n = 10
+    B = 64
+    psi = _rand_state(n, 43) * np.repeat(10.0 ** rng.uniform(-12, 0, size=(1 << n) // B), B)
+    psi[5 * B:6 * B] = 0  # a zero block
+    f = (psi.real.astype(np.float32).astype(np.float64) + 1j * psi.imag.astype(np.float32).astype(np.float64))
+    buf = oracle.q16_encode(psi, n)
+    codes, scales = oracle.q16_views(buf, n)
+    dec = oracle.q16_decode(buf, n)
+    for b in range(len(scales)):
+        blk = slice(b * B, (b + 1) * B)
+        m = max(np.abs(f[blk].real).max(), np.abs(f[blk].imag).max())
+        if m == 0:
+            assert not codes[blk].any()
+            continue
+        # largest code magnitude in [2^14, 2^15): 15 significant bits used
+        assert 16384 <= np.abs(codes[blk]).max() <= 32767
+        # rounding error at most half a step, and a step is at most m 2^-14
+        step = math.ldexp(1.0, int(scales[b]))
+        assert step <= m * 2.0 ** -14
+        err = max(np.abs(dec[blk].real - f[blk].real).max(), np.abs(dec[blk].imag - f[blk].imag).max())
+        assert err <= step / 2
+    # saturation: 1 - 2^-24 scales to 32767.99..., which rounds to 32768 and saturates
+    assert oracle.q16_code(np.float32(1 - 2.0 ** -24), oracle.q16_scale(np.float32(1 - 2.0 ** -24))) == 32767
+    # a block far below 2^-111 keeps the smallest scale, exactly
+    tiny = np.zeros(64, dtype=np.complex128)
+    tiny[3] = 2.0 ** -120
+    bt = oracle.q16_encode(tiny, 6)
+    ct, st = oracle.q16_views(bt, 6)
+    assert st[0] == -126 and ct[3, 0] == 64 and oracle.q16_decode(bt, 6)[3] == 2.0 ** -120
+
+
+def test_q16_permutation_and_sign_gates_are_exact():
+    n = 9
+    X = np.array([[0, 1], [1, 0]])
+    Z = np.diag([1, -1])
+    buf0 = _q16_random_buf(n, 44)
+    c0, s0 = oracle.q16_views(buf0, n)
+    # X on a high target swaps whole blocks, codes and scales
+    buf = buf0.copy()
+    oracle.q16_apply_gate(buf, n, 7, [], [], X)
+    c, s = oracle.q16_views(buf, n)
+    perm = np.arange(1 << n) ^ (1 << 7)
+    assert np.array_equal(c, c0[perm]) and np.array_equal(s, s0[np.arange(len(s0)) ^ 2])
+    # X on a low target permutes codes inside each block, scales unchanged
+    buf = buf0.copy()
+    oracle.q16_apply_gate(buf, n, 3, [], [], X)
+    c, s = oracle.q16_views(buf, n)
+    assert np.array_equal(c, c0[np.arange(1 << n) ^ 8]) and np.array_equal(s, s0)
+    # controlled on qubit 8: only blocks whose index has bit 2 set move
+    buf = buf0.copy()
+    oracle.q16_apply_gate(buf, n, 7, [8], [1], X)
+    k = np.arange(1 << n)
+    perm = np.where(k & 256, k ^ 128, k)
+    c, s = oracle.q16_views(buf, n)
+    assert np.array_equal(c, c0[perm])
+    bi = np.arange(len(s0))
+    assert np.array_equal(s, s0[np.where(bi & 4, bi ^ 2, bi)])
+    # Z negates the codes whose target bit is 1
+    buf = buf0.copy()
+    oracle.q16_apply_gate(buf, n, 2, [], [], Z)
+    c, s = oracle.q16_views(buf, n)
+    sign = np.where(k & 4, -1, 1)[:, None]
+    assert np.array_equal(c, c0 * sign) and np.array_equal(s, s0)
+
+
+@pytest.mark.parametrize("case", [(0, (), ()), (4, (1,), (0,)), (7, (2, 8), (1, 1)), (9, (0, 6), (1, 0)),
+                                  (2, (), ()), (5, (9,), (1,))])
+def test_q16_gate_within_quantisation_of_double(case):
+    n = 10
+    t, ctrls, vals = case
+    B = 64
+    U = _rand_unitary(45 + t)
+    buf = _q16_random_buf(n, 46 + t)
+    x = oracle.q16_decode(buf, n)
+    exact = oracle.apply_gate(x.copy(), n, t, ctrls, vals, U)
+    # the float matrix the arithmetic uses, applied exactly
+    U32 = U.real.astype(np.float32).astype(np.float64) + 1j * U.imag.astype(np.float32).astype(np.float64)
+    exact32 = oracle.apply_gate(x.copy(), n, t, ctrls, vals, U32)
+    out_buf = oracle.q16_apply_gate(buf.copy(), n, t, ctrls, vals, U)
+    out = oracle.q16_decode(out_buf, n)
+    cm, cv = oracle.masks(ctrls, vals)
+    k = np.arange(1 << n)
+    moved = ((k & cm) == cv)  # amplitudes of updated pairs
+    touched_blocks = np.unique(k[moved] // B)
+    for b in range(len(x) // B):
+        blk = slice(b * B, (b + 1) * B)
+        if b not in touched_blocks:
+            assert np.array_equal(out[blk], x[blk])  # untouched blocks keep their bytes
+            continue
+        m = max(np.abs(exact32[blk].real).max(), np.abs(exact32[blk].imag).max())
+        # half a quantisation step (<= m 2^-15) plus float rounding of the products
+        tol = m * 2.0 ** -15 * (1 + 1e-5) + 8 * 2.0 ** -24 * np.abs(x).max() * 2
+        err = max(np.abs(out[blk].real - exact32[blk].real).max(), np.abs(out[blk].imag - exact32[blk].imag).max())
+        assert err <= tol, (b, err, tol)
+    # and the float matrix differs from the double one by float rounding only
+    assert np.abs(exact32 - exact).max() <= 4 * 2.0 ** -24 * np.abs(x).max() * 2
+
+
+def test_q16_qft_within_rigorous_bound():
+    n = 10
+    circ = W.qft(n)
+    psi0 = _rand_state(n, 47)
+    buf = oracle.q16_run_circuit(circ, buf0=oracle.q16_encode(psi0, n))
+    # closed form of the QFT as drawn (no swaps, + sign): ifft of the
+    # bit-reversed input times sqrt(N)
+    N = 1 << n
+    rev = np.array([int(format(i, "0%db" % n)[::-1], 2) for i in range(N)])
+    want = np.fft.ifft(psi0[rev]) * math.sqrt(N)
+    err = np.linalg.norm(oracle.q16_decode(buf, n) - want)
+    # each gate adds at most sqrt(2 * 64) * 2^-15 (half steps over the
+    # re-encoded blocks, norm 1) plus float rounding; unitaries keep errors'
+    # norms, and the initial encoding adds one more such term
+    G = len(circ.gates)
+    assert err <= (G + 1) * (math.sqrt(128) * 2.0 ** -15 + 1e-6)
+    assert err < 5e-3  # far inside the bound in practice
