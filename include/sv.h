@@ -49,14 +49,28 @@ typedef enum sv_status {
     SV_ENOTSUP = -4  /* valid request the library does not handle */
 } sv_status;
 
-typedef enum sv_dtype { SV_C128 = 0, SV_C64 = 1 } sv_dtype;
+/* SV_CQ16: block-scaled 16-bit fixed-point complex, the fixed-point state
+ * precision the paper lists as future work (Sec. V).  Layout: 2^n
+ * amplitudes of two int16 codes (re, im; 4 bytes each), followed by one int8
+ * scale per block of 64 consecutive amplitudes (a single block of all 2^n
+ * when n < 6); a component's value is code * 2^scale.  Encoding a block
+ * takes m, its largest |component|, writes m = f 2^e with f in [0.5, 1),
+ * uses the scale e - 15 (clamped to [-126, 112]; -126 for an all-zero block)
+ * and rounds each value / 2^scale to the nearest code, ties to even,
+ * saturated to [-32767, 32767].  Storage is sv_state_bytes(n, SV_CQ16) bytes,
+ * 16-byte aligned.  Fixed-point states are taken by sv_alloc, sv_free,
+ * sv_init, sv_copy_state, sv_convert, sv_apply_gate(_masks), sv_gate_plan,
+ * and circuits without SV_FUSE, SV_DENSE or SV_REMAP; every other call
+ * returns SV_ENOTSUP for them. */
+typedef enum sv_dtype { SV_C128 = 0, SV_C64 = 1, SV_CQ16 = 2 } sv_dtype;
 
 /* Largest supported register: 2^34 complex128 amplitudes is 256 GiB. */
 #define SV_MAX_QUBITS_C128 34
 #define SV_MAX_QUBITS_C64 35
+#define SV_MAX_QUBITS_CQ16 36
 
 typedef struct sv_state {
-    void *data;    /* device pointer to 2^n amplitudes, caller-owned */
+    void *data;    /* device pointer to the state's storage, caller-owned */
     int32_t n;     /* number of qubits, 1 <= n <= SV_MAX_QUBITS_* */
     int32_t dtype; /* sv_dtype */
 } sv_state_t;
@@ -83,6 +97,19 @@ int sv_init(const sv_state_t *s, uint64_t basis_index, sv_stream_t st);
  * device buffers; a state copied onto itself is a no-op). */
 int sv_copy_state(const sv_state_t *dst, const sv_state_t *src, sv_stream_t st);
 
+/* Bytes of storage of an n-qubit state of the given dtype: 2^n * 16
+ * (complex128), 2^n * 8 (complex64), 2^n * 4 + max(1, 2^n / 64) (SV_CQ16).
+ * Host-only. */
+int sv_state_bytes(int n, int dtype, uint64_t *bytes);
+
+/* Convert src into dst, two states of the same n and any dtypes, in
+ * non-overlapping buffers (same dtype: a copy).  complex128 -> complex64
+ * rounds each component to nearest; to SV_CQ16, each component is first
+ * rounded to float and every block is encoded as described at SV_CQ16; from
+ * SV_CQ16 the decoded values code * 2^scale are exact in either float
+ * type. */
+int sv_convert(const sv_state_t *dst, const sv_state_t *src, sv_stream_t st);
+
 /* Kernel selection for sv_apply_gate. */
 typedef enum sv_mode {
     SV_MODE_AUTO = 0,   /* scheduled enumeration, kernel chosen from the target */
@@ -108,7 +135,15 @@ typedef enum sv_mode {
  *   U           8 doubles, host memory (converted to float for complex64)
  *   mode        sv_mode; every mode gives the same result
  * Scheduled modes launch 2^(n-1-ncontrols) pair updates; SV_MODE_MASKED
- * launches 2^(n-1) and skips the pairs whose controls fail. */
+ * launches 2^(n-1) and skips the pairs whose controls fail.
+ * SV_CQ16 states: the 64-amplitude block is the unit of work.  Controls on
+ * qubits >= 6 are scheduled over the block index (2^(n-7-c_high) block pairs
+ * for a target >= 6, 2^(n-6-c_high) blocks below), controls on qubits < 6
+ * are tested per amplitude; SV_MODE_MASKED visits every block (pair) and
+ * tests every control, every other mode is the scheduled kernel.  Each
+ * visited block is decoded to float, updated with the float matrix
+ * (U rounded to float), and re-encoded as described at SV_CQ16; other blocks
+ * keep their bytes. */
 int sv_apply_gate(const sv_state_t *s, int target, const int32_t *controls,
                   int ncontrols, uint64_t ctrl_vals, const double *U, int mode,
                   sv_stream_t st);
@@ -214,9 +249,8 @@ typedef struct sv_gate {
 #define SV_REMAP 16  /* move low qubits that control many gates (below the
                         cache-line granule, where their skips save no DRAM
                         traffic) to high bit positions: one qubit-exchange
-                        pass before the circuit and one after (Sec. V names
-                        layout remapping as future work); results are the
-                        same, the state is back in the caller's layout */
+                        pass before the circuit and one after; results are
+                        the same, the state is back in the caller's layout */
 #define SV_DENSE 8   /* with SV_FUSE: stretches of at least "dense_min_gates"
                         gates acting only on the "dense_qubits" lowest qubits
                         become one dense block applied with matrix cores
@@ -234,7 +268,9 @@ typedef struct sv_circuit sv_circuit_t;
  * sv_circuit_run (every gate's param must be < nparams).  Validation covers
  * every gate before anything is allocated, so an error names the first bad
  * gate (its index is in the message) and creates nothing.  The returned
- * handle is released with sv_circuit_destroy. */
+ * handle is released with sv_circuit_destroy.  SV_CQ16 circuits run one
+ * block-scaled gate kernel per gate: flags may hold SV_GRAPH and SV_MASKED
+ * only (SV_ENOTSUP otherwise). */
 int sv_circuit_create(int n, int dtype, const sv_gate_t *gates, int ngates, int nparams, int flags,
                       sv_circuit_t **out);
 
@@ -271,8 +307,8 @@ int sv_apply_dense_low(const sv_state_t *s, int k, const double *M, sv_stream_t 
 /* Exchange qubits: for each of the npairs disjoint pairs (pairs[2i],
  * pairs[2i+1]) the amplitude at index k moves to the index with those two
  * bits of k exchanged, all pairs at once (a relabelling of index bits, no
- * arithmetic; the basis for moving qubits between bit positions, the layout
- * remapping named as future work in Sec. V).  Every qubit in [0, n) at most
+ * arithmetic; the basis for moving qubits between bit positions, as
+ * SV_REMAP does).  Every qubit in [0, n) at most
  * once, npairs <= 32.  One read and one write of every moved amplitude. */
 int sv_swap_qubits(const sv_state_t *s, const int32_t *pairs, int npairs, sv_stream_t st);
 

@@ -211,7 +211,7 @@ def run_circuit(circ, params: Optional[np.ndarray] = None, psi0: Optional[np.nda
 # --------------------------------------------------------------------------
 # block-scaled 16-bit fixed-point states (format and arithmetic: the comment
 # above or_q16_scale in sv_oracle.c; the paper names fixed-point precision
-# as future work in its Conclusion)
+# as future work in Sec. V)
 # --------------------------------------------------------------------------
 
 Q16_BLOCK = 64

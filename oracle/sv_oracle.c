@@ -271,7 +271,7 @@ void or_swap_qubits(double *psi, int n, int a, int b)
 /* ------------------------------------------------------------------------
  * Block-scaled 16-bit fixed-point states.
  *
- * The paper names fixed-point arithmetic as future work (Conclusion) without
+ * The paper names fixed-point arithmetic as future work (Sec. V) without
  * a format.  The reading taken here: each component (re, im) of an amplitude
  * is a signed 16-bit code q, and the 64 consecutive amplitudes of a block
  * (all 2^n of them when n < 6) share one power-of-two scale s, so that a

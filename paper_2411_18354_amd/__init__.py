@@ -21,7 +21,7 @@ if not os.path.exists(LIB_PATH):
 _L = ctypes.CDLL(LIB_PATH)
 
 SV_OK, SV_EINVAL, SV_ENOMEM, SV_EHIP, SV_ENOTSUP = 0, -1, -2, -3, -4
-SV_C128, SV_C64 = 0, 1
+SV_C128, SV_C64, SV_CQ16 = 0, 1, 2
 SV_MODE_AUTO, SV_MODE_MASKED, SV_MODE_PAIR, SV_MODE_WAVE, SV_MODE_TILE = 0, 1, 2, 3, 4
 MODES = {"auto": SV_MODE_AUTO, "masked": SV_MODE_MASKED, "pair": SV_MODE_PAIR,
          "wave": SV_MODE_WAVE, "tile": SV_MODE_TILE}
@@ -102,21 +102,48 @@ def _dtype_code(t) -> int:
         return SV_C128
     if t.dtype == torch.complex64:
         return SV_C64
-    raise TypeError("state tensor must be complex128 or complex64, got %s" % t.dtype)
+    if t.dtype == torch.uint8:
+        return SV_CQ16
+    raise TypeError("state tensor must be complex128, complex64 or uint8 (SV_CQ16), got %s" % t.dtype)
+
+
+def q16_nbytes(n: int) -> int:
+    """Bytes of an n-qubit SV_CQ16 state: 4 per amplitude, then 1 per 64."""
+    return (4 << n) + max(1, (1 << n) // 64)
+
+
+def _q16_qubits(nbytes: int) -> int:
+    for n in range(1, 37):
+        if q16_nbytes(n) == nbytes:
+            return n
+    raise ValueError("%d bytes is not the size of a fixed-point state" % nbytes)
+
+
+def fixed_state(n: int, device="cuda"):
+    """Uninitialised uint8 tensor holding an n-qubit SV_CQ16 state."""
+    return _torch().empty(q16_nbytes(n), dtype=_torch().uint8, device=device)
 
 
 def state_view(t, n: Optional[int] = None) -> sv_state_t:
-    """sv_state_t view of a contiguous complex CUDA tensor of 2^n elements."""
+    """sv_state_t view of a contiguous CUDA tensor: complex of 2^n elements,
+    or uint8 of q16_nbytes(n) bytes for a fixed-point state."""
     if isinstance(t, sv_state_t):
         return t
     if not t.is_cuda or not t.is_contiguous():
         raise ValueError("state must be a contiguous CUDA tensor")
     numel = t.numel()
+    code = _dtype_code(t)
+    if code == SV_CQ16:
+        if n is None:
+            n = _q16_qubits(numel)
+        if numel != q16_nbytes(n):
+            raise ValueError("fixed-point state has %d bytes, expected %d" % (numel, q16_nbytes(n)))
+        return sv_state_t(t.data_ptr(), n, code)
     if n is None:
         n = numel.bit_length() - 1
     if numel != (1 << n):
         raise ValueError("state has %d elements, expected 2^%d" % (numel, n))
-    return sv_state_t(t.data_ptr(), n, _dtype_code(t))
+    return sv_state_t(t.data_ptr(), n, code)
 
 
 def _u8(U) -> ctypes.Array:
@@ -245,11 +272,25 @@ def sv_tune_get(key: str) -> int:
 
 
 _sig("sv_copy_state", [_sp, _sp, _vp])
+_sig("sv_convert", [_sp, _sp, _vp])
+_sig("sv_state_bytes", [ctypes.c_int, ctypes.c_int, ctypes.POINTER(_u64)])
 
 
 def sv_copy_state(dst, src, stream=None) -> None:
     a, b = state_view(dst), state_view(src)
     _check(_L.sv_copy_state(ctypes.byref(a), ctypes.byref(b), stream_ptr(stream)))
+
+
+def sv_convert(dst, src, stream=None) -> None:
+    """Convert src into dst (same n, any dtypes; SV_CQ16 encode/decode)."""
+    a, b = state_view(dst), state_view(src)
+    _check(_L.sv_convert(ctypes.byref(a), ctypes.byref(b), stream_ptr(stream)))
+
+
+def sv_state_bytes(n: int, dtype: int) -> int:
+    out = _u64(0)
+    _check(_L.sv_state_bytes(int(n), int(dtype), ctypes.byref(out)))
+    return int(out.value)
 
 
 # ---------------------------------------------------------------- circuits

@@ -46,17 +46,20 @@ Expand make_expand(int n, const std::vector<int> &positions, const std::vector<i
     return e;
 }
 
-int validate_state(const sv_state_t *s) {
+int validate_state(const sv_state_t *s, bool allow_fixed) {
     if (!s)
         return fail(SV_EINVAL, "state is NULL");
-    if (s->dtype != SV_C128 && s->dtype != SV_C64)
+    if (s->dtype != SV_C128 && s->dtype != SV_C64 && s->dtype != SV_CQ16)
         return fail(SV_EINVAL, "unknown dtype %d", s->dtype);
+    if (s->dtype == SV_CQ16 && !allow_fixed)
+        return fail(SV_ENOTSUP, "this call does not take fixed-point (SV_CQ16) states");
     if (s->n < 1 || s->n > max_qubits(s->dtype))
         return fail(SV_EINVAL, "n=%d outside [1, %d]", s->n, max_qubits(s->dtype));
     if (!s->data)
         return fail(SV_EINVAL, "state data is NULL");
-    if (((uintptr_t)s->data) % amp_bytes(s->dtype))
-        return fail(SV_EINVAL, "state data %p not aligned to %zu bytes", s->data, amp_bytes(s->dtype));
+    const size_t align = s->dtype == SV_CQ16 ? 16 : amp_bytes(s->dtype);
+    if (((uintptr_t)s->data) % align)
+        return fail(SV_EINVAL, "state data %p not aligned to %zu bytes", s->data, align);
     return SV_OK;
 }
 
@@ -170,12 +173,12 @@ int sv_alloc(sv_state_t *s, int n, int dtype) {
     clear_error();
     if (!s)
         return fail(SV_EINVAL, "state is NULL");
-    if (dtype != SV_C128 && dtype != SV_C64)
+    if (dtype != SV_C128 && dtype != SV_C64 && dtype != SV_CQ16)
         return fail(SV_EINVAL, "unknown dtype %d", dtype);
     if (n < 1 || n > max_qubits(dtype))
         return fail(SV_EINVAL, "n=%d outside [1, %d]", n, max_qubits(dtype));
     void *p = nullptr;
-    const size_t bytes = ((size_t)1 << n) * amp_bytes(dtype);
+    const size_t bytes = state_bytes(n, dtype);
     hipError_t e = hipMalloc(&p, bytes);
     if (e != hipSuccess) {
         (void)hipGetLastError();
@@ -199,7 +202,7 @@ int sv_free(sv_state_t *s) {
 
 int sv_init(const sv_state_t *s, uint64_t basis_index, sv_stream_t st) {
     clear_error();
-    SV_TRY(validate_state(s));
+    SV_TRY(validate_state(s, true));
     const uint64_t N = 1ull << s->n;
     if (basis_index >= N)
         return fail(SV_EINVAL, "basis index %llu >= 2^%d", (unsigned long long)basis_index, s->n);
@@ -207,6 +210,8 @@ int sv_init(const sv_state_t *s, uint64_t basis_index, sv_stream_t st) {
     SV_TRY(device_info(&di));
     const uint64_t want = (N + 255) / 256;
     const unsigned grid = (unsigned)std::min<uint64_t>(want, (uint64_t)di.num_cus * 16);
+    if (s->dtype == SV_CQ16)
+        return launch_q16_basis(s->data, s->n, basis_index, grid, (hipStream_t)st);
     if (s->dtype == SV_C128)
         hipLaunchKernelGGL(k_basis<double>, dim3(grid), dim3(256), 0, (hipStream_t)st,
                            (double2 *)s->data, N, basis_index);
@@ -219,25 +224,25 @@ int sv_init(const sv_state_t *s, uint64_t basis_index, sv_stream_t st) {
 
 int sv_copy_state(const sv_state_t *dst, const sv_state_t *src, sv_stream_t st) {
     clear_error();
-    SV_TRY(validate_state(dst));
-    SV_TRY(validate_state(src));
+    SV_TRY(validate_state(dst, true));
+    SV_TRY(validate_state(src, true));
     if (dst->n != src->n || dst->dtype != src->dtype)
         return fail(SV_EINVAL, "copy between states of different size or dtype");
     if (dst->data == src->data)
         return SV_OK;
-    const size_t bytes = ((size_t)1 << src->n) * amp_bytes(src->dtype);
+    const size_t bytes = state_bytes(src->n, src->dtype);
     const char *a = (const char *)src->data, *b = (const char *)dst->data;
     if (a < b + bytes && b < a + bytes)
         return fail(SV_EINVAL, "source and destination overlap");
     DeviceInfo di;
     SV_TRY(device_info(&di));
     const uint64_t n16 = bytes / 16;
-    if (n16 > 0) {
+    if (n16 > 0 && bytes % 16 == 0) {
         const unsigned grid = (unsigned)std::min<uint64_t>((n16 + 255) / 256, (uint64_t)di.num_cus * 8);
         hipLaunchKernelGGL(k_copy, dim3(grid), dim3(256), 0, (hipStream_t)st, (const uint4 *)src->data,
                            (uint4 *)dst->data, n16);
         SV_LAUNCH_CHECK();
-    } else {  // a complex64 state with n = 1 is 16 bytes; below that use the runtime
+    } else {  // sizes that are not whole 16-byte chunks (small or fixed-point states)
         SV_HIP_TRY(hipMemcpyAsync(dst->data, src->data, bytes, hipMemcpyDeviceToDevice, (hipStream_t)st));
     }
     return SV_OK;

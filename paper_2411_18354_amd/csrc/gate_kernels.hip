@@ -443,6 +443,13 @@ static int launch_tile1(const sv_state_t *s, const GateSpec &g, const double *U,
 }
 
 int launch_gate(const sv_state_t *s, const GateSpec &g, const double *U, int mode, hipStream_t st) {
+    if (s->dtype == SV_CQ16) {
+        if (mode < SV_MODE_AUTO || mode > SV_MODE_TILE)
+            return fail(SV_EINVAL, "unknown mode %d", mode);
+        Q16Plan q;
+        SV_TRY(make_q16_plan(g, mode == SV_MODE_MASKED, &q));
+        return launch_q16_gate(s->data, q, U, nullptr, st);
+    }
     GatePlan p;
     SV_TRY(make_gate_plan(g, s->dtype, mode, &p));
     if (p.kind == GateKernel::Tile)
@@ -461,7 +468,7 @@ extern "C" {
 int sv_apply_gate_masks(const sv_state_t *s, int target, uint64_t ctrl_mask, uint64_t ctrl_vals, const double *U,
                         int mode, sv_stream_t st) {
     clear_error();
-    SV_TRY(validate_state(s));
+    SV_TRY(validate_state(s, true));
     if (!U)
         return fail(SV_EINVAL, "U is NULL");
     GateSpec g{s->n, target, ctrl_mask, ctrl_vals};
@@ -472,7 +479,7 @@ int sv_apply_gate_masks(const sv_state_t *s, int target, uint64_t ctrl_mask, uin
 int sv_apply_gate(const sv_state_t *s, int target, const int32_t *controls, int ncontrols, uint64_t ctrl_vals,
                   const double *U, int mode, sv_stream_t st) {
     clear_error();
-    SV_TRY(validate_state(s));
+    SV_TRY(validate_state(s, true));
     if (!U)
         return fail(SV_EINVAL, "U is NULL");
     if (target < 0 || target >= s->n)
@@ -487,17 +494,28 @@ int sv_apply_gate(const sv_state_t *s, int target, const int32_t *controls, int 
 int sv_gate_plan(int n, int dtype, int target, uint64_t ctrl_mask, uint64_t ctrl_vals, int mode, char *kernel,
                  int kernel_len, uint64_t *iterations) {
     clear_error();
-    if (dtype != SV_C128 && dtype != SV_C64)
+    if (dtype != SV_C128 && dtype != SV_C64 && dtype != SV_CQ16)
         return fail(SV_EINVAL, "unknown dtype %d", dtype);
     if (n < 1 || n > max_qubits(dtype))
         return fail(SV_EINVAL, "n=%d outside [1, %d]", n, max_qubits(dtype));
     GateSpec g{n, target, ctrl_mask, ctrl_vals};
     SV_TRY(validate_gate(g));
-    GatePlan p;
-    SV_TRY(make_gate_plan(g, dtype, mode, &p));
-    const std::string name = gate_plan_name(p, dtype, "MatVal");
-    if (iterations)
-        *iterations = p.niter;
+    std::string name;
+    if (dtype == SV_CQ16) {
+        if (mode < SV_MODE_AUTO || mode > SV_MODE_TILE)
+            return fail(SV_EINVAL, "unknown mode %d", mode);
+        Q16Plan q;
+        SV_TRY(make_q16_plan(g, mode == SV_MODE_MASKED, &q));
+        name = q16_plan_name(q, "MatVal");
+        if (iterations)
+            *iterations = q.units;
+    } else {
+        GatePlan p;
+        SV_TRY(make_gate_plan(g, dtype, mode, &p));
+        name = gate_plan_name(p, dtype, "MatVal");
+        if (iterations)
+            *iterations = p.niter;
+    }
     if (kernel && kernel_len > 0) {
         strncpy(kernel, name.c_str(), (size_t)kernel_len - 1);
         kernel[kernel_len - 1] = '\0';

@@ -77,7 +77,7 @@ def test_gate_argument_errors(sv, case, needle):
 
 
 def test_state_errors(sv):
-    for st, needle in ((_state(sv, 0), "n=0"), (_state(sv, 35), "n=35"), (_state(sv, 8, 2), "dtype"),
+    for st, needle in ((_state(sv, 0), "n=0"), (_state(sv, 35), "n=35"), (_state(sv, 8, 3), "dtype"),
                        (_state(sv, 8, 0, 0), "NULL"), (_state(sv, 8, 0, 0x10008), "aligned")):
         code, msg = _rc(lambda: sv.sv_apply_gate(st, 0, U=U))
         assert code == sv.SV_EINVAL and needle in msg, msg
@@ -135,3 +135,59 @@ def test_tune_cache_load(sv, tmp_path, monkeypatch):
     finally:
         for k, v in before.items():
             sv.sv_tune_set(k, v)
+
+
+# ---------------------------------------------------------------- fixed-point states
+
+def test_fixed_point_state_bytes(sv):
+    for n in (1, 5, 6, 7, 12, 28, 36):
+        want = (4 << n) + max(1, (1 << n) // 64)
+        assert sv.sv_state_bytes(n, sv.SV_CQ16) == want == sv.q16_nbytes(n)
+    assert sv.sv_state_bytes(28, sv.SV_C128) == 16 << 28 and sv.sv_state_bytes(28, sv.SV_C64) == 8 << 28
+    code, msg = _rc(lambda: sv.sv_state_bytes(37, sv.SV_CQ16))
+    assert code == sv.SV_EINVAL
+
+
+@pytest.mark.parametrize("n,t,ctrls,masked,name,units", [
+    (28, 13, (17, 22), False, "k_q16_gate<false, true", 1 << 19),   # block pairs: 2^(22-1-2)
+    (28, 13, (17, 22), True, "k_q16_gate<true, true", 1 << 21),     # every block pair
+    (28, 3, (0, 20), False, "k_q16_gate<false, false", 1 << 21),    # blocks: 2^(22-1), qubit 0 tested
+    (28, 3, (0, 1), False, "k_q16_gate<false, false", 1 << 22),     # only in-block controls
+    (6, 5, (0,), False, "k_q16_gate<false, false", 1),
+    (5, 4, (0, 1), False, "k_q16_gate_small", 1),
+])
+def test_fixed_point_gate_plan(sv, n, t, ctrls, masked, name, units):
+    cm = sum(1 << q for q in ctrls)
+    k, it = sv.sv_gate_plan(n, sv.SV_CQ16, t, cm, cm, "masked" if masked else "auto")
+    assert name in k and it == units, (k, it)
+
+
+def test_fixed_point_rejected_where_unsupported(sv):
+    L = sv.lib()
+    s = _state(sv, 10, sv.SV_CQ16)
+    code, msg = _rc(lambda: sv.sv_swap_qubits(s, [(0, 9)]))
+    assert code == sv.SV_ENOTSUP and "fixed-point" in msg
+    code, msg = _rc(lambda: sv.sv_apply_dense_low(s, 4, __import__("numpy").eye(16)))
+    assert code == sv.SV_ENOTSUP
+    terms = (sv.sv_pauli_t * 1)()
+    rc = L.sv_expect(ctypes.byref(s), terms, 1, ctypes.c_void_p(0x1000), None)
+    assert rc == sv.SV_ENOTSUP
+    # circuits: fusion, dense blocks and remapping are not offered
+    for flags in (sv.SV_FUSE, sv.SV_DENSE | sv.SV_FUSE, sv.SV_REMAP):
+        code, msg = _rc(lambda: sv.Circuit(10, [], dtype=sv.SV_CQ16, flags=flags))
+        assert code == sv.SV_ENOTSUP and "SV_CQ16" in msg, msg
+    # 16-byte alignment, and the usual gate checks
+    code, msg = _rc(lambda: sv.sv_apply_gate(_state(sv, 10, sv.SV_CQ16, 0x10008), 0, U=U))
+    assert code == sv.SV_EINVAL and "aligned" in msg
+    code, msg = _rc(lambda: sv.sv_apply_gate(s, 3, controls=(3,), U=U))
+    assert code == sv.SV_EINVAL and "equals the target" in msg
+    code, msg = _rc(lambda: sv.sv_apply_gate(s, 3, U=U, mode=9))
+    assert code == sv.SV_EINVAL and "mode" in msg
+
+
+def test_convert_argument_errors(sv):
+    a = _state(sv, 10, sv.SV_CQ16, 0x100000)
+    code, msg = _rc(lambda: sv.sv_convert(a, _state(sv, 11, sv.SV_C128, 0x900000)))
+    assert code == sv.SV_EINVAL and "qubits" in msg
+    code, msg = _rc(lambda: sv.sv_convert(a, _state(sv, 10, sv.SV_C128, 0x100000 + 4096)))
+    assert code == sv.SV_EINVAL and "overlap" in msg
