@@ -263,9 +263,127 @@ def _energy_per_run(torch, stream, fn, read, min_s=1.0):
     return watts * (t1 - t0) / reps, watts
 
 
-def measure_extras(sv, W, torch, np, stream, with_layered):
+def _case_sweep(sv, torch, np, st, cases, U, stream, mode, reps=3):
+    """Median HIP-event time (ms) of every (target, controls) gate of the sweep
+    on state st, and the total time of reps back-to-back passes."""
+    with torch.cuda.stream(stream):
+        for t, ctrls in cases:
+            sv.sv_apply_gate(st, t, ctrls, None, U, mode=mode, stream=stream)
+        torch.cuda.synchronize()
+        evs = []
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(reps):
+            for t, ctrls in cases:
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                sv.sv_apply_gate(st, t, ctrls, None, U, mode=mode, stream=stream)
+                e1.record(stream)
+                evs.append(((t, ctrls), e0, e1))
+        b.record(stream)
+    torch.cuda.synchronize()
+    per = {}
+    for key, e0, e1 in evs:
+        per.setdefault(key, []).append(e0.elapsed_time(e1))
+    return a.elapsed_time(b), {k: float(np.median(v)) for k, v in per.items()}
+
+
+def measure_fixed_point(sv, W, torch, np, stream, psi_host, cases, U, energy):
+    """Block-scaled 16-bit fixed-point states (4 bytes per amplitude) beside
+    complex64 (8) on the same controlled-gate sweep, the paper's 29-qubit
+    circuits in fixed point, and the QFT's error against its closed form."""
+    dev = torch.device("cuda:0")
+    n = 28
+    out = {}
+    src = torch.from_numpy(psi_host).to(dev)
+    q = sv.fixed_state(n)
+    sv.sv_convert(q, src, stream=stream)
+    c64 = torch.empty(1 << n, dtype=torch.complex64, device=dev)
+    sv.sv_convert(c64, src, stream=stream)
+    torch.cuda.synchronize()
+    del src
+    torch.cuda.empty_cache()
+    log("fixed-point sweep n=28 (scheduled, masked) and complex64 sweep")
+    tq, pq = _case_sweep(sv, torch, np, q, cases, U, stream, "auto")
+    tm, pm = _case_sweep(sv, torch, np, q, cases, U, stream, "masked")
+    t64, p64 = _case_sweep(sv, torch, np, c64, cases, U, stream, "auto")
+    reps = 3
+    rows = []
+    for t, ctrls in cases:
+        c = len(ctrls)
+        ch = sum(1 for x in ctrls if x >= 6)  # controls scheduled over the block index
+        alg_q = 2 * (1 << (n - c)) * 4 + 2 * (1 << (n - 6 - ch))  # satisfying amplitudes + their scales
+        alg_64 = 2 * (1 << (n - c)) * 8
+        key = (t, ctrls)
+        rows.append({"t": t, "c": c, "c_in_block": c - ch,
+                     "q16_us": round(pq[key] * 1e3, 2), "q16_GBps": round(alg_q / pq[key] / 1e6, 1),
+                     "q16_masked_us": round(pm[key] * 1e3, 2),
+                     "c64_us": round(p64[key] * 1e3, 2), "c64_GBps": round(alg_64 / p64[key] / 1e6, 1)})
+    ng = reps * len(cases)
+    out["sweep_n28"] = {"q16_gates_per_s": round(ng / (tq / 1e3), 1),
+                        "q16_masked_gates_per_s": round(ng / (tm / 1e3), 1),
+                        "c64_gates_per_s": round(ng / (t64 / 1e3), 1), "rows": rows}
+    del q, c64
+    torch.cuda.empty_cache()
+    for name, circ in (("qft29", W.qft(29)), ("stream29", W.stream(29))):
+        log("paper circuit", name, "fixed point")
+        st = sv.fixed_state(29)
+        row = {"gates": len(circ.gates)}
+        for label, fl in (("masked", sv.SV_MASKED), ("scheduled", 0)):
+            p = sv.Circuit(29, circ, dtype=sv.SV_CQ16, flags=fl)
+
+            def run():
+                sv.sv_init(st, 1, stream=stream)
+                p.run(st, stream=stream)
+            row[label + "_ms"] = round(_time_ms(torch, stream, run, 3), 3)
+            row[label + "_J_rated"] = round(row[label + "_ms"] * 1e-3 * RATED_POWER_W, 2)
+            if energy is not None:
+                j, w = _energy_per_run(torch, stream, run, energy)
+                if j is not None:
+                    row[label + "_J_measured"] = round(j, 3)
+                    row[label + "_W_avg"] = round(w, 1)
+            p.close()
+        row["masked_over_scheduled"] = round(row["masked_ms"] / row["scheduled_ms"], 2)
+        out["%s_q16" % name] = row
+        del st
+        torch.cuda.empty_cache()
+    # accuracy: QFT (as drawn, no swaps) of a random state against the
+    # closed form ifft(psi[bit-reversed]) * sqrt(N)
+    ne = 20
+    log("QFT n=%d error against its closed form" % ne)
+    psi0 = W.random_state(ne, 34)
+    N = 1 << ne
+    rev = np.zeros(N, dtype=np.int64)
+    for b in range(ne):
+        rev |= ((np.arange(N) >> b) & 1) << (ne - 1 - b)
+    want = np.fft.ifft(psi0[rev]) * np.sqrt(N)
+    circ = W.qft(ne)
+    errs = {}
+    for label, td in (("c128", torch.complex128), ("c64", torch.complex64), ("q16", None)):
+        src = torch.from_numpy(psi0).to(dev)
+        if td is None:
+            st = sv.fixed_state(ne)
+            sv.sv_convert(st, src, stream=stream)
+        else:
+            st = torch.empty(N, dtype=td, device=dev)
+            sv.sv_convert(st, src, stream=stream)
+        sv.sv_apply_circuit(st, circ, flags=0, stream=stream)
+        res = torch.empty(N, dtype=torch.complex128, device=dev)
+        sv.sv_convert(res, st, stream=stream)
+        torch.cuda.synchronize()
+        got = res.cpu().numpy()
+        errs[label] = {"l2": float("%.3e" % np.linalg.norm(got - want)),
+                       "max_over_maxabs": float("%.3e" % (np.abs(got - want).max() / np.abs(want).max()))}
+    out["qft20_error_vs_closed_form"] = errs
+    return out
+
+
+def measure_extras(sv, W, torch, np, stream, with_layered, psi_host=None, cases=None, U=None):
     """Adjoint gradients (n=24 ansatz), batched circuits (4096 uneven circuits), the paper's
-    QFT and streaming circuits at 29 qubits, and optionally the layered n=32 circuit."""
+    QFT and streaming circuits at 29 qubits, fixed-point states, and optionally the
+    layered n=32 circuit."""
     out = {}
     dev = torch.device("cuda:0")
     # ---- adjoint gradients: n=24 HEA, 768 parameters
@@ -417,6 +535,8 @@ def measure_extras(sv, W, torch, np, stream, with_layered):
     out["low_control_n28"] = row
     del st
     torch.cuda.empty_cache()
+    if psi_host is not None:
+        out["fixed_point"] = measure_fixed_point(sv, W, torch, np, stream, psi_host, cases, U, energy)
     if with_layered:
         log("layered circuit: n=32 complex128")
         c2 = W.layered_circuit_n32()
@@ -577,7 +697,7 @@ def main():
     if not args.no_extras:
         del d
         torch.cuda.empty_cache()
-        extras = measure_extras(sv, W, torch, np, stream, args.layered_n32)
+        extras = measure_extras(sv, W, torch, np, stream, args.layered_n32, psi_host, cases, U)
 
     cpu = None
     if args.cpu_seconds > 0:

@@ -46,13 +46,24 @@ __device__ __forceinline__ int q_scale(float m) {
     return min(max(e, kQScaleMin), kQScaleMax);
 }
 
-// Code of v under scale s: round to nearest even, saturate to +-32767.
-__device__ __forceinline__ uint32_t q_code(float v, int s) {
-    const float r = fminf(fmaxf(rintf(ldexpf(v, -s)), -32767.0f), 32767.0f);
-    return (uint32_t)(uint16_t)(int16_t)(int)r;
+// Code of v under scale s, given inv = 2^-s: v * 2^-s rounded to nearest,
+// ties to even, saturated to +-32767.  |v * 2^-s| < 2^15, so adding
+// C = 1.5 * 2^23 in one fused multiply-add (the product is exact) lands in
+// [2^23, 2^24), where floats are the integers: that single rounding is the
+// round-to-nearest-even of v * 2^-s (C is even, so ties keep their parity).
+// Clamped to C +- 32767, the float's bits are 0x4B400000 + code, whose low
+// 16 bits are the code in two's complement.
+__device__ __forceinline__ uint32_t q_biased(float v, float inv) {
+    const float y = __builtin_fmaf(v, inv, 12582912.0f);
+    return __float_as_uint(__builtin_amdgcn_fmed3f(y, 12582912.0f - 32767.0f, 12582912.0f + 32767.0f));
 }
 
-__device__ __forceinline__ uint32_t q_word(float re, float im, int s) { return q_code(re, s) | (q_code(im, s) << 16); }
+__device__ __forceinline__ float q_inv(int s) { return ldexpf(1.0f, -s); }
+
+__device__ __forceinline__ uint32_t q_word(float re, float im, float inv) {
+    // low half: the re code, high half: the im code
+    return __builtin_amdgcn_perm(q_biased(im, inv), q_biased(re, inv), 0x05040100u);
+}
 
 __device__ __forceinline__ void q_unword(uint32_t w, int s, float &re, float &im) {
     re = q_dec((int)(int16_t)(w & 0xffffu), s);
@@ -67,28 +78,34 @@ __device__ __forceinline__ void q4_decode(u32x4 w, int s, float (&re)[4], float 
 }
 
 __device__ __forceinline__ u32x4 q4_encode(const float (&re)[4], const float (&im)[4], int s) {
+    const float inv = q_inv(s);
     u32x4 w;
-    w.x = q_word(re[0], im[0], s);
-    w.y = q_word(re[1], im[1], s);
-    w.z = q_word(re[2], im[2], s);
-    w.w = q_word(re[3], im[3], s);
+    w.x = q_word(re[0], im[0], inv);
+    w.y = q_word(re[1], im[1], inv);
+    w.z = q_word(re[2], im[2], inv);
+    w.w = q_word(re[3], im[3], inv);
     return w;
 }
 
 __device__ __forceinline__ float q4_absmax(const float (&re)[4], const float (&im)[4]) {
-    float m = 0.0f;
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-        m = fmaxf(m, fmaxf(fabsf(re[i]), fabsf(im[i])));
-    return m;
+    const float a = fmaxf(fmaxf(fabsf(re[0]), fabsf(im[0])), fabsf(re[1]));
+    const float b = fmaxf(fmaxf(fabsf(im[1]), fabsf(re[2])), fabsf(im[2]));
+    return fmaxf(fmaxf(a, b), fmaxf(fabsf(re[3]), fabsf(im[3])));
 }
 
-// Maximum over the 16 lanes of a group (lanes 16g .. 16g+15 of the wave).
+template <int Ctrl> __device__ __forceinline__ float dpp_max(float v) {
+    return fmaxf(v, __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), Ctrl, 0xf, 0xf, false)));
+}
+
+// Maximum over the 16 lanes of a group, which is one DPP row (lanes
+// 16g .. 16g+15): swap neighbours and pairs inside each quad, then mirror
+// each half row and the whole row.  All 16 lanes of a row are active
+// together (a group shares its work unit).
 __device__ __forceinline__ float group16_max(float v) {
-    v = fmaxf(v, lane_xor(v, 1));
-    v = fmaxf(v, lane_xor(v, 2));
-    v = fmaxf(v, lane_xor(v, 4));
-    v = fmaxf(v, lane_xor(v, 8));
+    v = dpp_max<0xB1>(v);   // quad_perm [1, 0, 3, 2]
+    v = dpp_max<0x4E>(v);   // quad_perm [2, 3, 0, 1]
+    v = dpp_max<0x141>(v);  // row_half_mirror
+    v = dpp_max<0x140>(v);  // row_mirror
     return v;
 }
 
@@ -115,73 +132,120 @@ __device__ __forceinline__ void q_row(const Mat2<float> &M, bool hi, float &xr, 
     xi = o.y;
 }
 
-template <bool Masked, bool High, typename MS>
+// Block index of unit u, or -1 when a masked launch skips it.  Block
+// indices have at most 30 bits.
+template <bool Masked, bool High> __device__ __forceinline__ int q_unit_block(const Q16Plan &p, uint64_t u) {
+    if (u >= p.units)
+        return -1;
+    const uint32_t v = (uint32_t)u;
+    if (!Masked)
+        return (int)expand_index<uint32_t>(p.e, v);
+    const uint32_t b = High ? (((v >> p.target) << (p.target + 1)) | (v & ((1u << p.target) - 1))) : v;
+    return ((b & (uint32_t)p.hmask) == (uint32_t)p.hvals) ? (int)b : -1;
+}
+
+// Units per loop iteration of a group: every load of an iteration is issued
+// before any arithmetic.  Unit k of an iteration is u0 + k * (groups in the
+// grid), so each wave-wide load covers 4 adjacent blocks.
+template <bool High> struct QUnroll { static constexpr int K = High ? 2 : 4; };
+
+// LowCtl: some control is one of the 6 in-block qubits (tested per
+// amplitude); without, every amplitude of a visited block is updated.
+template <bool Masked, bool High, bool LowCtl, typename MS>
 __global__ __launch_bounds__(kQThreads) void k_q16_gate(u32x4 *__restrict__ codes, int8_t *__restrict__ scales,
                                                         Q16Plan p, MS ms) {
+    constexpr int K = QUnroll<High>::K;
     const int j = threadIdx.x & 15;
-    const uint64_t gstride = ((uint64_t)gridDim.x * kQThreads) >> 4;
+    const uint32_t a0 = 4u * (uint32_t)j;  // first in-block amplitude of the lane
+    const uint64_t groups = ((uint64_t)gridDim.x * kQThreads) >> 4;
     const Mat2<float> M = ms.get();
-    for (uint64_t u = ((uint64_t)blockIdx.x * kQThreads + threadIdx.x) >> 4; u < p.units; u += gstride) {
-        uint64_t b;
-        if (Masked) {
-            b = High ? (((u >> p.target) << (p.target + 1)) | (u & ((1ull << p.target) - 1))) : u;
-            if ((b & p.hmask) != p.hvals)
-                continue;  // the whole group skips: lanes of a group share u
-        } else {
-            b = expand_index<uint64_t>(p.e, u);
-        }
-        u32x4 *ca = codes + b * 16 + j;
-        if (High) {
-            const uint64_t b2 = b | (1ull << p.target);
-            u32x4 *cb = codes + b2 * 16 + j;
-            const u32x4 wa = ld_nt4(ca), wb = ld_nt4(cb);
-            const int sa = scales[b], sb = scales[b2];
-            float xr[4], xi[4], yr[4], yi[4];
-            q4_decode(wa, sa, xr, xi);
-            q4_decode(wb, sb, yr, yi);
+    const int t = p.target;
+    // low targets 2..5: the partner is lane j ^ lm; this lane's row of G
+    const int lm = (!High && t >= 2) ? (1 << (t - 2)) : 0;
+    const bool hi = (j & lm) != 0;
+    const float ur = hi ? M.cr : M.ar, ui = hi ? M.ci : M.ai;
+    const float vr = hi ? M.dr : M.br, vi = hi ? M.di : M.bi;
+    auto ok = [&](uint32_t a) { return !LowCtl || ((a & p.lmask) == p.lvals); };
+    for (uint64_t u0 = ((uint64_t)blockIdx.x * kQThreads + threadIdx.x) >> 4; u0 < p.units; u0 += K * groups) {
+        int b[K];
+        u32x4 wa[K], wb[K];
+        int sa[K], sb[K];
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
-                if ((((uint32_t)(4 * j + i)) & p.lmask) == p.lvals)
-                    q_pair(M, xr[i], xi[i], yr[i], yi[i]);
-            const int na = q_scale(group16_max(q4_absmax(xr, xi)));
-            const int nb = q_scale(group16_max(q4_absmax(yr, yi)));
-            st_nt4(ca, q4_encode(xr, xi, na));
-            st_nt4(cb, q4_encode(yr, yi, nb));
-            if (j == 0) {
-                scales[b] = (int8_t)na;
-                scales[b2] = (int8_t)nb;
-            }
-        } else {
-            const u32x4 w = ld_nt4(ca);
-            const int s = scales[b];
-            float xr[4], xi[4];
-            q4_decode(w, s, xr, xi);
-            const int t = p.target;
-            const uint32_t a0 = 4u * (uint32_t)j;
-            if (t == 0) {
-                if (((a0 + 0) & p.lmask) == p.lvals)
-                    q_pair(M, xr[0], xi[0], xr[1], xi[1]);
-                if (((a0 + 2) & p.lmask) == p.lvals)
-                    q_pair(M, xr[2], xi[2], xr[3], xi[3]);
-            } else if (t == 1) {
-                if (((a0 + 0) & p.lmask) == p.lvals)
-                    q_pair(M, xr[0], xi[0], xr[2], xi[2]);
-                if (((a0 + 1) & p.lmask) == p.lvals)
-                    q_pair(M, xr[1], xi[1], xr[3], xi[3]);
-            } else {
-                const int lm = 1 << (t - 2);
-                const bool hi = (j & lm) != 0;
-#pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    const float pr = lane_xor(xr[i], lm), pi = lane_xor(xi[i], lm);
-                    if (((a0 + i) & p.lmask) == p.lvals)
-                        q_row(M, hi, xr[i], xi[i], pr, pi);
+        for (int k = 0; k < K; ++k) {
+            b[k] = q_unit_block<Masked, High>(p, u0 + k * groups);  // the same for a group's 16 lanes
+            if (b[k] >= 0) {
+                wa[k] = ld_nt4(codes + (size_t)b[k] * 16 + j);
+                sa[k] = scales[b[k]];
+                if (High) {
+                    const uint32_t b2 = (uint32_t)b[k] | (1u << t);
+                    wb[k] = ld_nt4(codes + (size_t)b2 * 16 + j);
+                    sb[k] = scales[b2];
                 }
             }
-            const int ns = q_scale(group16_max(q4_absmax(xr, xi)));
-            st_nt4(ca, q4_encode(xr, xi, ns));
-            if (j == 0)
-                scales[b] = (int8_t)ns;
+        }
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            if (b[k] < 0)
+                continue;
+            u32x4 *ca = codes + (size_t)b[k] * 16 + j;
+            float xr[4], xi[4];
+            q4_decode(wa[k], sa[k], xr, xi);
+            if (High) {
+                const uint32_t b2 = (uint32_t)b[k] | (1u << t);
+                float yr[4], yi[4];
+                q4_decode(wb[k], sb[k], yr, yi);
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    float nxr = xr[i], nxi = xi[i], nyr = yr[i], nyi = yi[i];
+                    q_pair(M, nxr, nxi, nyr, nyi);
+                    const bool w = ok(a0 + i);
+                    xr[i] = w ? nxr : xr[i];
+                    xi[i] = w ? nxi : xi[i];
+                    yr[i] = w ? nyr : yr[i];
+                    yi[i] = w ? nyi : yi[i];
+                }
+                const int na = q_scale(group16_max(q4_absmax(xr, xi)));
+                const int nb = q_scale(group16_max(q4_absmax(yr, yi)));
+                st_nt4(ca, q4_encode(xr, xi, na));
+                st_nt4(codes + (size_t)b2 * 16 + j, q4_encode(yr, yi, nb));
+                if (j == 0) {
+                    scales[b[k]] = (int8_t)na;
+                    scales[b2] = (int8_t)nb;
+                }
+            } else {
+                // pairs inside the lane (constant register indices)
+                auto upd = [&](int i1, int i2) {
+                    float nxr = xr[i1], nxi = xi[i1], nyr = xr[i2], nyi = xi[i2];
+                    q_pair(M, nxr, nxi, nyr, nyi);
+                    const bool w = ok(a0 + i1);
+                    xr[i1] = w ? nxr : xr[i1];
+                    xi[i1] = w ? nxi : xi[i1];
+                    xr[i2] = w ? nyr : xr[i2];
+                    xi[i2] = w ? nyi : xi[i2];
+                };
+                if (t == 0) {
+                    upd(0, 1);
+                    upd(2, 3);
+                } else if (t == 1) {
+                    upd(0, 2);
+                    upd(1, 3);
+                } else {
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const float pr = lane_xor(xr[i], lm), pi = lane_xor(xi[i], lm);
+                        const float2 p1 = hi ? make_float2(pr, pi) : make_float2(xr[i], xi[i]);
+                        const float2 p2 = hi ? make_float2(xr[i], xi[i]) : make_float2(pr, pi);
+                        const float2 o = cmac2<float>(ur, ui, p1, vr, vi, p2);
+                        const bool w = ok(a0 + i);
+                        xr[i] = w ? o.x : xr[i];
+                        xi[i] = w ? o.y : xi[i];
+                    }
+                }
+                const int ns = q_scale(group16_max(q4_absmax(xr, xi)));
+                st_nt4(ca, q4_encode(xr, xi, ns));
+                if (j == 0)
+                    scales[b[k]] = (int8_t)ns;
+            }
         }
     }
 }
@@ -206,7 +270,7 @@ __global__ __launch_bounds__(64) void k_q16_gate_small(uint32_t *__restrict__ co
         m = fmaxf(m, lane_xor(m, k));
     const int ns = q_scale(m);
     if (valid)
-        codes[l] = q_word(xr, xi, ns);
+        codes[l] = q_word(xr, xi, q_inv(ns));
     if (l == 0)
         scales[0] = (int8_t)ns;
 }
@@ -250,7 +314,7 @@ __global__ __launch_bounds__(64) void k_q16_encode_small(const cplx_t<R> *__rest
         m = fmaxf(m, lane_xor(m, k));
     const int ns = q_scale(m);
     if (valid)
-        codes[l] = q_word(re, im, ns);
+        codes[l] = q_word(re, im, q_inv(ns));
     if (l == 0)
         scales[0] = (int8_t)ns;
 }
@@ -346,8 +410,8 @@ std::string q16_plan_name(const Q16Plan &p, const char *matsrc) {
     if (p.small)
         snprintf(buf, sizeof(buf), "sv::k_q16_gate_small<sv::%s<float> >", matsrc);
     else
-        snprintf(buf, sizeof(buf), "sv::k_q16_gate<%s, %s, sv::%s<float> >", p.masked ? "true" : "false",
-                 p.high ? "true" : "false", matsrc);
+        snprintf(buf, sizeof(buf), "sv::k_q16_gate<%s, %s, %s, sv::%s<float> >", p.masked ? "true" : "false",
+                 p.high ? "true" : "false", p.lmask ? "true" : "false", matsrc);
     return buf;
 }
 
@@ -359,6 +423,14 @@ static unsigned q16_grid(uint64_t groups) {
     return (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(want, (uint64_t)di.num_cus * 32));
 }
 
+template <bool Masked, bool High, typename MS>
+static void go_q16(bool low, dim3 grid, u32x4 *codes, int8_t *sc, const Q16Plan &p, const MS &ms, hipStream_t st) {
+    if (low)
+        hipLaunchKernelGGL((k_q16_gate<Masked, High, true, MS>), grid, dim3(kQThreads), 0, st, codes, sc, p, ms);
+    else
+        hipLaunchKernelGGL((k_q16_gate<Masked, High, false, MS>), grid, dim3(kQThreads), 0, st, codes, sc, p, ms);
+}
+
 template <typename MS> static int launch_q16(void *state, const Q16Plan &p, const MS &ms, hipStream_t st) {
     int8_t *sc = q16_scales(state, p.n);
     if (p.small) {
@@ -367,15 +439,14 @@ template <typename MS> static int launch_q16(void *state, const Q16Plan &p, cons
         return SV_OK;
     }
     u32x4 *codes = (u32x4 *)state;
-    const dim3 grid(q16_grid(p.units)), block(kQThreads);
-    if (p.masked && p.high)
-        hipLaunchKernelGGL((k_q16_gate<true, true, MS>), grid, block, 0, st, codes, sc, p, ms);
-    else if (p.masked)
-        hipLaunchKernelGGL((k_q16_gate<true, false, MS>), grid, block, 0, st, codes, sc, p, ms);
-    else if (p.high)
-        hipLaunchKernelGGL((k_q16_gate<false, true, MS>), grid, block, 0, st, codes, sc, p, ms);
+    const uint64_t per_group = p.high ? QUnroll<true>::K : QUnroll<false>::K;
+    const dim3 grid(q16_grid((p.units + per_group - 1) / per_group));
+    const bool low = p.lmask != 0;
+    if (p.masked)
+        p.high ? go_q16<true, true>(low, grid, codes, sc, p, ms, st) : go_q16<true, false>(low, grid, codes, sc, p, ms, st);
     else
-        hipLaunchKernelGGL((k_q16_gate<false, false, MS>), grid, block, 0, st, codes, sc, p, ms);
+        p.high ? go_q16<false, true>(low, grid, codes, sc, p, ms, st)
+               : go_q16<false, false>(low, grid, codes, sc, p, ms, st);
     SV_LAUNCH_CHECK();
     return SV_OK;
 }
