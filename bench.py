@@ -167,6 +167,78 @@ def summarize_profile(trace_dir, fetch_dir, write_dir):
     print("\n".join(lines + [""] + tl))
 
 
+def _position_cases(n, t=13):
+    """(placement, c, controls) of the control-position sweep, in launch order."""
+    out = []
+    for place in ("lowest", "highest"):
+        free = [q for q in range(n) if q != t]
+        if place == "highest":
+            free = free[::-1]
+        for c in range(1, 9):
+            out.append((place, c, tuple(sorted(free[:c]))))
+    return out
+
+
+def _counter_by_dispatch(d, counter):
+    """[(dispatch id, kernel name, value)] in dispatch order (values of one
+    dispatch summed over the rows rocprofv3 writes for it)."""
+    acc = {}
+    for r in _read_csv_rows(d, "counter_collection.csv"):
+        if r.get("Counter_Name") != counter:
+            continue
+        k = int(r["Dispatch_Id"])
+        name, v = acc.get(k, (r["Kernel_Name"], 0.0))
+        acc[k] = (name, v + float(r["Counter_Value"]))
+    return [(k, acc[k][0], acc[k][1]) for k in sorted(acc)]
+
+
+def summarize_positions(fetch_dir, write_dir):
+    """HBM bytes of every control-position gate (bench.py --positions-only
+    under rocprofv3 --pmc) against its algorithmic bytes: exposes the
+    cache-line granularity of skipped pairs."""
+    n, t = N_QUBITS, 13
+    fetch = _counter_by_dispatch(fetch_dir, "FETCH_SIZE")
+    write = _counter_by_dispatch(write_dir, "WRITE_SIZE")
+
+    def copy_scale(rows):
+        v = [x for _, nm, x in rows if COPY_KERNEL in nm]
+        assert v, "copy calibration missing"
+        return COPY_BYTES / (sum(v) / len(v) * 1024.0)
+
+    def gates(rows):
+        return [x for _, nm, x in rows if "sv::k_pair" in nm or "sv::k_wave" in nm]
+    fs, ws = copy_scale(fetch), copy_scale(write)
+    gf, gw = gates(fetch), gates(write)
+    cases = _position_cases(n, t)
+    want = len(cases) * 2 * 2  # two modes, warm-up + one timed launch each
+    assert len(gf) == want and len(gw) == want, (len(gf), len(gw), want)
+    lines = ["# HBM traffic against control position: n=28 complex128, target 13", "",
+             "Commands (each its own run, from the repository root):", "",
+             "    rocprofv3 --pmc FETCH_SIZE -f csv -d <fetch_dir> -o pos -- python3 bench.py --positions-only "
+             "--pmc-copy",
+             "    rocprofv3 --pmc WRITE_SIZE -f csv -d <write_dir> -o pos -- python3 bench.py --positions-only "
+             "--pmc-copy", "",
+             "Counters (KiB per dispatch) are scaled by what they read for the plain copy kernel moving a "
+             "known 1 GiB: FETCH scale %.4f, WRITE scale %.4f.  Algorithmic bytes are the read and write of "
+             "every amplitude of a satisfying pair, 2 * 2^(n-c) * 16.  Controls placed on the lowest free "
+             "qubits sit below the 128-byte granule (qubits 0-2 of a complex128 index) until c >= 4; "
+             "there a scheduled skip saves no DRAM traffic." % (fs, ws), "",
+             "| placement | c | controls | mode | alg GB | HBM GB | HBM / alg |", "|---|---|---|---|---|---|---|"]
+    i = 0
+    for place, c, ctrls in cases:
+        for mode in ("scheduled", "masked"):
+            f_b = gf[i + 1] * 1024.0 * fs  # the launch after the warm-up
+            w_b = gw[i + 1] * 1024.0 * ws
+            i += 2
+            alg = 2 * (1 << (n - c)) * AMP_BYTES
+            lines.append("| %s | %d | %s | %s | %.3f | %.3f | %.2f |" % (
+                place, c, ",".join(map(str, ctrls)), mode, alg / 1e9, (f_b + w_b) / 1e9, (f_b + w_b) / alg))
+    path = os.path.join(ROOT, "profiles", "traffic_control_positions_n28.md")
+    with open(path, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 def _time_ms(torch, stream, fn, reps):
     """Median of reps HIP-event timings of fn() on stream (after one warmup)."""
     with torch.cuda.stream(stream):
@@ -191,32 +263,27 @@ def control_position_sweep(sv, torch, np, d, U, stream, n, t=13, reps=5):
     (controls below bit 3 of a complex128 index share 128-byte lines with
     updated pairs).  Median HIP-event time per gate, scheduled and masked."""
     out = []
-    for place in ("lowest", "highest"):
-        free = [q for q in range(n) if q != t]
-        if place == "highest":
-            free = free[::-1]
-        for c in range(1, 9):
-            ctrls = tuple(sorted(free[:c]))
-            row = {"placement": place, "t": t, "c": c, "controls": list(ctrls)}
-            alg = 2 * (1 << (n - c)) * AMP_BYTES
-            for mode in ("auto", "masked"):
-                ts = []
-                with torch.cuda.stream(stream):
+    for place, c, ctrls in _position_cases(n, t):
+        row = {"placement": place, "t": t, "c": c, "controls": list(ctrls)}
+        alg = 2 * (1 << (n - c)) * AMP_BYTES
+        for mode in ("auto", "masked"):
+            ts = []
+            with torch.cuda.stream(stream):
+                sv.sv_apply_gate(d, t, ctrls, None, U, mode=mode, stream=stream)
+                for _ in range(reps):
+                    e0 = torch.cuda.Event(enable_timing=True)
+                    e1 = torch.cuda.Event(enable_timing=True)
+                    e0.record(stream)
                     sv.sv_apply_gate(d, t, ctrls, None, U, mode=mode, stream=stream)
-                    for _ in range(reps):
-                        e0 = torch.cuda.Event(enable_timing=True)
-                        e1 = torch.cuda.Event(enable_timing=True)
-                        e0.record(stream)
-                        sv.sv_apply_gate(d, t, ctrls, None, U, mode=mode, stream=stream)
-                        e1.record(stream)
-                        ts.append((e0, e1))
-                torch.cuda.synchronize()
-                med = float(np.median([a.elapsed_time(b) for a, b in ts]))
-                key = "sched" if mode == "auto" else "masked"
-                row[key + "_us"] = round(med * 1e3, 2)
-                row[key + "_GBps"] = round(alg / med / 1e6, 1)
-            row["masked_over_sched"] = round(row["masked_us"] / row["sched_us"], 2)
-            out.append(row)
+                    e1.record(stream)
+                    ts.append((e0, e1))
+            torch.cuda.synchronize()
+            med = float(np.median([a.elapsed_time(b) for a, b in ts]))
+            key = "sched" if mode == "auto" else "masked"
+            row[key + "_us"] = round(med * 1e3, 2)
+            row[key + "_GBps"] = round(alg / med / 1e6, 1)
+        row["masked_over_sched"] = round(row["masked_us"] / row["sched_us"], 2)
+        out.append(row)
     return out
 
 
@@ -574,9 +641,18 @@ def main():
                     help="also time the layered n=32 circuit (64 GiB) with and without LDS fusion (about a minute)")
     ap.add_argument("--summarize-profile", nargs=3, metavar=("TRACE_DIR", "FETCH_DIR", "WRITE_DIR"),
                     help="write profiles/ summaries from rocprofv3 CSV output of this script and exit")
+    ap.add_argument("--positions-only", action="store_true",
+                    help="run only the control-position sweep (one timed launch per point), for rocprofv3 "
+                         "byte counters")
+    ap.add_argument("--summarize-positions", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="write the control-position traffic summary from rocprofv3 --pmc output of "
+                         "--positions-only and exit")
     args = ap.parse_args()
     if args.summarize_profile:
         summarize_profile(*args.summarize_profile)
+        return
+    if args.summarize_positions:
+        summarize_positions(*args.summarize_positions)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
@@ -609,6 +685,11 @@ def main():
             sv.sv_copy_state(b, a, stream=stream)
         torch.cuda.synchronize()
         del a, b
+
+    if args.positions_only:
+        rows = control_position_sweep(sv, torch, np, d, U, stream, n, reps=1)
+        print(json.dumps({"control_positions": rows}), flush=True)
+        return
 
     plans = {}
     for mode in ("auto", "masked"):
