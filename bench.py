@@ -239,6 +239,37 @@ def summarize_positions(fetch_dir, write_dir):
     print("\n".join(lines))
 
 
+EXTRAS_TRACE_CMD = ("rocprofv3 --kernel-trace --stats -f csv -d <dir> -o extras -- python3 bench.py --steps 1 "
+                    "--warmup 0 --cpu-seconds 0 --no-masked")
+
+
+def summarize_trace(trace_dir):
+    """Every kernel of a full bench run (the sweep plus the extras: fused
+    circuits, adjoint, batches, dense blocks, expectation values, qubit
+    exchange, fixed-point states) from rocprofv3 --kernel-trace --stats."""
+    stats = _read_csv_rows(trace_dir, "kernel_stats.csv")
+    assert stats, "no kernel_stats.csv under %s" % trace_dir
+    stats.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    lines = ["# Kernel trace: bench.py with every extra measurement", "",
+             "Command (from the repository root):", "", "    " + EXTRAS_TRACE_CMD, "",
+             "One sweep step, the control-position sweep, then the extras in bench order: the adjoint, "
+             "the batches, dense blocks, the paper's 29-qubit circuits (masked, scheduled, fused; energy "
+             "runs included), the remapped low-control circuit, and the fixed-point sweeps and circuits.  "
+             "Library kernels are in the `sv::` namespace.", "",
+             "| kernel | calls | total ms | avg us | min us | max us | share |", "|---|---|---|---|---|---|---|"]
+    for r in stats[:40]:
+        nm = r["Name"].split("(")[0].replace("void ", "")
+        if len(nm) > 110:
+            nm = nm[:107] + "..."
+        lines.append("| `%s` | %s | %.2f | %.2f | %.2f | %.2f | %.2f%% |" % (
+            nm, r["Calls"], float(r["TotalDurationNs"]) / 1e6, float(r["AverageNs"]) / 1e3,
+            float(r["MinNs"]) / 1e3, float(r["MaxNs"]) / 1e3, float(r["Percentage"])))
+    path = os.path.join(ROOT, "profiles", "kernel_trace_bench_extras.md")
+    with open(path, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 def _time_ms(torch, stream, fn, reps):
     """Median of reps HIP-event timings of fn() on stream (after one warmup)."""
     with torch.cuda.stream(stream):
@@ -647,7 +678,12 @@ def main():
     ap.add_argument("--summarize-positions", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="write the control-position traffic summary from rocprofv3 --pmc output of "
                          "--positions-only and exit")
+    ap.add_argument("--summarize-trace", metavar="TRACE_DIR",
+                    help="write the all-kernel summary of a full run from rocprofv3 --kernel-trace output and exit")
     args = ap.parse_args()
+    if args.summarize_trace:
+        summarize_trace(args.summarize_trace)
+        return
     if args.summarize_profile:
         summarize_profile(*args.summarize_profile)
         return
