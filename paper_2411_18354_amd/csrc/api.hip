@@ -154,8 +154,8 @@ __global__ __launch_bounds__(256) void k_copy(const uint4 *__restrict__ src, uin
 
 template <typename I>
 __global__ __launch_bounds__(256) void k_debug_indices(uint64_t *__restrict__ out, uint64_t count, Expand e) {
-    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < count)
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride)
         out[i] = (uint64_t)expand_index<I>(e, (I)i);
 }
 
@@ -266,7 +266,7 @@ int sv_debug_pair_indices(int n, int target, const int32_t *controls, int ncontr
     std::vector<int> pos, bits;
     gate_positions(g, pos, bits);
     const Expand e = make_expand(n, pos, bits);
-    const uint64_t blocks = (count + 255) / 256;
+    const uint64_t blocks = std::min<uint64_t>((count + 255) / 256, kMaxGridBlocks);
     if (n <= 32)
         hipLaunchKernelGGL(k_debug_indices<uint32_t>, dim3((unsigned)blocks), dim3(256), 0,
                            (hipStream_t)st, out_dev, count, e);

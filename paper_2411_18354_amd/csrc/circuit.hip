@@ -399,8 +399,12 @@ static int launch_tile_pass(cplx_t<R> *psi, const TileMap &tm_in, const DeviceGa
                             hipStream_t st) {
     TileMap tm = tm_in;
     tm.tab = 1;  // lds includes the tables
-    hipLaunchKernelGGL((k_tile<R, 512, DeviceGates>), dim3((unsigned)tm.ntiles), dim3(512), lds, st, psi, tm, dg);
-    SV_LAUNCH_CHECK();
+    for (uint64_t t0 = 0; t0 < tm.ntiles; t0 += kMaxGridBlocks) {
+        tm.tile0 = t0;
+        const dim3 grid((unsigned)std::min(kMaxGridBlocks, tm_in.ntiles - t0));
+        hipLaunchKernelGGL((k_tile<R, 512, DeviceGates>), grid, dim3(512), lds, st, psi, tm, dg);
+        SV_LAUNCH_CHECK();
+    }
     return SV_OK;
 }
 

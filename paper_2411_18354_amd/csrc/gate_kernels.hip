@@ -36,9 +36,10 @@ constexpr int kRewrite = 1;  // load and store the unchanged values, so that
 // ---------------------------------------------------------------------------
 template <typename R, typename I, int K, int POLICY, typename MS>
 __global__ __launch_bounds__(kThreads) void k_pair(cplx_t<R> *__restrict__ psi, uint64_t niter, Expand e,
-                                                   uint64_t tmask, uint64_t tvals, uint32_t t, MS ms) {
+                                                   uint64_t tmask, uint64_t tvals, uint32_t t, MS ms,
+                                                   uint64_t block0) {
     const Mat2<R> m = ms.get();
-    const uint64_t base = (uint64_t)blockIdx.x * (kThreads * K) + threadIdx.x;
+    const uint64_t base = (block0 + blockIdx.x) * (kThreads * K) + threadIdx.x;
     const I st = (I)1 << t;
     cplx_t<R> x[K], y[K];
     I p1[K];
@@ -79,7 +80,8 @@ __global__ __launch_bounds__(kThreads) void k_pair(cplx_t<R> *__restrict__ psi, 
 // ---------------------------------------------------------------------------
 template <typename R, int K, int POLICY, typename MS>
 __global__ __launch_bounds__(kThreads) void k_wave(cplx_t<R> *__restrict__ psi, uint64_t nwaves, Expand ae,
-                                                   uint32_t tmask, uint32_t tvals, uint32_t tl, MS ms) {
+                                                   uint32_t tmask, uint32_t tvals, uint32_t tl, MS ms,
+                                                   uint64_t block0) {
     const Mat2<R> m = ms.get();
     const uint32_t lane = threadIdx.x & 63;
     const uint32_t wave = threadIdx.x >> 6;
@@ -91,7 +93,7 @@ __global__ __launch_bounds__(kThreads) void k_wave(cplx_t<R> *__restrict__ psi, 
     bool in[K], pass[K];
 #pragma unroll
     for (int j = 0; j < K; ++j) {
-        const uint64_t w = ((uint64_t)blockIdx.x * K + j) * W + wave;
+        const uint64_t w = ((block0 + blockIdx.x) * K + j) * W + wave;
         in[j] = w < nwaves;
         addr[j] = expand_index<uint64_t>(ae, (w << 6) | lane);
         pass[j] = in[j] && (((uint32_t)addr[j] & tmask) == tvals);
@@ -371,24 +373,30 @@ std::string gate_plan_name(const GatePlan &p, int dtype, const char *matsrc) {
 template <typename R, typename I, int K, typename MS>
 static void go_pair(cplx_t<R> *psi, const GatePlan &p, const MS &ms, hipStream_t st) {
     const uint64_t blocks = (p.niter + kThreads * K - 1) / (kThreads * K);
-    if (p.policy == kRewrite)
-        hipLaunchKernelGGL((k_pair<R, I, K, kRewrite, MS>), dim3((unsigned)blocks), dim3(kThreads), 0, st, psi,
-                           p.niter, p.e, p.tmask, p.tvals, (uint32_t)p.target, ms);
-    else
-        hipLaunchKernelGGL((k_pair<R, I, K, kSkip, MS>), dim3((unsigned)blocks), dim3(kThreads), 0, st, psi,
-                           p.niter, p.e, p.tmask, p.tvals, (uint32_t)p.target, ms);
+    for (uint64_t b0 = 0; b0 < blocks; b0 += kMaxGridBlocks) {
+        const dim3 grid((unsigned)std::min(kMaxGridBlocks, blocks - b0));
+        if (p.policy == kRewrite)
+            hipLaunchKernelGGL((k_pair<R, I, K, kRewrite, MS>), grid, dim3(kThreads), 0, st, psi, p.niter, p.e,
+                               p.tmask, p.tvals, (uint32_t)p.target, ms, b0);
+        else
+            hipLaunchKernelGGL((k_pair<R, I, K, kSkip, MS>), grid, dim3(kThreads), 0, st, psi, p.niter, p.e,
+                               p.tmask, p.tvals, (uint32_t)p.target, ms, b0);
+    }
 }
 
 template <typename R, int K, typename MS>
 static void go_wave(cplx_t<R> *psi, const GatePlan &p, const MS &ms, hipStream_t st) {
     constexpr uint64_t W = kThreads / 64;
     const uint64_t blocks = (p.niter + W * K - 1) / (W * K);
-    if (p.policy == kRewrite)
-        hipLaunchKernelGGL((k_wave<R, K, kRewrite, MS>), dim3((unsigned)blocks), dim3(kThreads), 0, st, psi,
-                           p.niter, p.e, (uint32_t)p.tmask, (uint32_t)p.tvals, (uint32_t)p.target, ms);
-    else
-        hipLaunchKernelGGL((k_wave<R, K, kSkip, MS>), dim3((unsigned)blocks), dim3(kThreads), 0, st, psi,
-                           p.niter, p.e, (uint32_t)p.tmask, (uint32_t)p.tvals, (uint32_t)p.target, ms);
+    for (uint64_t b0 = 0; b0 < blocks; b0 += kMaxGridBlocks) {
+        const dim3 grid((unsigned)std::min(kMaxGridBlocks, blocks - b0));
+        if (p.policy == kRewrite)
+            hipLaunchKernelGGL((k_wave<R, K, kRewrite, MS>), grid, dim3(kThreads), 0, st, psi, p.niter, p.e,
+                               (uint32_t)p.tmask, (uint32_t)p.tvals, (uint32_t)p.target, ms, b0);
+        else
+            hipLaunchKernelGGL((k_wave<R, K, kSkip, MS>), grid, dim3(kThreads), 0, st, psi, p.niter, p.e,
+                               (uint32_t)p.tmask, (uint32_t)p.tvals, (uint32_t)p.target, ms, b0);
+    }
 }
 
 template <typename R, typename MS>
@@ -429,16 +437,20 @@ template int launch_plan<float, MatPtr<float>>(float2 *, const GatePlan &, const
 template <typename R>
 static int launch_tile1(const sv_state_t *s, const GateSpec &g, const double *U, hipStream_t st) {
     const int m = std::min(tile_log2(s->dtype), g.n);
-    const TileMap tm = contiguous_tile_map(g.n, m);
+    TileMap tm = contiguous_tile_map(g.n, m);
     InlineGates<1> gs;
     gs.g[0] = make_tile_gate(tm, g.target, g.cmask, g.cvals, U, false);
     gs.count = 1;
     const size_t lds = ((size_t)1 << m) * sizeof(cplx_t<R>);
     auto fn = k_tile<R, 512, InlineGates<1>>;
     SV_TRY(set_lds_limit<R>((const void *)fn, lds));
-    hipLaunchKernelGGL(fn, dim3((unsigned)tm.ntiles), dim3(512), lds, st, reinterpret_cast<cplx_t<R> *>(s->data), tm,
-                       gs);
-    SV_LAUNCH_CHECK();
+    const uint64_t ntiles = tm.ntiles;
+    for (uint64_t t0 = 0; t0 < ntiles; t0 += kMaxGridBlocks) {
+        tm.tile0 = t0;
+        hipLaunchKernelGGL(fn, dim3((unsigned)std::min(kMaxGridBlocks, ntiles - t0)), dim3(512), lds, st,
+                           reinterpret_cast<cplx_t<R> *>(s->data), tm, gs);
+        SV_LAUNCH_CHECK();
+    }
     return SV_OK;
 }
 

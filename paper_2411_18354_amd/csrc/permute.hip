@@ -32,7 +32,7 @@ __global__ __launch_bounds__(kPermThreads) void k_permute_tile(cplx_t<R> *__rest
     extern __shared__ unsigned char lds_raw[];
     cplx_t<R> *tile = reinterpret_cast<cplx_t<R> *>(lds_raw);
     const uint32_t T = 1u << tm.m;
-    const uint64_t base = expand_index<uint64_t>(tm.outer, (uint64_t)blockIdx.x);
+    const uint64_t base = expand_index<uint64_t>(tm.outer, tm.tile0 + blockIdx.x);
     for (uint32_t j = threadIdx.x; j < T; j += kPermThreads)
         tile[j] = ld_stream<R>(psi + (base | tile_offset(tm, j)));
     __syncthreads();
@@ -125,16 +125,22 @@ int launch_swap_qubits(int dtype, void *psi, int n, const int32_t *pairs, int np
                 return fail(SV_EINVAL, "internal: qubit outside the exchange tile");
         }
         const size_t lds = ((size_t)1 << m) * amp_bytes(dtype);
-        if (dtype == SV_C128) {
+        if (dtype == SV_C128)
             SV_TRY(set_perm_lds<double>(lds));
-            hipLaunchKernelGGL(k_permute_tile<double>, dim3((unsigned)tm.ntiles), dim3(kPermThreads), lds, st,
-                               (double2 *)psi, tm, sw);
-        } else {
+        else
             SV_TRY(set_perm_lds<float>(lds));
-            hipLaunchKernelGGL(k_permute_tile<float>, dim3((unsigned)tm.ntiles), dim3(kPermThreads), lds, st,
-                               (float2 *)psi, tm, sw);
+        for (uint64_t t0 = 0; t0 < tm.ntiles; t0 += kMaxGridBlocks) {
+            TileMap part = tm;
+            part.tile0 = t0;
+            const dim3 grid((unsigned)std::min(kMaxGridBlocks, tm.ntiles - t0));
+            if (dtype == SV_C128)
+                hipLaunchKernelGGL(k_permute_tile<double>, grid, dim3(kPermThreads), lds, st, (double2 *)psi, part,
+                                   sw);
+            else
+                hipLaunchKernelGGL(k_permute_tile<float>, grid, dim3(kPermThreads), lds, st, (float2 *)psi, part,
+                                   sw);
+            SV_LAUNCH_CHECK();
         }
-        SV_LAUNCH_CHECK();
     }
     return SV_OK;
 }

@@ -90,6 +90,12 @@ template <typename R> inline Mat2<R> to_mat(const double *U) {
 
 constexpr int kMaxSeg = SV_MAX_QUBITS_C64 + 2;
 
+// A dispatch covers fewer than 2^32 work-items per grid dimension, which
+// the largest registers exceed (2^34 pairs); launches whose grid grows with
+// 2^n are split into pieces of at most this many workgroups, each told the
+// index of its first workgroup.
+constexpr uint64_t kMaxGridBlocks = 1ull << 22;
+
 struct Expand {
     uint32_t nseg;
     uint32_t shift[kMaxSeg];

@@ -94,6 +94,7 @@ struct TileMap {
     uint64_t ntiles;  // launched tiles: 2^(n - m - fixed outer bits)
     uint32_t tab;     // the launch reserves the diagonal-sweep tables after the tile
     uint32_t pad;
+    uint64_t tile0;   // index of the launch's first tile (launches split at kMaxGridBlocks)
 };
 
 // Doubles of the diagonal-sweep tables for tile width m (0 below m = 7):
@@ -555,7 +556,7 @@ template <typename R, int THREADS, typename Src>
 __global__ __launch_bounds__(THREADS, 4) void k_tile(cplx_t<R> *__restrict__ psi, TileMap tm, Src gates) {
     extern __shared__ unsigned char lds_raw[];
     cplx_t<R> *tile = reinterpret_cast<cplx_t<R> *>(lds_raw);
-    const uint64_t base = expand_index<uint64_t>(tm.outer, (uint64_t)blockIdx.x);
+    const uint64_t base = expand_index<uint64_t>(tm.outer, tm.tile0 + blockIdx.x);
     const uint32_t T = 1u << tm.m;
     // a tile that no operation of the run touches is left alone
     if (!tile_touched(base, gates))

@@ -1,0 +1,114 @@
+"""The largest register each dtype supports on one MI355X (288 GB of HBM):
+n = 34 complex128 and n = 35 complex64 (256 GiB each), n = 36 fixed point
+(257 GiB).  64-bit indices throughout.  The checks are properties that pin
+the result without a second full-size buffer: a basis state moved by a
+controlled X, a gate whose controls fail on it leaving it alone, and the
+norm (or, for fixed point, whole-array reductions of codes and scales)
+showing that every other amplitude stayed zero.
+"""
+import numpy as np
+import pytest
+import torch
+
+sv = pytest.importorskip("paper_2411_18354_amd")
+
+pytestmark = pytest.mark.gpu
+
+X = np.array([[0, 1], [1, 0]])
+
+
+def _alloc(fn, what):
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    try:
+        return fn()
+    except torch.cuda.OutOfMemoryError as e:
+        pytest.skip("could not allocate %s: %s" % (what, str(e).splitlines()[0]))
+
+
+def _run_and_release(make, body, what):
+    """Allocate with make(), run body(buffer), and free the buffer before
+    reporting a failure: a traceback would otherwise keep frames (and the
+    256 GiB buffer they reference) alive for the tests that follow."""
+    buf = _alloc(make, what)
+    err = None
+    try:
+        body(buf)
+    except Exception as e:  # noqa: BLE001 - reported below without its frames
+        err = "%s: %s" % (type(e).__name__, e)
+    finally:
+        del buf
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+    if err:
+        pytest.fail(err, pytrace=False)
+
+
+def _isum(t, chunk=1 << 28):
+    """Integer sum of a huge tensor in int64, chunk by chunk (a sum with
+    dtype=int64 would first cast the whole tensor)."""
+    return sum(int(c.sum(dtype=torch.int64).item()) for c in t.split(chunk))
+
+
+def _basis(n):
+    # bits 0 and 2, bit 31 (beyond 31-bit lane arithmetic) and bit n-2
+    return (1 << (n - 2)) | (1 << 31) | 5
+
+
+@pytest.mark.parametrize("dtype,n", [("c128", 34), ("c64", 35)])
+def test_controlled_x_at_max_size(dtype, n):
+    td = torch.complex128 if dtype == "c128" else torch.complex64
+    print("max size: %s n=%d" % (dtype, n), flush=True)
+
+    def body(psi):
+        b = _basis(n)
+        t = n - 1
+        sv.sv_init(psi, b)
+        sv.sv_apply_gate(psi, t, (0, n - 2), None, X)            # scheduled: controls hold on b
+        sv.sv_apply_gate(psi, 3, (1,), None, X)                  # control on qubit 1 fails on b
+        sv.sv_apply_gate(psi, t - 1, (2,), 0, X, mode="masked")  # negative control fails on b
+        sv.sv_apply_gate(psi, 0, (), None, np.eye(2))            # every amplitude rewritten
+        w = b | (1 << t)
+        torch.cuda.synchronize()
+        assert psi[w].item() == 1 and psi[b].item() == 0
+        # <psi|I|psi> = 1 with |psi_w| = 1 forces every other amplitude to 0
+        nrm = sv.sv_expect(psi, [(1.0, 0, 0)]).item()
+        assert abs(nrm - 1.0) < 1e-12
+        # the masked kernel undoes the move
+        sv.sv_apply_gate(psi, t, (0, n - 2), None, X, mode="masked")
+        torch.cuda.synchronize()
+        assert psi[b].item() == 1 and psi[w].item() == 0
+
+    _run_and_release(lambda: torch.empty(1 << n, dtype=td, device="cuda"), body, "%s n=%d" % (dtype, n))
+
+
+def test_fixed_point_controlled_x_at_max_size():
+    n = 36
+    print("max size: fixed point n=%d" % n, flush=True)
+
+    def body(q):
+        N = 1 << n
+        nb = N >> 6
+        codes = q[:4 * N].view(torch.int32)  # one word per amplitude: re code low, im code high
+        scales = q[4 * N:].view(torch.int8)
+        b = _basis(n)
+        t = n - 1
+        sv.sv_init(q, b)
+        sv.sv_apply_gate(q, t, (0, n - 2), None, X)
+        sv.sv_apply_gate(q, 3, (1,), None, X)
+        w = b | (1 << t)
+        torch.cuda.synchronize()
+        # 1.0 is code 16384 under scale -14; every other word is 0 and
+        # every other block keeps the zero-block scale -126
+        assert codes[w].item() == 16384 and codes[b].item() == 0
+        assert codes.min().item() == 0 and codes.max().item() == 16384
+        assert _isum(codes) == 16384
+        assert scales[w >> 6].item() == -14
+        assert scales.max().item() == -14 and scales.min().item() == -126
+        assert _isum(scales) == -126 * (nb - 1) - 14
+        sv.sv_apply_gate(q, t, (0, n - 2), None, X, mode="masked")
+        torch.cuda.synchronize()
+        assert codes[b].item() == 16384 and codes[w].item() == 0
+        assert scales[b >> 6].item() == -14 and scales[w >> 6].item() == -126
+
+    _run_and_release(lambda: sv.fixed_state(n), body, "fixed point n=%d" % n)
