@@ -347,9 +347,13 @@ __device__ __forceinline__ double diag_phase_at(const TileGate &d, uint32_t j, b
 // where A collects the gates reading only bits of u, B those reading only
 // bits of v, R[q] those reading bits of u and the single bit 6+q, and rest
 // (evaluated per amplitude) those reading bits of u and two or more bits of
-// v.  Each wavefront builds whole tables (one lane per entry, skipping the
-// gates of other tables), so the per-amplitude cost is a handful of LDS reads
-// whatever the sweep's length.
+// v.  When every gate of the R[q] kind depends on u through one condition
+// (u & um) == uv (a target bit in u counting as a required 1 when its
+// zero-side phase is 0, as for controlled phases sharing a target), their
+// terms sum to [(u & um) == uv] * D[v] with a single table D instead of the
+// m-6 tables R[q].  Each wavefront builds whole tables (one lane per entry,
+// skipping the gates of other tables), so the per-amplitude cost is a
+// handful of LDS reads whatever the sweep's length.
 template <typename R, int THREADS, typename Src>
 __device__ __forceinline__ void diag_sweep_tables(cplx_t<R> *tile, double *tab, uint64_t base, uint32_t m,
                                                   const Src &gates, int i, int e) {
@@ -358,22 +362,43 @@ __device__ __forceinline__ void diag_sweep_tables(cplx_t<R> *tile, double *tab, 
     double *A = tab, *B = tab + 64, *Rt = tab + 64 + (1 << Hb);
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     double th0 = 0.0;
-    bool any_rest = false;
-    for (int q = i; q < e; ++q) {
+    bool any_rest = false, have_r = false, rank1 = true;
+    uint32_t um = 0, uv = 0;
+    for (int q = i; q < e; ++q) {  // uniform
         const TileGate &d = gates.get(q);
         if ((base & d.o_mask) != d.o_vals)
             continue;
         const uint32_t lm = d.l_mask | (d.l_target >= 0 ? 1u << d.l_target : 0u);
-        if (lm == 0)
+        if (lm == 0) {
             th0 += ((base >> d.target) & 1ull) ? d.ph[1] : d.ph[0];
-        else if ((lm & 63u) && __popc(lm >> 6) > 1)
+        } else if ((lm & 63u) && __popc(lm >> 6) > 1) {
             any_rest = true;
+        } else if ((lm & 63u) && (lm >> 6)) {  // an R[q] gate: its condition on u
+            uint32_t gm = d.l_mask & 63u, gv = d.l_vals & 63u;
+            if (d.l_target >= 0 && d.l_target < 6) {
+                if (uniform_f64(d.ph[0]) != 0.0)
+                    rank1 = false;
+                gm |= 1u << d.l_target;
+                gv |= 1u << d.l_target;
+            }
+            if (!have_r) {
+                um = gm;
+                uv = gv;
+                have_r = true;
+            } else if (gm != um || gv != uv) {
+                rank1 = false;
+            }
+        }
     }
-    // table tb: 0 = A, 1 = B, 2 + q = R[q]; entries per lane: A 1, B
-    // ceil(2^Hb / 64) (lanes beyond 2^Hb idle when Hb < 6), R 2
+    const bool use_d = have_r && rank1;
+    // table tb: 0 = A, 1 = B, then D (use_d) or 2 + q = R[q] (R gates of
+    // several conditions); entries per lane: A 1, B and D ceil(2^Hb / 64)
+    // (lanes beyond 2^Hb idle when Hb < 6), R 2.  D uses the R area.
     const uint32_t nb = 1u << Hb;
-    for (int tb = w; tb < 2 + Hb; tb += THREADS / 64) {  // uniform per wavefront
-        const int ne = tb == 0 ? 1 : (tb == 1 ? (int)((nb + 63) / 64) : 2);
+    const int ntab = 2 + (!have_r ? 0 : (use_d ? 1 : Hb));
+    for (int tb = w; tb < ntab; tb += THREADS / 64) {  // uniform per wavefront
+        const bool dtab = use_d && tb == 2;
+        const int ne = tb == 0 ? 1 : ((tb == 1 || dtab) ? (int)((nb + 63) / 64) : 2);
         double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
         for (int q = i; q < e; ++q) {
             const TileGate &d = gates.get(q);
@@ -381,15 +406,20 @@ __device__ __forceinline__ void diag_sweep_tables(cplx_t<R> *tile, double *tab, 
                 continue;  // uniform
             const uint32_t lm = d.l_mask | (d.l_target >= 0 ? 1u << d.l_target : 0u);
             const uint32_t lo = lm & 63u, hi = lm >> 6;
-            const bool mine = tb == 0 ? (lo && !hi) : tb == 1 ? (hi && !lo) : (lo && hi == (1u << (tb - 2)));
+            const bool mine = tb == 0   ? (lo && !hi)
+                              : tb == 1 ? (hi && !lo)
+                              : dtab    ? (lo && __popc(hi) == 1)
+                                        : (lo && hi == (1u << (tb - 2)));
             if (!mine)
                 continue;  // uniform
             const bool tone = (base >> d.target) & 1ull;
             const double p0 = uniform_f64(d.ph[0]), p1 = uniform_f64(d.ph[1]);
             // the tile-local index an entry stands for
             auto at = [&](int k) -> uint32_t {
-                return tb == 0 ? (uint32_t)lane
-                               : tb == 1 ? (uint32_t)(lane + 64 * k) << 6 : (uint32_t)lane | ((uint32_t)k << (4 + tb));
+                return tb == 0   ? (uint32_t)lane
+                       : tb == 1 ? (uint32_t)(lane + 64 * k) << 6
+                       : dtab    ? ((uint32_t)(lane + 64 * k) << 6) | uv
+                                 : (uint32_t)lane | ((uint32_t)k << (4 + tb));
             };
             acc0 += diag_phase_at(d, at(0), tone, p0, p1);
             if (ne > 1)
@@ -400,7 +430,7 @@ __device__ __forceinline__ void diag_sweep_tables(cplx_t<R> *tile, double *tab, 
             }
         }
         double *dst = tb == 0 ? A : tb == 1 ? B : Rt + (tb - 2) * 128;
-        if (tb != 1 || (uint32_t)lane < nb)
+        if ((tb != 1 && !dtab) || (uint32_t)lane < nb)
             dst[lane] = acc0;
         if (ne > 1)
             dst[lane + 64] = acc1;
@@ -413,8 +443,12 @@ __device__ __forceinline__ void diag_sweep_tables(cplx_t<R> *tile, double *tab, 
     for (uint32_t j = threadIdx.x; j < T; j += THREADS) {
         const uint32_t u = j & 63u, v = j >> 6;
         double t = th0 + A[u] + B[v];
-        for (int q = 0; q < Hb; ++q)
-            t += Rt[q * 128 + ((v >> q) & 1u) * 64 + u];
+        if (use_d) {  // uniform
+            t += ((u & um) == uv) ? Rt[v] : 0.0;
+        } else if (have_r) {
+            for (int q = 0; q < Hb; ++q)
+                t += Rt[q * 128 + ((v >> q) & 1u) * 64 + u];
+        }
         if (any_rest) {  // uniform
             for (int q = i; q < e; ++q) {
                 const TileGate &d = gates.get(q);
