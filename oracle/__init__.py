@@ -77,6 +77,17 @@ def lib():
         L.or_q16_decode.restype = None
         L.or_q16_apply_gate.argtypes = [i16p, i8p, ctypes.c_int, ctypes.c_int, u64, u64, dp]
         L.or_q16_apply_gate.restype = None
+        i32p = ctypes.POINTER(ctypes.c_int32)
+        L.or_q32_scale.argtypes = [ctypes.c_double]
+        L.or_q32_scale.restype = ctypes.c_int
+        L.or_q32_code.argtypes = [ctypes.c_double, ctypes.c_int]
+        L.or_q32_code.restype = ctypes.c_int32
+        L.or_q32_encode.argtypes = [dp, ctypes.c_int, i32p, i8p]
+        L.or_q32_encode.restype = None
+        L.or_q32_decode.argtypes = [i32p, i8p, ctypes.c_int, dp]
+        L.or_q32_decode.restype = None
+        L.or_q32_apply_gate.argtypes = [i32p, i8p, ctypes.c_int, ctypes.c_int, u64, u64, dp]
+        L.or_q32_apply_gate.restype = None
         L.or_num_threads.argtypes = []
         L.or_num_threads.restype = ctypes.c_int
         _lib = L
@@ -291,6 +302,69 @@ def q16_run_circuit(circ, params: Optional[np.ndarray] = None, buf0: Optional[np
     for g in circ.gates:
         U = gate_matrix(g.kind, gate_angle(g, params), g.matrix)
         q16_apply_gate(buf, n, g.target, g.controls, g.values, U)
+    return buf
+
+
+# 32-bit codes (same blocks and scale rule, computed in double; see the
+# comment above or_q32_scale in sv_oracle.c)
+
+def q32_nbytes(n: int) -> int:
+    """Bytes of an n-qubit 32-bit fixed-point state: 8 per amplitude, 1 per block."""
+    return (8 << n) + q16_blocks(n)
+
+
+def q32_views(buf: np.ndarray, n: int):
+    """(codes int32 [2^n, 2], scales int8 [blocks]) views of a state buffer."""
+    assert buf.dtype == np.uint8 and buf.size == q32_nbytes(n)
+    N = 1 << n
+    return buf[:8 * N].view(np.int32).reshape(N, 2), buf[8 * N:].view(np.int8)
+
+
+def _i32p(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+
+
+def q32_scale(m: float) -> int:
+    return int(lib().or_q32_scale(float(m)))
+
+
+def q32_code(v: float, s: int) -> int:
+    return int(lib().or_q32_code(float(v), int(s)))
+
+
+def q32_encode(psi: np.ndarray, n: int) -> np.ndarray:
+    psi = np.ascontiguousarray(psi, dtype=np.complex128)
+    assert psi.size == (1 << n)
+    buf = np.zeros(q32_nbytes(n), dtype=np.uint8)
+    codes, scales = q32_views(buf, n)
+    lib().or_q32_encode(_dptr(psi.view(np.float64)), n, _i32p(codes), _i8p(scales))
+    return buf
+
+
+def q32_decode(buf: np.ndarray, n: int) -> np.ndarray:
+    codes, scales = q32_views(buf, n)
+    psi = np.empty(1 << n, dtype=np.complex128)
+    lib().or_q32_decode(_i32p(codes), _i8p(scales), n, _dptr(psi.view(np.float64)))
+    return psi
+
+
+def q32_apply_gate(buf: np.ndarray, n: int, target: int, controls: Sequence[int],
+                   values: Sequence[int], U: np.ndarray) -> np.ndarray:
+    codes, scales = q32_views(buf, n)
+    cm, cv = masks(controls, values)
+    u = _u8(U)
+    lib().or_q32_apply_gate(_i32p(codes), _i8p(scales), n, int(target), cm, cv, _dptr(u))
+    return buf
+
+
+def q32_run_circuit(circ, params: Optional[np.ndarray] = None, buf0: Optional[np.ndarray] = None) -> np.ndarray:
+    n = circ.n
+    if params is None:
+        params = circ.params
+    buf = q32_encode(zero_state(n), n) if buf0 is None else np.array(buf0, dtype=np.uint8, copy=True)
+    for g in circ.gates:
+        U = gate_matrix(g.kind, gate_angle(g, params), g.matrix)
+        q32_apply_gate(buf, n, g.target, g.controls, g.values, U)
     return buf
 
 

@@ -408,3 +408,108 @@ void or_q16_apply_gate(int16_t *q, int8_t *s, int n, int t, uint64_t cmask, uint
     free(touched);
     free(v);
 }
+
+/* ------------------------------------------------------------------------
+ * Block-scaled 32-bit fixed-point states: the same layout and block rule
+ * with 32-bit codes, computed in double.  Each component is a signed
+ * 32-bit code; the 64 amplitudes of a block share one int8 scale s, so a
+ * value is code * 2^s.  Encoding a block: m = largest |component| (double),
+ * m = f 2^e with f in [0.5, 1), s = e - 31 clamped to [-128, 96] (-128 for
+ * m = 0), codes rounded to nearest, ties to even, saturated to
+ * +-(2^31 - 1); the largest code magnitude of a block is then in
+ * [2^30, 2^31 - 1].  A gate decodes (exact in double), applies the pair
+ * update of Sec. III in double with the fma order below, and re-encodes
+ * every block holding an element of an updated pair.
+ * ------------------------------------------------------------------------ */
+
+int or_q32_scale(double m)
+{
+    int e = 0;
+    if (m == 0.0)
+        return -128;
+    (void)frexp(m, &e);
+    int s = e - 31;
+    if (s < -128)
+        s = -128;
+    if (s > 96)
+        s = 96;
+    return s;
+}
+
+int32_t or_q32_code(double v, int s)
+{
+    double r = rint(ldexp(v, -s));
+    if (r > 2147483647.0)
+        r = 2147483647.0;
+    if (r < -2147483647.0)
+        r = -2147483647.0;
+    return (int32_t)r;
+}
+
+static void q32_encode_block(const double *v, int64_t len, int32_t *q, int8_t *s)
+{
+    double m = 0.0;
+    for (int64_t i = 0; i < 2 * len; ++i) {
+        const double a = fabs(v[i]);
+        if (a > m)
+            m = a;
+    }
+    const int sc = or_q32_scale(m);
+    for (int64_t i = 0; i < 2 * len; ++i)
+        q[i] = or_q32_code(v[i], sc);
+    *s = (int8_t)sc;
+}
+
+void or_q32_encode(const double *psi, int n, int32_t *q, int8_t *s)
+{
+    const int64_t N = (int64_t)1 << n, B = q16_block_len(n), nb = N / B;
+#pragma omp parallel for schedule(static)
+    for (int64_t b = 0; b < nb; ++b)
+        q32_encode_block(psi + 2 * b * B, B, q + 2 * b * B, s + b);
+}
+
+void or_q32_decode(const int32_t *q, const int8_t *s, int n, double *psi)
+{
+    const int64_t N = (int64_t)1 << n, B = q16_block_len(n);
+    for (int64_t k = 0; k < N; ++k) {
+        const int sc = s[k / B];
+        psi[2 * k] = ldexp((double)q[2 * k], sc);
+        psi[2 * k + 1] = ldexp((double)q[2 * k + 1], sc);
+    }
+}
+
+/* u * x + v * y in double, one rounding chain per component, in the order
+ * of q16_mac above. */
+static void q32_mac(const double *u, const double *v, double xr, double xi, double yr, double yi,
+                    double *outr, double *outi)
+{
+    *outr = fma(u[0], xr, fma(-u[1], xi, fma(v[0], yr, -(v[1] * yi))));
+    *outi = fma(u[0], xi, fma(u[1], xr, fma(v[0], yi, v[1] * yr)));
+}
+
+void or_q32_apply_gate(int32_t *q, int8_t *s, int n, int t, uint64_t cmask, uint64_t cvals,
+                       const double *U)
+{
+    const int64_t N = (int64_t)1 << n, B = q16_block_len(n), nb = N / B;
+    const int64_t st = (int64_t)1 << t;
+    double *v = (double *)malloc(sizeof(double) * 2 * (size_t)N);
+    char *touched = (char *)calloc((size_t)nb, 1);
+    or_q32_decode(q, s, n, v);
+    for (int64_t k = 0; k < N; ++k) {
+        if (k & st)
+            continue;
+        if (((uint64_t)k & cmask) != cvals)
+            continue;
+        const int64_t k2 = k + st;
+        const double xr = v[2 * k], xi = v[2 * k + 1], yr = v[2 * k2], yi = v[2 * k2 + 1];
+        q32_mac(U, U + 2, xr, xi, yr, yi, &v[2 * k], &v[2 * k + 1]);
+        q32_mac(U + 4, U + 6, xr, xi, yr, yi, &v[2 * k2], &v[2 * k2 + 1]);
+        touched[k / B] = 1;
+        touched[k2 / B] = 1;
+    }
+    for (int64_t b = 0; b < nb; ++b)
+        if (touched[b])
+            q32_encode_block(v + 2 * b * B, B, q + 2 * b * B, s + b);
+    free(touched);
+    free(v);
+}

@@ -594,3 +594,106 @@ def test_q16_qft_within_rigorous_bound():
     G = len(circ.gates)
     assert err <= (G + 1) * (math.sqrt(128) * 2.0 ** -15 + 1e-6)
     assert err < 5e-3  # far inside the bound in practice
+
+
+# ---------------------------------------------------------------- 32-bit fixed point
+#
+# The same block rule with 32-bit codes in double: pinned like the 16-bit
+# codes, by closed forms, exactly representable blocks and bounds.
+
+def test_q32_basis_and_hadamard_closed_forms():
+    n = 8
+    buf = oracle.q32_encode(oracle.zero_state(n), n)
+    codes, scales = oracle.q32_views(buf, n)
+    assert tuple(codes[0]) == (1 << 30, 0) and scales[0] == -30
+    assert not codes[1:].any() and (scales[1:] == -128).all()
+    oracle.q32_apply_gate(buf, n, 0, [], [], np.array([[1, 1], [1, -1]]) / math.sqrt(2))
+    # 2^31 / sqrt(2) = 1518500249.988...
+    assert tuple(codes[0]) == (1518500250, 0) and tuple(codes[1]) == (1518500250, 0) and scales[0] == -31
+    assert oracle.q32_nbytes(3) == 8 * 8 + 1
+
+
+def test_q32_exactly_representable_blocks_and_error_bound():
+    rng = np.random.default_rng(50)
+    n = 9
+    N, B = 1 << n, 64
+    codes = rng.integers(-(2 ** 31) + 1, 2 ** 31, size=(N, 2)).astype(np.int64)
+    scales = rng.integers(-90, -40, size=N // B)
+    for b in range(N // B):
+        blk = codes[b * B:(b + 1) * B]
+        big = int(rng.integers(2 ** 30, 2 ** 31))
+        blk[int(rng.integers(0, B)), 0] = big
+        np.clip(blk, -big, big, out=blk)
+    vals = codes.astype(np.float64) * np.ldexp(1.0, np.repeat(scales, B))[:, None]
+    psi = vals[:, 0] + 1j * vals[:, 1]
+    buf = oracle.q32_encode(psi, n)
+    c2, s2 = oracle.q32_views(buf, n)
+    assert np.array_equal(c2, codes) and np.array_equal(s2, scales)
+    assert np.array_equal(oracle.q32_decode(buf, n), psi)
+    # random state: half-step error, 31 significant bits, decode-encode identity
+    psi = _rand_state(n, 51) * np.repeat(10.0 ** rng.uniform(-20, 0, size=N // B), B)
+    buf = oracle.q32_encode(psi, n)
+    codes, scales = oracle.q32_views(buf, n)
+    dec = oracle.q32_decode(buf, n)
+    for b in range(N // B):
+        blk = slice(b * B, (b + 1) * B)
+        m = max(np.abs(psi[blk].real).max(), np.abs(psi[blk].imag).max())
+        assert 2 ** 30 <= np.abs(codes[blk]).max() <= 2 ** 31 - 1
+        step = math.ldexp(1.0, int(scales[b]))
+        assert step <= m * 2.0 ** -30
+        assert np.abs(dec[blk] - psi[blk]).max() <= step / 2 * math.sqrt(2)
+    assert np.array_equal(oracle.q32_encode(dec, n), buf)
+    # saturation and the smallest scale
+    v = 1 - 2.0 ** -53
+    assert oracle.q32_code(v, oracle.q32_scale(v)) == 2 ** 31 - 1
+    tiny = np.zeros(64, dtype=np.complex128)
+    tiny[5] = 2.0 ** -120
+    bt = oracle.q32_encode(tiny, 6)
+    ct, st = oracle.q32_views(bt, 6)
+    assert st[0] == -128 and ct[5, 0] == 256 and oracle.q32_decode(bt, 6)[5] == 2.0 ** -120
+
+
+def test_q32_permutation_gates_exact_and_gate_within_quantisation():
+    n = 9
+    X = np.array([[0, 1], [1, 0]])
+    buf0 = oracle.q32_encode(_rand_state(n, 52), n)
+    c0, s0 = oracle.q32_views(buf0, n)
+    k = np.arange(1 << n)
+    buf = oracle.q32_apply_gate(buf0.copy(), n, 7, [8], [1], X)
+    c, s = oracle.q32_views(buf, n)
+    assert np.array_equal(c, c0[np.where(k & 256, k ^ 128, k)])
+    bi = np.arange(len(s0))
+    assert np.array_equal(s, s0[np.where(bi & 4, bi ^ 2, bi)])
+    buf = oracle.q32_apply_gate(buf0.copy(), n, 3, [], [], X)
+    assert np.array_equal(oracle.q32_views(buf, n)[0], c0[k ^ 8])
+    # one Haar gate: within half a step (<= m 2^-31) plus double rounding
+    B = 64
+    for t, ctrls, vals in ((0, (), ()), (7, (2, 8), (1, 0)), (4, (6,), (1,))):
+        U = _rand_unitary(53 + t)
+        x = oracle.q32_decode(buf0, n)
+        exact = oracle.apply_gate(x.copy(), n, t, ctrls, vals, U)
+        out = oracle.q32_decode(oracle.q32_apply_gate(buf0.copy(), n, t, ctrls, vals, U), n)
+        cm, cv = oracle.masks(ctrls, vals)
+        touched = set(k[(k & cm) == cv] // B)
+        for b in range(len(x) // B):
+            blk = slice(b * B, (b + 1) * B)
+            if b not in touched:
+                assert np.array_equal(out[blk], x[blk])
+                continue
+            m = max(np.abs(exact[blk].real).max(), np.abs(exact[blk].imag).max())
+            err = max(np.abs(out[blk].real - exact[blk].real).max(), np.abs(out[blk].imag - exact[blk].imag).max())
+            assert err <= m * 2.0 ** -31 * (1 + 1e-9) + 1e-15 * np.abs(x).max(), (t, b, err)
+
+
+def test_q32_qft_within_rigorous_bound():
+    n = 10
+    circ = W.qft(n)
+    psi0 = _rand_state(n, 54)
+    buf = oracle.q32_run_circuit(circ, buf0=oracle.q32_encode(psi0, n))
+    N = 1 << n
+    rev = np.array([int(format(i, "0%db" % n)[::-1], 2) for i in range(N)])
+    want = np.fft.ifft(psi0[rev]) * math.sqrt(N)
+    err = np.linalg.norm(oracle.q32_decode(buf, n) - want)
+    G = len(circ.gates)
+    assert err <= (G + 1) * (math.sqrt(128) * 2.0 ** -31 + 1e-13)
+    assert err < 1e-7
