@@ -49,25 +49,29 @@ typedef enum sv_status {
     SV_ENOTSUP = -4  /* valid request the library does not handle */
 } sv_status;
 
-/* SV_CQ16: block-scaled 16-bit fixed-point complex, the fixed-point state
- * precision the paper lists as future work (Sec. V).  Layout: 2^n
- * amplitudes of two int16 codes (re, im; 4 bytes each), followed by one int8
- * scale per block of 64 consecutive amplitudes (a single block of all 2^n
- * when n < 6); a component's value is code * 2^scale.  Encoding a block
- * takes m, its largest |component|, writes m = f 2^e with f in [0.5, 1),
- * uses the scale e - 15 (clamped to [-126, 112]; -126 for an all-zero block)
- * and rounds each value / 2^scale to the nearest code, ties to even,
- * saturated to [-32767, 32767].  Storage is sv_state_bytes(n, SV_CQ16) bytes,
- * 16-byte aligned.  Fixed-point states are taken by sv_alloc, sv_free,
- * sv_init, sv_copy_state, sv_convert, sv_apply_gate(_masks), sv_gate_plan,
- * and circuits without SV_FUSE, SV_DENSE or SV_REMAP; every other call
- * returns SV_ENOTSUP for them. */
-typedef enum sv_dtype { SV_C128 = 0, SV_C64 = 1, SV_CQ16 = 2 } sv_dtype;
+/* SV_CQ16, SV_CQ32: block-scaled fixed-point complex with 16-bit or 32-bit
+ * codes, the fixed-point state precision the paper lists as future work
+ * (Sec. V).  Layout: 2^n amplitudes of two signed codes (re, im; 4 bytes
+ * per amplitude for SV_CQ16, 8 for SV_CQ32), followed by one int8 scale per
+ * block of 64 consecutive amplitudes (a single block of all 2^n when n < 6);
+ * a component's value is code * 2^scale.  Encoding a block takes m, its
+ * largest |component|, writes m = f 2^e with f in [0.5, 1), uses the scale
+ * e - B (B = 15 for SV_CQ16, 31 for SV_CQ32; clamped to [-126, 112] and
+ * [-128, 96], the minimum for an all-zero block) and rounds each
+ * value / 2^scale to the nearest code, ties to even, saturated to
+ * +-(2^B - 1).  Arithmetic is in float for SV_CQ16 and in double for
+ * SV_CQ32.  Storage is sv_state_bytes(n, dtype) bytes, 16-byte aligned.
+ * Fixed-point states are taken by sv_alloc, sv_free, sv_init,
+ * sv_copy_state, sv_convert, sv_apply_gate(_masks), sv_gate_plan, and
+ * circuits without SV_FUSE, SV_DENSE or SV_REMAP; every other call returns
+ * SV_ENOTSUP for them. */
+typedef enum sv_dtype { SV_C128 = 0, SV_C64 = 1, SV_CQ16 = 2, SV_CQ32 = 3 } sv_dtype;
 
 /* Largest supported register: 2^34 complex128 amplitudes is 256 GiB. */
 #define SV_MAX_QUBITS_C128 34
 #define SV_MAX_QUBITS_C64 35
 #define SV_MAX_QUBITS_CQ16 36
+#define SV_MAX_QUBITS_CQ32 35
 
 typedef struct sv_state {
     void *data;    /* device pointer to the state's storage, caller-owned */
@@ -98,16 +102,18 @@ int sv_init(const sv_state_t *s, uint64_t basis_index, sv_stream_t st);
 int sv_copy_state(const sv_state_t *dst, const sv_state_t *src, sv_stream_t st);
 
 /* Bytes of storage of an n-qubit state of the given dtype: 2^n * 16
- * (complex128), 2^n * 8 (complex64), 2^n * 4 + max(1, 2^n / 64) (SV_CQ16).
- * Host-only. */
+ * (complex128), 2^n * 8 (complex64), 2^n * 4 + max(1, 2^n / 64) (SV_CQ16),
+ * 2^n * 8 + max(1, 2^n / 64) (SV_CQ32).  Host-only. */
 int sv_state_bytes(int n, int dtype, uint64_t *bytes);
 
-/* Convert src into dst, two states of the same n and any dtypes, in
- * non-overlapping buffers (same dtype: a copy).  complex128 -> complex64
- * rounds each component to nearest; to SV_CQ16, each component is first
- * rounded to float and every block is encoded as described at SV_CQ16; from
- * SV_CQ16 the decoded values code * 2^scale are exact in either float
- * type. */
+/* Convert src into dst, two states of the same n, in non-overlapping
+ * buffers (same dtype: a copy).  complex128 -> complex64 rounds each
+ * component to nearest.  To a fixed-point dtype each component is first
+ * taken to the format's arithmetic type (float for SV_CQ16: rounded to
+ * nearest; double for SV_CQ32: exact) and every block is encoded as
+ * described at SV_CQ16; decoded values code * 2^scale are exact in double
+ * (and in float from SV_CQ16).  Between the two fixed-point dtypes:
+ * SV_ENOTSUP (convert through complex128). */
 int sv_convert(const sv_state_t *dst, const sv_state_t *src, sv_stream_t st);
 
 /* Kernel selection for sv_apply_gate. */
@@ -136,13 +142,13 @@ typedef enum sv_mode {
  *   mode        sv_mode; every mode gives the same result
  * Scheduled modes launch 2^(n-1-ncontrols) pair updates; SV_MODE_MASKED
  * launches 2^(n-1) and skips the pairs whose controls fail.
- * SV_CQ16 states: the 64-amplitude block is the unit of work.  Controls on
- * qubits >= 6 are scheduled over the block index (2^(n-7-c_high) block pairs
- * for a target >= 6, 2^(n-6-c_high) blocks below), controls on qubits < 6
- * are tested per amplitude; SV_MODE_MASKED visits every block (pair) and
+ * Fixed-point states: the 64-amplitude block is the unit of work.  Controls
+ * on qubits >= 6 are scheduled over the block index (2^(n-7-c_high) block
+ * pairs for a target >= 6, 2^(n-6-c_high) blocks below), controls on qubits
+ * < 6 are tested per amplitude; SV_MODE_MASKED visits every block (pair) and
  * tests every control, every other mode is the scheduled kernel.  Each
- * visited block is decoded to float, updated with the float matrix
- * (U rounded to float), and re-encoded as described at SV_CQ16; other blocks
+ * visited block is decoded, updated (SV_CQ16: float, U rounded to float;
+ * SV_CQ32: double), and re-encoded as described at SV_CQ16; other blocks
  * keep their bytes. */
 int sv_apply_gate(const sv_state_t *s, int target, const int32_t *controls,
                   int ncontrols, uint64_t ctrl_vals, const double *U, int mode,
@@ -268,9 +274,9 @@ typedef struct sv_circuit sv_circuit_t;
  * sv_circuit_run (every gate's param must be < nparams).  Validation covers
  * every gate before anything is allocated, so an error names the first bad
  * gate (its index is in the message) and creates nothing.  The returned
- * handle is released with sv_circuit_destroy.  SV_CQ16 circuits run one
- * block-scaled gate kernel per gate: flags may hold SV_GRAPH and SV_MASKED
- * only (SV_ENOTSUP otherwise). */
+ * handle is released with sv_circuit_destroy.  Fixed-point circuits run
+ * one block-scaled gate kernel per gate: flags may hold SV_GRAPH and
+ * SV_MASKED only (SV_ENOTSUP otherwise). */
 int sv_circuit_create(int n, int dtype, const sv_gate_t *gates, int ngates, int nparams, int flags,
                       sv_circuit_t **out);
 

@@ -21,7 +21,7 @@ if not os.path.exists(LIB_PATH):
 _L = ctypes.CDLL(LIB_PATH)
 
 SV_OK, SV_EINVAL, SV_ENOMEM, SV_EHIP, SV_ENOTSUP = 0, -1, -2, -3, -4
-SV_C128, SV_C64, SV_CQ16 = 0, 1, 2
+SV_C128, SV_C64, SV_CQ16, SV_CQ32 = 0, 1, 2, 3
 SV_MODE_AUTO, SV_MODE_MASKED, SV_MODE_PAIR, SV_MODE_WAVE, SV_MODE_TILE = 0, 1, 2, 3, 4
 MODES = {"auto": SV_MODE_AUTO, "masked": SV_MODE_MASKED, "pair": SV_MODE_PAIR,
          "wave": SV_MODE_WAVE, "tile": SV_MODE_TILE}
@@ -112,6 +112,30 @@ def q16_nbytes(n: int) -> int:
     return (4 << n) + max(1, (1 << n) // 64)
 
 
+def fixed_nbytes(n: int, dtype: int = SV_CQ16) -> int:
+    """Bytes of an n-qubit fixed-point state (SV_CQ16: 4 per amplitude,
+    SV_CQ32: 8), then one scale byte per 64 amplitudes."""
+    per = {SV_CQ16: 4, SV_CQ32: 8}[dtype]
+    return (per << n) + max(1, (1 << n) // 64)
+
+
+class FixedState:
+    """A fixed-point state: its bytes (a contiguous uint8 CUDA tensor), n and
+    dtype (SV_CQ16 or SV_CQ32).  Accepted wherever a state is."""
+
+    def __init__(self, n: int, dtype: int = SV_CQ16, data=None, device="cuda"):
+        nbytes = fixed_nbytes(n, dtype)
+        if data is None:
+            data = _torch().empty(nbytes, dtype=_torch().uint8, device=device)
+        if data.dtype != _torch().uint8 or data.numel() != nbytes:
+            raise ValueError("fixed-point state of %d qubits needs %d uint8 bytes" % (n, nbytes))
+        self.data, self.n, self.dtype = data, int(n), int(dtype)
+
+    @property
+    def device(self):
+        return self.data.device
+
+
 def _q16_qubits(nbytes: int) -> int:
     for n in range(1, 37):
         if q16_nbytes(n) == nbytes:
@@ -129,6 +153,10 @@ def state_view(t, n: Optional[int] = None) -> sv_state_t:
     or uint8 of q16_nbytes(n) bytes for a fixed-point state."""
     if isinstance(t, sv_state_t):
         return t
+    if isinstance(t, FixedState):
+        if not t.data.is_cuda or not t.data.is_contiguous():
+            raise ValueError("state must be a contiguous CUDA tensor")
+        return sv_state_t(t.data.data_ptr(), t.n, t.dtype)
     if not t.is_cuda or not t.is_contiguous():
         raise ValueError("state must be a contiguous CUDA tensor")
     numel = t.numel()

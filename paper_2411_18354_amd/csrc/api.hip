@@ -49,15 +49,15 @@ Expand make_expand(int n, const std::vector<int> &positions, const std::vector<i
 int validate_state(const sv_state_t *s, bool allow_fixed) {
     if (!s)
         return fail(SV_EINVAL, "state is NULL");
-    if (s->dtype != SV_C128 && s->dtype != SV_C64 && s->dtype != SV_CQ16)
+    if (!known_dtype(s->dtype))
         return fail(SV_EINVAL, "unknown dtype %d", s->dtype);
-    if (s->dtype == SV_CQ16 && !allow_fixed)
-        return fail(SV_ENOTSUP, "this call does not take fixed-point (SV_CQ16) states");
+    if (is_fixed(s->dtype) && !allow_fixed)
+        return fail(SV_ENOTSUP, "this call does not take fixed-point (SV_CQ16, SV_CQ32) states");
     if (s->n < 1 || s->n > max_qubits(s->dtype))
         return fail(SV_EINVAL, "n=%d outside [1, %d]", s->n, max_qubits(s->dtype));
     if (!s->data)
         return fail(SV_EINVAL, "state data is NULL");
-    const size_t align = s->dtype == SV_CQ16 ? 16 : amp_bytes(s->dtype);
+    const size_t align = is_fixed(s->dtype) ? 16 : amp_bytes(s->dtype);
     if (((uintptr_t)s->data) % align)
         return fail(SV_EINVAL, "state data %p not aligned to %zu bytes", s->data, align);
     return SV_OK;
@@ -173,7 +173,7 @@ int sv_alloc(sv_state_t *s, int n, int dtype) {
     clear_error();
     if (!s)
         return fail(SV_EINVAL, "state is NULL");
-    if (dtype != SV_C128 && dtype != SV_C64 && dtype != SV_CQ16)
+    if (!known_dtype(dtype))
         return fail(SV_EINVAL, "unknown dtype %d", dtype);
     if (n < 1 || n > max_qubits(dtype))
         return fail(SV_EINVAL, "n=%d outside [1, %d]", n, max_qubits(dtype));
@@ -210,8 +210,8 @@ int sv_init(const sv_state_t *s, uint64_t basis_index, sv_stream_t st) {
     SV_TRY(device_info(&di));
     const uint64_t want = (N + 255) / 256;
     const unsigned grid = (unsigned)std::min<uint64_t>(want, (uint64_t)di.num_cus * 16);
-    if (s->dtype == SV_CQ16)
-        return launch_q16_basis(s->data, s->n, basis_index, grid, (hipStream_t)st);
+    if (is_fixed(s->dtype))
+        return launch_fixed_basis(s->data, s->n, s->dtype, basis_index, grid, (hipStream_t)st);
     if (s->dtype == SV_C128)
         hipLaunchKernelGGL(k_basis<double>, dim3(grid), dim3(256), 0, (hipStream_t)st,
                            (double2 *)s->data, N, basis_index);

@@ -178,8 +178,8 @@ static int plan_circuit(sv_circuit *c, std::vector<TileGate> &tiles, std::vector
         p.first = p.count = 0;
         const sv_gate_t &g = c->gates[i];
         GateSpec gs{c->n, g.target, g.ctrl_mask, g.ctrl_vals};
-        if (c->dtype == SV_CQ16)
-            SV_TRY(make_q16_plan(gs, masked, &p.q16));
+        if (is_fixed(c->dtype))
+            SV_TRY(make_fixed_plan(gs, c->dtype, masked, &p.fx));
         else
             SV_TRY(make_gate_plan(gs, c->dtype, masked ? SV_MODE_MASKED : SV_MODE_AUTO, &p.plan));
         c->passes.push_back(p);
@@ -411,7 +411,7 @@ static int launch_tile_pass(cplx_t<R> *psi, const TileMap &tm_in, const DeviceGa
 int circuit_create(int n, int dtype, const sv_gate_t *gates, int ngates, int nparams, int flags, bool async,
                    hipStream_t st, int m_cap, sv_circuit **out) {
     *out = nullptr;
-    if (dtype != SV_C128 && dtype != SV_C64 && dtype != SV_CQ16)
+    if (!known_dtype(dtype))
         return fail(SV_EINVAL, "unknown dtype %d", dtype);
     if (n < 1 || n > max_qubits(dtype))
         return fail(SV_EINVAL, "n=%d outside [1, %d]", n, max_qubits(dtype));
@@ -421,8 +421,8 @@ int circuit_create(int n, int dtype, const sv_gate_t *gates, int ngates, int npa
         return fail(SV_EINVAL, "nparams %d < 0", nparams);
     if (flags & ~(SV_FUSE | SV_GRAPH | SV_MASKED | SV_DENSE | SV_REMAP))
         return fail(SV_EINVAL, "unknown flags 0x%x", flags);
-    if (dtype == SV_CQ16 && (flags & (SV_FUSE | SV_DENSE | SV_REMAP)))
-        return fail(SV_ENOTSUP, "fixed-point (SV_CQ16) circuits take SV_GRAPH and SV_MASKED only (flags 0x%x)",
+    if (is_fixed(dtype) && (flags & (SV_FUSE | SV_DENSE | SV_REMAP)))
+        return fail(SV_ENOTSUP, "fixed-point (SV_CQ16, SV_CQ32) circuits take SV_GRAPH and SV_MASKED only (flags 0x%x)",
                     flags);
     for (int i = 0; i < ngates; ++i)
         SV_TRY(validate_circuit_gate(n, nparams, gates[i], i));
@@ -461,7 +461,7 @@ int circuit_create(int n, int dtype, const sv_gate_t *gates, int ngates, int npa
     }
     // large LDS tiles need the per-kernel limit raised before any launch
     const size_t lds = fused_lds(c->m, dtype);
-    if (lds > 65536 && dtype != SV_CQ16) {
+    if (lds > 65536 && !is_fixed(dtype)) {
         if (dtype == SV_C128)
             SV_HIP_TRY(hipFuncSetAttribute((const void *)k_tile<double, 512, DeviceGates>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
@@ -515,16 +515,16 @@ template <typename R> static int enqueue(sv_circuit *c, cplx_t<R> *psi, const do
 
 // Fixed-point state: one block-scaled gate kernel per gate, matrices from
 // the plan's device table (parameterised ones written there first).
-static int enqueue_q16(sv_circuit *c, void *state, const double *params, hipStream_t st) {
+static int enqueue_fixed(sv_circuit *c, void *state, const double *params, hipStream_t st) {
     SV_TRY(circuit_param_mats(c, params, st));
     for (const Pass &p : c->passes)
-        SV_TRY(launch_q16_gate(state, p.q16, nullptr, c->d_mats + (size_t)8 * p.gate, st));
+        SV_TRY(launch_fixed_gate(state, p.fx, nullptr, c->d_mats + (size_t)8 * p.gate, st));
     return SV_OK;
 }
 
 static int enqueue_any(sv_circuit *c, const sv_state_t *s, const double *params, hipStream_t st) {
-    if (c->dtype == SV_CQ16)
-        return enqueue_q16(c, s->data, params, st);
+    if (is_fixed(c->dtype))
+        return enqueue_fixed(c, s->data, params, st);
     if (c->dtype == SV_C128)
         return enqueue<double>(c, reinterpret_cast<double2 *>(s->data), params, st);
     return enqueue<float>(c, reinterpret_cast<float2 *>(s->data), params, st);

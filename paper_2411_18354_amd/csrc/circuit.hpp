@@ -18,7 +18,7 @@ struct Pass {
     int gate;        // single: gate index
     int first, count;  // fused: descriptors [first, first + count)
     GatePlan plan;   // single
-    Q16Plan q16;     // single, fixed-point state
+    FixedPlan fx;    // single, fixed-point state
     TileMap tm;      // fused: which qubits a tile spans
 };
 

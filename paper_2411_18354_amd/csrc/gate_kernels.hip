@@ -455,12 +455,12 @@ static int launch_tile1(const sv_state_t *s, const GateSpec &g, const double *U,
 }
 
 int launch_gate(const sv_state_t *s, const GateSpec &g, const double *U, int mode, hipStream_t st) {
-    if (s->dtype == SV_CQ16) {
+    if (is_fixed(s->dtype)) {
         if (mode < SV_MODE_AUTO || mode > SV_MODE_TILE)
             return fail(SV_EINVAL, "unknown mode %d", mode);
-        Q16Plan q;
-        SV_TRY(make_q16_plan(g, mode == SV_MODE_MASKED, &q));
-        return launch_q16_gate(s->data, q, U, nullptr, st);
+        FixedPlan q;
+        SV_TRY(make_fixed_plan(g, s->dtype, mode == SV_MODE_MASKED, &q));
+        return launch_fixed_gate(s->data, q, U, nullptr, st);
     }
     GatePlan p;
     SV_TRY(make_gate_plan(g, s->dtype, mode, &p));
@@ -506,19 +506,19 @@ int sv_apply_gate(const sv_state_t *s, int target, const int32_t *controls, int 
 int sv_gate_plan(int n, int dtype, int target, uint64_t ctrl_mask, uint64_t ctrl_vals, int mode, char *kernel,
                  int kernel_len, uint64_t *iterations) {
     clear_error();
-    if (dtype != SV_C128 && dtype != SV_C64 && dtype != SV_CQ16)
+    if (!known_dtype(dtype))
         return fail(SV_EINVAL, "unknown dtype %d", dtype);
     if (n < 1 || n > max_qubits(dtype))
         return fail(SV_EINVAL, "n=%d outside [1, %d]", n, max_qubits(dtype));
     GateSpec g{n, target, ctrl_mask, ctrl_vals};
     SV_TRY(validate_gate(g));
     std::string name;
-    if (dtype == SV_CQ16) {
+    if (is_fixed(dtype)) {
         if (mode < SV_MODE_AUTO || mode > SV_MODE_TILE)
             return fail(SV_EINVAL, "unknown mode %d", mode);
-        Q16Plan q;
-        SV_TRY(make_q16_plan(g, mode == SV_MODE_MASKED, &q));
-        name = q16_plan_name(q, "MatVal");
+        FixedPlan q;
+        SV_TRY(make_fixed_plan(g, dtype, mode == SV_MODE_MASKED, &q));
+        name = fixed_plan_name(q, "MatVal");
         if (iterations)
             *iterations = q.units;
     } else {

@@ -52,16 +52,21 @@ template <> struct cplx<double> { using type = double2; };
 template <> struct cplx<float> { using type = float2; };
 template <typename R> using cplx_t = typename cplx<R>::type;
 
-inline size_t amp_bytes(int dtype) { return dtype == SV_C128 ? 16 : dtype == SV_C64 ? 8 : 4; }
+inline bool known_dtype(int dtype) { return dtype >= SV_C128 && dtype <= SV_CQ32; }
+inline bool is_fixed(int dtype) { return dtype == SV_CQ16 || dtype == SV_CQ32; }
+inline size_t amp_bytes(int dtype) { return dtype == SV_C128 ? 16 : dtype == SV_CQ16 ? 4 : 8; }
 inline int max_qubits(int dtype) {
-    return dtype == SV_C128 ? SV_MAX_QUBITS_C128 : dtype == SV_C64 ? SV_MAX_QUBITS_C64 : SV_MAX_QUBITS_CQ16;
+    return dtype == SV_C128   ? SV_MAX_QUBITS_C128
+           : dtype == SV_C64  ? SV_MAX_QUBITS_C64
+           : dtype == SV_CQ16 ? SV_MAX_QUBITS_CQ16
+                              : SV_MAX_QUBITS_CQ32;
 }
-// Fixed-point (SV_CQ16) states: 64 amplitudes share one int8 scale, stored
-// after the 2^n code pairs.
+// Fixed-point states: 64 amplitudes share one int8 scale, stored after the
+// 2^n code pairs.
 constexpr int kQBlockBits = 6;
 inline uint64_t q16_blocks(int n) { return n >= kQBlockBits ? (1ull << (n - kQBlockBits)) : 1ull; }
 inline size_t state_bytes(int n, int dtype) {
-    return ((size_t)1 << n) * amp_bytes(dtype) + (dtype == SV_CQ16 ? (size_t)q16_blocks(n) : 0);
+    return ((size_t)1 << n) * amp_bytes(dtype) + (is_fixed(dtype) ? (size_t)q16_blocks(n) : 0);
 }
 
 // 2x2 gate matrix in the compute precision: a, b, c, d as (re, im).
@@ -123,7 +128,7 @@ struct GateSpec {
     uint64_t cvals;
 };
 
-// allow_fixed: the caller handles SV_CQ16 states (SV_ENOTSUP otherwise).
+// allow_fixed: the caller handles fixed-point states (SV_ENOTSUP otherwise).
 int validate_state(const sv_state_t *s, bool allow_fixed = false);
 int validate_gate(const GateSpec &g);
 int controls_to_mask(int n, int target, const int32_t *controls, int nc, uint64_t *mask);
@@ -180,19 +185,20 @@ int launch_plan(cplx_t<R> *psi, const GatePlan &p, const MS &ms, hipStream_t st)
 
 // Fixed-point gates (fixed.hip).  Work unit: one 64-amplitude block (target
 // below bit 6) or the pair of blocks a target >= 6 couples.
-struct Q16Plan {
+struct FixedPlan {
     Expand e;                // scheduled: block index of a unit
     uint64_t units;          // work units
     uint64_t hmask, hvals;   // masked: control bits of the block index
     uint32_t lmask, lvals;   // controls on the 6 in-block bits, tested per amplitude
     int n, target;           // target: qubit (n < 6 or target < 6), else its block-index bit
+    int dtype;               // SV_CQ16 or SV_CQ32
     bool masked, high, small;
 };
-int make_q16_plan(const GateSpec &g, bool masked, Q16Plan *p);
-std::string q16_plan_name(const Q16Plan &p, const char *matsrc);
+int make_fixed_plan(const GateSpec &g, int dtype, bool masked, FixedPlan *p);
+std::string fixed_plan_name(const FixedPlan &p, const char *matsrc);
 // U: 8 doubles on the host (by value) or, when Ud is set, on the device.
-int launch_q16_gate(void *state, const Q16Plan &p, const double *U, const double *Ud, hipStream_t st);
-int launch_q16_basis(void *state, int n, uint64_t basis, unsigned grid, hipStream_t st);
+int launch_fixed_gate(void *state, const FixedPlan &p, const double *U, const double *Ud, hipStream_t st);
+int launch_fixed_basis(void *state, int n, int dtype, uint64_t basis, unsigned grid, hipStream_t st);
 
 // Launch helpers implemented in gate_kernels.hip, shared with the circuit
 // executor.

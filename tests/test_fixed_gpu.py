@@ -1,13 +1,15 @@
-"""GPU parity of the block-scaled 16-bit fixed-point states (SV_CQ16).
+"""GPU parity of the block-scaled fixed-point states (SV_CQ16: 16-bit codes
+in float; SV_CQ32: 32-bit codes in double).
 
-The library and the oracle follow the same definition: decode to float, the
-pair update in float with a fixed fused multiply-add order, re-encode every
-block an updated pair touches.  Codes and scales are integers, so parity is
+The library and the oracle follow the same definition: decode, the pair
+update with a fixed fused multiply-add order, re-encode every block an
+updated pair touches.  Codes and scales are integers, so parity is
 bit-exact: the state bytes must be identical.  The error against the
-double-precision oracle is checked against the rigorous norm bound of the
+double-precision oracle is checked against the rigorous norm bound of each
 format and reported.
 """
 import math
+from types import SimpleNamespace
 
 import numpy as np
 import pytest
@@ -20,71 +22,105 @@ sv = pytest.importorskip("paper_2411_18354_amd")
 
 pytestmark = pytest.mark.gpu
 
+CODECS = {
+    16: SimpleNamespace(bits=16, dtype=sv.SV_CQ16, enc=oracle.q16_encode, dec=oracle.q16_decode,
+                        gate=oracle.q16_apply_gate, run=oracle.q16_run_circuit, views=oracle.q16_views,
+                        nbytes=oracle.q16_nbytes, one=16384, one_scale=-14, step=2.0 ** -15),
+    32: SimpleNamespace(bits=32, dtype=sv.SV_CQ32, enc=oracle.q32_encode, dec=oracle.q32_decode,
+                        gate=oracle.q32_apply_gate, run=oracle.q32_run_circuit, views=oracle.q32_views,
+                        nbytes=oracle.q32_nbytes, one=1 << 30, one_scale=-30, step=2.0 ** -31),
+}
 
-def _dev(buf):
-    return torch.from_numpy(np.ascontiguousarray(buf)).cuda()
+
+@pytest.fixture(params=[16, 32], ids=["q16", "q32"])
+def C(request):
+    return CODECS[request.param]
 
 
-def _host(t):
+def _dev(buf, n, C):
+    return sv.FixedState(n, C.dtype, data=torch.from_numpy(np.ascontiguousarray(buf)).cuda())
+
+
+def _new(n, C):
+    return sv.FixedState(n, C.dtype)
+
+
+def _host(q):
     torch.cuda.synchronize()
-    return t.cpu().numpy()
+    return q.data.cpu().numpy()
 
 
-def _encode_gpu(psi, n):
+def _encode_gpu(psi, n, C):
     src = torch.from_numpy(psi).cuda()
-    q = sv.fixed_state(n)
+    q = _new(n, C)
     sv.sv_convert(q, src)
     return q
 
 
-def _diff_report(got, want, n):
-    gc, gs = oracle.q16_views(got, n)
-    wc, ws = oracle.q16_views(want, n)
+def _diff_report(got, want, n, C):
+    gc, gs = C.views(got, n)
+    wc, ws = C.views(want, n)
     bad_c = np.nonzero((gc != wc).any(axis=1))[0]
     bad_s = np.nonzero(gs != ws)[0]
     return "codes differ at %d amplitudes (first %s), scales at %d blocks (first %s)" % (
         len(bad_c), bad_c[:5].tolist(), len(bad_s), bad_s[:5].tolist())
 
 
-def _assert_same(got, want, n, what=""):
+def _assert_same(got, want, n, C, what=""):
     assert got.shape == want.shape
     if not np.array_equal(got, want):
-        pytest.fail("%s: %s" % (what, _diff_report(got, want, n)))
+        pytest.fail("q%d %s: %s" % (C.bits, what, _diff_report(got, want, n, C)))
 
 
 @pytest.mark.parametrize("n", [1, 3, 5, 6, 7, 12, 16])
-def test_convert_encode_decode_bit_exact(n):
+def test_convert_encode_decode_bit_exact(C, n):
     psi = W.random_state(n, 100 + n)
     psi[: min(64, 1 << n) // 2] *= 1e-9  # blocks of very different magnitude
-    want = oracle.q16_encode(psi, n)
-    q = _encode_gpu(psi, n)
-    _assert_same(_host(q), want, n, "encode from complex128")
+    want = C.enc(psi, n)
+    q = _encode_gpu(psi, n, C)
+    _assert_same(_host(q), want, n, C, "encode from complex128")
     out = torch.empty(1 << n, dtype=torch.complex128, device="cuda")
     sv.sv_convert(out, q)
-    assert np.array_equal(_host(out), oracle.q16_decode(want, n))
-    # complex64 in and out: the float values are the ones encoded
-    p64 = torch.from_numpy(psi.astype(np.complex64)).cuda()
-    q2 = sv.fixed_state(n)
-    sv.sv_convert(q2, p64)
-    _assert_same(_host(q2), oracle.q16_encode(psi.astype(np.complex64).astype(np.complex128), n), n,
-                 "encode from complex64")
+    assert np.array_equal(out.cpu().numpy(), C.dec(want, n))
+    # complex64 in: the widened values are the ones encoded
+    p64 = psi.astype(np.complex64)
+    q2 = _new(n, C)
+    sv.sv_convert(q2, torch.from_numpy(p64).cuda())
+    _assert_same(_host(q2), C.enc(p64.astype(np.complex128), n), n, C, "encode from complex64")
+    # complex64 out: the decoded doubles rounded to nearest
     o64 = torch.empty(1 << n, dtype=torch.complex64, device="cuda")
     sv.sv_convert(o64, q2)
-    assert np.array_equal(_host(o64).astype(np.complex128), oracle.q16_decode(_host(q2), n))
-    # complex128 <-> complex64 round to nearest / widen exactly
+    assert np.array_equal(o64.cpu().numpy(), C.dec(_host(q2), n).astype(np.complex64))
+    # the uint8 tensor form is the 16-bit format
+    if C.bits == 16:
+        q3 = sv.fixed_state(n)
+        sv.sv_convert(q3, torch.from_numpy(psi).cuda())
+        torch.cuda.synchronize()
+        assert np.array_equal(q3.cpu().numpy(), want)
+
+
+def test_complex_conversions_round_and_widen():
+    n = 12
+    psi = W.random_state(n, 99)
     c64 = torch.empty(1 << n, dtype=torch.complex64, device="cuda")
     sv.sv_convert(c64, torch.from_numpy(psi).cuda())
-    assert np.array_equal(_host(c64), psi.astype(np.complex64))
+    assert np.array_equal(c64.cpu().numpy(), psi.astype(np.complex64))
+    back = torch.empty(1 << n, dtype=torch.complex128, device="cuda")
+    sv.sv_convert(back, c64)
+    assert np.array_equal(back.cpu().numpy(), psi.astype(np.complex64).astype(np.complex128))
 
 
 @pytest.mark.parametrize("n,b", [(1, 1), (3, 5), (6, 63), (7, 64), (12, 4095), (12, 1234)])
-def test_init_basis_bit_exact(n, b):
-    q = sv.fixed_state(n)
-    q.fill_(0xA5)  # garbage the init must overwrite
+def test_init_basis_bit_exact(C, n, b):
+    q = _new(n, C)
+    q.data.fill_(0xA5)  # garbage the init must overwrite
     sv.sv_init(q, b)
     psi = np.zeros(1 << n, dtype=np.complex128)
     psi[b] = 1.0
-    _assert_same(_host(q), oracle.q16_encode(psi, n), n, "basis %d" % b)
+    want = C.enc(psi, n)
+    codes, scales = C.views(want, n)
+    assert codes[b, 0] == C.one and scales[b >> 6 if n >= 6 else 0] == C.one_scale
+    _assert_same(_host(q), want, n, C, "basis %d" % b)
 
 
 def _gate_cases(n, rng, count):
@@ -113,36 +149,38 @@ def _gate_cases(n, rng, count):
 
 @pytest.mark.parametrize("n", [1, 2, 4, 5, 6, 7, 9, 13])
 @pytest.mark.parametrize("mode", ["auto", "masked"])
-def test_single_gates_bit_exact(n, mode):
+def test_single_gates_bit_exact(C, n, mode):
     rng = np.random.default_rng(200 + n)
     psi = W.random_state(n, 300 + n)
-    ref = oracle.q16_encode(psi, n)
-    q = _dev(ref)
+    ref = C.enc(psi, n)
+    q = _dev(ref, n, C)
     for i, (t, ctrls, vals) in enumerate(_gate_cases(n, rng, 24)):
         U = oracle.gate_matrix("U", matrix=W.haar_unitary_2x2(400 + i))
         cm, cv = oracle.masks(ctrls, vals)
         sv.sv_apply_gate(q, t, ctrls, cv, np.asarray(W.haar_unitary_2x2(400 + i)), mode=mode)
-        oracle.q16_apply_gate(ref, n, t, ctrls, vals, U)
-        _assert_same(_host(q), ref, n, "gate %d: t=%d controls=%s values=%s" % (i, t, ctrls, vals))
+        C.gate(ref, n, t, ctrls, vals, U)
+        _assert_same(_host(q), ref, n, C, "gate %d: t=%d controls=%s values=%s" % (i, t, ctrls, vals))
 
 
-def test_scheduled_and_masked_agree_bitwise_n20():
+def test_scheduled_and_masked_agree_bitwise_n20(C):
     n = 20
     psi = W.random_state(n, 21)
-    base = oracle.q16_encode(psi, n)
+    base = C.enc(psi, n)
     U = np.asarray(W.haar_unitary_2x2(22))
     for t, ctrls in ((19, (3, 11)), (2, (0, 7, 15)), (10, ()), (0, (19,))):
-        a, b = _dev(base), _dev(base)
+        a, b = _dev(base, n, C), _dev(base, n, C)
         sv.sv_apply_gate(a, t, ctrls, None, U, mode="auto")
         sv.sv_apply_gate(b, t, ctrls, None, U, mode="masked")
-        assert torch.equal(a, b), (t, ctrls)
-        want = oracle.q16_apply_gate(base.copy(), n, t, ctrls, (), oracle.gate_matrix("U", matrix=tuple(U)))
-        _assert_same(_host(a), want, n, "t=%d controls=%s" % (t, ctrls))
+        torch.cuda.synchronize()
+        assert torch.equal(a.data, b.data), (t, ctrls)
+        want = C.gate(base.copy(), n, t, ctrls, (), oracle.gate_matrix("U", matrix=tuple(U)))
+        _assert_same(_host(a), want, n, C, "t=%d controls=%s" % (t, ctrls))
 
 
 def _named_matrices_agree(circ):
-    """The float matrices both sides use are equal (each side computes the
-    named gates' doubles itself; rounding to float must give the same)."""
+    """The float matrices the 16-bit format uses are equal (each side
+    computes the named gates' doubles itself; rounding to float must give
+    the same)."""
     for g in circ.gates:
         mine = np.asarray(sv.sv_gate_matrix(g.kind, g.theta, g.matrix)).astype(np.float32)
         U = oracle.gate_matrix(g.kind, g.theta, g.matrix)
@@ -151,67 +189,74 @@ def _named_matrices_agree(circ):
 
 
 @pytest.mark.parametrize("flags", [0, 4])  # unfused scheduled, masked
-def test_random_circuit_bit_exact(flags):
+def test_random_circuit_bit_exact_q16(flags):
+    C = CODECS[16]
     circ = W.random_gates_n12(seed=0)
     n = circ.n
     _named_matrices_agree(circ)
-    want = oracle.q16_run_circuit(circ)
-    q = sv.fixed_state(n)
+    want = C.run(circ)
+    q = _new(n, C)
     sv.sv_init(q, 0)
     sv.sv_apply_circuit(q, circ, flags=flags)
-    _assert_same(_host(q), want, n, "random_gates_n12 flags %d" % flags)
+    _assert_same(_host(q), want, n, C, "random_gates_n12 flags %d" % flags)
 
 
-def test_haar_circuit_with_graph_replays():
-    rng = np.random.default_rng(31)
-    n = 14
+def _haar_circuit(n, ngates, seed):
+    rng = np.random.default_rng(seed)
     gates = []
-    for i in range(120):
+    for i in range(ngates):
         t = int(rng.integers(0, n))
         others = [q for q in range(n) if q != t]
         nc = int(rng.integers(0, 4))
         ctrls = tuple(int(c) for c in rng.choice(others, size=nc, replace=False)) if nc else ()
         vals = tuple(int(v) for v in rng.integers(0, 2, size=nc))
         gates.append(W.Gate("U", t, ctrls, vals, matrix=W.haar_unitary_2x2(1000 + i)))
-    circ = W.Circuit(n, gates)
+    return W.Circuit(n, gates)
+
+
+@pytest.mark.parametrize("flags", [0, 4])
+def test_haar_circuit_with_graph_replays(C, flags):
+    n = 14
+    circ = _haar_circuit(n, 120, 31)
     psi = W.random_state(n, 32)
-    start = oracle.q16_encode(psi, n)
-    want = oracle.q16_run_circuit(circ, buf0=start)
-    eager = _dev(start)
-    sv.sv_apply_circuit(eager, circ, flags=0)
-    _assert_same(_host(eager), want, n, "eager")
-    plan = sv.Circuit(n, circ, dtype=sv.SV_CQ16, flags=sv.SV_GRAPH)
-    q = _dev(start)
+    start = C.enc(psi, n)
+    want = C.run(circ, buf0=start)
+    eager = _dev(start, n, C)
+    sv.sv_apply_circuit(eager, circ, flags=flags)
+    _assert_same(_host(eager), want, n, C, "eager flags %d" % flags)
+    plan = sv.Circuit(n, circ, dtype=C.dtype, flags=sv.SV_GRAPH | flags)
+    q = _dev(start, n, C)
+    src = torch.from_numpy(start).cuda()
     for rep in range(3):  # replays with eager work and synchronisation between
-        q.copy_(_dev(start))
+        q.data.copy_(src)
         torch.cuda.synchronize()
         plan.run(q)
         torch.cuda.synchronize()
-        assert torch.equal(q, eager), "replay %d" % rep
-    assert plan.info()["passes"] == len(gates)
+        assert torch.equal(q.data, eager.data), "replay %d" % rep
+    assert plan.info()["passes"] == len(circ.gates)
     plan.close()
 
 
-def test_parameterised_circuit_within_bound():
-    """Angles on the device: the matrices are computed there in double and
-    rounded to float, so the result is checked against the double oracle
-    within the format's bound (and against the fixed-point oracle, which
-    must agree to within one code step per gate)."""
+def test_parameterised_circuit_within_bound(C):
+    """Angles on the device: the matrices are computed there in double (and
+    rounded to float for 16-bit codes), so the result is checked against the
+    double oracle within the format's bound, and against the fixed-point
+    oracle within one step per gate."""
     circ = W.hea(8, 3, seed=33)
     n = circ.n
     params = torch.from_numpy(circ.params).cuda()
-    q = sv.fixed_state(n)
+    q = _new(n, C)
     sv.sv_init(q, 0)
     sv.sv_apply_circuit(q, circ, params=params, flags=0)
-    got = oracle.q16_decode(_host(q), n)
+    got = C.dec(_host(q), n)
     exact = oracle.run_circuit(circ)
     G = len(circ.gates)
-    assert np.linalg.norm(got - exact) <= (G + 1) * (math.sqrt(128) * 2.0 ** -15 + 1e-6)
-    ref = oracle.q16_decode(oracle.q16_run_circuit(circ), n)
-    assert np.abs(got - ref).max() <= 1e-3
+    assert np.linalg.norm(got - exact) <= (G + 1) * (math.sqrt(128) * C.step + 1e-6)
+    ref = C.dec(C.run(circ), n)
+    assert np.abs(got - ref).max() <= G * 2 * C.step
 
 
-def test_qft_error_against_double_oracle():
+def test_qft_error_against_double_oracle(C):
     """The QFT as drawn (no swaps): error of the fixed-point result against
     its closed form, within the rigorous bound, beside complex64's."""
     n = 16
@@ -220,53 +265,65 @@ def test_qft_error_against_double_oracle():
     N = 1 << n
     rev = np.array([int(format(i, "0%db" % n)[::-1], 2) for i in range(N)])
     want = np.fft.ifft(psi0[rev]) * math.sqrt(N)
-    q = _encode_gpu(psi0, n)
+    q = _encode_gpu(psi0, n, C)
     sv.sv_apply_circuit(q, circ, flags=0)
-    err = np.linalg.norm(oracle.q16_decode(_host(q), n) - want)
+    err = np.linalg.norm(C.dec(_host(q), n) - want)
     G = len(circ.gates)
-    assert err <= (G + 1) * (math.sqrt(128) * 2.0 ** -15 + 1e-6)
-    assert err < 2e-2
+    assert err <= (G + 1) * (math.sqrt(128) * C.step + 1e-12)
     c64 = torch.from_numpy(psi0.astype(np.complex64)).cuda()
     sv.sv_apply_circuit(c64, circ, flags=0)
-    err64 = np.linalg.norm(_host(c64).astype(np.complex128) - want)
-    print("QFT n=%d: fixed-point error %.3e, complex64 error %.3e (2-norm)" % (n, err, err64))
-    assert err64 < err  # 16-bit codes carry fewer bits than float
+    err64 = np.linalg.norm(c64.cpu().numpy().astype(np.complex128) - want)
+    print("QFT n=%d: %d-bit fixed-point error %.3e, complex64 error %.3e (2-norm)" % (n, C.bits, err, err64))
+    if C.bits == 16:
+        assert err64 < err  # 16-bit codes carry fewer bits than float
+    else:
+        assert err < err64 / 10  # 31 bits per block against a 24-bit mantissa
 
 
-def test_full_size_n28_bit_exact():
-    """The bench's configuration: n = 28 (1 GiB state), high and low targets,
+def test_full_size_bit_exact(C):
+    """The bench's register: n = 28 (1 GiB or 2 GiB), high and low targets,
     scheduled and masked kernels, whole-state comparison."""
     n = 28
     psi = W.random_state(n, 1)
-    ref = oracle.q16_encode(psi, n)
+    ref = C.enc(psi, n)
     del psi
-    q = _dev(ref)
+    q = _dev(ref, n, C)
     for t, ctrls, vals, mode in ((27, (0, 13), (1, 1), "auto"), (0, (14, 27), (1, 0), "masked"),
                                  (13, (), (), "auto")):
         U = W.haar_unitary_2x2(2)
         sv.sv_apply_gate(q, t, ctrls, oracle.masks(ctrls, vals)[1], np.asarray(U), mode=mode)
-        oracle.q16_apply_gate(ref, n, t, ctrls, vals, oracle.gate_matrix("U", matrix=U))
+        C.gate(ref, n, t, ctrls, vals, oracle.gate_matrix("U", matrix=U))
         got = _host(q)
-        assert np.array_equal(got, ref), "t=%d controls=%s %s: %s" % (t, ctrls, mode, _diff_report(got, ref, n))
+        assert np.array_equal(got, ref), "q%d t=%d controls=%s %s: %s" % (
+            C.bits, t, ctrls, mode, _diff_report(got, ref, n, C))
 
 
-def test_x_on_top_qubit_swaps_halves_n32():
-    """n = 32 (16 GiB state): X on qubit 31 exchanges the two halves exactly
-    (codes and scales), a property of any correct implementation."""
+def test_x_on_top_qubit_swaps_halves_n32(C):
+    """n = 32 (16 GiB or 32 GiB): X on qubit 31 exchanges the two halves
+    exactly (codes and scales), a property of any correct implementation."""
     n = 32
-    q = sv.fixed_state(n)
+    q = _new(n, C)
     N = 1 << n
-    codes = q[: 4 * N].view(torch.int16)
+    cb = N * (4 if C.bits == 16 else 8)  # bytes of codes
     gen = torch.Generator(device="cuda").manual_seed(35)
-    codes.copy_(torch.randint(-32767, 32767, (2 * N,), device="cuda", dtype=torch.int16, generator=gen))
-    scales = q[4 * N:].view(torch.int8)
-    scales.copy_(torch.randint(-40, -20, (N // 64,), device="cuda", dtype=torch.int8, generator=gen))
-    # make every block a valid encoding: largest magnitude at least 2^14
-    codes.view(N // 64, 128)[:, 0] = 20000
-    before = q.clone()
+    if C.bits == 16:
+        codes = q.data[:cb].view(torch.int16)
+        codes.copy_(torch.randint(-32767, 32767, (2 * N,), device="cuda", dtype=torch.int16, generator=gen))
+        codes.view(N // 64, 128)[:, 0] = 20000  # every block a valid encoding
+    else:
+        codes = q.data[:cb].view(torch.int32)
+        for part in codes.split(1 << 30):
+            part.copy_(torch.randint(-(2 ** 31) + 1, 2 ** 31 - 1, (part.numel(),), device="cuda",
+                                     dtype=torch.int32, generator=gen))
+        codes.view(N // 64, 128)[:, 0] = 1 << 30
+    scales = q.data[cb:].view(torch.int8)
+    scales.copy_(torch.randint(-60, -20, (N // 64,), device="cuda", dtype=torch.int8, generator=gen))
+    before = q.data.clone()
     sv.sv_apply_gate(q, 31, (), None, np.array([[0, 1], [1, 0]]))
     torch.cuda.synchronize()
-    h = 2 * N  # bytes per half of the codes
-    assert torch.equal(q[:h], before[h:4 * N]) and torch.equal(q[h:4 * N], before[:h])
+    h = cb // 2
+    assert torch.equal(q.data[:h], before[h:cb]) and torch.equal(q.data[h:cb], before[:h])
     hs = N // 128
-    assert torch.equal(q[4 * N:4 * N + hs], before[4 * N + hs:]) and torch.equal(q[4 * N + hs:], before[4 * N:4 * N + hs])
+    assert torch.equal(q.data[cb:cb + hs], before[cb + hs:]) and torch.equal(q.data[cb + hs:], before[cb:cb + hs])
+    del before, q
+    torch.cuda.empty_cache()

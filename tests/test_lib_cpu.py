@@ -77,7 +77,7 @@ def test_gate_argument_errors(sv, case, needle):
 
 
 def test_state_errors(sv):
-    for st, needle in ((_state(sv, 0), "n=0"), (_state(sv, 35), "n=35"), (_state(sv, 8, 3), "dtype"),
+    for st, needle in ((_state(sv, 0), "n=0"), (_state(sv, 35), "n=35"), (_state(sv, 8, 4), "dtype"),
                        (_state(sv, 8, 0, 0), "NULL"), (_state(sv, 8, 0, 0x10008), "aligned")):
         code, msg = _rc(lambda: sv.sv_apply_gate(st, 0, U=U))
         assert code == sv.SV_EINVAL and needle in msg, msg
@@ -143,23 +143,30 @@ def test_fixed_point_state_bytes(sv):
     for n in (1, 5, 6, 7, 12, 28, 36):
         want = (4 << n) + max(1, (1 << n) // 64)
         assert sv.sv_state_bytes(n, sv.SV_CQ16) == want == sv.q16_nbytes(n)
+    for n in (1, 5, 6, 12, 35):
+        want = (8 << n) + max(1, (1 << n) // 64)
+        assert sv.sv_state_bytes(n, sv.SV_CQ32) == want == sv.fixed_nbytes(n, sv.SV_CQ32)
+    assert _rc(lambda: sv.sv_state_bytes(36, sv.SV_CQ32))[0] == sv.SV_EINVAL
     assert sv.sv_state_bytes(28, sv.SV_C128) == 16 << 28 and sv.sv_state_bytes(28, sv.SV_C64) == 8 << 28
     code, msg = _rc(lambda: sv.sv_state_bytes(37, sv.SV_CQ16))
     assert code == sv.SV_EINVAL
 
 
+@pytest.mark.parametrize("bits", [16, 32])
 @pytest.mark.parametrize("n,t,ctrls,masked,name,units", [
-    (28, 13, (17, 22), False, "k_q16_gate<false, true", 1 << 19),   # block pairs: 2^(22-1-2)
-    (28, 13, (17, 22), True, "k_q16_gate<true, true", 1 << 21),     # every block pair
-    (28, 3, (0, 20), False, "k_q16_gate<false, false", 1 << 21),    # blocks: 2^(22-1), qubit 0 tested
-    (28, 3, (0, 1), False, "k_q16_gate<false, false", 1 << 22),     # only in-block controls
-    (6, 5, (0,), False, "k_q16_gate<false, false", 1),
-    (5, 4, (0, 1), False, "k_q16_gate_small", 1),
+    (28, 13, (17, 22), False, "false, true, false", 1 << 19),   # block pairs: 2^(22-1-2)
+    (28, 13, (17, 22), True, "true, true, false", 1 << 21),     # every block pair
+    (28, 3, (0, 20), False, "false, false, true", 1 << 21),     # blocks: 2^(22-1), qubit 0 tested
+    (28, 3, (0, 1), False, "false, false, true", 1 << 22),      # only in-block controls
+    (6, 5, (0,), False, "false, false, true", 1),
+    (5, 4, (0, 1), False, "small", 1),
 ])
-def test_fixed_point_gate_plan(sv, n, t, ctrls, masked, name, units):
+def test_fixed_point_gate_plan(sv, bits, n, t, ctrls, masked, name, units):
     cm = sum(1 << q for q in ctrls)
-    k, it = sv.sv_gate_plan(n, sv.SV_CQ16, t, cm, cm, "masked" if masked else "auto")
-    assert name in k and it == units, (k, it)
+    dtype = sv.SV_CQ16 if bits == 16 else sv.SV_CQ32
+    k, it = sv.sv_gate_plan(n, dtype, t, cm, cm, "masked" if masked else "auto")
+    want = ("k_fix_gate_small<sv::Q%d" % bits) if name == "small" else ("k_fix_gate<sv::Q%d, %s" % (bits, name))
+    assert want in k and it == units, (k, it)
 
 
 def test_fixed_point_rejected_where_unsupported(sv):
@@ -186,6 +193,11 @@ def test_fixed_point_rejected_where_unsupported(sv):
 
 
 def test_convert_argument_errors(sv):
+    code, msg = _rc(lambda: sv.sv_convert(_state(sv, 10, sv.SV_CQ32, 0x100000),
+                                          _state(sv, 10, sv.SV_CQ16, 0x900000)))
+    assert code == sv.SV_ENOTSUP and "complex128" in msg
+    code, msg = _rc(lambda: sv.sv_swap_qubits(_state(sv, 10, sv.SV_CQ32), [(0, 9)]))
+    assert code == sv.SV_ENOTSUP
     a = _state(sv, 10, sv.SV_CQ16, 0x100000)
     code, msg = _rc(lambda: sv.sv_convert(a, _state(sv, 11, sv.SV_C128, 0x900000)))
     assert code == sv.SV_EINVAL and "qubits" in msg

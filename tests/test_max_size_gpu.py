@@ -1,6 +1,6 @@
 """The largest register each dtype supports on one MI355X (288 GB of HBM):
-n = 34 complex128 and n = 35 complex64 (256 GiB each), n = 36 fixed point
-(257 GiB).  64-bit indices throughout.  The checks are properties that pin
+n = 34 complex128 and n = 35 complex64 (256 GiB each), n = 36 16-bit and
+n = 35 32-bit fixed point (257 GiB and 256.5 GiB).  64-bit indices throughout.  The checks are properties that pin
 the result without a second full-size buffer: a basis state moved by a
 controlled X, a gate whose controls fail on it leaving it alone, and the
 norm (or, for fixed point, whole-array reductions of codes and scales)
@@ -82,15 +82,21 @@ def test_controlled_x_at_max_size(dtype, n):
     _run_and_release(lambda: torch.empty(1 << n, dtype=td, device="cuda"), body, "%s n=%d" % (dtype, n))
 
 
-def test_fixed_point_controlled_x_at_max_size():
-    n = 36
-    print("max size: fixed point n=%d" % n, flush=True)
+@pytest.mark.parametrize("bits,n", [(16, 36), (32, 35)])
+def test_fixed_point_controlled_x_at_max_size(bits, n):
+    dtype = sv.SV_CQ16 if bits == 16 else sv.SV_CQ32
+    one, one_scale, zero_scale = (16384, -14, -126) if bits == 16 else (1 << 30, -30, -128)
+    print("max size: %d-bit fixed point n=%d" % (bits, n), flush=True)
 
     def body(q):
         N = 1 << n
         nb = N >> 6
-        codes = q[:4 * N].view(torch.int32)  # one word per amplitude: re code low, im code high
-        scales = q[4 * N:].view(torch.int8)
+        cb = N * (4 if bits == 16 else 8)
+        # 16-bit: one int32 word per amplitude (re code low); 32-bit: two
+        # int32 words per amplitude (re, im)
+        codes = q.data[:cb].view(torch.int32)
+        scales = q.data[cb:].view(torch.int8)
+        word = (lambda k: k) if bits == 16 else (lambda k: 2 * k)
         b = _basis(n)
         t = n - 1
         sv.sv_init(q, b)
@@ -98,17 +104,17 @@ def test_fixed_point_controlled_x_at_max_size():
         sv.sv_apply_gate(q, 3, (1,), None, X)
         w = b | (1 << t)
         torch.cuda.synchronize()
-        # 1.0 is code 16384 under scale -14; every other word is 0 and
-        # every other block keeps the zero-block scale -126
-        assert codes[w].item() == 16384 and codes[b].item() == 0
-        assert codes.min().item() == 0 and codes.max().item() == 16384
-        assert _isum(codes) == 16384
-        assert scales[w >> 6].item() == -14
-        assert scales.max().item() == -14 and scales.min().item() == -126
-        assert _isum(scales) == -126 * (nb - 1) - 14
+        # 1.0 is the code 2^14 (2^30) under scale -14 (-30); every other code
+        # is 0 and every other block keeps the zero-block scale
+        assert codes[word(w)].item() == one and codes[word(b)].item() == 0
+        assert codes.min().item() == 0 and codes.max().item() == one
+        assert _isum(codes) == one
+        assert scales[w >> 6].item() == one_scale
+        assert scales.max().item() == one_scale and scales.min().item() == zero_scale
+        assert _isum(scales) == zero_scale * (nb - 1) + one_scale
         sv.sv_apply_gate(q, t, (0, n - 2), None, X, mode="masked")
         torch.cuda.synchronize()
-        assert codes[b].item() == 16384 and codes[w].item() == 0
-        assert scales[b >> 6].item() == -14 and scales[w >> 6].item() == -126
+        assert codes[word(b)].item() == one and codes[word(w)].item() == 0
+        assert scales[b >> 6].item() == one_scale and scales[w >> 6].item() == zero_scale
 
-    _run_and_release(lambda: sv.fixed_state(n), body, "fixed point n=%d" % n)
+    _run_and_release(lambda: sv.FixedState(n, dtype), body, "%d-bit fixed point n=%d" % (bits, n))
