@@ -389,64 +389,73 @@ def _case_sweep(sv, torch, np, st, cases, U, stream, mode, reps=3):
 
 
 def measure_fixed_point(sv, W, torch, np, stream, psi_host, cases, U, energy):
-    """Block-scaled 16-bit fixed-point states (4 bytes per amplitude) beside
-    complex64 (8) on the same controlled-gate sweep, the paper's 29-qubit
-    circuits in fixed point, and the QFT's error against its closed form."""
+    """Block-scaled fixed-point states, 16-bit codes (4 bytes per amplitude)
+    and 32-bit codes (8), beside complex64 (8) on the same controlled-gate
+    sweep, the paper's 29-qubit circuits in fixed point, and the QFT's error
+    against its closed form."""
     dev = torch.device("cuda:0")
     n = 28
     out = {}
     src = torch.from_numpy(psi_host).to(dev)
-    q = sv.fixed_state(n)
+    q = sv.FixedState(n, sv.SV_CQ16)
     sv.sv_convert(q, src, stream=stream)
+    q32 = sv.FixedState(n, sv.SV_CQ32)
+    sv.sv_convert(q32, src, stream=stream)
     c64 = torch.empty(1 << n, dtype=torch.complex64, device=dev)
     sv.sv_convert(c64, src, stream=stream)
     torch.cuda.synchronize()
     del src
     torch.cuda.empty_cache()
-    log("fixed-point sweep n=28 (scheduled, masked) and complex64 sweep")
+    log("fixed-point sweeps n=28 (16-bit scheduled and masked, 32-bit) and complex64 sweep")
     tq, pq = _case_sweep(sv, torch, np, q, cases, U, stream, "auto")
     tm, pm = _case_sweep(sv, torch, np, q, cases, U, stream, "masked")
+    t32, p32 = _case_sweep(sv, torch, np, q32, cases, U, stream, "auto")
     t64, p64 = _case_sweep(sv, torch, np, c64, cases, U, stream, "auto")
     reps = 3
     rows = []
     for t, ctrls in cases:
         c = len(ctrls)
         ch = sum(1 for x in ctrls if x >= 6)  # controls scheduled over the block index
-        alg_q = 2 * (1 << (n - c)) * 4 + 2 * (1 << (n - 6 - ch))  # satisfying amplitudes + their scales
+        scl = 2 * (1 << (n - 6 - ch))  # the touched blocks' scales
+        alg_q = 2 * (1 << (n - c)) * 4 + scl  # satisfying amplitudes + their scales
+        alg_32 = 2 * (1 << (n - c)) * 8 + scl
         alg_64 = 2 * (1 << (n - c)) * 8
         key = (t, ctrls)
         rows.append({"t": t, "c": c, "c_in_block": c - ch,
                      "q16_us": round(pq[key] * 1e3, 2), "q16_GBps": round(alg_q / pq[key] / 1e6, 1),
                      "q16_masked_us": round(pm[key] * 1e3, 2),
+                     "q32_us": round(p32[key] * 1e3, 2), "q32_GBps": round(alg_32 / p32[key] / 1e6, 1),
                      "c64_us": round(p64[key] * 1e3, 2), "c64_GBps": round(alg_64 / p64[key] / 1e6, 1)})
     ng = reps * len(cases)
     out["sweep_n28"] = {"q16_gates_per_s": round(ng / (tq / 1e3), 1),
                         "q16_masked_gates_per_s": round(ng / (tm / 1e3), 1),
+                        "q32_gates_per_s": round(ng / (t32 / 1e3), 1),
                         "c64_gates_per_s": round(ng / (t64 / 1e3), 1), "rows": rows}
-    del q, c64
+    del q, q32, c64
     torch.cuda.empty_cache()
-    for name, circ in (("qft29", W.qft(29)), ("stream29", W.stream(29))):
-        log("paper circuit", name, "fixed point")
-        st = sv.fixed_state(29)
-        row = {"gates": len(circ.gates)}
-        for label, fl in (("masked", sv.SV_MASKED), ("scheduled", 0)):
-            p = sv.Circuit(29, circ, dtype=sv.SV_CQ16, flags=fl)
+    for bits, dtype in ((16, sv.SV_CQ16), (32, sv.SV_CQ32)):
+        for name, circ in (("qft29", W.qft(29)), ("stream29", W.stream(29))):
+            log("paper circuit", name, "%d-bit fixed point" % bits)
+            st = sv.FixedState(29, dtype)
+            row = {"gates": len(circ.gates)}
+            for label, fl in (("masked", sv.SV_MASKED), ("scheduled", 0)):
+                p = sv.Circuit(29, circ, dtype=dtype, flags=fl)
 
-            def run():
-                sv.sv_init(st, 1, stream=stream)
-                p.run(st, stream=stream)
-            row[label + "_ms"] = round(_time_ms(torch, stream, run, 3), 3)
-            row[label + "_J_rated"] = round(row[label + "_ms"] * 1e-3 * RATED_POWER_W, 2)
-            if energy is not None:
-                j, w = _energy_per_run(torch, stream, run, energy)
-                if j is not None:
-                    row[label + "_J_measured"] = round(j, 3)
-                    row[label + "_W_avg"] = round(w, 1)
-            p.close()
-        row["masked_over_scheduled"] = round(row["masked_ms"] / row["scheduled_ms"], 2)
-        out["%s_q16" % name] = row
-        del st
-        torch.cuda.empty_cache()
+                def run():
+                    sv.sv_init(st, 1, stream=stream)
+                    p.run(st, stream=stream)
+                row[label + "_ms"] = round(_time_ms(torch, stream, run, 3), 3)
+                row[label + "_J_rated"] = round(row[label + "_ms"] * 1e-3 * RATED_POWER_W, 2)
+                if energy is not None:
+                    j, w = _energy_per_run(torch, stream, run, energy)
+                    if j is not None:
+                        row[label + "_J_measured"] = round(j, 3)
+                        row[label + "_W_avg"] = round(w, 1)
+                p.close()
+            row["masked_over_scheduled"] = round(row["masked_ms"] / row["scheduled_ms"], 2)
+            out["%s_q%d" % (name, bits)] = row
+            del st
+            torch.cuda.empty_cache()
     # accuracy: QFT (as drawn, no swaps) of a random state against the
     # closed form ifft(psi[bit-reversed]) * sqrt(N)
     ne = 20
@@ -459,14 +468,14 @@ def measure_fixed_point(sv, W, torch, np, stream, psi_host, cases, U, energy):
     want = np.fft.ifft(psi0[rev]) * np.sqrt(N)
     circ = W.qft(ne)
     errs = {}
-    for label, td in (("c128", torch.complex128), ("c64", torch.complex64), ("q16", None)):
+    for label, td in (("c128", torch.complex128), ("c64", torch.complex64), ("q32", sv.SV_CQ32),
+                      ("q16", sv.SV_CQ16)):
         src = torch.from_numpy(psi0).to(dev)
-        if td is None:
-            st = sv.fixed_state(ne)
-            sv.sv_convert(st, src, stream=stream)
+        if isinstance(td, int):
+            st = sv.FixedState(ne, td)
         else:
             st = torch.empty(N, dtype=td, device=dev)
-            sv.sv_convert(st, src, stream=stream)
+        sv.sv_convert(st, src, stream=stream)
         sv.sv_apply_circuit(st, circ, flags=0, stream=stream)
         res = torch.empty(N, dtype=torch.complex128, device=dev)
         sv.sv_convert(res, st, stream=stream)
