@@ -700,8 +700,8 @@ def main():
         summarize_positions(*args.summarize_positions)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
-              "(the sharding design is described in DESIGN.md); rerun with --gpus 1", file=sys.stderr)
+        print("bench.py runs on exactly one GPU: the library has no multi-GPU path "
+              "(only its sharding design exists); rerun with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
