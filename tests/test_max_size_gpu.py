@@ -10,6 +10,8 @@ import numpy as np
 import pytest
 import torch
 
+import workloads as W
+
 sv = pytest.importorskip("paper_2411_18354_amd")
 
 pytestmark = pytest.mark.gpu
@@ -118,3 +120,44 @@ def test_fixed_point_controlled_x_at_max_size(bits, n):
         assert scales[b >> 6].item() == one_scale and scales[w >> 6].item() == zero_scale
 
     _run_and_release(lambda: sv.FixedState(n, dtype), body, "%d-bit fixed point n=%d" % (bits, n))
+
+
+def test_tile_launches_split_into_pieces():
+    """Tile and exchange kernels launched over more than 2^22 tiles (n = 30
+    complex128 with 2^7-amplitude tiles: 2^23 tiles, two pieces) give the
+    same state as the unfused kernels and as an axis transpose."""
+    n = 30
+    print("split tile launches: n=%d, tile width 2^7" % n, flush=True)
+    saved = sv.sv_tune_get("tile_log2_c128")
+    sv.sv_tune_set("tile_log2_c128", 7)
+    try:
+        def body(buf):
+            psi, ref, pre = buf
+            gen = torch.Generator(device="cuda").manual_seed(36)
+            psi.view(torch.float64).copy_(torch.randn(2 << n, dtype=torch.float64, device="cuda", generator=gen))
+            ref.copy_(psi)
+            # gates on the 7 lowest qubits (runs of tiles) and controls above
+            circ = W.Circuit(n, [W.Gate("H", q) for q in range(7)]
+                             + [W.Gate("U", 3, (29,), (), matrix=W.haar_unitary_2x2(37)),
+                                W.Gate("X", 5, (0, 20)), W.Gate("U", 6, (2,), (0,), matrix=W.haar_unitary_2x2(38))])
+            plan = sv.Circuit(n, circ, flags=sv.SV_FUSE)
+            assert plan.info()["fused_runs"] >= 1
+            plan.run(psi)
+            sv.sv_apply_circuit(ref, circ, flags=0)
+            torch.cuda.synchronize()
+            assert (psi - ref).abs().max().item() <= 1e-12 * ref.abs().max().item()
+            plan.close()
+            # exchange of qubits 0 and 29 = transpose of those index bits; twice = identity
+            pre.copy_(psi)
+            ref.copy_(psi.view(2, 1 << 28, 2).transpose(0, 2).contiguous().view(-1))
+            sv.sv_swap_qubits(psi, [(0, 29)])
+            torch.cuda.synchronize()
+            assert torch.equal(psi, ref)
+            sv.sv_swap_qubits(psi, [(0, 29)])
+            torch.cuda.synchronize()
+            assert torch.equal(psi, pre)
+
+        _run_and_release(lambda: [torch.empty(1 << n, dtype=torch.complex128, device="cuda") for _ in range(3)],
+                         body, "three n=30 complex128 states")
+    finally:
+        sv.sv_tune_set("tile_log2_c128", saved)
