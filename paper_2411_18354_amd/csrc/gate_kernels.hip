@@ -171,6 +171,45 @@ TileMap make_tile_map(int n, int m, int a, const std::vector<int> &high, uint64_
 
 TileMap contiguous_tile_map(int n, int m) { return make_tile_map(n, m, m, {}); }
 
+// What the phase tables of a sweep need to know about its gates, the same
+// for every tile (the first gate's npairs, unused by diagonal gates; see
+// diag_sweep_tables): whether gates reading bits of u and one bit of v
+// exist (R-type) and all depend on u through one condition (u & um) == uv,
+// and whether gates reading bits of u and two or more bits of v exist.  A
+// target bit in u counts as a required 1 only when the phase on its 0 side
+// is known to be 0 (not a parameterised gate).
+static uint32_t sweep_table_info(const TileGate *t, int count, const char *param_gate) {
+    bool have_r = false, rank1 = true, any_rest = false;
+    uint32_t um = 0, uv = 0;
+    for (int q = 0; q < count; ++q) {
+        const TileGate &d = t[q];
+        const uint32_t lm = d.l_mask | (d.l_target >= 0 ? 1u << d.l_target : 0u);
+        const uint32_t lo = lm & 63u, hi = lm >> 6;
+        if (!lo || !hi)
+            continue;
+        if (__builtin_popcount(hi) > 1) {
+            any_rest = true;
+            continue;
+        }
+        uint32_t gm = d.l_mask & 63u, gv = d.l_vals & 63u;
+        if (d.l_target >= 0 && d.l_target < 6) {
+            if (param_gate[q] || d.ph[0] != 0.0)
+                rank1 = false;
+            gm |= 1u << d.l_target;
+            gv |= 1u << d.l_target;
+        }
+        if (!have_r) {
+            um = gm;
+            uv = gv;
+            have_r = true;
+        } else if (gm != um || gv != uv) {
+            rank1 = false;
+        }
+    }
+    return kSweepInfoValid | um | (uv << 8) | (have_r ? kSweepHaveR : 0u) | (have_r && rank1 ? kSweepRank1 : 0u) |
+           (any_rest ? kSweepAnyRest : 0u);
+}
+
 void mark_diag_sweeps(TileGate *t, int count, const char *param_gate) {
     int k = 0;
     while (k < count) {
@@ -188,6 +227,7 @@ void mark_diag_sweeps(TileGate *t, int count, const char *param_gate) {
         }
         t[k].sweep_len = (uint16_t)(e - k);
         t[k].sweep_phase = (unit && nlocal >= kPhaseSweepMin) ? 1 : 0;
+        t[k].npairs = sweep_table_info(t + k, e - k, param_gate + k);
         k = e;
     }
 }

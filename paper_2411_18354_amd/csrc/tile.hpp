@@ -41,7 +41,8 @@ struct TileGate {
     uint64_t o_mask, o_vals;
     uint32_t diag;        // 1: diagonal gate applied elementwise
     uint32_t target;      // pair gate: tile-local bit; diagonal: global qubit
-    uint32_t npairs;      // 2^(m - 1 - in-tile controls)
+    uint32_t npairs;      // pair gate: 2^(m - 1 - in-tile controls); first gate of a
+                          // diagonal sweep: its table summary (kSweep* bits)
     uint32_t fixed;       // in-tile control bits that must be 1
     uint32_t l_mask, l_vals;
     int32_t l_target;
@@ -61,9 +62,15 @@ struct TileGate {
     int32_t pad2;
 };
 
+// Summary bits of a diagonal sweep's gates (host), kept in the first gate's
+// npairs: bits 0-5 um and 8-13 uv (the common condition on u of R-type
+// gates), and flags.
+constexpr uint32_t kSweepHaveR = 1u << 16, kSweepRank1 = 1u << 17, kSweepAnyRest = 1u << 18,
+                   kSweepInfoValid = 1u << 31;
+
 // Mark the blocks of consecutive diagonal gates among tiles[0 .. count) (one
-// fused run; host): length and phase-sum eligibility at each block's first
-// gate.  param_gate[i] != 0: the entries of gate i come from parameters at
+// fused run; host): length, phase-sum eligibility and table summary at each
+// block's first gate.  param_gate[i] != 0: the entries of gate i come from parameters at
 // run time (their kinds are unitary), so it counts as unit modulus.
 void mark_diag_sweeps(TileGate *tiles, int count, const char *param_gate);
 
@@ -340,6 +347,30 @@ __device__ __forceinline__ double diag_phase_at(const TileGate &d, uint32_t j, b
     return ((j & d.l_mask) == d.l_vals) ? (one ? p1 : p0) : 0.0;
 }
 
+// The fields of a diagonal gate the sweep tables read.
+struct SweepFields {
+    uint64_t o_mask, o_vals;
+    uint32_t l_mask, l_vals, target;
+    int32_t l_target;
+    double p0, p1;
+};
+
+__device__ __forceinline__ double diag_phase_at(const SweepFields &d, uint32_t j, bool tone) {
+    const bool one = d.l_target >= 0 ? ((j >> d.l_target) & 1u) : tone;
+    return ((j & d.l_mask) == d.l_vals) ? (one ? d.p1 : d.p0) : 0.0;
+}
+
+// Visit the diagonal gates [i, e) in order with wave-uniform fields (the
+// descriptors are read with scalar loads).
+template <typename Src, typename F>
+__device__ __forceinline__ void for_sweep_gates(const Src &gates, int i, int e, F f) {
+    for (int q = i; q < e; ++q) {
+        const TileGate &d = gates.get(q);
+        f(SweepFields{d.o_mask, d.o_vals, d.l_mask, d.l_vals, d.target, d.l_target, uniform_f64(d.ph[0]),
+                      uniform_f64(d.ph[1])});
+    }
+}
+
 // Long unit-modulus sweep with tables.  The phase of amplitude j is a sum of
 // gate terms, each depending on the few tile-local bits the gate reads.  With
 // u = bits 0..5 of j and v = bits 6..m-1:
@@ -360,23 +391,33 @@ __device__ __forceinline__ void diag_sweep_tables(cplx_t<R> *tile, double *tab, 
     const uint32_t T = 1u << m;
     const int Hb = (int)m - 6;
     double *A = tab, *B = tab + 64, *Rt = tab + 64 + (1 << Hb);
-    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    // the wavefront index is uniform: keep it (and the table loop) scalar
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     double th0 = 0.0;
     bool any_rest = false, have_r = false, rank1 = true;
     uint32_t um = 0, uv = 0;
-    for (int q = i; q < e; ++q) {  // uniform
-        const TileGate &d = gates.get(q);
+    // The host's summary of the sweep, when present, replaces a walk over its
+    // gates in every wavefront; the tile-uniform phases then go into A.
+    const uint32_t info = __builtin_amdgcn_readfirstlane(gates.get(i).npairs);
+    const bool summary = (info & kSweepInfoValid) != 0;
+    if (summary) {
+        um = info & 63u;
+        uv = (info >> 8) & 63u;
+        have_r = (info & kSweepHaveR) != 0;
+        rank1 = (info & kSweepRank1) != 0;
+        any_rest = (info & kSweepAnyRest) != 0;
+    } else for_sweep_gates(gates, i, e, [&](const SweepFields &d) {
         if ((base & d.o_mask) != d.o_vals)
-            continue;
+            return;
         const uint32_t lm = d.l_mask | (d.l_target >= 0 ? 1u << d.l_target : 0u);
         if (lm == 0) {
-            th0 += ((base >> d.target) & 1ull) ? d.ph[1] : d.ph[0];
+            th0 += ((base >> d.target) & 1ull) ? d.p1 : d.p0;
         } else if ((lm & 63u) && __popc(lm >> 6) > 1) {
             any_rest = true;
         } else if ((lm & 63u) && (lm >> 6)) {  // an R[q] gate: its condition on u
             uint32_t gm = d.l_mask & 63u, gv = d.l_vals & 63u;
             if (d.l_target >= 0 && d.l_target < 6) {
-                if (uniform_f64(d.ph[0]) != 0.0)
+                if (d.p0 != 0.0)
                     rank1 = false;
                 gm |= 1u << d.l_target;
                 gv |= 1u << d.l_target;
@@ -389,7 +430,7 @@ __device__ __forceinline__ void diag_sweep_tables(cplx_t<R> *tile, double *tab, 
                 rank1 = false;
             }
         }
-    }
+    });
     const bool use_d = have_r && rank1;
     // table tb: 0 = A, 1 = B, then D (use_d) or 2 + q = R[q] (R gates of
     // several conditions); entries per lane: A 1, B and D ceil(2^Hb / 64)
@@ -400,35 +441,33 @@ __device__ __forceinline__ void diag_sweep_tables(cplx_t<R> *tile, double *tab, 
         const bool dtab = use_d && tb == 2;
         const int ne = tb == 0 ? 1 : ((tb == 1 || dtab) ? (int)((nb + 63) / 64) : 2);
         double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
-        for (int q = i; q < e; ++q) {
-            const TileGate &d = gates.get(q);
+        // the tile-local index an entry stands for
+        auto at = [&](int k) -> uint32_t {
+            return tb == 0   ? (uint32_t)lane
+                   : tb == 1 ? (uint32_t)(lane + 64 * k) << 6
+                   : dtab    ? ((uint32_t)(lane + 64 * k) << 6) | uv
+                             : (uint32_t)lane | ((uint32_t)k << (4 + tb));
+        };
+        for_sweep_gates(gates, i, e, [&](const SweepFields &d) {
             if ((base & d.o_mask) != d.o_vals)
-                continue;  // uniform
+                return;  // uniform
             const uint32_t lm = d.l_mask | (d.l_target >= 0 ? 1u << d.l_target : 0u);
             const uint32_t lo = lm & 63u, hi = lm >> 6;
-            const bool mine = tb == 0   ? (lo && !hi)
+            const bool mine = tb == 0   ? ((lo && !hi) || (summary && lm == 0))
                               : tb == 1 ? (hi && !lo)
                               : dtab    ? (lo && __popc(hi) == 1)
                                         : (lo && hi == (1u << (tb - 2)));
             if (!mine)
-                continue;  // uniform
+                return;  // uniform
             const bool tone = (base >> d.target) & 1ull;
-            const double p0 = uniform_f64(d.ph[0]), p1 = uniform_f64(d.ph[1]);
-            // the tile-local index an entry stands for
-            auto at = [&](int k) -> uint32_t {
-                return tb == 0   ? (uint32_t)lane
-                       : tb == 1 ? (uint32_t)(lane + 64 * k) << 6
-                       : dtab    ? ((uint32_t)(lane + 64 * k) << 6) | uv
-                                 : (uint32_t)lane | ((uint32_t)k << (4 + tb));
-            };
-            acc0 += diag_phase_at(d, at(0), tone, p0, p1);
+            acc0 += diag_phase_at(d, at(0), tone);
             if (ne > 1)
-                acc1 += diag_phase_at(d, at(1), tone, p0, p1);
+                acc1 += diag_phase_at(d, at(1), tone);
             if (ne > 2) {
-                acc2 += diag_phase_at(d, at(2), tone, p0, p1);
-                acc3 += diag_phase_at(d, at(3), tone, p0, p1);
+                acc2 += diag_phase_at(d, at(2), tone);
+                acc3 += diag_phase_at(d, at(3), tone);
             }
-        }
+        });
         double *dst = tb == 0 ? A : tb == 1 ? B : Rt + (tb - 2) * 128;
         if ((tb != 1 && !dtab) || (uint32_t)lane < nb)
             dst[lane] = acc0;
