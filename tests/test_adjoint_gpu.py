@@ -206,3 +206,53 @@ def test_adjoint_fused_tiles(gpu, tile, low):
     finally:
         gpu.sv_tune_set("tile_log2_c128", 12)
         gpu.sv_tune_set("tile_low_bits_c128", 6)
+
+
+def test_adjoint_n32_product_state_closed_form(gpu):
+    """The adjoint at n = 32 (64 GiB per state vector; the sweep holds the
+    state and the co-state, no tape).  RY(theta_i) then RZ(phi_i) on every
+    qubit leaves the product state with Bloch vectors
+    (sin theta cos phi, sin theta sin phi, cos theta), so for
+    H = sum a_i Z_i Z_{i+1} + sum b_i X_i the loss is
+    sum a_i cos(theta_i) cos(theta_{i+1}) + sum b_i sin(theta_i) cos(phi_i),
+    and every derivative has a closed form."""
+    import torch
+    n = 32
+    rng = np.random.default_rng(56)
+    gates = []
+    for q in range(n):
+        gates.append(W.Gate("RY", q, param=2 * q))
+        gates.append(W.Gate("RZ", q, param=2 * q + 1))
+    c = W.Circuit(n, gates, rng.uniform(0.0, 2 * np.pi, size=2 * n))
+    terms = W.zz_x_hamiltonian(n, seed=56)
+    a = np.array([t.coef for t in terms[:n - 1]])
+    b = np.array([t.coef for t in terms[n - 1:]])
+    th, ph = c.params[0::2], c.params[1::2]
+    loss_ref = np.sum(a * np.cos(th[:-1]) * np.cos(th[1:])) + np.sum(b * np.sin(th) * np.cos(ph))
+    g_th = b * np.cos(th) * np.cos(ph)
+    g_th[1:] -= np.sin(th[1:]) * a * np.cos(th[:-1])
+    g_th[:-1] -= np.sin(th[:-1]) * a * np.cos(th[1:])
+    g_ph = -b * np.sin(th) * np.sin(ph)
+    ref = np.empty(2 * n)
+    ref[0::2], ref[1::2] = g_th, g_ph
+    _say("adjoint n=32 (two 64 GiB vectors)")
+    torch.cuda.empty_cache()
+    err = None
+    try:
+        psi = torch.empty(1 << n, dtype=torch.complex128, device="cuda")
+        lam = torch.empty_like(psi)
+        params = torch.from_numpy(c.params).cuda()
+        gpu.sv_init(psi, 0)
+        gpu.sv_apply_circuit(psi, c, params=params)
+        grad, loss = gpu.sv_adjoint_grad(psi, lam, c, params, terms)
+        g = grad.cpu().numpy()
+        lv = loss.item()
+        _say("adjoint n=32 loss %.12f (closed form %.12f), max grad err %.2e"
+             % (lv, loss_ref, np.max(np.abs(g - ref))))
+        if abs(lv - loss_ref) > 1e-10 or np.max(np.abs(g - ref)) > 1e-8 * max(1.0, np.max(np.abs(ref))):
+            err = "loss %.3e off, gradient %.3e off" % (abs(lv - loss_ref), np.max(np.abs(g - ref)))
+    finally:
+        psi = lam = None
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+    assert err is None, err
