@@ -479,6 +479,48 @@ __device__ __forceinline__ void diag_sweep_tables(cplx_t<R> *tile, double *tab, 
         }
     }
     __syncthreads();
+    // When every term sits in A, B and D (no R tables, no per-amplitude
+    // terms), the three phase tables become unit factors once per tile, in
+    // the free part of the R area after D's phases, and an amplitude costs
+    // two or three complex products instead of a sine and cosine.
+    constexpr int kSlots = (int)(sizeof(cplx_t<R>) / sizeof(double));  // table slots per factor
+    const int fbase = use_d ? (int)nb : 0;  // D's phases occupy Rt[0 .. nb)
+    const bool factors = !any_rest && (use_d || !have_r) && fbase + kSlots * (64 + 2 * (int)nb) <= Hb * 128;
+    if (factors) {  // uniform
+        cplx_t<R> *FA = reinterpret_cast<cplx_t<R> *>(Rt + fbase);
+        cplx_t<R> *FB = FA + 64, *FD = FB + nb;
+        const uint32_t nf = 64 + (use_d ? 2 : 1) * nb;
+        for (uint32_t k = threadIdx.x; k < nf; k += THREADS) {
+            const double ph = k < 64 ? th0 + A[k] : (k < 64 + nb ? B[k - 64] : Rt[k - 64 - nb]);
+            R fr, fi;
+            phase_factor<R>(ph, &fr, &fi);
+            cplx_t<R> f;
+            f.x = fr;
+            f.y = fi;
+            FA[k] = f;  // FA, FB and FD are consecutive
+        }
+        __syncthreads();
+        for (uint32_t j = threadIdx.x; j < T; j += THREADS) {
+            const uint32_t u = j & 63u, v = j >> 6;
+            const cplx_t<R> a = FA[u], b = FB[v];
+            cplx_t<R> f;
+            f.x = a.x * b.x - a.y * b.y;
+            f.y = a.x * b.y + a.y * b.x;
+            if (use_d && ((u & um) == uv)) {
+                const cplx_t<R> d = FD[v];
+                const R fx = f.x * d.x - f.y * d.y;
+                f.y = f.x * d.y + f.y * d.x;
+                f.x = fx;
+            }
+            const cplx_t<R> x = tile[j];
+            cplx_t<R> y;
+            y.x = x.x * f.x - x.y * f.y;
+            y.y = x.x * f.y + x.y * f.x;
+            tile[j] = y;
+        }
+        __syncthreads();
+        return;
+    }
     for (uint32_t j = threadIdx.x; j < T; j += THREADS) {
         const uint32_t u = j & 63u, v = j >> 6;
         double t = th0 + A[u] + B[v];
