@@ -27,11 +27,14 @@ def _err(got, ref):
     return float(np.max(np.abs(got.astype(np.complex128) - ref)) / np.max(np.abs(ref)))
 
 
-@pytest.mark.parametrize("dtype,k", [("c128", 4), ("c64", 4), ("c64", 5)])
-@pytest.mark.parametrize("n", [10, 11, 13, 20])
+# the block works on whole groups of 64 rows of 2^k amplitudes, so it needs
+# n >= k + 6; smaller states are rejected (test below)
+DENSE_CASES = [(dt, k, n) for dt, k in (("c128", 4), ("c64", 4), ("c64", 5)) for n in (10, 11, 13, 20)
+               if n >= k + 6]
+
+
+@pytest.mark.parametrize("dtype,k,n", DENSE_CASES)
 def test_dense_low_matrix(gpu, dtype, k, n):
-    if n < k + 6:
-        pytest.skip("the dense block needs n >= k + 6")
     M = _unitary(k, 100 * n + k)
     psi = W.random_state(n, n + k)
     ref = oracle.apply_block_low(psi.copy(), n, k, M)
@@ -45,6 +48,10 @@ def test_dense_low_rejects_unsupported(gpu):
     d = _dev(W.random_state(9, 1), "c128")
     with pytest.raises(gpu.SvError) as e:
         gpu.sv_apply_dense_low(d, 4, _unitary(4, 1))  # n < k + 6
+    assert e.value.code == gpu.SV_ENOTSUP
+    d = _dev(W.random_state(10, 1), "c64")
+    with pytest.raises(gpu.SvError) as e:
+        gpu.sv_apply_dense_low(d, 5, _unitary(5, 1))  # n < k + 6
     assert e.value.code == gpu.SV_ENOTSUP
     d = _dev(W.random_state(12, 1), "c128")
     with pytest.raises(gpu.SvError):
