@@ -550,6 +550,40 @@ __device__ __forceinline__ void diag_sweep_tables(cplx_t<R> *tile, double *tab, 
     __syncthreads();
 }
 
+// The pair loop of one gate on the tile.  The in-tile expansion of the
+// reduced index is held in NS register segments (the gate's own count or
+// more; unused ones have an empty mask), so the index costs two
+// instructions per segment: a gate with no tile-local control has at most
+// two segments, each tile-local control adds one.  NS = 0: the expansion is
+// read from the descriptor for every pair (long segment lists).
+template <typename R, int THREADS, int NS>
+__device__ __forceinline__ void tile_pairs(cplx_t<R> *tile, const Mat2<R> &mm, const TileGate &g, uint32_t st,
+                                           uint32_t np) {
+    constexpr int N = NS > 0 ? NS : 1;
+    uint32_t sh[N], mk[N];
+#pragma unroll
+    for (int s = 0; s < N; ++s) {
+        sh[s] = s < (int)g.nseg ? g.shift[s] : 0u;
+        mk[s] = s < (int)g.nseg ? g.mask[s] : 0u;
+    }
+    const uint32_t fixed = g.fixed;
+    for (uint32_t r = threadIdx.x; r < np; r += THREADS) {
+        uint32_t p1;
+        if (NS > 0) {
+            p1 = fixed;
+#pragma unroll
+            for (int s = 0; s < N; ++s)
+                p1 |= (r << sh[s]) & mk[s];
+        } else {
+            p1 = tile_expand(g, r);
+        }
+        cplx_t<R> x = tile[p1], y = tile[p1 | st];
+        apply_pair<R>(mm, x, y);
+        tile[p1] = x;
+        tile[p1 | st] = y;
+    }
+}
+
 // Whether any operation of the run acts on the tile at base.
 template <typename Src> __device__ __forceinline__ bool tile_touched(uint64_t base, const Src &gates) {
     bool any = false;
@@ -650,15 +684,17 @@ __device__ __forceinline__ void tile_run(cplx_t<R> *tile, uint64_t base, const T
             const Mat2<R> mm = tile_mat<R>(g);
             const uint32_t st = 1u << g.target;
             const uint32_t np = g.npairs;
-            const bool in_regs = g.nseg <= (uint32_t)kExpRegs;  // uniform
-            const TileExp ex = tile_exp_load(g);
-            for (uint32_t r = threadIdx.x; r < np; r += THREADS) {
-                const uint32_t p1 = in_regs ? tile_exp(ex, r) : tile_expand(g, r);
-                cplx_t<R> x = tile[p1], y = tile[p1 | st];
-                apply_pair<R>(mm, x, y);
-                tile[p1] = x;
-                tile[p1 | st] = y;
-            }
+            // the loop's index arithmetic sized to the gate (uniform branches)
+            if (g.nseg <= 2)
+                tile_pairs<R, THREADS, 2>(tile, mm, g, st, np);
+            else if (g.nseg <= 3)
+                tile_pairs<R, THREADS, 3>(tile, mm, g, st, np);
+            else if (g.nseg <= 4)
+                tile_pairs<R, THREADS, 4>(tile, mm, g, st, np);
+            else if (g.nseg <= (uint32_t)kExpRegs)
+                tile_pairs<R, THREADS, kExpRegs>(tile, mm, g, st, np);
+            else
+                tile_pairs<R, THREADS, 0>(tile, mm, g, st, np);
             __syncthreads();
         }
         ++i;
