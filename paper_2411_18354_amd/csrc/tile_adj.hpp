@@ -59,6 +59,53 @@ __device__ __forceinline__ bool adj_tile_touched(uint64_t base, const DeviceGate
     return false;
 }
 
+// One pair gate un-applied on both tiles, with its gradient term (sl >= 0;
+// generator a[8]) summed per lane in pair order.  The in-tile expansion is
+// held in NS register segments, as in the forward pass's pair loop (NS = 0:
+// read from the descriptor for every pair).
+template <typename R, int THREADS, int NS>
+__device__ __forceinline__ double adj_tile_pairs(cplx_t<R> *tp, cplx_t<R> *tl, const TileGate &g, int sl,
+                                                 const double *a) {
+    constexpr int N = NS > 0 ? NS : 1;
+    uint32_t sh[N], mk[N];
+#pragma unroll
+    for (int s = 0; s < N; ++s) {
+        sh[s] = s < (int)g.nseg ? g.shift[s] : 0u;
+        mk[s] = s < (int)g.nseg ? g.mask[s] : 0u;
+    }
+    const uint32_t fixed = g.fixed;
+    const Mat2<R> u = tile_mat<R>(g);
+    const uint32_t st = 1u << g.target;
+    double acc = 0.0;
+    for (uint32_t r = threadIdx.x; r < g.npairs; r += THREADS) {
+        uint32_t p1;
+        if (NS > 0) {
+            p1 = fixed;
+#pragma unroll
+            for (int s = 0; s < N; ++s)
+                p1 |= (r << sh[s]) & mk[s];
+        } else {
+            p1 = tile_expand(g, r);
+        }
+        cplx_t<R> x = tp[p1], y = tp[p1 | st], lx = tl[p1], ly = tl[p1 | st];
+        if (sl >= 0) {
+            const double xr = x.x, xi = x.y, yr = y.x, yi = y.y;
+            const double axr = a[0] * xr - a[1] * xi + a[2] * yr - a[3] * yi;
+            const double axi = a[0] * xi + a[1] * xr + a[2] * yi + a[3] * yr;
+            const double ayr = a[4] * xr - a[5] * xi + a[6] * yr - a[7] * yi;
+            const double ayi = a[4] * xi + a[5] * xr + a[6] * yi + a[7] * yr;
+            acc += 2.0 * ((double)lx.x * axr + (double)lx.y * axi + (double)ly.x * ayr + (double)ly.y * ayi);
+        }
+        apply_pair<R>(u, x, y);
+        apply_pair<R>(u, lx, ly);
+        tp[p1] = x;
+        tp[p1 | st] = y;
+        tl[p1] = lx;
+        tl[p1 | st] = ly;
+    }
+    return acc;
+}
+
 template <typename R, int THREADS>
 __device__ __forceinline__ void adj_tile_run(cplx_t<R> *tp, cplx_t<R> *tl, uint64_t base, uint32_t T,
                                              const DeviceGates &gates, const int32_t *__restrict__ gslot,
@@ -103,28 +150,17 @@ __device__ __forceinline__ void adj_tile_run(cplx_t<R> *tp, cplx_t<R> *tl, uint6
             }
         } else if ((base & g.hi_mask) == g.hi_vals) {  // uniform
             did = true;
-            const Mat2<R> u = tile_mat<R>(g);
-            const uint32_t st = 1u << g.target;
-            const bool in_regs = g.nseg <= (uint32_t)kExpRegs;  // uniform
-            const TileExp ex = tile_exp_load(g);
-            for (uint32_t r = threadIdx.x; r < g.npairs; r += THREADS) {
-                const uint32_t p1 = in_regs ? tile_exp(ex, r) : tile_expand(g, r);
-                cplx_t<R> x = tp[p1], y = tp[p1 | st], lx = tl[p1], ly = tl[p1 | st];
-                if (sl >= 0) {
-                    const double xr = x.x, xi = x.y, yr = y.x, yi = y.y;
-                    const double axr = a[0] * xr - a[1] * xi + a[2] * yr - a[3] * yi;
-                    const double axi = a[0] * xi + a[1] * xr + a[2] * yi + a[3] * yr;
-                    const double ayr = a[4] * xr - a[5] * xi + a[6] * yr - a[7] * yi;
-                    const double ayi = a[4] * xi + a[5] * xr + a[6] * yi + a[7] * yr;
-                    acc += 2.0 * ((double)lx.x * axr + (double)lx.y * axi + (double)ly.x * ayr + (double)ly.y * ayi);
-                }
-                apply_pair<R>(u, x, y);
-                apply_pair<R>(u, lx, ly);
-                tp[p1] = x;
-                tp[p1 | st] = y;
-                tl[p1] = lx;
-                tl[p1 | st] = ly;
-            }
+            // the loop's index arithmetic sized to the gate (uniform branches)
+            if (g.nseg <= 2)
+                acc = adj_tile_pairs<R, THREADS, 2>(tp, tl, g, sl, a);
+            else if (g.nseg <= 3)
+                acc = adj_tile_pairs<R, THREADS, 3>(tp, tl, g, sl, a);
+            else if (g.nseg <= 4)
+                acc = adj_tile_pairs<R, THREADS, 4>(tp, tl, g, sl, a);
+            else if (g.nseg <= (uint32_t)kExpRegs)
+                acc = adj_tile_pairs<R, THREADS, kExpRegs>(tp, tl, g, sl, a);
+            else
+                acc = adj_tile_pairs<R, THREADS, 0>(tp, tl, g, sl, a);
         }
         if (did) {  // uniform
             if (sl >= 0) {
