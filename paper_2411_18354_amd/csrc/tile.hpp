@@ -149,34 +149,10 @@ __device__ __forceinline__ uint32_t tile_expand(const TileGate &g, uint32_t x) {
     return p;
 }
 
-// A gate's in-tile pair expansion held in registers: up to kExpRegs
-// segments (the target plus up to four tile-local controls), unused ones
-// with an empty mask.  Loading it once per gate keeps the descriptor loads
-// out of the pair loop.
+// Most expansion segments a pair loop holds in registers (the target plus up
+// to four tile-local controls); a gate with more reads its expansion from
+// the descriptor for every pair.
 constexpr int kExpRegs = 6;
-struct TileExp {
-    uint32_t fixed;
-    uint32_t sh[kExpRegs], mk[kExpRegs];
-};
-
-__device__ __forceinline__ TileExp tile_exp_load(const TileGate &g) {
-    TileExp e;
-    e.fixed = g.fixed;
-#pragma unroll
-    for (int s = 0; s < kExpRegs; ++s) {
-        e.sh[s] = s < (int)g.nseg ? g.shift[s] : 0u;
-        e.mk[s] = s < (int)g.nseg ? g.mask[s] : 0u;
-    }
-    return e;
-}
-
-__device__ __forceinline__ uint32_t tile_exp(const TileExp &e, uint32_t x) {
-    uint32_t p = e.fixed;
-#pragma unroll
-    for (int s = 0; s < kExpRegs; ++s)
-        p |= (x << e.sh[s]) & e.mk[s];
-    return p;
-}
 
 __device__ __forceinline__ uint64_t tile_offset(const TileMap &tm, uint32_t j) {
     uint64_t o = j & ((1u << tm.a) - 1);
