@@ -9,10 +9,12 @@ gate is applied once with the scheduled kernels (27 launches per step).  The
 same sweep with the masked baseline kernel (all 2^(n-1) pairs, control test
 per pair) is timed separately for comparison.
 
-Prints one JSON line: gate updates/s of the scheduled sweep, the roofline
-of its dominant kernel (algorithmic bytes / HIP-event launch duration against
-the 8 TB/s HBM peak), per-(t, c) rows, and the CPU oracle timed on a bounded
-sample of the same sweep.
+The last stdout line is one short JSON object: gate updates/s of the
+scheduled sweep, the roofline of its dominant kernel (algorithmic bytes /
+HIP-event launch duration against the 8 TB/s HBM peak), the CPU oracle timed
+on a bounded sample of the same sweep, and a per-control-count summary.  The
+per-(t, c) rows and the extra measurements go to a JSON file (--detail-out)
+and to stderr.
 """
 import argparse
 import hashlib
@@ -316,6 +318,112 @@ def control_position_sweep(sv, torch, np, d, U, stream, n, t=13, reps=5):
         row["masked_over_sched"] = round(row["masked_us"] / row["sched_us"], 2)
         out.append(row)
     return out
+
+
+def _deposit(v, mask):
+    """Spread the low bits of v over the set bits of mask, in ascending order."""
+    out, b = 0, 0
+    for q in range(64):
+        if (mask >> q) & 1:
+            if (v >> b) & 1:
+                out |= 1 << q
+            b += 1
+    return out
+
+
+MALL_ROTATE_BYTES = 512 << 20  # twice the 256 MB Infinity Cache
+
+
+def graph_protocol(sv, torch, np, st, n, cases, U, stream, amp_bytes=AMP_BYTES, target_ms=30.0, trials=5,
+                   modes=("auto", "masked")):
+    """Per (target, controls) and kernel form: R back-to-back launches of the
+    gate captured once as a HIP graph and replayed, median of `trials`
+    replays after one warm-up, R chosen so that a replay lasts about
+    target_ms.  Consecutive launches rotate over K distinct control-value
+    combinations (K * touched bytes >= 512 MiB, at most 2^c), so each launch
+    touches amplitudes disjoint from the previous K - 1 and the 256 MB
+    Infinity Cache cannot serve them; the kernels do the same work for any
+    control values (the values are only the fixed bits of the index
+    expansion).  Both forms use the same launch machinery."""
+    rows = []
+    for t, ctrls in cases:
+        c = len(ctrls)
+        cm = sum(1 << q for q in ctrls)
+        touched = (1 << (n - c)) * amp_bytes
+        K = min(1 << c, max(1, -(-MALL_ROTATE_BYTES // touched)))
+        vals = [_deposit((1 << c) - 1 - r, cm) for r in range(K)]
+        alg = 2 * touched
+        row = {"t": t, "c": c, "K_vals": K}
+        for mode in modes:
+            with torch.cuda.stream(stream):
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                sv.sv_apply_gate_masks(st, t, cm, vals[0], U, mode=mode, stream=stream)
+                e0.record(stream)
+                for r in range(K):
+                    sv.sv_apply_gate_masks(st, t, cm, vals[r], U, mode=mode, stream=stream)
+                e1.record(stream)
+            torch.cuda.synchronize()
+            est = max(e0.elapsed_time(e1) / K, 1e-3)
+            R = int(min(4096, max(K, np.ceil(target_ms / est))))
+            R = -(-R // K) * K
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g, stream=stream):
+                for r in range(R):
+                    sv.sv_apply_gate_masks(st, t, cm, vals[r % K], U, mode=mode, stream=stream)
+            ts = []
+            with torch.cuda.stream(stream):
+                g.replay()
+                torch.cuda.synchronize()
+                for _ in range(trials):
+                    a = torch.cuda.Event(enable_timing=True)
+                    b = torch.cuda.Event(enable_timing=True)
+                    a.record(stream)
+                    g.replay()
+                    b.record(stream)
+                    torch.cuda.synchronize()
+                    ts.append(a.elapsed_time(b) / R)
+            del g
+            med = float(np.median(ts))
+            key = "sched" if mode == "auto" else "masked"
+            row[key + "_R"] = R
+            row[key + "_us"] = round(med * 1e3, 2)
+            row[key + "_GBps"] = round(alg / med / 1e6, 1)
+            row[key + "_frac"] = round(alg / med / 1e6 / HBM_PEAK_GBPS, 3)
+        if "sched_us" in row and "masked_us" in row:
+            row["masked_over_sched"] = round(row["masked_us"] / row["sched_us"], 2)
+        rows.append(row)
+    return rows
+
+
+def protocol_summary(rows):
+    """Mean over targets, per control count, of the protocol rows."""
+    by = {}
+    for r in rows:
+        by.setdefault(r["c"], []).append(r)
+    out = {"c": sorted(by)}
+    for k in ("sched_frac", "masked_frac", "masked_over_sched", "sched_us"):
+        if all(k in r for r in rows):
+            out[k] = [round(float(sum(r[k] for r in by[c]) / len(by[c])), 3) for c in out["c"]]
+    return out
+
+
+def protocol_n32(sv, W, torch, np, stream, U):
+    """The controlled-gate sweep at the metric's n=32 end: a 64 GiB
+    complex128 state of i.i.d. N(0,1) components (torch generator seed 11),
+    targets {0, 16, 31}, c = 0..8 random controls (seed 3), scheduled and
+    masked, timed by graph_protocol."""
+    n = 32
+    log("graph-launched sweep, n=32 complex128 (64 GiB)")
+    cases = W.gate_sweep_cases(n, seed=3, targets=(0, 16, 31))
+    st = torch.empty(1 << n, dtype=torch.complex128, device="cuda:0")
+    gen = torch.Generator(device="cuda:0")
+    gen.manual_seed(11)
+    st.view(torch.float64).normal_(generator=gen)
+    rows = graph_protocol(sv, torch, np, st, n, cases, U, stream, target_ms=40.0, trials=3)
+    del st
+    torch.cuda.empty_cache()
+    return rows
 
 
 RATED_POWER_W = 1400.0  # MI355X total board power
@@ -664,6 +772,59 @@ def measure_extras(sv, W, torch, np, stream, with_layered, psi_host=None, cases=
     return out
 
 
+METRIC = "gate updates/s & HBM GB/s vs #controls (n=28-32); adjoint grads/s"
+
+
+def cpu_model():
+    """CPU model name and physical core count of this host (from /proc/cpuinfo)."""
+    model, cores = None, set()
+    phys = core = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                k, _, v = line.partition(":")
+                k, v = k.strip(), v.strip()
+                if k == "model name" and model is None:
+                    model = v
+                elif k == "physical id":
+                    phys = v
+                elif k == "core id":
+                    core = v
+                elif not k and phys is not None:
+                    cores.add((phys, core))
+                    phys = core = None
+        if phys is not None:
+            cores.add((phys, core))
+    except OSError:
+        pass
+    return model, (len(cores) or None)
+
+
+def write_detail(detail, path):
+    """Write the per-row tables and extra measurements as JSON (also echoed on
+    stderr); returns the path written, or None."""
+    log("detail " + json.dumps(detail, separators=(",", ":")))
+    if not path:
+        return None
+    try:
+        d = os.path.dirname(os.path.abspath(path))
+        os.makedirs(d, exist_ok=True)
+        with open(path, "w") as fh:
+            json.dump(detail, fh, indent=1)
+        return os.path.relpath(path, ROOT) if os.path.abspath(path).startswith(ROOT) else path
+    except OSError as e:
+        log("could not write %s: %s" % (path, e))
+        return None
+
+
+def compact_adjoint(extras):
+    a = extras.get("adjoint_hea_n24")
+    if not a:
+        return None
+    return {"workload": "n=24 ansatz, 768 params", "grads_per_s": a["gradients_per_s"],
+            "param_derivs_per_s": a["param_derivatives_per_s"], "bwd_over_fwd": a["backward_over_forward"]}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -677,6 +838,9 @@ def main():
                          "(calibration of the rocprofv3 byte counters)")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the adjoint, batched and paper-circuit measurements")
+    ap.add_argument("--no-protocol", action="store_true",
+                    help="skip the graph-launched per-gate sweeps (n=28 and n=32)")
+    ap.add_argument("--no-n32", action="store_true", help="skip the n=32 graph-launched sweep (64 GiB state)")
     ap.add_argument("--layered-n32", action="store_true",
                     help="also time the layered n=32 circuit (64 GiB) with and without LDS fusion (about a minute)")
     ap.add_argument("--summarize-profile", nargs=3, metavar=("TRACE_DIR", "FETCH_DIR", "WRITE_DIR"),
@@ -687,6 +851,8 @@ def main():
     ap.add_argument("--summarize-positions", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="write the control-position traffic summary from rocprofv3 --pmc output of "
                          "--positions-only and exit")
+    ap.add_argument("--detail-out", default=os.path.join(ROOT, "gpurun_out", "bench_detail.json"),
+                    help="file receiving the per-row tables and extra measurements as JSON ('' disables)")
     ap.add_argument("--summarize-trace", metavar="TRACE_DIR",
                     help="write the all-kernel summary of a full run from rocprofv3 --kernel-trace output and exit")
     args = ap.parse_args()
@@ -819,11 +985,20 @@ def main():
     if not args.no_extras:
         positions = control_position_sweep(sv, torch, np, d, U, stream, n)
 
+    protocol = None
+    if not args.no_extras and not args.no_protocol:
+        log("graph-launched sweep, n=28 (control values rotated against the Infinity Cache)")
+        protocol = graph_protocol(sv, torch, np, d, n, cases, U, stream)
+
     extras = None
     if not args.no_extras:
         del d
         torch.cuda.empty_cache()
         extras = measure_extras(sv, W, torch, np, stream, args.layered_n32, psi_host, cases, U)
+
+    protocol32 = None
+    if not args.no_extras and not args.no_protocol and not args.no_n32:
+        protocol32 = protocol_n32(sv, W, torch, np, stream, U)
 
     cpu = None
     if args.cpu_seconds > 0:
@@ -837,14 +1012,38 @@ def main():
             oracle.apply_gate(host, n, t, ctrls, (), Uc)
             done += 1
         el = time.perf_counter() - t0
+        model, phys = cpu_model()
         cpu = {"value": round(done / el, 4), "unit": "gate updates/s", "cores": oracle.num_threads(),
-               "kind": "oracle",
-               "sample": "%d gates (the %d-gate sweep in order, repeated) on the same n=28 complex128 state "
-                         "(plain loop over all 2^28 indices per gate, OpenMP), %.1f s" % (done, len(cases), el)}
+               "kind": "oracle", "cpu_model": model, "physical_cores": phys,
+               "sample": "%d gates of the %d-gate sweep in order on the same n=28 state, plain loop over "
+                         "all 2^28 indices per gate, OpenMP, %.1f s" % (done, len(cases), el)}
         del host
 
+    by_c = {}
+    for r in rows:
+        by_c.setdefault(r["c"], []).append(r)
+    cs = sorted(by_c)
+    summary_by_c = {"c": cs, "eager_frac": [round(float(np.mean([r["sched_frac"] for r in by_c[c]])), 3)
+                                            for c in cs]}
+    if protocol:
+        ps = protocol_summary(protocol)
+        summary_by_c["graph_frac"] = ps.get("sched_frac")
+        summary_by_c["graph_masked_frac"] = ps.get("masked_frac")
+        summary_by_c["graph_masked_over_sched"] = ps.get("masked_over_sched")
+    if protocol32:
+        ps = protocol_summary(protocol32)
+        summary_by_c["n32_graph_frac"] = ps.get("sched_frac")
+        summary_by_c["n32_graph_masked_over_sched"] = ps.get("masked_over_sched")
+    detail = {
+        "sweep": rows,
+        "graph_protocol_n28": protocol,
+        "graph_protocol_n32": protocol32,
+        "control_positions": positions,
+        "extras": extras,
+    }
+    detail_path = write_detail(detail, args.detail_out)
     out = {
-        "metric": "gate updates/s (n=28 complex128 controlled-gate sweep, c=0..8)",
+        "metric": METRIC,
         "value": round(value, 2),
         "unit": "gate updates/s",
         "n_gpus": 1,
@@ -856,18 +1055,25 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "controlled-gate sweep: n=28 complex128 state (4 GiB), Haar 2x2, "
-                               "t in {0,13,27} x c=0..8 random controls, scheduled kernels",
-                   "n": n, "gates_per_step": len(cases), "seeds": {"state": 1, "gate": 2, "controls": 3}},
+        "config": {"workload": "n=28 complex128 controlled-gate sweep: Haar 2x2, t in {0,13,27} x c=0..8 "
+                               "random controls (value 1), scheduled kernels, 27 gates per step",
+                   "n": n, "gates_per_step": len(cases), "seeds": [1, 2, 3]},
         "hbm_GBps_alg": round(alg_total / total_ms / 1e6, 1),
-        "roofline": roofline,
+        "roofline": {k: roofline[k] for k in ("bound", "achieved", "peak", "unit", "frac", "traffic", "kernel",
+                                              "avg_launch_us")},
         "cpu_baseline": cpu,
         "masked_value": None if masked_total is None else round(ngates / (masked_total / 1e3), 2),
-        "sweep": rows,
-        "control_positions": positions,
-        "extras": extras,
+        "by_c": summary_by_c,
+        "adjoint": None if not extras else compact_adjoint(extras),
+        "detail": detail_path,
     }
-    print(json.dumps(out), flush=True)
+    line = json.dumps(out, separators=(",", ":"))
+    for k in ("graph_masked_frac", "n32_graph_masked_over_sched", "eager_frac", "graph_masked_over_sched"):
+        if len(line) <= 2000:  # keep the last line short enough for any log tail
+            break
+        out["by_c"].pop(k, None)
+        line = json.dumps(out, separators=(",", ":"))
+    print(line, flush=True)
 
 
 if __name__ == "__main__":
