@@ -428,19 +428,33 @@ def _with_gates(circ, gates):
     return Circuit(circ.n, gates, circ.params, dict(circ.meta))
 
 
+# Conjugating a rotation by this Pauli flips the sign of its angle:
+# F R(phi) F = R(-phi) because F anticommutes with the rotation's own Pauli.
+_SHIFT_FLIP = {"RX": "Z", "RY": "X", "RZ": "X"}
+
+
 def grad_param_shift(circ, params: np.ndarray, terms, which: Optional[Iterable[int]] = None) -> np.ndarray:
     """dL/dtheta_j by the parameter-shift rule.
 
-    For an uncontrolled rotation exp(-i theta P/2) the rule
-    [L(theta + pi/2) - L(theta - pi/2)] / 2 is exact.  A rotation with
-    controls is first rewritten as R(theta/2) . C^kX . R(-theta/2) . C^kX on
-    the same target (Barenco et al., Phys. Rev. A 52, 3457 (1995)), valid for
-    RY and RZ because X R(phi) X = R(-phi); each half-angle rotation is then
-    uncontrolled and shifted on its own; with alpha = beta = theta/2 in
-    R(alpha) . C^kX . R(-beta) . C^kX the chain rule gives
-    dL/dtheta = (dL/dalpha + dL/dbeta) / 2, where the shift rule holds for
-    beta as well because R(-beta) = exp(+i beta P/2).  A parameter used by several
-    gates sums the contributions of each use (product rule)."""
+    The two-term rule dL/dtheta = [L(theta + pi/2) - L(theta - pi/2)] / 2 is
+    exact for a gate exp(-i theta G) whose generator G has exactly two
+    eigenvalues differing by 1 (a constant added to G is a global phase,
+    which cancels in L).  It is applied to the gate as it stands for
+    * an uncontrolled RX/RY/RZ (G = P/2) or its adjoint (G = -P/2);
+    * P(theta), with or without controls, and its adjoint: with controls the
+      gate is exp(i theta Pi), Pi the projector onto the amplitudes whose
+      controls hold and whose target bit is 1, and Pi has eigenvalues 0, 1.
+    A controlled rotation has generator eigenvalues -1/2, 0, +1/2, so it is
+    rewritten first as C-R(phi) = R(phi/2) . C^kF . R(-phi/2) . C^kF on the
+    same target with the same controls (Barenco et al., Phys. Rev. A 52,
+    3457 (1995)), F = X for RY and RZ and F = Z for RX, valid because
+    F R(psi) F = R(-psi).  Each half-angle rotation is uncontrolled; with
+    alpha = beta = phi/2 in R(alpha) . C^kF . R(-beta) . C^kF the chain rule
+    gives dL/dphi = (dL/dalpha + dL/dbeta) / 2, and the shift rule holds for
+    beta as well because R(-beta) = exp(+i beta P/2).  An adjoint-flagged
+    controlled rotation is C-R(-theta): its derivative is minus the one at
+    phi = -theta.  A parameter used by several gates sums the contributions
+    of each use (product rule)."""
     from workloads import Gate
     params = np.asarray(params, dtype=np.float64)
     idx = list(range(len(params))) if which is None else list(which)
@@ -452,24 +466,26 @@ def grad_param_shift(circ, params: np.ndarray, terms, which: Optional[Iterable[i
                 continue
             th = float(params[j])
             base = list(circ.gates)
-            if not g.controls:
+            adj = g.kind.startswith("~")
+            kind = g.kind[1:] if adj else g.kind
+            if not g.controls or kind == "P":
                 for sgn in (+1.0, -1.0):
                     gs = list(base)
-                    gs[gi] = Gate(g.kind, g.target, (), (), th + sgn * np.pi / 2.0)
+                    gs[gi] = Gate(g.kind, g.target, g.controls, g.values, th + sgn * np.pi / 2.0)
                     total += 0.5 * sgn * loss(_with_gates(circ, gs), params, terms)
-            else:
-                if g.kind not in ("RY", "RZ"):
-                    raise ValueError("controlled %s has no shift decomposition here" % g.kind)
-                cx = Gate("X", g.target, g.controls, g.values)
-                for which_half, coef in ((0, 0.5), (1, 0.5)):
-                    for sgn in (+1.0, -1.0):
-                        alpha = th / 2.0 + (sgn * np.pi / 2.0 if which_half == 0 else 0.0)
-                        beta = th / 2.0 + (sgn * np.pi / 2.0 if which_half == 1 else 0.0)
-                        # circuit order (first applied first): C^kX, R(-beta), C^kX, R(alpha)
-                        rep = [cx, Gate(g.kind, g.target, (), (), -beta), cx,
-                               Gate(g.kind, g.target, (), (), alpha)]
-                        gs = base[:gi] + rep + base[gi + 1:]
-                        total += coef * 0.5 * sgn * loss(_with_gates(circ, gs), params, terms)
+                continue
+            if kind not in _SHIFT_FLIP:
+                raise ValueError("controlled %s has no shift decomposition here" % g.kind)
+            phi, dsign = (-th, -1.0) if adj else (th, 1.0)
+            flip = Gate(_SHIFT_FLIP[kind], g.target, g.controls, g.values)
+            for which_half in (0, 1):
+                for sgn in (+1.0, -1.0):
+                    alpha = phi / 2.0 + (sgn * np.pi / 2.0 if which_half == 0 else 0.0)
+                    beta = phi / 2.0 + (sgn * np.pi / 2.0 if which_half == 1 else 0.0)
+                    # circuit order (first applied first): C^kF, R(-beta), C^kF, R(alpha)
+                    rep = [flip, Gate(kind, g.target, (), (), -beta), flip, Gate(kind, g.target, (), (), alpha)]
+                    gs = base[:gi] + rep + base[gi + 1:]
+                    total += dsign * 0.5 * 0.5 * sgn * loss(_with_gates(circ, gs), params, terms)
         out[oi] = total
     return out
 

@@ -1,7 +1,6 @@
 """GPU parity of expectation values and adjoint gradients against the
 oracle: <psi|H|psi> and H psi to 1e-12, gradients to 1e-8 against the
-oracle's parameter-shift rule (and central finite differences where no shift
-rule applies), through the C ABI and through torch.autograd."""
+oracle's parameter-shift rule, through the C ABI and through torch.autograd."""
 import numpy as np
 import pytest
 
@@ -116,14 +115,16 @@ def test_adjoint_controlled_rotations_vs_param_shift(gpu):
     _grad_check(gpu, circ, terms, ref)
 
 
-def test_adjoint_rx_phase_and_adjoint_flags_vs_finite_differences(gpu):
-    """Kinds without a shift rule in the oracle here (controlled RX and P,
-    adjoint-flagged rotations): central differences, h = 1e-5."""
+def test_adjoint_rx_phase_and_adjoint_flags_vs_param_shift(gpu):
+    """Every angle kind, uncontrolled and with up to two controls of mixed
+    values: controlled RX and P and the adjoint-flagged rotations against the
+    oracle's exact shift rules at 1e-8; central differences (h = 1e-5) as a
+    second, looser check."""
     n = 6
     rng = np.random.default_rng(4)
     gates = []
-    kinds = ("RX", "P", "~RY", "~RZ", "RZ", "~P")
-    for i in range(30):
+    kinds = ("RX", "P", "~RY", "~RZ", "RZ", "~P", "~RX", "RY")
+    for i in range(40):
         t = int(rng.integers(0, n))
         others = [q for q in range(n) if q != t]
         c = int(rng.integers(0, 3))
@@ -133,8 +134,11 @@ def test_adjoint_rx_phase_and_adjoint_flags_vs_finite_differences(gpu):
         gates.append(W.Gate("H", int(rng.integers(0, n))))
     circ = W.Circuit(n, gates, rng.uniform(0, 2 * np.pi, size=5))
     terms = _rand_terms(n, 10, 5)
-    ref = oracle.grad_finite_diff(circ, circ.params, terms)
-    _grad_check(gpu, circ, terms, ref, tol=1e-7)
+    ref = oracle.grad_param_shift(circ, circ.params, terms)
+    err = _grad_check(gpu, circ, terms, ref, tol=1e-8)
+    fd = oracle.grad_finite_diff(circ, circ.params, terms)
+    assert np.max(np.abs(fd - ref)) <= 1e-7
+    _say("all kinds: adjoint vs shift %.2e" % err)
 
 
 def test_autograd_function(gpu):

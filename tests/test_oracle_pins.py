@@ -10,6 +10,7 @@ import math
 import os
 
 import numpy as np
+from scipy.linalg import expm
 import pytest
 
 import oracle
@@ -293,9 +294,18 @@ def test_gradient_one_qubit_analytic():
     assert abs(g[0] + math.sin(0.9)) < 1e-14
 
 
+def _generator(kind):
+    """A with dG/dtheta = A G(theta) for the angle kinds: -i P/2 for
+    RX/RY/RZ = exp(-i theta P/2), i |1><1| for P = diag(1, e^{i theta}); an
+    adjoint-flagged kind G(-theta) has -A."""
+    adj = kind.startswith("~")
+    A = {"RX": -0.5j * D.PX, "RY": -0.5j * D.PY, "RZ": -0.5j * D.PZ, "P": 1j * D.P1}[kind.lstrip("~")]
+    return -A if adj else A
+
+
 def _dense_grad(c, params, terms):
-    """Exact gradient from dense matrices: d/dtheta of a (controlled)
-    rotation is P_sat (x) dR/dtheta with dR/dtheta = -i/2 P R."""
+    """Exact gradient from dense matrices: d/dtheta of a (controlled) gate
+    is P_sat (x) dG/dtheta, summed over every gate using the parameter."""
     n = c.n
     H = D.hamiltonian_matrix(n, terms)
     mats = []
@@ -309,8 +319,7 @@ def _dense_grad(c, params, terms):
         if g.param < 0:
             continue
         th = params[g.param]
-        Pm = {"RX": D.PX, "RY": D.PY, "RZ": D.PZ}[g.kind]
-        dR = -0.5j * Pm @ oracle.gate_matrix(g.kind, th)
+        dR = _generator(g.kind) @ oracle.gate_matrix(g.kind, th)
         vals = g.values if len(g.values) else [1] * len(g.controls)
         proj = {q: (D.P1 if v else D.P0) for q, v in zip(g.controls, vals)}
         dM = D.kron_ops({**proj, g.target: dR}, n)
@@ -347,6 +356,101 @@ def test_param_shift_vs_dense_with_controlled_rotations():
     fd = oracle.grad_finite_diff(c, params, terms)
     assert np.max(np.abs(ps - ref)) < 1e-12
     assert np.max(np.abs(fd - ref)) < 1e-8
+
+
+ANGLE_KINDS = ("RX", "RY", "RZ", "P", "~RX", "~RY", "~RZ", "~P")
+
+
+def _all_kinds_circuit(seed):
+    """Every angle kind, uncontrolled and with one and two controls of mixed
+    values, parameters shared between kinds, fixed gates in between."""
+    n = 4
+    rng = np.random.default_rng(seed)
+    gates = []
+    for i, kind in enumerate(ANGLE_KINDS * 3):
+        t = int(rng.integers(0, n))
+        others = [q for q in range(n) if q != t]
+        nc = (i // len(ANGLE_KINDS)) % 3
+        ctrls = tuple(int(q) for q in rng.choice(others, size=nc, replace=False))
+        vals = tuple(int(v) for v in rng.integers(0, 2, size=nc))
+        gates.append(W.Gate(kind, t, ctrls, vals, param=int(rng.integers(0, 6))))
+        gates.append(W.Gate("H", int(rng.integers(0, n))))
+    return W.Circuit(n, gates, rng.uniform(0, 2 * math.pi, size=6))
+
+
+def test_param_shift_every_kind_vs_dense():
+    """The shift rule for controlled RX (C^kZ conjugation), controlled P
+    (two generator eigenvalues), and adjoint-flagged kinds, against dense
+    derivatives, and central differences against the same."""
+    for seed in (71, 72):
+        c = _all_kinds_circuit(seed)
+        terms = W.zz_x_hamiltonian(c.n, seed)
+        ref = _dense_grad(c, c.params, terms)
+        ps = oracle.grad_param_shift(c, c.params, terms)
+        fd = oracle.grad_finite_diff(c, c.params, terms)
+        assert np.max(np.abs(ps - ref)) < 1e-12, np.max(np.abs(ps - ref))
+        assert np.max(np.abs(fd - ref)) < 1e-8
+
+
+def test_param_shift_planted_mistakes_fail(monkeypatch):
+    """The dense pin catches plausible mistakes in the shift rule: a
+    conjugating Pauli that commutes with the rotation (X for RX, Y for RY,
+    Z for RZ) and a dropped sign for adjoint-flagged controlled rotations."""
+    c = _all_kinds_circuit(71)
+    terms = W.zz_x_hamiltonian(c.n, 71)
+    ref = _dense_grad(c, c.params, terms)
+    for flip in ({"RX": "X", "RY": "X", "RZ": "X"}, {"RX": "Z", "RY": "Y", "RZ": "X"},
+                 {"RX": "Z", "RY": "X", "RZ": "Z"}):
+        monkeypatch.setattr(oracle, "_SHIFT_FLIP", flip)
+        assert np.max(np.abs(oracle.grad_param_shift(c, c.params, terms) - ref)) > 1e-3
+    monkeypatch.undo()
+    # drop the adjoint sign: shift ~R as if it were R(+theta) controlled
+    gates = [W.Gate(g.kind.lstrip("~"), g.target, g.controls, g.values, g.theta, g.param)
+             if g.kind.startswith("~") and g.controls and g.kind != "~P" else g for g in c.gates]
+    wrong = oracle.grad_param_shift(W.Circuit(c.n, gates, c.params), c.params, terms)
+    assert np.max(np.abs(wrong - ref)) > 1e-3
+
+
+def _pauli_pin_failures(gm):
+    """Checks that fix Y and Z from X and H (pinned by the paper's closed
+    forms) and the Pauli algebra; returns the names of the failing ones."""
+    X, Y, Z, H = gm("X"), gm("Y"), gm("Z"), gm("H")
+    I = np.eye(2)
+    bad = []
+    checks = {
+        "Z = H X H": np.allclose(Z, H @ X @ H, atol=1e-15),
+        "Y = i X Z": np.allclose(Y, 1j * X @ Z, atol=1e-15),
+        "XY = iZ": np.allclose(X @ Y, 1j * Z, atol=1e-15),
+        "YZ = iX": np.allclose(Y @ Z, 1j * X, atol=1e-15),
+        "ZX = iY": np.allclose(Z @ X, 1j * Y, atol=1e-15),
+        "squares": all(np.allclose(P @ P, I, atol=1e-15) for P in (X, Y, Z)),
+        "Z|0> = |0>": np.allclose(Z @ [1, 0], [1, 0], atol=1e-15),
+        "Y|0> = i|1>": np.allclose(Y @ [1, 0], [0, 1j], atol=1e-15),
+    }
+    for th in (0.3, 2.1):
+        checks["RX = exp(-i th X/2) %g" % th] = np.allclose(gm("RX", th), expm(-0.5j * th * X), atol=1e-14)
+        checks["RY = exp(-i th Y/2) %g" % th] = np.allclose(gm("RY", th), expm(-0.5j * th * Y), atol=1e-14)
+        checks["RZ = exp(-i th Z/2) %g" % th] = np.allclose(gm("RZ", th), expm(-0.5j * th * Z), atol=1e-14)
+        checks["P = e^{i th/2} RZ %g" % th] = np.allclose(gm("P", th), np.exp(0.5j * th) * gm("RZ", th), atol=1e-14)
+    checks["RY(pi/2)|0> = H|0>"] = np.allclose(gm("RY", math.pi / 2) @ [1, 0], H @ [1, 0], atol=1e-15)
+    return [k for k, ok in checks.items() if not ok]
+
+
+def test_pauli_and_rotation_matrices_pinned():
+    """Y and Z (named but not printed in the paper) from the paper's X and H
+    via Z = HXH and Y = iXZ, the Pauli algebra, and the rotations as matrix
+    exponentials of them (scipy expm).  Planted sign mistakes fail."""
+    assert _pauli_pin_failures(oracle.gate_matrix) == []
+
+    def mutate(which, f):
+        def gm(kind, theta=0.0, matrix=None):
+            U = oracle.gate_matrix(kind, theta, matrix)
+            return f(U) if kind == which else U
+        return gm
+    for which, f in (("Y", lambda U: -U), ("Z", lambda U: -U), ("Y", lambda U: U.T),
+                     ("RY", lambda U: U.T), ("RZ", lambda U: U.conj()), ("RX", lambda U: U.conj()),
+                     ("P", lambda U: U.conj())):
+        assert _pauli_pin_failures(mutate(which, f)), which
 
 
 def test_param_shift_shared_parameter():
