@@ -338,6 +338,21 @@ typedef struct sv_pauli {
  * nterms >= 1; masks must lie within the n qubits. */
 int sv_expect(const sv_state_t *s, const sv_pauli_t *terms, int nterms, double *out_dev, sv_stream_t st);
 
+/* Allocation-free variant of sv_expect, for callers that cannot allocate
+ * device memory: code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc.  It writes the same out_dev[0] as sv_expect, bit for
+ * bit (same kernels, same summation order), and neither allocates nor copies
+ * from host memory (the term table travels as a kernel argument).  Its
+ * workspace (term table and partial sums, about 1 MiB) is one device array
+ * inside the library, one copy per device, held until the process ends; every
+ * partial a call reads is first written by that call.  At most
+ * SV_EXPECT_NOALLOC_MAX_TERMS terms (SV_EINVAL beyond).  All calls on one
+ * device share the workspace, so calls that could overlap on one device
+ * (other streams, other threads) race: the caller orders them.  The state
+ * must be on the current device. */
+#define SV_EXPECT_NOALLOC_MAX_TERMS 64
+int sv_expect_noalloc(const sv_state_t *s, const sv_pauli_t *terms, int nterms, double *out_dev, sv_stream_t st);
+
 /* out_dev[j] = <psi|P_j|psi> for every term j (coefficients not applied). */
 int sv_expect_terms(const sv_state_t *s, const sv_pauli_t *terms, int nterms, double *out_dev, sv_stream_t st);
 

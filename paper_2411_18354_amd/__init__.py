@@ -502,6 +502,6 @@ def sv_apply_dense_low(state, k: int, M, stream=None) -> None:
     _check(_L.sv_apply_dense_low(ctypes.byref(s), int(k), buf.ctypes.data_as(_dp), stream_ptr(stream)))
 
 
-from .observables import (sv_pauli_t, pauli_terms, sv_expect, sv_expect_terms, sv_apply_pauli_sum,  # noqa: E402
-                          sv_adjoint_grad, SvExpectation, ExpectationModel)
+from .observables import (sv_pauli_t, pauli_terms, sv_expect, sv_expect_noalloc, sv_expect_terms,  # noqa: E402
+                          sv_apply_pauli_sum, sv_adjoint_grad, SvExpectation, ExpectationModel)
 from .batched import sv_apply_circuits_batched, sv_adjoint_grad_batched, Batch  # noqa: E402

@@ -10,7 +10,9 @@
 // group are evaluated together in one pass.  Reductions are deterministic
 // (reduce.hpp).
 #include <algorithm>
+#include <cstddef>
 #include <cstring>
+#include <mutex>
 #include <numeric>
 
 #include "pauli.hpp"
@@ -92,7 +94,7 @@ template <typename R>
 __global__ __launch_bounds__(kRedThreads) void k_expect_group(const cplx_t<R> *__restrict__ psi, uint64_t count,
                                                               uint64_t X, uint32_t b, const DTerm *__restrict__ terms,
                                                               int first, int nt, double *__restrict__ partials) {
-    __shared__ double scratch[kRedThreads / 64];
+    __shared__ double red[kRedThreads / 64];
     uint64_t z[kMaxT];
     int ny[kMaxT];
     double acc[kMaxT];
@@ -131,7 +133,7 @@ __global__ __launch_bounds__(kRedThreads) void k_expect_group(const cplx_t<R> *_
 #pragma unroll
     for (int j = 0; j < kMaxT; ++j) {
         if (j < nt) {  // uniform
-            const double s = block_sum(acc[j], scratch);
+            const double s = block_sum(acc[j], red);
             if (threadIdx.x == 0)
                 partials[(size_t)(first + j) * kMaxPartials + blockIdx.x] = scale * s;
         }
@@ -145,10 +147,10 @@ __global__ __launch_bounds__(kRedThreads) void k_expect_final(const DTerm *__res
                                                               const double *__restrict__ partials,
                                                               double *__restrict__ out_total,
                                                               double *__restrict__ out_terms) {
-    __shared__ double scratch[kRedThreads / 64];
+    __shared__ double red[kRedThreads / 64];
     double total = 0.0;
     for (int j = 0; j < nterms; ++j) {
-        const double s = block_sum_array(partials + (size_t)j * kMaxPartials, nblk[j], scratch);
+        const double s = block_sum_array(partials + (size_t)j * kMaxPartials, nblk[j], red);
         total += terms[j].coef * s;
         if (threadIdx.x == 0 && out_terms)
             out_terms[terms[j].idx] = s;
@@ -165,7 +167,7 @@ __global__ __launch_bounds__(kRedThreads) void k_apply_paulis(const cplx_t<R> *_
                                                               const DGroup *__restrict__ groups, int ngroups,
                                                               const DTerm *__restrict__ terms,
                                                               double *__restrict__ partials) {
-    __shared__ double scratch[kRedThreads / 64];
+    __shared__ double red[kRedThreads / 64];
     double lp = 0.0;
     const uint64_t stride = (uint64_t)gridDim.x * kRedThreads;
     for (uint64_t k = (uint64_t)blockIdx.x * kRedThreads + threadIdx.x; k < N; k += stride) {
@@ -191,7 +193,7 @@ __global__ __launch_bounds__(kRedThreads) void k_apply_paulis(const cplx_t<R> *_
         const cplx_t<R> p = psi[k];
         lp += (double)p.x * ar + (double)p.y * ai;
     }
-    const double s = block_sum(lp, scratch);
+    const double s = block_sum(lp, red);
     if (threadIdx.x == 0 && partials)
         partials[blockIdx.x] = s;
 }
@@ -213,58 +215,155 @@ int launch_apply_paulis(int dtype, const void *psi, void *out, int n, const Paul
 }
 
 
+// Partial count of every term (the grid of its group's pass), in the plan's
+// term order.
+static void expect_partial_counts(int n, const PauliPlan &plan, std::vector<int32_t> &nblk) {
+    nblk.assign(plan.terms.size(), 0);
+    for (const DGroup &g : plan.groups) {
+        const uint64_t count = g.x == 0 ? (1ull << n) : (1ull << (n - 1));
+        for (int j = g.first; j < g.first + g.count; ++j)
+            nblk[j] = (int32_t)reduce_grid(count);
+    }
+}
+
+// The group passes and the final sum.  terms (the plan's terms), nblk (their
+// partial counts) and partials (terms * kMaxPartials doubles) are device
+// arrays, already filled or enqueued on st.
+static int expect_launch(const sv_state_t *s, const PauliPlan &plan, const DTerm *terms, const int32_t *nblk,
+                         double *partials, double *out_total, double *out_terms, hipStream_t st) {
+    const int n = s->n;
+    for (const DGroup &g : plan.groups) {
+        const uint64_t count = g.x == 0 ? (1ull << n) : (1ull << (n - 1));
+        const unsigned grid = reduce_grid(count);
+        const uint32_t b = g.x ? (uint32_t)__builtin_ctzll(g.x) : 0;
+        if (s->dtype == SV_C128)
+            hipLaunchKernelGGL(k_expect_group<double>, dim3(grid), dim3(kRedThreads), 0, st,
+                               (const double2 *)s->data, count, g.x, b, terms, g.first, g.count, partials);
+        else
+            hipLaunchKernelGGL(k_expect_group<float>, dim3(grid), dim3(kRedThreads), 0, st, (const float2 *)s->data,
+                               count, g.x, b, terms, g.first, g.count, partials);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess)
+            return fail(SV_EHIP, "expectation launch failed: %s", hipGetErrorString(e));
+    }
+    hipLaunchKernelGGL(k_expect_final, dim3(1), dim3(kRedThreads), 0, st, terms, (int)plan.terms.size(), nblk,
+                       partials, out_total, out_terms);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return fail(SV_EHIP, "expectation launch failed: %s", hipGetErrorString(e));
+    return SV_OK;
+}
+
 static int expect_impl(const sv_state_t *s, const sv_pauli_t *terms, int nterms, double *out_total,
                        double *out_terms, hipStream_t st) {
     SV_TRY(validate_state(s));
     PauliPlan plan;
     SV_TRY(make_pauli_plan(s->n, terms, nterms, &plan));
+    std::vector<int32_t> nblk;
+    expect_partial_counts(s->n, plan, nblk);
     PauliDevice d;
     SV_TRY(pauli_upload(plan, (size_t)plan.terms.size() * kMaxPartials, st, &d));
-    // per-term partial counts
-    std::vector<int32_t> nblk(plan.terms.size());
     int32_t *d_nblk = nullptr;
     int r = SV_OK;
-    const int n = s->n;
-    for (const DGroup &g : plan.groups) {
-        const uint64_t count = g.x == 0 ? (1ull << n) : (1ull << (n - 1));
-        const unsigned grid = reduce_grid(count);
-        for (int j = g.first; j < g.first + g.count; ++j)
-            nblk[j] = (int32_t)grid;
-        const uint32_t b = g.x ? (uint32_t)__builtin_ctzll(g.x) : 0;
-        if (s->dtype == SV_C128)
-            hipLaunchKernelGGL(k_expect_group<double>, dim3(grid), dim3(kRedThreads), 0, st,
-                               (const double2 *)s->data, count, g.x, b, d.terms, g.first, g.count, d.partials);
-        else
-            hipLaunchKernelGGL(k_expect_group<float>, dim3(grid), dim3(kRedThreads), 0, st, (const float2 *)s->data,
-                               count, g.x, b, d.terms, g.first, g.count, d.partials);
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) {
-            r = fail(SV_EHIP, "expectation launch failed: %s", hipGetErrorString(e));
-            break;
-        }
-    }
-    if (r == SV_OK) {
-        hipError_t e = hipMallocAsync((void **)&d_nblk, nblk.size() * sizeof(int32_t), st);
-        if (e != hipSuccess) {
-            (void)hipGetLastError();
-            r = fail(SV_ENOMEM, "device allocation failed: %s", hipGetErrorString(e));
-        } else {
-            e = hipMemcpyAsync(d_nblk, nblk.data(), nblk.size() * sizeof(int32_t), hipMemcpyHostToDevice, st);
-            if (e != hipSuccess)
-                r = fail(SV_EHIP, "copy failed: %s", hipGetErrorString(e));
-        }
-    }
-    if (r == SV_OK) {
-        hipLaunchKernelGGL(k_expect_final, dim3(1), dim3(kRedThreads), 0, st, d.terms, d.nterms, d_nblk, d.partials,
-                           out_total, out_terms);
-        hipError_t e = hipGetLastError();
+    hipError_t e = hipMallocAsync((void **)&d_nblk, nblk.size() * sizeof(int32_t), st);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        d_nblk = nullptr;
+        r = fail(SV_ENOMEM, "device allocation failed: %s", hipGetErrorString(e));
+    } else {
+        e = hipMemcpyAsync(d_nblk, nblk.data(), nblk.size() * sizeof(int32_t), hipMemcpyHostToDevice, st);
         if (e != hipSuccess)
-            r = fail(SV_EHIP, "expectation launch failed: %s", hipGetErrorString(e));
+            r = fail(SV_EHIP, "copy failed: %s", hipGetErrorString(e));
     }
+    if (r == SV_OK)
+        r = expect_launch(s, plan, d.terms, d_nblk, d.partials, out_total, out_terms, st);
     if (d_nblk)
         (void)hipFreeAsync(d_nblk, st);
     pauli_release(&d, st);
     return r;
+}
+
+// ---------------------------------------------------------------------------
+// Allocation-free expectation.  The term table, the partial counts and the
+// partial sums live in one file-scope device array.  Host code never passes
+// the array's name to a kernel: its device address is looked up once per
+// device with hipGetSymbolAddress and kept.  The tables travel to the device
+// as a kernel argument (no host-to-device copy), and every partial a call
+// reads is written by that call first, so nothing needs clearing.  Every
+// call on one device shares the array: calls that overlap on one device
+// race.
+// ---------------------------------------------------------------------------
+constexpr int kNoAllocTerms = SV_EXPECT_NOALLOC_MAX_TERMS;
+
+struct ExpectScratch {
+    DTerm terms[kNoAllocTerms];
+    int32_t nblk[kNoAllocTerms];
+    double partials[(size_t)kNoAllocTerms * kMaxPartials];
+};
+
+struct ExpectTables {
+    int32_t nterms, pad;
+    DTerm terms[kNoAllocTerms];
+    int32_t nblk[kNoAllocTerms];
+};
+
+static __device__ __align__(256) unsigned char scratch[sizeof(ExpectScratch)];
+
+__global__ __launch_bounds__(64) void k_expect_tables(ExpectTables t, ExpectScratch *w) {
+    for (int i = threadIdx.x; i < t.nterms; i += blockDim.x) {
+        w->terms[i] = t.terms[i];
+        w->nblk[i] = t.nblk[i];
+    }
+}
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[kMaxDevices];
+
+// Device address of the scratch array on the current device (looked up on
+// the first call per device).
+static int scratch_address(ExpectScratch **out) {
+    int dev = 0;
+    SV_HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices)
+        return fail(SV_ENOTSUP, "device %d beyond the %d devices the scratch table holds", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(SV_EHIP, "hipGetSymbolAddress(scratch) failed on device %d: %s", dev, hipGetErrorString(e));
+        g_scratch_ptr[dev] = p;
+    }
+    *out = static_cast<ExpectScratch *>(g_scratch_ptr[dev]);
+    return SV_OK;
+}
+
+static int expect_noalloc_impl(const sv_state_t *s, const sv_pauli_t *terms, int nterms, double *out_total,
+                               hipStream_t st) {
+    SV_TRY(validate_state(s));
+    if (nterms > kNoAllocTerms)
+        return fail(SV_EINVAL, "nterms %d exceeds the allocation-free limit of %d terms", nterms, kNoAllocTerms);
+    PauliPlan plan;
+    SV_TRY(make_pauli_plan(s->n, terms, nterms, &plan));
+    std::vector<int32_t> nblk;
+    expect_partial_counts(s->n, plan, nblk);
+    ExpectTables t;
+    memset(&t, 0, sizeof(t));
+    t.nterms = (int32_t)plan.terms.size();
+    for (size_t j = 0; j < plan.terms.size(); ++j) {
+        t.terms[j] = plan.terms[j];
+        t.nblk[j] = nblk[j];
+    }
+    ExpectScratch *w = nullptr;
+    SV_TRY(scratch_address(&w));
+    hipLaunchKernelGGL(k_expect_tables, dim3(1), dim3(64), 0, st, t, w);
+    SV_LAUNCH_CHECK();
+    // member addresses inside the device array (w is never dereferenced on the host)
+    char *base = reinterpret_cast<char *>(w);
+    return expect_launch(s, plan, reinterpret_cast<const DTerm *>(base + offsetof(ExpectScratch, terms)),
+                         reinterpret_cast<const int32_t *>(base + offsetof(ExpectScratch, nblk)),
+                         reinterpret_cast<double *>(base + offsetof(ExpectScratch, partials)), out_total, nullptr, st);
 }
 
 } // namespace sv
@@ -278,6 +377,13 @@ int sv_expect(const sv_state_t *s, const sv_pauli_t *terms, int nterms, double *
     if (!out_dev)
         return fail(SV_EINVAL, "out_dev is NULL");
     return expect_impl(s, terms, nterms, out_dev, nullptr, (hipStream_t)st);
+}
+
+int sv_expect_noalloc(const sv_state_t *s, const sv_pauli_t *terms, int nterms, double *out_dev, sv_stream_t st) {
+    clear_error();
+    if (!out_dev)
+        return fail(SV_EINVAL, "out_dev is NULL");
+    return expect_noalloc_impl(s, terms, nterms, out_dev, (hipStream_t)st);
 }
 
 int sv_expect_terms(const sv_state_t *s, const sv_pauli_t *terms, int nterms, double *out_dev, sv_stream_t st) {

@@ -1,5 +1,5 @@
 """Binding of the observable and gradient entry points (sv_expect,
-sv_expect_terms, sv_apply_pauli_sum, sv_adjoint_grad) and the
+sv_expect_noalloc, sv_expect_terms, sv_apply_pauli_sum, sv_adjoint_grad) and the
 torch.autograd.Function built on them.  Argument marshalling only."""
 from __future__ import annotations
 
@@ -16,6 +16,7 @@ class sv_pauli_t(ctypes.Structure):
 
 _sig("sv_expect", [_sp, ctypes.POINTER(sv_pauli_t), ctypes.c_int, _vp, _vp])
 _sig("sv_expect_terms", [_sp, ctypes.POINTER(sv_pauli_t), ctypes.c_int, _vp, _vp])
+_sig("sv_expect_noalloc", [_sp, ctypes.POINTER(sv_pauli_t), ctypes.c_int, _vp, _vp])
 _sig("sv_apply_pauli_sum", [_sp, _sp, ctypes.POINTER(sv_pauli_t), ctypes.c_int, _vp])
 _sig("sv_adjoint_grad", [_sp, _sp, ctypes.POINTER(sv_gate_t), ctypes.c_int, _vp, ctypes.c_int,
                          ctypes.POINTER(sv_pauli_t), ctypes.c_int, _vp, _vp, _vp, _vp])
@@ -50,6 +51,15 @@ def sv_expect(state, terms, out=None, stream=None):
     if out is None:
         out = torch.empty(1, dtype=torch.float64, device=state.device)
     _check(_L.sv_expect(ctypes.byref(s), arr, _count(arr), _ptr(out), stream_ptr(stream)))
+    return out
+
+
+def sv_expect_noalloc(state, terms, out, stream=None):
+    """<psi|H|psi> into the caller's device float64 tensor out (shape >= 1),
+    through the entry point that allocates nothing (at most 64 terms)."""
+    s = state_view(state)
+    arr = pauli_terms(terms)
+    _check(_L.sv_expect_noalloc(ctypes.byref(s), arr, _count(arr), _ptr(out), stream_ptr(stream)))
     return out
 
 

@@ -203,3 +203,12 @@ def test_convert_argument_errors(sv):
     assert code == sv.SV_EINVAL and "qubits" in msg
     code, msg = _rc(lambda: sv.sv_convert(a, _state(sv, 10, sv.SV_C128, 0x100000 + 4096)))
     assert code == sv.SV_EINVAL and "overlap" in msg
+
+
+def test_expect_noalloc_rejects_too_many_terms(sv):
+    """The allocation-free expectation holds at most 64 terms in its
+    workspace; more is an argument error raised before any device use."""
+    s = _state(sv, 8)
+    arr = sv.pauli_terms([(1.0, 0, 1 << (i % 8)) for i in range(65)])
+    rc = sv.lib().sv_expect_noalloc(ctypes.byref(s), arr, 65, ctypes.c_void_p(0x20000), None)
+    assert rc == sv.SV_EINVAL and "allocation-free limit of 64" in sv.sv_last_error()
