@@ -17,6 +17,7 @@ per-(t, c) rows and the extra measurements go to a JSON file (--detail-out)
 and to stderr.
 """
 import argparse
+import gc
 import hashlib
 import json
 import os
@@ -909,38 +910,46 @@ def main():
             plans[(mode, t, ctrls)] = sv.sv_gate_plan(n, sv.SV_C128, t, cm, cm, mode)
 
     def sweep(mode, steps, warmup):
+        """Warm-up steps, then `steps` timed steps of the sweep: HIP events
+        around the whole region, around every step and around every gate
+        (all created before the region; Python's collector paused inside)."""
         per = {(t, ctrls): [] for t, ctrls in cases}
+        ng = len(cases)
+        gev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps * ng)]
+        sev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
         with torch.cuda.stream(stream):
             for _ in range(warmup):
                 for t, ctrls in cases:
                     sv.sv_apply_gate(d, t, ctrls, None, U, mode=mode, stream=stream)
             torch.cuda.synchronize()
-            evs = []
-            t_start = torch.cuda.Event(enable_timing=True)
-            t_end = torch.cuda.Event(enable_timing=True)
-            t_start.record(stream)
-            for _ in range(steps):
-                for t, ctrls in cases:
-                    e0 = torch.cuda.Event(enable_timing=True)
-                    e1 = torch.cuda.Event(enable_timing=True)
-                    e0.record(stream)
-                    sv.sv_apply_gate(d, t, ctrls, None, U, mode=mode, stream=stream)
-                    e1.record(stream)
-                    evs.append(((t, ctrls), e0, e1))
-            t_end.record(stream)
+            gc.disable()
+            try:
+                sev[0].record(stream)
+                for k in range(steps):
+                    for j, (t, ctrls) in enumerate(cases):
+                        e0, e1 = gev[k * ng + j]
+                        e0.record(stream)
+                        sv.sv_apply_gate(d, t, ctrls, None, U, mode=mode, stream=stream)
+                        e1.record(stream)
+                    sev[k + 1].record(stream)
+            finally:
+                gc.enable()
         torch.cuda.synchronize()
-        total_ms = t_start.elapsed_time(t_end)
-        for key, e0, e1 in evs:
-            per[key].append(e0.elapsed_time(e1))
-        return total_ms, per
+        total_ms = sev[0].elapsed_time(sev[-1])
+        step_ms = [sev[k].elapsed_time(sev[k + 1]) for k in range(steps)]
+        for k in range(steps):
+            for j, key in enumerate(cases):
+                e0, e1 = gev[k * ng + j]
+                per[key].append(e0.elapsed_time(e1))
+        return total_ms, per, step_ms
 
     torch.cuda.synchronize()
     log("scheduled sweep: %d warmup + %d timed steps of %d gates" % (args.warmup, args.steps, len(cases)))
-    total_ms, per = sweep("auto", args.steps, args.warmup)
+    total_ms, per, step_ms = sweep("auto", args.steps, args.warmup)
     masked_total, per_m = (None, None)
     if not args.no_masked:
         log("masked sweep")
-        masked_total, per_m = sweep("masked", args.steps, args.warmup)
+        masked_total, per_m, _ = sweep("masked", args.steps, args.warmup)
 
     ngates = args.steps * len(cases)
     value = ngates / (total_ms / 1e3)
@@ -1035,6 +1044,7 @@ def main():
         summary_by_c["n32_graph_frac"] = ps.get("sched_frac")
         summary_by_c["n32_graph_masked_over_sched"] = ps.get("masked_over_sched")
     detail = {
+        "step_ms": [round(x, 4) for x in step_ms],
         "sweep": rows,
         "graph_protocol_n28": protocol,
         "graph_protocol_n32": protocol32,
@@ -1050,6 +1060,7 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": round(total_ms / args.steps, 4),
+        "step_ms_median_max": [round(float(np.median(step_ms)), 3), round(max(step_ms), 3)],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
