@@ -4,17 +4,25 @@
 // (composed on the device, so angles may come from device memory).  Viewing
 // the state as rows of 2^k consecutive amplitudes, the run is row <- M row
 // for every row: a dense contraction.  With interleaved (re, im) storage a
-// row is 2^(k+1) reals and M acts through its real embedding
+// row is D = 2^(k+1) reals and M acts through its real embedding
 //     Re: R[2a][2b] = Re M[a][b],  R[2a][2b+1] = -Im M[a][b]
 //     Im: R[2a+1][2b] = Im M[a][b], R[2a+1][2b+1] = Re M[a][b],
-// so OUT = X R^T with X the (rows x 2^(k+1)) real matrix: a GEMM on
+// so OUT = X R^T with X the (rows x D) real matrix: a GEMM on
 // v_mfma_f64_16x16x4f64 (complex128) or v_mfma_f32_16x16x4f32 (complex64).
-// Each wavefront takes 16 rows at a time through LDS (coalesced 16-byte
-// loads and stores); R^T is staged in LDS once per workgroup.
 //
-// Roofline: 2^(k+3) flop per amplitude against 2 S bytes moved, i.e. 4 flop/B
-// at k=4 in complex128 (HBM-bound on MI355X, whose FP64 ridge is ~10 flop/B)
-// and 8 flop/B at k=5 in complex64 (also below the FP32 ridge).
+// Each wavefront takes 16 rows at a time.  R^T, the B operand, stays in
+// registers for the whole launch.  The 16 rows move between HBM and the
+// wavefront's LDS slice with 16-byte nontemporal accesses (consecutive lanes
+// on consecutive 16 bytes); the next 16 rows are already being loaded while
+// the current ones are multiplied.  The contraction index is permuted so
+// that lane (row r, quarter q) supplies X[r][q D/4 + s] at MFMA step s: each
+// lane then reads D/4 consecutive reals of its row from LDS with 16-byte
+// reads, and the B registers use the same permutation.
+//
+// Roofline: 2^(k+3) flop per amplitude against 2 S bytes moved, i.e.
+// 4 flop/B at k=4 in complex128 (FP64 ridge about 78.6 TFLOP/s / 8 TB/s =
+// 10 flop/B) and 16 flop/B at k=5 in complex64 (FP32 MFMA ridge about
+// 157 TFLOP/s / 8 TB/s = 20 flop/B): both HBM-bound on MI355X.
 #include <algorithm>
 #include <cstring>
 
@@ -25,6 +33,7 @@ namespace sv {
 
 typedef double d4v __attribute__((ext_vector_type(4)));
 typedef float f4v __attribute__((ext_vector_type(4)));
+typedef double d2v __attribute__((ext_vector_type(2)));
 
 __device__ __forceinline__ d4v mfma16x16x4(double a, double b, d4v c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
@@ -36,6 +45,10 @@ __device__ __forceinline__ f4v mfma16x16x4(float a, float b, f4v c) {
 template <typename R> struct Acc;
 template <> struct Acc<double> { using type = d4v; };
 template <> struct Acc<float> { using type = f4v; };
+// 16 bytes of reals
+template <typename R> struct Vec16;
+template <> struct Vec16<double> { using type = d2v; };
+template <> struct Vec16<float> { using type = f4v; };
 
 // Result element (lane l, register r) of a 16x16 MFMA tile, as measured on
 // gfx950: f64 -> row 4r + l/16; f32 -> row 4(l/16) + r; column l % 16.
@@ -43,52 +56,99 @@ template <typename R> __device__ __forceinline__ int acc_row(int l, int r);
 template <> __device__ __forceinline__ int acc_row<double>(int l, int r) { return 4 * r + (l >> 4); }
 template <> __device__ __forceinline__ int acc_row<float>(int l, int r) { return 4 * (l >> 4) + r; }
 
+// LDS accesses of one wavefront to its own slice: the wavefront's lanes run
+// in lockstep and its LDS operations complete in order, so ordering needs only
+// the compiler not to move memory operations across this point.
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 constexpr int kDenseThreads = 256;
 
-// x: the state as reals; ngroups: groups of 64 rows (4 wavefronts x 16 rows);
+// x: the state as reals; nwg: groups of 16 rows (one per wavefront pass);
 // rmat: the D x D real embedding, row-major.
 template <typename R, int KQ>
-__global__ __launch_bounds__(kDenseThreads) void k_dense(R *__restrict__ x, uint64_t ngroups,
+__global__ __launch_bounds__(kDenseThreads) void k_dense(R *__restrict__ x, uint64_t nwg,
                                                          const R *__restrict__ rmat) {
-    constexpr int D = 2 << KQ;  // reals per row
-    constexpr int NS = D / 4;   // k-steps of the MFMA
-    constexpr int NT = D / 16;  // 16-wide output tiles
-    constexpr int P = D + 1;    // padded LDS row (bank spread)
-    __shared__ R rs[D * P];
-    __shared__ R xs[4 * 16 * P];
-    for (int e = threadIdx.x; e < D * D; e += kDenseThreads)
-        rs[(e / D) * P + (e % D)] = rmat[e];
+    using V = typename Vec16<R>::type;
+    constexpr int D = 2 << KQ;               // reals per row
+    constexpr int NS = D / 4;                // MFMA k-steps
+    constexpr int NT = D / 16;               // 16-wide output tiles
+    constexpr int VR = 16 / sizeof(R);       // reals per 16-byte vector
+    constexpr int P = D + VR;                // padded LDS row, 16-byte aligned
+    constexpr int NV = 16 * D / VR / 64;     // 16-byte vectors per lane per group
+    constexpr int NA = NS / VR;              // 16-byte A reads per lane per group
+    static_assert(NS % VR == 0 && NV >= 1, "tile shape");
+    __shared__ __align__(16) R xs[(kDenseThreads / 64) * 16 * P];
     const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    const int r16 = l & 15, q = l >> 4;
     R *xw = xs + w * 16 * P;
-    __syncthreads();
-    for (uint64_t g = blockIdx.x; g < ngroups; g += gridDim.x) {  // uniform per workgroup
-        R *src = x + (g * 64 + (uint64_t)w * 16) * D;
-        for (int e = l; e < 16 * D; e += 64)
-            xw[(e / D) * P + (e % D)] = __builtin_nontemporal_load(src + e);
-        __syncthreads();
+    // B operand at step s, tile jt: R^T[kk][j] = R[j][kk], kk = q NS + s, j = 16 jt + r16
+    R b[NT][NS];
+#pragma unroll
+    for (int jt = 0; jt < NT; ++jt)
+#pragma unroll
+        for (int s = 0; s < NS; ++s)
+            b[jt][s] = rmat[(jt * 16 + r16) * D + q * NS + s];
+    const uint64_t stride = (uint64_t)gridDim.x * (kDenseThreads / 64);
+    uint64_t g = (uint64_t)blockIdx.x * (kDenseThreads / 64) + w;
+    V t[NV];
+    if (g < nwg) {
+        const V *src = reinterpret_cast<const V *>(x + g * 16 * D);
+#pragma unroll
+        for (int v = 0; v < NV; ++v)
+            t[v] = __builtin_nontemporal_load(src + l + 64 * v);
+    }
+    while (g < nwg) {  // uniform per wavefront
+        // vector e = l + 64 v holds reals [VR e, VR e + VR): row VR e / D, column VR e % D
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            const int e = l + 64 * v;
+            *reinterpret_cast<V *>(xw + (e * VR / D) * P + (e * VR) % D) = t[v];
+        }
+        const uint64_t gn = g + stride;
+        if (gn < nwg) {  // the next group's loads are in flight during the products
+            const V *src = reinterpret_cast<const V *>(x + gn * 16 * D);
+#pragma unroll
+            for (int v = 0; v < NV; ++v)
+                t[v] = __builtin_nontemporal_load(src + l + 64 * v);
+        }
+        wave_lds_sync();
+        R a[NS];
+#pragma unroll
+        for (int i = 0; i < NA; ++i) {
+            const V u = *reinterpret_cast<const V *>(xw + r16 * P + q * NS + i * VR);
+#pragma unroll
+            for (int c = 0; c < VR; ++c)
+                a[i * VR + c] = u[c];
+        }
         typename Acc<R>::type acc[NT];
 #pragma unroll
         for (int jt = 0; jt < NT; ++jt)
             acc[jt] = typename Acc<R>::type{0, 0, 0, 0};
 #pragma unroll
-        for (int s = 0; s < NS; ++s) {
-            const R a = xw[(l & 15) * P + 4 * s + (l >> 4)];  // X[row][kk]
+        for (int s = 0; s < NS; ++s)
 #pragma unroll
-            for (int jt = 0; jt < NT; ++jt) {
-                const R b = rs[(jt * 16 + (l & 15)) * P + 4 * s + (l >> 4)];  // R^T[kk][j] = R[j][kk]
-                acc[jt] = mfma16x16x4(a, b, acc[jt]);
-            }
-        }
-        __syncthreads();
+            for (int jt = 0; jt < NT; ++jt)
+                acc[jt] = mfma16x16x4(a[s], b[jt][s], acc[jt]);
+        wave_lds_sync();
 #pragma unroll
         for (int jt = 0; jt < NT; ++jt)
 #pragma unroll
             for (int r = 0; r < 4; ++r)
-                xw[acc_row<R>(l, r) * P + jt * 16 + (l & 15)] = acc[jt][r];
-        __syncthreads();
-        for (int e = l; e < 16 * D; e += 64)
-            __builtin_nontemporal_store(xw[(e / D) * P + (e % D)], src + e);
-        __syncthreads();
+                xw[acc_row<R>(l, r) * P + jt * 16 + r16] = acc[jt][r];
+        wave_lds_sync();
+        V *dst = reinterpret_cast<V *>(x + g * 16 * D);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            const int e = l + 64 * v;
+            __builtin_nontemporal_store(*reinterpret_cast<const V *>(xw + (e * VR / D) * P + (e * VR) % D),
+                                        dst + l + 64 * v);
+        }
+        wave_lds_sync();
+        g = gn;
     }
 }
 
@@ -143,16 +203,19 @@ bool dense_supported(int dtype, int kq, int n) {
     return dtype == SV_C128 ? kq == 4 : (kq == 4 || kq == 5);
 }
 
-static unsigned dense_grid(uint64_t ngroups) {
+// Workgroups of the persistent dense launch: a few per CU, never more than
+// the 16-row groups need (4 per workgroup).
+static unsigned dense_grid(uint64_t nwg) {
     DeviceInfo di;
     const uint64_t cap = device_info(&di) == SV_OK ? (uint64_t)di.num_cus * 8 : 2048;
-    return (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(ngroups, cap));
+    const uint64_t need = (nwg + kDenseThreads / 64 - 1) / (kDenseThreads / 64);
+    return (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(need, cap));
 }
 
 int launch_dense(int dtype, void *psi, int n, int kq, const void *rmat, hipStream_t st) {
     if (!dense_supported(dtype, kq, n))
         return fail(SV_ENOTSUP, "dense block of %d qubits unsupported for dtype %d, n=%d", kq, dtype, n);
-    const uint64_t ngroups = 1ull << (n - kq - 6);
+    const uint64_t ngroups = 1ull << (n - kq - 4);  // groups of 16 rows of 2^kq amplitudes
     const unsigned grid = dense_grid(ngroups);
     if (dtype == SV_C128)
         hipLaunchKernelGGL((k_dense<double, 4>), dim3(grid), dim3(kDenseThreads), 0, st, (double *)psi, ngroups,
