@@ -1,6 +1,9 @@
 """GPU parity of expectation values and adjoint gradients against the
 oracle: <psi|H|psi> and H psi to 1e-12, gradients to 1e-8 against the
 oracle's parameter-shift rule, through the C ABI and through torch.autograd."""
+import json
+import os
+
 import numpy as np
 import pytest
 
@@ -159,14 +162,21 @@ def test_autograd_function(gpu):
     assert torch.equal(p.grad, p2.grad)
 
 
-def test_adjoint_hea_n24_sampled(gpu):
-    """The n=24 ansatz problem at full size (n=24, 16 layers, 768 parameters): adjoint
-    gradient against the oracle's parameter shift on a seeded sample of
-    parameters, and loss against the oracle."""
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def test_adjoint_hea_n24_full_size(gpu):
+    """The n=24 ansatz problem at full size (n=24, 16 layers, 768 parameters).
+    (a) Loss and 32 seeded gradients (first, two middle and last layers, RY
+    and RZ) against the oracle's parameter shift stored by
+    tests/golden/make_hea_n24_grads.py, at 1e-8.  (b) All 768 gradients
+    against a parameter shift evaluated on the GPU's forward path and
+    sv_expect (both held to the oracle at 1e-12 elsewhere; they share no code
+    with the reverse sweep), at 1e-8."""
     import torch
     c, terms = W.hea_problem_n24()
-    rng = np.random.default_rng(55)
-    sample = sorted(rng.choice(c.nparams, size=4, replace=False).tolist())
+    with open(os.path.join(GOLDEN, "hea_n24_param_shift.json")) as fh:
+        gold = json.load(fh)
     params = torch.from_numpy(c.params).cuda()
     psi = torch.empty(1 << c.n, dtype=torch.complex128, device="cuda")
     gpu.sv_init(psi, 0)
@@ -174,13 +184,35 @@ def test_adjoint_hea_n24_sampled(gpu):
     lam = torch.empty_like(psi)
     grad, loss = gpu.sv_adjoint_grad(psi, lam, c, params, terms)
     g = grad.cpu().numpy()
-    _say("hea n24 loss %.12f" % loss.item())
-    ref_loss = oracle.loss(c, c.params, terms)
-    assert abs(loss.item() - ref_loss) <= 1e-10
-    ref = oracle.grad_param_shift(c, c.params, terms, which=sample)
-    err = np.max(np.abs(g[sample] - ref)) / max(1.0, np.max(np.abs(ref)))
-    _say("hea n24 sampled grad err %.2e" % err)
+    _say("hea n24 loss %.15f (oracle %.15f)" % (loss.item(), gold["loss"]))
+    assert abs(loss.item() - gold["loss"]) <= 1e-10
+    idx = np.array(gold["params"])
+    ref = np.array(gold["grad"])
+    assert len(idx) == 32
+    err = np.max(np.abs(g[idx] - ref)) / max(1.0, np.max(np.abs(ref)))
+    _say("hea n24 golden grad err %.2e over %d parameters" % (err, len(idx)))
     assert err <= 1e-8
+    # (b) every parameter: shifted angle sets, one forward pass + <H> each
+    P = c.nparams
+    shifts = np.repeat(c.params[None, :], 2 * P, axis=0)
+    shifts[2 * np.arange(P), np.arange(P)] += np.pi / 2
+    shifts[2 * np.arange(P) + 1, np.arange(P)] -= np.pi / 2
+    sh = torch.from_numpy(shifts).cuda()
+    losses = torch.empty(2 * P, dtype=torch.float64, device="cuda")
+    plan = gpu.Circuit(c.n, c, nparams=P, flags=gpu.SV_FUSE)
+    try:
+        for r in range(2 * P):
+            gpu.sv_init(psi, 0)
+            plan.run(psi, sh[r])
+            gpu.sv_expect(psi, terms, out=losses[r:r + 1])
+        lv = losses.cpu().numpy()
+    finally:
+        plan.close()
+    shift = 0.5 * (lv[0::2] - lv[1::2])
+    err_all = np.max(np.abs(g - shift)) / max(1.0, np.max(np.abs(shift)))
+    _say("hea n24 adjoint vs GPU parameter shift, all %d: %.2e" % (P, err_all))
+    assert err_all <= 1e-8
+    assert np.max(np.abs(shift[idx] - ref)) <= 1e-10
 
 
 @pytest.mark.parametrize("tile,low", [(8, 3), (10, 5), (13, 6)])

@@ -2,6 +2,9 @@
 batches (LDS-resident and global-memory circuits), the 4096-circuit batch at full size on
 a seeded sample of circuits, batched adjoint gradients, and planned batches
 (sv_batch_*) run repeatedly."""
+import json
+import os
+
 import numpy as np
 import pytest
 
@@ -87,8 +90,8 @@ def test_batched_errors_name_circuit(gpu):
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
 def test_uneven_batch_full_sampled(gpu, dtype):
     """4096 circuits, n uniform in 10..20, 100-400 gates each
-    (12.5 GB of complex128 states); a seeded sample checked against the
-    oracle, every state's norm checked on the device."""
+    (12.5 GB of complex128 states); 24 seeded circuits and one of every width
+    checked against the oracle, every state's norm checked on the device."""
     import torch
     circs = W.uneven_batch()
     _say("uneven batch", dtype, "states", sum(1 << c.n for c in circs) * (16 if dtype == "c128" else 8) / 2 ** 30, "GiB")
@@ -97,8 +100,8 @@ def test_uneven_batch_full_sampled(gpu, dtype):
     gpu.sv_apply_circuits_batched(views, circs)
     torch.cuda.synchronize()
     rng = np.random.default_rng(17)
-    sample = sorted(rng.choice(len(circs), size=5, replace=False).tolist())
-    big = [i for i, c in enumerate(circs) if c.n == 20][:1]
+    sample = sorted(rng.choice(len(circs), size=24, replace=False).tolist())
+    big = [next(i for i, c in enumerate(circs) if c.n == nq) for nq in range(10, 21)]  # every width once
     tol = 1e-12 if dtype == "c128" else 1e-5
     for i in sample + big:
         ref = oracle.run_circuit(circs[i])
@@ -139,10 +142,12 @@ def test_batched_adjoint_small(gpu):
         assert abs(back[0] - 1) <= 1e-12 and np.max(np.abs(back[1:])) <= 1e-12
 
 
-def test_hea_batch_n16_full_sampled(gpu):
+def test_hea_batch_n16_full_size(gpu):
     """256 ansatz circuits at n=16, 4 layers (128 parameters each): batched
-    forward and batched adjoint; gradients of a seeded sample against the
-    oracle's parameter shift."""
+    forward and batched adjoint; 8 seeded circuits checked on all 128
+    gradients and the loss against the oracle's parameter shift stored by
+    tests/golden/make_hea_batch_n16_grads.py; every circuit's psi back at
+    |0...0> after the reverse sweep."""
     import torch
     pairs = W.hea_batch_n16()
     circs = [c for c, _ in pairs]
@@ -154,15 +159,23 @@ def test_hea_batch_n16_full_sampled(gpu):
     gpu.sv_apply_circuits_batched(views, circs, params)
     grad, loss = gpu.sv_adjoint_grad_batched(views, lviews, circs, params, hams)
     g = grad.cpu().numpy()
-    rng = np.random.default_rng(23)
-    for ci in rng.choice(len(circs), size=2, replace=False).tolist():
-        c, h = circs[ci], hams[ci]
-        which = sorted(rng.choice(c.nparams, size=3, replace=False).tolist())
-        ref = oracle.grad_param_shift(c, c.params, h, which=which)
-        got = g[ci * 128 + np.array(which)]
-        _say("hea batch circuit", ci, "err", np.max(np.abs(got - ref)))
-        assert np.max(np.abs(got - ref)) <= 1e-8 * max(1, np.max(np.abs(ref)))
-        assert abs(loss[ci].item() - oracle.loss(c, c.params, h)) <= 1e-10
+    L = loss.cpu().numpy()
+    with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                           "hea_batch_n16_param_shift.json")) as fh:
+        gold = json.load(fh)
+    assert len(gold["circuits"]) == 8
+    for rec in gold["circuits"]:
+        ci = rec["index"]
+        ref = np.array(rec["grad"])
+        got = g[ci * 128:(ci + 1) * 128]
+        e = np.max(np.abs(got - ref)) / max(1.0, np.max(np.abs(ref)))
+        _say("hea batch circuit", ci, "grad err", e)
+        assert e <= 1e-8
+        assert abs(L[ci] - rec["loss"]) <= 1e-10
+    back = buf.view(len(circs), 1 << 16)
+    e0 = torch.zeros_like(back)
+    e0[:, 0] = 1
+    assert float((back - e0).abs().max()) <= 1e-12
 
 
 def test_batch_object_reuse(gpu):
