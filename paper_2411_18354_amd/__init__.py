@@ -259,6 +259,19 @@ _sig("sv_gate_plan", [ctypes.c_int, ctypes.c_int, ctypes.c_int, _u64, _u64, ctyp
                       ctypes.c_int, ctypes.POINTER(_u64)])
 
 
+_sig("sv_hbm_probe", [_sp, _u64, _u64, ctypes.c_int, _vp])
+
+PROBE_OPS = {"rmw": 0, "read": 1, "write": 2}
+
+
+def sv_hbm_probe(state, fixed_mask: int = 0, fixed_vals: int = 0, op="rmw", stream=None) -> None:
+    """Measurement helper: stream over the amplitudes matching fixed_vals on
+    fixed_mask ("rmw" keeps the values, "read" reads only, "write" zeroes)."""
+    s = state_view(state)
+    o = PROBE_OPS[op] if isinstance(op, str) else int(op)
+    _check(_L.sv_hbm_probe(ctypes.byref(s), int(fixed_mask), int(fixed_vals), o, stream_ptr(stream)))
+
+
 def sv_gate_plan(n: int, dtype: int, target: int, ctrl_mask: int = 0, ctrl_vals: int = 0, mode="auto"):
     """(kernel name, work items) that sv_apply_gate would launch."""
     buf = ctypes.create_string_buffer(256)

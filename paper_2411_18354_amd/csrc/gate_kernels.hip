@@ -13,7 +13,12 @@
 
 namespace sv {
 
-constexpr int kThreads = 256;
+// One wavefront per workgroup for the scheduled pair and wavefront kernels:
+// measured on MI355X, 64-lane workgroups with one pair (or amplitude) per
+// lane stream an in-place 4 GiB gate at 6.4-6.8 TB/s, against 5.7-5.8 TB/s
+// for 256-lane workgroups with four per lane.  The masked baseline's
+// workgroup size is a knob ("masked_block": 64 or 256).
+constexpr int kThreads = 64;
 
 // What a pair or lane does when its lane-tested controls fail.
 constexpr int kSkip = 0;     // no load, no store (the baseline kernel figure)
@@ -31,22 +36,21 @@ constexpr int kRewrite = 1;  // load and store the unchanged values, so that
 //   Masked baseline (Sec. III-A, baseline kernel figure): i runs over all
 //     2^(n-1) pairs, the expansion inserts only the target bit, and the pair
 //     is skipped unless all its control bits (tmask) match.
-// Each lane handles K iterations spaced kThreads apart so a wavefront's loads
-// are contiguous and 2K loads per lane are in flight.
+// A workgroup has T lanes; each lane handles K iterations spaced T apart so
+// a wavefront's loads are contiguous and 2K loads per lane are in flight.
 // ---------------------------------------------------------------------------
-template <typename R, typename I, int K, int POLICY, typename MS>
-__global__ __launch_bounds__(kThreads) void k_pair(cplx_t<R> *__restrict__ psi, uint64_t niter, Expand e,
-                                                   uint64_t tmask, uint64_t tvals, uint32_t t, MS ms,
-                                                   uint64_t block0) {
+template <typename R, typename I, int K, int POLICY, int T, typename MS>
+__global__ __launch_bounds__(T) void k_pair(cplx_t<R> *__restrict__ psi, uint64_t niter, Expand e,
+                                            uint64_t tmask, uint64_t tvals, uint32_t t, MS ms, uint64_t block0) {
     const Mat2<R> m = ms.get();
-    const uint64_t base = (block0 + blockIdx.x) * (kThreads * K) + threadIdx.x;
+    const uint64_t base = (block0 + blockIdx.x) * (T * K) + threadIdx.x;
     const I st = (I)1 << t;
     cplx_t<R> x[K], y[K];
     I p1[K];
     bool in[K], pass[K];
 #pragma unroll
     for (int j = 0; j < K; ++j) {
-        const uint64_t i = base + (uint64_t)j * kThreads;
+        const uint64_t i = base + (uint64_t)j * T;
         p1[j] = expand_index<I>(e, (I)i);
         in[j] = i < niter;
         pass[j] = in[j] && (((uint64_t)p1[j] & tmask) == tvals);
@@ -232,6 +236,20 @@ void mark_diag_sweeps(TileGate *t, int count, const char *param_gate) {
     }
 }
 
+void mark_coset_pairs(TileGate *t, int count) {
+    for (int k = 0; k + 1 < count;) {
+        TileGate &a = t[k], &b = t[k + 1];
+        const bool ok = !a.diag && !b.diag && a.target != b.target &&
+                        (a.l_mask & ~(1u << b.target)) == 0 && (b.l_mask & ~(1u << a.target)) == 0;
+        if (ok) {
+            a.sweep_len = 2;
+            k += 2;
+        } else {
+            ++k;
+        }
+    }
+}
+
 // Tile-local bit of global qubit q, or -1 when q is outside S.
 static int local_bit(const TileMap &tm, int q) {
     if (q < (int)tm.a)
@@ -317,10 +335,10 @@ template <typename R> static int set_lds_limit(const void *fn, size_t bytes) {
     return SV_OK;
 }
 
-// Pairs (or wavefronts) per lane: 4 once the launch has enough work to fill
-// the chip several times over, 1 below that so small launches still spread
-// over every CU.
-constexpr uint64_t kBigLaunch = (uint64_t)kThreads * 4 * 2048;
+// Pairs (or wavefronts) per lane: the "pair_unroll" / "masked_unroll" knob
+// (1 or 4) once the launch has enough work to fill the chip several times
+// over, 1 below that so small launches still spread over every CU.
+constexpr uint64_t kBigLaunch = (uint64_t)256 * 4 * 2048;
 
 int make_gate_plan(const GateSpec &g, int dtype, int mode, GatePlan *p) {
     const Tuning &tn = tuning();
@@ -383,7 +401,9 @@ int make_gate_plan(const GateSpec &g, int dtype, int mode, GatePlan *p) {
         return fail(SV_EINVAL, "unknown mode %d", mode);
     }
     const uint64_t work = p->kind == GateKernel::Wave ? p->niter * 64 : p->niter;
-    p->unroll = work >= kBigLaunch ? 4 : 1;
+    const int knob = p->kind == GateKernel::Masked ? tn.masked_unroll : tn.pair_unroll;
+    p->unroll = (work >= kBigLaunch && knob >= 4) ? 4 : 1;
+    p->block = p->kind == GateKernel::Masked ? tn.masked_block : kThreads;
     if (p->kind == GateKernel::Masked || p->kind == GateKernel::Pair)
         p->index64 = g.n > 32;
     else
@@ -397,8 +417,8 @@ std::string gate_plan_name(const GatePlan &p, int dtype, const char *matsrc) {
     switch (p.kind) {
     case GateKernel::Masked:
     case GateKernel::Pair:
-        snprintf(buf, sizeof(buf), "sv::k_pair<%s, %s, %d, %d, sv::%s<%s> >", R,
-                 p.index64 ? "unsigned long" : "unsigned int", p.unroll, p.policy, matsrc, R);
+        snprintf(buf, sizeof(buf), "sv::k_pair<%s, %s, %d, %d, %d, sv::%s<%s> >", R,
+                 p.index64 ? "unsigned long" : "unsigned int", p.unroll, p.policy, p.block, matsrc, R);
         break;
     case GateKernel::Wave:
         snprintf(buf, sizeof(buf), "sv::k_wave<%s, %d, %d, sv::%s<%s> >", R, p.unroll, p.policy, matsrc, R);
@@ -410,17 +430,32 @@ std::string gate_plan_name(const GatePlan &p, int dtype, const char *matsrc) {
     return buf;
 }
 
-template <typename R, typename I, int K, typename MS>
+template <typename R, typename I, int K, int T, typename MS>
 static void go_pair(cplx_t<R> *psi, const GatePlan &p, const MS &ms, hipStream_t st) {
-    const uint64_t blocks = (p.niter + kThreads * K - 1) / (kThreads * K);
+    const uint64_t blocks = (p.niter + T * K - 1) / (T * K);
     for (uint64_t b0 = 0; b0 < blocks; b0 += kMaxGridBlocks) {
         const dim3 grid((unsigned)std::min(kMaxGridBlocks, blocks - b0));
         if (p.policy == kRewrite)
-            hipLaunchKernelGGL((k_pair<R, I, K, kRewrite, MS>), grid, dim3(kThreads), 0, st, psi, p.niter, p.e,
-                               p.tmask, p.tvals, (uint32_t)p.target, ms, b0);
+            hipLaunchKernelGGL((k_pair<R, I, K, kRewrite, T, MS>), grid, dim3(T), 0, st, psi, p.niter, p.e, p.tmask,
+                               p.tvals, (uint32_t)p.target, ms, b0);
         else
-            hipLaunchKernelGGL((k_pair<R, I, K, kSkip, MS>), grid, dim3(kThreads), 0, st, psi, p.niter, p.e,
-                               p.tmask, p.tvals, (uint32_t)p.target, ms, b0);
+            hipLaunchKernelGGL((k_pair<R, I, K, kSkip, T, MS>), grid, dim3(T), 0, st, psi, p.niter, p.e, p.tmask,
+                               p.tvals, (uint32_t)p.target, ms, b0);
+    }
+}
+
+template <typename R, typename I, typename MS>
+static void go_pair_shape(cplx_t<R> *psi, const GatePlan &p, const MS &ms, hipStream_t st) {
+    if (p.block == 256) {
+        if (p.unroll == 4)
+            go_pair<R, I, 4, 256>(psi, p, ms, st);
+        else
+            go_pair<R, I, 1, 256>(psi, p, ms, st);
+    } else {
+        if (p.unroll == 4)
+            go_pair<R, I, 4, kThreads>(psi, p, ms, st);
+        else
+            go_pair<R, I, 1, kThreads>(psi, p, ms, st);
     }
 }
 
@@ -444,17 +479,10 @@ int launch_plan(cplx_t<R> *psi, const GatePlan &p, const MS &ms, hipStream_t st)
     switch (p.kind) {
     case GateKernel::Masked:
     case GateKernel::Pair:
-        if (p.index64) {
-            if (p.unroll == 4)
-                go_pair<R, uint64_t, 4>(psi, p, ms, st);
-            else
-                go_pair<R, uint64_t, 1>(psi, p, ms, st);
-        } else {
-            if (p.unroll == 4)
-                go_pair<R, uint32_t, 4>(psi, p, ms, st);
-            else
-                go_pair<R, uint32_t, 1>(psi, p, ms, st);
-        }
+        if (p.index64)
+            go_pair_shape<R, uint64_t>(psi, p, ms, st);
+        else
+            go_pair_shape<R, uint32_t>(psi, p, ms, st);
         break;
     case GateKernel::Wave:
         if (p.unroll == 4)
@@ -491,6 +519,53 @@ static int launch_tile1(const sv_state_t *s, const GateSpec &g, const double *U,
                            reinterpret_cast<cplx_t<R> *>(s->data), tm, gs);
         SV_LAUNCH_CHECK();
     }
+    return SV_OK;
+}
+
+// ---------------------------------------------------------------------------
+// HBM probe (measurement helper, not part of the method): the same streaming
+// access as the scheduled kernels (64-lane workgroups, one 16- or 8-byte
+// amplitude per lane, nontemporal) over the amplitudes whose index bits
+// match a fixed pattern, with no arithmetic beyond a multiply by 1.  It gives
+// the bandwidth a gate's own address set can reach, and a kernel of known
+// traffic for calibrating the byte counters of the profiler.
+//   OP 0: read and write back every selected amplitude (unchanged values)
+//   OP 1: read only;  OP 2: write zeros
+// ---------------------------------------------------------------------------
+template <typename R, int OP>
+__global__ __launch_bounds__(kThreads) void k_hbm_probe(cplx_t<R> *__restrict__ psi, uint64_t count, Expand e,
+                                                        R scale, R *__restrict__ sink, uint64_t block0) {
+    const uint64_t i = (block0 + blockIdx.x) * kThreads + threadIdx.x;
+    if (i >= count)
+        return;
+    const uint64_t k = expand_index<uint64_t>(e, i);
+    if (OP == 2) {
+        cplx_t<R> z;
+        z.x = (R)0;
+        z.y = (R)0;
+        st_stream<R>(psi + k, z);
+        return;
+    }
+    cplx_t<R> v = ld_stream<R>(psi + k);
+    if (OP == 0) {
+        v.x *= scale;  // scale is 1: the values stay as they were
+        v.y *= scale;
+        st_stream<R>(psi + k, v);
+    } else if (v.x == scale) {  // scale is NaN for reads: never true, keeps the load
+        sink[0] = v.y;
+    }
+}
+
+template <typename R, int OP>
+static int go_probe(void *psi, uint64_t count, const Expand &e, hipStream_t st) {
+    const uint64_t blocks = (count + kThreads - 1) / kThreads;
+    const R scale = OP == 1 ? (R)__builtin_nan("") : (R)1;
+    for (uint64_t b0 = 0; b0 < blocks; b0 += kMaxGridBlocks) {
+        const dim3 grid((unsigned)std::min(kMaxGridBlocks, blocks - b0));
+        hipLaunchKernelGGL((k_hbm_probe<R, OP>), grid, dim3(kThreads), 0, st, reinterpret_cast<cplx_t<R> *>(psi),
+                           count, e, scale, reinterpret_cast<R *>(psi), b0);
+    }
+    SV_LAUNCH_CHECK();
     return SV_OK;
 }
 
@@ -541,6 +616,35 @@ int sv_apply_gate(const sv_state_t *s, int target, const int32_t *controls, int 
     GateSpec g{s->n, target, mask, ctrl_vals};
     SV_TRY(validate_gate(g));
     return launch_gate(s, g, U, mode, (hipStream_t)st);
+}
+
+int sv_hbm_probe(const sv_state_t *s, uint64_t fixed_mask, uint64_t fixed_vals, int op, sv_stream_t st) {
+    clear_error();
+    SV_TRY(validate_state(s));
+    const uint64_t full = (s->n >= 64) ? ~0ull : ((1ull << s->n) - 1);
+    if (fixed_mask & ~full)
+        return fail(SV_EINVAL, "fixed_mask 0x%llx has bits >= n=%d", (unsigned long long)fixed_mask, s->n);
+    if (fixed_vals & ~fixed_mask)
+        return fail(SV_EINVAL, "fixed_vals 0x%llx has bits outside fixed_mask 0x%llx",
+                    (unsigned long long)fixed_vals, (unsigned long long)fixed_mask);
+    if (op < 0 || op > 2)
+        return fail(SV_EINVAL, "unknown probe operation %d", op);
+    std::vector<int> pos, bits;
+    for (int q = 0; q < s->n; ++q)
+        if (fixed_mask & (1ull << q)) {
+            pos.push_back(q);
+            bits.push_back((int)((fixed_vals >> q) & 1));
+        }
+    const Expand e = make_expand(s->n, pos, bits);
+    const uint64_t count = 1ull << (s->n - popcount64(fixed_mask));
+    const hipStream_t hs = (hipStream_t)st;
+    if (s->dtype == SV_C128)
+        return op == 0 ? go_probe<double, 0>(s->data, count, e, hs)
+               : op == 1 ? go_probe<double, 1>(s->data, count, e, hs)
+                         : go_probe<double, 2>(s->data, count, e, hs);
+    return op == 0 ? go_probe<float, 0>(s->data, count, e, hs)
+           : op == 1 ? go_probe<float, 1>(s->data, count, e, hs)
+                     : go_probe<float, 2>(s->data, count, e, hs);
 }
 
 int sv_gate_plan(int n, int dtype, int target, uint64_t ctrl_mask, uint64_t ctrl_vals, int mode, char *kernel,

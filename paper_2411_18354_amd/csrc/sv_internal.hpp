@@ -160,6 +160,11 @@ struct Tuning {
     int fuse_min_gates;   // shortest run worth an LDS pass
     int dense_qubits;     // k of dense k-qubit blocks (SV_DENSE)
     int dense_min_gates;  // shortest stretch on qubits < k made a dense block
+    int pair_unroll;      // pairs (wavefronts) per lane of large scheduled launches: 1 or 4
+    int masked_unroll;    // the same for the masked baseline kernel
+    int masked_block;     // lanes per workgroup of the masked baseline kernel: 64 or 256
+    int fuse_group;       // fused runs: gather diagonal gates into blocks (commutation moves)
+    int fuse_pairs;       // fused runs: apply adjacent coset-closed pair gates together
 };
 Tuning &tuning();
 
@@ -174,6 +179,7 @@ struct GatePlan {
     uint64_t niter;    // pairs, wavefronts (64 amplitudes) or tiles
     int target;        // pair kernels: t; wave kernel: t's bit in the iteration index
     int unroll;
+    int block;         // lanes per workgroup (pair kernels)
     int policy;
     bool index64;
 };

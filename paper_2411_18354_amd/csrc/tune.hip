@@ -21,7 +21,14 @@ Tuning &tuning() {
     //    qubits, i.e. 1 KiB contiguous runs, plus qubits picked per run.
     //  - dense blocks (SV_DENSE) on the 4 lowest qubits for stretches of at
     //    least 16 gates.
-    static Tuning t = {{3, 4}, 1, 1, {12, 13}, {6, 7}, 2, 4, 16};
+    //  - one pair (or amplitude) per lane in the scheduled pair and
+    //    wavefront kernels (64-lane workgroups): in-place streams of 4 GiB
+    //    reach about 6.7 TB/s that way against about 5.7 TB/s with four per
+    //    lane; the masked baseline is fastest over the n=28 sweep with
+    //    256-lane workgroups and one pair per lane (10.8 ms against 12.5 ms
+    //    with four per lane, 16.1 ms with 64-lane workgroups, whose many
+    //    workgroups cost more when most lanes only test and exit).
+    static Tuning t = {{3, 4}, 1, 1, {12, 13}, {6, 7}, 2, 4, 16, 1, 1, 256, 1, 1};
     return t;
 }
 
@@ -45,6 +52,11 @@ static int find_key(const char *name, Key *out) {
         {"fuse_min_gates", &t.fuse_min_gates, 1, 1 << 20},
         {"dense_qubits", &t.dense_qubits, 4, 5},
         {"dense_min_gates", &t.dense_min_gates, 1, 1 << 20},
+        {"pair_unroll", &t.pair_unroll, 1, 4},
+        {"masked_unroll", &t.masked_unroll, 1, 4},
+        {"masked_block", &t.masked_block, 64, 256},
+        {"fuse_group", &t.fuse_group, 0, 1},
+        {"fuse_pairs", &t.fuse_pairs, 0, 1},
     };
     for (const Key &k : keys)
         if (name && strcmp(k.name, name) == 0) {
@@ -66,6 +78,10 @@ int sv_tune_set(const char *key, int64_t value) {
     SV_TRY(find_key(key, &k));
     if (value < k.lo || value > k.hi)
         return fail(SV_EINVAL, "tuning %s=%lld outside [%d, %d]", key, (long long)value, k.lo, k.hi);
+    // two-valued knobs: only the bounds themselves
+    const bool two = !strcmp(key, "pair_unroll") || !strcmp(key, "masked_unroll") || !strcmp(key, "masked_block");
+    if (two && value != k.lo && value != k.hi)
+        return fail(SV_EINVAL, "tuning %s takes %d or %d (got %lld)", key, k.lo, k.hi, (long long)value);
     *k.slot = (int)value;
     return SV_OK;
 }

@@ -212,3 +212,40 @@ def test_expect_noalloc_rejects_too_many_terms(sv):
     arr = sv.pauli_terms([(1.0, 0, 1 << (i % 8)) for i in range(65)])
     rc = sv.lib().sv_expect_noalloc(ctypes.byref(s), arr, 65, ctypes.c_void_p(0x20000), None)
     assert rc == sv.SV_EINVAL and "allocation-free limit of 64" in sv.sv_last_error()
+
+
+def test_hbm_probe_argument_errors(sv):
+    s = _state(sv, 8)
+    for args, needle in (((1 << 9, 0, 0), "bits >= n"), ((3, 4, 0), "outside fixed_mask"), ((0, 0, 5), "operation")):
+        code, msg = _rc(lambda: sv.sv_hbm_probe(s, *args))
+        assert code == sv.SV_EINVAL and needle in msg, msg
+
+
+def test_two_valued_knobs(sv):
+    for key, good, bad in (("pair_unroll", (1, 4), 2), ("masked_unroll", (1, 4), 3), ("masked_block", (64, 256), 128)):
+        old = sv.sv_tune_get(key)
+        try:
+            for v in good:
+                sv.sv_tune_set(key, v)
+                assert sv.sv_tune_get(key) == v
+            code, msg = _rc(lambda: sv.sv_tune_set(key, bad))
+            assert code == sv.SV_EINVAL and "takes" in msg
+        finally:
+            sv.sv_tune_set(key, old)
+
+
+def test_adjoint_rejects_non_unitary_matrix(sv):
+    """The reverse sweep un-applies gates by their conjugate transpose, so a
+    fixed matrix that is not unitary is an argument error (before any device
+    use)."""
+    import numpy as np
+    import workloads as W
+    psi, lam = _state(sv, 4, ptr=0x10000), _state(sv, 4, ptr=0x20000)
+    M = np.array([[1.0, 0.0], [0.0, 1.0 + 1e-9]], dtype=np.complex128)  # off by 1e-9
+    m8 = tuple(np.stack([M.real, M.imag], axis=-1).reshape(8))
+    c = W.Circuit(4, [W.Gate("RY", 0, param=0), W.Gate("U", 1, (0,), matrix=m8)], np.array([0.3]))
+    gates = sv.circuit_gates(c)
+    terms = sv.pauli_terms([W.PauliTerm(1.0, 0, 1)])
+    rc = sv.lib().sv_adjoint_grad(ctypes.byref(psi), ctypes.byref(lam), gates, 2, ctypes.c_void_p(0x30000), 1,
+                                  terms, 1, ctypes.c_void_p(0x40000), None, None, None)
+    assert rc == sv.SV_EINVAL and "not unitary" in sv.sv_last_error(), sv.sv_last_error()
