@@ -25,6 +25,7 @@
 namespace sv {
 
 int validate_circuit_gate(int n, int nparams, const sv_gate_t &g, int index);
+int validate_unitary_gate(const sv_gate_t &g, int index);
 
 // One gate of the reverse sweep on the pairs of a scheduled plan (pair index
 // p1 = expand(i), partner p1 | 2^t; tmask/tvals as in the pair kernel).
@@ -187,8 +188,10 @@ int adjoint_impl(const sv_state_t *psi, const sv_state_t *lam, const sv_gate_t *
     if (nparams < 0 || (nparams > 0 && (!params || !grad)))
         return fail(SV_EINVAL, "nparams %d needs params_dev and grad_dev", nparams);
     const int n = psi->n, dtype = psi->dtype;
-    for (int i = 0; i < ngates; ++i)
+    for (int i = 0; i < ngates; ++i) {
         SV_TRY(validate_circuit_gate(n, nparams, gates[i], i));
+        SV_TRY(validate_unitary_gate(gates[i], i));
+    }
     PauliPlan pplan;
     SV_TRY(make_pauli_plan(n, terms, nterms, &pplan));
 

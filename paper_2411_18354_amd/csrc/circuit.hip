@@ -11,6 +11,7 @@
 // the two commute (see commute() below), so runs are not cut by every
 // unrelated high-target gate.
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 #include <memory>
 
@@ -56,6 +57,22 @@ static bool commute(const sv_gate_t &a, const sv_gate_t &b) {
     return true;
 }
 
+int validate_unitary_gate(const sv_gate_t &g, int index) {
+    if ((g.kind & ~SV_G_ADJOINT) != SV_G_MATRIX)
+        return SV_OK;  // named kinds are unitary for every angle
+    const double *u = g.U;
+    // rows (a, b) and (c, d): |a|^2 + |b|^2 = 1, |c|^2 + |d|^2 = 1, a conj(c) + b conj(d) = 0
+    const double r0 = u[0] * u[0] + u[1] * u[1] + u[2] * u[2] + u[3] * u[3] - 1.0;
+    const double r1 = u[4] * u[4] + u[5] * u[5] + u[6] * u[6] + u[7] * u[7] - 1.0;
+    const double xr = u[0] * u[4] + u[1] * u[5] + u[2] * u[6] + u[3] * u[7];
+    const double xi = u[1] * u[4] - u[0] * u[5] + u[3] * u[6] - u[2] * u[7];
+    const double dev = std::max(std::max(std::fabs(r0), std::fabs(r1)), std::sqrt(xr * xr + xi * xi));
+    if (!(dev <= 1e-12))
+        return fail(SV_EINVAL, "gate %d: matrix is not unitary (|U U^dag - I| = %.3g); the adjoint sweep "
+                               "un-applies each gate by its conjugate transpose", index, dev);
+    return SV_OK;
+}
+
 int validate_circuit_gate(int n, int nparams, const sv_gate_t &g, int index) {
     if (!gate_kind_valid(g.kind))
         return fail(SV_EINVAL, "gate %d: unknown kind %d", index, g.kind);
@@ -91,6 +108,35 @@ static bool gate_is_diagonal(const sv_gate_t &g, const double *mat) {
     if (g.param >= 0)
         return false;
     return mat[2] == 0.0 && mat[3] == 0.0 && mat[4] == 0.0 && mat[5] == 0.0;
+}
+
+// Inside a fused run, gather diagonal gates into blocks.  First every
+// diagonal gate moves later past the non-diagonal gates that follow it and
+// commute with it, up to the next diagonal gate (scanning from the end, so
+// moved gates collect).  Then a diagonal gate that can move earlier past the
+// non-diagonal gates before it, all of which it commutes with, until it meets
+// a diagonal gate, joins that block.  Gates only pass gates they commute
+// with, so the run computes the same unitary; diagonal blocks grow (one sweep
+// each) and pair gates become adjacent (coset pairs).  An ansatz layer
+// RY(q) RZ(q) ... then CNOT(q -> q+1) ... becomes all RY, all RZ, the CNOTs.
+static void group_diagonals(std::vector<int> &run, const std::vector<char> &diag,
+                            const std::vector<sv_gate_t> &gates) {
+    const int R = (int)run.size();
+    for (int k = R - 2; k >= 0; --k) {
+        if (!diag[run[k]])
+            continue;
+        for (int j = k; j + 1 < R && !diag[run[j + 1]] && commute(gates[run[j]], gates[run[j + 1]]); ++j)
+            std::swap(run[j], run[j + 1]);
+    }
+    for (int k = 1; k < R; ++k) {
+        if (!diag[run[k]] || diag[run[k - 1]])
+            continue;
+        int j = k;
+        while (j - 1 >= 0 && !diag[run[j - 1]] && commute(gates[run[j - 1]], gates[run[k]]))
+            --j;
+        if (j - 1 >= 0 && diag[run[j - 1]])  // reached a block: join it
+            std::rotate(run.begin() + j, run.begin() + k, run.begin() + k + 1);
+    }
 }
 
 // Greedy fusion planner.
@@ -223,6 +269,8 @@ static int plan_circuit(sv_circuit *c, std::vector<TileGate> &tiles, std::vector
                 }
             }
             if ((int)run.size() >= min_run) {
+                if (tuning().fuse_group)
+                    group_diagonals(run, diag, c->gates);
                 // fill the tile's qubit set up to m, preferring the lowest free qubits
                 std::sort(high.begin(), high.end());
                 for (int q = a; (int)high.size() < m - a && q < c->n; ++q)
@@ -286,6 +334,8 @@ static int plan_circuit(sv_circuit *c, std::vector<TileGate> &tiles, std::vector
                     k = e;
                 }
                 mark_diag_sweeps(&tiles[p.first], p.count, from_param.data());
+                if (tuning().fuse_pairs)
+                    mark_coset_pairs(&tiles[p.first], p.count);
                 c->passes.push_back(p);
                 c->fused_gates += (int64_t)run.size();
                 c->fused_runs++;

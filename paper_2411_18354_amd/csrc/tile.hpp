@@ -48,7 +48,9 @@ struct TileGate {
     int32_t l_target;
     // first gate of a block of consecutive diagonal gates: the block's
     // length, and whether it is long enough and of unit modulus throughout
-    // to add phases (bit 0); set on the host
+    // to add phases (bit 0); set on the host.  A pair gate with sweep_len 2
+    // is applied together with the next gate over 4-amplitude cosets (see
+    // mark_coset_pairs).
     uint16_t sweep_len, sweep_phase;
     // diagonal gate: phases of its two entries, and whether both have unit
     // modulus (then a sweep may add phases instead of multiplying factors)
@@ -73,6 +75,15 @@ constexpr uint32_t kSweepHaveR = 1u << 16, kSweepRank1 = 1u << 17, kSweepAnyRest
 // block's first gate.  param_gate[i] != 0: the entries of gate i come from parameters at
 // run time (their kinds are unitary), so it counts as unit modulus.
 void mark_diag_sweeps(TileGate *tiles, int count, const char *param_gate);
+
+// Mark coset pairs among tiles[0 .. count) (one fused run; host): two
+// adjacent pair gates on different tile-local targets t1, t2 whose
+// tile-local controls lie only on the other gate's target.  Every coset
+// {b, b + 2^t1, b + 2^t2, b + 2^t1 + 2^t2} is then closed under both gates,
+// so one LDS read and write of its four amplitudes applies both, with the
+// same pair arithmetic in the same order as two separate loops.  The first
+// gate of a pair gets sweep_len = 2; pairs do not overlap.
+void mark_coset_pairs(TileGate *tiles, int count);
 
 // Phases of the diagonal entries m[0..1] and m[6..7] (host and device).
 __host__ __device__ inline void diag_phases(const double *m, double *ph, uint32_t *unit) {
@@ -560,6 +571,40 @@ __device__ __forceinline__ void tile_pairs(cplx_t<R> *tile, const Mat2<R> &mm, c
     }
 }
 
+// Two pair gates over 4-amplitude cosets (a coset pair marked on the host):
+// g1 on target t1, then g2 on target t2, each possibly controlled by the
+// other's target; the coset's other bits are free, so every coset is
+// visited.
+template <typename R, int THREADS>
+__device__ __forceinline__ void tile_pairs2(cplx_t<R> *tile, uint32_t T, const TileGate &g1, const TileGate &g2) {
+    const uint32_t t1 = g1.target, t2 = g2.target;
+    const uint32_t lo = min(t1, t2), hi = max(t1, t2);
+    const uint32_t s1 = 1u << t1, s2 = 1u << t2;
+    // g1 controlled by t2 (value v1) acts on one of its two pairs; likewise g2
+    const bool c1 = (g1.l_mask >> t2) & 1u, c2 = (g2.l_mask >> t1) & 1u;
+    const uint32_t v1 = (g1.l_vals >> t2) & 1u, v2 = (g2.l_vals >> t1) & 1u;
+    const bool a0 = !c1 || v1 == 0, a1 = !c1 || v1 == 1, b0 = !c2 || v2 == 0, b1 = !c2 || v2 == 1;
+    const Mat2<R> m1 = tile_mat<R>(g1), m2 = tile_mat<R>(g2);
+    for (uint32_t r = threadIdx.x; r < (T >> 2); r += THREADS) {
+        uint32_t b = ((r >> lo) << (lo + 1)) | (r & ((1u << lo) - 1u));
+        b = ((b >> hi) << (hi + 1)) | (b & ((1u << hi) - 1u));
+        // x_{bit t2, bit t1}
+        cplx_t<R> x00 = tile[b], x01 = tile[b | s1], x10 = tile[b | s2], x11 = tile[b | s1 | s2];
+        if (a0)
+            apply_pair<R>(m1, x00, x01);
+        if (a1)
+            apply_pair<R>(m1, x10, x11);
+        if (b0)
+            apply_pair<R>(m2, x00, x10);
+        if (b1)
+            apply_pair<R>(m2, x01, x11);
+        tile[b] = x00;
+        tile[b | s1] = x01;
+        tile[b | s2] = x10;
+        tile[b | s1 | s2] = x11;
+    }
+}
+
 // Whether any operation of the run acts on the tile at base.
 template <typename Src> __device__ __forceinline__ bool tile_touched(uint64_t base, const Src &gates) {
     bool any = false;
@@ -655,6 +700,16 @@ __device__ __forceinline__ void tile_run(cplx_t<R> *tile, uint64_t base, const T
             __syncthreads();
             i = e;
             continue;
+        }
+        if (g.sweep_len == 2 && i + 1 < gates.size()) {  // a coset pair (uniform)
+            const TileGate &g2 = gates.get(i + 1);
+            const bool p1 = (base & g.hi_mask) == g.hi_vals, p2 = (base & g2.hi_mask) == g2.hi_vals;
+            if (p1 && p2) {  // uniform across the workgroup
+                tile_pairs2<R, THREADS>(tile, T, g, g2);
+                __syncthreads();
+                i += 2;
+                continue;
+            }
         }
         if ((base & g.hi_mask) == g.hi_vals) {  // uniform across the workgroup
             const Mat2<R> mm = tile_mat<R>(g);

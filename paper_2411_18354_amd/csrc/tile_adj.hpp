@@ -59,6 +59,19 @@ __device__ __forceinline__ bool adj_tile_touched(uint64_t base, const DeviceGate
     return false;
 }
 
+// Gradient term of one amplitude pair: 2 Re <lambda| A |psi> restricted to
+// the pair, A = a[8] (the generator, 2x2 complex) acting on (x, y).
+template <typename R>
+__device__ __forceinline__ double adj_pair_term(const double *a, const cplx_t<R> &x, const cplx_t<R> &y,
+                                                const cplx_t<R> &lx, const cplx_t<R> &ly) {
+    const double xr = x.x, xi = x.y, yr = y.x, yi = y.y;
+    const double axr = a[0] * xr - a[1] * xi + a[2] * yr - a[3] * yi;
+    const double axi = a[0] * xi + a[1] * xr + a[2] * yi + a[3] * yr;
+    const double ayr = a[4] * xr - a[5] * xi + a[6] * yr - a[7] * yi;
+    const double ayi = a[4] * xi + a[5] * xr + a[6] * yi + a[7] * yr;
+    return 2.0 * ((double)lx.x * axr + (double)lx.y * axi + (double)ly.x * ayr + (double)ly.y * ayi);
+}
+
 // One pair gate un-applied on both tiles, with its gradient term (sl >= 0;
 // generator a[8]) summed per lane in pair order.  The in-tile expansion is
 // held in NS register segments, as in the forward pass's pair loop (NS = 0:
@@ -88,14 +101,8 @@ __device__ __forceinline__ double adj_tile_pairs(cplx_t<R> *tp, cplx_t<R> *tl, c
             p1 = tile_expand(g, r);
         }
         cplx_t<R> x = tp[p1], y = tp[p1 | st], lx = tl[p1], ly = tl[p1 | st];
-        if (sl >= 0) {
-            const double xr = x.x, xi = x.y, yr = y.x, yi = y.y;
-            const double axr = a[0] * xr - a[1] * xi + a[2] * yr - a[3] * yi;
-            const double axi = a[0] * xi + a[1] * xr + a[2] * yi + a[3] * yr;
-            const double ayr = a[4] * xr - a[5] * xi + a[6] * yr - a[7] * yi;
-            const double ayi = a[4] * xi + a[5] * xr + a[6] * yi + a[7] * yr;
-            acc += 2.0 * ((double)lx.x * axr + (double)lx.y * axi + (double)ly.x * ayr + (double)ly.y * ayi);
-        }
+        if (sl >= 0)
+            acc += adj_pair_term<R>(a, x, y, lx, ly);
         apply_pair<R>(u, x, y);
         apply_pair<R>(u, lx, ly);
         tp[p1] = x;
@@ -104,6 +111,158 @@ __device__ __forceinline__ double adj_tile_pairs(cplx_t<R> *tp, cplx_t<R> *tl, c
         tl[p1 | st] = ly;
     }
     return acc;
+}
+
+// A coset pair (marked on the host, as in the forward pass) un-applied on
+// both tiles: g1 then g2 over every 4-amplitude coset, each gate's gradient
+// term taken on the values it sees in the sequential order (acc1, acc2).
+template <typename R, int THREADS>
+__device__ __forceinline__ void adj_tile_pairs2(cplx_t<R> *tp, cplx_t<R> *tl, uint32_t T, const TileGate &g1,
+                                                const TileGate &g2, int sl1, int sl2, const double *a1,
+                                                const double *a2, double *acc1, double *acc2) {
+    const uint32_t t1 = g1.target, t2 = g2.target;
+    const uint32_t lo = min(t1, t2), hi = max(t1, t2);
+    const uint32_t s1 = 1u << t1, s2 = 1u << t2;
+    const bool c1 = (g1.l_mask >> t2) & 1u, c2 = (g2.l_mask >> t1) & 1u;
+    const uint32_t v1 = (g1.l_vals >> t2) & 1u, v2 = (g2.l_vals >> t1) & 1u;
+    const bool p0 = !c1 || v1 == 0, p1 = !c1 || v1 == 1, q0 = !c2 || v2 == 0, q1 = !c2 || v2 == 1;
+    const Mat2<R> u1 = tile_mat<R>(g1), u2 = tile_mat<R>(g2);
+    double s_1 = 0.0, s_2 = 0.0;
+    for (uint32_t r = threadIdx.x; r < (T >> 2); r += THREADS) {
+        uint32_t b = ((r >> lo) << (lo + 1)) | (r & ((1u << lo) - 1u));
+        b = ((b >> hi) << (hi + 1)) | (b & ((1u << hi) - 1u));
+        const uint32_t i01 = b | s1, i10 = b | s2, i11 = b | s1 | s2;
+        cplx_t<R> x00 = tp[b], x01 = tp[i01], x10 = tp[i10], x11 = tp[i11];
+        cplx_t<R> l00 = tl[b], l01 = tl[i01], l10 = tl[i10], l11 = tl[i11];
+        if (p0) {
+            if (sl1 >= 0)
+                s_1 += adj_pair_term<R>(a1, x00, x01, l00, l01);
+            apply_pair<R>(u1, x00, x01);
+            apply_pair<R>(u1, l00, l01);
+        }
+        if (p1) {
+            if (sl1 >= 0)
+                s_1 += adj_pair_term<R>(a1, x10, x11, l10, l11);
+            apply_pair<R>(u1, x10, x11);
+            apply_pair<R>(u1, l10, l11);
+        }
+        if (q0) {
+            if (sl2 >= 0)
+                s_2 += adj_pair_term<R>(a2, x00, x10, l00, l10);
+            apply_pair<R>(u2, x00, x10);
+            apply_pair<R>(u2, l00, l10);
+        }
+        if (q1) {
+            if (sl2 >= 0)
+                s_2 += adj_pair_term<R>(a2, x01, x11, l01, l11);
+            apply_pair<R>(u2, x01, x11);
+            apply_pair<R>(u2, l01, l11);
+        }
+        tp[b] = x00;
+        tp[i01] = x01;
+        tp[i10] = x10;
+        tp[i11] = x11;
+        tl[b] = l00;
+        tl[i01] = l01;
+        tl[i10] = l10;
+        tl[i11] = l11;
+    }
+    *acc1 = s_1;
+    *acc2 = s_2;
+}
+
+// A block [i, e) of consecutive diagonal gates un-applied in one pass over
+// both tiles.  Un-applying a unit-modulus diagonal gate multiplies psi_j and
+// lambda_j by the same factor f_j, so w_j = conj(lambda_j) psi_j is the same
+// before and after every gate of the block, and a gate's gradient term
+// 2 Re <lambda| A |psi> = sum_j 2 Re(a_j w_j) (a_j: the generator's diagonal
+// entry on amplitude j's target bit, over the amplitudes whose controls
+// hold) needs only w_j.  So each lane forms w_j once, adds every
+// parameterised gate's term (a wavefront sum into that gate's accumulator),
+// multiplies the factors and writes psi_j f_j and lambda_j f_j once.  Every
+// gate of an adjoint sweep is unitary (checked on the host).  Returns the
+// accumulator index after the block.
+template <typename R, int THREADS>
+__device__ __forceinline__ int adj_diag_block(cplx_t<R> *tp, cplx_t<R> *tl, uint64_t base, uint32_t T,
+                                              const DeviceGates &gates, int i, int e, const int32_t *gslot,
+                                              const double *gens, double *accl, int kacc) {
+    const int w = threadIdx.x >> 6;
+    const uint32_t nch = (T + 4 * THREADS - 1) / (4 * THREADS);  // uniform
+    int k = kacc;
+    for (uint32_t ch = 0; ch < nch; ++ch) {
+        uint32_t j[4];
+        bool in[4];
+        cplx_t<R> x[4], l[4];
+        double wr[4], wi[4];
+        R fr[4], fi[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            j[q] = ch * 4 * THREADS + q * THREADS + threadIdx.x;
+            in[q] = j[q] < T;
+            if (in[q]) {
+                x[q] = tp[j[q]];
+                l[q] = tl[j[q]];
+            } else {
+                x[q].x = x[q].y = l[q].x = l[q].y = (R)0;
+            }
+            wr[q] = (double)l[q].x * (double)x[q].x + (double)l[q].y * (double)x[q].y;
+            wi[q] = (double)l[q].x * (double)x[q].y - (double)l[q].y * (double)x[q].x;
+            fr[q] = (R)1;
+            fi[q] = (R)0;
+        }
+        k = kacc;
+        for (int q = i; q < e; ++q) {
+            const TileGate &d = gates.get(q);
+            const int sl = gslot[q];
+            if ((base & d.o_mask) != d.o_vals) {  // uniform: the gate skips this tile
+                k += sl >= 0 ? 1 : 0;
+                continue;
+            }
+            const bool tin = d.l_target >= 0;
+            const bool tone = (base >> d.target) & 1ull;
+            if (sl >= 0) {  // uniform
+                const double a0r = gens[8 * sl + 0], a0i = gens[8 * sl + 1];
+                const double a1r = gens[8 * sl + 6], a1i = gens[8 * sl + 7];
+                double part = 0.0;
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    if (!in[u] || (j[u] & d.l_mask) != d.l_vals)
+                        continue;
+                    const bool one = tin ? ((j[u] >> d.l_target) & 1u) : tone;
+                    const double gr = one ? a1r : a0r, gi = one ? a1i : a0i;
+                    part += 2.0 * (gr * wr[u] - gi * wi[u]);
+                }
+                const double sum = wave_sum(part);
+                if ((threadIdx.x & 63) == 0)
+                    accl[k * kAdjWaves + w] += sum;
+                ++k;
+            }
+            const R m0r = (R)uniform_f64(d.m[0]), m0i = (R)uniform_f64(d.m[1]);
+            const R m1r = (R)uniform_f64(d.m[6]), m1i = (R)uniform_f64(d.m[7]);
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const bool on = (j[u] & d.l_mask) == d.l_vals;
+                const bool one = tin ? ((j[u] >> d.l_target) & 1u) : tone;
+                const R ur = on ? (one ? m1r : m0r) : (R)1, ui = on ? (one ? m1i : m0i) : (R)0;
+                const R nr = fr[u] * ur - fi[u] * ui;
+                fi[u] = fr[u] * ui + fi[u] * ur;
+                fr[u] = nr;
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            if (!in[q])
+                continue;
+            cplx_t<R> nx, nl;
+            nx.x = x[q].x * fr[q] - x[q].y * fi[q];
+            nx.y = x[q].x * fi[q] + x[q].y * fr[q];
+            nl.x = l[q].x * fr[q] - l[q].y * fi[q];
+            nl.y = l[q].x * fi[q] + l[q].y * fr[q];
+            tp[j[q]] = nx;
+            tl[j[q]] = nl;
+        }
+    }
+    return k;
 }
 
 template <typename R, int THREADS>
@@ -115,6 +274,41 @@ __device__ __forceinline__ void adj_tile_run(cplx_t<R> *tp, cplx_t<R> *tl, uint6
     for (int i = 0; i < gates.size(); ++i) {
         const TileGate &g = gates.get(i);
         const int sl = gslot[i];
+        if (g.diag && g.sweep_len > 1) {  // a block of diagonal gates (uniform)
+            const int e = min(gates.size(), i + (int)g.sweep_len);
+            kacc = adj_diag_block<R, THREADS>(tp, tl, base, T, gates, i, e, gslot, gens, accl, kacc);
+            __syncthreads();
+            i = e - 1;
+            continue;
+        }
+        if (!g.diag && g.sweep_len == 2 && i + 1 < gates.size()) {  // a coset pair (uniform)
+            const TileGate &g2 = gates.get(i + 1);
+            if ((base & g.hi_mask) == g.hi_vals && (base & g2.hi_mask) == g2.hi_vals) {
+                const int sl2 = gslot[i + 1];
+                double a1[8], a2[8];
+                for (int q = 0; q < 8; ++q) {
+                    a1[q] = sl >= 0 ? gens[8 * sl + q] : 0.0;
+                    a2[q] = sl2 >= 0 ? gens[8 * sl2 + q] : 0.0;
+                }
+                double acc1, acc2;
+                adj_tile_pairs2<R, THREADS>(tp, tl, T, g, g2, sl, sl2, a1, a2, &acc1, &acc2);
+                if (sl >= 0) {
+                    const double s1 = wave_sum(acc1);
+                    if ((threadIdx.x & 63) == 0)
+                        accl[kacc * kAdjWaves + w] += s1;
+                    ++kacc;
+                }
+                if (sl2 >= 0) {
+                    const double s2 = wave_sum(acc2);
+                    if ((threadIdx.x & 63) == 0)
+                        accl[kacc * kAdjWaves + w] += s2;
+                    ++kacc;
+                }
+                __syncthreads();
+                ++i;
+                continue;
+            }
+        }
         double a[8];
         for (int q = 0; q < 8; ++q)
             a[q] = sl >= 0 ? gens[8 * sl + q] : 0.0;

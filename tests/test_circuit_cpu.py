@@ -191,3 +191,29 @@ def test_remap_plan_host():
     _, _, a = sv.sv_circuit_plan(20, plain, flags=0)
     _, _, b = sv.sv_circuit_plan(20, plain, flags=sv.SV_REMAP)
     assert a == b
+
+
+def test_diagonal_gates_grouped_inside_runs(sv):
+    """Inside a fused run, diagonal gates move later past the non-diagonal
+    gates they commute with: an ansatz layer RY(q) RZ(q) for every qubit
+    becomes all RY then all RZ (one diagonal block), and the order stays
+    equivalent to the circuit's (oracle).  A diagonal gate never passes a
+    pair gate on its own qubit."""
+    n = 8
+    c = W.hea(n, 2, seed=3)
+    order, pass_of, _ = sv.sv_circuit_plan(n, c, nparams=c.nparams, flags=sv.SV_FUSE)
+    kinds = [c.gates[i].kind for i in order]
+    assert len(set(pass_of)) == 1  # n=8 fits one tile: one run
+    # per layer: every RY, then every RZ (one diagonal block), then the CNOT chain
+    assert kinds == (["RY"] * n + ["RZ"] * n + ["X"] * (n - 1)) * 2, kinds
+    for i, gi in enumerate(order):
+        g = c.gates[gi]
+        if g.kind == "RZ":  # its own qubit's RY (the gate before it in the circuit) still comes first
+            assert order.index(gi - 1) < i
+    psi0 = W.random_state(n, 4)
+    ref = oracle.run_circuit(c, c.params, psi0)
+    psi = psi0.copy()
+    for gi in order:
+        g = c.gates[gi]
+        oracle.apply_gate(psi, n, g.target, g.controls, g.values, oracle.gate_matrix(g.kind, c.params[g.param]))
+    assert np.max(np.abs(psi - ref)) < 1e-12
