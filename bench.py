@@ -63,7 +63,7 @@ def load_traffic(kernel, src_hash):
         return None
 
 
-COPY_KERNEL = "sv::k_copy"
+COPY_KERNEL = "sv::k_hbm_probe<double, 0>"  # counter calibration: in-place read-modify-write
 COPY_BYTES = 1 << 30  # read and written per calibration launch
 
 
@@ -154,8 +154,8 @@ def summarize_profile(trace_dir, fetch_dir, write_dir):
           "--warmup 0 --cpu-seconds 0 --no-masked --no-extras --pmc-copy",
           "    rocprofv3 --pmc WRITE_SIZE -f csv -d <write_dir> -o bench -- python3 bench.py --steps 2 "
           "--warmup 0 --cpu-seconds 0 --no-masked --no-extras --pmc-copy", "",
-          "Counters are KiB per dispatch.  Each is scaled by what it reads for the library's plain copy "
-          "kernel `sv::k_copy` moving a known 1 GiB (read 1 GiB, write 1 GiB): FETCH scale %.4f, "
+          "Counters are KiB per dispatch.  Each is scaled by what it reads for the library's HBM probe "
+          "`sv::k_hbm_probe<double, 0>` streaming a known 1 GiB in place (read 1 GiB, write 1 GiB): FETCH scale %.4f, "
           "WRITE scale %.4f." % (f_scale, w_scale), "",
           "- kernel: %s" % kname.replace(" ", "_"),
           "- kernel_source_hash: %s" % src_hash,
@@ -221,7 +221,7 @@ def summarize_positions(fetch_dir, write_dir):
              "--pmc-copy",
              "    rocprofv3 --pmc WRITE_SIZE -f csv -d <write_dir> -o pos -- python3 bench.py --positions-only "
              "--pmc-copy", "",
-             "Counters (KiB per dispatch) are scaled by what they read for the plain copy kernel moving a "
+             "Counters (KiB per dispatch) are scaled by what they read for the HBM probe streaming a "
              "known 1 GiB: FETCH scale %.4f, WRITE scale %.4f.  Algorithmic bytes are the read and write of "
              "every amplitude of a satisfying pair, 2 * 2^(n-c) * 16.  Controls placed on the lowest free "
              "qubits sit below the 128-byte granule (qubits 0-2 of a complex128 index) until c >= 4; "
@@ -243,7 +243,7 @@ def summarize_positions(fetch_dir, write_dir):
 
 
 EXTRAS_TRACE_CMD = ("rocprofv3 --kernel-trace --stats -f csv -d <dir> -o extras -- python3 bench.py --steps 1 "
-                    "--warmup 0 --cpu-seconds 0 --no-masked")
+                    "--warmup 0 --cpu-seconds 0 --no-masked --no-protocol")
 
 
 def summarize_trace(trace_dir):
@@ -268,6 +268,70 @@ def summarize_trace(trace_dir):
             nm, r["Calls"], float(r["TotalDurationNs"]) / 1e6, float(r["AverageNs"]) / 1e3,
             float(r["MinNs"]) / 1e3, float(r["MaxNs"]) / 1e3, float(r["Percentage"])))
     path = os.path.join(ROOT, "profiles", "kernel_trace_bench_extras.md")
+    with open(path, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
+FUSED_ONLY_CMD = "python3 bench.py --fused-only"
+
+
+def run_fused_only(sv, W, torch, np, stream):
+    """One run each of the fused workloads whose kernels the counter
+    profiles cover: the layered circuit at n=28 (5 layers, complex128), QFT29
+    fused (complex128), and the n=24 ansatz forward and adjoint backward."""
+    dev = torch.device("cuda:0")
+    c2 = W.layered_circuit_n32(n=28, layers=5)
+    st = torch.empty(1 << 28, dtype=torch.complex128, device=dev)
+    p = sv.Circuit(28, c2, flags=sv.SV_FUSE)
+    sv.sv_init(st, 0, stream=stream)
+    p.run(st, stream=stream)
+    p.close()
+    del st
+    st = torch.empty(1 << 29, dtype=torch.complex128, device=dev)
+    p = sv.Circuit(29, W.qft(29), flags=sv.SV_FUSE)
+    sv.sv_init(st, 1, stream=stream)
+    p.run(st, stream=stream)
+    p.close()
+    del st
+    c3, H = W.hea_problem_n24()
+    params = torch.from_numpy(c3.params).to(dev)
+    psi = torch.empty(1 << c3.n, dtype=torch.complex128, device=dev)
+    lam = torch.empty_like(psi)
+    plan = sv.Circuit(c3.n, c3, nparams=c3.nparams, flags=sv.SV_FUSE)
+    sv.sv_init(psi, 0, stream=stream)
+    plan.run(psi, params, stream=stream)
+    sv.sv_adjoint_grad(psi, lam, sv.circuit_gates(c3), params, sv.pauli_terms(H), stream=stream)
+    plan.close()
+    torch.cuda.synchronize()
+    print(json.dumps({"fused_only": "done"}), flush=True)
+
+
+def summarize_counters(name, cmd, dirs):
+    """Per-kernel averages of rocprofv3 --pmc counters (one directory per
+    pass) into profiles/counters_<name>.md."""
+    table = {}
+    for d in dirs:
+        acc = {}
+        for r in _read_csv_rows(d, "counter_collection.csv"):
+            k = (r["Kernel_Name"].split("(")[0].replace("void ", ""), r["Counter_Name"])
+            key = (k, int(r["Dispatch_Id"]))
+            acc[key] = acc.get(key, 0.0) + float(r["Counter_Value"])
+        for ((kern, ctr), _), v in acc.items():
+            table.setdefault(kern, {}).setdefault(ctr, []).append(v)
+    ctrs = sorted({c for k in table.values() for c in k})
+    lines = ["# Counters: %s" % name, "", "Commands (one pass each, from the repository root):", ""]
+    lines += ["    " + c for c in cmd]
+    lines += ["", "Average per dispatch over the dispatches of each kernel (sums over the rows rocprofv3 writes "
+              "for one dispatch).", "", "| kernel | dispatches | " + " | ".join(ctrs) + " |",
+              "|---|---|" + "---|" * len(ctrs)]
+    for kern in sorted(table, key=lambda k: -max(len(v) for v in table[k].values())):
+        vals = table[kern]
+        nd = max(len(v) for v in vals.values())
+        nm = kern if len(kern) <= 90 else kern[:87] + "..."
+        lines.append("| `%s` | %d | " % (nm, nd) + " | ".join(
+            ("%.4g" % (sum(vals[c]) / len(vals[c]))) if c in vals else "-" for c in ctrs) + " |")
+    path = os.path.join(ROOT, "profiles", "counters_%s.md" % name)
     with open(path, "w") as fh:
         fh.write("\n".join(lines) + "\n")
     print("\n".join(lines))
@@ -336,7 +400,7 @@ MALL_ROTATE_BYTES = 512 << 20  # twice the 256 MB Infinity Cache
 
 
 def graph_protocol(sv, torch, np, st, n, cases, U, stream, amp_bytes=AMP_BYTES, target_ms=30.0, trials=5,
-                   modes=("auto", "masked")):
+                   modes=("auto", "masked", "probe")):
     """Per (target, controls) and kernel form: R back-to-back launches of the
     gate captured once as a HIP graph and replayed, median of `trials`
     replays after one warm-up, R chosen so that a replay lasts about
@@ -345,7 +409,10 @@ def graph_protocol(sv, torch, np, st, n, cases, U, stream, amp_bytes=AMP_BYTES, 
     touches amplitudes disjoint from the previous K - 1 and the 256 MB
     Infinity Cache cannot serve them; the kernels do the same work for any
     control values (the values are only the fixed bits of the index
-    expansion).  Both forms use the same launch machinery."""
+    expansion).  Both forms use the same launch machinery.  Mode "probe"
+    streams the HBM probe over the same address set (the scheduled controls
+    fixed, the rest of each cache line included) with the same rotation: the
+    bandwidth that set can reach with no gate arithmetic."""
     rows = []
     for t, ctrls in cases:
         c = len(ctrls)
@@ -355,14 +422,22 @@ def graph_protocol(sv, torch, np, st, n, cases, U, stream, amp_bytes=AMP_BYTES, 
         vals = [_deposit((1 << c) - 1 - r, cm) for r in range(K)]
         alg = 2 * touched
         row = {"t": t, "c": c, "K_vals": K}
+        gb = sv.sv_tune_get("granule_bits_c128" if amp_bytes == 16 else "granule_bits_c64")
+        pm = cm & ~((1 << gb) - 1)  # the controls the kernel schedules; lower ones are rewritten
+
+        def launch(mode, r):
+            if mode == "probe":
+                sv.sv_hbm_probe(st, pm, vals[r] & pm, "rmw", stream=stream)
+            else:
+                sv.sv_apply_gate_masks(st, t, cm, vals[r], U, mode=mode, stream=stream)
         for mode in modes:
             with torch.cuda.stream(stream):
                 e0 = torch.cuda.Event(enable_timing=True)
                 e1 = torch.cuda.Event(enable_timing=True)
-                sv.sv_apply_gate_masks(st, t, cm, vals[0], U, mode=mode, stream=stream)
+                launch(mode, 0)
                 e0.record(stream)
                 for r in range(K):
-                    sv.sv_apply_gate_masks(st, t, cm, vals[r], U, mode=mode, stream=stream)
+                    launch(mode, r)
                 e1.record(stream)
             torch.cuda.synchronize()
             est = max(e0.elapsed_time(e1) / K, 1e-3)
@@ -371,7 +446,7 @@ def graph_protocol(sv, torch, np, st, n, cases, U, stream, amp_bytes=AMP_BYTES, 
             g = torch.cuda.CUDAGraph()
             with torch.cuda.graph(g, stream=stream):
                 for r in range(R):
-                    sv.sv_apply_gate_masks(st, t, cm, vals[r % K], U, mode=mode, stream=stream)
+                    launch(mode, r % K)
             ts = []
             with torch.cuda.stream(stream):
                 g.replay()
@@ -386,13 +461,16 @@ def graph_protocol(sv, torch, np, st, n, cases, U, stream, amp_bytes=AMP_BYTES, 
                     ts.append(a.elapsed_time(b) / R)
             del g
             med = float(np.median(ts))
-            key = "sched" if mode == "auto" else "masked"
+            key = {"auto": "sched", "masked": "masked", "probe": "probe"}[mode]
+            byts = 2 * (1 << (n - bin(pm).count("1"))) * amp_bytes if mode == "probe" else alg
             row[key + "_R"] = R
             row[key + "_us"] = round(med * 1e3, 2)
-            row[key + "_GBps"] = round(alg / med / 1e6, 1)
-            row[key + "_frac"] = round(alg / med / 1e6 / HBM_PEAK_GBPS, 3)
+            row[key + "_GBps"] = round(byts / med / 1e6, 1)
+            row[key + "_frac"] = round(byts / med / 1e6 / HBM_PEAK_GBPS, 3)
         if "sched_us" in row and "masked_us" in row:
             row["masked_over_sched"] = round(row["masked_us"] / row["sched_us"], 2)
+        if "sched_us" in row and "probe_us" in row:
+            row["sched_over_probe"] = round(row["sched_us"] / row["probe_us"], 3)
         rows.append(row)
     return rows
 
@@ -403,9 +481,33 @@ def protocol_summary(rows):
     for r in rows:
         by.setdefault(r["c"], []).append(r)
     out = {"c": sorted(by)}
-    for k in ("sched_frac", "masked_frac", "masked_over_sched", "sched_us"):
+    for k in ("sched_frac", "masked_frac", "masked_over_sched", "sched_us", "probe_frac", "sched_over_probe"):
         if all(k in r for r in rows):
             out[k] = [round(float(sum(r[k] for r in by[c]) / len(by[c])), 3) for c in out["c"]]
+    return out
+
+
+def hbm_ceiling(sv, torch, np, st, stream, reps=10, trials=5):
+    """HBM probe over the whole state: in-place read-modify-write and
+    read-only passes, reps back-to-back launches per HIP-event pair, median
+    of trials (after one warm-up)."""
+    nbytes = st.numel() * st.element_size()
+    out = {}
+    for op, mult in (("rmw", 2), ("read", 1)):
+        ts = []
+        with torch.cuda.stream(stream):
+            sv.sv_hbm_probe(st, 0, 0, op, stream=stream)
+            torch.cuda.synchronize()
+            for _ in range(trials):
+                a = torch.cuda.Event(enable_timing=True)
+                b = torch.cuda.Event(enable_timing=True)
+                a.record(stream)
+                for _ in range(reps):
+                    sv.sv_hbm_probe(st, 0, 0, op, stream=stream)
+                b.record(stream)
+                torch.cuda.synchronize()
+                ts.append(a.elapsed_time(b) / reps)
+        out[op + "_GBps"] = round(mult * nbytes / float(np.median(ts)) / 1e6, 1)
     return out
 
 
@@ -596,6 +698,26 @@ def measure_fixed_point(sv, W, torch, np, stream, psi_host, cases, U, energy):
     return out
 
 
+def batch_occupancy(np, st, ns_tick, ns, workgroups):
+    """From per-circuit [start, end] clock stamps of one persistent batched
+    run: the run's span, the mean number of workgroups busy with a circuit
+    over the span against the workgroups launched, the longest circuit, and
+    per width n the count and mean/max time per circuit."""
+    t0, t1 = st[0::2].astype(np.float64), st[1::2].astype(np.float64)
+    span = (t1.max() - t0.min()) * ns_tick * 1e-6
+    busy = (t1 - t0) * ns_tick * 1e-6
+    per = {}
+    for n in sorted(set(ns)):
+        sel = np.array(ns) == n
+        per[str(n)] = [int(sel.sum()), round(float(busy[sel].mean()), 4), round(float(busy[sel].max()), 4)]
+    last_start = (t0.max() - t0.min()) * ns_tick * 1e-6
+    return {"span_ms": round(span, 3), "workgroups": workgroups,
+            "mean_busy_workgroups": round(float(busy.sum() / span), 1),
+            "utilisation": round(float(busy.sum() / span / workgroups), 3),
+            "longest_circuit_ms": round(float(busy.max()), 3), "last_start_ms": round(last_start, 3),
+            "per_n_count_mean_max_ms": per}
+
+
 def measure_extras(sv, W, torch, np, stream, with_layered, psi_host=None, cases=None, U=None):
     """Adjoint gradients (n=24 ansatz), batched circuits (4096 uneven circuits), the paper's
     QFT and streaming circuits at 29 qubits, fixed-point states, and optionally the
@@ -650,13 +772,23 @@ def measure_extras(sv, W, torch, np, stream, with_layered, psi_host=None, cases=
         sv.sv_apply_circuits_batched(views, circs, stream=stream)
         torch.cuda.synchronize()
         t_once = (time.perf_counter() - t0) * 1e3
+        # per-circuit device clock stamps of one more run: time per circuit
+        # width, and how busy the persistent workgroups are over the run
+        stamps = torch.zeros(2 * len(circs), dtype=torch.int64, device=dev)
+        ns_tick = batch.set_timing(stamps)
+        batch.run(stream=stream)
+        torch.cuda.synchronize()
+        batch.set_timing(None)
+        occ = batch_occupancy(np, stamps.cpu().numpy(), ns_tick, ns,
+                              2 * torch.cuda.get_device_properties(0).multi_processor_count)
         ngates = sum(len(c.gates) for c in circs)
         alg = sum(len(c.gates) * (1 << c.n) * 2 * (16 if dt == "c128" else 8) for c in circs)
         out["batched_uneven4096_" + dt] = {"circuits": len(circs), "gates": ngates, "ms": round(t_b4, 2),
                                         "circuits_per_s": round(len(circs) * 1e3 / t_b4, 1),
                                         "gate_updates_per_s": round(ngates * 1e3 / t_b4, 1),
                                         "unfused_equivalent_GBps": round(alg / t_b4 / 1e6, 1),
-                                        "plan_ms": round(t_create, 1), "one_shot_ms": round(t_once, 1)}
+                                        "plan_ms": round(t_create, 1), "one_shot_ms": round(t_once, 1),
+                                        "occupancy": occ}
         batch.close()
         del buf, views
         torch.cuda.empty_cache()
@@ -685,9 +817,18 @@ def measure_extras(sv, W, torch, np, stream, with_layered, psi_host=None, cases=
 
     t_bf = _time_ms(torch, stream, bfwd, 3)
     t_bb = _time_ms(torch, stream, bboth, 3) - t_bf
+    stamps = torch.zeros(2 * len(circs), dtype=torch.int64, device=dev)
+    with torch.cuda.stream(stream):
+        bfwd()
+        ns_tick = hbatch.set_timing(stamps)  # stamps of the adjoint run only
+        hbatch.adjoint(bparams, grad=bgrad, loss=bloss, stream=stream)
+    torch.cuda.synchronize()
+    hbatch.set_timing(None)
+    occ = batch_occupancy(np, stamps.cpu().numpy(), ns_tick, [16] * len(circs),
+                          2 * torch.cuda.get_device_properties(0).multi_processor_count)
     out["batched_adjoint_hea256_n16"] = {"circuits": len(circs), "n": 16, "params_each": circs[0].nparams,
                                       "forward_ms": round(t_bf, 2), "backward_ms": round(t_bb, 2),
-                                      "gradients_per_s": round(len(circs) * 1e3 / t_bb, 1)}
+                                      "gradients_per_s": round(len(circs) * 1e3 / t_bb, 1), "occupancy": occ}
     hbatch.close()
     del buf, lbuf, views, lviews
     torch.cuda.empty_cache()
@@ -835,8 +976,8 @@ def main():
                     help="time budget of the CPU-oracle baseline sample (0 disables it)")
     ap.add_argument("--no-masked", action="store_true", help="skip the masked-baseline sweep")
     ap.add_argument("--pmc-copy", action="store_true",
-                    help="first copy a 1 GiB state three times with the library's plain copy kernel "
-                         "(calibration of the rocprofv3 byte counters)")
+                    help="first stream the HBM probe three times over a 1 GiB state, read and written in "
+                         "place (calibration of the rocprofv3 byte counters)")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the adjoint, batched and paper-circuit measurements")
     ap.add_argument("--no-protocol", action="store_true",
@@ -854,11 +995,22 @@ def main():
                          "--positions-only and exit")
     ap.add_argument("--detail-out", default=os.path.join(ROOT, "gpurun_out", "bench_detail.json"),
                     help="file receiving the per-row tables and extra measurements as JSON ('' disables)")
+    ap.add_argument("--fused-only", action="store_true",
+                    help="run once each the fused layered circuit (n=28), QFT29 and the n=24 adjoint, for counters")
+    ap.add_argument("--summarize-counters", nargs="+", metavar="ARG",
+                    help="NAME CMDFILE DIR...: per-kernel averages of rocprofv3 --pmc passes into "
+                         "profiles/counters_NAME.md (CMDFILE: the commands, one per line)")
     ap.add_argument("--summarize-trace", metavar="TRACE_DIR",
                     help="write the all-kernel summary of a full run from rocprofv3 --kernel-trace output and exit")
     args = ap.parse_args()
     if args.summarize_trace:
         summarize_trace(args.summarize_trace)
+        return
+    if args.summarize_counters:
+        name, cmdfile, *dirs = args.summarize_counters
+        with open(cmdfile) as fh:
+            cmds = [l.strip() for l in fh if l.strip()]
+        summarize_counters(name, cmds, dirs)
         return
     if args.summarize_profile:
         summarize_profile(*args.summarize_profile)
@@ -879,6 +1031,9 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
+    if args.fused_only:
+        run_fused_only(sv, W, torch, np, torch.cuda.Stream(device=dev))
+        return
     n = N_QUBITS
     log("generating n=%d input state" % n)
     psi_host = W.random_state(n, seed=1)
@@ -892,11 +1047,10 @@ def main():
     stream = torch.cuda.Stream(device=dev)  # default priority
     if args.pmc_copy:
         a = torch.zeros(1 << 26, dtype=torch.complex128, device=dev)  # 1 GiB
-        b = torch.empty_like(a)
         for _ in range(3):
-            sv.sv_copy_state(b, a, stream=stream)
+            sv.sv_hbm_probe(a, 0, 0, "rmw", stream=stream)
         torch.cuda.synchronize()
-        del a, b
+        del a
 
     if args.positions_only:
         rows = control_position_sweep(sv, torch, np, d, U, stream, n, reps=1)
@@ -944,6 +1098,10 @@ def main():
         return total_ms, per, step_ms
 
     torch.cuda.synchronize()
+    ceiling = {"rmw_GBps": None, "read_GBps": None}
+    if not args.pmc_copy:  # under the byte counters the probe is the calibration only
+        log("HBM probe over the 4 GiB state")
+        ceiling = hbm_ceiling(sv, torch, np, d, stream)
     log("scheduled sweep: %d warmup + %d timed steps of %d gates" % (args.warmup, args.steps, len(cases)))
     total_ms, per, step_ms = sweep("auto", args.steps, args.warmup)
     masked_total, per_m = (None, None)
@@ -986,6 +1144,8 @@ def main():
     traffic = load_traffic(dom, src_hash)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic,
+                "probe_rmw_GBps": ceiling["rmw_GBps"], "probe_read_GBps": ceiling["read_GBps"],
+                "frac_of_probe": round(achieved / ceiling["rmw_GBps"], 3) if ceiling["rmw_GBps"] else None,
                 "kernel": dom, "avg_launch_us": round(avg_ms * 1e3, 2),
                 "alg_bytes_per_launch": avg_bytes, "launches": ks["launches"],
                 "kernel_source_hash": src_hash}
@@ -1039,6 +1199,7 @@ def main():
         summary_by_c["graph_frac"] = ps.get("sched_frac")
         summary_by_c["graph_masked_frac"] = ps.get("masked_frac")
         summary_by_c["graph_masked_over_sched"] = ps.get("masked_over_sched")
+        summary_by_c["graph_probe_frac"] = ps.get("probe_frac")
     if protocol32:
         ps = protocol_summary(protocol32)
         summary_by_c["n32_graph_frac"] = ps.get("sched_frac")
@@ -1071,7 +1232,7 @@ def main():
                    "n": n, "gates_per_step": len(cases), "seeds": [1, 2, 3]},
         "hbm_GBps_alg": round(alg_total / total_ms / 1e6, 1),
         "roofline": {k: roofline[k] for k in ("bound", "achieved", "peak", "unit", "frac", "traffic", "kernel",
-                                              "avg_launch_us")},
+                                              "avg_launch_us", "probe_rmw_GBps", "frac_of_probe")},
         "cpu_baseline": cpu,
         "masked_value": None if masked_total is None else round(ngates / (masked_total / 1e3), 2),
         "by_c": summary_by_c,
@@ -1079,7 +1240,8 @@ def main():
         "detail": detail_path,
     }
     line = json.dumps(out, separators=(",", ":"))
-    for k in ("graph_masked_frac", "n32_graph_masked_over_sched", "eager_frac", "graph_masked_over_sched"):
+    for k in ("graph_masked_frac", "graph_probe_frac", "n32_graph_masked_over_sched", "eager_frac",
+              "graph_masked_over_sched"):
         if len(line) <= 2000:  # keep the last line short enough for any log tail
             break
         out["by_c"].pop(k, None)

@@ -168,6 +168,16 @@ int sv_gate_plan(int n, int dtype, int target, uint64_t ctrl_mask,
                  uint64_t ctrl_vals, int mode, char *kernel, int kernel_len,
                  uint64_t *iterations);
 
+/* Measurement helper (not part of the method): stream over the amplitudes
+ * whose index bits match fixed_vals on fixed_mask (all amplitudes for mask
+ * 0), with the access pattern of the scheduled gate kernels and no
+ * arithmetic.  It measures the HBM bandwidth a gate's own address set can
+ * reach and is a kernel of known traffic for calibrating profiler byte
+ * counters.  op: 0 reads and writes back every selected amplitude (values
+ * unchanged), 1 reads only (the state is unchanged), 2 writes zeros to the
+ * selected amplitudes.  complex128 and complex64 states. */
+int sv_hbm_probe(const sv_state_t *s, uint64_t fixed_mask, uint64_t fixed_vals, int op, sv_stream_t st);
+
 /* Launch-choice knobs shared by every call of the process (not per device).
  * Keys and ranges:
  *   "granule_bits_c128", "granule_bits_c64"  [0, 6]  controls on index bits
@@ -184,8 +194,19 @@ int sv_gate_plan(int n, int dtype, int target, uint64_t ctrl_mask,
  *   "fuse_min_gates"  [1, 2^20]  shortest gate run fused into one LDS pass
  *   "dense_qubits"    [4, 5]  k of dense blocks (SV_DENSE)
  *   "dense_min_gates" [1, 2^20]  shortest stretch made a dense block
- * None of them changes results.  SV_EINVAL for an unknown key or a value out
- * of range.  Not thread-safe against concurrent launches. */
+ *   "pair_unroll"     1 or 4  pairs (or 64-amplitude wavefronts) per lane in
+ *       large launches of the scheduled pair and wavefront kernels
+ *   "masked_unroll"   1 or 4  the same for the masked baseline kernel
+ *   "masked_block"    64 or 256  lanes per workgroup of the masked kernel
+ *   "fuse_group"      [0, 1]  inside a fused run, move diagonal gates past
+ *       gates they commute with so that they form blocks (one sweep each)
+ *   "fuse_pairs"      [0, 1]  apply two adjacent pair gates of a fused run
+ *       together over 4-amplitude cosets when each one's tile-local controls
+ *       lie only on the other's target
+ * None of them changes results beyond floating-point rounding (fusion
+ * choices change the order in which commuting operations are rounded).
+ * SV_EINVAL for an unknown key or a value out of range.  Not thread-safe
+ * against concurrent launches. */
 int sv_tune_set(const char *key, int64_t value);
 int sv_tune_get(const char *key, int64_t *value);
 
@@ -368,7 +389,9 @@ int sv_apply_pauli_sum(const sv_state_t *in, const sv_state_t *out, const sv_pau
  *             un-applying every gate (the forward state is consumed)
  *   lam       workspace state of the same n and dtype (overwritten)
  *   gates     the circuit as given to sv_circuit_create; only RX/RY/RZ/P
- *             gates with param >= 0 are differentiated
+ *             gates with param >= 0 are differentiated; every SV_G_MATRIX
+ *             gate must be unitary to 1e-12 (the sweep un-applies each gate
+ *             by its conjugate transpose), SV_EINVAL otherwise
  *   params_dev device array of nparams angles
  *   grad_dev  device array of nparams doubles, overwritten with dL/dtheta_j
  *             (summed over every gate using parameter j; 0 for unused ones),
@@ -434,6 +457,15 @@ int sv_batch_create(const sv_state_t *states, const sv_state_t *lam_states, int 
 int sv_batch_run(sv_batch_t *b, const double *params_dev, sv_stream_t st);
 int sv_batch_adjoint(sv_batch_t *b, const double *params_dev, double *grad_dev, double *loss_dev, sv_stream_t st);
 int sv_batch_destroy(sv_batch_t *b);
+
+/* Measurement helper: with stamps_dev not NULL, every later sv_batch_run and
+ * sv_batch_adjoint of b writes for each circuit c the device's constant-rate
+ * clock when a workgroup starts it (stamps_dev[2c]) and when that workgroup
+ * has finished it (stamps_dev[2c + 1]); stamps_dev holds 2 * ncirc uint64
+ * values on the batch's device and must outlive those runs.  NULL turns the
+ * stamps off.  ns_per_tick (may be NULL) receives the clock period in
+ * nanoseconds.  Results of the runs are unchanged. */
+int sv_batch_set_timing(sv_batch_t *b, uint64_t *stamps_dev, double *ns_per_tick);
 
 /* Write, for each reduced iteration index i_r in [0, 2^(n-1-ncontrols)), the
  * index of the first pair element (bit target clear) that the scheduled

@@ -1,6 +1,7 @@
 """Binding of the batched entry points (sv_apply_circuits_batched,
 sv_adjoint_grad_batched, and the planned batch sv_batch_create / sv_batch_run /
-sv_batch_adjoint / sv_batch_destroy).  Argument marshalling only."""
+sv_batch_adjoint / sv_batch_set_timing / sv_batch_destroy).  Argument
+marshalling only."""
 from __future__ import annotations
 
 import ctypes
@@ -15,6 +16,7 @@ _sig("sv_apply_circuits_batched", [ctypes.POINTER(sv_state_t), ctypes.c_int, cty
 _sig("sv_adjoint_grad_batched", [ctypes.POINTER(sv_state_t), ctypes.POINTER(sv_state_t), ctypes.c_int,
                                  ctypes.POINTER(sv_gate_t), _i64p, _vp, _i64p, ctypes.c_int64,
                                  ctypes.POINTER(sv_pauli_t), _i64p, _vp, _vp, _vp])
+_sig("sv_batch_set_timing", [_vp, _vp, ctypes.POINTER(ctypes.c_double)])
 _sig("sv_batch_create", [ctypes.POINTER(sv_state_t), ctypes.POINTER(sv_state_t), ctypes.c_int,
                          ctypes.POINTER(sv_gate_t), _i64p, _i64p, ctypes.c_int64, ctypes.POINTER(sv_pauli_t), _i64p,
                          ctypes.POINTER(_vp)])
@@ -124,6 +126,16 @@ class Batch:
         _check(_L.sv_batch_adjoint(self._h, ctypes.c_void_p(params.data_ptr()), ctypes.c_void_p(grad.data_ptr()),
                                    ctypes.c_void_p(loss.data_ptr()), stream_ptr(stream)))
         return grad[:self.nparams_total], loss
+
+    def set_timing(self, stamps=None) -> float:
+        """Per-circuit start/end clock stamps of later runs into the device
+        uint64 (or int64) tensor stamps (2 * ncirc values; None turns them
+        off).  Returns the clock period in nanoseconds."""
+        ns = ctypes.c_double(0.0)
+        p = ctypes.c_void_p(0 if stamps is None else stamps.data_ptr())
+        _check(_L.sv_batch_set_timing(self._h, p, ctypes.byref(ns)))
+        self._stamps = stamps
+        return ns.value
 
     def close(self) -> None:
         if getattr(self, "_h", None):

@@ -33,6 +33,7 @@
 namespace sv {
 
 int validate_circuit_gate(int n, int nparams, const sv_gate_t &g, int index);
+int validate_unitary_gate(const sv_gate_t &g, int index);
 
 constexpr int kBatchThreads = 512;
 constexpr size_t kBatchLds = 65536;  // the tile (or a whole resident state)
@@ -218,7 +219,8 @@ __global__ __launch_bounds__(kBatchThreads) void k_batched(const BCirc *__restri
                                                            const BPass *__restrict__ passes,
                                                            const TileGate *__restrict__ tiles,
                                                            const double *__restrict__ params,
-                                                           unsigned int *__restrict__ queue) {
+                                                           unsigned int *__restrict__ queue,
+                                                           uint64_t *__restrict__ stamps) {
     extern __shared__ unsigned char lds_raw[];
     int *item = reinterpret_cast<int *>(lds_raw);
     cplx_t<R> *lds = reinterpret_cast<cplx_t<R> *>(lds_raw + kBatchSlot);
@@ -230,8 +232,13 @@ __global__ __launch_bounds__(kBatchThreads) void k_batched(const BCirc *__restri
         __syncthreads();
         if (it >= ncirc)
             break;
+        const uint64_t t0 = stamps ? wall_clock64() : 0;
         run_circuit_block<R>(circs[order[it]], gates, passes, tiles, params, lds);
         __syncthreads();
+        if (stamps && threadIdx.x == 0) {
+            stamps[2 * order[it]] = t0;
+            stamps[2 * order[it] + 1] = wall_clock64();
+        }
     }
 }
 
@@ -368,7 +375,7 @@ __global__ __launch_bounds__(kBatchThreads) void k_batched_adjoint(
     const BPass *__restrict__ apasses, const TileGate *__restrict__ atiles, const int32_t *__restrict__ atslot,
     const int32_t *__restrict__ slot_param, const double *__restrict__ params, const DTerm *__restrict__ terms,
     const double *__restrict__ gens, const int32_t *__restrict__ gen_of, double *__restrict__ grad,
-    double *__restrict__ loss, unsigned int *__restrict__ queue) {
+    double *__restrict__ loss, unsigned int *__restrict__ queue, uint64_t *__restrict__ stamps) {
     extern __shared__ unsigned char lds_raw[];  // psi and lambda tiles, then gradient accumulators
     __shared__ double scratch[kBatchThreads / 64];
     __shared__ int item;
@@ -381,9 +388,14 @@ __global__ __launch_bounds__(kBatchThreads) void k_batched_adjoint(
         if (it >= ncirc)
             break;
         const int ci = order[it];
+        const uint64_t t0 = stamps ? wall_clock64() : 0;
         adjoint_block<R>(circs[ci], gates, apasses, atiles, atslot, slot_param, params, terms, gens, gen_of, grad,
                          loss + ci, scratch, lds_raw);
         __syncthreads();
+        if (stamps && threadIdx.x == 0) {
+            stamps[2 * ci] = t0;
+            stamps[2 * ci + 1] = wall_clock64();
+        }
     }
 }
 
@@ -442,8 +454,11 @@ static int build_circuit(const BatchArgs &A, int c, int dtype, bool adjoint, Cir
     bc.first_param = (int32_t)p0;
     bc.nparams = (int32_t)(p1 - p0);
     if (bc.ngates > 0) {
-        for (int64_t i = g0; i < g1; ++i)
+        for (int64_t i = g0; i < g1; ++i) {
             SV_TRY(validate_circuit_gate(s.n, (int)(p1 - p0), A.gates[i], (int)(i - g0)));
+            if (adjoint)
+                SV_TRY(validate_unitary_gate(A.gates[i], (int)(i - g0)));
+        }
         const bool resident = ((size_t)1 << s.n) * amp_bytes(dtype) <= kBatchLds;
         if (!adjoint && !resident) {
             std::vector<PlanPass> pp;
@@ -818,7 +833,8 @@ static unsigned persistent_grid(int ncirc) {
     return std::min<unsigned>(g, (unsigned)ncirc);
 }
 
-static int launch_forward(int dtype, const BatchDevice &d, int ncirc, const double *params, hipStream_t s) {
+static int launch_forward(int dtype, const BatchDevice &d, int ncirc, const double *params, hipStream_t s,
+                          uint64_t *stamps = nullptr) {
     hipError_t a = dtype == SV_C128 ? hipFuncSetAttribute((const void *)k_batched<double>,
                                                           hipFuncAttributeMaxDynamicSharedMemorySize,
                                                           (int)kBatchDynLds)
@@ -834,10 +850,10 @@ static int launch_forward(int dtype, const BatchDevice &d, int ncirc, const doub
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, s, d.queue);
     if (dtype == SV_C128)
         hipLaunchKernelGGL(k_batched<double>, dim3(grid), dim3(kBatchThreads), kBatchDynLds, s, d.circs, d.order,
-                           ncirc, d.gates, d.passes, d.tiles, params, d.queue);
+                           ncirc, d.gates, d.passes, d.tiles, params, d.queue, stamps);
     else
         hipLaunchKernelGGL(k_batched<float>, dim3(grid), dim3(kBatchThreads), kBatchDynLds, s, d.circs, d.order,
-                           ncirc, d.gates, d.passes, d.tiles, params, d.queue);
+                           ncirc, d.gates, d.passes, d.tiles, params, d.queue, stamps);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess)
         return fail(SV_EHIP, "batched launch failed: %s", hipGetErrorString(e));
@@ -845,7 +861,7 @@ static int launch_forward(int dtype, const BatchDevice &d, int ncirc, const doub
 }
 
 static int launch_adjoint(int dtype, const BatchDevice &d, int ncirc, const double *params, double *grad,
-                          double *loss, hipStream_t s) {
+                          double *loss, hipStream_t s, uint64_t *stamps = nullptr) {
     constexpr size_t kLdsPerWorkgroup = 160 * 1024;  // gfx950, with the opt-in limit raised
     const size_t lds = std::max<size_t>(d.adj_lds, 8);
     if (lds + 1024 > kLdsPerWorkgroup)
@@ -864,11 +880,11 @@ static int launch_adjoint(int dtype, const BatchDevice &d, int ncirc, const doub
     if (dtype == SV_C128)
         hipLaunchKernelGGL(k_batched_adjoint<double>, dim3(grid), dim3(kBatchThreads), lds, s, d.circs, d.order, ncirc,
                            d.gates, d.apasses, d.atiles, d.atslot, d.slot_param, params, d.terms, d.gens, d.gen_of,
-                           grad, loss, d.queue);
+                           grad, loss, d.queue, stamps);
     else
         hipLaunchKernelGGL(k_batched_adjoint<float>, dim3(grid), dim3(kBatchThreads), lds, s, d.circs, d.order, ncirc,
                            d.gates, d.apasses, d.atiles, d.atslot, d.slot_param, params, d.terms, d.gens, d.gen_of,
-                           grad, loss, d.queue);
+                           grad, loss, d.queue, stamps);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess)
         return fail(SV_EHIP, "batched adjoint launch failed: %s", hipGetErrorString(e));
@@ -884,6 +900,7 @@ struct sv_batch {
     bool has_adjoint = false;
     sv::BatchDevice fwd, adj;
     hipEvent_t done = nullptr;  // end of the last run
+    uint64_t *stamps = nullptr; // per-circuit start/end clock of later runs (measurement), or none
 };
 
 using namespace sv;
@@ -946,7 +963,7 @@ static int batch_done(sv_batch_t *b, hipStream_t st) {
 int sv_batch_run(sv_batch_t *b, const double *params_dev, sv_stream_t st) {
     clear_error();
     SV_TRY(batch_check(b, params_dev));
-    SV_TRY(launch_forward(b->dtype, b->fwd, b->ncirc, params_dev, (hipStream_t)st));
+    SV_TRY(launch_forward(b->dtype, b->fwd, b->ncirc, params_dev, (hipStream_t)st, b->stamps));
     return batch_done(b, (hipStream_t)st);
 }
 
@@ -957,8 +974,23 @@ int sv_batch_adjoint(sv_batch_t *b, const double *params_dev, double *grad_dev, 
         return fail(SV_EINVAL, "batch was created without lambda states and terms");
     if (!grad_dev || !loss_dev)
         return fail(SV_EINVAL, "grad_dev and loss_dev are required");
-    SV_TRY(launch_adjoint(b->dtype, b->adj, b->ncirc, params_dev, grad_dev, loss_dev, (hipStream_t)st));
+    SV_TRY(launch_adjoint(b->dtype, b->adj, b->ncirc, params_dev, grad_dev, loss_dev, (hipStream_t)st, b->stamps));
     return batch_done(b, (hipStream_t)st);
+}
+
+int sv_batch_set_timing(sv_batch_t *b, uint64_t *stamps_dev, double *ns_per_tick) {
+    clear_error();
+    if (!b)
+        return fail(SV_EINVAL, "batch is NULL");
+    b->stamps = stamps_dev;
+    if (ns_per_tick) {
+        int khz = 0;
+        SV_HIP_TRY(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, b->device));
+        if (khz <= 0)
+            return fail(SV_EHIP, "device reports no constant-rate clock");
+        *ns_per_tick = 1e6 / (double)khz;
+    }
+    return SV_OK;
 }
 
 int sv_batch_destroy(sv_batch_t *b) {
