@@ -39,7 +39,7 @@ def log(*a):
 
 def kernel_source_hash():
     h = hashlib.sha1()
-    for f in ("gate_kernels.hip", "gate_math.hpp", "sv_internal.hpp", "tile.hpp"):
+    for f in ("gate_kernels.hip", "gate_math.hpp", "sv_internal.hpp"):  # the sources of k_pair and k_wave
         with open(os.path.join(ROOT, "paper_2411_18354_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:12]
