@@ -742,18 +742,27 @@ def measure_extras(sv, W, torch, np, stream, with_layered, psi_host=None, cases=
         plan.run(psi, params, stream=stream)
         sv.sv_expect(psi, terms, out=loss, stream=stream)
 
+    aplan = sv.AdjointPlan(c3.n, gates, terms, c3.nparams)
+
     def bwd():
+        sv.sv_copy_state(work, psi, stream=stream)
+        aplan.run(work, lam, params, grad=grad, stream=stream)
+
+    def bwd_once():
         sv.sv_copy_state(work, psi, stream=stream)
         sv.sv_adjoint_grad(work, lam, gates, params, terms, grad=grad, stream=stream)
 
     t_f = _time_ms(torch, stream, fwd, 5)
     t_b = _time_ms(torch, stream, bwd, 5)
+    t_b1 = _time_ms(torch, stream, bwd_once, 5)
     out["adjoint_hea_n24"] = {
         "n": c3.n, "params": c3.nparams, "gates": len(c3.gates), "forward_ms": round(t_f, 3),
         "backward_ms": round(t_b, 3), "backward_over_forward": round(t_b / t_f, 2),
+        "backward_one_shot_ms": round(t_b1, 3),
         "gradients_per_s": round(1e3 / t_b, 3), "param_derivatives_per_s": round(c3.nparams * 1e3 / t_b, 1),
         "forward_passes": plan.info()["passes"]}
     plan.close()
+    aplan.close()
     del psi, work, lam
     torch.cuda.empty_cache()
     # ---- batched: 4096 uneven circuits forward (complex128 and complex64) and batched adjoint

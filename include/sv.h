@@ -402,6 +402,23 @@ int sv_adjoint_grad(const sv_state_t *psi, const sv_state_t *lam, const sv_gate_
                     const double *params_dev, int nparams, const sv_pauli_t *terms, int nterms, double *grad_dev,
                     double *loss_dev, const double *scale_dev, sv_stream_t st);
 
+/* A planned adjoint gradient, for differentiating the same circuit and
+ * Hamiltonian many times (new angles, new states): sv_adjoint_create
+ * validates the gates (as sv_adjoint_grad does, unitarity of fixed matrices
+ * included) and the terms, plans the reverse sweep and uploads its tables to
+ * the current device; sv_adjoint_run then enqueues exactly the work of
+ * sv_adjoint_grad for states of that n and dtype (arguments as there; psi is
+ * consumed), with no host planning and no allocation.  Runs of one plan
+ * share its reduction buffers: enqueue them on one stream (or order them).
+ * sv_adjoint_destroy waits for the device, then frees the plan; NULL is a
+ * no-op. */
+typedef struct sv_adjoint sv_adjoint_t;
+int sv_adjoint_create(int n, int dtype, const sv_gate_t *gates, int ngates, int nparams, const sv_pauli_t *terms,
+                      int nterms, sv_adjoint_t **out);
+int sv_adjoint_run(sv_adjoint_t *plan, const sv_state_t *psi, const sv_state_t *lam, const double *params_dev,
+                   double *grad_dev, double *loss_dev, const double *scale_dev, sv_stream_t st);
+int sv_adjoint_destroy(sv_adjoint_t *plan);
+
 /* ------------------------------------------------------------------ batches
  *
  * Many independent circuits, each on its own state (n may differ; one dtype

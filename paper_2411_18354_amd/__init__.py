@@ -516,5 +516,5 @@ def sv_apply_dense_low(state, k: int, M, stream=None) -> None:
 
 
 from .observables import (sv_pauli_t, pauli_terms, sv_expect, sv_expect_noalloc, sv_expect_terms,  # noqa: E402
-                          sv_apply_pauli_sum, sv_adjoint_grad, SvExpectation, ExpectationModel)
+                          sv_apply_pauli_sum, sv_adjoint_grad, AdjointPlan, SvExpectation, ExpectationModel)
 from .batched import sv_apply_circuits_batched, sv_adjoint_grad_batched, Batch  # noqa: E402

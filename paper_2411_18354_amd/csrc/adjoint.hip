@@ -79,8 +79,10 @@ __global__ __launch_bounds__(kRedThreads) void k_adj(cplx_t<R> *__restrict__ psi
 // and lambda tiles together in LDS, the run's operations un-applied by
 // adj_tile_run (tile_adj.hpp), each workgroup's gradient partials written
 // once at the end.
+// Two workgroups share a CU (two 64 KiB tile pairs), so registers are capped
+// for 4 waves per SIMD.
 template <typename R>
-__global__ __launch_bounds__(kAdjTileThreads) void k_adj_tile(cplx_t<R> *__restrict__ psi, cplx_t<R> *__restrict__ lam,
+__global__ __launch_bounds__(kAdjTileThreads, 4) void k_adj_tile(cplx_t<R> *__restrict__ psi, cplx_t<R> *__restrict__ lam,
                                                               TileMap tm, DeviceGates gates,
                                                               const int32_t *__restrict__ gslot,
                                                               const double *__restrict__ gens,
@@ -174,26 +176,60 @@ static void launch_adj(void *psi, void *lam, const GatePlan &p, const double *ud
     }
 }
 
-int adjoint_impl(const sv_state_t *psi, const sv_state_t *lam, const sv_gate_t *gates, int ngates,
-                 const double *params, int nparams, const sv_pauli_t *terms, int nterms, double *grad, double *loss,
-                 const double *scale, hipStream_t st) {
-    SV_TRY(validate_state(psi));
-    SV_TRY(validate_state(lam));
-    if (psi->n != lam->n || psi->dtype != lam->dtype)
-        return fail(SV_EINVAL, "psi and lambda differ in size or dtype");
-    if (psi->data == lam->data)
-        return fail(SV_EINVAL, "psi and lambda must be different buffers");
+// The reverse sweep of one circuit and Hamiltonian, planned once: the
+// reverse circuit's fused plan, the generator table, the reduction layout
+// and the Pauli terms, on one device.
+struct AdjointPlan {
+    int n = 0, dtype = 0, ngates = 0, nparams = 0, nslots = 0, device = 0;
+    bool async = false;
+    sv_circuit *rc = nullptr;
+    std::vector<int> gen_slot;
+    std::vector<GatePlan> single_plan;
+    std::vector<size_t> pass_lds;
+    size_t off_slots = 0, off_blocks = 0;
+    double *d_gen = nullptr, *d_partials = nullptr;
+    int32_t *d_ints = nullptr, *d_dslot = nullptr;
+    PauliDevice pd;
+};
+
+static void adjoint_free(AdjointPlan *a, hipStream_t st) {
+    a->pd.partials = nullptr;  // borrowed from d_partials
+    pauli_release(&a->pd, st);
+    void *bufs[] = {a->d_gen, a->d_partials, a->d_ints, a->d_dslot};
+    for (void *b : bufs)
+        if (b)
+            (void)(a->async ? hipFreeAsync(b, st) : hipFree(b));
+    a->d_gen = a->d_partials = nullptr;
+    a->d_ints = a->d_dslot = nullptr;
+    if (a->rc)
+        circuit_free(a->rc, st);
+    a->rc = nullptr;
+}
+
+// Validate and plan; device tables allocated stream-ordered on st when async
+// (a one-shot gradient), otherwise allocated and filled before returning.
+static int adjoint_plan(int n, int dtype, const sv_gate_t *gates, int ngates, int nparams, const sv_pauli_t *terms,
+                        int nterms, bool async, hipStream_t st, AdjointPlan *a) {
+    if (dtype != SV_C128 && dtype != SV_C64)
+        return fail(SV_EINVAL, "the adjoint takes complex128 and complex64 states (dtype %d)", dtype);
+    if (n < 1 || n > max_qubits(dtype))
+        return fail(SV_EINVAL, "n=%d outside [1, %d]", n, max_qubits(dtype));
     if (ngates < 0 || (ngates > 0 && !gates))
         return fail(SV_EINVAL, "bad gate list");
-    if (nparams < 0 || (nparams > 0 && (!params || !grad)))
-        return fail(SV_EINVAL, "nparams %d needs params_dev and grad_dev", nparams);
-    const int n = psi->n, dtype = psi->dtype;
+    if (nparams < 0)
+        return fail(SV_EINVAL, "nparams %d", nparams);
     for (int i = 0; i < ngates; ++i) {
         SV_TRY(validate_circuit_gate(n, nparams, gates[i], i));
         SV_TRY(validate_unitary_gate(gates[i], i));
     }
     PauliPlan pplan;
     SV_TRY(make_pauli_plan(n, terms, nterms, &pplan));
+    a->n = n;
+    a->dtype = dtype;
+    a->ngates = ngates;
+    a->nparams = nparams;
+    a->async = async;
+    SV_HIP_TRY(hipGetDevice(&a->device));
 
     // The reverse sweep is the circuit of inverses in reverse order, planned
     // like a forward circuit (fused runs of two LDS tiles, so one size down).
@@ -204,7 +240,7 @@ int adjoint_impl(const sv_state_t *psi, const sv_state_t *lam, const sv_gate_t *
     }
     // generator of every differentiated gate (A with dU/dtheta = A U; A^dag
     // for a gate given with the adjoint flag, as A commutes with U)
-    std::vector<int> gen_slot(ngates, -1);
+    a->gen_slot.assign(ngates, -1);
     std::vector<double> gen;
     std::vector<std::vector<int>> param_slots(nparams);
     for (int r = 0; r < ngates; ++r) {
@@ -219,36 +255,36 @@ int adjoint_impl(const sv_state_t *psi, const sv_state_t *lam, const sv_gate_t *
             std::swap(A[2], A[4]);
             std::swap(A[3], A[5]);
         }
-        gen_slot[r] = (int)(gen.size() / 8);
+        a->gen_slot[r] = (int)(gen.size() / 8);
         gen.insert(gen.end(), A, A + 8);
-        param_slots[g.param].push_back(gen_slot[r]);
+        param_slots[g.param].push_back(a->gen_slot[r]);
     }
     const int nslots = (int)(gen.size() / 8);
+    a->nslots = nslots;
     const int m_cap = std::max(1, tuning().tile_log2[dtype == SV_C128 ? 0 : 1] - 1);
-    sv_circuit *rc = nullptr;
-    SV_TRY(circuit_create(n, dtype, rev.data(), ngates, nparams, SV_FUSE, true, st, m_cap, &rc));
+    SV_TRY(circuit_create(n, dtype, rev.data(), ngates, nparams, SV_FUSE, async, st, m_cap, &a->rc));
+    sv_circuit *rc = a->rc;
 
     // per pass: single passes need pair plans, fused ones per-descriptor slots
-    std::vector<GatePlan> single_plan(rc->passes.size());
+    a->single_plan.assign(rc->passes.size(), GatePlan());
     std::vector<int32_t> dslot(rc->tile_src.size(), -1);
     std::vector<int32_t> slot_blocks(std::max(1, nslots), 1);
-    int r = SV_OK;
-    for (size_t pi = 0; pi < rc->passes.size() && r == SV_OK; ++pi) {
+    for (size_t pi = 0; pi < rc->passes.size(); ++pi) {
         const Pass &p = rc->passes[pi];
         if (p.fused) {
             const unsigned grid = (unsigned)std::min<uint64_t>(p.tm.ntiles, kMaxPartials);
             for (int j = 0; j < p.count; ++j) {
                 const int gi = rc->tile_src[p.first + j];
-                dslot[p.first + j] = gen_slot[gi];
-                if (gen_slot[gi] >= 0)
-                    slot_blocks[gen_slot[gi]] = (int32_t)grid;
+                dslot[p.first + j] = a->gen_slot[gi];
+                if (a->gen_slot[gi] >= 0)
+                    slot_blocks[a->gen_slot[gi]] = (int32_t)grid;
             }
         } else {
             const sv_gate_t &g = rev[p.gate];
             GateSpec gs{n, g.target, g.ctrl_mask, g.ctrl_vals};
-            r = make_gate_plan(gs, dtype, SV_MODE_PAIR, &single_plan[pi]);
-            if (r == SV_OK && gen_slot[p.gate] >= 0)
-                slot_blocks[gen_slot[p.gate]] = (int32_t)reduce_grid(single_plan[pi].niter);
+            SV_TRY(make_gate_plan(gs, dtype, SV_MODE_PAIR, &a->single_plan[pi]));
+            if (a->gen_slot[p.gate] >= 0)
+                slot_blocks[a->gen_slot[p.gate]] = (int32_t)reduce_grid(a->single_plan[pi].niter);
         }
     }
     std::vector<int32_t> ints;  // CSR of slots per parameter, then blocks per slot
@@ -264,15 +300,13 @@ int adjoint_impl(const sv_state_t *psi, const sv_state_t *lam, const sv_gate_t *
                 ints.push_back(sidx);
         ints.insert(ints.end(), slot_blocks.begin(), slot_blocks.begin() + nslots);
     }
-    const size_t off_slots = (size_t)nparams + 1, off_blocks = off_slots + (size_t)nslots;
+    a->off_slots = (size_t)nparams + 1;
+    a->off_blocks = a->off_slots + (size_t)nslots;
 
-    double *d_gen = nullptr, *d_partials = nullptr;
-    int32_t *d_ints = nullptr, *d_dslot = nullptr;
-    PauliDevice pd;
     auto alloc = [&](void **ptr, size_t bytes) -> int {
         if (bytes == 0)
             return SV_OK;
-        hipError_t e = hipMallocAsync(ptr, bytes, st);
+        hipError_t e = async ? hipMallocAsync(ptr, bytes, st) : hipMalloc(ptr, bytes);
         if (e != hipSuccess) {
             (void)hipGetLastError();
             *ptr = nullptr;
@@ -286,32 +320,17 @@ int adjoint_impl(const sv_state_t *psi, const sv_state_t *lam, const sv_gate_t *
         hipError_t e = hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st);
         return e == hipSuccess ? SV_OK : fail(SV_EHIP, "copy failed: %s", hipGetErrorString(e));
     };
-    if (r == SV_OK)
-        r = alloc((void **)&d_gen, gen.size() * sizeof(double));
-    if (r == SV_OK)
-        r = alloc((void **)&d_partials, ((size_t)nslots + 1) * kMaxPartials * sizeof(double));
-    if (r == SV_OK)
-        r = alloc((void **)&d_ints, ints.size() * sizeof(int32_t));
-    if (r == SV_OK)
-        r = alloc((void **)&d_dslot, dslot.size() * sizeof(int32_t));
-    if (r == SV_OK)
-        r = put(d_gen, gen.data(), gen.size() * sizeof(double));
-    if (r == SV_OK)
-        r = put(d_ints, ints.data(), ints.size() * sizeof(int32_t));
-    if (r == SV_OK)
-        r = put(d_dslot, dslot.data(), dslot.size() * sizeof(int32_t));
-    if (r == SV_OK)
-        r = pauli_upload(pplan, 0, st, &pd);
-    double *loss_partials = d_partials ? d_partials + (size_t)nslots * kMaxPartials : nullptr;
-    pd.partials = loss_partials;  // borrowed
-    unsigned loss_blocks = 1;
-    if (r == SV_OK)
-        r = circuit_param_mats(rc, params, st);
-    if (r == SV_OK)
-        r = launch_apply_paulis(dtype, psi->data, lam->data, n, pd, st, &loss_blocks);
+    SV_TRY(alloc((void **)&a->d_gen, gen.size() * sizeof(double)));
+    SV_TRY(alloc((void **)&a->d_partials, ((size_t)nslots + 1) * kMaxPartials * sizeof(double)));
+    SV_TRY(alloc((void **)&a->d_ints, ints.size() * sizeof(int32_t)));
+    SV_TRY(alloc((void **)&a->d_dslot, dslot.size() * sizeof(int32_t)));
+    SV_TRY(put(a->d_gen, gen.data(), gen.size() * sizeof(double)));
+    SV_TRY(put(a->d_ints, ints.data(), ints.size() * sizeof(int32_t)));
+    SV_TRY(put(a->d_dslot, dslot.data(), dslot.size() * sizeof(int32_t)));
+    SV_TRY(pauli_upload(pplan, 0, st, &a->pd));
     // dynamic LDS: the two tiles, then 8 accumulators per parameterised gate
     // of the pass (sized for the largest pass)
-    std::vector<size_t> pass_lds(rc->passes.size(), 0);
+    a->pass_lds.assign(rc->passes.size(), 0);
     size_t lds = 0;
     for (size_t pi = 0; pi < rc->passes.size(); ++pi) {
         const Pass &p = rc->passes[pi];
@@ -320,13 +339,13 @@ int adjoint_impl(const sv_state_t *psi, const sv_state_t *lam, const sv_gate_t *
         size_t npg = 0;
         for (int j = 0; j < p.count; ++j)
             npg += dslot[p.first + j] >= 0 ? 1 : 0;
-        pass_lds[pi] = ((size_t)2 << rc->m) * amp_bytes(dtype) + npg * (kAdjTileThreads / 64) * sizeof(double);
-        lds = std::max(lds, pass_lds[pi]);
+        a->pass_lds[pi] = ((size_t)2 << rc->m) * amp_bytes(dtype) + npg * (kAdjTileThreads / 64) * sizeof(double);
+        lds = std::max(lds, a->pass_lds[pi]);
     }
     constexpr size_t kLdsPerWorkgroup = 160 * 1024;  // gfx950, with the opt-in limit raised
-    if (r == SV_OK && lds > kLdsPerWorkgroup)
-        r = fail(SV_ENOTSUP, "adjoint pass needs %zu bytes of LDS", lds);
-    if (r == SV_OK && lds > 65536) {
+    if (lds > kLdsPerWorkgroup)
+        return fail(SV_ENOTSUP, "adjoint pass needs %zu bytes of LDS", lds);
+    if (lds > 65536) {
         const hipError_t e = dtype == SV_C128 ? hipFuncSetAttribute((const void *)k_adj_tile<double>,
                                                                     hipFuncAttributeMaxDynamicSharedMemorySize,
                                                                     (int)lds)
@@ -334,27 +353,43 @@ int adjoint_impl(const sv_state_t *psi, const sv_state_t *lam, const sv_gate_t *
                                                                     hipFuncAttributeMaxDynamicSharedMemorySize,
                                                                     (int)lds);
         if (e != hipSuccess)
-            r = fail(SV_EHIP, "LDS limit for %zu bytes: %s", lds, hipGetErrorString(e));
+            return fail(SV_EHIP, "LDS limit for %zu bytes: %s", lds, hipGetErrorString(e));
     }
-    for (size_t pi = 0; pi < rc->passes.size() && r == SV_OK; ++pi) {
+    if (!async)
+        SV_HIP_TRY(hipStreamSynchronize(st));  // the tables are in place before the plan is handed out
+    return SV_OK;
+}
+
+// Enqueue one reverse sweep: lambda = H psi (and the loss partials), the
+// passes of the reverse plan, the fixed-order final sums.
+static int adjoint_enqueue(AdjointPlan *a, const sv_state_t *psi, const sv_state_t *lam, const double *params,
+                           double *grad, double *loss, const double *scale, hipStream_t st) {
+    sv_circuit *rc = a->rc;
+    const int n = a->n, dtype = a->dtype, nparams = a->nparams;
+    double *loss_partials = a->d_partials + (size_t)a->nslots * kMaxPartials;
+    a->pd.partials = loss_partials;  // borrowed
+    unsigned loss_blocks = 1;
+    SV_TRY(circuit_param_mats(rc, params, st));
+    SV_TRY(launch_apply_paulis(dtype, psi->data, lam->data, n, a->pd, st, &loss_blocks));
+    for (size_t pi = 0; pi < rc->passes.size(); ++pi) {
         const Pass &p = rc->passes[pi];
         if (p.fused) {
             const unsigned grid = (unsigned)std::min<uint64_t>(p.tm.ntiles, kMaxPartials);
             const DeviceGates dg{rc->d_tiles + p.first, p.count};
             if (dtype == SV_C128)
-                hipLaunchKernelGGL(k_adj_tile<double>, dim3(grid), dim3(kAdjTileThreads), pass_lds[pi], st,
-                                   (double2 *)psi->data, (double2 *)lam->data, p.tm, dg, d_dslot + p.first, d_gen,
-                                   d_partials);
+                hipLaunchKernelGGL(k_adj_tile<double>, dim3(grid), dim3(kAdjTileThreads), a->pass_lds[pi], st,
+                                   (double2 *)psi->data, (double2 *)lam->data, p.tm, dg, a->d_dslot + p.first,
+                                   a->d_gen, a->d_partials);
             else
-                hipLaunchKernelGGL(k_adj_tile<float>, dim3(grid), dim3(kAdjTileThreads), pass_lds[pi], st,
-                                   (float2 *)psi->data,
-                                   (float2 *)lam->data, p.tm, dg, d_dslot + p.first, d_gen, d_partials);
+                hipLaunchKernelGGL(k_adj_tile<float>, dim3(grid), dim3(kAdjTileThreads), a->pass_lds[pi], st,
+                                   (float2 *)psi->data, (float2 *)lam->data, p.tm, dg, a->d_dslot + p.first,
+                                   a->d_gen, a->d_partials);
         } else {
-            const GatePlan &gp = single_plan[pi];
+            const GatePlan &gp = a->single_plan[pi];
             const int gi = p.gate;
             const unsigned grid = reduce_grid(gp.niter);
-            const double *gptr = gen_slot[gi] >= 0 ? d_gen + (size_t)8 * gen_slot[gi] : nullptr;
-            double *part = gen_slot[gi] >= 0 ? d_partials + (size_t)gen_slot[gi] * kMaxPartials : nullptr;
+            const double *gptr = a->gen_slot[gi] >= 0 ? a->d_gen + (size_t)8 * a->gen_slot[gi] : nullptr;
+            double *part = a->gen_slot[gi] >= 0 ? a->d_partials + (size_t)a->gen_slot[gi] * kMaxPartials : nullptr;
             if (dtype == SV_C128)
                 launch_adj<double>(psi->data, lam->data, gp, rc->d_mats + (size_t)8 * gi, gptr, part, grid, st);
             else
@@ -362,23 +397,44 @@ int adjoint_impl(const sv_state_t *psi, const sv_state_t *lam, const sv_gate_t *
         }
         hipError_t e = hipGetLastError();
         if (e != hipSuccess)
-            r = fail(SV_EHIP, "adjoint launch failed: %s", hipGetErrorString(e));
+            return fail(SV_EHIP, "adjoint launch failed: %s", hipGetErrorString(e));
     }
-    if (r == SV_OK && (nparams > 0 || loss)) {
-        hipLaunchKernelGGL(k_grad_final, dim3((unsigned)nparams + 1), dim3(kRedThreads), 0, st, nparams, d_ints,
-                           d_ints + off_slots, d_ints + off_blocks, d_partials, loss_partials, (int)loss_blocks, scale,
-                           grad, loss);
+    if (nparams > 0 || loss) {
+        hipLaunchKernelGGL(k_grad_final, dim3((unsigned)nparams + 1), dim3(kRedThreads), 0, st, nparams, a->d_ints,
+                           a->d_ints + a->off_slots, a->d_ints + a->off_blocks, a->d_partials, loss_partials,
+                           (int)loss_blocks, scale, grad, loss);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess)
-            r = fail(SV_EHIP, "launch failed: %s", hipGetErrorString(e));
+            return fail(SV_EHIP, "launch failed: %s", hipGetErrorString(e));
     }
-    pd.partials = nullptr;
-    pauli_release(&pd, st);
-    void *bufs[] = {d_gen, d_partials, d_ints, d_dslot};
-    for (void *b : bufs)
-        if (b)
-            (void)hipFreeAsync(b, st);
-    circuit_free(rc, st);
+    return SV_OK;
+}
+
+static int check_adjoint_states(const sv_state_t *psi, const sv_state_t *lam, int n, int dtype) {
+    SV_TRY(validate_state(psi));
+    SV_TRY(validate_state(lam));
+    if (psi->n != lam->n || psi->dtype != lam->dtype)
+        return fail(SV_EINVAL, "psi and lambda differ in size or dtype");
+    if (psi->data == lam->data)
+        return fail(SV_EINVAL, "psi and lambda must be different buffers");
+    if (psi->n != n || psi->dtype != dtype)
+        return fail(SV_EINVAL, "states (n=%d, dtype %d) do not match the plan (n=%d, dtype %d)", psi->n, psi->dtype, n,
+                    dtype);
+    return SV_OK;
+}
+
+int adjoint_impl(const sv_state_t *psi, const sv_state_t *lam, const sv_gate_t *gates, int ngates,
+                 const double *params, int nparams, const sv_pauli_t *terms, int nterms, double *grad, double *loss,
+                 const double *scale, hipStream_t st) {
+    SV_TRY(validate_state(psi));
+    if (nparams < 0 || (nparams > 0 && (!params || !grad)))
+        return fail(SV_EINVAL, "nparams %d needs params_dev and grad_dev", nparams);
+    SV_TRY(check_adjoint_states(psi, lam, psi->n, psi->dtype));
+    AdjointPlan a;
+    int r = adjoint_plan(psi->n, psi->dtype, gates, ngates, nparams, terms, nterms, true, st, &a);
+    if (r == SV_OK)
+        r = adjoint_enqueue(&a, psi, lam, params, grad, loss, scale, st);
+    adjoint_free(&a, st);
     return r;
 }
 
@@ -394,6 +450,50 @@ int sv_adjoint_grad(const sv_state_t *psi, const sv_state_t *lam, const sv_gate_
     clear_error();
     return adjoint_impl(psi, lam, gates, ngates, params_dev, nparams, terms, nterms, grad_dev, loss_dev, scale_dev,
                         (hipStream_t)st);
+}
+
+int sv_adjoint_create(int n, int dtype, const sv_gate_t *gates, int ngates, int nparams, const sv_pauli_t *terms,
+                      int nterms, sv_adjoint_t **out) {
+    clear_error();
+    if (!out)
+        return fail(SV_EINVAL, "out is NULL");
+    *out = nullptr;
+    auto *a = new AdjointPlan();
+    const int r = adjoint_plan(n, dtype, gates, ngates, nparams, terms, nterms, false, nullptr, a);
+    if (r != SV_OK) {
+        adjoint_free(a, nullptr);
+        delete a;
+        return r;
+    }
+    *out = reinterpret_cast<sv_adjoint_t *>(a);
+    return SV_OK;
+}
+
+int sv_adjoint_run(sv_adjoint_t *plan, const sv_state_t *psi, const sv_state_t *lam, const double *params_dev,
+                   double *grad_dev, double *loss_dev, const double *scale_dev, sv_stream_t st) {
+    clear_error();
+    if (!plan)
+        return fail(SV_EINVAL, "plan is NULL");
+    auto *a = reinterpret_cast<AdjointPlan *>(plan);
+    SV_TRY(check_adjoint_states(psi, lam, a->n, a->dtype));
+    if (a->nparams > 0 && (!params_dev || !grad_dev))
+        return fail(SV_EINVAL, "nparams %d needs params_dev and grad_dev", a->nparams);
+    int dev = 0;
+    SV_HIP_TRY(hipGetDevice(&dev));
+    if (dev != a->device)
+        return fail(SV_EINVAL, "plan was made on device %d, current device is %d", a->device, dev);
+    return adjoint_enqueue(a, psi, lam, params_dev, grad_dev, loss_dev, scale_dev, (hipStream_t)st);
+}
+
+int sv_adjoint_destroy(sv_adjoint_t *plan) {
+    clear_error();
+    if (!plan)
+        return SV_OK;
+    auto *a = reinterpret_cast<AdjointPlan *>(plan);
+    (void)hipDeviceSynchronize();  // runs enqueued earlier may still read the tables
+    adjoint_free(a, nullptr);
+    delete a;
+    return SV_OK;
 }
 
 } // extern "C"

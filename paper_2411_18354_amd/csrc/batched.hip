@@ -213,7 +213,7 @@ __global__ void k_batch_tile_params(const BTileJob *__restrict__ jobs, int njobs
 }
 
 template <typename R>
-__global__ __launch_bounds__(kBatchThreads) void k_batched(const BCirc *__restrict__ circs,
+__global__ __launch_bounds__(kBatchThreads, 4) void k_batched(const BCirc *__restrict__ circs,
                                                            const int32_t *__restrict__ order, int ncirc,
                                                            const BGate *__restrict__ gates,
                                                            const BPass *__restrict__ passes,
@@ -370,7 +370,7 @@ __device__ void adjoint_block(const BCirc &c, const BGate *__restrict__ gates, c
 }
 
 template <typename R>
-__global__ __launch_bounds__(kBatchThreads) void k_batched_adjoint(
+__global__ __launch_bounds__(kBatchThreads, 4) void k_batched_adjoint(
     const BCirc *__restrict__ circs, const int32_t *__restrict__ order, int ncirc, const BGate *__restrict__ gates,
     const BPass *__restrict__ apasses, const TileGate *__restrict__ atiles, const int32_t *__restrict__ atslot,
     const int32_t *__restrict__ slot_param, const double *__restrict__ params, const DTerm *__restrict__ terms,

@@ -1,5 +1,6 @@
 """Binding of the observable and gradient entry points (sv_expect,
-sv_expect_noalloc, sv_expect_terms, sv_apply_pauli_sum, sv_adjoint_grad) and the
+sv_expect_noalloc, sv_expect_terms, sv_apply_pauli_sum, sv_adjoint_grad, and
+the planned adjoint sv_adjoint_create / sv_adjoint_run / sv_adjoint_destroy) and the
 torch.autograd.Function built on them.  Argument marshalling only."""
 from __future__ import annotations
 
@@ -96,13 +97,56 @@ def sv_adjoint_grad(psi, lam, gates, params, terms, grad=None, loss=None, scale=
     return grad[:nparams], loss
 
 
+_sig("sv_adjoint_create", [ctypes.c_int, ctypes.c_int, ctypes.POINTER(sv_gate_t), ctypes.c_int, ctypes.c_int,
+                           ctypes.POINTER(sv_pauli_t), ctypes.c_int, ctypes.POINTER(_vp)])
+_sig("sv_adjoint_run", [_vp, _sp, _sp, _vp, _vp, _vp, _vp, _vp])
+_sig("sv_adjoint_destroy", [_vp])
+
+
+class AdjointPlan:
+    """A planned adjoint gradient (sv_adjoint_create) of one circuit and
+    Hamiltonian; run() enqueues sv_adjoint_run (psi is consumed)."""
+
+    def __init__(self, n: int, gates, terms, nparams: int, dtype: int = SV_C128):
+        self.n, self.dtype, self.nparams = n, dtype, int(nparams)
+        self._g = gates if isinstance(gates, ctypes.Array) else circuit_gates(gates)
+        self._t = pauli_terms(terms)
+        h = _vp()
+        _check(_L.sv_adjoint_create(int(n), int(dtype), self._g, _count(self._g), self.nparams, self._t,
+                                    _count(self._t), ctypes.byref(h)))
+        self._h = h
+
+    def run(self, psi, lam, params, grad=None, loss=None, scale=None, stream=None):
+        """Returns (grad, loss) device tensors."""
+        import torch
+        s, l = state_view(psi), state_view(lam)
+        if grad is None:
+            grad = torch.empty(max(1, self.nparams), dtype=torch.float64, device=psi.device)
+        if loss is None:
+            loss = torch.empty(1, dtype=torch.float64, device=psi.device)
+        _check(_L.sv_adjoint_run(self._h, ctypes.byref(s), ctypes.byref(l), _ptr(params), _ptr(grad), _ptr(loss),
+                                 _ptr(scale), stream_ptr(stream)))
+        return grad[:self.nparams], loss
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            _L.sv_adjoint_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 class SvExpectation:
     """L(theta) = <0|U(theta)^dag H U(theta)|0> as a torch.autograd.Function.
 
     forward: sv_init + circuit run (fused plan, angles read from the params
     tensor on the device) + sv_expect.  backward: copy of the saved final
-    state (so backward can run more than once), sv_adjoint_grad with the
-    upstream gradient passed as the device scale.  At most three state
+    state (so backward can run more than once), the model's planned adjoint
+    (sv_adjoint_run) with the upstream gradient passed as the device scale.  At most three state
     vectors are alive: the saved forward state, its copy being un-applied and
     the co-state."""
 
@@ -133,7 +177,7 @@ class SvExpectation:
                     work = ctx.state.clone()
                     lam = torch.empty_like(work)
                     scale = grad_out.detach().to(torch.float64).reshape(1).contiguous()
-                    grad, _ = sv_adjoint_grad(work, lam, model.gates, params, model.terms, scale=scale)
+                    grad, _ = model.adjoint.run(work, lam, params, scale=scale)
                     return grad, None
 
             cls._fn = _Fn
@@ -156,6 +200,7 @@ class ExpectationModel:
         self.dtype = dtype
         self.torch_dtype = torch.complex128 if dtype == SV_C128 else torch.complex64
         self.plan = Circuit(self.n, self.gates, dtype=dtype, nparams=self.nparams, flags=flags)
+        self.adjoint = AdjointPlan(self.n, self.gates, self.terms, self.nparams, dtype=dtype)
 
     def __call__(self, params):
         return SvExpectation.apply(params, self)

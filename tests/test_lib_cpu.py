@@ -249,3 +249,15 @@ def test_adjoint_rejects_non_unitary_matrix(sv):
     rc = sv.lib().sv_adjoint_grad(ctypes.byref(psi), ctypes.byref(lam), gates, 2, ctypes.c_void_p(0x30000), 1,
                                   terms, 1, ctypes.c_void_p(0x40000), None, None, None)
     assert rc == sv.SV_EINVAL and "not unitary" in sv.sv_last_error(), sv.sv_last_error()
+
+
+def test_adjoint_plan_argument_errors(sv):
+    import numpy as np
+    """Planned adjoint: validation at creation names the bad gate; a run on
+    states of another shape, or a NULL plan, is an argument error."""
+    import workloads as W
+    bad = W.Circuit(4, [W.Gate("RY", 7, param=0)], np.array([0.1]))
+    code, msg = _rc(lambda: sv.AdjointPlan(4, bad, [W.PauliTerm(1.0, 0, 1)], 1))
+    assert code == sv.SV_EINVAL and "gate 0" in msg, msg
+    s = _state(sv, 4)
+    assert sv.lib().sv_adjoint_run(None, ctypes.byref(s), ctypes.byref(s), None, None, None, None, None) == sv.SV_EINVAL
