@@ -833,8 +833,11 @@ def measure_extras(sv, W, torch, np, stream, with_layered, psi_host=None, cases=
         hbatch.adjoint(bparams, grad=bgrad, loss=bloss, stream=stream)
     torch.cuda.synchronize()
     hbatch.set_timing(None)
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    # the batched adjoint runs one 1024-lane workgroup per circuit when there
+    # are at most as many circuits as CUs, else two 512-lane ones per CU
     occ = batch_occupancy(np, stamps.cpu().numpy(), ns_tick, [16] * len(circs),
-                          2 * torch.cuda.get_device_properties(0).multi_processor_count)
+                          len(circs) if len(circs) <= cus else 2 * cus)
     out["batched_adjoint_hea256_n16"] = {"circuits": len(circs), "n": 16, "params_each": circs[0].nparams,
                                       "forward_ms": round(t_bf, 2), "backward_ms": round(t_bb, 2),
                                       "gradients_per_s": round(len(circs) * 1e3 / t_bb, 1), "occupancy": occ}

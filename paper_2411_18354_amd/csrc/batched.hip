@@ -36,6 +36,7 @@ int validate_circuit_gate(int n, int nparams, const sv_gate_t &g, int index);
 int validate_unitary_gate(const sv_gate_t &g, int index);
 
 constexpr int kBatchThreads = 512;
+constexpr int kBatchAdjMaxThreads = 1024;  // the batched adjoint's wider shape
 constexpr size_t kBatchLds = 65536;  // the tile (or a whole resident state)
 // dynamic LDS: the work-item slot, the tile, then the diagonal-sweep tables
 constexpr size_t kBatchSlot = 64;
@@ -248,7 +249,7 @@ __global__ void k_zero_u32(unsigned int *p) { *p = 0u; }
 
 // One gate of the reverse sweep over the whole state in global memory:
 // gradient term (when parameterised) and un-apply on psi and lambda.
-template <typename R>
+template <typename R, int THREADS>
 __device__ void adj_gate_global(const BCirc &c, const BGate &g, int gs, const double *__restrict__ params,
                                 const double *__restrict__ gens, cplx_t<R> *psi, cplx_t<R> *lam,
                                 double *__restrict__ grad, double *scratch) {
@@ -260,7 +261,7 @@ __device__ void adj_gate_global(const BCirc &c, const BGate &g, int gs, const do
     const uint64_t npairs = 1ull << (c.n - 1 - __popcll(g.cmask));
     const uint64_t st = 1ull << g.target;
     double acc = 0.0;
-    for (uint64_t it = threadIdx.x; it < npairs; it += kBatchThreads) {
+    for (uint64_t it = threadIdx.x; it < npairs; it += THREADS) {
         const uint64_t p1 = insert_bits<uint64_t>(it, pos, g.cvals);
         cplx_t<R> x = psi[p1], y = psi[p1 | st], lx = lam[p1], ly = lam[p1 | st];
         if (gs >= 0) {
@@ -292,7 +293,7 @@ __device__ void adj_gate_global(const BCirc &c, const BGate &g, int gs, const do
 // adjoint), and single gates over global memory.  Gradient sums are reduced
 // in a fixed order (per wavefront, then wavefronts in index order, then
 // passes in order), so results are reproducible.
-template <typename R>
+template <typename R, int THREADS>
 __device__ void adjoint_block(const BCirc &c, const BGate *__restrict__ gates, const BPass *__restrict__ apasses,
                               const TileGate *__restrict__ atiles, const int32_t *__restrict__ atslot,
                               const int32_t *__restrict__ slot_param, const double *__restrict__ params,
@@ -302,11 +303,11 @@ __device__ void adjoint_block(const BCirc &c, const BGate *__restrict__ gates, c
     cplx_t<R> *psi = reinterpret_cast<cplx_t<R> *>(c.psi);
     cplx_t<R> *lam = reinterpret_cast<cplx_t<R> *>(c.lam);
     const uint64_t N = 1ull << c.n;
-    for (int j = threadIdx.x; j < c.nparams; j += kBatchThreads)
+    for (int j = threadIdx.x; j < c.nparams; j += THREADS)
         grad[c.first_param + j] = 0.0;
     // lambda = H psi; terms are sorted by x mask
     double lp = 0.0;
-    for (uint64_t k = threadIdx.x; k < N; k += kBatchThreads) {
+    for (uint64_t k = threadIdx.x; k < N; k += THREADS) {
         double ar = 0.0, ai = 0.0;
         for (int j = 0; j < c.nterms; ++j) {
             const DTerm T = terms[c.first_term + j];
@@ -343,14 +344,14 @@ __device__ void adjoint_block(const BCirc &c, const BGate *__restrict__ gates, c
                 const uint64_t base = expand_index<uint64_t>(p.tm.outer, tt);
                 if (!adj_tile_touched(base, dg))
                     continue;  // uniform
-                for (uint32_t k = threadIdx.x; k < T; k += kBatchThreads) {
+                for (uint32_t k = threadIdx.x; k < T; k += THREADS) {
                     const uint64_t o = base | tile_offset(p.tm, k);
                     tp[k] = psi[o];
                     tl[k] = lam[o];
                 }
                 __syncthreads();
-                adj_tile_run<R, kBatchThreads>(tp, tl, base, T, dg, gs, gens, accl);
-                for (uint32_t k = threadIdx.x; k < T; k += kBatchThreads) {
+                adj_tile_run<R, THREADS>(tp, tl, base, T, dg, gs, gens, accl);
+                for (uint32_t k = threadIdx.x; k < T; k += THREADS) {
                     const uint64_t o = base | tile_offset(p.tm, k);
                     psi[o] = tp[k];
                     lam[o] = tl[k];
@@ -363,21 +364,23 @@ __device__ void adjoint_block(const BCirc &c, const BGate *__restrict__ gates, c
             __syncthreads();
         } else {
             const int f = p.gate;  // forward index of the gate un-applied here
-            adj_gate_global<R>(c, gates[c.first_gate + f], gen_of[c.first_gate + f], params, gens, psi, lam, grad,
+            adj_gate_global<R, THREADS>(c, gates[c.first_gate + f], gen_of[c.first_gate + f], params, gens, psi, lam, grad,
                                scratch);
         }
     }
 }
 
-template <typename R>
-__global__ __launch_bounds__(kBatchThreads, 4) void k_batched_adjoint(
+// THREADS = 512 (two workgroups per CU) or 1024 (one per CU, for batches of
+// at most one circuit per CU: twice the wavefronts on each circuit).
+template <typename R, int THREADS>
+__global__ __launch_bounds__(THREADS, 2048 / THREADS) void k_batched_adjoint(
     const BCirc *__restrict__ circs, const int32_t *__restrict__ order, int ncirc, const BGate *__restrict__ gates,
     const BPass *__restrict__ apasses, const TileGate *__restrict__ atiles, const int32_t *__restrict__ atslot,
     const int32_t *__restrict__ slot_param, const double *__restrict__ params, const DTerm *__restrict__ terms,
     const double *__restrict__ gens, const int32_t *__restrict__ gen_of, double *__restrict__ grad,
     double *__restrict__ loss, unsigned int *__restrict__ queue, uint64_t *__restrict__ stamps) {
     extern __shared__ unsigned char lds_raw[];  // psi and lambda tiles, then gradient accumulators
-    __shared__ double scratch[kBatchThreads / 64];
+    __shared__ double scratch[THREADS / 64];
     __shared__ int item;
     for (;;) {
         if (threadIdx.x == 0)
@@ -389,7 +392,7 @@ __global__ __launch_bounds__(kBatchThreads, 4) void k_batched_adjoint(
             break;
         const int ci = order[it];
         const uint64_t t0 = stamps ? wall_clock64() : 0;
-        adjoint_block<R>(circs[ci], gates, apasses, atiles, atslot, slot_param, params, terms, gens, gen_of, grad,
+        adjoint_block<R, THREADS>(circs[ci], gates, apasses, atiles, atslot, slot_param, params, terms, gens, gen_of, grad,
                          loss + ci, scratch, lds_raw);
         __syncthreads();
         if (stamps && threadIdx.x == 0) {
@@ -551,7 +554,7 @@ static int build_circuit(const BatchArgs &A, int c, int dtype, bool adjoint, Cir
                 for (int j = 0; j < q.count; ++j)
                     npg += out->gen_of[bc.ngates - 1 - out->atiles[q.first + j].src_gate] >= 0 ? 1 : 0;
                 out->adj_lds = std::max(out->adj_lds, ((size_t)2 << q.tm.m) * amp_bytes(dtype) +
-                                                          npg * kAdjWaves * sizeof(double));
+                                                          npg * (kBatchAdjMaxThreads / 64) * sizeof(double));
             } else {
                 b.gate = bc.ngates - 1 - q.gate;  // forward index
             }
@@ -860,35 +863,44 @@ static int launch_forward(int dtype, const BatchDevice &d, int ncirc, const doub
     return SV_OK;
 }
 
+template <typename R, int THREADS>
+static int go_adjoint(const BatchDevice &d, int ncirc, unsigned grid, size_t lds, const double *params, double *grad,
+                      double *loss, hipStream_t s, uint64_t *stamps) {
+    hipError_t a = hipFuncSetAttribute((const void *)k_batched_adjoint<R, THREADS>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (a != hipSuccess)
+        return fail(SV_EHIP, "LDS limit: %s", hipGetErrorString(a));
+    hipLaunchKernelGGL((k_batched_adjoint<R, THREADS>), dim3(grid), dim3(THREADS), lds, s, d.circs, d.order, ncirc,
+                       d.gates, d.apasses, d.atiles, d.atslot, d.slot_param, params, d.terms, d.gens, d.gen_of, grad,
+                       loss, d.queue, stamps);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return fail(SV_EHIP, "batched adjoint launch failed: %s", hipGetErrorString(e));
+    return SV_OK;
+}
+
+// A batch of at most one circuit per CU runs one 1024-lane workgroup per
+// circuit (two 512-lane ones per CU would leave half the workgroups idle);
+// larger batches run two 512-lane workgroups per CU.
 static int launch_adjoint(int dtype, const BatchDevice &d, int ncirc, const double *params, double *grad,
                           double *loss, hipStream_t s, uint64_t *stamps = nullptr) {
     constexpr size_t kLdsPerWorkgroup = 160 * 1024;  // gfx950, with the opt-in limit raised
     const size_t lds = std::max<size_t>(d.adj_lds, 8);
     if (lds + 1024 > kLdsPerWorkgroup)
         return fail(SV_ENOTSUP, "a fused reverse pass needs %zu bytes of LDS", lds);
-    hipError_t a = dtype == SV_C128 ? hipFuncSetAttribute((const void *)k_batched_adjoint<double>,
-                                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds)
-                                    : hipFuncSetAttribute((const void *)k_batched_adjoint<float>,
-                                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (a != hipSuccess)
-        return fail(SV_EHIP, "LDS limit: %s", hipGetErrorString(a));
-    const unsigned grid = persistent_grid(ncirc);
+    DeviceInfo di;
+    const int cus = device_info(&di) == SV_OK ? di.num_cus : 256;
+    const bool wide = ncirc <= cus;
+    const unsigned grid = wide ? (unsigned)std::max(1, ncirc) : persistent_grid(ncirc);
     if (d.najobs > 0)
         hipLaunchKernelGGL(k_batch_tile_params, dim3((d.najobs + 255) / 256), dim3(256), 0, s, d.ajobs, d.najobs,
                            params, d.atiles);
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, s, d.queue);
     if (dtype == SV_C128)
-        hipLaunchKernelGGL(k_batched_adjoint<double>, dim3(grid), dim3(kBatchThreads), lds, s, d.circs, d.order, ncirc,
-                           d.gates, d.apasses, d.atiles, d.atslot, d.slot_param, params, d.terms, d.gens, d.gen_of,
-                           grad, loss, d.queue, stamps);
-    else
-        hipLaunchKernelGGL(k_batched_adjoint<float>, dim3(grid), dim3(kBatchThreads), lds, s, d.circs, d.order, ncirc,
-                           d.gates, d.apasses, d.atiles, d.atslot, d.slot_param, params, d.terms, d.gens, d.gen_of,
-                           grad, loss, d.queue, stamps);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess)
-        return fail(SV_EHIP, "batched adjoint launch failed: %s", hipGetErrorString(e));
-    return SV_OK;
+        return wide ? go_adjoint<double, kBatchAdjMaxThreads>(d, ncirc, grid, lds, params, grad, loss, s, stamps)
+                    : go_adjoint<double, kBatchThreads>(d, ncirc, grid, lds, params, grad, loss, s, stamps);
+    return wide ? go_adjoint<float, kBatchAdjMaxThreads>(d, ncirc, grid, lds, params, grad, loss, s, stamps)
+                : go_adjoint<float, kBatchThreads>(d, ncirc, grid, lds, params, grad, loss, s, stamps);
 }
 
 } // namespace sv

@@ -6,7 +6,8 @@
 // When gslot[i] >= 0, its gradient term 2 Re <lambda|Pi_c A|psi> (A: the
 // generator in gens[8 gslot[i] ..]) is taken first, over exactly the pairs
 // the scheduling enumerates.  It is added to one accumulator per wavefront
-// in LDS, for the k-th parameterised gate of the run accl[k * kAdjWaves + w],
+// in LDS, for the k-th parameterised gate of the run accl[k * nw + w] (nw:
+// the workgroup's wavefronts),
 // so a gate needs a wavefront reduction, not a workgroup barrier.
 #pragma once
 
@@ -24,7 +25,7 @@ __device__ __forceinline__ int adj_acc_zero(const DeviceGates &gates, const int3
     int npg = 0;
     for (int i = 0; i < gates.size(); ++i)
         npg += gslot[i] >= 0 ? 1 : 0;
-    for (int k = threadIdx.x; k < npg * kAdjWaves; k += blockDim.x)
+    for (int k = threadIdx.x; k < npg * (int)(blockDim.x >> 6); k += blockDim.x)
         accl[k] = 0.0;
     __syncthreads();
     return npg;
@@ -44,9 +45,10 @@ __device__ __forceinline__ int adj_acc_slot(const DeviceGates &gates, const int3
 
 // The k-th accumulator summed over the wavefronts in index order.
 __device__ __forceinline__ double adj_acc_sum(const double *accl, int k) {
+    const int nw = (int)(blockDim.x >> 6);
     double s = 0.0;
-    for (int q = 0; q < kAdjWaves; ++q)
-        s += accl[k * kAdjWaves + q];
+    for (int q = 0; q < nw; ++q)
+        s += accl[k * nw + q];
     return s;
 }
 
@@ -234,7 +236,7 @@ __device__ __forceinline__ int adj_diag_block(cplx_t<R> *tp, cplx_t<R> *tl, uint
                 }
                 const double sum = wave_sum(part);
                 if ((threadIdx.x & 63) == 0)
-                    accl[k * kAdjWaves + w] += sum;
+                    accl[k * (THREADS / 64) + w] += sum;
                 ++k;
             }
             const R m0r = (R)uniform_f64(d.m[0]), m0i = (R)uniform_f64(d.m[1]);
@@ -295,13 +297,13 @@ __device__ __forceinline__ void adj_tile_run(cplx_t<R> *tp, cplx_t<R> *tl, uint6
                 if (sl >= 0) {
                     const double s1 = wave_sum(acc1);
                     if ((threadIdx.x & 63) == 0)
-                        accl[kacc * kAdjWaves + w] += s1;
+                        accl[kacc * (THREADS / 64) + w] += s1;
                     ++kacc;
                 }
                 if (sl2 >= 0) {
                     const double s2 = wave_sum(acc2);
                     if ((threadIdx.x & 63) == 0)
-                        accl[kacc * kAdjWaves + w] += s2;
+                        accl[kacc * (THREADS / 64) + w] += s2;
                     ++kacc;
                 }
                 __syncthreads();
@@ -360,7 +362,7 @@ __device__ __forceinline__ void adj_tile_run(cplx_t<R> *tp, cplx_t<R> *tl, uint6
             if (sl >= 0) {
                 const double s = wave_sum(acc);
                 if ((threadIdx.x & 63) == 0)
-                    accl[kacc * kAdjWaves + w] += s;
+                    accl[kacc * (THREADS / 64) + w] += s;
             }
             __syncthreads();
         }
