@@ -17,8 +17,11 @@ Tuning &tuning() {
     //  - the wavefront kernel is the faster scheduled kernel whenever the
     //    target is among the 6 lowest free index bits;
     //  - 64 KiB LDS tiles for the fused pass.
-    //  - fused tiles always hold the 6 (complex128) / 7 (complex64) lowest
-    //    qubits, i.e. 1 KiB contiguous runs, plus qubits picked per run.
+    //  - fused tiles always hold the 4 (complex128) / 5 (complex64) lowest
+    //    qubits, i.e. 256-byte contiguous runs, plus qubits picked per run:
+    //    against 1 KiB runs this leaves more tile qubits to the planner and
+    //    cut passes and time by 7-12% on layered and random circuits (equal
+    //    on QFT29), while narrower runs gained nothing more.
     //  - dense blocks (SV_DENSE) on the 4 lowest qubits for stretches of at
     //    least 16 gates.
     //  - one pair (or amplitude) per lane in the scheduled pair and
@@ -28,7 +31,7 @@ Tuning &tuning() {
     //    256-lane workgroups and one pair per lane (10.8 ms against 12.5 ms
     //    with four per lane, 16.1 ms with 64-lane workgroups, whose many
     //    workgroups cost more when most lanes only test and exit).
-    static Tuning t = {{3, 4}, 1, 1, {12, 13}, {6, 7}, 2, 4, 16, 1, 1, 256, 1, 1};
+    static Tuning t = {{3, 4}, 1, 1, {12, 13}, {4, 5}, 2, 4, 16, 1, 1, 256, 1, 1};
     return t;
 }
 

@@ -27,3 +27,18 @@ def gpu():
         pytest.skip("no GPU visible")
     import paper_2411_18354_amd as sv
     return sv
+
+
+@pytest.fixture(autouse=True)
+def _restore_tuning():
+    """Tests may change the library's launch knobs; each one ends with the
+    values it started with."""
+    try:
+        import paper_2411_18354_amd as mod
+        saved = {k: mod.sv_tune_get(k) for k in mod.TUNE_KEYS}
+    except (ImportError, OSError):
+        saved = None
+    yield
+    if saved is not None:
+        for k, v in saved.items():
+            mod.sv_tune_set(k, v)
