@@ -40,7 +40,7 @@ constexpr int kBatchAdjMaxThreads = 1024;  // the batched adjoint's wider shape
 constexpr size_t kBatchLds = 65536;  // the tile (or a whole resident state)
 // dynamic LDS: the work-item slot, the tile, then the diagonal-sweep tables
 constexpr size_t kBatchSlot = 64;
-constexpr size_t kBatchDynLds = kBatchSlot + kBatchLds + 8 * 1088;  // tables for tile widths up to 13
+constexpr size_t kBatchDynLds = kBatchSlot + kBatchLds + 8 * 1600;  // tables for tile widths up to 13
 
 struct BGate {
     double m[8];      // matrix of a fixed gate
@@ -154,7 +154,8 @@ __device__ __forceinline__ void gate_on_block(cplx_t<R> *base, int nbits, int ta
 
 template <typename R>
 __device__ void run_circuit_block(const BCirc &c, const BGate *__restrict__ gates, const BPass *__restrict__ passes,
-                                  const TileGate *__restrict__ tiles, const double *__restrict__ params,
+                                  const TileGate *__restrict__ tiles, const SweepPat *__restrict__ pats,
+                                  const SweepMember *__restrict__ mems, const double *__restrict__ params,
                                   cplx_t<R> *lds) {
     cplx_t<R> *psi = reinterpret_cast<cplx_t<R> *>(c.psi);
     const uint64_t N = 1ull << c.n;
@@ -174,7 +175,7 @@ __device__ void run_circuit_block(const BCirc &c, const BGate *__restrict__ gate
     for (int pi = 0; pi < c.npasses; ++pi) {
         const BPass &p = passes[c.first_pass + pi];
         if (p.fused) {  // uniform
-            const DeviceGates dg{tiles + p.first, p.count};
+            const DeviceGates dg{tiles + p.first, p.count, pats, mems};
             const uint32_t T = 1u << p.tm.m;
             for (uint64_t tt = 0; tt < p.tm.ntiles; ++tt) {
                 const uint64_t base = expand_index<uint64_t>(p.tm.outer, tt);
@@ -199,7 +200,7 @@ __device__ void run_circuit_block(const BCirc &c, const BGate *__restrict__ gate
 // Angles of the parameterised gates inside fused runs, into their tile
 // descriptors (matrix, and phases of diagonal ones).
 __global__ void k_batch_tile_params(const BTileJob *__restrict__ jobs, int njobs, const double *__restrict__ params,
-                                    TileGate *__restrict__ tiles) {
+                                    TileGate *__restrict__ tiles, SweepMember *__restrict__ mems) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= njobs)
         return;
@@ -209,8 +210,12 @@ __global__ void k_batch_tile_params(const BTileJob *__restrict__ jobs, int njobs
     TileGate &t = tiles[j.tile];
     for (int k = 0; k < 8; ++k)
         t.m[k] = m[k];
-    if (t.diag)
+    if (t.diag) {
         diag_phases(m, t.ph, &t.unit);
+        for (int s = 0; s < 2; ++s)  // the phase-sweep members holding ph (forward plans)
+            if (mems && t.mem[s] >= 0)
+                mems[t.mem[s]].theta = t.ph[s];
+    }
 }
 
 template <typename R>
@@ -219,6 +224,8 @@ __global__ __launch_bounds__(kBatchThreads, 4) void k_batched(const BCirc *__res
                                                            const BGate *__restrict__ gates,
                                                            const BPass *__restrict__ passes,
                                                            const TileGate *__restrict__ tiles,
+                                                           const SweepPat *__restrict__ pats,
+                                                           const SweepMember *__restrict__ mems,
                                                            const double *__restrict__ params,
                                                            unsigned int *__restrict__ queue,
                                                            uint64_t *__restrict__ stamps) {
@@ -234,7 +241,7 @@ __global__ __launch_bounds__(kBatchThreads, 4) void k_batched(const BCirc *__res
         if (it >= ncirc)
             break;
         const uint64_t t0 = stamps ? wall_clock64() : 0;
-        run_circuit_block<R>(circs[order[it]], gates, passes, tiles, params, lds);
+        run_circuit_block<R>(circs[order[it]], gates, passes, tiles, pats, mems, params, lds);
         __syncthreads();
         if (stamps && threadIdx.x == 0) {
             stamps[2 * order[it]] = t0;
@@ -411,6 +418,8 @@ struct CircBuild {
     std::vector<BGate> gates;
     std::vector<BPass> passes;     // forward plan (circuit-local indices)
     std::vector<TileGate> tiles;
+    std::vector<SweepPat> pats;    // phase patterns of the table sweeps (circuit-local)
+    std::vector<SweepMember> mems;
     std::vector<BTileJob> jobs;    // tile indices circuit-local
     // adjoint: the reverse sweep's fused plan, each descriptor's generator
     // slot (circuit-local, -1 none), each slot's parameter (batch-global)
@@ -467,7 +476,7 @@ static int build_circuit(const BatchArgs &A, int c, int dtype, bool adjoint, Cir
             std::vector<PlanPass> pp;
             int m_used = 0;
             SV_TRY(circuit_plan_tiles(s.n, dtype, A.gates + g0, bc.ngates, (int)(p1 - p0), m_cap, &pp, &out->tiles,
-                                      &m_used));
+                                      &m_used, &out->pats, &out->mems));
             if (m_used != bc.m)
                 return fail(SV_EINVAL, "planner tile width %d != %d", m_used, bc.m);
             for (const PlanPass &q : pp) {
@@ -596,6 +605,8 @@ struct BatchHost {
     std::vector<BGate> gates;
     std::vector<BPass> passes;
     std::vector<TileGate> tiles;
+    std::vector<SweepPat> pats;
+    std::vector<SweepMember> mems;
     std::vector<BTileJob> jobs;
     std::vector<BPass> apasses;
     std::vector<TileGate> atiles;
@@ -699,7 +710,22 @@ static int build_batch(const BatchArgs &A, bool adjoint, BatchHost *h, int *dtyp
             j.tile += tbase;
             h->jobs.push_back(j);
         }
-        h->tiles.insert(h->tiles.end(), b.tiles.begin(), b.tiles.end());
+        // phase patterns: rebase the descriptors' and patterns' indices
+        const uint32_t pbase = (uint32_t)h->pats.size(), mbase = (uint32_t)h->mems.size();
+        for (TileGate t : b.tiles) {
+            if (t.diag) {
+                t.pat0 += pbase;
+                for (int s = 0; s < 2; ++s)
+                    if (t.mem[s] >= 0)
+                        t.mem[s] += (int32_t)mbase;
+            }
+            h->tiles.push_back(t);
+        }
+        for (SweepPat p : b.pats) {
+            p.first += mbase;
+            h->pats.push_back(p);
+        }
+        h->mems.insert(h->mems.end(), b.mems.begin(), b.mems.end());
         const int32_t gbase = (int32_t)(h->gens.size() / 8);  // generator slots before this circuit's
         b.bc.first_apass = (int32_t)h->apasses.size();
         const int32_t abase = (int32_t)h->atiles.size();
@@ -736,6 +762,8 @@ struct BatchDevice {
     BGate *gates = nullptr;
     BPass *passes = nullptr;
     TileGate *tiles = nullptr;
+    SweepPat *pats = nullptr;
+    SweepMember *mems = nullptr;
     BTileJob *jobs = nullptr;
     int njobs = 0;
     BPass *apasses = nullptr;
@@ -753,8 +781,8 @@ struct BatchDevice {
 // Stream-ordered release when async (after the kernels enqueued on st),
 // otherwise an immediate free.
 static void batch_release(BatchDevice *d, bool async, hipStream_t st) {
-    void *ps[] = {d->circs,  d->gates,  d->passes, d->tiles,  d->jobs,  d->apasses, d->atiles,
-                  d->ajobs,  d->atslot, d->slot_param, d->order, d->gen_of, d->gens,    d->terms,
+    void *ps[] = {d->circs,  d->gates,  d->passes, d->tiles,  d->pats, d->mems, d->jobs,  d->apasses,
+                  d->atiles, d->ajobs,  d->atslot, d->slot_param, d->order, d->gen_of, d->gens,    d->terms,
                   d->queue};
     for (void *p : ps)
         if (p)
@@ -791,6 +819,10 @@ static int upload_batch(const BatchHost &h, bool async, hipStream_t st, BatchDev
         r = dev_copy(&d->passes, h.passes, async, st, 1);
     if (r == SV_OK)
         r = dev_copy(&d->tiles, h.tiles, async, st, 1);
+    if (r == SV_OK)
+        r = dev_copy(&d->pats, h.pats, async, st, 1);
+    if (r == SV_OK)
+        r = dev_copy(&d->mems, h.mems, async, st, 1);
     if (r == SV_OK)
         r = dev_copy(&d->jobs, h.jobs, async, st, 1);
     d->njobs = (int)h.jobs.size();
@@ -849,14 +881,14 @@ static int launch_forward(int dtype, const BatchDevice &d, int ncirc, const doub
     const unsigned grid = persistent_grid(ncirc);
     if (d.njobs > 0)
         hipLaunchKernelGGL(k_batch_tile_params, dim3((d.njobs + 255) / 256), dim3(256), 0, s, d.jobs, d.njobs, params,
-                           d.tiles);
+                           d.tiles, d.mems);
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, s, d.queue);
     if (dtype == SV_C128)
         hipLaunchKernelGGL(k_batched<double>, dim3(grid), dim3(kBatchThreads), kBatchDynLds, s, d.circs, d.order,
-                           ncirc, d.gates, d.passes, d.tiles, params, d.queue, stamps);
+                           ncirc, d.gates, d.passes, d.tiles, d.pats, d.mems, params, d.queue, stamps);
     else
         hipLaunchKernelGGL(k_batched<float>, dim3(grid), dim3(kBatchThreads), kBatchDynLds, s, d.circs, d.order,
-                           ncirc, d.gates, d.passes, d.tiles, params, d.queue, stamps);
+                           ncirc, d.gates, d.passes, d.tiles, d.pats, d.mems, params, d.queue, stamps);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess)
         return fail(SV_EHIP, "batched launch failed: %s", hipGetErrorString(e));
@@ -894,7 +926,7 @@ static int launch_adjoint(int dtype, const BatchDevice &d, int ncirc, const doub
     const unsigned grid = wide ? (unsigned)std::max(1, ncirc) : persistent_grid(ncirc);
     if (d.najobs > 0)
         hipLaunchKernelGGL(k_batch_tile_params, dim3((d.najobs + 255) / 256), dim3(256), 0, s, d.ajobs, d.najobs,
-                           params, d.atiles);
+                           params, d.atiles, nullptr);
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, s, d.queue);
     if (dtype == SV_C128)
         return wide ? go_adjoint<double, kBatchAdjMaxThreads>(d, ncirc, grid, lds, params, grad, loss, s, stamps)

@@ -21,7 +21,7 @@
 namespace sv {
 
 __global__ void k_param_mats(const ParamJob *__restrict__ jobs, int njobs, const double *__restrict__ params,
-                             double *__restrict__ mats, TileGate *__restrict__ tiles) {
+                             double *__restrict__ mats, TileGate *__restrict__ tiles, SweepMember *__restrict__ mems) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= njobs)
         return;
@@ -34,8 +34,12 @@ __global__ void k_param_mats(const ParamJob *__restrict__ jobs, int njobs, const
         TileGate &t = tiles[j.tile_slot];
         for (int k = 0; k < 8; ++k)
             t.m[k] = m[k];
-        if (t.diag)
+        if (t.diag) {
             diag_phases(m, t.ph, &t.unit);
+            for (int s = 0; s < 2; ++s)  // the phase-sweep members holding ph
+                if (t.mem[s] >= 0)
+                    mems[t.mem[s]].theta = t.ph[s];
+        }
     }
 }
 
@@ -196,7 +200,8 @@ static void apply_remap(sv_circuit *c) {
 }
 
 static int plan_circuit(sv_circuit *c, std::vector<TileGate> &tiles, std::vector<ParamJob> &jobs,
-                        std::vector<double> &mats, std::vector<DenseGate> &dense_list, int &dense_runs) {
+                        std::vector<double> &mats, std::vector<DenseGate> &dense_list, int &dense_runs,
+                        std::vector<SweepPat> &pats, std::vector<SweepMember> &mems) {
     const int G = (int)c->gates.size();
     mats.assign((size_t)G * 8, 0.0);
     for (int i = 0; i < G; ++i) {
@@ -334,6 +339,7 @@ static int plan_circuit(sv_circuit *c, std::vector<TileGate> &tiles, std::vector
                     k = e;
                 }
                 mark_diag_sweeps(&tiles[p.first], p.count, from_param.data());
+                build_sweep_patterns(&tiles[p.first], p.count, (int)p.tm.m, from_param.data(), pats, mems);
                 if (tuning().fuse_pairs)
                     mark_coset_pairs(&tiles[p.first], p.count);
                 c->passes.push_back(p);
@@ -405,7 +411,7 @@ static int plan_circuit(sv_circuit *c, std::vector<TileGate> &tiles, std::vector
 }
 
 static void free_buffers(sv_circuit *c, hipStream_t st) {
-    void *bufs[5] = {c->d_mats, c->d_tiles, c->d_jobs, c->d_dense, c->d_rmat};
+    void *bufs[7] = {c->d_mats, c->d_tiles, c->d_jobs, c->d_dense, c->d_rmat, c->d_pats, c->d_mems};
     for (void *b : bufs)
         if (b) {
             if (c->async_buffers)
@@ -418,6 +424,8 @@ static void free_buffers(sv_circuit *c, hipStream_t st) {
     c->d_jobs = nullptr;
     c->d_dense = nullptr;
     c->d_rmat = nullptr;
+    c->d_pats = nullptr;
+    c->d_mems = nullptr;
 }
 
 template <typename T> static int upload(T **dst, const std::vector<T> &src, bool async, hipStream_t st) {
@@ -491,9 +499,15 @@ int circuit_create(int n, int dtype, const sv_gate_t *gates, int ngates, int npa
     std::vector<ParamJob> jobs;
     std::vector<double> mats;
     std::vector<DenseGate> dense_list;
+    std::vector<SweepPat> pats;
+    std::vector<SweepMember> mems;
     int dense_runs = 0;
-    SV_TRY(plan_circuit(c.get(), tiles, jobs, mats, dense_list, dense_runs));
+    SV_TRY(plan_circuit(c.get(), tiles, jobs, mats, dense_list, dense_runs, pats, mems));
     int r = upload(&c->d_mats, mats, async, st);
+    if (r == SV_OK)
+        r = upload(&c->d_pats, pats, async, st);
+    if (r == SV_OK)
+        r = upload(&c->d_mems, mems, async, st);
     if (r == SV_OK)
         r = upload(&c->d_tiles, tiles, async, st);
     if (r == SV_OK)
@@ -526,7 +540,7 @@ int circuit_create(int n, int dtype, const sv_gate_t *gates, int ngates, int npa
 int circuit_param_mats(sv_circuit *c, const double *params, hipStream_t st) {
     if (c->njobs > 0) {
         hipLaunchKernelGGL(k_param_mats, dim3((c->njobs + 127) / 128), dim3(128), 0, st, c->d_jobs, c->njobs,
-                           params, c->d_mats, c->d_tiles);
+                           params, c->d_mats, c->d_tiles, c->d_mems);
         SV_LAUNCH_CHECK();
     }
     return SV_OK;
@@ -552,7 +566,7 @@ template <typename R> static int enqueue(sv_circuit *c, cplx_t<R> *psi, const do
                                         c->dense_k, rm, st));
             SV_TRY(launch_dense(c->dtype, psi, c->n, c->dense_k, rm, st));
         } else if (p.fused) {
-            DeviceGates dg{c->d_tiles + p.first, p.count};
+            DeviceGates dg{c->d_tiles + p.first, p.count, c->d_pats, c->d_mems};
             SV_TRY(launch_tile_pass<R>(psi, p.tm, dg, lds, st));
         } else {
             SV_TRY(launch_plan<R>(psi, p.plan, MatPtr<R>{c->d_mats + (size_t)8 * p.gate}, st));
@@ -658,7 +672,8 @@ int sv_circuit_plan(int n, int dtype, const sv_gate_t *gates, int ngates, int np
 namespace sv {
 
 int circuit_plan_tiles(int n, int dtype, const sv_gate_t *gates, int ngates, int nparams, int m_cap,
-                       std::vector<PlanPass> *passes, std::vector<TileGate> *tiles, int *m_used) {
+                       std::vector<PlanPass> *passes, std::vector<TileGate> *tiles, int *m_used,
+                       std::vector<SweepPat> *pats, std::vector<SweepMember> *mems) {
     if (dtype != SV_C128 && dtype != SV_C64)
         return fail(SV_EINVAL, "unknown dtype %d", dtype);
     if (n < 1 || n > max_qubits(dtype))
@@ -678,8 +693,14 @@ int circuit_plan_tiles(int n, int dtype, const sv_gate_t *gates, int ngates, int
     std::vector<double> mats;
     std::vector<DenseGate> dense_list;
     int dense_runs = 0;
+    std::vector<SweepPat> pv;
+    std::vector<SweepMember> mv;
     tiles->clear();
-    SV_TRY(plan_circuit(&c, *tiles, jobs, mats, dense_list, dense_runs));
+    SV_TRY(plan_circuit(&c, *tiles, jobs, mats, dense_list, dense_runs, pv, mv));
+    if (pats)
+        pats->swap(pv);
+    if (mems)
+        mems->swap(mv);
     passes->clear();
     for (const Pass &p : c.passes) {
         PlanPass q;
@@ -723,7 +744,9 @@ static int circuit_plan_order(int n, int dtype, const sv_gate_t *gates, int ngat
     std::vector<double> mats;
     std::vector<DenseGate> dense_list;
     int dense_runs = 0;
-    SV_TRY(plan_circuit(&c, tiles, jobs, mats, dense_list, dense_runs));
+    std::vector<SweepPat> pats;
+    std::vector<SweepMember> mems;
+    SV_TRY(plan_circuit(&c, tiles, jobs, mats, dense_list, dense_runs, pats, mems));
     int k = 0;
     for (size_t pi = 0; pi < c.passes.size(); ++pi) {
         const Pass &p = c.passes[pi];

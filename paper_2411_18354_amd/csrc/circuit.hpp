@@ -40,6 +40,8 @@ struct sv_circuit {
     double *d_mats = nullptr;
     sv::TileGate *d_tiles = nullptr;
     sv::ParamJob *d_jobs = nullptr;
+    sv::SweepPat *d_pats = nullptr;      // phase patterns of the table sweeps
+    sv::SweepMember *d_mems = nullptr;   // and their members
     bool async_buffers = false;  // allocated stream-ordered (one-shot use)
     hipStream_t cap = nullptr;
     hipGraph_t graph = nullptr;
@@ -64,8 +66,11 @@ struct PlanPass {
     TileMap tm;
     int32_t fused, gate, first, count;
 };
+// pats/mems (optional): the phase patterns of the table sweeps, indexed
+// from 0 (pat0 and mem[] of the descriptors refer to them).
 int circuit_plan_tiles(int n, int dtype, const sv_gate_t *gates, int ngates, int nparams, int m_cap,
-                       std::vector<PlanPass> *passes, std::vector<TileGate> *tiles, int *m_used);
+                       std::vector<PlanPass> *passes, std::vector<TileGate> *tiles, int *m_used,
+                       std::vector<SweepPat> *pats = nullptr, std::vector<SweepMember> *mems = nullptr);
 
 int circuit_create(int n, int dtype, const sv_gate_t *gates, int ngates, int nparams, int flags, bool async,
                    hipStream_t st, int m_cap, sv_circuit **out);

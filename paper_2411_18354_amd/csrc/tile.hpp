@@ -27,6 +27,28 @@ namespace sv {
 constexpr int kTileSeg = 16;   // m <= 14 gives at most 15 segments
 constexpr int kTileMaxLog = 14;
 constexpr int kTileMaxHigh = 8;  // qubits of S above the contiguous low block
+// Phase patterns of one diagonal sweep: at most this many (their per-tile
+// phases sit in LDS after the tables); a longer sweep is split.
+constexpr int kSweepMaxPats = 512;
+// pattern classes of a sweep: A, B, one per tile-local bit q >= 6 (R[q], or
+// D in class 2), then the per-amplitude rest; one slot more for the end
+constexpr int kSweepClassSlots = 12;
+
+// A condition (j & lmask) == lvals on the tile-local index j under which the
+// phases of the members [first, first + count) are added.
+struct SweepPat {
+    uint32_t lmask, lvals;
+    uint32_t first, count;
+};
+
+// One phase of a diagonal gate in a sweep: theta is added where the tile's
+// outer index bits satisfy (base & om) == ov (the gate's controls outside S,
+// and its target bit when the target is outside S) and the pattern holds.
+struct SweepMember {
+    uint64_t om, ov;
+    double theta;
+    uint64_t pad;
+};
 
 struct TileGate {
     // The first 64 bytes hold what the loops over a run read for every gate,
@@ -61,7 +83,14 @@ struct TileGate {
     uint32_t shift[kTileSeg];
     uint32_t mask[kTileSeg];
     int32_t src_gate;     // index of the gate in its circuit (host bookkeeping)
-    int32_t pad2;
+    // first gate of a diagonal sweep that uses the phase tables: its first
+    // phase pattern (an index into the run's pattern array) and the start of
+    // each pattern class relative to it (see build_sweep_patterns)
+    uint32_t pat0;
+    uint32_t sweep_cls[kSweepClassSlots];
+    // diagonal gate: the phase-pattern members that hold its phases ph[0]
+    // and ph[1] (-1: none), refreshed with ph when the angle is a parameter
+    int32_t mem[2];
 };
 
 // Summary bits of a diagonal sweep's gates (host), kept in the first gate's
@@ -75,6 +104,19 @@ constexpr uint32_t kSweepHaveR = 1u << 16, kSweepRank1 = 1u << 17, kSweepAnyRest
 // block's first gate.  param_gate[i] != 0: the entries of gate i come from parameters at
 // run time (their kinds are unitary), so it counts as unit modulus.
 void mark_diag_sweeps(TileGate *tiles, int count, const char *param_gate);
+
+// Phase patterns of the table sweeps among tiles[0 .. count) (one fused run
+// over tiles of width m >= 7, after mark_diag_sweeps; host).  Every phase
+// of a sweep's gates becomes a member of the pattern given by its tile-local
+// condition (controls in S, and the target bit when the target is in S),
+// with a predicate on the outer bits; gates with the same tile-local
+// condition share one pattern.  Patterns are appended to pats sorted by
+// class (A, B, R[q] or D, rest) in order of first appearance, members in
+// gate order; the sweep's first gate gets pat0, sweep_cls and the table
+// summary, and each gate the indices of its members.  A sweep with more
+// than kSweepMaxPats patterns is split into several sweeps.
+void build_sweep_patterns(TileGate *tiles, int count, int m, const char *param_gate, std::vector<SweepPat> &pats,
+                          std::vector<SweepMember> &mems);
 
 // Mark coset pairs among tiles[0 .. count) (one fused run; host): two
 // adjacent pair gates on different tile-local targets t1, t2 whose
@@ -116,10 +158,14 @@ struct TileMap {
 };
 
 // Doubles of the diagonal-sweep tables for tile width m (0 below m = 7):
-// A[64] over tile-local bits 0..5, B[2^(m-6)] over bits 6..m-1, and for each
-// bit q >= 6 and value b a row R[q][b][64] over bits 0..5.
+// A[64] over tile-local bits 0..5, B[2^(m-6)] over bits 6..m-1, for each
+// bit q >= 6 and value b a row R[q][b][64] over bits 0..5, then the phases
+// of up to kSweepMaxPats patterns for the current tile.
+__host__ __device__ inline uint32_t diag_pattern_offset(uint32_t m) {
+    return 64u + (1u << (m - 6)) + (m - 6) * 128u;
+}
 __host__ __device__ inline uint32_t diag_table_doubles(uint32_t m) {
-    return m < 7 ? 0u : 64u + (1u << (m - 6)) + (m - 6) * 128u;
+    return m < 7 ? 0u : diag_pattern_offset(m) + (uint32_t)kSweepMaxPats;
 }
 
 // Tile map for S = {0 .. a-1} u high (host).  high: ascending qubits >= a;
@@ -138,14 +184,31 @@ template <int NG> struct InlineGates {
     int count;
     __device__ __forceinline__ const TileGate &get(int i) const { return g[i]; }
     __device__ __forceinline__ int size() const { return count; }
+    // no phase patterns: sweeps take the per-amplitude path
+    __device__ __forceinline__ const SweepPat *pats() const { return nullptr; }
+    __device__ __forceinline__ const SweepMember *mems() const { return nullptr; }
 };
 
+// A run's descriptors in device memory, with the phase patterns of its
+// table sweeps (null: sweeps take the per-amplitude path).
 struct DeviceGates {
     const TileGate *g;
     int count;
+    const SweepPat *p = nullptr;
+    const SweepMember *mm = nullptr;
     __device__ __forceinline__ const TileGate &get(int i) const { return g[i]; }
     __device__ __forceinline__ int size() const { return count; }
+    __device__ __forceinline__ const SweepPat *pats() const { return p; }
+    __device__ __forceinline__ const SweepMember *mems() const { return mm; }
 };
+
+// sweep_len (low half) and sweep_phase (high half) read as one 32-bit word,
+// which keeps the read a scalar load
+__device__ __forceinline__ uint32_t sweep_word(const TileGate &g) {
+    uint32_t w;
+    __builtin_memcpy(&w, &g.sweep_len, sizeof(w));
+    return __builtin_amdgcn_readfirstlane(w);
+}
 
 template <typename R>
 __device__ __forceinline__ Mat2<R> tile_mat(const TileGate &g) {
@@ -327,104 +390,60 @@ __device__ __forceinline__ void diag_sweep_phases(cplx_t<R> *tile, uint64_t base
     __syncthreads();
 }
 
-// Phase of one diagonal gate at tile-local index j (0 unless its tile-local
-// controls hold there); tone: its target bit when the target is outside S.
-__device__ __forceinline__ double diag_phase_at(const TileGate &d, uint32_t j, bool tone, double p0, double p1) {
-    const bool one = d.l_target >= 0 ? ((j >> d.l_target) & 1u) : tone;
-    return ((j & d.l_mask) == d.l_vals) ? (one ? p1 : p0) : 0.0;
-}
-
-// The fields of a diagonal gate the sweep tables read.
-struct SweepFields {
-    uint64_t o_mask, o_vals;
-    uint32_t l_mask, l_vals, target;
-    int32_t l_target;
-    double p0, p1;
-};
-
-__device__ __forceinline__ double diag_phase_at(const SweepFields &d, uint32_t j, bool tone) {
-    const bool one = d.l_target >= 0 ? ((j >> d.l_target) & 1u) : tone;
-    return ((j & d.l_mask) == d.l_vals) ? (one ? d.p1 : d.p0) : 0.0;
-}
-
-// Visit the diagonal gates [i, e) in order with wave-uniform fields (the
-// descriptors are read with scalar loads).
-template <typename Src, typename F>
-__device__ __forceinline__ void for_sweep_gates(const Src &gates, int i, int e, F f) {
-    for (int q = i; q < e; ++q) {
-        const TileGate &d = gates.get(q);
-        f(SweepFields{d.o_mask, d.o_vals, d.l_mask, d.l_vals, d.target, d.l_target, uniform_f64(d.ph[0]),
-                      uniform_f64(d.ph[1])});
-    }
-}
-
-// Long unit-modulus sweep with tables.  The phase of amplitude j is a sum of
-// gate terms, each depending on the few tile-local bits the gate reads.  With
-// u = bits 0..5 of j and v = bits 6..m-1:
-//   theta(j) = th0 + A[u] + B[v] + sum over q of R[q][bit q of v][u] + rest,
-// where A collects the gates reading only bits of u, B those reading only
-// bits of v, R[q] those reading bits of u and the single bit 6+q, and rest
-// (evaluated per amplitude) those reading bits of u and two or more bits of
-// v.  When every gate of the R[q] kind depends on u through one condition
-// (u & um) == uv (a target bit in u counting as a required 1 when its
-// zero-side phase is 0, as for controlled phases sharing a target), their
-// terms sum to [(u & um) == uv] * D[v] with a single table D instead of the
-// m-6 tables R[q].  Each wavefront builds whole tables (one lane per entry,
-// skipping the gates of other tables), so the per-amplitude cost is a
-// handful of LDS reads whatever the sweep's length.
+// Long unit-modulus sweep with tables.  The host turned the sweep's gates
+// into phase patterns (build_sweep_patterns): a pattern adds its members'
+// phases where a condition on the tile-local index j holds, each member
+// only in tiles whose outer bits satisfy its predicate.  Per tile, the
+// wavefronts first sum each pattern's members that hold for this tile.
+// Then with u = bits 0..5 of j and v = bits 6..m-1,
+//   theta(j) = A[u] + B[v] + sum over q of R[q][bit q of v][u] + rest,
+// where A collects the patterns reading only bits of u (or none), B those
+// reading only bits of v, R[q] those reading bits of u and the single bit
+// 6+q, and rest (evaluated per amplitude) those reading bits of u and two or
+// more bits of v.  When every R-type pattern depends on u through one
+// condition (u & um) == uv, their terms sum to [(u & um) == uv] * D[v] with
+// a single table D instead of the m-6 tables R[q].  Patterns come sorted by
+// table, so a wavefront building a table walks only that table's patterns;
+// every walk is wave-uniform (scalar loads of the host's records).
 template <typename R, int THREADS, typename Src>
 __device__ __forceinline__ void diag_sweep_tables(cplx_t<R> *tile, double *tab, uint64_t base, uint32_t m,
-                                                  const Src &gates, int i, int e) {
+                                                  const Src &gates, int i) {
     const uint32_t T = 1u << m;
     const int Hb = (int)m - 6;
     double *A = tab, *B = tab + 64, *Rt = tab + 64 + (1 << Hb);
-    // the wavefront index is uniform: keep it (and the table loop) scalar
+    double *thp = tab + diag_pattern_offset(m);  // this tile's pattern phases
+    // the wavefront index is uniform: keep it (and the pattern loops) scalar
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
-    double th0 = 0.0;
-    bool any_rest = false, have_r = false, rank1 = true;
-    uint32_t um = 0, uv = 0;
-    // The host's summary of the sweep, when present, replaces a walk over its
-    // gates in every wavefront; the tile-uniform phases then go into A.
-    const uint32_t info = __builtin_amdgcn_readfirstlane(gates.get(i).npairs);
-    const bool summary = (info & kSweepInfoValid) != 0;
-    if (summary) {
-        um = info & 63u;
-        uv = (info >> 8) & 63u;
-        have_r = (info & kSweepHaveR) != 0;
-        rank1 = (info & kSweepRank1) != 0;
-        any_rest = (info & kSweepAnyRest) != 0;
-    } else for_sweep_gates(gates, i, e, [&](const SweepFields &d) {
-        if ((base & d.o_mask) != d.o_vals)
-            return;
-        const uint32_t lm = d.l_mask | (d.l_target >= 0 ? 1u << d.l_target : 0u);
-        if (lm == 0) {
-            th0 += ((base >> d.target) & 1ull) ? d.p1 : d.p0;
-        } else if ((lm & 63u) && __popc(lm >> 6) > 1) {
-            any_rest = true;
-        } else if ((lm & 63u) && (lm >> 6)) {  // an R[q] gate: its condition on u
-            uint32_t gm = d.l_mask & 63u, gv = d.l_vals & 63u;
-            if (d.l_target >= 0 && d.l_target < 6) {
-                if (d.p0 != 0.0)
-                    rank1 = false;
-                gm |= 1u << d.l_target;
-                gv |= 1u << d.l_target;
-            }
-            if (!have_r) {
-                um = gm;
-                uv = gv;
-                have_r = true;
-            } else if (gm != um || gv != uv) {
-                rank1 = false;
-            }
+    constexpr int kWaves = THREADS / 64;
+    const TileGate &g = gates.get(i);
+    const uint32_t info = __builtin_amdgcn_readfirstlane(g.npairs);
+    const uint32_t um = info & 63u, uv = (info >> 8) & 63u;
+    const bool have_r = (info & kSweepHaveR) != 0, rank1 = (info & kSweepRank1) != 0;
+    const bool any_rest = (info & kSweepAnyRest) != 0;
+    const SweepPat *P = gates.pats() + __builtin_amdgcn_readfirstlane(g.pat0);
+    const SweepMember *M = gates.mems();
+    const uint32_t np = __builtin_amdgcn_readfirstlane(g.sweep_cls[3 + Hb]);
+    // 1. pattern phases of this tile: one wavefront per pattern
+    for (uint32_t p = (uint32_t)w; p < np; p += kWaves) {
+        const uint32_t f = __builtin_amdgcn_readfirstlane(P[p].first);
+        const uint32_t e = f + __builtin_amdgcn_readfirstlane(P[p].count);
+        double s = 0.0;
+        for (uint32_t k = f; k < e; ++k) {
+            const SweepMember &mm = M[k];
+            if ((base & mm.om) == mm.ov)  // uniform
+                s += uniform_f64(mm.theta);
         }
-    });
+        if (lane == 0)
+            thp[p] = s;
+    }
+    __syncthreads();
     const bool use_d = have_r && rank1;
-    // table tb: 0 = A, 1 = B, then D (use_d) or 2 + q = R[q] (R gates of
+    // table tb: 0 = A, 1 = B, then D (use_d) or 2 + q = R[q] (R patterns of
     // several conditions); entries per lane: A 1, B and D ceil(2^Hb / 64)
     // (lanes beyond 2^Hb idle when Hb < 6), R 2.  D uses the R area.
     const uint32_t nb = 1u << Hb;
     const int ntab = 2 + (!have_r ? 0 : (use_d ? 1 : Hb));
-    for (int tb = w; tb < ntab; tb += THREADS / 64) {  // uniform per wavefront
+    for (int tb = w; tb < ntab; tb += kWaves) {  // uniform per wavefront
         const bool dtab = use_d && tb == 2;
         const int ne = tb == 0 ? 1 : ((tb == 1 || dtab) ? (int)((nb + 63) / 64) : 2);
         double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
@@ -435,26 +454,20 @@ __device__ __forceinline__ void diag_sweep_tables(cplx_t<R> *tile, double *tab, 
                    : dtab    ? ((uint32_t)(lane + 64 * k) << 6) | uv
                              : (uint32_t)lane | ((uint32_t)k << (4 + tb));
         };
-        for_sweep_gates(gates, i, e, [&](const SweepFields &d) {
-            if ((base & d.o_mask) != d.o_vals)
-                return;  // uniform
-            const uint32_t lm = d.l_mask | (d.l_target >= 0 ? 1u << d.l_target : 0u);
-            const uint32_t lo = lm & 63u, hi = lm >> 6;
-            const bool mine = tb == 0   ? ((lo && !hi) || (summary && lm == 0))
-                              : tb == 1 ? (hi && !lo)
-                              : dtab    ? (lo && __popc(hi) == 1)
-                                        : (lo && hi == (1u << (tb - 2)));
-            if (!mine)
-                return;  // uniform
-            const bool tone = (base >> d.target) & 1ull;
-            acc0 += diag_phase_at(d, at(0), tone);
+        const uint32_t c0 = __builtin_amdgcn_readfirstlane(g.sweep_cls[tb]);
+        const uint32_t c1 = __builtin_amdgcn_readfirstlane(g.sweep_cls[tb + 1]);
+        for (uint32_t p = c0; p < c1; ++p) {
+            const uint32_t lm = __builtin_amdgcn_readfirstlane(P[p].lmask);
+            const uint32_t lv = __builtin_amdgcn_readfirstlane(P[p].lvals);
+            const double th = thp[p];
+            acc0 += (at(0) & lm) == lv ? th : 0.0;
             if (ne > 1)
-                acc1 += diag_phase_at(d, at(1), tone);
+                acc1 += (at(1) & lm) == lv ? th : 0.0;
             if (ne > 2) {
-                acc2 += diag_phase_at(d, at(2), tone);
-                acc3 += diag_phase_at(d, at(3), tone);
+                acc2 += (at(2) & lm) == lv ? th : 0.0;
+                acc3 += (at(3) & lm) == lv ? th : 0.0;
             }
-        });
+        }
         double *dst = tb == 0 ? A : tb == 1 ? B : Rt + (tb - 2) * 128;
         if ((tb != 1 && !dtab) || (uint32_t)lane < nb)
             dst[lane] = acc0;
@@ -478,7 +491,7 @@ __device__ __forceinline__ void diag_sweep_tables(cplx_t<R> *tile, double *tab, 
         cplx_t<R> *FB = FA + 64, *FD = FB + nb;
         const uint32_t nf = 64 + (use_d ? 2 : 1) * nb;
         for (uint32_t k = threadIdx.x; k < nf; k += THREADS) {
-            const double ph = k < 64 ? th0 + A[k] : (k < 64 + nb ? B[k - 64] : Rt[k - 64 - nb]);
+            const double ph = k < 64 ? A[k] : (k < 64 + nb ? B[k - 64] : Rt[k - 64 - nb]);
             R fr, fi;
             phase_factor<R>(ph, &fr, &fi);
             cplx_t<R> f;
@@ -508,9 +521,10 @@ __device__ __forceinline__ void diag_sweep_tables(cplx_t<R> *tile, double *tab, 
         __syncthreads();
         return;
     }
+    const uint32_t r0 = __builtin_amdgcn_readfirstlane(g.sweep_cls[2 + Hb]);
     for (uint32_t j = threadIdx.x; j < T; j += THREADS) {
         const uint32_t u = j & 63u, v = j >> 6;
-        double t = th0 + A[u] + B[v];
+        double t = A[u] + B[v];
         if (use_d) {  // uniform
             t += ((u & um) == uv) ? Rt[v] : 0.0;
         } else if (have_r) {
@@ -518,12 +532,10 @@ __device__ __forceinline__ void diag_sweep_tables(cplx_t<R> *tile, double *tab, 
                 t += Rt[q * 128 + ((v >> q) & 1u) * 64 + u];
         }
         if (any_rest) {  // uniform
-            for (int q = i; q < e; ++q) {
-                const TileGate &d = gates.get(q);
-                const uint32_t lm = d.l_mask | (d.l_target >= 0 ? 1u << d.l_target : 0u);
-                if ((base & d.o_mask) != d.o_vals || !(lm & 63u) || __popc(lm >> 6) < 2)
-                    continue;  // uniform
-                t += diag_phase_at(d, j, (base >> d.target) & 1ull, uniform_f64(d.ph[0]), uniform_f64(d.ph[1]));
+            for (uint32_t p = r0; p < np; ++p) {
+                const uint32_t lm = __builtin_amdgcn_readfirstlane(P[p].lmask);
+                const uint32_t lv = __builtin_amdgcn_readfirstlane(P[p].lvals);
+                t += (j & lm) == lv ? thp[p] : 0.0;
             }
         }
         R fr, fi;
@@ -627,7 +639,8 @@ __device__ __forceinline__ void tile_run(cplx_t<R> *tile, uint64_t base, const T
         const TileGate &g = gates.get(i);
         if (g.diag) {
             // the block marked on the host, kept inside the run
-            const int e = min(gates.size(), i + max(1, (int)g.sweep_len));
+            const uint32_t sw = sweep_word(g);
+            const int e = min(gates.size(), i + max(1, (int)(sw & 0xffffu)));
             // Diagonal gates commute, so the sweep multiplies each amplitude
             // by the product of its factors.  Gates whose target and controls
             // all lie outside S give the whole tile one factor (computed
@@ -636,9 +649,9 @@ __device__ __forceinline__ void tile_run(cplx_t<R> *tile, uint64_t base, const T
             // turned into one factor per amplitude at the end.
             // Long sweeps whose factors all have unit modulus add phases
             // (one sine and cosine per amplitude); short ones multiply.
-            if (g.sweep_phase) {  // uniform
-                if (tm.tab && tm.m >= 7)
-                    diag_sweep_tables<R, THREADS>(tile, reinterpret_cast<double *>(tile + T), base, tm.m, gates, i, e);
+            if (sw >> 16) {  // uniform: a phase sweep
+                if (tm.tab && tm.m >= 7 && gates.pats() != nullptr)
+                    diag_sweep_tables<R, THREADS>(tile, reinterpret_cast<double *>(tile + T), base, tm.m, gates, i);
                 else
                     diag_sweep_phases<R, THREADS>(tile, base, T, gates, i, e);
                 i = e;
@@ -701,7 +714,7 @@ __device__ __forceinline__ void tile_run(cplx_t<R> *tile, uint64_t base, const T
             i = e;
             continue;
         }
-        if (g.sweep_len == 2 && i + 1 < gates.size()) {  // a coset pair (uniform)
+        if ((sweep_word(g) & 0xffffu) == 2 && i + 1 < gates.size()) {  // a coset pair (uniform)
             const TileGate &g2 = gates.get(i + 1);
             const bool p1 = (base & g.hi_mask) == g.hi_vals, p2 = (base & g2.hi_mask) == g2.hi_vals;
             if (p1 && p2) {  // uniform across the workgroup

@@ -276,14 +276,15 @@ __device__ __forceinline__ void adj_tile_run(cplx_t<R> *tp, cplx_t<R> *tl, uint6
     for (int i = 0; i < gates.size(); ++i) {
         const TileGate &g = gates.get(i);
         const int sl = gslot[i];
-        if (g.diag && g.sweep_len > 1) {  // a block of diagonal gates (uniform)
-            const int e = min(gates.size(), i + (int)g.sweep_len);
+        const uint32_t slen = sweep_word(g) & 0xffffu;
+        if (g.diag && slen > 1) {  // a block of diagonal gates (uniform)
+            const int e = min(gates.size(), i + (int)slen);
             kacc = adj_diag_block<R, THREADS>(tp, tl, base, T, gates, i, e, gslot, gens, accl, kacc);
             __syncthreads();
             i = e - 1;
             continue;
         }
-        if (!g.diag && g.sweep_len == 2 && i + 1 < gates.size()) {  // a coset pair (uniform)
+        if (!g.diag && slen == 2 && i + 1 < gates.size()) {  // a coset pair (uniform)
             const TileGate &g2 = gates.get(i + 1);
             if ((base & g.hi_mask) == g.hi_vals && (base & g2.hi_mask) == g2.hi_vals) {
                 const int sl2 = gslot[i + 1];

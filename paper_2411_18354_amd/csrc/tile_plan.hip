@@ -56,45 +56,6 @@ TileMap make_tile_map(int n, int m, int a, const std::vector<int> &high, uint64_
 
 TileMap contiguous_tile_map(int n, int m) { return make_tile_map(n, m, m, {}); }
 
-// What the phase tables of a sweep need to know about its gates, the same
-// for every tile (the first gate's npairs, unused by diagonal gates; see
-// diag_sweep_tables): whether gates reading bits of u and one bit of v
-// exist (R-type) and all depend on u through one condition (u & um) == uv,
-// and whether gates reading bits of u and two or more bits of v exist.  A
-// target bit in u counts as a required 1 only when the phase on its 0 side
-// is known to be 0 (not a parameterised gate).
-static uint32_t sweep_table_info(const TileGate *t, int count, const char *param_gate) {
-    bool have_r = false, rank1 = true, any_rest = false;
-    uint32_t um = 0, uv = 0;
-    for (int q = 0; q < count; ++q) {
-        const TileGate &d = t[q];
-        const uint32_t lm = d.l_mask | (d.l_target >= 0 ? 1u << d.l_target : 0u);
-        const uint32_t lo = lm & 63u, hi = lm >> 6;
-        if (!lo || !hi)
-            continue;
-        if (__builtin_popcount(hi) > 1) {
-            any_rest = true;
-            continue;
-        }
-        uint32_t gm = d.l_mask & 63u, gv = d.l_vals & 63u;
-        if (d.l_target >= 0 && d.l_target < 6) {
-            if (param_gate[q] || d.ph[0] != 0.0)
-                rank1 = false;
-            gm |= 1u << d.l_target;
-            gv |= 1u << d.l_target;
-        }
-        if (!have_r) {
-            um = gm;
-            uv = gv;
-            have_r = true;
-        } else if (gm != um || gv != uv) {
-            rank1 = false;
-        }
-    }
-    return kSweepInfoValid | um | (uv << 8) | (have_r ? kSweepHaveR : 0u) | (have_r && rank1 ? kSweepRank1 : 0u) |
-           (any_rest ? kSweepAnyRest : 0u);
-}
-
 void mark_diag_sweeps(TileGate *t, int count, const char *param_gate) {
     int k = 0;
     while (k < count) {
@@ -112,8 +73,165 @@ void mark_diag_sweeps(TileGate *t, int count, const char *param_gate) {
         }
         t[k].sweep_len = (uint16_t)(e - k);
         t[k].sweep_phase = (unit && nlocal >= kPhaseSweepMin) ? 1 : 0;
-        t[k].npairs = sweep_table_info(t + k, e - k, param_gate + k);
         k = e;
+    }
+}
+
+namespace {
+
+// One phase of a sweep gate before grouping: its tile-local condition and
+// its member record.
+struct PhasePart {
+    uint32_t lm, lv;
+    SweepMember mem;
+    int gate, slot;  // the gate (index in the run) and which of its phases
+};
+
+// Parts of diagonal gate d: ph[1] where its target bit is 1, ph[0] where it
+// is 0; a phase known to be 0 adds nothing and is left out (a parameterised
+// gate keeps both, its angle changes between runs).
+int phase_parts(const TileGate &d, int q, bool param, PhasePart *out) {
+    int np = 0;
+    for (int s = 0; s < 2; ++s) {
+        if (!param && d.ph[s] == 0.0)
+            continue;
+        PhasePart pt;
+        pt.lm = d.l_mask;
+        pt.lv = d.l_vals;
+        pt.mem = SweepMember{d.o_mask, d.o_vals, d.ph[s], 0};
+        if (d.l_target >= 0) {
+            pt.lm |= 1u << d.l_target;
+            pt.lv |= (uint32_t)s << d.l_target;
+        } else {
+            pt.mem.om |= 1ull << d.target;
+            pt.mem.ov |= (uint64_t)s << d.target;
+        }
+        pt.gate = q;
+        pt.slot = s;
+        out[np++] = pt;
+    }
+    return np;
+}
+
+} // namespace
+
+void build_sweep_patterns(TileGate *t, int count, int m, const char *param_gate, std::vector<SweepPat> &pats,
+                          std::vector<SweepMember> &mems) {
+    if (m < 7)
+        return;  // no tables below 7 tile qubits
+    const int Hb = m - 6;
+    for (int k = 0; k < count;) {
+        if (!t[k].diag) {
+            ++k;
+            continue;
+        }
+        int end = std::min(count, k + std::max(1, (int)t[k].sweep_len));
+        if (!t[k].sweep_phase) {
+            k = end;
+            continue;
+        }
+        // the gates' phases, grouped by tile-local condition (first
+        // appearance numbers the patterns); a sweep that would exceed
+        // kSweepMaxPats patterns ends before the gate that would
+        std::vector<PhasePart> parts;
+        std::vector<std::pair<uint64_t, int>> keys;  // (lm << 32 | lv, pattern id), ordered by key
+        auto find = [&](uint64_t key) -> int {
+            auto it = std::lower_bound(keys.begin(), keys.end(), std::make_pair(key, -1));
+            return (it != keys.end() && it->first == key) ? it->second : -1;
+        };
+        std::vector<int> part_pat;
+        int q = k;
+        for (; q < end; ++q) {
+            PhasePart c[2];
+            const int nc = phase_parts(t[q], q, param_gate[q] != 0, c);
+            int add = 0;
+            for (int i = 0; i < nc; ++i) {
+                const uint64_t key = ((uint64_t)c[i].lm << 32) | c[i].lv;
+                if (find(key) < 0 && !(i == 1 && nc == 2 && c[0].lm == c[1].lm && c[0].lv == c[1].lv))
+                    ++add;
+            }
+            if (q > k && (int)keys.size() + add > kSweepMaxPats)
+                break;
+            for (int i = 0; i < nc; ++i) {
+                const uint64_t key = ((uint64_t)c[i].lm << 32) | c[i].lv;
+                int id = find(key);
+                if (id < 0) {
+                    id = (int)keys.size();
+                    keys.insert(std::lower_bound(keys.begin(), keys.end(), std::make_pair(key, -1)),
+                                std::make_pair(key, id));
+                }
+                parts.push_back(c[i]);
+                part_pat.push_back(id);
+            }
+        }
+        if (q < end) {  // split: [k, q) now, [q, end) as a sweep of its own
+            t[q].sweep_len = (uint16_t)(end - q);
+            t[q].sweep_phase = 1;
+            t[k].sweep_len = (uint16_t)(q - k);
+            end = q;
+        }
+        const int npat = (int)keys.size();
+        std::vector<uint32_t> plm(npat), plv(npat);
+        for (size_t i = 0; i < parts.size(); ++i) {
+            plm[part_pat[i]] = parts[i].lm;
+            plv[part_pat[i]] = parts[i].lv;
+        }
+        // classes: 0 = A (bits of u only, or none), 1 = B (bits of v only),
+        // 2 + q = R[q] (bits of u and bit 6 + q), 2 + Hb = rest
+        std::vector<int> cls(npat);
+        bool have_r = false, rank1 = true, any_rest = false;
+        uint32_t um = 0, uv = 0;
+        for (int p = 0; p < npat; ++p) {
+            const uint32_t lo = plm[p] & 63u, hi = plm[p] >> 6;
+            if (!hi) {
+                cls[p] = 0;
+            } else if (!lo) {
+                cls[p] = 1;
+            } else if (__builtin_popcount(hi) == 1) {
+                cls[p] = 2 + __builtin_ctz(hi);
+                if (!have_r) {
+                    um = lo;
+                    uv = plv[p] & 63u;
+                    have_r = true;
+                } else if (lo != um || (plv[p] & 63u) != uv) {
+                    rank1 = false;
+                }
+            } else {
+                cls[p] = 2 + Hb;
+                any_rest = true;
+            }
+        }
+        if (have_r && rank1)  // one table D: every R pattern in class 2
+            for (int p = 0; p < npat; ++p)
+                if (cls[p] >= 2 && cls[p] < 2 + Hb)
+                    cls[p] = 2;
+        // emit patterns by class, then each pattern's members in gate order
+        std::vector<int> order(npat);
+        for (int p = 0; p < npat; ++p)
+            order[p] = p;
+        std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return cls[x] < cls[y]; });
+        std::vector<std::vector<int>> members(npat);
+        for (size_t i = 0; i < parts.size(); ++i)
+            members[part_pat[i]].push_back((int)i);
+        TileGate &h = t[k];
+        h.pat0 = (uint32_t)pats.size();
+        for (int c = 0; c < kSweepClassSlots; ++c)
+            h.sweep_cls[c] = (uint32_t)npat;
+        for (int r = npat - 1; r >= 0; --r)
+            h.sweep_cls[cls[order[r]]] = (uint32_t)r;
+        for (int c = kSweepClassSlots - 2; c >= 0; --c)  // empty classes start where the next one does
+            h.sweep_cls[c] = std::min(h.sweep_cls[c], h.sweep_cls[c + 1]);
+        for (int r = 0; r < npat; ++r) {
+            const int p = order[r];
+            pats.push_back(SweepPat{plm[p], plv[p], (uint32_t)mems.size(), (uint32_t)members[p].size()});
+            for (int i : members[p]) {
+                t[parts[i].gate].mem[parts[i].slot] = (int32_t)mems.size();
+                mems.push_back(parts[i].mem);
+            }
+        }
+        h.npairs = kSweepInfoValid | um | (uv << 8) | (have_r ? kSweepHaveR : 0u) |
+                   (have_r && rank1 ? kSweepRank1 : 0u) | (any_rest ? kSweepAnyRest : 0u);
+        k = end;
     }
 }
 
@@ -147,6 +265,7 @@ TileGate make_tile_gate(const TileMap &tm, int target, uint64_t cmask, uint64_t 
     memset(&g, 0, sizeof(g));
     for (int i = 0; i < 8; ++i)
         g.m[i] = U[i];
+    g.mem[0] = g.mem[1] = -1;
     if (diagonal) {
         g.diag = 1;
         g.sweep_len = 1;  // a block of one unless a run marks a longer one
