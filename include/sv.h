@@ -203,6 +203,9 @@ int sv_hbm_probe(const sv_state_t *s, uint64_t fixed_mask, uint64_t fixed_vals, 
  *   "fuse_pairs"      [0, 1]  apply two adjacent pair gates of a fused run
  *       together over 4-amplitude cosets when each one's tile-local controls
  *       lie only on the other's target
+ *   "plan_lookahead"  [0, 1]  pick a fused run's tile qubits one at a time,
+ *       each the target that lets the run take the most of the next gates
+ *       (0: the first targets met, in order)
  * None of them changes results beyond floating-point rounding (fusion
  * choices change the order in which commuting operations are rounded).
  * SV_EINVAL for an unknown key or a value out of range.  Not thread-safe

@@ -97,18 +97,10 @@ __global__ __launch_bounds__(kAdjTileThreads, 4) void k_adj_tile(cplx_t<R> *__re
         const uint64_t base = expand_index<uint64_t>(tm.outer, t);
         if (!adj_tile_touched(base, gates))
             continue;  // uniform
-        for (uint32_t j = threadIdx.x; j < T; j += kAdjTileThreads) {
-            const uint64_t k = base | tile_offset(tm, j);
-            tp[j] = ld_stream<R>(psi + k);
-            tl[j] = ld_stream<R>(lam + k);
-        }
+        tile_load2<R, kAdjTileThreads>(tp, tl, psi, lam, base, tm, T);
         __syncthreads();
         adj_tile_run<R, kAdjTileThreads>(tp, tl, base, T, gates, gslot, gens, accl);
-        for (uint32_t j = threadIdx.x; j < T; j += kAdjTileThreads) {
-            const uint64_t k = base | tile_offset(tm, j);
-            st_stream<R>(psi + k, tp[j]);
-            st_stream<R>(lam + k, tl[j]);
-        }
+        tile_store2<R, kAdjTileThreads>(psi, lam, tp, tl, base, tm, T);
         __syncthreads();
     }
     // this workgroup's partial of every parameterised gate: its wavefronts'

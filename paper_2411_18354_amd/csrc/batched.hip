@@ -37,6 +37,10 @@ int validate_unitary_gate(const sv_gate_t &g, int index);
 
 constexpr int kBatchThreads = 512;
 constexpr int kBatchAdjMaxThreads = 1024;  // the batched adjoint's wider shape
+// amplitudes per lane in flight when the batched adjoint copies a tile pair
+// (the batched kernels have fewer registers to spare than the
+// single-circuit ones; the forward one copies one amplitude at a time)
+constexpr int kBatchCopy = 2;
 constexpr size_t kBatchLds = 65536;  // the tile (or a whole resident state)
 // dynamic LDS: the work-item slot, the tile, then the diagonal-sweep tables
 constexpr size_t kBatchSlot = 64;
@@ -181,12 +185,10 @@ __device__ void run_circuit_block(const BCirc &c, const BGate *__restrict__ gate
                 const uint64_t base = expand_index<uint64_t>(p.tm.outer, tt);
                 if (!tile_touched(base, dg))
                     continue;  // uniform
-                for (uint32_t k = threadIdx.x; k < T; k += kBatchThreads)
-                    lds[k] = psi[base | tile_offset(p.tm, k)];
+                tile_load<R, kBatchThreads, false, 1>(lds, psi, base, p.tm, T);
                 __syncthreads();
                 tile_run<R, kBatchThreads>(lds, base, p.tm, dg);
-                for (uint32_t k = threadIdx.x; k < T; k += kBatchThreads)
-                    psi[base | tile_offset(p.tm, k)] = lds[k];
+                tile_store<R, kBatchThreads, false, 1>(psi, lds, base, p.tm, T);
                 __syncthreads();
             }
         } else {
@@ -351,18 +353,10 @@ __device__ void adjoint_block(const BCirc &c, const BGate *__restrict__ gates, c
                 const uint64_t base = expand_index<uint64_t>(p.tm.outer, tt);
                 if (!adj_tile_touched(base, dg))
                     continue;  // uniform
-                for (uint32_t k = threadIdx.x; k < T; k += THREADS) {
-                    const uint64_t o = base | tile_offset(p.tm, k);
-                    tp[k] = psi[o];
-                    tl[k] = lam[o];
-                }
+                tile_load2<R, THREADS, false, kBatchCopy>(tp, tl, psi, lam, base, p.tm, T);
                 __syncthreads();
                 adj_tile_run<R, THREADS>(tp, tl, base, T, dg, gs, gens, accl);
-                for (uint32_t k = threadIdx.x; k < T; k += THREADS) {
-                    const uint64_t o = base | tile_offset(p.tm, k);
-                    psi[o] = tp[k];
-                    lam[o] = tl[k];
-                }
+                tile_store2<R, THREADS, false, kBatchCopy>(psi, lam, tp, tl, base, p.tm, T);
                 __syncthreads();
             }
             if (threadIdx.x == 0)  // in order: gates may share a parameter

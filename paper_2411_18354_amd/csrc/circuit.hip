@@ -236,6 +236,70 @@ static int plan_circuit(sv_circuit *c, std::vector<TileGate> &tiles, std::vector
         c->passes.push_back(p);
         return SV_OK;
     };
+    // Gates a run starting at stream[pos] would take with the tile qubits
+    // {0 .. a-1} u high, scanning at most `window` gates (a dry run of the
+    // planner's scan below, with no qubits added on the way).
+    auto run_size = [&](const std::vector<int> &stream, size_t pos, const std::vector<int> &high,
+                        size_t window) -> int {
+        std::vector<int> deferred;
+        int taken = 0;
+        const size_t end = std::min(stream.size(), pos + window);
+        for (size_t i = pos; i < end; ++i) {
+            const sv_gate_t &g = c->gates[stream[i]];
+            const bool fits = diag[stream[i]] || g.target < a ||
+                              std::find(high.begin(), high.end(), g.target) != high.end();
+            bool free = true;
+            for (int d : deferred)
+                if (!commute(g, c->gates[d])) {
+                    free = false;
+                    break;
+                }
+            if (fits && free) {
+                ++taken;
+            } else if (taken > 0) {
+                deferred.push_back(stream[i]);
+                if (deferred.size() > 256)
+                    break;
+            } else {
+                return 0;
+            }
+        }
+        return taken;
+    };
+    // The high qubits of the next run, chosen one at a time: each step adds
+    // the target (among the next gates') that lets the run take the most
+    // gates.  Looking ahead this way keeps qubits whose gates come later in
+    // the same run instead of filling the set with the first targets met.
+    auto choose_high = [&](const std::vector<int> &stream, size_t pos) -> std::vector<int> {
+        constexpr size_t kWindow = 1024;
+        std::vector<int> cand, high;
+        for (size_t i = pos; i < std::min(stream.size(), pos + kWindow); ++i) {
+            const sv_gate_t &g = c->gates[stream[i]];
+            if (!diag[stream[i]] && g.target >= a && std::find(cand.begin(), cand.end(), g.target) == cand.end())
+                cand.push_back(g.target);
+        }
+        std::sort(cand.begin(), cand.end());
+        int cur = run_size(stream, pos, high, kWindow);
+        while ((int)high.size() < m - a) {
+            int best = -1, best_n = cur;
+            for (int q : cand) {
+                if (std::find(high.begin(), high.end(), q) != high.end())
+                    continue;
+                std::vector<int> h2(high);
+                h2.push_back(q);
+                const int k = run_size(stream, pos, h2, kWindow);
+                if (k > best_n) {
+                    best_n = k;
+                    best = q;
+                }
+            }
+            if (best < 0)
+                break;
+            high.push_back(best);
+            cur = best_n;
+        }
+        return high;
+    };
     // fusion planner over one stream of gate indices
     auto fuse_stream = [&](std::vector<int> stream) -> int {
         std::vector<int> run, deferred, high;
@@ -244,6 +308,8 @@ static int plan_circuit(sv_circuit *c, std::vector<TileGate> &tiles, std::vector
             run.clear();
             deferred.clear();
             high.clear();
+            if (tuning().plan_lookahead)
+                high = choose_high(stream, pos);
             size_t i = pos;
             for (; i < stream.size(); ++i) {
                 const int gi = stream[i];
@@ -267,7 +333,7 @@ static int plan_circuit(sv_circuit *c, std::vector<TileGate> &tiles, std::vector
                     SV_TRY(single(gi));
                 } else {
                     deferred.push_back(gi);
-                    if (deferred.size() > 64) {
+                    if (deferred.size() > 256) {
                         ++i;
                         break;
                     }

@@ -33,8 +33,7 @@ __global__ __launch_bounds__(kPermThreads) void k_permute_tile(cplx_t<R> *__rest
     cplx_t<R> *tile = reinterpret_cast<cplx_t<R> *>(lds_raw);
     const uint32_t T = 1u << tm.m;
     const uint64_t base = expand_index<uint64_t>(tm.outer, tm.tile0 + blockIdx.x);
-    for (uint32_t j = threadIdx.x; j < T; j += kPermThreads)
-        tile[j] = ld_stream<R>(psi + (base | tile_offset(tm, j)));
+    tile_load<R, kPermThreads>(tile, psi, base, tm, T);
     __syncthreads();
     for (uint32_t j = threadIdx.x; j < T; j += kPermThreads) {
         uint32_t d = 0;
@@ -50,8 +49,7 @@ __global__ __launch_bounds__(kPermThreads) void k_permute_tile(cplx_t<R> *__rest
         }
     }
     __syncthreads();
-    for (uint32_t j = threadIdx.x; j < T; j += kPermThreads)
-        st_stream<R>(psi + (base | tile_offset(tm, j)), tile[j]);
+    tile_store<R, kPermThreads>(psi, tile, base, tm, T);
 }
 
 int check_swap_pairs(int n, const int32_t *pairs, int npairs) {

@@ -26,7 +26,7 @@ namespace sv {
 
 constexpr int kTileSeg = 16;   // m <= 14 gives at most 15 segments
 constexpr int kTileMaxLog = 14;
-constexpr int kTileMaxHigh = 8;  // qubits of S above the contiguous low block
+constexpr int kTileMaxHigh = 10;  // qubits of S above the contiguous low block
 // Phase patterns of one diagonal sweep: at most this many (their per-tile
 // phases sit in LDS after the tables); a longer sweep is split.
 constexpr int kSweepMaxPats = 512;
@@ -233,6 +233,124 @@ __device__ __forceinline__ uint64_t tile_offset(const TileMap &tm, uint32_t j) {
     for (uint32_t s = 0; s < tm.nseg; ++s)
         o |= (uint64_t)(j & tm.seg_in[s]) << tm.seg_shift[s];
     return o;
+}
+
+// Copies between a state in global memory and tiles in LDS.  Each lane
+// forms the addresses of NB amplitudes (kTileBatch by default) and issues
+// all their loads before its first LDS write, so NB loads per lane are in
+// flight instead of one (a loop of load, wait, write keeps a single one in
+// flight and leaves the load phase latency-bound).  NT: nontemporal accesses (a
+// pass streams the state once); without it the accesses may stay in the
+// caches (small batched states).  With two states, both tiles are copied
+// together (psi's and lambda's loads in flight at once).
+constexpr int kTileBatch = 8;
+
+template <typename R, bool NT>
+__device__ __forceinline__ cplx_t<R> tile_ld(const cplx_t<R> *p) {
+    if constexpr (NT)
+        return ld_stream<R>(p);
+    else
+        return *p;
+}
+
+template <typename R, bool NT>
+__device__ __forceinline__ void tile_st(cplx_t<R> *p, const cplx_t<R> &v) {
+    if constexpr (NT)
+        st_stream<R>(p, v);
+    else
+        *p = v;
+}
+
+template <typename R, int THREADS, bool NT = true, int NB = kTileBatch>
+__device__ __forceinline__ void tile_load(cplx_t<R> *tile, const cplx_t<R> *psi, uint64_t base, const TileMap &tm,
+                                          uint32_t T) {
+    for (uint32_t j0 = threadIdx.x; j0 < T; j0 += NB * THREADS) {
+        cplx_t<R> v[NB];
+#pragma unroll
+        for (int u = 0; u < NB; ++u) {
+            const uint32_t j = j0 + u * THREADS;
+            if (j < T)
+                v[u] = tile_ld<R, NT>(psi + (base | tile_offset(tm, j)));
+        }
+#pragma unroll
+        for (int u = 0; u < NB; ++u) {
+            const uint32_t j = j0 + u * THREADS;
+            if (j < T)
+                tile[j] = v[u];
+        }
+    }
+}
+
+template <typename R, int THREADS, bool NT = true, int NB = kTileBatch>
+__device__ __forceinline__ void tile_store(cplx_t<R> *psi, const cplx_t<R> *tile, uint64_t base, const TileMap &tm,
+                                           uint32_t T) {
+    for (uint32_t j0 = threadIdx.x; j0 < T; j0 += NB * THREADS) {
+        cplx_t<R> v[NB];
+#pragma unroll
+        for (int u = 0; u < NB; ++u) {
+            const uint32_t j = j0 + u * THREADS;
+            if (j < T)
+                v[u] = tile[j];
+        }
+#pragma unroll
+        for (int u = 0; u < NB; ++u) {
+            const uint32_t j = j0 + u * THREADS;
+            if (j < T)
+                tile_st<R, NT>(psi + (base | tile_offset(tm, j)), v[u]);
+        }
+    }
+}
+
+template <typename R, int THREADS, bool NT = true, int NB = kTileBatch>
+__device__ __forceinline__ void tile_load2(cplx_t<R> *tp, cplx_t<R> *tl, const cplx_t<R> *psi, const cplx_t<R> *lam,
+                                           uint64_t base, const TileMap &tm, uint32_t T) {
+    constexpr int B = NB / 2;
+    for (uint32_t j0 = threadIdx.x; j0 < T; j0 += B * THREADS) {
+        cplx_t<R> v[B], w[B];
+#pragma unroll
+        for (int u = 0; u < B; ++u) {
+            const uint32_t j = j0 + u * THREADS;
+            if (j < T) {
+                const uint64_t o = base | tile_offset(tm, j);
+                v[u] = tile_ld<R, NT>(psi + o);
+                w[u] = tile_ld<R, NT>(lam + o);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < B; ++u) {
+            const uint32_t j = j0 + u * THREADS;
+            if (j < T) {
+                tp[j] = v[u];
+                tl[j] = w[u];
+            }
+        }
+    }
+}
+
+template <typename R, int THREADS, bool NT = true, int NB = kTileBatch>
+__device__ __forceinline__ void tile_store2(cplx_t<R> *psi, cplx_t<R> *lam, const cplx_t<R> *tp, const cplx_t<R> *tl,
+                                            uint64_t base, const TileMap &tm, uint32_t T) {
+    constexpr int B = NB / 2;
+    for (uint32_t j0 = threadIdx.x; j0 < T; j0 += B * THREADS) {
+        cplx_t<R> v[B], w[B];
+#pragma unroll
+        for (int u = 0; u < B; ++u) {
+            const uint32_t j = j0 + u * THREADS;
+            if (j < T) {
+                v[u] = tp[j];
+                w[u] = tl[j];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < B; ++u) {
+            const uint32_t j = j0 + u * THREADS;
+            if (j < T) {
+                const uint64_t o = base | tile_offset(tm, j);
+                tile_st<R, NT>(psi + o, v[u]);
+                tile_st<R, NT>(lam + o, w[u]);
+            }
+        }
+    }
 }
 
 // Diagonal sweeps with at least this many gates reading tile-local bits add
@@ -756,12 +874,10 @@ __global__ __launch_bounds__(THREADS, 4) void k_tile(cplx_t<R> *__restrict__ psi
     // a tile that no operation of the run touches is left alone
     if (!tile_touched(base, gates))
         return;
-    for (uint32_t j = threadIdx.x; j < T; j += THREADS)
-        tile[j] = ld_stream<R>(psi + (base | tile_offset(tm, j)));
+    tile_load<R, THREADS>(tile, psi, base, tm, T);
     __syncthreads();
     tile_run<R, THREADS>(tile, base, tm, gates);
-    for (uint32_t j = threadIdx.x; j < T; j += THREADS)
-        st_stream<R>(psi + (base | tile_offset(tm, j)), tile[j]);
+    tile_store<R, THREADS>(psi, tile, base, tm, T);
 }
 
 } // namespace sv

@@ -17,11 +17,12 @@ Tuning &tuning() {
     //  - the wavefront kernel is the faster scheduled kernel whenever the
     //    target is among the 6 lowest free index bits;
     //  - 64 KiB LDS tiles for the fused pass.
-    //  - fused tiles always hold the 4 (complex128) / 5 (complex64) lowest
-    //    qubits, i.e. 256-byte contiguous runs, plus qubits picked per run:
-    //    against 1 KiB runs this leaves more tile qubits to the planner and
-    //    cut passes and time by 7-12% on layered and random circuits (equal
-    //    on QFT29), while narrower runs gained nothing more.
+    //  - fused tiles always hold the 3 (complex128) / 5 (complex64) lowest
+    //    qubits, i.e. 128- and 256-byte contiguous runs, plus qubits picked
+    //    per run: narrower runs leave more tile qubits to the planner (the
+    //    n=32 layered circuit takes 80 passes with 128-byte runs, 91 with
+    //    256-byte ones and 139 with 1 KiB ones), which outweighs their less
+    //    efficient HBM accesses down to 128 bytes; 64-byte runs lost again.
     //  - dense blocks (SV_DENSE) on the 4 lowest qubits for stretches of at
     //    least 16 gates.
     //  - one pair (or amplitude) per lane in the scheduled pair and
@@ -31,7 +32,7 @@ Tuning &tuning() {
     //    256-lane workgroups and one pair per lane (10.8 ms against 12.5 ms
     //    with four per lane, 16.1 ms with 64-lane workgroups, whose many
     //    workgroups cost more when most lanes only test and exit).
-    static Tuning t = {{3, 4}, 1, 1, {12, 13}, {4, 5}, 2, 4, 16, 1, 1, 256, 1, 1};
+    static Tuning t = {{3, 4}, 1, 1, {12, 13}, {3, 5}, 2, 4, 16, 1, 1, 256, 1, 1, 1};
     return t;
 }
 
@@ -60,6 +61,7 @@ static int find_key(const char *name, Key *out) {
         {"masked_block", &t.masked_block, 64, 256},
         {"fuse_group", &t.fuse_group, 0, 1},
         {"fuse_pairs", &t.fuse_pairs, 0, 1},
+        {"plan_lookahead", &t.plan_lookahead, 0, 1},
     };
     for (const Key &k : keys)
         if (name && strcmp(k.name, name) == 0) {
