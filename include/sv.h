@@ -206,6 +206,8 @@ int sv_hbm_probe(const sv_state_t *s, uint64_t fixed_mask, uint64_t fixed_vals, 
  *   "plan_lookahead"  [0, 1]  pick a fused run's tile qubits one at a time,
  *       each the target that lets the run take the most of the next gates
  *       (0: the first targets met, in order)
+ *   "fuse_perm"       [0, 1]  apply runs of consecutive X gates (any controls)
+ *       of a fused run as one permutation of the tile
  * None of them changes results beyond floating-point rounding (fusion
  * choices change the order in which commuting operations are rounded).
  * SV_EINVAL for an unknown key or a value out of range.  Not thread-safe

@@ -187,7 +187,7 @@ __device__ void run_circuit_block(const BCirc &c, const BGate *__restrict__ gate
                     continue;  // uniform
                 tile_load<R, kBatchThreads, false, 1>(lds, psi, base, p.tm, T);
                 __syncthreads();
-                tile_run<R, kBatchThreads>(lds, base, p.tm, dg);
+                tile_run<R, kBatchThreads, false>(lds, base, p.tm, dg);  // at its register limit
                 tile_store<R, kBatchThreads, false, 1>(psi, lds, base, p.tm, T);
                 __syncthreads();
             }

@@ -408,6 +408,8 @@ static int plan_circuit(sv_circuit *c, std::vector<TileGate> &tiles, std::vector
                 build_sweep_patterns(&tiles[p.first], p.count, (int)p.tm.m, from_param.data(), pats, mems);
                 if (tuning().fuse_pairs)
                     mark_coset_pairs(&tiles[p.first], p.count);
+                if (tuning().fuse_perm)  // checked first by the tile loops
+                    mark_permutation_runs(&tiles[p.first], p.count);
                 c->passes.push_back(p);
                 c->fused_gates += (int64_t)run.size();
                 c->fused_runs++;

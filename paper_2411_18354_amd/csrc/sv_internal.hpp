@@ -166,6 +166,7 @@ struct Tuning {
     int fuse_group;       // fused runs: gather diagonal gates into blocks (commutation moves)
     int fuse_pairs;       // fused runs: apply adjacent coset-closed pair gates together
     int plan_lookahead;   // fused runs: choose a run's high qubits by looking ahead
+    int fuse_perm;        // fused runs: apply runs of X gates as one gather
 };
 Tuning &tuning();
 

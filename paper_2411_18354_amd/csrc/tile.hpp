@@ -91,6 +91,9 @@ struct TileGate {
     // diagonal gate: the phase-pattern members that hold its phases ph[0]
     // and ph[1] (-1: none), refreshed with ph when the angle is a parameter
     int32_t mem[2];
+    // first gate of a permutation run (see mark_permutation_runs): its length
+    uint32_t perm_len;
+    uint32_t pad3;
 };
 
 // Summary bits of a diagonal sweep's gates (host), kept in the first gate's
@@ -117,6 +120,18 @@ void mark_diag_sweeps(TileGate *tiles, int count, const char *param_gate);
 // than kSweepMaxPats patterns is split into several sweeps.
 void build_sweep_patterns(TileGate *tiles, int count, int m, const char *param_gate, std::vector<SweepPat> &pats,
                           std::vector<SweepMember> &mems);
+
+// Permutation runs among tiles[0 .. count) (one fused run; host): maximal
+// runs of at least two consecutive pair gates whose matrix is exactly X
+// (any controls).  Such a run maps basis states to basis states, so inside
+// a tile it is one gather: amplitude j of the result is amplitude
+// g_1(g_2(... g_L(j))) of the tile, each g flipping its target bit where
+// its controls hold (outer controls decide per tile).  One LDS read and
+// write of the tile then replace one per gate.  A run is marked only when
+// its gates together touch at least 1.5 tiles' worth of amplitudes (a gate
+// with c tile-local controls touches 2^-c of the tile), where one gather
+// moves less than the gates would.  The first gate gets perm_len.
+void mark_permutation_runs(TileGate *tiles, int count);
 
 // Mark coset pairs among tiles[0 .. count) (one fused run; host): two
 // adjacent pair gates on different tile-local targets t1, t2 whose
@@ -735,6 +750,63 @@ __device__ __forceinline__ void tile_pairs2(cplx_t<R> *tile, uint32_t T, const T
     }
 }
 
+// Amplitudes per lane a permutation run gathers at most (its lane's part of
+// the tile, or of both tiles in the reverse sweep, held in registers between
+// the gather and the write-back): 128 bytes per lane.
+template <typename R> constexpr int perm_per_lane() { return 128 / (int)sizeof(cplx_t<R>); }
+
+// Source indices of the lane's tile-local indices threadIdx.x + k THREADS
+// (k < NP) under the permutation run [i, i + L): the run's gates applied to
+// each index last to first (each X gate is its own inverse), those whose
+// outer controls fail skipped for the whole tile.  The gate loop is outside
+// so that every register index stays a constant.
+template <int NP, int THREADS, typename Src>
+__device__ __forceinline__ void perm_sources(uint32_t *src, uint64_t base, const Src &gates, int i, int L) {
+#pragma unroll
+    for (int k = 0; k < NP; ++k)
+        src[k] = threadIdx.x + k * THREADS;
+    for (int q = i + L - 1; q >= i; --q) {
+        const TileGate &d = gates.get(q);
+        if ((base & d.hi_mask) != d.hi_vals)
+            continue;  // uniform
+        const uint32_t lm = d.l_mask, lv = d.l_vals, flip = 1u << d.target;
+#pragma unroll
+        for (int k = 0; k < NP; ++k)
+            src[k] ^= ((src[k] & lm) == lv) ? flip : 0u;
+    }
+}
+
+// A permutation run on one tile: every lane gathers its amplitudes from
+// their source indices, then (after a barrier) writes them back in place.
+// Requires T <= perm_per_lane<R>() * THREADS (checked by the caller).
+template <typename R, int THREADS, typename Src>
+__device__ __forceinline__ void tile_permute(cplx_t<R> *tile, uint32_t T, uint64_t base, const Src &gates, int i,
+                                             int L) {
+    constexpr int NP = perm_per_lane<R>();
+    uint32_t src[NP];
+    perm_sources<NP, THREADS>(src, base, gates, i, L);
+    R vx[NP], vy[NP];  // components apart: an array of vector-typed values filled from LDS stays in scratch
+#pragma unroll
+    for (int k = 0; k < NP; ++k)
+        if (threadIdx.x + k * THREADS < T) {
+            const cplx_t<R> a = tile[src[k]];
+            vx[k] = a.x;
+            vy[k] = a.y;
+        }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < NP; ++k) {
+        const uint32_t j = threadIdx.x + k * THREADS;
+        if (j < T) {
+            cplx_t<R> a;
+            a.x = vx[k];
+            a.y = vy[k];
+            tile[j] = a;
+        }
+    }
+    __syncthreads();
+}
+
 // Whether any operation of the run acts on the tile at base.
 template <typename Src> __device__ __forceinline__ bool tile_touched(uint64_t base, const Src &gates) {
     bool any = false;
@@ -749,7 +821,9 @@ template <typename Src> __device__ __forceinline__ bool tile_touched(uint64_t ba
 
 // The run's operations applied to the tile held in LDS (all threads of the
 // workgroup; the tile is complete in LDS on entry and on exit).
-template <typename R, int THREADS, typename Src>
+// PERM: permutation runs are applied as gathers (false: as their gates, for
+// kernels without the registers to spare).
+template <typename R, int THREADS, bool PERM = true, typename Src>
 __device__ __forceinline__ void tile_run(cplx_t<R> *tile, uint64_t base, const TileMap &tm, const Src &gates) {
     const uint32_t T = 1u << tm.m;
     int i = 0;
@@ -830,6 +904,13 @@ __device__ __forceinline__ void tile_run(cplx_t<R> *tile, uint64_t base, const T
             }
             __syncthreads();
             i = e;
+            continue;
+        }
+        const uint32_t plen = __builtin_amdgcn_readfirstlane(g.perm_len);
+        if (PERM && plen >= 2 && T <= (uint32_t)(perm_per_lane<R>() * THREADS)) {  // a permutation run (uniform)
+            const int L = min((int)plen, gates.size() - i);
+            tile_permute<R, THREADS>(tile, T, base, gates, i, L);
+            i += L;
             continue;
         }
         if ((sweep_word(g) & 0xffffu) == 2 && i + 1 < gates.size()) {  // a coset pair (uniform)

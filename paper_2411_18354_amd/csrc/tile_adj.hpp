@@ -267,6 +267,42 @@ __device__ __forceinline__ int adj_diag_block(cplx_t<R> *tp, cplx_t<R> *tl, uint
     return k;
 }
 
+// A permutation run (marked on the host, as in the forward pass) on both
+// tiles: X gates carry no parameter, so the run only moves amplitudes, and
+// psi and lambda move alike.  Requires 2 T <= perm_per_lane<R>() * THREADS.
+template <typename R, int THREADS>
+__device__ __forceinline__ void adj_tile_permute(cplx_t<R> *tp, cplx_t<R> *tl, uint32_t T, uint64_t base,
+                                                 const DeviceGates &gates, int i, int L) {
+    constexpr int NP = perm_per_lane<R>() / 2;
+    uint32_t src[NP];
+    perm_sources<NP, THREADS>(src, base, gates, i, L);
+    R vx[NP], vy[NP], wx[NP], wy[NP];  // components apart (see tile_permute)
+#pragma unroll
+    for (int k = 0; k < NP; ++k)
+        if (threadIdx.x + k * THREADS < T) {
+            const cplx_t<R> a = tp[src[k]], b = tl[src[k]];
+            vx[k] = a.x;
+            vy[k] = a.y;
+            wx[k] = b.x;
+            wy[k] = b.y;
+        }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < NP; ++k) {
+        const uint32_t j = threadIdx.x + k * THREADS;
+        if (j < T) {
+            cplx_t<R> a, b;
+            a.x = vx[k];
+            a.y = vy[k];
+            b.x = wx[k];
+            b.y = wy[k];
+            tp[j] = a;
+            tl[j] = b;
+        }
+    }
+    __syncthreads();
+}
+
 template <typename R, int THREADS>
 __device__ __forceinline__ void adj_tile_run(cplx_t<R> *tp, cplx_t<R> *tl, uint64_t base, uint32_t T,
                                              const DeviceGates &gates, const int32_t *__restrict__ gslot,
@@ -282,6 +318,13 @@ __device__ __forceinline__ void adj_tile_run(cplx_t<R> *tp, cplx_t<R> *tl, uint6
             kacc = adj_diag_block<R, THREADS>(tp, tl, base, T, gates, i, e, gslot, gens, accl, kacc);
             __syncthreads();
             i = e - 1;
+            continue;
+        }
+        const uint32_t plen = __builtin_amdgcn_readfirstlane(g.perm_len);
+        if (!g.diag && plen >= 2 && 2 * T <= (uint32_t)(perm_per_lane<R>() * THREADS)) {  // a permutation run
+            const int L = min((int)plen, gates.size() - i);
+            adj_tile_permute<R, THREADS>(tp, tl, T, base, gates, i, L);
+            i += L - 1;
             continue;
         }
         if (!g.diag && slen == 2 && i + 1 < gates.size()) {  // a coset pair (uniform)

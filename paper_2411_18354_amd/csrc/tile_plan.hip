@@ -2,6 +2,7 @@
 // set, per-gate tile descriptors (the in-tile index expansion of Sec. III-B at
 // tile scope), the diagonal-sweep summaries and the coset pairs of a run.
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 
 #include "tile.hpp"
@@ -232,6 +233,24 @@ void build_sweep_patterns(TileGate *t, int count, int m, const char *param_gate,
         h.npairs = kSweepInfoValid | um | (uv << 8) | (have_r ? kSweepHaveR : 0u) |
                    (have_r && rank1 ? kSweepRank1 : 0u) | (any_rest ? kSweepAnyRest : 0u);
         k = end;
+    }
+}
+
+void mark_permutation_runs(TileGate *t, int count) {
+    auto is_x = [](const TileGate &g) {
+        return !g.diag && g.m[0] == 0.0 && g.m[1] == 0.0 && g.m[2] == 1.0 && g.m[3] == 0.0 && g.m[4] == 1.0 &&
+               g.m[5] == 0.0 && g.m[6] == 0.0 && g.m[7] == 0.0;
+    };
+    for (int k = 0; k < count;) {
+        int e = k;
+        double touched = 0.0;  // tiles' worth of amplitudes the run's gates move
+        while (e < count && is_x(t[e]) && e - k < 0xffff) {
+            touched += std::ldexp(1.0, -__builtin_popcount(t[e].l_mask));
+            ++e;
+        }
+        if (e - k >= 2 && touched >= 1.5)
+            t[k].perm_len = (uint32_t)(e - k);
+        k = std::max(e, k + 1);
     }
 }
 

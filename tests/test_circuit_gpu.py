@@ -436,3 +436,51 @@ def test_remapped_circuits(gpu, flags):
         plan.run(d)
         assert _err(d.cpu().numpy(), ref) <= 1e-12, (flags, rep)
     plan.close()
+
+
+def _x_runs(n, seed, nruns=40):
+    """Runs of 2-10 X gates (0-3 controls anywhere, some negative) between
+    single rotations and H gates: permutation runs whose gates read
+    tile-local, outer and in-tile-negated controls."""
+    rng = np.random.default_rng(seed)
+    gates = [W.Gate("H", q) for q in range(n)]
+    for _ in range(nruns):
+        for _ in range(int(rng.integers(2, 11))):
+            t = int(rng.integers(0, n))
+            others = [q for q in range(n) if q != t]
+            c = int(rng.integers(0, 4))
+            ctrls = tuple(int(q) for q in rng.choice(others, size=c, replace=False)) if c else ()
+            vals = tuple(int(v) for v in rng.integers(0, 2, size=c))
+            gates.append(W.Gate("X", t, ctrls, vals))
+        q = int(rng.integers(0, n))
+        gates.append(W.Gate("RY" if rng.random() < 0.5 else "H", q, (), (), float(rng.uniform(0, 2 * np.pi))))
+    return W.Circuit(n, gates)
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_permutation_runs(gpu, dtype):
+    """Runs of X gates applied as one gather per tile: a GHZ ladder, the
+    layered circuit and random X runs, on the default tiles and on narrow
+    ones, against the oracle and (exactly) against the same plans with the
+    runs applied gate by gate."""
+    import torch
+    circs = [(14, W.ghz(14), 0), (16, W.layered_circuit_n32(n=16, layers=4), 0), (15, _x_runs(15, 3), 0),
+             (13, _x_runs(13, 4), 8)]
+    for n, c, width in circs:
+        if width:
+            gpu.sv_tune_set("tile_log2_" + dtype, width)
+        psi0 = W.random_state(n, n + width)
+        ref = oracle.run_circuit(c, None, psi0)
+        got = {}
+        for perm in (1, 0):
+            gpu.sv_tune_set("fuse_perm", perm)
+            d = _dev_state(n, dtype, psi0)
+            circ = gpu.Circuit(n, c, dtype=0 if dtype == "c128" else 1, flags=gpu.SV_FUSE)
+            circ.run(d)
+            circ.close()
+            got[perm] = d.cpu()
+            e = _err(got[perm].numpy(), ref)
+            _say("perm", perm, dtype, "n", n, "width", width, "err", e)
+            assert e <= TOL[dtype], (n, perm, e)
+        assert torch.equal(got[0], got[1]), n
+        gpu.sv_tune_set("fuse_perm", 1)
