@@ -11,11 +11,30 @@ namespace sv {
 constexpr int kRedThreads = 256;
 constexpr int kMaxPartials = 2048;  // workgroups of a reducing launch
 
+// v from the lane DPP control CTRL names, within rows of 16 lanes.
+template <int CTRL> __device__ __forceinline__ double dpp_double(double v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ double lane_value(double v, int lane) {
+    return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), lane),
+                            __builtin_amdgcn_readlane(__double2loint(v), lane));
+}
+
+// Sum of v over the 64 lanes of a wavefront, the same value in every lane.
+// Inside each row of 16 lanes by data-parallel-primitive moves (partner lane
+// xor 1, xor 2, then the mirrored lane within 8 and within 16: after each
+// step both partners hold the same sum, a + b = b + a), then the four row
+// sums read from lanes 0, 16, 32, 48 and added in a fixed order.  No LDS
+// round trip (lane exchanges through ds_bpermute took six dependent ones).
 __device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int m = 32; m >= 1; m >>= 1)
-        v += lane_xor(v, m);
-    return v;
+    v += dpp_double<0xB1>(v);   // quad_perm [1, 0, 3, 2]
+    v += dpp_double<0x4E>(v);   // quad_perm [2, 3, 0, 1]
+    v += dpp_double<0x141>(v);  // row_half_mirror
+    v += dpp_double<0x140>(v);  // row_mirror
+    return (lane_value(v, 0) + lane_value(v, 16)) + (lane_value(v, 32) + lane_value(v, 48));
 }
 
 // Sum of v over the whole workgroup (blockDim.x lanes, a multiple of 64);
