@@ -270,7 +270,10 @@ static int plan_circuit(sv_circuit *c, std::vector<TileGate> &tiles, std::vector
     // the target (among the next gates') that lets the run take the most
     // gates.  Looking ahead this way keeps qubits whose gates come later in
     // the same run instead of filling the set with the first targets met.
-    auto choose_high = [&](const std::vector<int> &stream, size_t pos) -> std::vector<int> {
+    // depth 2: each of the six best targets is scored by the best run it
+    // allows together with one more target, and the step takes the best of
+    // those (a qubit whose gates pay off only with another one).
+    auto choose_high = [&](const std::vector<int> &stream, size_t pos, int depth) -> std::vector<int> {
         constexpr size_t kWindow = 1024;
         std::vector<int> cand, high;
         for (size_t i = pos; i < std::min(stream.size(), pos + kWindow); ++i) {
@@ -281,19 +284,40 @@ static int plan_circuit(sv_circuit *c, std::vector<TileGate> &tiles, std::vector
         std::sort(cand.begin(), cand.end());
         int cur = run_size(stream, pos, high, kWindow);
         while ((int)high.size() < m - a) {
-            int best = -1, best_n = cur;
+            // score every candidate, then look one step further for the best few
+            std::vector<std::pair<int, int>> sc;  // (gates taken, qubit)
             for (int q : cand) {
                 if (std::find(high.begin(), high.end(), q) != high.end())
                     continue;
                 std::vector<int> h2(high);
                 h2.push_back(q);
-                const int k = run_size(stream, pos, h2, kWindow);
-                if (k > best_n) {
-                    best_n = k;
-                    best = q;
+                sc.push_back({run_size(stream, pos, h2, kWindow), q});
+            }
+            if (sc.empty())
+                break;
+            std::stable_sort(sc.begin(), sc.end(), [](const std::pair<int, int> &x, const std::pair<int, int> &y) {
+                return x.first > y.first;
+            });
+            int best = -1, best_n = cur, best2 = -1;
+            const size_t top = std::min<size_t>(sc.size(), depth > 1 ? 6 : 1);
+            for (size_t t = 0; t < top; ++t) {
+                int two = sc[t].first;
+                if (depth > 1 && (int)high.size() + 2 <= m - a)
+                    for (const auto &o : sc) {
+                        if (o.second == sc[t].second)
+                            continue;
+                        std::vector<int> h3(high);
+                        h3.push_back(sc[t].second);
+                        h3.push_back(o.second);
+                        two = std::max(two, run_size(stream, pos, h3, kWindow));
+                    }
+                if (two > best2 || (two == best2 && sc[t].first > best_n)) {
+                    best2 = two;
+                    best = sc[t].second;
+                    best_n = sc[t].first;
                 }
             }
-            if (best < 0)
+            if (best < 0 || best2 <= cur)
                 break;
             high.push_back(best);
             cur = best_n;
@@ -308,8 +332,9 @@ static int plan_circuit(sv_circuit *c, std::vector<TileGate> &tiles, std::vector
             run.clear();
             deferred.clear();
             high.clear();
-            if (tuning().plan_lookahead)
-                high = choose_high(stream, pos);
+            const int depth = std::min(tuning().plan_lookahead, c->max_lookahead);
+            if (depth > 0)
+                high = choose_high(stream, pos, depth);
             size_t i = pos;
             for (; i < stream.size(); ++i) {
                 const int gi = stream[i];
@@ -756,6 +781,7 @@ int circuit_plan_tiles(int n, int dtype, const sv_gate_t *gates, int ngates, int
     c.flags = SV_FUSE;
     c.nparams = nparams;
     c.m_cap = m_cap;
+    c.max_lookahead = 1;  // thousands of circuits: the one-step lookahead keeps planning cheap
     c.gates.assign(gates, gates + ngates);
     std::vector<ParamJob> jobs;
     std::vector<double> mats;

@@ -165,7 +165,7 @@ struct Tuning {
     int masked_block;     // lanes per workgroup of the masked baseline kernel: 64 or 256
     int fuse_group;       // fused runs: gather diagonal gates into blocks (commutation moves)
     int fuse_pairs;       // fused runs: apply adjacent coset-closed pair gates together
-    int plan_lookahead;   // fused runs: choose a run's high qubits by looking ahead
+    int plan_lookahead;   // fused runs: lookahead depth choosing a run's high qubits (0-2)
     int fuse_perm;        // fused runs: apply runs of X gates as one gather
 };
 Tuning &tuning();
