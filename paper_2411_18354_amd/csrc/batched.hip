@@ -44,7 +44,7 @@ constexpr int kBatchCopy = 2;
 constexpr size_t kBatchLds = 65536;  // the tile (or a whole resident state)
 // dynamic LDS: the work-item slot, the tile, then the diagonal-sweep tables
 constexpr size_t kBatchSlot = 64;
-constexpr size_t kBatchDynLds = kBatchSlot + kBatchLds + 8 * 1600;  // tables for tile widths up to 13
+constexpr size_t kBatchDynLds = kBatchSlot + kBatchLds + sizeof(double) * diag_table_doubles(13);  // tile widths up to 13
 
 struct BGate {
     double m[8];      // matrix of a fixed gate

@@ -176,10 +176,10 @@ struct TileMap {
 // A[64] over tile-local bits 0..5, B[2^(m-6)] over bits 6..m-1, for each
 // bit q >= 6 and value b a row R[q][b][64] over bits 0..5, then the phases
 // of up to kSweepMaxPats patterns for the current tile.
-__host__ __device__ inline uint32_t diag_pattern_offset(uint32_t m) {
+__host__ __device__ constexpr uint32_t diag_pattern_offset(uint32_t m) {
     return 64u + (1u << (m - 6)) + (m - 6) * 128u;
 }
-__host__ __device__ inline uint32_t diag_table_doubles(uint32_t m) {
+__host__ __device__ constexpr uint32_t diag_table_doubles(uint32_t m) {
     return m < 7 ? 0u : diag_pattern_offset(m) + (uint32_t)kSweepMaxPats;
 }
 

@@ -37,10 +37,15 @@ def _apply_in_order(c, order, psi0):
     return psi
 
 
+@pytest.mark.parametrize("depth", [0, 1, 2])
 @pytest.mark.parametrize("seed", range(6))
-def test_planned_order_equivalent(sv, seed):
+def test_planned_order_equivalent(sv, seed, depth):
+    """The planner's gate order (deferrals past commuting gates, each run's
+    tile qubits chosen without lookahead, one step or two) applied by the
+    oracle equals the circuit's own order."""
     n = 10
     sv.sv_tune_set("tile_log2_c128", 6)
+    sv.sv_tune_set("plan_lookahead", depth)
     try:
         c = _rand_circuit(n, 300, seed)
         order, pass_of, npasses = sv.sv_circuit_plan(n, c, flags=sv.SV_FUSE)
