@@ -37,9 +37,10 @@ int validate_unitary_gate(const sv_gate_t &g, int index);
 
 constexpr int kBatchThreads = 512;
 constexpr int kBatchAdjMaxThreads = 1024;  // the batched adjoint's wider shape
-// amplitudes per lane in flight when the batched adjoint copies a tile pair
-// (the batched kernels have fewer registers to spare than the
-// single-circuit ones; the forward one copies one amplitude at a time)
+// amplitudes per lane in flight when the batched adjoint writes a tile pair
+// back (the batched kernels have fewer registers to spare than the
+// single-circuit ones: they load tiles by direct HBM-to-LDS copies and the
+// forward one writes one amplitude at a time)
 constexpr int kBatchCopy = 2;
 constexpr size_t kBatchLds = 65536;  // the tile (or a whole resident state)
 // dynamic LDS: the work-item slot, the tile, then the diagonal-sweep tables
@@ -185,7 +186,7 @@ __device__ void run_circuit_block(const BCirc &c, const BGate *__restrict__ gate
                 const uint64_t base = expand_index<uint64_t>(p.tm.outer, tt);
                 if (!tile_touched(base, dg))
                     continue;  // uniform
-                tile_load<R, kBatchThreads, false, 1>(lds, psi, base, p.tm, T);
+                tile_load_dma<R, kBatchThreads>(lds, psi, base, p.tm, T);
                 __syncthreads();
                 tile_run<R, kBatchThreads, false>(lds, base, p.tm, dg);  // at its register limit
                 tile_store<R, kBatchThreads, false, 1>(psi, lds, base, p.tm, T);
@@ -353,7 +354,8 @@ __device__ void adjoint_block(const BCirc &c, const BGate *__restrict__ gates, c
                 const uint64_t base = expand_index<uint64_t>(p.tm.outer, tt);
                 if (!adj_tile_touched(base, dg))
                     continue;  // uniform
-                tile_load2<R, THREADS, false, kBatchCopy>(tp, tl, psi, lam, base, p.tm, T);
+                tile_load_dma<R, THREADS>(tp, psi, base, p.tm, T);
+                tile_load_dma<R, THREADS>(tl, lam, base, p.tm, T);
                 __syncthreads();
                 adj_tile_run<R, THREADS>(tp, tl, base, T, dg, gs, gens, accl);
                 tile_store2<R, THREADS, false, kBatchCopy>(psi, lam, tp, tl, base, p.tm, T);

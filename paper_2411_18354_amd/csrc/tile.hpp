@@ -368,6 +368,33 @@ __device__ __forceinline__ void tile_store2(cplx_t<R> *psi, cplx_t<R> *lam, cons
     }
 }
 
+// A tile copied from the state into LDS by direct HBM-to-LDS loads (for
+// kernels without registers to spare): each wavefront fills 1 KiB of the
+// tile per instruction, lane l writing its bytes 16 l .. 16 l + 15 (one
+// complex128 amplitude, or two adjacent complex64 ones, which lie in the
+// tile's contiguous low block), so no register holds the data and all of a
+// lane's loads are in flight together.  The caller's barrier waits for them.
+// Tiles smaller than one wavefront's 1 KiB (T a power of two below 64 * 16 /
+// sizeof(amplitude)) are copied by the plain loop instead.
+template <typename R, int THREADS>
+__device__ __forceinline__ void tile_load_dma(cplx_t<R> *tile, const cplx_t<R> *psi, uint64_t base, const TileMap &tm,
+                                              uint32_t T) {
+    constexpr uint32_t A = 16 / sizeof(cplx_t<R>);  // amplitudes per lane and load
+    constexpr uint32_t CH = 64 * A;                 // amplitudes per wavefront and load
+    if (T < CH) {  // uniform
+        for (uint32_t j = threadIdx.x; j < T; j += THREADS)
+            tile[j] = psi[base | tile_offset(tm, j)];
+        return;
+    }
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const uint32_t lane = threadIdx.x & 63u;
+    for (uint32_t c0 = wave * CH; c0 < T; c0 += (THREADS / 64) * CH) {  // uniform per wavefront
+        const uint32_t j = c0 + lane * A;
+        __builtin_amdgcn_global_load_lds((const void *)(psi + (base | tile_offset(tm, j))),
+                                         (__attribute__((address_space(3))) void *)(tile + c0), 16, 0, 0);
+    }
+}
+
 // Diagonal sweeps with at least this many gates reading tile-local bits add
 // phases instead of multiplying factors (measured break-even on MI355X is a
 // handful of gates).
