@@ -206,7 +206,8 @@ int sv_hbm_probe(const sv_state_t *s, uint64_t fixed_mask, uint64_t fixed_vals, 
  *   "plan_lookahead"  [0, 2]  pick a fused run's tile qubits one at a time,
  *       each the target that lets the run take the most of the next gates
  *       (1), or the most together with one further target (2); 0: the first
- *       targets met, in order.  Batches plan with at most 1.
+ *       targets met, in order.  Batches and one-shot calls (sv_apply_circuit,
+ *       sv_adjoint_grad) plan with at most 1.
  *   "fuse_perm"       [0, 1]  apply runs of consecutive X gates (any controls)
  *       of a fused run as one permutation of the tile
  * None of them changes results beyond floating-point rounding (fusion

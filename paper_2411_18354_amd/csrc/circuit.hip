@@ -584,6 +584,9 @@ int circuit_create(int n, int dtype, const sv_gate_t *gates, int ngates, int npa
     c->nparams = nparams;
     c->async_buffers = async;
     c->m_cap = m_cap;
+    // a one-shot plan (stream-ordered buffers, run once) keeps planning cheap:
+    // the two-step lookahead pays for itself only over repeated runs
+    c->max_lookahead = async ? 1 : 2;
     SV_HIP_TRY(hipGetDevice(&c->device));
     c->gates.assign(gates, gates + ngates);
     if ((flags & SV_REMAP) && !(flags & SV_MASKED))

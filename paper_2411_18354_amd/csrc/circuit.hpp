@@ -28,7 +28,7 @@ struct sv_circuit {
     // (the C ABI's opaque sv_circuit_t)
     int n = 0, dtype = 0, flags = 0, nparams = 0, device = 0, m = 0;
     int m_cap = 64;  // upper bound on the tile width (callers with a fixed LDS budget)
-    int max_lookahead = 2;  // cap on the planner's lookahead depth (batches plan many circuits)
+    int max_lookahead = 2;  // cap on the planner's lookahead depth (one-shot plans and batches: 1)
     std::vector<sv_gate_t> gates;   // after the SV_REMAP relabelling, if any
     std::vector<int32_t> remap;      // SV_REMAP: qubit swaps a0 b0 a1 b1 ... (empty: none)
     std::vector<sv::Pass> passes;
