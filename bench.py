@@ -399,7 +399,7 @@ def _deposit(v, mask):
 MALL_ROTATE_BYTES = 512 << 20  # twice the 256 MB Infinity Cache
 
 
-def graph_protocol(sv, torch, np, st, n, cases, U, stream, amp_bytes=AMP_BYTES, target_ms=30.0, trials=5,
+def graph_protocol(sv, torch, np, st, n, cases, U, stream, amp_bytes=AMP_BYTES, target_ms=50.0, trials=7,
                    modes=("auto", "masked", "probe")):
     """Per (target, controls) and kernel form: R back-to-back launches of the
     gate captured once as a HIP graph and replayed, median of `trials`
@@ -441,7 +441,7 @@ def graph_protocol(sv, torch, np, st, n, cases, U, stream, amp_bytes=AMP_BYTES, 
                 e1.record(stream)
             torch.cuda.synchronize()
             est = max(e0.elapsed_time(e1) / K, 1e-3)
-            R = int(min(4096, max(K, np.ceil(target_ms / est))))
+            R = int(min(8192, max(K, np.ceil(target_ms / est))))
             R = -(-R // K) * K
             g = torch.cuda.CUDAGraph()
             with torch.cuda.graph(g, stream=stream):
@@ -523,7 +523,7 @@ def protocol_n32(sv, W, torch, np, stream, U):
     gen = torch.Generator(device="cuda:0")
     gen.manual_seed(11)
     st.view(torch.float64).normal_(generator=gen)
-    rows = graph_protocol(sv, torch, np, st, n, cases, U, stream, target_ms=40.0, trials=3)
+    rows = graph_protocol(sv, torch, np, st, n, cases, U, stream)
     del st
     torch.cuda.empty_cache()
     return rows
