@@ -698,23 +698,36 @@ def measure_fixed_point(sv, W, torch, np, stream, psi_host, cases, U, energy):
     return out
 
 
-def batch_occupancy(np, st, ns_tick, ns, workgroups):
-    """From per-circuit [start, end] clock stamps of one persistent batched
-    run: the run's span, the mean number of workgroups busy with a circuit
-    over the span against the workgroups launched, the longest circuit, and
-    per width n the count and mean/max time per circuit."""
+def batch_occupancy(np, st, ns_tick, ns, workgroups, items=None):
+    """From per-work-item [start, end] clock stamps of one persistent batched
+    run (items[i] = the item's circuit; None: one item per circuit, i = c):
+    the run's span, the mean number of workgroups busy with an item over the
+    span against the workgroups launched, the longest circuit (first start to
+    last end of its items), and per width n the count and mean/max time per
+    circuit."""
+    if items is None:
+        items = list(range(len(ns)))
+    items = np.asarray(items)
+    st = st[:2 * len(items)]
     t0, t1 = st[0::2].astype(np.float64), st[1::2].astype(np.float64)
     span = (t1.max() - t0.min()) * ns_tick * 1e-6
     busy = (t1 - t0) * ns_tick * 1e-6
+    c0 = np.full(len(ns), np.inf)
+    c1 = np.full(len(ns), -np.inf)
+    np.minimum.at(c0, items, t0)
+    np.maximum.at(c1, items, t1)
+    ctime = (c1 - c0) * ns_tick * 1e-6
     per = {}
     for n in sorted(set(ns)):
         sel = np.array(ns) == n
-        per[str(n)] = [int(sel.sum()), round(float(busy[sel].mean()), 4), round(float(busy[sel].max()), 4)]
+        per[str(n)] = [int(sel.sum()), round(float(ctime[sel].mean()), 4), round(float(ctime[sel].max()), 4)]
     last_start = (t0.max() - t0.min()) * ns_tick * 1e-6
-    return {"span_ms": round(span, 3), "workgroups": workgroups,
+    counts = np.bincount(items, minlength=len(ns))
+    return {"span_ms": round(span, 3), "workgroups": workgroups, "items": int(len(items)),
+            "split_circuits": int((counts > 1).sum()),
             "mean_busy_workgroups": round(float(busy.sum() / span), 1),
             "utilisation": round(float(busy.sum() / span / workgroups), 3),
-            "longest_circuit_ms": round(float(busy.max()), 3), "last_start_ms": round(last_start, 3),
+            "longest_circuit_ms": round(float(ctime.max()), 3), "last_start_ms": round(last_start, 3),
             "per_n_count_mean_max_ms": per}
 
 
@@ -783,13 +796,15 @@ def measure_extras(sv, W, torch, np, stream, with_layered, psi_host=None, cases=
         t_once = (time.perf_counter() - t0) * 1e3
         # per-circuit device clock stamps of one more run: time per circuit
         # width, and how busy the persistent workgroups are over the run
-        stamps = torch.zeros(2 * len(circs), dtype=torch.int64, device=dev)
+        items = batch.items()
+        stamps = torch.zeros(2 * max(len(circs), len(items)), dtype=torch.int64, device=dev)
         ns_tick = batch.set_timing(stamps)
         batch.run(stream=stream)
         torch.cuda.synchronize()
         batch.set_timing(None)
         occ = batch_occupancy(np, stamps.cpu().numpy(), ns_tick, ns,
-                              2 * torch.cuda.get_device_properties(0).multi_processor_count)
+                              min(len(items), 2 * torch.cuda.get_device_properties(0).multi_processor_count),
+                              items)
         ngates = sum(len(c.gates) for c in circs)
         alg = sum(len(c.gates) * (1 << c.n) * 2 * (16 if dt == "c128" else 8) for c in circs)
         out["batched_uneven4096_" + dt] = {"circuits": len(circs), "gates": ngates, "ms": round(t_b4, 2),

@@ -210,6 +210,8 @@ int sv_hbm_probe(const sv_state_t *s, uint64_t fixed_mask, uint64_t fixed_vals, 
  *       sv_adjoint_grad) plan with at most 1.
  *   "fuse_perm"       [0, 1]  apply runs of consecutive X gates (any controls)
  *       of a fused run as one permutation of the tile
+ *   "batch_split"     [1, 64]  most workgroups a batched circuit may be split
+ *       over (read when a batch is planned; 1: one workgroup per circuit)
  * None of them changes results beyond floating-point rounding (fusion
  * choices change the order in which commuting operations are rounded).
  * SV_EINVAL for an unknown key or a value out of range.  Not thread-safe
@@ -430,10 +432,17 @@ int sv_adjoint_destroy(sv_adjoint_t *plan);
  *
  * Many independent circuits, each on its own state (n may differ; one dtype
  * per batch), run by one persistent launch: each workgroup takes the next
- * circuit from a device work queue (longest first) and applies all its
+ * work item from a device work queue (longest first) and applies all its
  * gates; a state of at most 64 KiB stays in LDS for the whole circuit, a
  * larger one runs its fused plan pass by pass (a fused run through LDS tiles
- * over the run's qubit set, other gates as pair loops over the state).
+ * over the run's qubit set, other gates as pair loops over the state).  A
+ * forward circuit that costs more than the batch's mean load per workgroup
+ * is split over about cost / mean workgroups (at most the "batch_split"
+ * knob): its passes are cut into chunks of whole tiles or pair-loop steps
+ * that the workgroups joining it take in order, a pass's chunks starting once
+ * every chunk of the earlier passes is written (device-scope counters; no
+ * workgroup waits for another to arrive).  Results do not depend on the
+ * split.
  *   states        ncirc state views (device buffers must not overlap)
  *   gates         all circuits' gates concatenated; circuit c owns
  *                 gates[gate_offsets[c] .. gate_offsets[c+1])
@@ -482,14 +491,25 @@ int sv_batch_run(sv_batch_t *b, const double *params_dev, sv_stream_t st);
 int sv_batch_adjoint(sv_batch_t *b, const double *params_dev, double *grad_dev, double *loss_dev, sv_stream_t st);
 int sv_batch_destroy(sv_batch_t *b);
 
-/* Measurement helper: with stamps_dev not NULL, every later sv_batch_run and
- * sv_batch_adjoint of b writes for each circuit c the device's constant-rate
- * clock when a workgroup starts it (stamps_dev[2c]) and when that workgroup
- * has finished it (stamps_dev[2c + 1]); stamps_dev holds 2 * ncirc uint64
- * values on the batch's device and must outlive those runs.  NULL turns the
- * stamps off.  ns_per_tick (may be NULL) receives the clock period in
- * nanoseconds.  Results of the runs are unchanged. */
+/* Measurement helper: with stamps_dev not NULL, every later run of b writes
+ * the device's constant-rate clock when a workgroup starts a work item
+ * (stamps_dev[2i]) and when that workgroup has finished it (stamps_dev[2i +
+ * 1]).  sv_batch_run's items are those sv_batch_info lists (i in queue
+ * order); sv_batch_adjoint's are the circuits (i = c).  stamps_dev holds
+ * 2 * max(ncirc, nitems) uint64 values on the batch's device and must
+ * outlive those runs.  NULL turns the stamps off.  ns_per_tick (may be NULL)
+ * receives the clock period in nanoseconds.  Results of the runs are
+ * unchanged. */
 int sv_batch_set_timing(sv_batch_t *b, uint64_t *stamps_dev, double *ns_per_tick);
+
+/* The work items of b's forward runs: *nitems (may be NULL) receives their
+ * number (ncirc plus one more per extra workgroup a split circuit may take),
+ * item_circuit (host, may be NULL, cap >= nitems entries) the circuit of
+ * each item in queue order.  wait_timeouts (may be NULL) receives the number
+ * of chunk waits of split circuits that gave up (after 10 s; the run's
+ * results are then undefined) over all runs so far: it waits for b's last
+ * run.  SV_EINVAL when cap is too small. */
+int sv_batch_info(sv_batch_t *b, int64_t *nitems, int32_t *item_circuit, int64_t cap, uint64_t *wait_timeouts);
 
 /* Write, for each reduced iteration index i_r in [0, 2^(n-1-ncontrols)), the
  * index of the first pair element (bit target clear) that the scheduled

@@ -1,7 +1,7 @@
 """Binding of the batched entry points (sv_apply_circuits_batched,
 sv_adjoint_grad_batched, and the planned batch sv_batch_create / sv_batch_run /
-sv_batch_adjoint / sv_batch_set_timing / sv_batch_destroy).  Argument
-marshalling only."""
+sv_batch_adjoint / sv_batch_set_timing / sv_batch_info / sv_batch_destroy).
+Argument marshalling only."""
 from __future__ import annotations
 
 import ctypes
@@ -23,6 +23,7 @@ _sig("sv_batch_create", [ctypes.POINTER(sv_state_t), ctypes.POINTER(sv_state_t),
 _sig("sv_batch_run", [_vp, _vp, _vp])
 _sig("sv_batch_adjoint", [_vp, _vp, _vp, _vp, _vp])
 _sig("sv_batch_destroy", [_vp])
+_sig("sv_batch_info", [_vp, _i64p, ctypes.POINTER(ctypes.c_int32), ctypes.c_int64, ctypes.POINTER(ctypes.c_uint64)])
 
 
 def _states(tensors):
@@ -128,14 +129,32 @@ class Batch:
         return grad[:self.nparams_total], loss
 
     def set_timing(self, stamps=None) -> float:
-        """Per-circuit start/end clock stamps of later runs into the device
-        uint64 (or int64) tensor stamps (2 * ncirc values; None turns them
-        off).  Returns the clock period in nanoseconds."""
+        """Start/end clock stamps of later runs into the device uint64 (or
+        int64) tensor stamps: per work item of run() (the circuits items()
+        lists), per circuit of adjoint(); 2 * max(ncirc, nitems) values; None
+        turns them off.  Returns the clock period in nanoseconds."""
         ns = ctypes.c_double(0.0)
         p = ctypes.c_void_p(0 if stamps is None else stamps.data_ptr())
         _check(_L.sv_batch_set_timing(self._h, p, ctypes.byref(ns)))
         self._stamps = stamps
         return ns.value
+
+    def items(self):
+        """The forward run's work items in queue order, each a circuit index
+        (a circuit split over workgroups appears once per workgroup that may
+        join it)."""
+        n = ctypes.c_int64(0)
+        _check(_L.sv_batch_info(self._h, ctypes.byref(n), None, 0, None))
+        arr = (ctypes.c_int32 * max(1, n.value))()
+        _check(_L.sv_batch_info(self._h, None, arr, n.value, None))
+        return [int(arr[i]) for i in range(n.value)]
+
+    def wait_timeouts(self) -> int:
+        """Chunk waits of split circuits that gave up, over all runs so far
+        (waits for the last run)."""
+        v = ctypes.c_uint64(0)
+        _check(_L.sv_batch_info(self._h, None, None, 0, ctypes.byref(v)))
+        return int(v.value)
 
     def close(self) -> None:
         if getattr(self, "_h", None):

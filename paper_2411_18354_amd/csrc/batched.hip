@@ -62,6 +62,11 @@ struct BPass {
     int32_t fused;    // 1: tile descriptors [first, first + count); 0: gate `gate`
     int32_t gate;     // single: index among the circuit's gates
     int32_t first, count;
+    // circuits split over several workgroups: the pass's chunks are tickets
+    // [chunk0, chunk0 + nchunks) of the circuit, each chunk_len tiles (fused)
+    // or pairs (single gate)
+    int32_t chunk0, nchunks;
+    uint64_t chunk_len;
 };
 
 // A parameterised gate inside a fused run: its descriptor's matrix (and
@@ -81,6 +86,8 @@ struct BCirc {
     int32_t ngates;
     int32_t first_param, nparams;  // adjoint: gradient slots
     int32_t first_term, nterms;    // adjoint: Hamiltonian terms
+    int32_t group;       // forward: >= 0 when split over workgroups (its ticket counters)
+    int32_t nchunks;     // forward, split: tickets over all passes
 };
 
 // Insert the target bit (0) and the control bits (their values) into x,
@@ -110,20 +117,23 @@ __device__ __forceinline__ Mat2<R> bgate_mat(const BGate &g, const double *param
     return Mat2<R>{(R)m[0], (R)m[1], (R)m[2], (R)m[3], (R)m[4], (R)m[5], (R)m[6], (R)m[7]};
 }
 
+constexpr int kBatchPairUnroll = 4;  // pairs per lane per step of a pair loop
+
 // Apply one gate (target, controls) to amplitudes held at base[0 .. 2^nbits)
 // (LDS or global), controls below nbits enumerated, controls at or above
-// nbits already known to hold.
+// nbits already known to hold: the iteration indices [lo, min(hi, pairs)).
 template <typename R, typename I>
 __device__ __forceinline__ void gate_on_block_i(cplx_t<R> *base, int nbits, int target, uint64_t cmask,
-                                                uint64_t cvals, const Mat2<R> &mm) {
+                                                uint64_t cvals, const Mat2<R> &mm, uint64_t lo, uint64_t hi) {
     const uint64_t lowm = (nbits >= 64) ? ~0ull : ((1ull << nbits) - 1);
     const I cm = (I)(cmask & lowm);
     const I pos = cm | ((I)1 << target);
-    const I npairs = (I)1 << (nbits - 1 - __popcll((uint64_t)cm));
+    const uint64_t all = 1ull << (nbits - 1 - __popcll((uint64_t)cm));
+    const I npairs = (I)(hi < all ? hi : all);
     const I st = (I)1 << target;
     const I cv = (I)(cvals & cm);
-    constexpr int U = 4;  // pairs per lane per step: 2U loads in flight
-    for (I i0 = threadIdx.x; i0 < npairs; i0 += (I)U * kBatchThreads) {
+    constexpr int U = kBatchPairUnroll;  // 2U loads in flight
+    for (I i0 = (I)lo + threadIdx.x; i0 < npairs; i0 += (I)U * kBatchThreads) {
         cplx_t<R> x[U], y[U];
         I p1[U];
 #pragma unroll
@@ -150,11 +160,30 @@ __device__ __forceinline__ void gate_on_block_i(cplx_t<R> *base, int nbits, int 
 // tiles; for global memory up to n = 32).
 template <typename R>
 __device__ __forceinline__ void gate_on_block(cplx_t<R> *base, int nbits, int target, uint64_t cmask, uint64_t cvals,
-                                              const Mat2<R> &mm) {
+                                              const Mat2<R> &mm, uint64_t lo = 0, uint64_t hi = ~0ull) {
     if (nbits <= 32)
-        gate_on_block_i<R, uint32_t>(base, nbits, target, cmask, cvals, mm);
+        gate_on_block_i<R, uint32_t>(base, nbits, target, cmask, cvals, mm, lo, hi);
     else
-        gate_on_block_i<R, uint64_t>(base, nbits, target, cmask, cvals, mm);
+        gate_on_block_i<R, uint64_t>(base, nbits, target, cmask, cvals, mm, lo, hi);
+}
+
+// Tiles [lo, hi) of a fused pass over the state in global memory.
+template <typename R>
+__device__ __forceinline__ void fused_tiles(cplx_t<R> *psi, const BPass &p, const TileGate *__restrict__ tiles,
+                                            const SweepPat *__restrict__ pats, const SweepMember *__restrict__ mems,
+                                            cplx_t<R> *lds, uint64_t lo, uint64_t hi) {
+    const DeviceGates dg{tiles + p.first, p.count, pats, mems};
+    const uint32_t T = 1u << p.tm.m;
+    for (uint64_t tt = lo; tt < hi; ++tt) {
+        const uint64_t base = expand_index<uint64_t>(p.tm.outer, tt);
+        if (!tile_touched(base, dg))
+            continue;  // uniform
+        tile_load_dma<R, kBatchThreads>(lds, psi, base, p.tm, T);
+        __syncthreads();
+        tile_run<R, kBatchThreads, false>(lds, base, p.tm, dg);  // at its register limit
+        tile_store<R, kBatchThreads, false, 1>(psi, lds, base, p.tm, T);
+        __syncthreads();
+    }
 }
 
 template <typename R>
@@ -180,23 +209,91 @@ __device__ void run_circuit_block(const BCirc &c, const BGate *__restrict__ gate
     for (int pi = 0; pi < c.npasses; ++pi) {
         const BPass &p = passes[c.first_pass + pi];
         if (p.fused) {  // uniform
-            const DeviceGates dg{tiles + p.first, p.count, pats, mems};
-            const uint32_t T = 1u << p.tm.m;
-            for (uint64_t tt = 0; tt < p.tm.ntiles; ++tt) {
-                const uint64_t base = expand_index<uint64_t>(p.tm.outer, tt);
-                if (!tile_touched(base, dg))
-                    continue;  // uniform
-                tile_load_dma<R, kBatchThreads>(lds, psi, base, p.tm, T);
-                __syncthreads();
-                tile_run<R, kBatchThreads, false>(lds, base, p.tm, dg);  // at its register limit
-                tile_store<R, kBatchThreads, false, 1>(psi, lds, base, p.tm, T);
-                __syncthreads();
-            }
+            fused_tiles<R>(psi, p, tiles, pats, mems, lds, 0, p.tm.ntiles);
         } else {
             const BGate &g = gates[c.first_gate + p.gate];
             gate_on_block<R>(psi, c.n, g.target, g.cmask, g.cvals, bgate_mat<R>(g, params, false));
             __syncthreads();
         }
+    }
+}
+
+// Wait (lane 0 polling, the workgroup held at a barrier) until *ctr >= target,
+// then make other workgroups' writes visible to this one.  The wait is
+// bounded: after `limit` clock ticks it gives up and counts a timeout in
+// *err (the results of that run are then undefined).
+__device__ __forceinline__ void wait_count(unsigned int *ctr, unsigned int target, uint64_t limit,
+                                           unsigned int *err) {
+    if (threadIdx.x == 0) {
+        if (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            const uint64_t t0 = wall_clock64();
+            do {
+                __builtin_amdgcn_s_sleep(2);
+                if (wall_clock64() - t0 > limit) {
+                    atomicAdd(err, 1u);
+                    break;
+                }
+            } while (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");  // the CU's and the XCD's caches refetch
+    }
+    __syncthreads();
+}
+
+// A circuit split over several workgroups.  Every workgroup that joins it
+// takes chunk tickets from the circuit's counter: the chunks of all passes
+// are numbered in program order, and a chunk of pass p starts once the
+// circuit's completion count has reached the first ticket of p.  Chunks of
+// p and later cannot complete before that, so the count then says that every
+// chunk of the earlier passes is written.  The holder of the lowest unfinished
+// ticket never waits, so the circuit progresses whatever the number of
+// workgroups that have joined (one is enough); a workgroup that finds the
+// tickets used up goes back to the work queue.  Each tile or pair is
+// computed exactly as by one workgroup, so results do not depend on the
+// split.
+template <typename R>
+__device__ void run_circuit_split(const BCirc &c, const BGate *__restrict__ gates, const BPass *__restrict__ passes,
+                                  const TileGate *__restrict__ tiles, const SweepPat *__restrict__ pats,
+                                  const SweepMember *__restrict__ mems, const double *__restrict__ params,
+                                  unsigned int *gstate, uint64_t limit, unsigned int *err, cplx_t<R> *lds,
+                                  int *slot) {
+    cplx_t<R> *psi = reinterpret_cast<cplx_t<R> *>(c.psi);
+    unsigned int *next = gstate + 2 * c.group, *done = next + 1;
+    int pi = 0, ready = -1;
+    for (;;) {
+        if (threadIdx.x == 0)
+            *slot = (int)__hip_atomic_fetch_add(next, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __syncthreads();
+        const int k = *slot;
+        __syncthreads();
+        if (k >= c.nchunks)
+            break;
+        while (k >= passes[c.first_pass + pi].chunk0 + passes[c.first_pass + pi].nchunks)
+            ++pi;  // tickets only grow
+        const BPass &p = passes[c.first_pass + pi];
+        if (ready != pi) {
+            wait_count(done, (unsigned int)p.chunk0, limit, err);
+            ready = pi;
+        }
+        const uint64_t lo = (uint64_t)(k - p.chunk0) * p.chunk_len;
+        if (p.fused) {  // uniform
+            const uint64_t hi = lo + p.chunk_len < p.tm.ntiles ? lo + p.chunk_len : p.tm.ntiles;
+            fused_tiles<R>(psi, p, tiles, pats, mems, lds, lo, hi);
+        } else {
+            const BGate &g = gates[c.first_gate + p.gate];
+            gate_on_block<R>(psi, c.n, g.target, g.cmask, g.cvals, bgate_mat<R>(g, params, false), lo,
+                             lo + p.chunk_len);
+        }
+        // Publish the chunk: every wavefront waits until its own stores have
+        // reached the L2 (a workgroup barrier alone does not wait for them),
+        // then lane 0's device-scope release writes the L2 back once and
+        // counts the chunk.  (A release in every wavefront writes the L2 back
+        // eight times: a 256-circuit batch of width 16 ran 2.95 ms against
+        // 2.15 ms this way.)
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        __syncthreads();
+        if (threadIdx.x == 0)
+            __hip_atomic_fetch_add(done, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     }
 }
 
@@ -221,9 +318,11 @@ __global__ void k_batch_tile_params(const BTileJob *__restrict__ jobs, int njobs
     }
 }
 
+// Work items: items[i] is a circuit; a circuit split over workgroups appears
+// once per workgroup that may join it.
 template <typename R>
 __global__ __launch_bounds__(kBatchThreads, 4) void k_batched(const BCirc *__restrict__ circs,
-                                                           const int32_t *__restrict__ order, int ncirc,
+                                                           const int32_t *__restrict__ items, int nitems,
                                                            const BGate *__restrict__ gates,
                                                            const BPass *__restrict__ passes,
                                                            const TileGate *__restrict__ tiles,
@@ -231,9 +330,11 @@ __global__ __launch_bounds__(kBatchThreads, 4) void k_batched(const BCirc *__res
                                                            const SweepMember *__restrict__ mems,
                                                            const double *__restrict__ params,
                                                            unsigned int *__restrict__ queue,
-                                                           uint64_t *__restrict__ stamps) {
+                                                           unsigned int *gstate, uint64_t limit,
+                                                           unsigned int *err, uint64_t *__restrict__ stamps) {
     extern __shared__ unsigned char lds_raw[];
     int *item = reinterpret_cast<int *>(lds_raw);
+    int *ticket = item + 1;
     cplx_t<R> *lds = reinterpret_cast<cplx_t<R> *>(lds_raw + kBatchSlot);
     for (;;) {
         if (threadIdx.x == 0)
@@ -241,19 +342,29 @@ __global__ __launch_bounds__(kBatchThreads, 4) void k_batched(const BCirc *__res
         __syncthreads();
         const int it = *item;
         __syncthreads();
-        if (it >= ncirc)
+        if (it >= nitems)
             break;
         const uint64_t t0 = stamps ? wall_clock64() : 0;
-        run_circuit_block<R>(circs[order[it]], gates, passes, tiles, pats, mems, params, lds);
+        const BCirc &c = circs[items[it]];
+        if (c.group >= 0)  // uniform
+            run_circuit_split<R>(c, gates, passes, tiles, pats, mems, params, gstate, limit, err, lds, ticket);
+        else
+            run_circuit_block<R>(c, gates, passes, tiles, pats, mems, params, lds);
         __syncthreads();
         if (stamps && threadIdx.x == 0) {
-            stamps[2 * order[it]] = t0;
-            stamps[2 * order[it] + 1] = wall_clock64();
+            stamps[2 * it] = t0;
+            stamps[2 * it + 1] = wall_clock64();
         }
     }
 }
 
 __global__ void k_zero_u32(unsigned int *p) { *p = 0u; }
+
+__global__ void k_zero_words(unsigned int *p, int count) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count)
+        p[i] = 0u;
+}
 
 // ----------------------------------------------------------------- adjoint
 
@@ -451,6 +562,7 @@ static int build_circuit(const BatchArgs &A, int c, int dtype, bool adjoint, Cir
     const int64_t p0 = A.param_off ? A.param_off[c] : 0, p1 = A.param_off ? A.param_off[c + 1] : 0;
     BCirc &bc = out->bc;
     memset(&bc, 0, sizeof(bc));
+    bc.group = -1;
     bc.psi = s.data;
     bc.lam = adjoint ? A.lams[c].data : nullptr;
     bc.n = s.n;
@@ -609,15 +721,76 @@ struct BatchHost {
     std::vector<BTileJob> ajobs;
     std::vector<int32_t> atslot, slot_param;
     size_t adj_lds = 0;
-    std::vector<int32_t> order;
+    std::vector<int32_t> order;    // work items in queue order (each a circuit)
+    int ngroups = 0;               // circuits split over workgroups
     std::vector<double> gens;
     std::vector<int32_t> gen_of;
     std::vector<DTerm> terms;
 };
 
+// A chunk wait gives up after this long.  A chunk takes far less (its tiles
+// or pair steps are bounded), so only a workgroup stalled from outside (the
+// device preempted, a fault elsewhere) can reach it.
+constexpr uint64_t kWaitLimitSeconds = 10;
+
+// A circuit that costs more than the batch's mean load per workgroup is
+// split into that many workgroups' worth of work items (at most the
+// "batch_split" knob): else the widest circuits, started first, still run
+// long after the rest of the batch is done.  A split circuit's passes are cut
+// into chunk tickets of whole tiles (fused passes) or whole pair-loop steps
+// (single gates), kChunksPerWorker per joining workgroup.  Measured on the
+// 4096-circuit batch (widths 10-20): splitting also the circuits above a
+// quarter or a half of the mean load, or into items of half of it, was
+// slower, and so were 8 or 16 chunks per workgroup.
+constexpr int kChunksPerWorker = 4;
+
+static void split_circuits(BatchHost *h, const std::vector<double> &cost, std::vector<int32_t> *workers) {
+    const int gmax = tuning().batch_split;
+    if (gmax <= 1)
+        return;
+    DeviceInfo di;
+    const double P = device_info(&di) == SV_OK ? 2.0 * di.num_cus : 512.0;  // persistent workgroups
+    double W = 0.0;
+    for (double c : cost)
+        W += c;
+    const double load = W / P;
+    const int kc = kChunksPerWorker;
+    for (size_t c = 0; c < h->circs.size(); ++c) {
+        BCirc &bc = h->circs[c];
+        if (bc.npasses == 0 || !(cost[c] > load))
+            continue;  // LDS-resident, empty, or short enough
+        const int g = (int)std::min<double>(gmax, std::ceil(cost[c] / load));
+        if (g < 2 || (int64_t)bc.npasses * g * kc > (1 << 30))
+            continue;
+        int64_t k = 0;
+        for (int pi = 0; pi < bc.npasses; ++pi) {
+            BPass &p = h->passes[bc.first_pass + pi];
+            uint64_t total, unit;
+            if (p.fused) {
+                total = p.tm.ntiles;
+                unit = 1;
+            } else {
+                const BGate &gt = h->gates[bc.first_gate + p.gate];
+                total = 1ull << (bc.n - 1 - popcount64(gt.cmask));
+                unit = (uint64_t)kBatchPairUnroll * kBatchThreads;
+            }
+            const uint64_t steps = (total + unit - 1) / unit;
+            const uint64_t want = std::max<uint64_t>(1, std::min<uint64_t>(steps, (uint64_t)g * kc));
+            const uint64_t len = (steps + want - 1) / want * unit;
+            p.chunk0 = (int32_t)k;
+            p.nchunks = (int32_t)((total + len - 1) / len);
+            p.chunk_len = len;
+            k += p.nchunks;
+        }
+        bc.group = h->ngroups++;
+        bc.nchunks = (int32_t)k;  // at most npasses * 4 * 64
+        (*workers)[c] = g;
+    }
+}
+
 // Checks the batch description, plans every circuit (in parallel over host
 // threads for large batches) and concatenates the tables; circuits are
-// ordered by decreasing cost for the work queue.
+// ordered by decreasing cost per workgroup for the work queue.
 static int build_batch(const BatchArgs &A, bool adjoint, BatchHost *h, int *dtype) {
     if (A.ncirc < 1 || !A.states || !A.gate_off || (A.gate_off[A.ncirc] > 0 && !A.gates))
         return fail(SV_EINVAL, "bad batch description (ncirc %d)", A.ncirc);
@@ -747,9 +920,15 @@ static int build_batch(const BatchArgs &A, bool adjoint, BatchHost *h, int *dtyp
         h->circs.push_back(b.bc);
         cost[c] = b.cost;
     }
-    h->order.resize(A.ncirc);
-    std::iota(h->order.begin(), h->order.end(), 0);
-    std::stable_sort(h->order.begin(), h->order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+    std::vector<int32_t> workers(A.ncirc, 1);
+    if (!adjoint)
+        split_circuits(h, cost, &workers);
+    std::vector<int32_t> circ(A.ncirc);
+    std::iota(circ.begin(), circ.end(), 0);
+    std::stable_sort(circ.begin(), circ.end(),
+                     [&](int a, int b) { return cost[a] / workers[a] > cost[b] / workers[b]; });
+    for (int c : circ)
+        h->order.insert(h->order.end(), (size_t)workers[c], c);
     return SV_OK;
 }
 
@@ -769,9 +948,15 @@ struct BatchDevice {
     int32_t *atslot = nullptr, *slot_param = nullptr;
     size_t adj_lds = 0;
     int32_t *order = nullptr, *gen_of = nullptr;
+    int nitems = 0;
     double *gens = nullptr;
     DTerm *terms = nullptr;
     unsigned int *queue = nullptr;
+    // split circuits: two ticket counters each, then the count of waits
+    // that timed out
+    unsigned int *gstate = nullptr;
+    int ngroups = 0;
+    uint64_t wait_limit = 0;  // clock ticks
 };
 
 // Stream-ordered release when async (after the kernels enqueued on st),
@@ -779,7 +964,7 @@ struct BatchDevice {
 static void batch_release(BatchDevice *d, bool async, hipStream_t st) {
     void *ps[] = {d->circs,  d->gates,  d->passes, d->tiles,  d->pats, d->mems, d->jobs,  d->apasses,
                   d->atiles, d->ajobs,  d->atslot, d->slot_param, d->order, d->gen_of, d->gens,    d->terms,
-                  d->queue};
+                  d->queue, d->gstate};
     for (void *p : ps)
         if (p)
             (void)(async ? hipFreeAsync(p, st) : hipFree(p));
@@ -836,6 +1021,7 @@ static int upload_batch(const BatchHost &h, bool async, hipStream_t st, BatchDev
     d->adj_lds = h.adj_lds;
     if (r == SV_OK)
         r = dev_copy(&d->order, h.order, async, st);
+    d->nitems = (int)h.order.size();
     if (r == SV_OK)
         r = dev_copy(&d->gen_of, h.gen_of, async, st, 1);
     if (r == SV_OK)
@@ -849,6 +1035,27 @@ static int upload_batch(const BatchHost &h, bool async, hipStream_t st, BatchDev
             (void)hipGetLastError();
             d->queue = nullptr;
             r = fail(SV_ENOMEM, "device allocation failed");
+        }
+    }
+    d->ngroups = h.ngroups;
+    if (r == SV_OK && h.ngroups > 0) {
+        const int words = 2 * h.ngroups + 1;
+        hipError_t e = async ? hipMallocAsync((void **)&d->gstate, words * sizeof(unsigned int), st)
+                             : hipMalloc((void **)&d->gstate, words * sizeof(unsigned int));
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            d->gstate = nullptr;
+            r = fail(SV_ENOMEM, "device allocation failed");
+        } else {
+            hipLaunchKernelGGL(k_zero_words, dim3((words + 255) / 256), dim3(256), 0, st, d->gstate, words);
+            if (!async)
+                r = hipStreamSynchronize(st) == hipSuccess ? SV_OK : fail(SV_EHIP, "clearing the batch counters failed");
+            int dev = 0, khz = 0;
+            if (r == SV_OK && (hipGetDevice(&dev) != hipSuccess ||
+                               hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess ||
+                               khz <= 0))
+                r = fail(SV_EHIP, "device reports no constant-rate clock");
+            d->wait_limit = (uint64_t)khz * 1000ull * kWaitLimitSeconds;
         }
     }
     if (r != SV_OK)
@@ -874,17 +1081,24 @@ static int launch_forward(int dtype, const BatchDevice &d, int ncirc, const doub
                                                           (int)kBatchDynLds);
     if (a != hipSuccess)
         return fail(SV_EHIP, "LDS limit: %s", hipGetErrorString(a));
-    const unsigned grid = persistent_grid(ncirc);
+    (void)ncirc;
+    const unsigned grid = persistent_grid(d.nitems);
     if (d.njobs > 0)
         hipLaunchKernelGGL(k_batch_tile_params, dim3((d.njobs + 255) / 256), dim3(256), 0, s, d.jobs, d.njobs, params,
                            d.tiles, d.mems);
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, s, d.queue);
+    if (d.ngroups > 0)  // the ticket counters, not the timeout count after them
+        hipLaunchKernelGGL(k_zero_words, dim3((2 * d.ngroups + 255) / 256), dim3(256), 0, s, d.gstate,
+                           2 * d.ngroups);
+    unsigned int *err = d.gstate ? d.gstate + 2 * d.ngroups : nullptr;
     if (dtype == SV_C128)
         hipLaunchKernelGGL(k_batched<double>, dim3(grid), dim3(kBatchThreads), kBatchDynLds, s, d.circs, d.order,
-                           ncirc, d.gates, d.passes, d.tiles, d.pats, d.mems, params, d.queue, stamps);
+                           d.nitems, d.gates, d.passes, d.tiles, d.pats, d.mems, params, d.queue, d.gstate,
+                           d.wait_limit, err, stamps);
     else
         hipLaunchKernelGGL(k_batched<float>, dim3(grid), dim3(kBatchThreads), kBatchDynLds, s, d.circs, d.order,
-                           ncirc, d.gates, d.passes, d.tiles, d.pats, d.mems, params, d.queue, stamps);
+                           d.nitems, d.gates, d.passes, d.tiles, d.pats, d.mems, params, d.queue, d.gstate,
+                           d.wait_limit, err, stamps);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess)
         return fail(SV_EHIP, "batched launch failed: %s", hipGetErrorString(e));
@@ -939,6 +1153,7 @@ struct sv_batch {
     int64_t nparams_total = 0;
     bool has_adjoint = false;
     sv::BatchDevice fwd, adj;
+    std::vector<int32_t> items; // the forward run's work items (circuits), in queue order
     hipEvent_t done = nullptr;  // end of the last run
     uint64_t *stamps = nullptr; // per-circuit start/end clock of later runs (measurement), or none
 };
@@ -967,6 +1182,7 @@ int sv_batch_create(const sv_state_t *states, const sv_state_t *lam_states, int 
     b->nparams_total = nparams_total;
     b->has_adjoint = adj;
     int r = hipGetDevice(&b->device) == hipSuccess ? SV_OK : fail(SV_EHIP, "no current device");
+    b->items = hf.order;
     if (r == SV_OK)
         r = upload_batch(hf, false, nullptr, &b->fwd);
     if (r == SV_OK && adj)
@@ -1029,6 +1245,32 @@ int sv_batch_set_timing(sv_batch_t *b, uint64_t *stamps_dev, double *ns_per_tick
         if (khz <= 0)
             return fail(SV_EHIP, "device reports no constant-rate clock");
         *ns_per_tick = 1e6 / (double)khz;
+    }
+    return SV_OK;
+}
+
+int sv_batch_info(sv_batch_t *b, int64_t *nitems, int32_t *item_circuit, int64_t cap, uint64_t *wait_timeouts) {
+    clear_error();
+    if (!b)
+        return fail(SV_EINVAL, "batch is NULL");
+    const int64_t n = (int64_t)b->items.size();
+    if (nitems)
+        *nitems = n;
+    if (item_circuit) {
+        if (cap < n)
+            return fail(SV_EINVAL, "item_circuit holds %lld entries, the batch has %lld items", (long long)cap,
+                        (long long)n);
+        std::copy(b->items.begin(), b->items.end(), item_circuit);
+    }
+    if (wait_timeouts) {
+        *wait_timeouts = 0;
+        if (b->fwd.ngroups > 0) {
+            if (b->done)
+                SV_HIP_TRY(hipEventSynchronize(b->done));
+            unsigned int v = 0;
+            SV_HIP_TRY(hipMemcpy(&v, b->fwd.gstate + 2 * b->fwd.ngroups, sizeof(v), hipMemcpyDeviceToHost));
+            *wait_timeouts = v;
+        }
     }
     return SV_OK;
 }

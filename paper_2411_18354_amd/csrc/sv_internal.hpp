@@ -167,6 +167,7 @@ struct Tuning {
     int fuse_pairs;       // fused runs: apply adjacent coset-closed pair gates together
     int plan_lookahead;   // fused runs: lookahead depth choosing a run's high qubits (0-2)
     int fuse_perm;        // fused runs: apply runs of X gates as one gather
+    int batch_split;      // batches: most workgroups one circuit may be split over
 };
 Tuning &tuning();
 
