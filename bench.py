@@ -1197,22 +1197,47 @@ def main():
         protocol32 = protocol_n32(sv, W, torch, np, stream, U)
 
     cpu = None
+    cpu_detail = None
     if args.cpu_seconds > 0:
         import oracle
         log("CPU oracle baseline (budget %.0f s)" % args.cpu_seconds)
         Uc = oracle.gate_matrix("U", matrix=tuple(U))
         host = psi_host.copy()
+        threads = oracle.num_threads()
+        per_case = [[] for _ in cases]
         done, t0 = 0, time.perf_counter()
         while time.perf_counter() - t0 < args.cpu_seconds:
             t, ctrls = cases[done % len(cases)]
+            g0 = time.perf_counter()
             oracle.apply_gate(host, n, t, ctrls, (), Uc)
+            per_case[done % len(cases)].append(time.perf_counter() - g0)
             done += 1
         el = time.perf_counter() - t0
+        # the same loop on one thread, over a shorter budget
+        oracle.set_num_threads(1)
+        done1, t1 = 0, time.perf_counter()
+        while time.perf_counter() - t1 < args.cpu_seconds / 3:
+            t, ctrls = cases[done1 % len(cases)]
+            oracle.apply_gate(host, n, t, ctrls, (), Uc)
+            done1 += 1
+        el1 = time.perf_counter() - t1
+        oracle.set_num_threads(threads)
+        # the 200-gate n=12 random circuit, once, all threads
+        c0 = W.random_gates_n12()
+        g0 = time.perf_counter()
+        oracle.run_circuit(c0)
+        cfg0_ms = (time.perf_counter() - g0) * 1e3
         model, phys = cpu_model()
-        cpu = {"value": round(done / el, 4), "unit": "gate updates/s", "cores": oracle.num_threads(),
+        cpu = {"value": round(done / el, 4), "unit": "gate updates/s", "cores": threads,
                "kind": "oracle", "cpu_model": model, "physical_cores": phys,
+               "single_thread_value": round(done1 / el1, 4),
                "sample": "%d gates of the %d-gate sweep in order on the same n=28 state, plain loop over "
-                         "all 2^28 indices per gate, OpenMP, %.1f s" % (done, len(cases), el)}
+                         "all 2^28 indices per gate, OpenMP, %.1f s (single thread: %d gates, %.1f s)"
+                         % (done, len(cases), el, done1, el1)}
+        cpu_detail = {"per_case_ms_mean": [{"t": t, "c": len(ctrls), "controls": list(ctrls), "calls": len(v),
+                                            "ms": round(1e3 * float(np.mean(v)), 2) if v else None}
+                                           for (t, ctrls), v in zip(cases, per_case)],
+                      "random_gates_n12_200_gates_ms": round(cfg0_ms, 2), "threads": threads}
         del host
 
     by_c = {}
@@ -1238,6 +1263,7 @@ def main():
         "graph_protocol_n32": protocol32,
         "control_positions": positions,
         "extras": extras,
+        "cpu_oracle": cpu_detail,
     }
     detail_path = write_detail(detail, args.detail_out)
     out = {

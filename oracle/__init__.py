@@ -61,6 +61,8 @@ def lib():
         L.or_norm2.restype = ctypes.c_double
         L.or_basis.argtypes = [dp, ctypes.c_int, u64]
         L.or_basis.restype = None
+        L.or_set_num_threads.argtypes = [ctypes.c_int]
+        L.or_set_num_threads.restype = None
         L.or_apply_block_low.argtypes = [dp, ctypes.c_int, ctypes.c_int, dp]
         L.or_apply_block_low.restype = None
         L.or_swap_qubits.argtypes = [dp, ctypes.c_int, ctypes.c_int, ctypes.c_int]
@@ -101,6 +103,12 @@ def _dptr(a: np.ndarray):
 
 def num_threads() -> int:
     return int(lib().or_num_threads())
+
+
+def set_num_threads(k: int) -> None:
+    """Threads of later parallel loops (timing only: results do not depend
+    on it)."""
+    lib().or_set_num_threads(int(k))
 
 
 # --------------------------------------------------------------------------

@@ -221,6 +221,18 @@ int or_num_threads(void)
 #endif
 }
 
+/* Use k threads in later parallel loops (for timing; every loop writes
+ * disjoint outputs, so results do not depend on k). */
+void or_set_num_threads(int k)
+{
+#ifdef _OPENMP
+    extern void omp_set_num_threads(int);
+    omp_set_num_threads(k > 0 ? k : 1);
+#else
+    (void)k;
+#endif
+}
+
 /* A 2^k x 2^k complex matrix M (row-major, interleaved re/im) applied to the
  * k lowest qubits: each row of 2^k consecutive amplitudes becomes M . row.
  * Plain triple loop through a temporary row. */

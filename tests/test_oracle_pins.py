@@ -801,3 +801,20 @@ def test_q32_qft_within_rigorous_bound():
     G = len(circ.gates)
     assert err <= (G + 1) * (math.sqrt(128) * 2.0 ** -31 + 1e-13)
     assert err < 1e-7
+
+
+def test_thread_count_does_not_change_results():
+    """The oracle's parallel loops write disjoint outputs, so one thread and
+    all threads give the same bits (the CPU baseline is timed both ways)."""
+    n = 14
+    psi = W.random_state(n, 3)
+    c = W.random_gates_n12(seed=4, n=n, ngates=40)
+    threads = oracle.num_threads()
+    try:
+        oracle.set_num_threads(1)
+        one = oracle.run_circuit(c, psi0=psi)
+        assert oracle.num_threads() == 1
+    finally:
+        oracle.set_num_threads(threads)
+    every = oracle.run_circuit(c, psi0=psi)
+    assert np.array_equal(one, every)
