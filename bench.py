@@ -649,8 +649,9 @@ def measure_fixed_point(sv, W, torch, np, stream, psi_host, cases, U, energy):
             log("paper circuit", name, "%d-bit fixed point" % bits)
             st = sv.FixedState(29, dtype)
             row = {"gates": len(circ.gates)}
-            for label, fl in (("masked", sv.SV_MASKED), ("scheduled", 0)):
+            for label, fl in (("masked", sv.SV_MASKED), ("scheduled", 0), ("scheduled_fused", sv.SV_FUSE)):
                 p = sv.Circuit(29, circ, dtype=dtype, flags=fl)
+                row[label + "_passes"] = p.info()["passes"]
 
                 def run():
                     sv.sv_init(st, 1, stream=stream)
@@ -679,15 +680,16 @@ def measure_fixed_point(sv, W, torch, np, stream, psi_host, cases, U, energy):
     want = np.fft.ifft(psi0[rev]) * np.sqrt(N)
     circ = W.qft(ne)
     errs = {}
-    for label, td in (("c128", torch.complex128), ("c64", torch.complex64), ("q32", sv.SV_CQ32),
-                      ("q16", sv.SV_CQ16)):
+    for label, td, fl in (("c128", torch.complex128, 0), ("c64", torch.complex64, 0), ("q32", sv.SV_CQ32, 0),
+                          ("q16", sv.SV_CQ16, 0), ("q32_fused", sv.SV_CQ32, sv.SV_FUSE),
+                          ("q16_fused", sv.SV_CQ16, sv.SV_FUSE)):
         src = torch.from_numpy(psi0).to(dev)
         if isinstance(td, int):
             st = sv.FixedState(ne, td)
         else:
             st = torch.empty(N, dtype=td, device=dev)
         sv.sv_convert(st, src, stream=stream)
-        sv.sv_apply_circuit(st, circ, flags=0, stream=stream)
+        sv.sv_apply_circuit(st, circ, flags=fl, stream=stream)
         res = torch.empty(N, dtype=torch.complex128, device=dev)
         sv.sv_convert(res, st, stream=stream)
         torch.cuda.synchronize()

@@ -304,9 +304,15 @@ typedef struct sv_circuit sv_circuit_t;
  * sv_circuit_run (every gate's param must be < nparams).  Validation covers
  * every gate before anything is allocated, so an error names the first bad
  * gate (its index is in the message) and creates nothing.  The returned
- * handle is released with sv_circuit_destroy.  Fixed-point circuits run
- * one block-scaled gate kernel per gate: flags may hold SV_GRAPH and
- * SV_MASKED only (SV_ENOTSUP otherwise). */
+ * handle is released with sv_circuit_destroy.  Fixed-point circuits take
+ * SV_FUSE, SV_GRAPH and SV_MASKED (SV_ENOTSUP for SV_DENSE and SV_REMAP):
+ * without SV_FUSE each gate runs the block-scaled gate kernel; with it, a
+ * fused run decodes each tile (whole 64-amplitude blocks: the tile holds
+ * qubits 0..5) to float (SV_CQ16) or double (SV_CQ32), applies the run's
+ * operations as for complex64 / complex128 tiles, and re-encodes every
+ * block of the tile once (as described at SV_CQ16), so blocks are rounded
+ * once per pass instead of once per gate; tiles no operation of the run
+ * touches keep their bytes. */
 int sv_circuit_create(int n, int dtype, const sv_gate_t *gates, int ngates, int nparams, int flags,
                       sv_circuit_t **out);
 

@@ -209,13 +209,19 @@ static int plan_circuit(sv_circuit *c, std::vector<TileGate> &tiles, std::vector
         if (g.param < 0)
             gate_matrix(g.kind, g.theta, g.U, &mats[(size_t)8 * i]);
     }
-    const int di = c->dtype == SV_C128 ? 0 : 1;
+    // tiles hold the arithmetic type: fixed-point states decode 16-bit codes
+    // to float (complex64 tiles) and 32-bit codes to double (complex128)
+    const int tdt = tile_dtype(c->dtype);
+    const int di = tdt == SV_C128 ? 0 : 1;
     const bool masked = c->flags & SV_MASKED;
-    const bool fuse = (c->flags & SV_FUSE) && !masked;
     c->m = std::min(std::min(tuning().tile_log2[di], c->n), c->m_cap);
     const int m = c->m;
+    // a fixed-point tile holds whole 64-amplitude blocks
+    const bool fuse = (c->flags & SV_FUSE) && !masked && (!is_fixed(c->dtype) || m >= kQBlockBits);
     // the tile holds the a lowest qubits plus at most kTileMaxHigh others
-    const int a = std::max(std::min(tuning().tile_low_bits[di], m), m - kTileMaxHigh);
+    int a = std::max(std::min(tuning().tile_low_bits[di], m), m - kTileMaxHigh);
+    if (is_fixed(c->dtype))
+        a = std::min(std::max(a, kQBlockBits), m);
     const int min_run = std::max(1, tuning().fuse_min_gates);
     std::vector<int> tile_slot(G, -1);
     std::vector<char> diag(G, 0);
@@ -539,9 +545,11 @@ template <typename T> static int upload(T **dst, const std::vector<T> &src, bool
     return SV_OK;
 }
 
-// Dynamic LDS of a fused pass: the tile, then the diagonal-sweep tables.
+// Dynamic LDS of a fused pass: the tile (in the arithmetic type), then the
+// diagonal-sweep tables.
 static size_t fused_lds(int m, int dtype) {
-    return ((size_t)1 << m) * amp_bytes(dtype) + (size_t)diag_table_doubles((uint32_t)m) * sizeof(double);
+    return ((size_t)1 << m) * amp_bytes(tile_dtype(dtype)) +
+           (size_t)diag_table_doubles((uint32_t)m) * sizeof(double);
 }
 
 // One fused pass: one workgroup per launched tile.
@@ -572,9 +580,9 @@ int circuit_create(int n, int dtype, const sv_gate_t *gates, int ngates, int npa
         return fail(SV_EINVAL, "nparams %d < 0", nparams);
     if (flags & ~(SV_FUSE | SV_GRAPH | SV_MASKED | SV_DENSE | SV_REMAP))
         return fail(SV_EINVAL, "unknown flags 0x%x", flags);
-    if (is_fixed(dtype) && (flags & (SV_FUSE | SV_DENSE | SV_REMAP)))
-        return fail(SV_ENOTSUP, "fixed-point (SV_CQ16, SV_CQ32) circuits take SV_GRAPH and SV_MASKED only (flags 0x%x)",
-                    flags);
+    if (is_fixed(dtype) && (flags & (SV_DENSE | SV_REMAP)))
+        return fail(SV_ENOTSUP, "fixed-point (SV_CQ16, SV_CQ32) circuits take SV_FUSE, SV_GRAPH and SV_MASKED only "
+                                "(flags 0x%x)", flags);
     for (int i = 0; i < ngates; ++i)
         SV_TRY(validate_circuit_gate(n, nparams, gates[i], i));
     std::unique_ptr<sv_circuit> c(new sv_circuit());
@@ -621,7 +629,9 @@ int circuit_create(int n, int dtype, const sv_gate_t *gates, int ngates, int npa
     }
     // large LDS tiles need the per-kernel limit raised before any launch
     const size_t lds = fused_lds(c->m, dtype);
-    if (lds > 65536 && !is_fixed(dtype)) {
+    if (lds > 65536 && is_fixed(dtype)) {
+        SV_TRY(fixed_tile_lds_limit(dtype, lds));
+    } else if (lds > 65536) {
         if (dtype == SV_C128)
             SV_HIP_TRY(hipFuncSetAttribute((const void *)k_tile<double, 512, DeviceGates>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
@@ -673,12 +683,20 @@ template <typename R> static int enqueue(sv_circuit *c, cplx_t<R> *psi, const do
     return SV_OK;
 }
 
-// Fixed-point state: one block-scaled gate kernel per gate, matrices from
-// the plan's device table (parameterised ones written there first).
+// Fixed-point state: fused runs decode, run and re-encode tiles; other gates
+// run the block-scaled gate kernel, matrices from the plan's device table
+// (parameterised ones written there first).
 static int enqueue_fixed(sv_circuit *c, void *state, const double *params, hipStream_t st) {
     SV_TRY(circuit_param_mats(c, params, st));
-    for (const Pass &p : c->passes)
-        SV_TRY(launch_fixed_gate(state, p.fx, nullptr, c->d_mats + (size_t)8 * p.gate, st));
+    const size_t lds = fused_lds(c->m, c->dtype);
+    for (const Pass &p : c->passes) {
+        if (p.fused) {
+            DeviceGates dg{c->d_tiles + p.first, p.count, c->d_pats, c->d_mems};
+            SV_TRY(launch_fixed_tile_pass(state, c->n, c->dtype, p.tm, dg, lds, st));
+        } else {
+            SV_TRY(launch_fixed_gate(state, p.fx, nullptr, c->d_mats + (size_t)8 * p.gate, st));
+        }
+    }
     return SV_OK;
 }
 

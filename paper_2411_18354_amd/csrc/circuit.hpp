@@ -12,6 +12,16 @@ struct ParamJob {
     int32_t tile_slot;  // fused-run descriptor index or -1
 };
 
+// The complex type a fused tile holds: fixed-point states decode 16-bit
+// codes to float and 32-bit codes to double.
+inline int tile_dtype(int dtype) { return dtype == SV_CQ32 ? SV_C128 : dtype == SV_CQ16 ? SV_C64 : dtype; }
+
+// Fused pass over a block-scaled fixed-point state (the tile's qubit set
+// holds qubits 0..5): decode each tile into LDS, run, re-encode its blocks.
+int launch_fixed_tile_pass(void *state, int n, int dtype, const TileMap &tm, const DeviceGates &dg, size_t lds,
+                           hipStream_t st);
+int fixed_tile_lds_limit(int dtype, size_t lds);
+
 struct Pass {
     bool fused;
     bool dense = false;  // dense k-qubit block: gates [first, first+count) of the dense list

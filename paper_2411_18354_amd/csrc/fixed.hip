@@ -27,7 +27,7 @@
 #include <algorithm>
 #include <cstring>
 
-#include "gate_math.hpp"
+#include "circuit.hpp"
 
 namespace sv {
 
@@ -466,6 +466,62 @@ __global__ __launch_bounds__(256) void k_fix_basis(char *__restrict__ codes, int
         scales[k] = (int8_t)((k == (b >> kQBlockBits)) ? Q::kOneScale : Q::kScaleMin);
 }
 
+// ---------------------------------------------------------------- fused pass
+//
+// A fused run over a fixed-point state: each workgroup decodes one tile (the
+// 2^m amplitudes sharing the index bits outside the run's qubit set, which
+// holds qubits 0..5, so a tile is whole blocks) into LDS in the format's
+// arithmetic type, applies the run's operations there with the same tile code
+// as complex states (float tiles for 16-bit codes, double for 32-bit), and
+// re-encodes every block of the tile once.  So a block is rounded once per
+// pass instead of once per gate.  A 16-lane group holds one block, 4
+// amplitudes per lane, as in the gate kernel.
+template <typename Q>
+__global__ __launch_bounds__(512, 4) void k_fix_tile(char *__restrict__ codes, int8_t *__restrict__ scales,
+                                                     TileMap tm, DeviceGates gates) {
+    using R = typename Q::R;
+    constexpr size_t kBlockBytes = 64 * Q::kAmpBytes;
+    extern __shared__ unsigned char lds_raw[];
+    cplx_t<R> *tile = reinterpret_cast<cplx_t<R> *>(lds_raw);
+    const uint64_t base = expand_index<uint64_t>(tm.outer, tm.tile0 + blockIdx.x);
+    if (!tile_touched(base, gates))
+        return;  // no operation of the run touches it: its blocks stay as they are
+    const uint32_t nblk = 1u << (tm.m - kQBlockBits);
+    const int j = threadIdx.x & 15;
+    for (uint32_t bl = threadIdx.x >> 4; bl < nblk; bl += 512 / 16) {
+        const uint32_t t0 = bl << kQBlockBits;  // tile index of the block's first amplitude
+        const uint64_t b = (base | tile_offset(tm, t0)) >> kQBlockBits;
+        const typename Q::Lane w = Q::ld(codes + b * kBlockBytes, j);
+        R re[4], im[4];
+        Q::decode(w, scales[b], re, im);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            cplx_t<R> v;
+            v.x = re[i];
+            v.y = im[i];
+            tile[t0 + 4 * j + i] = v;
+        }
+    }
+    __syncthreads();
+    tile_run<R, 512>(tile, base, tm, gates);
+    __syncthreads();
+    for (uint32_t bl = threadIdx.x >> 4; bl < nblk; bl += 512 / 16) {
+        const uint32_t t0 = bl << kQBlockBits;
+        const uint64_t b = (base | tile_offset(tm, t0)) >> kQBlockBits;
+        R re[4], im[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const cplx_t<R> v = tile[t0 + 4 * j + i];
+            re[i] = v.x;
+            im[i] = v.y;
+        }
+        const int s = Q::scale(group16_max<R>(absmax4<R>(re, im)));
+        Q::st(codes + b * kBlockBytes, j, Q::encode(re, im, s));
+        if (j == 0)
+            scales[b] = (int8_t)s;
+    }
+}
+
 // ---------------------------------------------------------------- host side
 
 static int8_t *fixed_scales(void *state, int n, int dtype) {
@@ -608,6 +664,32 @@ static unsigned flat_grid(uint64_t N) {
     if (device_info(&di) != SV_OK)
         di.num_cus = 256;
     return (unsigned)std::max<uint64_t>(1, std::min<uint64_t>((N + 255) / 256, (uint64_t)di.num_cus * 16));
+}
+
+int fixed_tile_lds_limit(int dtype, size_t lds) {
+    const void *fn = dtype == SV_CQ16 ? (const void *)k_fix_tile<Q16> : (const void *)k_fix_tile<Q32>;
+    SV_HIP_TRY(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    return SV_OK;
+}
+
+int launch_fixed_tile_pass(void *state, int n, int dtype, const TileMap &tm_in, const DeviceGates &dg, size_t lds,
+                           hipStream_t st) {
+    if (tm_in.m < (uint32_t)kQBlockBits || tm_in.a < (uint32_t)kQBlockBits)
+        return fail(SV_EINVAL, "fixed-point tile (m=%u, contiguous %u) must hold whole blocks", tm_in.m, tm_in.a);
+    char *codes = (char *)state;
+    int8_t *sc = fixed_scales(state, n, dtype);
+    TileMap tm = tm_in;
+    tm.tab = 1;  // lds includes the tables
+    for (uint64_t t0 = 0; t0 < tm.ntiles; t0 += kMaxGridBlocks) {
+        tm.tile0 = t0;
+        const dim3 grid((unsigned)std::min(kMaxGridBlocks, tm_in.ntiles - t0));
+        if (dtype == SV_CQ16)
+            hipLaunchKernelGGL(k_fix_tile<Q16>, grid, dim3(512), lds, st, codes, sc, tm, dg);
+        else
+            hipLaunchKernelGGL(k_fix_tile<Q32>, grid, dim3(512), lds, st, codes, sc, tm, dg);
+        SV_LAUNCH_CHECK();
+    }
+    return SV_OK;
 }
 
 template <typename Q, typename RD> static int decode_to(const sv_state_t *dst, const sv_state_t *src, hipStream_t st) {

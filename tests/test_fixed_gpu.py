@@ -331,3 +331,139 @@ def test_x_on_top_qubit_swaps_halves_n32(C):
     assert torch.equal(q.data[cb:cb + hs], before[cb + hs:]) and torch.equal(q.data[cb + hs:], before[cb:cb + hs])
     del before, q
     torch.cuda.empty_cache()
+
+
+# ---------------------------------------------------------------- fused passes
+#
+# A fused pass decodes each tile (whole blocks), runs the pass's gates in the
+# format's arithmetic type and re-encodes every block of the tile once.  The
+# re-encoding of a pass moves the state by at most sqrt(128) * step in
+# 2-norm (each block's 128 components by half a step of that block's scale,
+# at most step times the block's largest component; the blocks' largest
+# components squared sum to at most 1), so after P passes the state is within
+# (P + 1) * sqrt(128) * step of the exact one, plus the arithmetic rounding of
+# each gate (float for 16-bit codes, double for 32-bit).
+
+ARITH = {16: 1e-6, 32: 1e-14}  # rounding per gate, 2-norm, unit state
+
+
+def _fused_bound(C, passes, gates):
+    return (passes + 1) * math.sqrt(128) * C.step + gates * ARITH[C.bits]
+
+
+def _fused_cases():
+    return {
+        "random_n14": (W.random_gates_n12(seed=61, n=14, ngates=300), W.random_state(14, 62)),
+        "haar_values_n13": (_haar_circuit(13, 200, 63), W.random_state(13, 64)),
+        "hea_n12": (W.hea(12, 4, seed=65), None),
+    }
+
+
+@pytest.mark.parametrize("case", ["random_n14", "haar_values_n13", "hea_n12"])
+def test_fused_circuit_within_bound(C, case):
+    """Fused passes against the exact (double oracle) result, within the
+    bound of the passes actually run; the plan fuses the circuit into far
+    fewer passes than gates."""
+    circ, psi = _fused_cases()[case]
+    n, G = circ.n, len(circ.gates)
+    params = circ.params if circ.nparams else None
+    exact = oracle.run_circuit(circ, params, psi)
+    plan = sv.Circuit(n, circ, dtype=C.dtype, nparams=circ.nparams, flags=sv.SV_FUSE)
+    try:
+        P = plan.info()["passes"]
+        assert P < G // 3, (P, G)
+        q = _encode_gpu(psi, n, C) if psi is not None else _new(n, C)
+        if psi is None:
+            sv.sv_init(q, 0)
+        plan.run(q, torch.from_numpy(params).cuda() if params is not None else None)
+        got = C.dec(_host(q), n)
+    finally:
+        plan.close()
+    err = float(np.linalg.norm(got - exact))
+    bound = _fused_bound(C, P, G)
+    print("fused q%d %s: %d gates in %d passes, error %.3e (bound %.3e)" % (C.bits, case, G, P, err, bound))
+    assert err <= bound
+
+
+def test_fused_qft_closed_form_and_fewer_roundings(C):
+    """QFT n=16 fused: within the bound of its passes, and closer to the
+    closed form than the unfused run, which rounds every block after every
+    gate."""
+    n = 16
+    circ = W.qft(n)
+    psi0 = W.random_state(n, 66)
+    N = 1 << n
+    rev = np.array([int(format(i, "0%db" % n)[::-1], 2) for i in range(N)])
+    want = np.fft.ifft(psi0[rev]) * math.sqrt(N)
+    plan = sv.Circuit(n, circ, dtype=C.dtype, flags=sv.SV_FUSE)
+    try:
+        P = plan.info()["passes"]
+        q = _encode_gpu(psi0, n, C)
+        plan.run(q)
+        err_f = float(np.linalg.norm(C.dec(_host(q), n) - want))
+    finally:
+        plan.close()
+    u = _encode_gpu(psi0, n, C)
+    sv.sv_apply_circuit(u, circ, flags=0)
+    err_u = float(np.linalg.norm(C.dec(_host(u), n) - want))
+    G = len(circ.gates)
+    print("QFT n=%d q%d: fused %d passes error %.3e, unfused %d gates error %.3e" % (n, C.bits, P, err_f, G, err_u))
+    assert err_f <= _fused_bound(C, P, G)
+    assert err_f < err_u
+
+
+def test_fused_graph_replays_and_one_shot(C):
+    """A fused plan captured as a graph: replays equal the eager plan run
+    bitwise, and so does the one-shot call."""
+    n = 14
+    circ = _haar_circuit(n, 150, 67)
+    start = C.enc(W.random_state(n, 68), n)
+    src = torch.from_numpy(start).cuda()
+    eager = _dev(start, n, C)
+    p0 = sv.Circuit(n, circ, dtype=C.dtype, flags=sv.SV_FUSE)
+    try:
+        p0.run(eager)
+    finally:
+        p0.close()
+    one = _dev(start, n, C)
+    sv.sv_apply_circuit(one, circ, flags=sv.SV_FUSE)
+    torch.cuda.synchronize()
+    plan = sv.Circuit(n, circ, dtype=C.dtype, flags=sv.SV_FUSE | sv.SV_GRAPH)
+    try:
+        q = _dev(start, n, C)
+        for rep in range(3):
+            q.data.copy_(src)
+            torch.cuda.synchronize()
+            plan.run(q)
+            torch.cuda.synchronize()
+            assert torch.equal(q.data, eager.data), "replay %d" % rep
+    finally:
+        plan.close()
+    # the one-shot plan may fuse differently (it looks ahead less), so it is
+    # held to the bound rather than to the bits
+    exact = oracle.run_circuit(circ, None, C.dec(start, n))
+    assert np.linalg.norm(C.dec(_host(one), n) - exact) <= _fused_bound(C, len(circ.gates), len(circ.gates))
+
+
+def test_fused_untouched_tiles_keep_their_bytes(C):
+    """Gates all controlled by qubit 15 = 1 (value 1) on a state whose upper
+    half is never selected: the fused passes skip those tiles, so the lower
+    half's codes and scales stay byte-identical."""
+    n = 16
+    rng = np.random.default_rng(69)
+    gates = []
+    for i in range(80):
+        t = int(rng.integers(0, 15))
+        gates.append(W.Gate("U", t, (15,), (1,), matrix=W.haar_unitary_2x2(2000 + i)))
+    circ = W.Circuit(n, gates)
+    start = C.enc(W.random_state(n, 70), n)
+    q = _dev(start, n, C)
+    sv.sv_apply_circuit(q, circ, flags=sv.SV_FUSE)
+    got = _host(q)
+    gc, gs = C.views(got, n)
+    sc, ss = C.views(start, n)
+    half = 1 << (n - 1)
+    assert np.array_equal(gc[:half], sc[:half]) and np.array_equal(gs[:half >> 6], ss[:half >> 6])
+    assert not np.array_equal(gc[half:], sc[half:])
+    exact = oracle.run_circuit(circ, None, C.dec(start, n))
+    assert np.linalg.norm(C.dec(got, n) - exact) <= _fused_bound(C, len(gates), len(gates))

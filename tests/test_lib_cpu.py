@@ -179,8 +179,8 @@ def test_fixed_point_rejected_where_unsupported(sv):
     terms = (sv.sv_pauli_t * 1)()
     rc = L.sv_expect(ctypes.byref(s), terms, 1, ctypes.c_void_p(0x1000), None)
     assert rc == sv.SV_ENOTSUP
-    # circuits: fusion, dense blocks and remapping are not offered
-    for flags in (sv.SV_FUSE, sv.SV_DENSE | sv.SV_FUSE, sv.SV_REMAP):
+    # circuits: dense blocks and remapping are not offered (fusion is)
+    for flags in (sv.SV_DENSE | sv.SV_FUSE, sv.SV_REMAP):
         code, msg = _rc(lambda: sv.Circuit(10, [], dtype=sv.SV_CQ16, flags=flags))
         assert code == sv.SV_ENOTSUP and "SV_CQ16" in msg, msg
     # 16-byte alignment, and the usual gate checks

@@ -113,3 +113,45 @@ def test_stream29_shifts_by_one(gpu, dtype):
     sv.sv_init(st, 0)
     sv.sv_apply_circuit(st, W.stream(n), flags=sv.SV_FUSE)
     assert float(st[N - 1].abs()) == 1.0 and float(st.abs().pow(2).sum()) == 1.0
+
+
+@pytest.mark.parametrize("bits", [16, 32])
+def test_qft29_and_stream29_fixed_point_fused(gpu, bits):
+    """Fused passes over block-scaled fixed-point states at n = 29.  QFT29 on
+    a basis input against its closed form: every block is re-encoded once per
+    pass, each component within half a code step, at most 2^-B of the
+    block's largest component (B = 15 or 31), so each pass moves the unit
+    state by at most sqrt(128) 2^-B in 2-norm; add the arithmetic rounding of
+    each gate (float or double).  Stream29 on a basis input moves one
+    amplitude of exactly 1.0: the result is the basis state below it,
+    exactly."""
+    import torch
+    sv = gpu
+    n, N = N29, 1 << N29
+    dtype = sv.SV_CQ16 if bits == 16 else sv.SV_CQ32
+    arith = 1e-6 if bits == 16 else 1e-14  # per gate, 2-norm
+    st = sv.FixedState(n, dtype)
+    out = torch.empty(N, dtype=torch.complex128, device="cuda")
+    plan = sv.Circuit(n, W.qft(n), dtype=dtype, flags=sv.SV_FUSE)
+    try:
+        P = plan.info()["passes"]
+        x0 = 0x0A5A5A5
+        r = int(_rev_bits(torch.tensor([x0]), n)[0])
+        y = torch.arange(N, dtype=torch.int64, device="cuda")
+        ph = ((y * r) & (N - 1)).double() * (2 * math.pi / N)
+        del y
+        sv.sv_init(st, x0)
+        plan.run(st)
+        sv.sv_convert(out, st)
+        err = float((out - torch.polar(torch.full_like(ph, 1.0 / math.sqrt(N)), ph)).abs().pow(2).sum().sqrt())
+        del ph
+        tol = (P + 1) * math.sqrt(128) * 2.0 ** -(bits - 1) + len(W.qft(n).gates) * arith
+        _say("qft29 q%d fused: %d passes, error %.3e (2-norm; bound %.3e)" % (bits, P, err, tol))
+        assert err <= tol
+    finally:
+        plan.close()
+    sv.sv_init(st, 5)
+    sv.sv_apply_circuit(st, W.stream(n), flags=sv.SV_FUSE)
+    sv.sv_convert(out, st)
+    torch.cuda.synchronize()
+    assert float(out[4].real) == 1.0 and float(out.abs().pow(2).sum()) == 1.0
