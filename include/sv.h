@@ -212,6 +212,10 @@ int sv_hbm_probe(const sv_state_t *s, uint64_t fixed_mask, uint64_t fixed_vals, 
  *       of a fused run as one permutation of the tile
  *   "batch_split"     [1, 64]  most workgroups a batched circuit may be split
  *       over (read when a batch is planned; 1: one workgroup per circuit)
+ *   "phase_sweep_min_c128", "phase_sweep_min_c64" [1, 64]  a fused run's
+ *       diagonal block with at least this many gates reading tile-local bits
+ *       is one sweep adding phases; the gates of shorter blocks run as pair
+ *       gates (fixed-point states follow their tiles' arithmetic type)
  * None of them changes results beyond floating-point rounding (fusion
  * choices change the order in which commuting operations are rounded).
  * SV_EINVAL for an unknown key or a value out of range.  Not thread-safe

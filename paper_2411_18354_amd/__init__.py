@@ -290,7 +290,7 @@ _sig("sv_tune_get", [ctypes.c_char_p, ctypes.POINTER(_i64)])
 TUNE_KEYS = ("granule_bits_c128", "granule_bits_c64", "low_policy", "wave_auto", "tile_log2_c128",
              "tile_log2_c64", "tile_low_bits_c128", "tile_low_bits_c64", "fuse_min_gates", "dense_qubits",
              "dense_min_gates", "pair_unroll", "masked_unroll", "masked_block", "fuse_group", "fuse_pairs",
-             "plan_lookahead", "fuse_perm", "batch_split")
+             "plan_lookahead", "fuse_perm", "batch_split", "phase_sweep_min_c128", "phase_sweep_min_c64")
 
 
 def sv_tune_set(key: str, value: int) -> None:

@@ -168,6 +168,7 @@ struct Tuning {
     int plan_lookahead;   // fused runs: lookahead depth choosing a run's high qubits (0-2)
     int fuse_perm;        // fused runs: apply runs of X gates as one gather
     int batch_split;      // batches: most workgroups one circuit may be split over
+    int phase_sweep_min[2]; // [c128, c64] fused runs: a diagonal block with this many tile-local gates is one sweep
 };
 Tuning &tuning();
 

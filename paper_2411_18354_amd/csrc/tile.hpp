@@ -103,10 +103,11 @@ constexpr uint32_t kSweepHaveR = 1u << 16, kSweepRank1 = 1u << 17, kSweepAnyRest
                    kSweepInfoValid = 1u << 31;
 
 // Mark the blocks of consecutive diagonal gates among tiles[0 .. count) (one
-// fused run; host): length, phase-sum eligibility and table summary at each
-// block's first gate.  param_gate[i] != 0: the entries of gate i come from parameters at
-// run time (their kinds are unitary), so it counts as unit modulus.
-void mark_diag_sweeps(TileGate *tiles, int count, const char *param_gate);
+// fused run; host): length, phase-sum eligibility (unit modulus and at least
+// phase_min gates reading tile-local bits) and table summary at each block's
+// first gate.  param_gate[i] != 0: the entries of gate i come from parameters
+// at run time (their kinds are unitary), so it counts as unit modulus.
+void mark_diag_sweeps(TileGate *tiles, int count, const char *param_gate, int phase_min);
 
 // Phase patterns of the table sweeps among tiles[0 .. count) (one fused run
 // over tiles of width m >= 7, after mark_diag_sweeps; host).  Every phase
@@ -395,10 +396,7 @@ __device__ __forceinline__ void tile_load_dma(cplx_t<R> *tile, const cplx_t<R> *
     }
 }
 
-// Diagonal sweeps with at least this many gates reading tile-local bits add
-// phases instead of multiplying factors (measured break-even on MI355X is a
-// handful of gates).
-constexpr int kPhaseSweepMin = 8;
+
 
 // A wave-uniform double held in scalar registers.
 __device__ __forceinline__ double uniform_f64(double v) {

@@ -57,7 +57,7 @@ TileMap make_tile_map(int n, int m, int a, const std::vector<int> &high, uint64_
 
 TileMap contiguous_tile_map(int n, int m) { return make_tile_map(n, m, m, {}); }
 
-void mark_diag_sweeps(TileGate *t, int count, const char *param_gate) {
+void mark_diag_sweeps(TileGate *t, int count, const char *param_gate, int phase_min) {
     int k = 0;
     while (k < count) {
         if (!t[k].diag) {
@@ -73,7 +73,7 @@ void mark_diag_sweeps(TileGate *t, int count, const char *param_gate) {
             ++e;
         }
         t[k].sweep_len = (uint16_t)(e - k);
-        t[k].sweep_phase = (unit && nlocal >= kPhaseSweepMin) ? 1 : 0;
+        t[k].sweep_phase = (unit && nlocal >= phase_min) ? 1 : 0;
         k = e;
     }
 }

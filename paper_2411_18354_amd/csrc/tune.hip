@@ -32,7 +32,7 @@ Tuning &tuning() {
     //    256-lane workgroups and one pair per lane (10.8 ms against 12.5 ms
     //    with four per lane, 16.1 ms with 64-lane workgroups, whose many
     //    workgroups cost more when most lanes only test and exit).
-    static Tuning t = {{3, 4}, 1, 1, {12, 13}, {3, 5}, 2, 4, 16, 1, 1, 256, 1, 1, 2, 1, 16};
+    static Tuning t = {{3, 4}, 1, 1, {12, 13}, {3, 5}, 2, 4, 16, 1, 1, 256, 1, 1, 2, 1, 16, {4, 8}};
     return t;
 }
 
@@ -64,6 +64,8 @@ static int find_key(const char *name, Key *out) {
         {"plan_lookahead", &t.plan_lookahead, 0, 2},
         {"fuse_perm", &t.fuse_perm, 0, 1},
         {"batch_split", &t.batch_split, 1, 64},
+        {"phase_sweep_min_c128", &t.phase_sweep_min[0], 1, 64},
+        {"phase_sweep_min_c64", &t.phase_sweep_min[1], 1, 64},
     };
     for (const Key &k : keys)
         if (name && strcmp(k.name, name) == 0) {
