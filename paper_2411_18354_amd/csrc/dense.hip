@@ -203,29 +203,38 @@ bool dense_supported(int dtype, int kq, int n) {
     return dtype == SV_C128 ? kq == 4 : (kq == 4 || kq == 5);
 }
 
-// Workgroups of the persistent dense launch: a few per CU, never more than
-// the 16-row groups need (4 per workgroup).
-static unsigned dense_grid(uint64_t nwg) {
+// Workgroups of the persistent dense launch: as many as are resident at
+// once (the kernel's occupancy times the CUs), never more than the 16-row
+// groups need (4 per workgroup).  Every workgroup strides over the same
+// share, so workgroups beyond the resident ones would run as a second round
+// and stretch the launch (k = 4 complex128 holds 5 workgroups per CU: 8 per
+// CU took 1.84 ms at n = 28).
+static unsigned dense_grid(const void *kernel, uint64_t nwg) {
     DeviceInfo di;
-    const uint64_t cap = device_info(&di) == SV_OK ? (uint64_t)di.num_cus * 8 : 2048;
+    const uint64_t cus = device_info(&di) == SV_OK ? (uint64_t)di.num_cus : 256;
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kDenseThreads, 0) != hipSuccess ||
+        per_cu < 1) {
+        (void)hipGetLastError();
+        per_cu = 4;
+    }
     const uint64_t need = (nwg + kDenseThreads / 64 - 1) / (kDenseThreads / 64);
-    return (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(need, cap));
+    return (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(need, cus * (uint64_t)per_cu));
 }
 
 int launch_dense(int dtype, void *psi, int n, int kq, const void *rmat, hipStream_t st) {
     if (!dense_supported(dtype, kq, n))
         return fail(SV_ENOTSUP, "dense block of %d qubits unsupported for dtype %d, n=%d", kq, dtype, n);
     const uint64_t ngroups = 1ull << (n - kq - 4);  // groups of 16 rows of 2^kq amplitudes
-    const unsigned grid = dense_grid(ngroups);
     if (dtype == SV_C128)
-        hipLaunchKernelGGL((k_dense<double, 4>), dim3(grid), dim3(kDenseThreads), 0, st, (double *)psi, ngroups,
-                           (const double *)rmat);
+        hipLaunchKernelGGL((k_dense<double, 4>), dim3(dense_grid((const void *)k_dense<double, 4>, ngroups)),
+                           dim3(kDenseThreads), 0, st, (double *)psi, ngroups, (const double *)rmat);
     else if (kq == 4)
-        hipLaunchKernelGGL((k_dense<float, 4>), dim3(grid), dim3(kDenseThreads), 0, st, (float *)psi, ngroups,
-                           (const float *)rmat);
+        hipLaunchKernelGGL((k_dense<float, 4>), dim3(dense_grid((const void *)k_dense<float, 4>, ngroups)),
+                           dim3(kDenseThreads), 0, st, (float *)psi, ngroups, (const float *)rmat);
     else
-        hipLaunchKernelGGL((k_dense<float, 5>), dim3(grid), dim3(kDenseThreads), 0, st, (float *)psi, ngroups,
-                           (const float *)rmat);
+        hipLaunchKernelGGL((k_dense<float, 5>), dim3(dense_grid((const void *)k_dense<float, 5>, ngroups)),
+                           dim3(kDenseThreads), 0, st, (float *)psi, ngroups, (const float *)rmat);
     SV_LAUNCH_CHECK();
     return SV_OK;
 }
