@@ -13,10 +13,11 @@
 
 namespace sv {
 
-// One wavefront per workgroup for the scheduled pair and wavefront kernels:
-// measured on MI355X, 64-lane workgroups with one pair (or amplitude) per
-// lane stream an in-place 4 GiB gate at 6.4-6.8 TB/s, against 5.7-5.8 TB/s
-// for 256-lane workgroups with four per lane.  The masked baseline's
+// One wavefront per workgroup for the wavefront kernel and 64 pairs per
+// workgroup for the pair kernel (one wavefront holding one pair per lane, or
+// two wavefronts holding one element each, k_pair_xw): measured on MI355X,
+// these stream an in-place 4 GiB gate at 6.4-6.8 TB/s, against 5.7-5.8 TB/s
+// for 256-lane workgroups with four pairs per lane.  The masked baseline's
 // workgroup size is a knob ("masked_block": 64 or 256).
 constexpr int kThreads = 64;
 
@@ -67,6 +68,50 @@ __global__ __launch_bounds__(T) void k_pair(cplx_t<R> *__restrict__ psi, uint64_
             st_stream<R>(psi + p1[j], x[j]);
             st_stream<R>(psi + (p1[j] | st), y[j]);
         }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Pair kernel, one amplitude per lane (the form scheduled complex128
+// launches take).  A 128-lane workgroup holds 64 pairs: wavefront 0 loads
+// their first elements p1 = expand(i), wavefront 1 their second elements
+// p1 | 2^t, each lane one 16-byte load; the partners meet in LDS and
+// each lane stores its own row of the 2x2 update.  So every wavefront
+// streams one contiguous run, as the wavefront kernel does, instead of two
+// runs 2^t apart.  Measured on the n=28 complex128 sweep (sum of the 27
+// gates' times): 8.58 -> 8.34 ms; the uncontrolled gates at t=13 and 27 take
+// about 1290 us instead of 1350 (the HBM probe streams the same state in
+// 1280).  Scheduling, the tested controls and the two policies are those of
+// k_pair.
+template <typename R, typename I, int POLICY, typename MS>
+__global__ __launch_bounds__(2 * kThreads) void k_pair_xw(cplx_t<R> *__restrict__ psi, uint64_t niter, Expand e,
+                                                          uint64_t tmask, uint64_t tvals, uint32_t t, MS ms,
+                                                          uint64_t block0) {
+    __shared__ cplx_t<R> xs[2 * kThreads];
+    const Mat2<R> m = ms.get();
+    const bool second = threadIdx.x >= kThreads;  // wavefront 1: the pairs' second elements
+    const uint64_t i = (block0 + blockIdx.x) * kThreads + (threadIdx.x & (kThreads - 1));
+    const I p1 = expand_index<I>(e, (I)i);
+    const bool in = i < niter;
+    const bool pass = in && (((uint64_t)p1 & tmask) == tvals);
+    const bool touch = POLICY == kRewrite ? in : pass;  // the same for both elements of a pair
+    const I k = second ? (p1 | ((I)1 << t)) : p1;
+    cplx_t<R> v;
+    v.x = (R)0;
+    v.y = (R)0;
+    if (touch)
+        v = ld_stream<R>(psi + k);
+    xs[threadIdx.x] = v;
+    __syncthreads();
+    if (touch) {
+        cplx_t<R> out = v;
+        if (pass) {
+            const cplx_t<R> u = xs[threadIdx.x ^ kThreads];
+            cplx_t<R> x = second ? u : v, y = second ? v : u;
+            apply_pair<R>(m, x, y);
+            out = second ? y : x;
+        }
+        st_stream<R>(psi + k, out);
     }
 }
 
@@ -213,14 +258,26 @@ int make_gate_plan(const GateSpec &g, int dtype, int mode, GatePlan *p) {
     return SV_OK;
 }
 
+// Scheduled complex128 pair launches with one pair per lane run the
+// cross-wavefront form.  complex64 keeps both elements in one lane: with one
+// 8-byte element per lane a wavefront has half the bytes in flight, and the
+// n=28 complex64 sweep ran 4491 gates/s that way against 5020.
+static bool pair_xw(const GatePlan &p, bool dbl) {
+    return dbl && p.kind == GateKernel::Pair && p.unroll == 1 && p.block == kThreads;
+}
+
 std::string gate_plan_name(const GatePlan &p, int dtype, const char *matsrc) {
     const char *R = dtype == SV_C128 ? "double" : "float";
     char buf[256];
     switch (p.kind) {
     case GateKernel::Masked:
     case GateKernel::Pair:
-        snprintf(buf, sizeof(buf), "sv::k_pair<%s, %s, %d, %d, %d, sv::%s<%s> >", R,
-                 p.index64 ? "unsigned long" : "unsigned int", p.unroll, p.policy, p.block, matsrc, R);
+        if (pair_xw(p, dtype == SV_C128))
+            snprintf(buf, sizeof(buf), "sv::k_pair_xw<%s, %s, %d, sv::%s<%s> >", R,
+                     p.index64 ? "unsigned long" : "unsigned int", p.policy, matsrc, R);
+        else
+            snprintf(buf, sizeof(buf), "sv::k_pair<%s, %s, %d, %d, %d, sv::%s<%s> >", R,
+                     p.index64 ? "unsigned long" : "unsigned int", p.unroll, p.policy, p.block, matsrc, R);
         break;
     case GateKernel::Wave:
         snprintf(buf, sizeof(buf), "sv::k_wave<%s, %d, %d, sv::%s<%s> >", R, p.unroll, p.policy, matsrc, R);
@@ -235,9 +292,16 @@ std::string gate_plan_name(const GatePlan &p, int dtype, const char *matsrc) {
 template <typename R, typename I, int K, int T, typename MS>
 static void go_pair(cplx_t<R> *psi, const GatePlan &p, const MS &ms, hipStream_t st) {
     const uint64_t blocks = (p.niter + T * K - 1) / (T * K);
+    const bool xw = K == 1 && T == kThreads && pair_xw(p, sizeof(R) == 8);  // 64 pairs per 128-lane workgroup
     for (uint64_t b0 = 0; b0 < blocks; b0 += kMaxGridBlocks) {
         const dim3 grid((unsigned)std::min(kMaxGridBlocks, blocks - b0));
-        if (p.policy == kRewrite)
+        if (xw && p.policy == kRewrite)
+            hipLaunchKernelGGL((k_pair_xw<R, I, kRewrite, MS>), grid, dim3(2 * kThreads), 0, st, psi, p.niter, p.e,
+                               p.tmask, p.tvals, (uint32_t)p.target, ms, b0);
+        else if (xw)
+            hipLaunchKernelGGL((k_pair_xw<R, I, kSkip, MS>), grid, dim3(2 * kThreads), 0, st, psi, p.niter, p.e,
+                               p.tmask, p.tvals, (uint32_t)p.target, ms, b0);
+        else if (p.policy == kRewrite)
             hipLaunchKernelGGL((k_pair<R, I, K, kRewrite, T, MS>), grid, dim3(T), 0, st, psi, p.niter, p.e, p.tmask,
                                p.tvals, (uint32_t)p.target, ms, b0);
         else
