@@ -268,14 +268,15 @@ def test_adjoint_plan_argument_errors(sv):
     ("c128", "auto", 27, (3, 20), "sv::k_pair_xw<double, unsigned int, 1, sv::MatVal<double> >", 1 << 25),
     ("c64", "auto", 13, (), "sv::k_pair<float, unsigned int, 1, 1, 64, sv::MatVal<float> >", 1 << 27),
     ("c128", "masked", 13, (5,), "sv::k_pair<double, unsigned int, 1, 0, 256, sv::MatVal<double> >", 1 << 27),
+    ("c64", "masked", 13, (5,), "sv::k_pair<float, unsigned int, 1, 0, 256, sv::MatVal<float> >", 1 << 27),
     ("c128", "auto", 0, (), "sv::k_wave<double, 1, 1, sv::MatVal<double> >", 1 << 22),
 ])
 def test_single_gate_kernel_choice(sv, dtype, mode, t, ctrls, want, units):
     """The kernel a single gate launches at n=28 (its name as the profiler
     reports it) and its work items: complex128 scheduled pairs run the
-    cross-wavefront form, complex64 keeps one pair per lane, the masked
-    baseline runs over all 2^(n-1) pairs, low targets take the wavefront
-    kernel."""
+    cross-wavefront form (64 pairs per workgroup), complex64 keeps one pair
+    per lane, the masked baseline runs over all 2^(n-1) pairs with one pair
+    per lane, low targets take the wavefront kernel."""
     cm = sum(1 << q for q in ctrls)
     code = sv.SV_C128 if dtype == "c128" else sv.SV_C64
     k, it = sv.sv_gate_plan(28, code, t, cm, cm, mode)
