@@ -467,3 +467,29 @@ def test_fused_untouched_tiles_keep_their_bytes(C):
     assert not np.array_equal(gc[half:], sc[half:])
     exact = oracle.run_circuit(circ, None, C.dec(start, n))
     assert np.linalg.norm(C.dec(got, n) - exact) <= _fused_bound(C, len(gates), len(gates))
+
+
+@pytest.mark.parametrize("n", [5, 6, 7, 9])
+def test_fused_small_states(C, n):
+    """Fusion at the smallest widths: n = 6 is one block and one tile, n = 7
+    and 9 hold two and eight blocks in one tile; below 6 qubits there is no
+    whole block to tile, so the plan runs every gate unfused (bit-exact with
+    the oracle's per-gate arithmetic)."""
+    circ = W.random_gates_n12(seed=80 + n, n=n, ngates=40)
+    psi = W.random_state(n, 81 + n)
+    start = C.enc(psi, n)
+    q = _dev(start, n, C)
+    plan = sv.Circuit(n, circ, dtype=C.dtype, flags=sv.SV_FUSE)
+    try:
+        P = plan.info()["passes"]
+        plan.run(q)
+        got = _host(q)
+    finally:
+        plan.close()
+    if n < 6:
+        assert P == len(circ.gates)
+        _assert_same(got, C.run(circ, buf0=start), n, C, "n=%d unfused" % n)
+    else:
+        assert P < len(circ.gates)
+        exact = oracle.run_circuit(circ, None, C.dec(start, n))
+        assert np.linalg.norm(C.dec(got, n) - exact) <= _fused_bound(C, P, len(circ.gates))
