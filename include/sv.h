@@ -375,7 +375,11 @@ typedef struct sv_pauli {
 } sv_pauli_t;
 
 /* out_dev[0] = <psi|H|psi> (real), written when the stream reaches it.
- * nterms >= 1; masks must lie within the n qubits. */
+ * nterms >= 1; masks must lie within the n qubits.  Any dtype: a
+ * fixed-point state (SV_CQ16, SV_CQ32) is read through its codes, each
+ * amplitude code * 2^scale taken exactly to double, so the result is that
+ * of the decoded state (no decoded copy is made).  sv_expect_noalloc and
+ * sv_expect_terms take every dtype the same way. */
 int sv_expect(const sv_state_t *s, const sv_pauli_t *terms, int nterms, double *out_dev, sv_stream_t st);
 
 /* Allocation-free variant of sv_expect, for callers that cannot allocate
@@ -396,7 +400,8 @@ int sv_expect_noalloc(const sv_state_t *s, const sv_pauli_t *terms, int nterms, 
 /* out_dev[j] = <psi|P_j|psi> for every term j (coefficients not applied). */
 int sv_expect_terms(const sv_state_t *s, const sv_pauli_t *terms, int nterms, double *out_dev, sv_stream_t st);
 
-/* out = H in (out and in distinct, same n and dtype). */
+/* out = H in (out and in distinct, same n and dtype; SV_C128 or SV_C64,
+ * SV_ENOTSUP for fixed-point states). */
 int sv_apply_pauli_sum(const sv_state_t *in, const sv_state_t *out, const sv_pauli_t *terms, int nterms,
                        sv_stream_t st);
 

@@ -8,7 +8,10 @@
 // x-mask group, enumerated with the same index expansion as the gate
 // kernels.  Diagonal terms (X = 0) sum |psi_k|^2 (-1)^{z.k}.  Terms of a
 // group are evaluated together in one pass.  Reductions are deterministic
-// (reduce.hpp).
+// (reduce.hpp).  Fixed-point states (SV_CQ16, SV_CQ32) are read through
+// their codes: each amplitude is code * 2^scale of its 64-amplitude block,
+// which double holds exactly, so an expectation of a fixed-point state is
+// that of the decoded state with the same double arithmetic.
 #include <algorithm>
 #include <cstddef>
 #include <cstring>
@@ -19,7 +22,8 @@
 
 namespace sv {
 
-constexpr int kMaxT = 16;  // terms evaluated per pass
+constexpr int kMaxT = 16;        // terms evaluated per pass
+constexpr int kExpectLoads = 4;  // visits per lane loaded together
 
 int make_pauli_plan(int n, const sv_pauli_t *terms, int nterms, PauliPlan *p) {
     if (nterms < 1 || !terms)
@@ -87,13 +91,47 @@ void pauli_release(PauliDevice *d, hipStream_t st) {
     *d = PauliDevice();
 }
 
+// Amplitude sources for the expectation passes: amplitude k as two doubles.
+template <typename R> struct CplxAmps {
+    const cplx_t<R> *__restrict__ psi;
+    __device__ void get(uint64_t k, double &re, double &im) const {
+        const cplx_t<R> v = psi[k];
+        re = (double)v.x;
+        im = (double)v.y;
+    }
+};
+
+// SV_CQ16: one 32-bit word per amplitude, re in the low half.
+struct Q16Amps {
+    const uint32_t *__restrict__ codes;
+    const int8_t *__restrict__ scales;
+    __device__ void get(uint64_t k, double &re, double &im) const {
+        const uint32_t w = codes[k];
+        const int s = scales[k >> 6];
+        re = ldexp((double)(int16_t)(w & 0xffffu), s);
+        im = ldexp((double)(int16_t)(w >> 16), s);
+    }
+};
+
+// SV_CQ32: two 32-bit words per amplitude (re, im).
+struct Q32Amps {
+    const uint2 *__restrict__ codes;
+    const int8_t *__restrict__ scales;
+    __device__ void get(uint64_t k, double &re, double &im) const {
+        const uint2 w = codes[k];
+        const int s = scales[k >> 6];
+        re = ldexp((double)(int32_t)w.x, s);
+        im = ldexp((double)(int32_t)w.y, s);
+    }
+};
+
 // One pass for one group (<= kMaxT terms sharing the x mask X).
 // partials[(first + j) * kMaxPartials + block] receives the workgroup's sum
 // of <P_j> contributions.
-template <typename R>
-__global__ __launch_bounds__(kRedThreads) void k_expect_group(const cplx_t<R> *__restrict__ psi, uint64_t count,
-                                                              uint64_t X, uint32_t b, const DTerm *__restrict__ terms,
-                                                              int first, int nt, double *__restrict__ partials) {
+template <typename A>
+__global__ __launch_bounds__(kRedThreads) void k_expect_group(const A amps, uint64_t count, uint64_t X, uint32_t b,
+                                                              const DTerm *__restrict__ terms, int first, int nt,
+                                                              double *__restrict__ partials) {
     __shared__ double red[kRedThreads / 64];
     uint64_t z[kMaxT];
     int ny[kMaxT];
@@ -104,29 +142,57 @@ __global__ __launch_bounds__(kRedThreads) void k_expect_group(const cplx_t<R> *_
         z[j] = j < nt ? terms[first + j].z : 0;
         ny[j] = j < nt ? terms[first + j].ny : 0;
     }
+    // Each lane visits i0, i0 + stride, i0 + 2 stride, ...; kExpectLoads of
+    // those visits load before any of them is summed, so enough bytes are in
+    // flight for the narrow formats too.  The lane's summation order is that
+    // of the visits.
     const uint64_t stride = (uint64_t)gridDim.x * kRedThreads;
     const uint64_t lowb = (1ull << b) - 1;
-    for (uint64_t i = (uint64_t)blockIdx.x * kRedThreads + threadIdx.x; i < count; i += stride) {
-        if (X == 0) {
-            const cplx_t<R> v = psi[i];
-            const double pr = (double)v.x * (double)v.x + (double)v.y * (double)v.y;
+    const uint64_t i0 = (uint64_t)blockIdx.x * kRedThreads + threadIdx.x;
+    if (X == 0) {
+        for (uint64_t i = i0; i < count; i += kExpectLoads * stride) {
+            double vr[kExpectLoads], vi[kExpectLoads];
 #pragma unroll
-            for (int j = 0; j < kMaxT; ++j)
-                if (j < nt)
-                    acc[j] += odd_parity(z[j] & i) ? -pr : pr;
-        } else {
-            const uint64_t k = ((i >> b) << (b + 1)) | (i & lowb);  // bit b cleared
-            const uint64_t k2 = k ^ X;
-            const cplx_t<R> u = psi[k], v = psi[k2];
-            // w = conj(u) * v
-            const double wr = (double)u.x * (double)v.x + (double)u.y * (double)v.y;
-            const double wi = (double)u.x * (double)v.y - (double)u.y * (double)v.x;
+            for (int u = 0; u < kExpectLoads; ++u)  // visits past the end load the last amplitude, unused
+                amps.get(min(i + u * stride, count - 1), vr[u], vi[u]);
 #pragma unroll
-            for (int j = 0; j < kMaxT; ++j)
-                if (j < nt) {
-                    const double r = re_ipow(ny[j], wr, wi);
-                    acc[j] += odd_parity(z[j] & k2) ? -r : r;
+            for (int u = 0; u < kExpectLoads; ++u) {
+                const uint64_t iu = i + u * stride;
+                if (iu < count) {
+                    const double pr = vr[u] * vr[u] + vi[u] * vi[u];
+#pragma unroll
+                    for (int j = 0; j < kMaxT; ++j)
+                        if (j < nt)
+                            acc[j] += odd_parity(z[j] & iu) ? -pr : pr;
                 }
+            }
+        }
+    } else {
+        for (uint64_t i = i0; i < count; i += kExpectLoads * stride) {
+            double ur[kExpectLoads], ui[kExpectLoads], vr[kExpectLoads], vi[kExpectLoads];
+#pragma unroll
+            for (int u = 0; u < kExpectLoads; ++u) {  // visits past the end load the last pair, unused
+                const uint64_t iu = min(i + u * stride, count - 1);
+                const uint64_t k = ((iu >> b) << (b + 1)) | (iu & lowb);  // bit b cleared
+                amps.get(k, ur[u], ui[u]);
+                amps.get(k ^ X, vr[u], vi[u]);
+            }
+#pragma unroll
+            for (int u = 0; u < kExpectLoads; ++u) {
+                const uint64_t iu = i + u * stride;
+                if (iu < count) {
+                    const uint64_t k2 = (((iu >> b) << (b + 1)) | (iu & lowb)) ^ X;
+                    // w = conj(u) * v
+                    const double wr = ur[u] * vr[u] + ui[u] * vi[u];
+                    const double wi = ur[u] * vi[u] - ui[u] * vr[u];
+#pragma unroll
+                    for (int j = 0; j < kMaxT; ++j)
+                        if (j < nt) {
+                            const double r = re_ipow(ny[j], wr, wi);
+                            acc[j] += odd_parity(z[j] & k2) ? -r : r;
+                        }
+                }
+            }
         }
     }
     const double scale = X == 0 ? 1.0 : 2.0;
@@ -140,23 +206,32 @@ __global__ __launch_bounds__(kRedThreads) void k_expect_group(const cplx_t<R> *_
     }
 }
 
-// Sum every term's partials in a fixed order; write per-term values (in the
-// caller's order) and the coefficient-weighted total.
-__global__ __launch_bounds__(kRedThreads) void k_expect_final(const DTerm *__restrict__ terms, int nterms,
-                                                              const int32_t *__restrict__ nblk,
-                                                              const double *__restrict__ partials,
-                                                              double *__restrict__ out_total,
-                                                              double *__restrict__ out_terms) {
+// Every term's sum of its partials, one workgroup per term (plan order,
+// each in the fixed order of block_sum_array).
+__global__ __launch_bounds__(kRedThreads) void k_expect_sums(const int32_t *__restrict__ nblk,
+                                                             const double *__restrict__ partials,
+                                                             double *__restrict__ sums) {
     __shared__ double red[kRedThreads / 64];
-    double total = 0.0;
-    for (int j = 0; j < nterms; ++j) {
-        const double s = block_sum_array(partials + (size_t)j * kMaxPartials, nblk[j], red);
-        total += terms[j].coef * s;
-        if (threadIdx.x == 0 && out_terms)
-            out_terms[terms[j].idx] = s;
-    }
-    if (threadIdx.x == 0 && out_total)
+    const int j = blockIdx.x;
+    const double s = block_sum_array(partials + (size_t)j * kMaxPartials, nblk[j], red);
+    if (threadIdx.x == 0)
+        sums[j] = s;
+}
+
+// Per-term values in the caller's order, and the coefficient-weighted total
+// summed in plan order by one lane.
+__global__ __launch_bounds__(64) void k_expect_final(const DTerm *__restrict__ terms, int nterms,
+                                                     const double *__restrict__ sums, double *__restrict__ out_total,
+                                                     double *__restrict__ out_terms) {
+    if (out_terms)
+        for (int j = threadIdx.x; j < nterms; j += blockDim.x)
+            out_terms[terms[j].idx] = sums[j];
+    if (threadIdx.x == 0 && out_total) {
+        double total = 0.0;
+        for (int j = 0; j < nterms; ++j)
+            total += terms[j].coef * sums[j];
         out_total[0] = total;
+    }
 }
 
 // out_k = sum_groups sum_terms coef i^ny (-1)^{z.(k^X)} psi_{k^X}; partials
@@ -226,28 +301,47 @@ static void expect_partial_counts(int n, const PauliPlan &plan, std::vector<int3
     }
 }
 
-// The group passes and the final sum.  terms (the plan's terms), nblk (their
-// partial counts) and partials (terms * kMaxPartials doubles) are device
-// arrays, already filled or enqueued on st.
+// The group passes and the final sums.  terms (the plan's terms), nblk (their
+// partial counts), partials (terms * kMaxPartials doubles) and sums (terms
+// doubles) are device arrays, the first two already filled or enqueued on st.
 static int expect_launch(const sv_state_t *s, const PauliPlan &plan, const DTerm *terms, const int32_t *nblk,
-                         double *partials, double *out_total, double *out_terms, hipStream_t st) {
+                         double *partials, double *sums, double *out_total, double *out_terms, hipStream_t st) {
     const int n = s->n;
     for (const DGroup &g : plan.groups) {
         const uint64_t count = g.x == 0 ? (1ull << n) : (1ull << (n - 1));
         const unsigned grid = reduce_grid(count);
         const uint32_t b = g.x ? (uint32_t)__builtin_ctzll(g.x) : 0;
-        if (s->dtype == SV_C128)
-            hipLaunchKernelGGL(k_expect_group<double>, dim3(grid), dim3(kRedThreads), 0, st,
-                               (const double2 *)s->data, count, g.x, b, terms, g.first, g.count, partials);
-        else
-            hipLaunchKernelGGL(k_expect_group<float>, dim3(grid), dim3(kRedThreads), 0, st, (const float2 *)s->data,
-                               count, g.x, b, terms, g.first, g.count, partials);
+        const char *base = static_cast<const char *>(s->data);
+        const int8_t *scales = reinterpret_cast<const int8_t *>(base + (((size_t)1 << n) * amp_bytes(s->dtype)));
+        switch (s->dtype) {
+        case SV_C128:
+            hipLaunchKernelGGL(k_expect_group<CplxAmps<double>>, dim3(grid), dim3(kRedThreads), 0, st,
+                               CplxAmps<double>{(const double2 *)base}, count, g.x, b, terms, g.first, g.count,
+                               partials);
+            break;
+        case SV_C64:
+            hipLaunchKernelGGL(k_expect_group<CplxAmps<float>>, dim3(grid), dim3(kRedThreads), 0, st,
+                               CplxAmps<float>{(const float2 *)base}, count, g.x, b, terms, g.first, g.count,
+                               partials);
+            break;
+        case SV_CQ16:
+            hipLaunchKernelGGL(k_expect_group<Q16Amps>, dim3(grid), dim3(kRedThreads), 0, st,
+                               Q16Amps{(const uint32_t *)base, scales}, count, g.x, b, terms, g.first, g.count,
+                               partials);
+            break;
+        default:
+            hipLaunchKernelGGL(k_expect_group<Q32Amps>, dim3(grid), dim3(kRedThreads), 0, st,
+                               Q32Amps{(const uint2 *)base, scales}, count, g.x, b, terms, g.first, g.count,
+                               partials);
+            break;
+        }
         hipError_t e = hipGetLastError();
         if (e != hipSuccess)
             return fail(SV_EHIP, "expectation launch failed: %s", hipGetErrorString(e));
     }
-    hipLaunchKernelGGL(k_expect_final, dim3(1), dim3(kRedThreads), 0, st, terms, (int)plan.terms.size(), nblk,
-                       partials, out_total, out_terms);
+    const int nt = (int)plan.terms.size();
+    hipLaunchKernelGGL(k_expect_sums, dim3(nt), dim3(kRedThreads), 0, st, nblk, partials, sums);
+    hipLaunchKernelGGL(k_expect_final, dim3(1), dim3(64), 0, st, terms, nt, sums, out_total, out_terms);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess)
         return fail(SV_EHIP, "expectation launch failed: %s", hipGetErrorString(e));
@@ -256,13 +350,13 @@ static int expect_launch(const sv_state_t *s, const PauliPlan &plan, const DTerm
 
 static int expect_impl(const sv_state_t *s, const sv_pauli_t *terms, int nterms, double *out_total,
                        double *out_terms, hipStream_t st) {
-    SV_TRY(validate_state(s));
+    SV_TRY(validate_state(s, true));
     PauliPlan plan;
     SV_TRY(make_pauli_plan(s->n, terms, nterms, &plan));
     std::vector<int32_t> nblk;
     expect_partial_counts(s->n, plan, nblk);
     PauliDevice d;
-    SV_TRY(pauli_upload(plan, (size_t)plan.terms.size() * kMaxPartials, st, &d));
+    SV_TRY(pauli_upload(plan, (size_t)plan.terms.size() * (kMaxPartials + 1), st, &d));
     int32_t *d_nblk = nullptr;
     int r = SV_OK;
     hipError_t e = hipMallocAsync((void **)&d_nblk, nblk.size() * sizeof(int32_t), st);
@@ -276,7 +370,8 @@ static int expect_impl(const sv_state_t *s, const sv_pauli_t *terms, int nterms,
             r = fail(SV_EHIP, "copy failed: %s", hipGetErrorString(e));
     }
     if (r == SV_OK)
-        r = expect_launch(s, plan, d.terms, d_nblk, d.partials, out_total, out_terms, st);
+        r = expect_launch(s, plan, d.terms, d_nblk, d.partials, d.partials + plan.terms.size() * kMaxPartials,
+                          out_total, out_terms, st);
     if (d_nblk)
         (void)hipFreeAsync(d_nblk, st);
     pauli_release(&d, st);
@@ -299,6 +394,7 @@ struct ExpectScratch {
     DTerm terms[kNoAllocTerms];
     int32_t nblk[kNoAllocTerms];
     double partials[(size_t)kNoAllocTerms * kMaxPartials];
+    double sums[kNoAllocTerms];
 };
 
 struct ExpectTables {
@@ -341,7 +437,7 @@ static int scratch_address(ExpectScratch **out) {
 
 static int expect_noalloc_impl(const sv_state_t *s, const sv_pauli_t *terms, int nterms, double *out_total,
                                hipStream_t st) {
-    SV_TRY(validate_state(s));
+    SV_TRY(validate_state(s, true));
     if (nterms > kNoAllocTerms)
         return fail(SV_EINVAL, "nterms %d exceeds the allocation-free limit of %d terms", nterms, kNoAllocTerms);
     PauliPlan plan;
@@ -363,7 +459,8 @@ static int expect_noalloc_impl(const sv_state_t *s, const sv_pauli_t *terms, int
     char *base = reinterpret_cast<char *>(w);
     return expect_launch(s, plan, reinterpret_cast<const DTerm *>(base + offsetof(ExpectScratch, terms)),
                          reinterpret_cast<const int32_t *>(base + offsetof(ExpectScratch, nblk)),
-                         reinterpret_cast<double *>(base + offsetof(ExpectScratch, partials)), out_total, nullptr, st);
+                         reinterpret_cast<double *>(base + offsetof(ExpectScratch, partials)),
+                         reinterpret_cast<double *>(base + offsetof(ExpectScratch, sums)), out_total, nullptr, st);
 }
 
 } // namespace sv

@@ -493,3 +493,83 @@ def test_fused_small_states(C, n):
         assert P < len(circ.gates)
         exact = oracle.run_circuit(circ, None, C.dec(start, n))
         assert np.linalg.norm(C.dec(got, n) - exact) <= _fused_bound(C, P, len(circ.gates))
+
+
+def _pauli_sum(n, rng, nterms=24):
+    """Random Pauli sum on n qubits: diagonal terms, single X and Y on the
+    lowest and highest qubits, and random strings (X, Y, Z mixed), with
+    N(0, 1) coefficients."""
+    top = n - 1
+    terms = [W.PauliTerm(float(rng.normal()), 0, 1), W.PauliTerm(float(rng.normal()), 1, 0),
+             W.PauliTerm(float(rng.normal()), 1 << top, 1 << top), W.PauliTerm(float(rng.normal()), 1 << top, 0)]
+    while len(terms) < nterms:
+        x = int(rng.integers(0, 1 << n)) if len(terms) % 3 else 0
+        terms.append(W.PauliTerm(float(rng.normal()), x, int(rng.integers(0, 1 << n))))
+    return terms
+
+
+def _block_scaled_state(n, seed):
+    """A unit state whose 64-amplitude blocks differ in magnitude by up to
+    2^60 (one block all zero when there are several), so every block has its
+    own scale."""
+    rng = np.random.default_rng(seed)
+    psi = W.random_state(n, seed)
+    nb = max(1, (1 << n) >> 6)
+    f = 2.0 ** -rng.integers(0, 61, size=nb).astype(np.float64)
+    if nb > 2:
+        f[nb // 2] = 0.0
+    psi = psi * np.repeat(f, min(64, 1 << n))
+    return psi / np.linalg.norm(psi)
+
+
+@pytest.mark.parametrize("n", [1, 3, 6, 7, 12, 17])
+def test_expectation_of_fixed_state(C, n):
+    """<psi|H|psi> straight from the codes: equal (to the summation order's
+    rounding) to the oracle's expectation of the decoded state, which holds
+    the same doubles; the per-term values and the allocation-free entry point
+    agree; and the decoded state's expectation differs from that of the
+    unquantised state by at most sum|c_j| (2 d + d^2), d = ||psi_q - psi||
+    (P_j unitary, ||psi|| = 1)."""
+    rng = np.random.default_rng(700 + 2 * n + C.bits)
+    psi = _block_scaled_state(n, 710 + n)
+    buf = C.enc(psi, n)
+    dec = C.dec(buf, n)
+    q = _dev(buf, n, C)
+    terms = _pauli_sum(n, rng)
+    l1 = sum(abs(t.coef) for t in terms)
+    got = sv.sv_expect(q, terms).item()
+    per = sv.sv_expect_terms(q, terms).cpu().numpy()
+    out = torch.full((1,), np.nan, dtype=torch.float64, device="cuda")
+    sv.sv_expect_noalloc(q, terms, out)
+    want = oracle.expect(dec, n, terms)
+    want_per = np.array([oracle.expect_pauli(dec, n, t.x_mask, t.z_mask).real for t in terms])
+    assert abs(got - want) <= 1e-12 * l1, (got, want)
+    assert np.max(np.abs(per - want_per)) <= 1e-12
+    assert out.item() == got
+    d = float(np.linalg.norm(dec - psi))
+    exact = oracle.expect(psi, n, terms)
+    print("q%d n=%d <H> %.15f  decoded-exact %.2e  bound %.2e" % (C.bits, n, got, abs(want - exact),
+                                                                  l1 * (2 * d + d * d)), flush=True)
+    assert abs(want - exact) <= l1 * (2 * d + d * d)
+
+
+def test_expectation_of_fixed_state_n24(C):
+    """The expectation workload's register and Hamiltonian (n = 24, 23 ZZ +
+    24 X terms) on a fixed-point state, against the oracle on the decoded
+    values, and one term of every kind evaluated alone."""
+    n = 24
+    psi = W.random_state(n, 724)
+    buf = C.enc(psi, n)
+    del psi
+    dec = C.dec(buf, n)
+    q = _dev(buf, n, C)
+    terms = W.zz_x_hamiltonian(n, 5)
+    l1 = sum(abs(t.coef) for t in terms)
+    got = sv.sv_expect(q, terms).item()
+    want = oracle.expect(dec, n, terms)
+    assert abs(got - want) <= 1e-12 * l1, (got, want)
+    for t in (W.PauliTerm(1.0, 0, 1 << 23), W.PauliTerm(1.0, 1 << 5, 0), W.PauliTerm(1.0, 1 << 6, 1 << 6),
+              W.PauliTerm(1.0, (1 << 23) | 1, 1 << 12)):
+        g = sv.sv_expect(q, [t]).item()
+        w = oracle.expect_pauli(dec, n, t.x_mask, t.z_mask).real
+        assert abs(g - w) <= 1e-12, (t, g, w)

@@ -176,8 +176,10 @@ def test_fixed_point_rejected_where_unsupported(sv):
     assert code == sv.SV_ENOTSUP and "fixed-point" in msg
     code, msg = _rc(lambda: sv.sv_apply_dense_low(s, 4, __import__("numpy").eye(16)))
     assert code == sv.SV_ENOTSUP
+    # expectation values read fixed-point codes; H psi (a fixed-point output) does not
     terms = (sv.sv_pauli_t * 1)()
-    rc = L.sv_expect(ctypes.byref(s), terms, 1, ctypes.c_void_p(0x1000), None)
+    out = _state(sv, 10, sv.SV_CQ16, 0x900000)
+    rc = L.sv_apply_pauli_sum(ctypes.byref(s), ctypes.byref(out), terms, 1, None)
     assert rc == sv.SV_ENOTSUP
     # circuits: dense blocks and remapping are not offered (fusion is)
     for flags in (sv.SV_DENSE | sv.SV_FUSE, sv.SV_REMAP):
