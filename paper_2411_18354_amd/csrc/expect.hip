@@ -12,6 +12,16 @@
 // their codes: each amplitude is code * 2^scale of its 64-amplitude block,
 // which double holds exactly, so an expectation of a fixed-point state is
 // that of the decoded state with the same double arithmetic.
+//
+// Tile passes.  A tile is the 2^m amplitudes (m = min(n, 12)) whose indices
+// agree outside a qubit set T made of qubits 0..5 and m - 6 others.  A term
+// whose x mask lies inside T pairs amplitudes of one tile only, so one read
+// of the state into LDS serves every such term: the terms are split into
+// tile sets (the first is qubits 0..m-1; the others take the remaining x
+// masks' qubits above 5, first fit, then are filled up to m with the lowest
+// unused qubits), and one pass per set (<= 64 terms) evaluates them all.
+// Diagonal terms join the first set.  Groups whose x mask has more than
+// m - 6 qubits above 5 keep the one-pass-per-group kernel.
 #include <algorithm>
 #include <cstddef>
 #include <cstring>
@@ -206,6 +216,213 @@ __global__ __launch_bounds__(kRedThreads) void k_expect_group(const A amps, uint
     }
 }
 
+constexpr int kTileBits = 12;                                 // tile: 2^12 amplitudes, 64 KiB of double2
+constexpr int kTileLow = 6;                                   // qubits 0..5 are in every tile
+constexpr int kTileTerms = 64;                                // terms per tile pass: one lane each
+constexpr int kTileThreads = 256;
+constexpr int kTilePerLane = (1 << kTileBits) / kTileThreads;  // amplitudes per lane and tile
+
+// A term of a tile pass, its masks split at the tile's qubit set T.
+struct TTerm {
+    uint64_t zh;      // z outside T: the sign set by the tile's fixed bits
+    uint32_t xl, zl;  // x (inside T, nonzero unless diagonal) and z on T, as tile-local bits
+    int32_t ny;       // |x & z| mod 4: the power of i
+    int32_t slot;     // the term's position in the plan: its row of partials
+};
+
+// One tile pass.  Tile-local bit r < L (L = min(m, 6)) is qubit r; bit L + q
+// is the q-th lowest qubit of himask; the tile number's bit r is the r-th
+// lowest qubit of frmask.
+struct TilePass {
+    uint64_t himask, frmask;
+    int32_t m, nfree;
+    int32_t nt, nd, ne, pad;  // terms: nd diagonal, then ne with even ny, then odd ny
+    TTerm t[kTileTerms];
+};
+
+// The bits of v, lowest first, placed at the set bits of mask, lowest first.
+__device__ __forceinline__ uint64_t deposit_bits(uint64_t v, uint64_t mask) {
+    uint64_t out = 0;
+    while (mask) {
+        if (v & 1ull)
+            out |= mask & (~mask + 1ull);
+        v >>= 1;
+        mask &= mask - 1ull;
+    }
+    return out;
+}
+
+// Four terms of a tile pass at a time (independent chains for the
+// scheduler to interleave): slots past the end repeat the last term and are
+// dropped.  Diagonal terms: sum over this lane's amplitudes of
+// s(l) |t_l|^2.  Off-diagonal terms with Re(i^ny w) taken from Re w (IM
+// false, ny even) or Im w (IM true, ny odd): twice the sum over this lane's
+// pairs (l, l ^ xl) of s(l ^ xl) Re(i^ny conj(t_l) t_{l^xl}).  s(k) =
+// (-1)^{zl.k}.  Lane tid's r-th index is tid | (r << 8); inserting a cleared
+// bit b is linear over xor, so each sign splits into a lane part and a part
+// per r (uniform), and every update is one fused multiply-add by +-1.
+struct TileTerms {
+    uint32_t txl, tzl, tzh_lo, tzh_hi;
+    int tny;
+};
+
+__device__ __forceinline__ void tile_accumulate(const TileTerms &T, int j, int end, const double (&ts)[4],
+                                                uint64_t base, uint32_t lane, double &acc) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int jq = j + q;
+        if (jq < end) {
+            const uint64_t zh = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)T.tzh_hi, jq) << 32) |
+                                (uint32_t)__builtin_amdgcn_readlane((int)T.tzh_lo, jq);
+            if (lane == (uint32_t)jq)
+                acc += odd_parity(zh & base) ? -ts[q] : ts[q];
+        }
+    }
+}
+
+__device__ __forceinline__ void tile_diag(const TileTerms &T, int j0, int j1, const double (&pr)[kTilePerLane],
+                                          uint32_t tid, uint32_t M, uint64_t base, uint32_t lane, double &acc) {
+    for (int j = j0; j < j1; j += 4) {
+        uint32_t zl[4];
+        double ts[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            zl[q] = (uint32_t)__builtin_amdgcn_readlane((int)T.tzl, min(j + q, j1 - 1));
+            ts[q] = 0.0;
+        }
+#pragma unroll
+        for (int r = 0; r < kTilePerLane; ++r)
+            if ((tid | ((uint32_t)r << 8)) < M)
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    ts[q] = __builtin_fma((__popc(zl[q] & ((uint32_t)r << 8)) & 1) ? -1.0 : 1.0, pr[r], ts[q]);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            if (__popc(zl[q] & tid) & 1)
+                ts[q] = -ts[q];
+            ts[q] = wave_sum(ts[q]);
+        }
+        tile_accumulate(T, j, j1, ts, base, lane, acc);
+    }
+}
+
+template <bool IM>
+__device__ __forceinline__ void tile_offdiag(const TileTerms &T, int j0, int j1, const double2 *tile, uint32_t tid,
+                                             uint32_t M, uint64_t base, uint32_t lane, double &acc) {
+    for (int j = j0; j < j1; j += 4) {
+        uint32_t xl[4], zl[4], b[4], lt[4];
+        double ts[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int jq = min(j + q, j1 - 1);
+            xl[q] = (uint32_t)__builtin_amdgcn_readlane((int)T.txl, jq);
+            zl[q] = (uint32_t)__builtin_amdgcn_readlane((int)T.tzl, jq);
+            b[q] = (uint32_t)__builtin_ctz(xl[q]);
+            lt[q] = ((tid >> b[q]) << (b[q] + 1)) | (tid & ((1u << b[q]) - 1));
+            ts[q] = 0.0;
+        }
+#pragma unroll
+        for (uint32_t r = 0; r < (uint32_t)kTilePerLane / 2; ++r) {
+            if ((tid | (r << 8)) < M / 2) {
+                const uint32_t ir = r << 8;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const uint32_t lr = ((ir >> b[q]) << (b[q] + 1)) | (ir & ((1u << b[q]) - 1));
+                    const uint32_t l = lt[q] ^ lr;
+                    const double2 u = tile[l], v = tile[l ^ xl[q]];
+                    const double w = IM ? u.x * v.y - u.y * v.x : u.x * v.x + u.y * v.y;
+                    ts[q] = __builtin_fma((__popc(zl[q] & lr) & 1) ? -1.0 : 1.0, w, ts[q]);
+                }
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            // Re(i^ny w): ny = 0, 1, 2, 3 give Re w, -Im w, -Re w, Im w
+            const int ny = __builtin_amdgcn_readlane(T.tny, min(j + q, j1 - 1));
+            const bool neg = (ny == 1 || ny == 2) != (bool)(__popc(zl[q] & (lt[q] ^ xl[q])) & 1);
+            ts[q] = wave_sum(neg ? -2.0 * ts[q] : 2.0 * ts[q]);
+        }
+        tile_accumulate(T, j, j1, ts, base, lane, acc);
+    }
+}
+
+// Every tile of the pass into LDS once, then every term of the pass over it
+// (diagonal terms, then those with even and with odd ny).  Lane j of each
+// wavefront holds term j's masks (read by every lane with readlane, so the
+// term loops load nothing from memory) and accumulates term j over the
+// wavefront's tiles, in tile order; the four wavefronts' sums are added in
+// order at the end.  The next tile's loads are issued before the current
+// tile's terms are evaluated.
+template <typename A>
+__global__ __launch_bounds__(kTileThreads) void k_expect_tile(const A amps, const TilePass P,
+                                                              double *__restrict__ partials) {
+    __shared__ double2 tile[1 << kTileBits];
+    const uint32_t tid = threadIdx.x, lane = tid & 63;
+    const uint32_t M = 1u << P.m;
+    const int L = P.m < kTileLow ? P.m : kTileLow;
+    const uint32_t lowmask = (1u << L) - 1;
+    const uint64_t ntiles = 1ull << P.nfree, himask = P.himask, frmask = P.frmask;
+    const int nt = P.nt, nd = P.nd, ne = P.ne;
+    // this lane's amplitudes of a tile, l = tid | (r << 8): index bits on the
+    // tile's qubits (lanes past a small tile's end take its last amplitude,
+    // unused)
+    uint64_t off[kTilePerLane];
+#pragma unroll
+    for (int r = 0; r < kTilePerLane; ++r) {
+        const uint32_t l = min(tid | ((uint32_t)r << 8), M - 1);
+        off[r] = (l & lowmask) | deposit_bits(l >> L, himask);
+    }
+    TileTerms T{0, 0, 0, 0, 0};
+    if ((int)lane < nt) {
+        T.txl = P.t[lane].xl;
+        T.tzl = P.t[lane].zl;
+        T.tny = P.t[lane].ny;
+        T.tzh_lo = (uint32_t)P.t[lane].zh;
+        T.tzh_hi = (uint32_t)(P.t[lane].zh >> 32);
+    }
+    double acc = 0.0;
+    double vr[kTilePerLane], vi[kTilePerLane];
+    uint64_t tl = blockIdx.x;
+    if (tl < ntiles) {
+        const uint64_t base = deposit_bits(tl, frmask);
+#pragma unroll
+        for (int r = 0; r < kTilePerLane; ++r)
+            amps.get(base | off[r], vr[r], vi[r]);
+    }
+    for (; tl < ntiles; tl += gridDim.x) {
+        const uint64_t base = deposit_bits(tl, frmask);
+        __syncthreads();  // every read of the previous tile is done
+        double pr[kTilePerLane];
+#pragma unroll
+        for (int r = 0; r < kTilePerLane; ++r) {
+            const uint32_t l = tid | ((uint32_t)r << 8);
+            if (l < M)
+                tile[l] = make_double2(vr[r], vi[r]);
+            pr[r] = vr[r] * vr[r] + vi[r] * vi[r];
+        }
+        __syncthreads();
+        if (tl + gridDim.x < ntiles) {
+            const uint64_t nb = deposit_bits(tl + gridDim.x, frmask);
+#pragma unroll
+            for (int r = 0; r < kTilePerLane; ++r)
+                amps.get(nb | off[r], vr[r], vi[r]);
+        }
+        tile_diag(T, 0, nd, pr, tid, M, base, lane, acc);
+        tile_offdiag<false>(T, nd, nd + ne, tile, tid, M, base, lane, acc);
+        tile_offdiag<true>(T, nd + ne, nt, tile, tid, M, base, lane, acc);
+    }
+    __syncthreads();  // the tile's LDS now holds the wavefronts' sums
+    double *wsum = reinterpret_cast<double *>(tile);
+    wsum[tid] = acc;
+    __syncthreads();
+    if ((int)tid < nt) {
+        double s = 0.0;
+        for (int q = 0; q < kTileThreads / 64; ++q)
+            s += wsum[q * 64 + tid];
+        partials[(size_t)P.t[tid].slot * kMaxPartials + blockIdx.x] = s;
+    }
+}
+
 // Every term's sum of its partials, one workgroup per term (plan order,
 // each in the fixed order of block_sum_array).
 __global__ __launch_bounds__(kRedThreads) void k_expect_sums(const int32_t *__restrict__ nblk,
@@ -290,56 +507,158 @@ int launch_apply_paulis(int dtype, const void *psi, void *out, int n, const Paul
 }
 
 
-// Partial count of every term (the grid of its group's pass), in the plan's
-// term order.
-static void expect_partial_counts(int n, const PauliPlan &plan, std::vector<int32_t> &nblk) {
-    nblk.assign(plan.terms.size(), 0);
-    for (const DGroup &g : plan.groups) {
-        const uint64_t count = g.x == 0 ? (1ull << n) : (1ull << (n - 1));
-        for (int j = g.first; j < g.first + g.count; ++j)
-            nblk[j] = (int32_t)reduce_grid(count);
+// The passes of one expectation call: tile passes for the terms whose x
+// mask fits a tile set, one pass per group for the rest, and every plan
+// term's partial count (the grid of the pass that evaluates it).
+struct ExpectPlan {
+    PauliPlan pp;
+    std::vector<TilePass> tiles;
+    std::vector<DGroup> rest;
+    std::vector<int32_t> nblk;
+    unsigned tile_grid = 0;
+};
+
+// mask's bits on the tile's qubits (0..L-1 and himask) as tile-local bits,
+// and its other bits.
+static void tile_split(uint64_t mask, int L, uint64_t himask, uint32_t *local, uint64_t *outside) {
+    const uint64_t lowm = (1ull << L) - 1;
+    uint32_t l = (uint32_t)(mask & lowm);
+    int q = 0;
+    for (uint64_t h = himask; h; h &= h - 1, ++q)
+        if (mask & h & (~h + 1ull))
+            l |= 1u << (L + q);
+    *local = l;
+    *outside = mask & ~lowm & ~himask;
+}
+
+static int make_expect_plan(int n, const sv_pauli_t *terms, int nterms, ExpectPlan *e) {
+    SV_TRY(make_pauli_plan(n, terms, nterms, &e->pp));
+    const PauliPlan &pp = e->pp;
+    e->tiles.clear();
+    e->rest.clear();
+    e->nblk.assign(pp.terms.size(), 0);
+    const int m = std::min(n, kTileBits), L = std::min(m, kTileLow), nh = m - L;
+    const uint64_t lowm = (1ull << L) - 1;
+    DeviceInfo di;
+    const uint64_t cus = device_info(&di) == SV_OK ? (uint64_t)di.num_cus : 256;
+    e->tile_grid = (unsigned)std::min<uint64_t>({1ull << (n - m), 2 * cus, (uint64_t)kMaxPartials});
+    // tile sets (qubits above L), first fit; the first is qubits L..m-1
+    std::vector<uint64_t> sets{((1ull << m) - 1) & ~lowm};
+    std::vector<std::vector<int>> members(1);
+    for (int gi = 0; gi < (int)pp.groups.size(); ++gi) {
+        const DGroup &g = pp.groups[gi];
+        const uint64_t h = g.x & ~lowm;
+        int at = -1;
+        for (size_t k = 0; k < sets.size() && at < 0; ++k)
+            if (popcount64(sets[k] | h) <= nh)
+                at = (int)k;
+        if (at < 0 && popcount64(h) <= nh) {
+            sets.push_back(0);
+            members.emplace_back();
+            at = (int)sets.size() - 1;
+        }
+        if (at < 0) {  // too many qubits above L for one tile
+            e->rest.push_back(g);
+            for (int j = g.first; j < g.first + g.count; ++j)
+                e->nblk[j] = (int32_t)reduce_grid(g.x == 0 ? (1ull << n) : (1ull << (n - 1)));
+            continue;
+        }
+        sets[at] |= h;
+        members[at].push_back(gi);
+    }
+    for (size_t k = 0; k < sets.size(); ++k) {
+        if (members[k].empty())
+            continue;
+        uint64_t set = sets[k];
+        for (int q = L; q < n && popcount64(set) < nh; ++q)  // fill up with the lowest unused qubits
+            set |= 1ull << q;
+        TilePass P;
+        memset(&P, 0, sizeof(P));
+        P.m = m;
+        P.nfree = n - m;
+        P.himask = set;
+        P.frmask = ((n >= 64) ? ~0ull : ((1ull << n) - 1)) & ~lowm & ~set;
+        for (int gi : members[k]) {
+            const DGroup &g = pp.groups[gi];
+            for (int j = g.first; j < g.first + g.count; ++j) {
+                if (P.nt == kTileTerms) {
+                    e->tiles.push_back(P);
+                    P.nt = 0;
+                }
+                TTerm &T = P.t[P.nt++];
+                uint64_t xo = 0, zh = 0;
+                tile_split(g.x, L, P.himask, &T.xl, &xo);
+                tile_split(pp.terms[j].z, L, P.himask, &T.zl, &zh);
+                if (xo)
+                    return fail(SV_EINVAL, "internal: x mask 0x%llx outside its tile set", (unsigned long long)g.x);
+                T.zh = zh;
+                T.ny = pp.terms[j].ny;
+                T.slot = j;
+                e->nblk[j] = (int32_t)e->tile_grid;
+            }
+        }
+        if (P.nt)
+            e->tiles.push_back(P);
+    }
+    for (TilePass &P : e->tiles) {  // diagonal terms first, then even ny, then odd ny
+        auto kind = [](const TTerm &t) { return t.xl == 0 ? 0 : 1 + (t.ny & 1); };
+        std::stable_sort(P.t, P.t + P.nt, [&](const TTerm &a, const TTerm &b) { return kind(a) < kind(b); });
+        P.nd = (int32_t)std::count_if(P.t, P.t + P.nt, [&](const TTerm &t) { return kind(t) == 0; });
+        P.ne = (int32_t)std::count_if(P.t, P.t + P.nt, [&](const TTerm &t) { return kind(t) == 1; });
+    }
+    return SV_OK;
+}
+
+// f(amps) with the state's amplitude source.
+template <typename F> static void with_amps(const sv_state_t *s, F &&f) {
+    const char *base = static_cast<const char *>(s->data);
+    const int8_t *scales = reinterpret_cast<const int8_t *>(base + (((size_t)1 << s->n) * amp_bytes(s->dtype)));
+    switch (s->dtype) {
+    case SV_C128:
+        f(CplxAmps<double>{(const double2 *)base});
+        break;
+    case SV_C64:
+        f(CplxAmps<float>{(const float2 *)base});
+        break;
+    case SV_CQ16:
+        f(Q16Amps{(const uint32_t *)base, scales});
+        break;
+    default:
+        f(Q32Amps{(const uint2 *)base, scales});
+        break;
     }
 }
 
-// The group passes and the final sums.  terms (the plan's terms), nblk (their
+// The passes and the final sums.  terms (the plan's terms), nblk (their
 // partial counts), partials (terms * kMaxPartials doubles) and sums (terms
 // doubles) are device arrays, the first two already filled or enqueued on st.
-static int expect_launch(const sv_state_t *s, const PauliPlan &plan, const DTerm *terms, const int32_t *nblk,
+static int expect_launch(const sv_state_t *s, const ExpectPlan &plan, const DTerm *terms, const int32_t *nblk,
                          double *partials, double *sums, double *out_total, double *out_terms, hipStream_t st) {
     const int n = s->n;
-    for (const DGroup &g : plan.groups) {
-        const uint64_t count = g.x == 0 ? (1ull << n) : (1ull << (n - 1));
-        const unsigned grid = reduce_grid(count);
-        const uint32_t b = g.x ? (uint32_t)__builtin_ctzll(g.x) : 0;
-        const char *base = static_cast<const char *>(s->data);
-        const int8_t *scales = reinterpret_cast<const int8_t *>(base + (((size_t)1 << n) * amp_bytes(s->dtype)));
-        switch (s->dtype) {
-        case SV_C128:
-            hipLaunchKernelGGL(k_expect_group<CplxAmps<double>>, dim3(grid), dim3(kRedThreads), 0, st,
-                               CplxAmps<double>{(const double2 *)base}, count, g.x, b, terms, g.first, g.count,
+    for (const TilePass &P : plan.tiles) {
+        with_amps(s, [&](auto amps) {
+            using A = decltype(amps);
+            hipLaunchKernelGGL((k_expect_tile<A>), dim3(plan.tile_grid), dim3(kTileThreads), 0, st, amps, P,
                                partials);
-            break;
-        case SV_C64:
-            hipLaunchKernelGGL(k_expect_group<CplxAmps<float>>, dim3(grid), dim3(kRedThreads), 0, st,
-                               CplxAmps<float>{(const float2 *)base}, count, g.x, b, terms, g.first, g.count,
-                               partials);
-            break;
-        case SV_CQ16:
-            hipLaunchKernelGGL(k_expect_group<Q16Amps>, dim3(grid), dim3(kRedThreads), 0, st,
-                               Q16Amps{(const uint32_t *)base, scales}, count, g.x, b, terms, g.first, g.count,
-                               partials);
-            break;
-        default:
-            hipLaunchKernelGGL(k_expect_group<Q32Amps>, dim3(grid), dim3(kRedThreads), 0, st,
-                               Q32Amps{(const uint2 *)base, scales}, count, g.x, b, terms, g.first, g.count,
-                               partials);
-            break;
-        }
+        });
         hipError_t e = hipGetLastError();
         if (e != hipSuccess)
             return fail(SV_EHIP, "expectation launch failed: %s", hipGetErrorString(e));
     }
-    const int nt = (int)plan.terms.size();
+    for (const DGroup &g : plan.rest) {
+        const uint64_t count = g.x == 0 ? (1ull << n) : (1ull << (n - 1));
+        const unsigned grid = reduce_grid(count);
+        const uint32_t b = g.x ? (uint32_t)__builtin_ctzll(g.x) : 0;
+        with_amps(s, [&](auto amps) {
+            using A = decltype(amps);
+            hipLaunchKernelGGL((k_expect_group<A>), dim3(grid), dim3(kRedThreads), 0, st, amps, count, g.x, b, terms,
+                               g.first, g.count, partials);
+        });
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess)
+            return fail(SV_EHIP, "expectation launch failed: %s", hipGetErrorString(e));
+    }
+    const int nt = (int)plan.pp.terms.size();
     hipLaunchKernelGGL(k_expect_sums, dim3(nt), dim3(kRedThreads), 0, st, nblk, partials, sums);
     hipLaunchKernelGGL(k_expect_final, dim3(1), dim3(64), 0, st, terms, nt, sums, out_total, out_terms);
     hipError_t e = hipGetLastError();
@@ -351,12 +670,11 @@ static int expect_launch(const sv_state_t *s, const PauliPlan &plan, const DTerm
 static int expect_impl(const sv_state_t *s, const sv_pauli_t *terms, int nterms, double *out_total,
                        double *out_terms, hipStream_t st) {
     SV_TRY(validate_state(s, true));
-    PauliPlan plan;
-    SV_TRY(make_pauli_plan(s->n, terms, nterms, &plan));
-    std::vector<int32_t> nblk;
-    expect_partial_counts(s->n, plan, nblk);
+    ExpectPlan plan;
+    SV_TRY(make_expect_plan(s->n, terms, nterms, &plan));
+    const std::vector<int32_t> &nblk = plan.nblk;
     PauliDevice d;
-    SV_TRY(pauli_upload(plan, (size_t)plan.terms.size() * (kMaxPartials + 1), st, &d));
+    SV_TRY(pauli_upload(plan.pp, (size_t)plan.pp.terms.size() * (kMaxPartials + 1), st, &d));
     int32_t *d_nblk = nullptr;
     int r = SV_OK;
     hipError_t e = hipMallocAsync((void **)&d_nblk, nblk.size() * sizeof(int32_t), st);
@@ -370,7 +688,7 @@ static int expect_impl(const sv_state_t *s, const sv_pauli_t *terms, int nterms,
             r = fail(SV_EHIP, "copy failed: %s", hipGetErrorString(e));
     }
     if (r == SV_OK)
-        r = expect_launch(s, plan, d.terms, d_nblk, d.partials, d.partials + plan.terms.size() * kMaxPartials,
+        r = expect_launch(s, plan, d.terms, d_nblk, d.partials, d.partials + plan.pp.terms.size() * kMaxPartials,
                           out_total, out_terms, st);
     if (d_nblk)
         (void)hipFreeAsync(d_nblk, st);
@@ -440,16 +758,14 @@ static int expect_noalloc_impl(const sv_state_t *s, const sv_pauli_t *terms, int
     SV_TRY(validate_state(s, true));
     if (nterms > kNoAllocTerms)
         return fail(SV_EINVAL, "nterms %d exceeds the allocation-free limit of %d terms", nterms, kNoAllocTerms);
-    PauliPlan plan;
-    SV_TRY(make_pauli_plan(s->n, terms, nterms, &plan));
-    std::vector<int32_t> nblk;
-    expect_partial_counts(s->n, plan, nblk);
+    ExpectPlan plan;
+    SV_TRY(make_expect_plan(s->n, terms, nterms, &plan));
     ExpectTables t;
     memset(&t, 0, sizeof(t));
-    t.nterms = (int32_t)plan.terms.size();
-    for (size_t j = 0; j < plan.terms.size(); ++j) {
-        t.terms[j] = plan.terms[j];
-        t.nblk[j] = nblk[j];
+    t.nterms = (int32_t)plan.pp.terms.size();
+    for (size_t j = 0; j < plan.pp.terms.size(); ++j) {
+        t.terms[j] = plan.pp.terms[j];
+        t.nblk[j] = plan.nblk[j];
     }
     ExpectScratch *w = nullptr;
     SV_TRY(scratch_address(&w));

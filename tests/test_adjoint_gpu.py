@@ -53,6 +53,56 @@ def test_expect_random_paulis(gpu, n):
     assert abs(tot64 - ref) <= 1e-5 * max(1.0, np.sum(np.abs([t.coef for t in terms])))
 
 
+def _tile_mix_terms(n, seed):
+    """Terms for every path of the expectation passes: the chain ZZ + X
+    Hamiltonian; 70 more diagonal terms (a tile set of more than 64 terms
+    takes two passes); 20 terms sharing one x mask (groups split at 16);
+    x masks with at most six qubits above qubit 5 (tile sets beyond the
+    first) and, for n > 12, masks with more (a pass per group); Y terms on
+    the lowest and highest qubits."""
+    rng = np.random.default_rng(seed)
+    terms = list(W.zz_x_hamiltonian(n, seed))
+    terms += [W.PauliTerm(float(rng.standard_normal()), 0, int(rng.integers(0, 1 << n))) for _ in range(70)]
+    xs = int(rng.integers(1, 1 << n))
+    terms += [W.PauliTerm(float(rng.standard_normal()), xs, int(rng.integers(0, 1 << n))) for _ in range(20)]
+    for _ in range(16):
+        hi = rng.choice(np.arange(min(6, n), n), size=min(n - min(6, n), int(rng.integers(0, 7))), replace=False)
+        x = int(rng.integers(0, 1 << min(6, n))) | sum(1 << int(q) for q in hi)
+        terms.append(W.PauliTerm(float(rng.standard_normal()), x, int(rng.integers(0, 1 << n))))
+    if n > 12:
+        for _ in range(6):
+            terms.append(W.PauliTerm(float(rng.standard_normal()), int(rng.integers(1, 1 << n)) | (0x7f << (n - 7)),
+                                     int(rng.integers(0, 1 << n))))
+    top = n - 1
+    terms += [W.PauliTerm(0.5, 1, 1), W.PauliTerm(-0.25, 1 << top, 1 << top)]
+    return terms
+
+
+@pytest.mark.parametrize("n", [2, 5, 12, 13, 18, 20])
+def test_expect_tile_passes(gpu, n):
+    """Per-term values and the total against the oracle at 1e-12 for a
+    Hamiltonian that reaches every pass kind (tile sets, split sets, split
+    groups, masks too wide for a tile); the allocation-free entry point
+    gives the total of its first 64 terms bit for bit."""
+    import torch
+    psi = W.random_state(n, 90 + n)
+    terms = _tile_mix_terms(n, 91 + n)
+    d = _dev(psi)
+    per = gpu.sv_expect_terms(d, terms).cpu().numpy()
+    tot = gpu.sv_expect(d, terms).item()
+    ref_per = np.array([oracle.expect_pauli(psi, n, t.x_mask, t.z_mask).real for t in terms])
+    l1 = float(np.sum(np.abs([t.coef for t in terms])))
+    e = float(np.max(np.abs(per - ref_per)))
+    _say("n", n, "terms", len(terms), "max term err", e)
+    assert e <= 1e-12
+    assert abs(tot - oracle.expect(psi, n, terms)) <= 1e-12 * l1
+    few = terms[-64:]
+    out = torch.full((1,), float("nan"), dtype=torch.float64, device="cuda")
+    gpu.sv_expect_noalloc(d, few, out)
+    assert out.item() == gpu.sv_expect(d, few).item()
+    assert abs(out.item() - oracle.expect(psi, n, few)) <= 1e-12 * float(np.sum(np.abs([t.coef for t in few])))
+
+
 @pytest.mark.parametrize("n", [2, 9, 13])
 def test_apply_pauli_sum(gpu, n):
     import torch
