@@ -254,13 +254,13 @@ __device__ __forceinline__ uint64_t deposit_bits(uint64_t v, uint64_t mask) {
 
 // Four terms of a tile pass at a time (independent chains for the
 // scheduler to interleave): slots past the end repeat the last term and are
-// dropped.  Diagonal terms: sum over this lane's amplitudes of
-// s(l) |t_l|^2.  Off-diagonal terms with Re(i^ny w) taken from Re w (IM
-// false, ny even) or Im w (IM true, ny odd): twice the sum over this lane's
-// pairs (l, l ^ xl) of s(l ^ xl) Re(i^ny conj(t_l) t_{l^xl}).  s(k) =
-// (-1)^{zl.k}.  Lane tid's r-th index is tid | (r << 8); inserting a cleared
-// bit b is linear over xor, so each sign splits into a lane part and a part
-// per r (uniform), and every update is one fused multiply-add by +-1.
+// dropped.  s(k) = (-1)^{zl.k}.  Lane tid's r-th amplitude of a tile is
+// l = tid | (r << 8), and its r-th pair index tid | (r << 8); inserting a
+// cleared bit b is linear over xor, so each sign splits into a lane part
+// and a part per r (uniform), and every update is one fused multiply-add by
+// +-1.  Off-diagonal terms take Re(i^ny w) from Re w (IM false, ny even) or
+// Im w (IM true, ny odd) and add twice the sum over the lane's pairs
+// (l, l ^ xl) of s(l ^ xl) Re(i^ny conj(t_l) t_{l^xl}).
 struct TileTerms {
     uint32_t txl, tzl, tzh_lo, tzh_hi;
     int tny;
@@ -280,28 +280,57 @@ __device__ __forceinline__ void tile_accumulate(const TileTerms &T, int j, int e
     }
 }
 
-__device__ __forceinline__ void tile_diag(const TileTerms &T, int j0, int j1, const double (&pr)[kTilePerLane],
-                                          uint32_t tid, uint32_t M, uint64_t base, uint32_t lane, double &acc) {
+// Walsh transform over the register bits: v[s] <- sum_r (-1)^{popc(s & r)} v[r].
+__device__ __forceinline__ void walsh16(double (&v)[kTilePerLane]) {
+#pragma unroll
+    for (int h = 1; h < kTilePerLane; h <<= 1)
+#pragma unroll
+        for (int r = 0; r < kTilePerLane; ++r)
+            if (!(r & h)) {
+                const double a = v[r], b = v[r | h];
+                v[r] = a + b;
+                v[r | h] = a - b;
+            }
+}
+
+// v[s] for a uniform s < 16 (static register indices).
+__device__ __forceinline__ double pick16(const double (&v)[kTilePerLane], uint32_t s) {
+    switch (s) {
+    case 0: return v[0];
+    case 1: return v[1];
+    case 2: return v[2];
+    case 3: return v[3];
+    case 4: return v[4];
+    case 5: return v[5];
+    case 6: return v[6];
+    case 7: return v[7];
+    case 8: return v[8];
+    case 9: return v[9];
+    case 10: return v[10];
+    case 11: return v[11];
+    case 12: return v[12];
+    case 13: return v[13];
+    case 14: return v[14];
+    default: return v[15];
+    }
+}
+
+// Diagonal terms: the lane's sum of s(l) |t_l|^2 over l = tid | (r << 8) is
+// (-1)^{zl.tid} times the Walsh coefficient of its |t|^2 at zl >> 8.
+__device__ __forceinline__ void tile_diag(const TileTerms &T, int j0, int j1, const double (&wc)[kTilePerLane],
+                                          uint32_t tid, uint64_t base, uint32_t lane, double &acc) {
     for (int j = j0; j < j1; j += 4) {
-        uint32_t zl[4];
         double ts[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            zl[q] = (uint32_t)__builtin_amdgcn_readlane((int)T.tzl, min(j + q, j1 - 1));
-            ts[q] = 0.0;
-        }
-#pragma unroll
-        for (int r = 0; r < kTilePerLane; ++r)
-            if ((tid | ((uint32_t)r << 8)) < M)
-#pragma unroll
-                for (int q = 0; q < 4; ++q)
-                    ts[q] = __builtin_fma((__popc(zl[q] & ((uint32_t)r << 8)) & 1) ? -1.0 : 1.0, pr[r], ts[q]);
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            if (__popc(zl[q] & tid) & 1)
+            const uint32_t zl = (uint32_t)__builtin_amdgcn_readlane((int)T.tzl, min(j + q, j1 - 1));
+            ts[q] = pick16(wc, zl >> 8);
+            if (__popc(zl & tid) & 1)
                 ts[q] = -ts[q];
-            ts[q] = wave_sum(ts[q]);
         }
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            ts[q] = wave_sum(ts[q]);
         tile_accumulate(T, j, j1, ts, base, lane, acc);
     }
 }
@@ -346,13 +375,13 @@ __device__ __forceinline__ void tile_offdiag(const TileTerms &T, int j0, int j1,
     }
 }
 
-// Every tile of the pass into LDS once, then every term of the pass over it
-// (diagonal terms, then those with even and with odd ny).  Lane j of each
+// Every tile of the pass into LDS once, then, once the next tile's loads
+// are issued, every term of the pass over it: diagonal terms from a Walsh
+// transform of the lane's |t|^2, then the pairs read from LDS.  Lane j of each
 // wavefront holds term j's masks (read by every lane with readlane, so the
 // term loops load nothing from memory) and accumulates term j over the
 // wavefront's tiles, in tile order; the four wavefronts' sums are added in
-// order at the end.  The next tile's loads are issued before the current
-// tile's terms are evaluated.
+// order at the end.
 template <typename A>
 __global__ __launch_bounds__(kTileThreads) void k_expect_tile(const A amps, const TilePass P,
                                                               double *__restrict__ partials) {
@@ -392,13 +421,13 @@ __global__ __launch_bounds__(kTileThreads) void k_expect_tile(const A amps, cons
     for (; tl < ntiles; tl += gridDim.x) {
         const uint64_t base = deposit_bits(tl, frmask);
         __syncthreads();  // every read of the previous tile is done
-        double pr[kTilePerLane];
+        double wc[kTilePerLane];
 #pragma unroll
         for (int r = 0; r < kTilePerLane; ++r) {
             const uint32_t l = tid | ((uint32_t)r << 8);
             if (l < M)
                 tile[l] = make_double2(vr[r], vi[r]);
-            pr[r] = vr[r] * vr[r] + vi[r] * vi[r];
+            wc[r] = l < M ? vr[r] * vr[r] + vi[r] * vi[r] : 0.0;
         }
         __syncthreads();
         if (tl + gridDim.x < ntiles) {
@@ -407,7 +436,10 @@ __global__ __launch_bounds__(kTileThreads) void k_expect_tile(const A amps, cons
             for (int r = 0; r < kTilePerLane; ++r)
                 amps.get(nb | off[r], vr[r], vi[r]);
         }
-        tile_diag(T, 0, nd, pr, tid, M, base, lane, acc);
+        if (nd) {
+            walsh16(wc);
+            tile_diag(T, 0, nd, wc, tid, base, lane, acc);
+        }
         tile_offdiag<false>(T, nd, nd + ne, tile, tid, M, base, lane, acc);
         tile_offdiag<true>(T, nd + ne, nt, tile, tid, M, base, lane, acc);
     }
