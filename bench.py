@@ -780,6 +780,27 @@ def measure_extras(sv, W, torch, np, stream, with_layered, psi_host=None, cases=
     aplan.close()
     del psi, work, lam
     torch.cuda.empty_cache()
+    # ---- expectation values: the chain ZZ + X Hamiltonian (47 / 55 terms), every dtype
+    for n_e in (24, 28):
+        log("expectation: n=%d chain Hamiltonian, four dtypes" % n_e)
+        h_arr = sv.pauli_terms(W.zz_x_hamiltonian(n_e, 5))
+        ps = torch.randn(1 << n_e, dtype=torch.complex128, device=dev)
+        ps /= torch.linalg.vector_norm(ps)
+        states = {"c128": ps, "c64": ps.to(torch.complex64)}
+        for name, code in (("q16", sv.SV_CQ16), ("q32", sv.SV_CQ32)):
+            q = sv.FixedState(n_e, code)
+            sv.sv_convert(q, ps)
+            states[name] = q
+        eo = torch.empty(1, dtype=torch.float64, device=dev)
+        row = {"terms": len(h_arr)}
+        for name, st_ in states.items():
+            ms = _time_ms(torch, stream, lambda: sv.sv_expect_noalloc(st_, h_arr, eo, stream=stream), 5)
+            nbytes = sv.sv_state_bytes(n_e, {"c128": sv.SV_C128, "c64": sv.SV_C64, "q16": sv.SV_CQ16,
+                                             "q32": sv.SV_CQ32}[name])
+            row[name] = {"ms": round(ms, 3), "one_read_GBps": round(nbytes / ms / 1e6, 1)}
+        out["expect_chain_n%d" % n_e] = row
+        del states, ps
+        torch.cuda.empty_cache()
     # ---- batched: 4096 uneven circuits forward (complex128 and complex64) and batched adjoint
     for dt, td in (("c128", torch.complex128), ("c64", torch.complex64)):
         log("batched: 4096 uneven circuits", dt)
