@@ -307,6 +307,23 @@ def run_fused_only(sv, W, torch, np, stream):
     print(json.dumps({"fused_only": "done"}), flush=True)
 
 
+def run_expect_only(sv, W, torch, np, stream):
+    """One expectation call each on an n=24 complex128 and 16-bit fixed-point
+    state (the 47-term chain ZZ + X Hamiltonian: 3 tile passes), for
+    counters."""
+    dev = torch.device("cuda:0")
+    h_arr = sv.pauli_terms(W.zz_x_hamiltonian(24, 5))
+    ps = torch.randn(1 << 24, dtype=torch.complex128, device=dev)
+    ps /= torch.linalg.vector_norm(ps)
+    q = sv.FixedState(24, sv.SV_CQ16)
+    sv.sv_convert(q, ps)
+    eo = torch.empty(1, dtype=torch.float64, device=dev)
+    for st_ in (ps, q):
+        sv.sv_expect_noalloc(st_, h_arr, eo, stream=stream)
+    torch.cuda.synchronize()
+    print(json.dumps({"expect_only": "done", "value": eo.item()}), flush=True)
+
+
 def summarize_counters(name, cmd, dirs):
     """Per-kernel averages of rocprofv3 --pmc counters (one directory per
     pass) into profiles/counters_<name>.md."""
@@ -1047,6 +1064,8 @@ def main():
                     help="file receiving the per-row tables and extra measurements as JSON ('' disables)")
     ap.add_argument("--fused-only", action="store_true",
                     help="run once each the fused layered circuit (n=28), QFT29 and the n=24 adjoint, for counters")
+    ap.add_argument("--expect-only", action="store_true",
+                    help="run one expectation call each on n=24 complex128 and 16-bit states, for counters")
     ap.add_argument("--summarize-counters", nargs="+", metavar="ARG",
                     help="NAME CMDFILE DIR...: per-kernel averages of rocprofv3 --pmc passes into "
                          "profiles/counters_NAME.md (CMDFILE: the commands, one per line)")
@@ -1083,6 +1102,9 @@ def main():
     dev = torch.device("cuda:0")
     if args.fused_only:
         run_fused_only(sv, W, torch, np, torch.cuda.Stream(device=dev))
+        return
+    if args.expect_only:
+        run_expect_only(sv, W, torch, np, torch.cuda.Stream(device=dev))
         return
     n = N_QUBITS
     log("generating n=%d input state" % n)
