@@ -2,7 +2,8 @@
 n = 34 complex128 and n = 35 complex64 (256 GiB each), n = 36 16-bit and
 n = 35 32-bit fixed point (257 GiB and 256.5 GiB).  64-bit indices throughout.  The checks are properties that pin
 the result without a second full-size buffer: a basis state moved by a
-controlled X, a gate whose controls fail on it leaving it alone, and the
+controlled X, a gate whose controls fail on it leaving it alone, Pauli
+expectations of that state after a Hadamard on the top qubit, and the
 norm (or, for fixed point, whole-array reductions of codes and scales)
 showing that every other amplitude stayed zero.
 """
@@ -17,6 +18,7 @@ sv = pytest.importorskip("paper_2411_18354_amd")
 pytestmark = pytest.mark.gpu
 
 X = np.array([[0, 1], [1, 0]])
+H = np.array([[1, 1], [1, -1]]) / np.sqrt(2.0)
 
 
 def _alloc(fn, what):
@@ -76,6 +78,22 @@ def test_controlled_x_at_max_size(dtype, n):
         # <psi|I|psi> = 1 with |psi_w| = 1 forces every other amplitude to 0
         nrm = sv.sv_expect(psi, [(1.0, 0, 0)]).item()
         assert abs(nrm - 1.0) < 1e-12
+        # H on the top qubit (set in w): (|w - 2^t> - |w>) / sqrt(2), whose
+        # Pauli expectations are closed forms of w's bits; X and Y on qubit t
+        # run a tile pass whose tile holds qubit t, Z on qubit 31 a sign from
+        # outside the tile
+        sv.sv_apply_gate(psi, t, (), None, H)
+        terms = [(1.0, 0, 1 << t), (1.0, 1 << t, 0), (1.0, 1 << t, 1 << t), (1.0, 0, 1),
+                 (1.0, 1 << t, 1 << 31), (1.0, 0, (1 << 31) | (1 << (n - 2)))]
+        want = [0.0, -1.0, 0.0, -1.0 if w & 1 else 1.0, 1.0 if (w >> 31) & 1 else -1.0,
+                1.0 if ((w >> 31) ^ (w >> (n - 2))) & 1 == 0 else -1.0]
+        got = sv.sv_expect_terms(psi, terms).cpu().numpy()
+        tol = 1e-12 if dtype == "c128" else 1e-6
+        assert np.max(np.abs(got - np.array(want))) <= tol, (got, want)
+        sv.sv_apply_gate(psi, t, (), None, H)
+        torch.cuda.synchronize()
+        assert abs(psi[w].item() - 1) <= tol and abs(psi[b].item()) <= tol
+        psi[w], psi[b] = 1, 0  # H H = I up to rounding; the checks below are exact
         # the masked kernel undoes the move
         sv.sv_apply_gate(psi, t, (0, n - 2), None, X, mode="masked")
         torch.cuda.synchronize()
