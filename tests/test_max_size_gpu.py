@@ -132,6 +132,12 @@ def test_fixed_point_controlled_x_at_max_size(bits, n):
         assert scales[w >> 6].item() == one_scale
         assert scales.max().item() == one_scale and scales.min().item() == zero_scale
         assert _isum(scales) == zero_scale * (nb - 1) + one_scale
+        # expectations read from the codes: the basis state w decodes to
+        # exactly 1 at w, so Z terms give the sign of w's bits, X terms 0
+        terms = [(1.0, 0, 0), (1.0, 0, 1 << t), (1.0, 0, (1 << 31) | 1), (1.0, 1 << t, 0), (-0.5, 1 << t, 1 << t)]
+        want = [1.0, -1.0 if (w >> t) & 1 else 1.0, 1.0 if (((w >> 31) ^ w) & 1) == 0 else -1.0, 0.0, 0.0]
+        got = sv.sv_expect_terms(q, terms).cpu().numpy()
+        assert np.array_equal(got, np.array(want)), (got, want)
         sv.sv_apply_gate(q, t, (0, n - 2), None, X, mode="masked")
         torch.cuda.synchronize()
         assert codes[word(b)].item() == one and codes[word(w)].item() == 0
