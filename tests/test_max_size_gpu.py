@@ -3,8 +3,8 @@ n = 34 complex128 and n = 35 complex64 (256 GiB each), n = 36 16-bit and
 n = 35 32-bit fixed point (257 GiB and 256.5 GiB).  64-bit indices throughout.  The checks are properties that pin
 the result without a second full-size buffer: a basis state moved by a
 controlled X, a gate whose controls fail on it leaving it alone, Pauli
-expectations of that state after a Hadamard on the top qubit, and the
-norm (or, for fixed point, whole-array reductions of codes and scales)
+expectations with closed forms (of the basis state, and for complex states
+of the state after a Hadamard on the top qubit), and the norm (or, for fixed point, whole-array reductions of codes and scales)
 showing that every other amplitude stayed zero.
 """
 import numpy as np
